@@ -1,0 +1,188 @@
+"""CPU oracle of the Co-Sim. SPFD Poisson solve (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark may import this package; the product library never does.
+It wraps ``spfd_oracle.c`` (plain C + OpenMP, FP64) through ctypes and adds a
+dense NumPy reference for tiny grids (``oracle.dense``).  It shares no code
+with the HIP library.
+
+All arrays use the index conventions of ``workloads``: voxel arrays
+(nz, ny, nx), node arrays (nz+1, ny+1, nx+1), edge arrays (3, nz+1, ny+1, nx+1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "spfd_oracle.c")
+_LIB = os.path.join(_HERE, "libspfd_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fast-math: IEEE FP64 round-to-nearest)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class OracleInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("ncomp", ctypes.c_int), ("ndof", ctypes.c_long),
+                ("relres", ctypes.c_double), ("bnorm", ctypes.c_double),
+                ("t_assemble", ctypes.c_double), ("t_solve", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        D = ctypes.c_double
+        lib.oracle_edge_conductance.argtypes = [I, I, I, P, P, P]
+        lib.oracle_edge_conductance.restype = None
+        lib.oracle_components.argtypes = [I, I, I, P, P, P]
+        lib.oracle_components.restype = I
+        lib.oracle_solve.argtypes = [I, I, I, P, P, P, D, I, I, P, ctypes.POINTER(OracleInfo)]
+        lib.oracle_solve.restype = I
+        lib.oracle_residual.argtypes = [I, I, I, P, P, P, P, I, P]
+        lib.oracle_residual.restype = D
+        lib.oracle_efield.argtypes = [I, I, I, P, P, P, P, D, P, P]
+        lib.oracle_efield.restype = None
+        lib.oracle_adjoint.argtypes = [I, I, I, P, P, P, P, D, P, D, I, I, P, I, P, P,
+                                       ctypes.POINTER(OracleInfo)]
+        lib.oracle_adjoint.restype = I
+        lib.oracle_dense_system.argtypes = [I, I, I, P, P, P, P, P, P, P, ctypes.c_long]
+        lib.oracle_dense_system.restype = ctypes.c_long
+        _lib = lib
+    return _lib
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _ptr(x):
+    return x.ctypes.data_as(ctypes.c_void_p) if x is not None else None
+
+
+def _dims(sigma):
+    nz, ny, nx = sigma.shape
+    return nx, ny, nz
+
+
+def edge_conductance(sigma, h):
+    """M_kappa as an edge array (3, nz+1, ny+1, nx+1)."""
+    sigma = _f64(sigma)
+    nx, ny, nz = _dims(sigma)
+    h = _f64(h)
+    M = np.empty((3, nz + 1, ny + 1, nx + 1))
+    _load().oracle_edge_conductance(nx, ny, nz, _ptr(h), _ptr(sigma), _ptr(M))
+    return M
+
+
+def components(sigma, h):
+    """(comp (nz+1,ny+1,nx+1) int32 with -1 at non-DOF nodes, number of components)."""
+    sigma = _f64(sigma)
+    nx, ny, nz = _dims(sigma)
+    h = _f64(h)
+    M = edge_conductance(sigma, h)
+    comp = np.empty((nz + 1, ny + 1, nx + 1), np.int32)
+    nc = _load().oracle_components(nx, ny, nz, _ptr(h), _ptr(M), _ptr(comp))
+    return comp, nc
+
+
+def solve(sigma, h, a, tol=1e-12, max_iter=200000, nthreads=0):
+    """Mean-zero solution psi of Eq. (3) (node array) and an info dict."""
+    sigma = _f64(sigma)
+    nx, ny, nz = _dims(sigma)
+    h = _f64(h)
+    a = _f64(a)
+    assert a.shape == (3, nz + 1, ny + 1, nx + 1)
+    psi = np.empty((nz + 1, ny + 1, nx + 1))
+    info = OracleInfo()
+    _load().oracle_solve(nx, ny, nz, _ptr(h), _ptr(sigma), _ptr(a), tol, max_iter, nthreads,
+                         _ptr(psi), ctypes.byref(info))
+    return psi, info.as_dict()
+
+
+def residual(sigma, h, a, psi, nthreads=0, want_nodes=False):
+    """||b - A psi|| / ||b|| of a given psi (and optionally the residual node array)."""
+    sigma = _f64(sigma)
+    nx, ny, nz = _dims(sigma)
+    h = _f64(h)
+    a = _f64(a)
+    psi = _f64(psi)
+    r = np.empty((nz + 1, ny + 1, nx + 1)) if want_nodes else None
+    rel = _load().oracle_residual(nx, ny, nz, _ptr(h), _ptr(sigma), _ptr(a), _ptr(psi), nthreads, _ptr(r))
+    return (rel, r) if want_nodes else rel
+
+
+def efield(sigma, h, a, psi, omega):
+    """(u edge array, |E| voxel array) from Eq. (1) and the voxel average."""
+    sigma = _f64(sigma)
+    nx, ny, nz = _dims(sigma)
+    h = _f64(h)
+    a = _f64(a)
+    psi = _f64(psi)
+    u = np.empty((3, nz + 1, ny + 1, nx + 1))
+    emag = np.empty((nz, ny, nx))
+    _load().oracle_efield(nx, ny, nz, _ptr(h), _ptr(sigma), _ptr(a), _ptr(psi), omega, _ptr(u), _ptr(emag))
+    return u, emag
+
+
+def adjoint(sigma, h, a, psi, omega, grad_emag, tol=1e-12, max_iter=200000, nthreads=0,
+            labels=None, n_labels=0):
+    """(dJ/dsigma per voxel, dJ/dsigma per label or None, info) for a given dJ/d|E|."""
+    sigma = _f64(sigma)
+    nx, ny, nz = _dims(sigma)
+    h = _f64(h)
+    a = _f64(a)
+    psi = _f64(psi)
+    ge = _f64(grad_emag)
+    gs = np.empty((nz, ny, nx))
+    gt = np.empty(n_labels) if labels is not None else None
+    lab = np.ascontiguousarray(labels, dtype=np.uint8) if labels is not None else None
+    info = OracleInfo()
+    _load().oracle_adjoint(nx, ny, nz, _ptr(h), _ptr(sigma), _ptr(a), _ptr(psi), omega, _ptr(ge),
+                           tol, max_iter, nthreads, _ptr(lab), n_labels, _ptr(gs), _ptr(gt),
+                           ctypes.byref(info))
+    return gs, gt, info.as_dict()
+
+
+def dense_system(sigma, h, a, max_dof=4000):
+    """Dense A (ndof x ndof), b, DOF->node map and DOF->component for tiny grids."""
+    sigma = _f64(sigma)
+    nx, ny, nz = _dims(sigma)
+    h = _f64(h)
+    a = _f64(a)
+    nd = _load().oracle_dense_system(nx, ny, nz, _ptr(h), _ptr(sigma), _ptr(a), None, None, None, None, 0)
+    if nd > max_dof:
+        raise ValueError(f"{nd} DOFs exceed max_dof={max_dof}")
+    A = np.empty((nd, nd))
+    b = np.empty(nd)
+    node_of = np.empty(nd, np.int64)
+    comp_of = np.empty(nd, np.int32)
+    _load().oracle_dense_system(nx, ny, nz, _ptr(h), _ptr(sigma), _ptr(a), _ptr(A), _ptr(b),
+                                _ptr(node_of), _ptr(comp_of), max_dof)
+    return A, b, node_of, comp_of
+
+
+def pnorm_objective(emag, p=8):
+    """J = (sum |E_v|^p)^(1/p) over body voxels and dJ/d|E| (air voxels have |E| = 0)."""
+    e = np.asarray(emag, dtype=np.float64)
+    J = float(np.sum(e ** p) ** (1.0 / p))
+    g = (e / J) ** (p - 1) if J > 0 else np.zeros_like(e)
+    return J, g

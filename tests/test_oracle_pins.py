@@ -1,0 +1,341 @@
+"""Pins of the CPU oracle against hand computation, closed forms, brute force and invariants.
+
+Each test fixes the oracle to something other than itself:
+  * single- and two-voxel systems written out by hand (assembly of M_kappa and Eq. (3));
+  * a voxel-by-voxel "element" assembly (scatter of each voxel's 12 edges),
+    a different route to G^T M G than the oracle's edge gather;
+  * dense pseudo-inverse solves on tiny grids with holes and several components;
+  * manufactured discrete solutions (exact Psi and exact u, since C G = 0);
+  * the continuum solution of a homogeneous ellipsoid in a uniform B field (signs, scale, O(h));
+  * invariants: conductivity scaling, source linearity, mirror symmetry, Thomson's principle,
+    current continuity G^T M u = 0 (Eq. (1) with Eq. (3));
+  * adjoint gradient against central finite differences and the Euler identity.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import discrete as D
+
+
+def _cube_laplacian(wx, wy, wz):
+    """Hand-built 8x8 matrix of one voxel: node (i,j,k) in {0,1}^3 -> i + 2j + 4k; nodes that
+    differ in exactly one coordinate are joined by an edge of weight wx/wy/wz."""
+    A = np.zeros((8, 8))
+    for p in range(8):
+        for q in range(8):
+            diff = p ^ q
+            if diff in (1, 2, 4):
+                w = {1: wx, 2: wy, 4: wz}[diff]
+                A[p, q] = -w
+                A[p, p] += w
+    return A
+
+
+def test_single_voxel_system_by_hand():
+    # sigma = 1, h = (1, 2, 4): x-edge conductance = 1/4 * hy*hz/hx = 2, y: 1/4*4/2 = 0.5, z: 1/4*2/4 = 0.125
+    sig = np.ones((1, 1, 1))
+    A, b, node_of, comp = oracle.dense_system(sig, (1.0, 2.0, 4.0), np.zeros((3, 2, 2, 2)))
+    assert A.shape == (8, 8)
+    assert list(node_of) == list(range(8))
+    np.testing.assert_allclose(A, _cube_laplacian(2.0, 0.5, 0.125), rtol=0, atol=1e-15)
+    M = oracle.edge_conductance(sig, (1.0, 2.0, 4.0))
+    assert M[0, 0, 0, 0] == 2.0 and M[1, 0, 0, 0] == 0.5 and M[2, 0, 0, 0] == 0.125
+    assert M[0, 0, 0, 1] == 0.0            # x-edge leaving the grid
+    assert np.count_nonzero(M) == 12
+
+
+def test_single_voxel_rhs_by_hand():
+    # a = 1 on the x-edge from node 0 to node 1 only; M = 0.5 (sigma 2, h 1):
+    # b = -G^T M a: node 0 (tail) gets +0.5, node 1 (head) gets -0.5
+    sig = np.full((1, 1, 1), 2.0)
+    a = np.zeros((3, 2, 2, 2))
+    a[0, 0, 0, 0] = 1.0
+    A, b, node_of, _ = oracle.dense_system(sig, (1.0, 1.0, 1.0), a)
+    np.testing.assert_allclose(b, [0.5, -0.5, 0, 0, 0, 0, 0, 0], atol=1e-16)
+    np.testing.assert_allclose(A, _cube_laplacian(0.5, 0.5, 0.5), atol=1e-16)
+
+
+def test_two_voxels_shared_face_by_hand():
+    # voxels 0 (sigma 1) and 1 (sigma 3) along x, h = 1: the 4 edges in the shared face
+    # (y- and z-edges at i = 1) carry (1+3)/4 = 1; edges of voxel 0 only: 1/4; of voxel 1 only: 3/4
+    sig = np.array([[[1.0, 3.0]]])
+    M = oracle.edge_conductance(sig, (1.0, 1.0, 1.0))
+    # y-edges at i = 1: nodes (1, 0, k), k = 0, 1; z-edges at i = 1: nodes (1, j, 0), j = 0, 1
+    assert M[1, 0, 0, 1] == 1.0 and M[1, 1, 0, 1] == 1.0
+    assert M[2, 0, 0, 1] == 1.0 and M[2, 0, 1, 1] == 1.0
+    assert M[1, 0, 0, 0] == 0.25 and M[1, 0, 0, 2] == 0.75
+    assert M[0, 0, 0, 0] == 0.25 and M[0, 0, 0, 1] == 0.75
+    assert M[0, 1, 1, 1] == 0.75
+    assert np.count_nonzero(M) == 20        # 12 + 12 - 4 shared
+
+
+def _element_assembly(sig, h):
+    """A = sum over voxels of sigma_v * (area/4/length) * (cube Laplacian of its 12 edges),
+    mapped to global nodes by scatter; the independent route to G^T M G."""
+    nz, ny, nx = sig.shape
+    Nx, Ny, Nz = nx + 1, ny + 1, nz + 1
+    nn = Nx * Ny * Nz
+    A = np.zeros((nn, nn))
+    geo = (h[1] * h[2] / h[0], h[0] * h[2] / h[1], h[0] * h[1] / h[2])
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                s = sig[k, j, i]
+                if s == 0:
+                    continue
+                loc = _cube_laplacian(s * geo[0] / 4, s * geo[1] / 4, s * geo[2] / 4)
+                nodes = [(i + (c & 1)) + Nx * ((j + ((c >> 1) & 1)) + Ny * (k + ((c >> 2) & 1))) for c in range(8)]
+                for p in range(8):
+                    for q in range(8):
+                        A[nodes[p], nodes[q]] += loc[p, q]
+    return A
+
+
+@pytest.mark.parametrize("seed,shape", [(1, (3, 4, 2)), (2, (4, 3, 5)), (3, (5, 5, 4)), (4, (1, 6, 3))])
+def test_element_assembly_matches(seed, shape):
+    w = W.tiny_random_phantom(*shape, seed=seed)
+    sig = w.sigma_voxel()
+    A, b, node_of, _ = oracle.dense_system(sig, w.h, w.a)
+    Afull = _element_assembly(sig, w.h)
+    np.testing.assert_allclose(A, Afull[np.ix_(node_of, node_of)], rtol=1e-14, atol=1e-18)
+    # the nodes that are not DOFs have empty rows in the element assembly
+    others = np.setdiff1d(np.arange(Afull.shape[0]), node_of)
+    assert np.all(Afull[others] == 0)
+    # b = -G^T M a with M from the element view: M_e = -A_{tail,head}
+    M = np.zeros_like(w.a)
+    Nz, Ny, Nx = w.nz + 1, w.ny + 1, w.nx + 1
+    step = (1, Nx, Nx * Ny)
+    flatM = M.reshape(3, -1)
+    for d in range(3):
+        for n in range(Nx * Ny * Nz):
+            m = n + step[d]
+            i, j, k = n % Nx, (n // Nx) % Ny, n // (Nx * Ny)
+            if (d == 0 and i == Nx - 1) or (d == 1 and j == Ny - 1) or (d == 2 and k == Nz - 1):
+                continue
+            flatM[d, n] = -Afull[n, m]
+    bfull = -D.div_T(M * w.a).reshape(-1)
+    np.testing.assert_allclose(b, bfull[node_of], rtol=1e-12, atol=1e-22)
+
+
+@pytest.mark.parametrize("seed,shape,fill", [(5, (4, 4, 4), 0.5), (6, (6, 5, 4), 0.35), (7, (3, 6, 6), 0.7),
+                                              (8, (6, 6, 6), 0.3)])
+def test_solve_matches_dense_pinv(seed, shape, fill):
+    w = W.tiny_random_phantom(*shape, seed=seed, fill=fill)
+    sig = w.sigma_voxel()
+    A, b, node_of, comp = oracle.dense_system(sig, w.h, w.a)
+    x_ref = np.linalg.pinv(A) @ b           # minimum norm = mean-zero on every component
+    psi, info = oracle.solve(sig, w.h, w.a, tol=1e-14, max_iter=100000)
+    x = psi.reshape(-1)[node_of]
+    assert info["ncomp"] == len(np.unique(comp))
+    np.testing.assert_allclose(x, x_ref, rtol=0, atol=1e-10 * np.abs(x_ref).max())
+    for c in np.unique(comp):
+        assert abs(x[comp == c].sum()) <= 1e-12 * np.abs(x).sum()
+    assert np.all(psi.reshape(-1)[np.setdiff1d(np.arange(psi.size), node_of)] == 0)
+
+
+def test_several_components_counted():
+    # sig is indexed (k, j, i); voxel (i,j,k) owns the nodes i..i+1, j..j+1, k..k+1
+    sig = np.zeros((5, 5, 7))
+    sig[1:3, 1:3, 0:2] = 1.0     # block A: nodes i 0..2, j 1..3, k 1..3
+    sig[1:3, 1:3, 4:6] = 0.5     # block B: nodes i 4..6: no node shared with A
+    sig[4, 4, 6] = 2.0           # single voxel: nodes i 6..7, j 4..5, k 4..5
+    comp, nc = oracle.components(sig, (1e-3,) * 3)
+    assert nc == 3
+    sig[3, 3, 3] = 1.0           # nodes i 3..4, j 3..4, k 3..4: shares node (4,3,3) with B
+    sig[3, 3, 1] = 1.0           # nodes i 1..2: shares (1..2,3,3) with A, nothing with (3,3,3)
+    comp, nc = oracle.components(sig, (1e-3,) * 3)
+    assert nc == 3
+    sig[3, 3, 2] = 1.0           # nodes i 2..3: joins the voxels at i = 1 and i = 3, hence A and B
+    comp, nc = oracle.components(sig, (1e-3,) * 3)
+    assert nc == 2
+    assert comp[3, 3, 4] == comp[2, 2, 1] != comp[5, 5, 7]
+
+
+@pytest.mark.parametrize("cfg", ["ellipsoid", "hetero"])
+def test_manufactured_solution(cfg):
+    rng = np.random.default_rng(11)
+    if cfg == "ellipsoid":
+        w = W.homogeneous_ellipsoid(n_nodes=20, semi=(7.0, 6.0, 8.0))
+    else:
+        w = W.random_ellipsoid_phantom(24, 20, 28, seed=99, n_ell=6, semi_range=(3.0, 8.0))
+    sig = w.sigma_voxel()
+    body = sig > 0
+    M = oracle.edge_conductance(sig, w.h)
+    a, psi_star, u_exact = D.manufactured(M, body, rng)
+    assert np.all(D.curl_T(np.zeros_like(a)) == 0)
+    psi, info = oracle.solve(sig, w.h, a, tol=1e-13)
+    comp, _ = oracle.components(sig, w.h)
+    expect = D.project_mean_zero(psi_star, comp)
+    err = np.abs(psi - expect).max() / np.abs(expect).max()
+    assert err < 1e-9, err
+    u, E = oracle.efield(sig, w.h, a, psi, w.omega)
+    np.testing.assert_allclose(u, u_exact, rtol=0, atol=1e-8 * np.abs(u_exact).max())
+    E_ref = D.voxel_emag_bruteforce(u_exact, body, w.h, w.omega)
+    np.testing.assert_allclose(E, E_ref, rtol=1e-8, atol=1e-12 * E_ref.max())
+    assert np.all(E[~body] == 0)
+
+
+def test_gradient_source_gives_zero_field():
+    # a = -G psi*: the whole source is a gauge, so u = 0 and psi = psi* (mean-zero)
+    w = W.homogeneous_ellipsoid(n_nodes=16, semi=(6.0, 5.0, 7.0))
+    sig = w.sigma_voxel()
+    rng = np.random.default_rng(3)
+    psi_star = rng.standard_normal((16, 16, 16)) * 1e-6
+    a = -D.grad(psi_star)
+    psi, info = oracle.solve(sig, w.h, a, tol=1e-14)
+    comp, _ = oracle.components(sig, w.h)
+    np.testing.assert_allclose(psi, D.project_mean_zero(psi_star, comp), atol=1e-9 * 1e-6)
+    u, E = oracle.efield(sig, w.h, a, psi, w.omega)
+    assert np.abs(u).max() < 1e-9 * np.abs(a).max()
+
+
+def _ellipsoid_uniform_B(n_vox, semi_m=(0.012, 0.010, 0.014), B=1e-3):
+    """Homogeneous ellipsoid in uniform B_z, symmetric gauge A = B/2 (-y, x, 0) about its centre."""
+    L = 2 * max(semi_m) * 1.1
+    h = L / n_vox
+    c = n_vox / 2.0
+    xc = (np.arange(n_vox) + 0.5 - c) * h
+    q = (xc[None, None, :] / semi_m[0]) ** 2 + (xc[None, :, None] / semi_m[1]) ** 2 + (xc[:, None, None] / semi_m[2]) ** 2
+    sig = np.where(q <= 1.0, 0.3, 0.0)
+    xn = (np.arange(n_vox + 1) - c) * h
+    a = np.zeros((3, n_vox + 1, n_vox + 1, n_vox + 1))
+    # A_x = -B y/2 is constant along an x-edge, A_y = B x/2 along a y-edge
+    a[0, :, :, :-1] = (-B / 2 * xn[None, :, None] * h) * np.ones((n_vox + 1, 1, n_vox))
+    a[1, :, :-1, :] = (B / 2 * xn[None, None, :] * h) * np.ones((n_vox + 1, n_vox, 1))
+    return sig, (h, h, h), a, xn, xc
+
+
+def test_ellipsoid_uniform_field_continuum():
+    ax_, by_ = 0.012, 0.010
+    B = 1e-3
+    kappa = B / 2 * (by_ ** 2 - ax_ ** 2) / (ax_ ** 2 + by_ ** 2)
+    errs = []
+    for n in (16, 32, 48):
+        sig, h, a, xn, xc = _ellipsoid_uniform_B(n, B=B)
+        psi, info = oracle.solve(sig, h, a, tol=1e-12)
+        comp, _ = oracle.components(sig, h)
+        ref = kappa * xn[None, None, :] * xn[None, :, None] * np.ones((n + 1, 1, 1))
+        ref = D.project_mean_zero(ref, comp)
+        dof = comp >= 0
+        errs.append(np.sqrt(((psi - ref)[dof] ** 2).sum() / (ref[dof] ** 2).sum()))
+        u, E = oracle.efield(sig, h, a, psi, 1.0)
+        # field deep inside (normalised radius < 0.6) vs E = omega B/(a^2+b^2) (-a^2 y, b^2 x, 0)
+        q = np.sqrt((xc[None, None, :] / ax_) ** 2 + (xc[None, :, None] / by_) ** 2 + (xc[:, None, None] / 0.014) ** 2)
+        inner = q < 0.6
+        Eref = B / (ax_ ** 2 + by_ ** 2) * np.sqrt((ax_ ** 2 * xc[None, :, None]) ** 2 + (by_ ** 2 * xc[None, None, :]) ** 2) \
+            * np.ones((n, 1, 1))
+        rel = np.sqrt(((E - Eref)[inner] ** 2).sum() / (Eref[inner] ** 2).sum())
+        assert rel < 0.12, (n, rel)
+    # first-order (staircase) convergence: the error falls at least like h
+    assert errs[1] < errs[0] * 0.6 and errs[2] < errs[1] * 0.8 and errs[2] < 0.12, errs
+    # sign and scale: psi follows kappa*x*y with kappa < 0 (b < a)
+    assert kappa < 0
+    c = float(np.sum(psi[dof] * ref[dof]) / np.sum(ref[dof] ** 2))
+    assert 0.9 < c < 1.1, c
+
+
+def test_conductivity_scaling_and_source_linearity():
+    w = W.random_ellipsoid_phantom(20, 16, 24, seed=7, n_ell=5, semi_range=(3.0, 7.0))
+    sig = w.sigma_voxel()
+    psi, _ = oracle.solve(sig, w.h, w.a, tol=1e-13)
+    psi2, _ = oracle.solve(sig * 37.0, w.h, w.a, tol=1e-13)
+    psi3, _ = oracle.solve(sig, w.h, -2.5 * w.a, tol=1e-13)
+    s = np.abs(psi).max()
+    assert np.abs(psi2 - psi).max() < 1e-9 * s
+    assert np.abs(psi3 + 2.5 * psi).max() < 1e-9 * s
+
+
+def test_mirror_symmetry():
+    # ellipsoid and dipole symmetric under x -> -x; A_x is even in x... (A_x = -c Y f(R)) so
+    # a_x(-x) equals a_x(x) on mirrored edges while a_y flips sign: psi is odd in x.
+    w = W.homogeneous_ellipsoid(n_nodes=20, semi=(7.0, 6.0, 8.0))
+    sig = w.sigma_voxel()
+    assert np.array_equal(sig, sig[:, :, ::-1])
+    psi, _ = oracle.solve(sig, w.h, w.a, tol=1e-13)
+    assert np.abs(psi + psi[:, :, ::-1]).max() < 1e-8 * np.abs(psi).max()
+    u, E = oracle.efield(sig, w.h, w.a, psi, w.omega)
+    np.testing.assert_allclose(E, E[:, :, ::-1], rtol=1e-7, atol=1e-10 * E.max())
+
+
+def test_thomson_principle_and_continuity():
+    w = W.random_ellipsoid_phantom(18, 16, 20, seed=5, n_ell=5, semi_range=(3.0, 7.0))
+    sig = w.sigma_voxel()
+    M = oracle.edge_conductance(sig, w.h)
+    psi, _ = oracle.solve(sig, w.h, w.a, tol=1e-13)
+    u, _ = oracle.efield(sig, w.h, w.a, psi, w.omega)
+    comp, _ = oracle.components(sig, w.h)
+    dof = comp >= 0
+    # current continuity G^T M u = 0 (relative to G^T M a)
+    cont = D.div_T(M * u)[dof]
+    ref = D.div_T(M * w.a)[dof]
+    assert np.linalg.norm(cont) < 1e-11 * np.linalg.norm(ref)
+    # dissipated power u^T M u is minimal over a + G(psi + dpsi)
+    P0 = np.sum(M * u * u)
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        dpsi = rng.standard_normal(psi.shape) * 1e-3 * np.abs(psi).max()
+        u2 = np.where(M > 0, w.a + D.grad(psi + dpsi), 0.0)
+        assert np.sum(M * u2 * u2) > P0
+
+
+def test_dipole_field_zero_in_air_and_continuity_c1():
+    w = W.config(0)
+    sig = w.sigma_voxel()
+    psi, info = oracle.solve(sig, w.h, w.a, tol=1e-10)
+    assert info["ndof"] == 8400 and info["ncomp"] == 1
+    assert info["relres"] <= 1e-10 * 1.01
+    u, E = oracle.efield(sig, w.h, w.a, psi, w.omega)
+    assert np.all(E[sig == 0] == 0) and np.all(E[sig > 0] > 0)
+    M = oracle.edge_conductance(sig, w.h)
+    comp, _ = oracle.components(sig, w.h)
+    cont = D.div_T(M * u)[comp >= 0]
+    ref = D.div_T(M * w.a)[comp >= 0]
+    assert np.linalg.norm(cont) <= 1.01e-10 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------------------- adjoint
+def _J_of(sig, h, a, omega, tol=1e-14):
+    psi, _ = oracle.solve(sig, h, a, tol=tol, max_iter=200000)
+    _, E = oracle.efield(sig, h, a, psi, omega)
+    return oracle.pnorm_objective(E)[0], psi, E
+
+
+def test_adjoint_against_finite_differences():
+    w = W.tiny_random_phantom(5, 4, 6, seed=21, fill=0.8, n_classes=3)
+    labels = w.labels
+    table = w.sigma_table
+    h = w.h
+    J0, psi, E = _J_of(table[labels], h, w.a, w.omega)
+    _, gE = oracle.pnorm_objective(E)
+    gs, gt, info = oracle.adjoint(table[labels], h, w.a, psi, w.omega, gE, tol=1e-14,
+                                  labels=labels, n_labels=len(table))
+    assert info["relres"] < 1e-12
+    for t in range(1, len(table)):
+        if not np.any(labels == t):
+            continue
+        st = table[t]
+        step = 1e-6 * st
+        tp, tm = table.copy(), table.copy()
+        tp[t] += step
+        tm[t] -= step
+        fd = (_J_of(tp[labels], h, w.a, w.omega)[0] - _J_of(tm[labels], h, w.a, w.omega)[0]) / (2 * step)
+        assert abs(gt[t] - fd) <= 1e-5 * abs(fd) + 1e-9 * J0 / st, (t, gt[t], fd)
+    # per voxel, on a few voxels
+    sig = table[labels].copy()
+    body = np.argwhere(sig > 0)
+    for idx in body[:: max(1, len(body) // 6)]:
+        k, j, i = idx
+        step = 1e-6 * sig[k, j, i]
+        sp, sm = sig.copy(), sig.copy()
+        sp[k, j, i] += step
+        sm[k, j, i] -= step
+        fd = (_J_of(sp, h, w.a, w.omega)[0] - _J_of(sm, h, w.a, w.omega)[0]) / (2 * step)
+        assert abs(gs[k, j, i] - fd) <= 1e-4 * abs(fd) + 1e-7 * J0 / sig[k, j, i], (idx, gs[k, j, i], fd)
+    # Euler identity: J is invariant under sigma -> c sigma, so sum sigma_v dJ/dsigma_v = 0
+    assert abs(np.sum(sig * gs)) <= 1e-9 * np.sum(np.abs(sig * gs))
+    # per label = sum of per voxel
+    for t in range(len(table)):
+        assert abs(gt[t] - gs[labels == t].sum()) <= 1e-12 * (np.abs(gs).sum() + 1e-300)
+    assert np.all(gs[sig == 0] == 0)
