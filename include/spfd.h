@@ -1,0 +1,130 @@
+/*
+ * spfd.h -- C-ABI of the MI355X (gfx950) library for the Co-Sim. SPFD Poisson
+ * solve and E-field post-processing.
+ *
+ * The operation (paper, Sec. II, Eqs. (1) and (3); Sec. III.A; Sec. III.F):
+ *   on a voxel body model with per-voxel tissue conductivity sigma, let
+ *   M_kappa be the diagonal matrix of edge conductances
+ *       M_e = (mean sigma of the four voxels sharing edge e) * (dual facet area) / (edge length),
+ *   G the node-to-edge gradient ((G Psi)_e = Psi_head - Psi_tail) and a the
+ *   source edge potentials (line integrals of the magnetic vector potential).
+ *   Solve  G^T M_kappa G Psi = -G^T M_kappa a  (Eq. (3)) for the nodal
+ *   potentials Psi of the conducting voxels only (Sec. III.A), then form the
+ *   edge voltages e = -j omega (a + G Psi) (Eq. (1)) and the voxel-averaged
+ *   field magnitude |E| (Sec. III.F).  Eq. (3) is singular (constants per
+ *   connected conductor); the library returns the solution with zero mean
+ *   over every connected component.
+ *
+ * Index conventions (all arrays contiguous):
+ *   voxel (i,j,k)  -> i + nx*(j + ny*k)                       [nvox = nx*ny*nz]
+ *   node  (i,j,k)  -> i + (nx+1)*(j + (ny+1)*k)               [nnodes = (nx+1)(ny+1)(nz+1)]
+ *   edge arrays [3][nnodes]: entry [d][n] is the edge from node n to node n + e_d
+ *   (d = 0,1,2 = x,y,z); entries of edges that leave the grid are ignored.
+ *   Voxel (i,j,k) spans nodes i..i+1, j..j+1, k..k+1; h = (hx,hy,hz) metres.
+ *   labels: uint8 per voxel, looked up in a sigma table; sigma_table[label] = 0 is air.
+ *
+ * Memory: every array argument marked "device" is a device pointer on the
+ * handle's GPU, owned by the caller; the library never frees it and does not
+ * keep it after the call returns.  Arguments marked "host" are host memory.
+ * Work is enqueued on the stream given at creation; every call returns after
+ * its work has completed, so the caller may reuse its buffers immediately.
+ *
+ * Errors: every function returns a status; no C++ exception crosses the ABI.
+ * On SPFD_INVALID_ARG or SPFD_BAD_STATE nothing is written.  On
+ * SPFD_NOT_CONVERGED / SPFD_BREAKDOWN the best iterate and the info are still
+ * written.  spfd_last_error() gives a message for the last failing call.
+ * A handle must be used by one thread at a time.
+ */
+#ifndef SPFD_H
+#define SPFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spfd_ctx *spfd_handle;
+
+typedef enum {
+    SPFD_OK = 0,
+    SPFD_INVALID_ARG = 1,     /* bad size, pointer, NaN/negative sigma, zero conducting voxels ... */
+    SPFD_BAD_STATE = 2,       /* call order violated (geometry -> sigma -> build -> source -> solve) */
+    SPFD_OUT_OF_MEMORY = 3,
+    SPFD_HIP_ERROR = 4,
+    SPFD_NOT_CONVERGED = 5,   /* max_iter reached; best iterate written */
+    SPFD_BREAKDOWN = 6        /* non-positive or non-finite curvature in CG; best iterate written */
+} spfd_status;
+
+enum { SPFD_FP64 = 0, SPFD_MIXED = 1 };          /* precision of the multigrid cycle */
+enum { SPFD_CYCLE_V = 0, SPFD_CYCLE_K = 1 };
+
+/* Multigrid preconditioner (the paper uses an algebraic multigrid
+ * preconditioner inside a Krylov solver, Sec. III; its configuration is not
+ * given).  Zero-initialised options select the defaults. */
+typedef struct {
+    int precision;        /* SPFD_FP64 (default) or SPFD_MIXED: FP32 cycle, FP64 outer CG, dots and coarsest solve */
+    int cycle;            /* SPFD_CYCLE_V (default) or SPFD_CYCLE_K */
+    int smooth_degree;    /* Chebyshev degree per pre/post smoothing, default 2, max 4 */
+    int coarsest_max;     /* coarsen until the coarsest level has <= this many unknowns, default 400, max 1024 */
+    double cheby_ratio;   /* smoothing interval [2/ratio, 2] of D^-1 A, default 8 */
+    double coarse_scale;  /* scaling of the coarse-grid correction, default 1 */
+} spfd_amg_options;
+
+typedef struct {
+    double rel_tol;       /* stop when ||b - A Psi||_2 <= rel_tol * ||b||_2 (true residual at exit); default 1e-8 */
+    int max_iter;         /* default 500 */
+    int use_x0;           /* nonzero: psi holds the start iterate on entry */
+} spfd_solve_options;
+
+typedef struct {
+    int iterations;
+    double rel_residual;  /* true ||b - A Psi||_2 / ||b||_2 of the returned Psi */
+    int status;           /* spfd_status of this right-hand side */
+} spfd_rhs_info;
+
+/* Create a handle on HIP device `device`; `hip_stream` is a hipStream_t (NULL = default stream). */
+spfd_status spfd_create(int device, void *hip_stream, spfd_handle *out);
+void spfd_destroy(spfd_handle h);
+/* Message of the last failing call on h (valid until the next call on h). */
+const char *spfd_last_error(spfd_handle h);
+
+/* Voxel geometry (Sec. III.A): grid sizes, voxel edge lengths in metres,
+ * labels [nvox] (device, uint8).  Finds the bricks that hold conducting
+ * voxels once the conductivities are known (spfd_build). */
+spfd_status spfd_set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, double hy, double hz,
+                              const uint8_t *labels);
+/* Conductivity per label, S/m (host, n_labels <= 256, finite, >= 0; 0 = air).
+ * M_kappa at the field's frequency (Eq. (3)). */
+spfd_status spfd_set_sigma_table(spfd_handle h, const double *sigma, int n_labels);
+/* Conductivity per voxel (device, [nvox], finite, >= 0): overrides the table. */
+spfd_status spfd_set_sigma_voxel(spfd_handle h, const double *sigma_voxel);
+/* Assemble the edge conductances and build the multigrid hierarchy (opt may be NULL). */
+spfd_status spfd_build(spfd_handle h, const spfd_amg_options *opt);
+/* Sizes after build (any pointer may be NULL): unknowns, connected
+ * components, multigrid levels, device bytes held by the handle. */
+spfd_status spfd_get_info(spfd_handle h, long long *n_dofs, int *n_components, int *n_levels,
+                          size_t *device_bytes);
+/* Number of right-hand sides solved together (default 1); resets the sources. */
+spfd_status spfd_set_num_rhs(spfd_handle h, int nrhs);
+/* Right-hand side of Eq. (3) for source `rhs`: b = -G^T M_kappa a, with
+ * a [3][nnodes] (device, FP64, V*s). */
+spfd_status spfd_set_source(spfd_handle h, int rhs, const double *a);
+/* Solve Eq. (3) for every right-hand side.  psi [nrhs][nnodes] (device,
+ * FP64): start iterate on entry if opt->use_x0, on exit the solution with zero
+ * mean per connected component and 0 at nodes outside the conductor.
+ * info [nrhs] (host) may be NULL.  opt may be NULL (defaults). */
+spfd_status spfd_solve(spfd_handle h, const spfd_solve_options *opt, double *psi, spfd_rhs_info *info);
+/* Eq. (1) and the voxel average (Sec. III.F) for one source:
+ * u_edges [3][nnodes] (device, nullable) = a + G psi on conducting edges
+ * (0 elsewhere), so that Im(e) = -omega*u and Re(e) = 0;
+ * emag [nvox] (device) = omega * |mean of the voxel's d-edges / h_d| per
+ * conducting voxel, 0 in air.  a and psi as in spfd_set_source / spfd_solve. */
+spfd_status spfd_efield(spfd_handle h, double omega, const double *a, const double *psi,
+                        double *u_edges, double *emag);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPFD_H */

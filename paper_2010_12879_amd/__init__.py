@@ -1,0 +1,267 @@
+"""MI355X (gfx950) Co-Sim. SPFD solver: Python binding of ``libspfd.so``.
+
+The binding only marshals arguments: every step of the solve runs in the HIP
+kernels behind the C-ABI declared in ``include/spfd.h``.  Arrays are torch
+tensors on the GPU (PyTorch supplies device memory and the stream).  If the
+library has not been built, every entry point raises; there is no CPU path.
+
+Low-level functions carry the C names (``spfd_create``, ``spfd_set_geometry``,
+...); :class:`Solver` strings them together.
+
+Shapes (numpy/torch order, x fastest): voxel arrays (nz, ny, nx), node arrays
+(nz+1, ny+1, nx+1), edge arrays (3, nz+1, ny+1, nx+1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspfd.so")
+
+FP64, MIXED = 0, 1
+CYCLE_V, CYCLE_K = 0, 1
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "BAD_STATE", 3: "OUT_OF_MEMORY", 4: "HIP_ERROR", 5: "NOT_CONVERGED",
+          6: "BREAKDOWN"}
+
+
+class SPFDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class AmgOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("cycle", ctypes.c_int), ("smooth_degree", ctypes.c_int),
+                ("coarsest_max", ctypes.c_int), ("cheby_ratio", ctypes.c_double), ("coarse_scale", ctypes.c_double)]
+
+
+class SolveOptions(ctypes.Structure):
+    _fields_ = [("rel_tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("use_x0", ctypes.c_int)]
+
+
+class RhsInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double), ("status", ctypes.c_int)]
+
+    def as_dict(self):
+        return {"iterations": self.iterations, "rel_residual": self.rel_residual, "status": STATUS[self.status]}
+
+
+_lib = None
+EXPORTS = ["spfd_create", "spfd_destroy", "spfd_last_error", "spfd_set_geometry", "spfd_set_sigma_table",
+           "spfd_set_sigma_voxel", "spfd_build", "spfd_get_info", "spfd_set_num_rhs", "spfd_set_source",
+           "spfd_solve", "spfd_efield"]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libspfd.so (torch first, so that its HIP runtime is the one in use)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (shares one HIP runtime with the library)
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2010_12879_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    H = ctypes.c_void_p
+    lib.spfd_create.argtypes = [I, P, ctypes.POINTER(H)]
+    lib.spfd_destroy.argtypes = [H]
+    lib.spfd_destroy.restype = None
+    lib.spfd_last_error.argtypes = [H]
+    lib.spfd_last_error.restype = ctypes.c_char_p
+    lib.spfd_set_geometry.argtypes = [H, I, I, I, D, D, D, P]
+    lib.spfd_set_sigma_table.argtypes = [H, P, I]
+    lib.spfd_set_sigma_voxel.argtypes = [H, P]
+    lib.spfd_build.argtypes = [H, ctypes.POINTER(AmgOptions)]
+    lib.spfd_get_info.argtypes = [H, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I), ctypes.POINTER(I),
+                                  ctypes.POINTER(ctypes.c_size_t)]
+    lib.spfd_set_num_rhs.argtypes = [H, I]
+    lib.spfd_set_source.argtypes = [H, I, P]
+    lib.spfd_solve.argtypes = [H, ctypes.POINTER(SolveOptions), P, ctypes.POINTER(RhsInfo)]
+    lib.spfd_efield.argtypes = [H, D, P, P, P, P]
+    for name in EXPORTS:
+        if name not in ("spfd_destroy", "spfd_last_error"):
+            getattr(lib, name).restype = I
+    _lib = lib
+    return lib
+
+
+def _check(h, status, allow=()):
+    if status != 0 and status not in allow:
+        msg = load_library().spfd_last_error(h)
+        raise SPFDError(status, msg.decode() if msg else "")
+    return status
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _require_cuda(t, dtype, shape=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+# ---------------------------------------------------------------- the C names
+def spfd_create(device: int = 0, stream=None):
+    lib = load_library()
+    h = ctypes.c_void_p()
+    st = lib.spfd_create(device, ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+    if st != 0:
+        raise SPFDError(st, "spfd_create failed")
+    return h
+
+
+def spfd_destroy(h):
+    load_library().spfd_destroy(h)
+
+
+def spfd_last_error(h) -> str:
+    m = load_library().spfd_last_error(h)
+    return m.decode() if m else ""
+
+
+def spfd_set_geometry(h, nx, ny, nz, hx, hy, hz, labels):
+    import torch
+    _require_cuda(labels, torch.uint8, (nz, ny, nx), "labels")
+    return _check(h, load_library().spfd_set_geometry(h, nx, ny, nz, hx, hy, hz, _ptr(labels)))
+
+
+def spfd_set_sigma_table(h, sigma):
+    arr = (ctypes.c_double * len(sigma))(*[float(s) for s in sigma])
+    return _check(h, load_library().spfd_set_sigma_table(h, arr, len(sigma)))
+
+
+def spfd_set_sigma_voxel(h, sigma_voxel):
+    import torch
+    _require_cuda(sigma_voxel, torch.float64, None, "sigma_voxel")
+    return _check(h, load_library().spfd_set_sigma_voxel(h, _ptr(sigma_voxel)))
+
+
+def spfd_build(h, opts: AmgOptions | None = None):
+    return _check(h, load_library().spfd_build(h, ctypes.byref(opts) if opts is not None else None))
+
+
+def spfd_get_info(h):
+    nd, nc, nl, nbytes = ctypes.c_longlong(), ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+    _check(h, load_library().spfd_get_info(h, ctypes.byref(nd), ctypes.byref(nc), ctypes.byref(nl), ctypes.byref(nbytes)))
+    return {"n_dofs": nd.value, "n_components": nc.value, "n_levels": nl.value, "device_bytes": nbytes.value}
+
+
+def spfd_set_num_rhs(h, nrhs):
+    return _check(h, load_library().spfd_set_num_rhs(h, nrhs))
+
+
+def spfd_set_source(h, rhs, a):
+    import torch
+    _require_cuda(a, torch.float64, None, "a")
+    return _check(h, load_library().spfd_set_source(h, rhs, _ptr(a)))
+
+
+def spfd_solve(h, opts: SolveOptions | None, psi, nrhs: int):
+    import torch
+    _require_cuda(psi, torch.float64, None, "psi")
+    info = (RhsInfo * nrhs)()
+    st = load_library().spfd_solve(h, ctypes.byref(opts) if opts is not None else None, _ptr(psi), info)
+    _check(h, st, allow=(5, 6))
+    return st, [i.as_dict() for i in info]
+
+
+def spfd_efield(h, omega, a, psi, u_edges, emag):
+    import torch
+    for t, n in ((a, "a"), (psi, "psi"), (emag, "emag")):
+        _require_cuda(t, torch.float64, None, n)
+    if u_edges is not None:
+        _require_cuda(u_edges, torch.float64, None, "u_edges")
+    return _check(h, load_library().spfd_efield(h, float(omega), _ptr(a), _ptr(psi), _ptr(u_edges), _ptr(emag)))
+
+
+# ---------------------------------------------------------------- convenience
+class Solver:
+    """Eq. (3) solver on one voxel model; the hierarchy is reused for every source.
+
+    labels: uint8 CUDA tensor (nz, ny, nx); sigma: sequence per label (label 0 = air
+    normally) or a float64 CUDA tensor per voxel; h: voxel edge lengths (m).
+    """
+
+    def __init__(self, labels, sigma, h, precision="fp64", device=None, smooth_degree=2, coarsest_max=400,
+                 cheby_ratio=8.0, coarse_scale=1.0, cycle="v"):
+        import torch
+        self.device = labels.device if device is None else torch.device(device)
+        self.nz, self.ny, self.nx = labels.shape
+        self.h = tuple(float(v) for v in h)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        self.handle = spfd_create(self.device.index or 0, stream)
+        try:
+            spfd_set_geometry(self.handle, self.nx, self.ny, self.nz, *self.h, labels)
+            if isinstance(sigma, torch.Tensor):
+                spfd_set_sigma_voxel(self.handle, sigma)
+            else:
+                spfd_set_sigma_table(self.handle, list(sigma))
+            self.opts = AmgOptions(MIXED if precision == "mixed" else FP64, CYCLE_K if cycle == "k" else CYCLE_V,
+                                   smooth_degree, coarsest_max, cheby_ratio, coarse_scale)
+            spfd_build(self.handle, self.opts)
+        except Exception:
+            spfd_destroy(self.handle)
+            self.handle = None
+            raise
+        self.nrhs = 1
+
+    @property
+    def node_shape(self):
+        return (self.nz + 1, self.ny + 1, self.nx + 1)
+
+    def info(self):
+        return spfd_get_info(self.handle)
+
+    def set_sources(self, a):
+        """a: (3, Nz, Ny, Nx) or (nrhs, 3, Nz, Ny, Nx) float64 CUDA tensor."""
+        a = a if a.dim() == 5 else a.unsqueeze(0)
+        if tuple(a.shape[1:]) != (3,) + self.node_shape:
+            raise ValueError(f"a must have shape (nrhs, 3) + {self.node_shape}")
+        if a.shape[0] != self.nrhs:
+            spfd_set_num_rhs(self.handle, a.shape[0])
+            self.nrhs = a.shape[0]
+        for r in range(a.shape[0]):
+            spfd_set_source(self.handle, r, a[r].contiguous())
+
+    def solve(self, a=None, tol=1e-8, max_iter=500, x0=None, check=True):
+        """Psi (nrhs or none, Nz, Ny, Nx) and the per-source info dicts."""
+        import torch
+        squeeze = a is not None and a.dim() == 4
+        if a is not None:
+            self.set_sources(a)
+        if x0 is not None:
+            psi = x0.reshape((self.nrhs,) + self.node_shape).clone().contiguous()
+        else:
+            psi = torch.empty((self.nrhs,) + self.node_shape, dtype=torch.float64, device=self.device)
+        st, info = spfd_solve(self.handle, SolveOptions(tol, max_iter, 1 if x0 is not None else 0), psi, self.nrhs)
+        if check and st != 0:
+            raise SPFDError(st, spfd_last_error(self.handle))
+        return (psi[0] if squeeze else psi), (info[0] if squeeze else info)
+
+    def efield(self, a, psi, omega, want_u=False):
+        """|E| per voxel (nz, ny, nx) [and u edges (3, Nz, Ny, Nx)] for one source."""
+        import torch
+        emag = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        u = torch.empty((3,) + self.node_shape, dtype=torch.float64, device=self.device) if want_u else None
+        spfd_efield(self.handle, omega, a.contiguous(), psi.contiguous(), u, emag)
+        return (emag, u) if want_u else emag
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            spfd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

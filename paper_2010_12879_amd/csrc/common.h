@@ -1,0 +1,180 @@
+// Shared device-side definitions of the SPFD library (gfx950, wave64).
+//
+// Node arrays of every multigrid level live in 8x8x8 bricks: only bricks that
+// hold unknowns are stored, brick b occupies elements [b*512, b*512+512) and
+// node (tx,ty,tz) of a brick sits at tx + 8*ty + 64*tz.  A workgroup of 512
+// threads owns one brick, so each wave covers one 8x8 z-slice (512 contiguous
+// bytes in FP64).  Neighbour bricks come from a [nb][6] table (-1 = absent).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spfd {
+
+constexpr int BD = 8;              // brick edge in nodes
+constexpr int BS = 512;            // nodes per brick
+constexpr int TILE = 9;            // label tile edge: the brick's voxels plus one layer on the minus side
+constexpr int TILE_VOX = 729;
+constexpr int TILE_BYTES = 768;    // 729 padded
+constexpr int MAX_LABELS = 256;
+constexpr int NT = 512;            // threads per brick workgroup
+
+// neighbour slots
+enum { NMX = 0, NPX = 1, NMY = 2, NPY = 3, NMZ = 4, NPZ = 5 };
+
+// per right-hand side scalars of the outer CG, resident in device memory
+struct Scal {
+    double rz;       // r.z of the current iterate
+    double pq;       // p.q
+    double alpha;
+    double beta;
+    double rr;       // ||r||^2
+    double bb;       // ||b||^2
+    double zq;       // z.q (flexible beta)
+    double tol2;     // (rel_tol)^2 * ||b||^2
+    int done;        // 1 = converged or stopped: later kernels of this solve return at once
+    int iters;
+    int status;      // 0 ok, 5 not converged, 6 breakdown
+    int pad;
+};
+
+struct Topo {
+    int nb;              // active bricks
+    const int *nbr;      // [nb*6]
+};
+
+// XCD-aware workgroup -> brick map: the hardware hands consecutive workgroup
+// ids to the 8 XCDs in turn; giving each XCD a contiguous run of bricks keeps
+// neighbour bricks (halo reads) in the same L2.  Returns -1 for padding ids.
+__device__ __forceinline__ int xcd_brick(int wg, int nb)
+{
+    int per = (nb + 7) >> 3;
+    int b = (wg & 7) * per + (wg >> 3);
+    return b < nb ? b : -1;
+}
+
+__host__ __forceinline__ int xcd_grid(int nb) { return ((nb + 7) >> 3) << 3; }
+
+__device__ __forceinline__ void brick_xyz(int t, int &tx, int &ty, int &tz)
+{
+    tx = t & 7;
+    ty = (t >> 3) & 7;
+    tz = t >> 6;
+}
+
+// values of the six face neighbours of node t of brick b (0 where absent)
+template <typename T>
+__device__ __forceinline__ void nbr_vals(const T *__restrict__ x, long long base, int t, int tx, int ty, int tz,
+                                         const int *nb, T X[6])
+{
+    X[NMX] = tx > 0 ? x[base + t - 1] : (nb[NMX] >= 0 ? x[(long long)nb[NMX] * BS + t + 7] : T(0));
+    X[NPX] = tx < 7 ? x[base + t + 1] : (nb[NPX] >= 0 ? x[(long long)nb[NPX] * BS + t - 7] : T(0));
+    X[NMY] = ty > 0 ? x[base + t - 8] : (nb[NMY] >= 0 ? x[(long long)nb[NMY] * BS + t + 56] : T(0));
+    X[NPY] = ty < 7 ? x[base + t + 8] : (nb[NPY] >= 0 ? x[(long long)nb[NPY] * BS + t - 56] : T(0));
+    X[NMZ] = tz > 0 ? x[base + t - 64] : (nb[NMZ] >= 0 ? x[(long long)nb[NMZ] * BS + t + 448] : T(0));
+    X[NPZ] = tz < 7 ? x[base + t + 64] : (nb[NPZ] >= 0 ? x[(long long)nb[NPZ] * BS + t - 448] : T(0));
+}
+
+// edge weights of node t from stored arrays w[d*stride + node] (edge to +d);
+// the minus-side weights are the plus-side weights of the minus neighbours
+template <typename T>
+__device__ __forceinline__ void stored_weights(const T *__restrict__ w, long long stride, long long base, int t,
+                                               int tx, int ty, int tz, const int *nb, T W[6])
+{
+    const long long n = base + t;
+    W[NPX] = w[n];
+    W[NPY] = w[stride + n];
+    W[NPZ] = w[2 * stride + n];
+    W[NMX] = tx > 0 ? w[n - 1] : (nb[NMX] >= 0 ? w[(long long)nb[NMX] * BS + t + 7] : T(0));
+    W[NMY] = ty > 0 ? w[stride + n - 8] : (nb[NMY] >= 0 ? w[stride + (long long)nb[NMY] * BS + t + 56] : T(0));
+    W[NMZ] = tz > 0 ? w[2 * stride + n - 64] : (nb[NMZ] >= 0 ? w[2 * stride + (long long)nb[NMZ] * BS + t + 448] : T(0));
+}
+
+// Conductances of the six edges of a node from the conductivities of its eight
+// surrounding voxels, held in an LDS tile s[a + 9*(b + 9*c)] where (a,b,c) =
+// (tx,ty,tz) + {0,1}^3.  Edge to +x: the four voxels at a = tx+1, and so on.
+// geo4[d] = (area of the dual facet) / (length) / 4 of a d-edge.  The sums keep
+// the order (j-1,k-1), (j,k-1), (j-1,k), (j,k) of the other two axes.
+template <typename T>
+__device__ __forceinline__ void tile_weights(const T *s, int tx, int ty, int tz, const T geo4[3], T W[6])
+{
+    const T *p = s + tx + 9 * (ty + 9 * tz);
+    const T s000 = p[0], s100 = p[1], s010 = p[9], s110 = p[10];
+    const T s001 = p[81], s101 = p[82], s011 = p[90], s111 = p[91];
+    W[NPX] = (((s100 + s110) + s101) + s111) * geo4[0];
+    W[NMX] = (((s000 + s010) + s001) + s011) * geo4[0];
+    W[NPY] = (((s010 + s110) + s011) + s111) * geo4[1];
+    W[NMY] = (((s000 + s100) + s001) + s101) * geo4[1];
+    W[NPZ] = (((s001 + s101) + s011) + s111) * geo4[2];
+    W[NMZ] = (((s000 + s100) + s010) + s110) * geo4[2];
+}
+
+// (A x)_n = sum over edges of w (x_n - x_m); exact zero for a constant field
+template <typename T>
+__device__ __forceinline__ T stencil_apply(T x0, const T X[6], const T W[6])
+{
+    T y = W[0] * (x0 - X[0]);
+    y += W[1] * (x0 - X[1]);
+    y += W[2] * (x0 - X[2]);
+    y += W[3] * (x0 - X[3]);
+    y += W[4] * (x0 - X[4]);
+    y += W[5] * (x0 - X[5]);
+    return y;
+}
+
+template <typename T>
+__device__ __forceinline__ T diag_of(const T W[6])
+{
+    return ((((W[0] + W[1]) + W[2]) + W[3]) + W[4]) + W[5];
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// sum over a 512-thread block, valid in thread 0; lds needs 8 doubles
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) lds[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+        for (int i = 0; i < nw; ++i) s += lds[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+// Ticket for the deterministic two-stage reduction: every brick block writes
+// its partial, then the block that arrives last sums the partials in brick
+// order.  Returns true in all threads of that last block (counter re-armed).
+__device__ __forceinline__ bool last_block(int *counter, int nblocks, int *flag_lds)
+{
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ticket = atomicAdd(counter, 1);
+        *flag_lds = (ticket == nblocks - 1);
+        if (*flag_lds) *counter = 0;
+    }
+    __syncthreads();
+    bool last = *flag_lds != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+// fixed-order sum of n partials by one 512-thread block (valid in thread 0)
+__device__ __forceinline__ double sum_partials(const double *part, int n, double *lds)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return block_sum(s, lds);
+}
+
+}  // namespace spfd

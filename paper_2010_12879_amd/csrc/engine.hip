@@ -1,0 +1,884 @@
+// Host engine and C-ABI of the SPFD library: geometry and brick layout,
+// multigrid hierarchy, flexible preconditioned CG driver, E-field.
+//
+// Method (paper, Sec. II Eqs. (1), (3); Sec. III): Eq. (3) is solved by CG
+// preconditioned with a multigrid cycle; the paper used a closed-source
+// algebraic multigrid inside FGMRES with an unstated configuration.  Here the
+// hierarchy is a structured aggregation multigrid built for the voxel grid:
+//   * aggregates are 2x2x2 blocks of nodes; with the piecewise-constant
+//     prolongation P the Galerkin operator P^T A P of a 7-point graph
+//     Laplacian is again a 7-point graph Laplacian whose edge conductance is
+//     the sum of the four fine conductances crossing the aggregate interface;
+//   * smoothing is a Chebyshev polynomial in D^-1 A on [2/ratio, 2]; the grid
+//     graph is bipartite, so the largest eigenvalue of D^-1 A is exactly 2;
+//   * the coarsest level (<= coarsest_max unknowns) is solved with a dense
+//     FP64 pseudo-inverse;
+//   * the outer iteration is flexible CG in FP64 (alpha, beta, residual norms
+//     and the final gauge in FP64); in mixed precision the whole cycle runs in
+//     FP32.  All scalars stay on the device; the host only polls a stop flag.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "spfd.h"
+
+using namespace spfd;
+
+namespace {
+
+struct Level {
+    int N[3] = {0, 0, 0};        // nodes
+    int G[3] = {0, 0, 0};        // bricks
+    int nb = 0;
+    std::vector<int> slot_of;    // dense brick grid -> slot (host)
+    std::vector<int4> coord;     // slot -> brick coordinates (host)
+    int *d_slot_of = nullptr;
+    int *d_nbr = nullptr;
+    int4 *d_coord = nullptr;
+    int *d_parent_slot = nullptr;  // slot of the coarse brick that holds this brick (levels < last)
+    uint8_t *d_tiles = nullptr;    // finest level, label form
+    double *d_w64 = nullptr;
+    float *d_w32 = nullptr;
+    // cycle buffers (type of the cycle)
+    void *x = nullptr, *x2 = nullptr, *d = nullptr, *b = nullptr;
+    long long dofs = 0;
+    Topo topo() const { return Topo{nb, d_nbr}; }
+    long long nodes() const { return (long long)nb * BS; }
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // geometry
+    int state = 0;  // 0 created, 1 geometry, 2 sigma, 3 built, 4 sources
+    Grid g{};
+    double h[3] = {0, 0, 0};
+    double geo4[3] = {0, 0, 0};
+    uint8_t *d_labels = nullptr;
+    double *d_sigvox = nullptr;
+    bool voxel_mode = false;
+    int nlab = 0;
+    double table[MAX_LABELS];
+    double *d_table64 = nullptr;
+    float *d_table32 = nullptr;
+    // hierarchy
+    spfd_amg_options opt{};
+    std::vector<Level> lv;
+    int ncomp = 0;
+    int *d_comp = nullptr;
+    int *d_counts = nullptr;
+    double *d_means = nullptr;
+    int ncoarse = 0;
+    int *d_cdof_node = nullptr;
+    int *d_node_cdof = nullptr;
+    int *d_cadj = nullptr;
+    double *d_Ainv = nullptr;
+    int *d_cwork = nullptr;
+    std::vector<double> cheb_c1, cheb_c2;
+    double cheb_c0 = 0.0;
+    // outer CG state
+    int nrhs = 0;
+    std::vector<double *> d_b;
+    std::vector<int> has_source;
+    double *d_x = nullptr, *d_r = nullptr, *d_p = nullptr, *d_q = nullptr;
+    void *d_z = nullptr;
+    Scal *d_scal = nullptr;
+    Scal *h_scal = nullptr;   // pinned
+    double *d_part = nullptr;
+    int *d_counter = nullptr;
+    int *d_ints = nullptr;    // small scratch ints
+    int *h_ints = nullptr;    // pinned
+    // bookkeeping
+    std::vector<void *> geo_allocs, hier_allocs, rhs_allocs;
+    size_t bytes = 0;
+};
+
+struct HipFail {
+    hipError_t e;
+    const char *what;
+};
+
+#define HIPCHK(...)                                                  \
+    do {                                                             \
+        hipError_t e_ = (__VA_ARGS__);                               \
+        if (e_ != hipSuccess) throw HipFail{e_, #__VA_ARGS__};       \
+    } while (0)
+
+template <typename T>
+T *dalloc(Ctx *c, std::vector<void *> &owner, size_t count)
+{
+    void *p = nullptr;
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
+    owner.push_back(p);
+    c->bytes += bytes;
+    return (T *)p;
+}
+
+void free_all(Ctx *c, std::vector<void *> &owner)
+{
+    for (void *p : owner) (void)hipFree(p);
+    owner.clear();
+}
+
+spfd_status fail(Ctx *c, spfd_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+// ------------------------------------------------------------ brick topology on the host
+void build_topology(Ctx *c, Level &L, const std::vector<uint8_t> &flags, std::vector<void *> &owner)
+{
+    const int G0 = L.G[0], G1 = L.G[1], G2 = L.G[2];
+    L.slot_of.assign((size_t)G0 * G1 * G2, -1);
+    L.coord.clear();
+    // slots in brick-grid order (x fastest): neighbours along x are adjacent slots
+    for (int bz = 0; bz < G2; ++bz)
+        for (int by = 0; by < G1; ++by)
+            for (int bx = 0; bx < G0; ++bx) {
+                const size_t id = bx + (size_t)G0 * (by + (size_t)G1 * bz);
+                if (flags[id]) {
+                    L.slot_of[id] = (int)L.coord.size();
+                    L.coord.push_back(make_int4(bx, by, bz, 0));
+                }
+            }
+    L.nb = (int)L.coord.size();
+    std::vector<int> nbr((size_t)L.nb * 6 + 6, -1);
+    auto look = [&](int x, int y, int z) -> int {
+        if (x < 0 || y < 0 || z < 0 || x >= G0 || y >= G1 || z >= G2) return -1;
+        return L.slot_of[x + (size_t)G0 * (y + (size_t)G1 * z)];
+    };
+    for (int s = 0; s < L.nb; ++s) {
+        const int4 q = L.coord[s];
+        nbr[s * 6 + NMX] = look(q.x - 1, q.y, q.z);
+        nbr[s * 6 + NPX] = look(q.x + 1, q.y, q.z);
+        nbr[s * 6 + NMY] = look(q.x, q.y - 1, q.z);
+        nbr[s * 6 + NPY] = look(q.x, q.y + 1, q.z);
+        nbr[s * 6 + NMZ] = look(q.x, q.y, q.z - 1);
+        nbr[s * 6 + NPZ] = look(q.x, q.y, q.z + 1);
+    }
+    L.d_slot_of = dalloc<int>(c, owner, L.slot_of.size());
+    L.d_nbr = dalloc<int>(c, owner, nbr.size());
+    L.d_coord = dalloc<int4>(c, owner, L.coord.size() + 1);
+    HIPCHK(hipMemcpyAsync(L.d_slot_of, L.slot_of.data(), L.slot_of.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(L.d_nbr, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    if (L.nb)
+        HIPCHK(hipMemcpyAsync(L.d_coord, L.coord.data(), L.coord.size() * sizeof(int4), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+__global__ void k_count_dofs(const double *w, long long stride, Topo topo, int *count)
+{
+    __shared__ int nb[6];
+    __shared__ int cnt;
+    const int b = blockIdx.x, t = threadIdx.x;
+    if (t < 6) nb[t] = topo.nbr[b * 6 + t];
+    if (t == 0) cnt = 0;
+    __syncthreads();
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    double W[6];
+    stored_weights(w, stride, (long long)b * BS, t, tx, ty, tz, nb, W);
+    if (diag_of(W) > 0.0) atomicAdd(&cnt, 1);
+    __syncthreads();
+    if (t == 0 && cnt) atomicAdd(count, cnt);
+}
+
+long long count_dofs(Ctx *c, const Level &L)
+{
+    HIPCHK(hipMemsetAsync(c->d_ints, 0, sizeof(int), c->stream));
+    if (L.nb > 0) hipLaunchKernelGGL(k_count_dofs, dim3(L.nb), dim3(NT), 0, c->stream, L.d_w64, L.nodes(), L.topo(), c->d_ints);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->h_ints, c->d_ints, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return c->h_ints[0];
+}
+
+template <typename T>
+OpArgs<T> level_op(Ctx *c, int l);
+
+template <>
+OpArgs<double> level_op<double>(Ctx *c, int l)
+{
+    OpArgs<double> op{};
+    const Level &L = c->lv[l];
+    op.stride = L.nodes();
+    if (l == 0 && !c->voxel_mode) {
+        op.w = nullptr;
+        op.tiles = L.d_tiles;
+        op.table = c->d_table64;
+        op.nlab = c->nlab;
+        for (int d = 0; d < 3; ++d) op.geo4[d] = c->geo4[d];
+    } else {
+        op.w = L.d_w64;
+    }
+    return op;
+}
+
+template <>
+OpArgs<float> level_op<float>(Ctx *c, int l)
+{
+    OpArgs<float> op{};
+    const Level &L = c->lv[l];
+    op.stride = L.nodes();
+    if (l == 0 && !c->voxel_mode) {
+        op.w = nullptr;
+        op.tiles = L.d_tiles;
+        op.table = c->d_table32;
+        op.nlab = c->nlab;
+        for (int d = 0; d < 3; ++d) op.geo4[d] = (float)c->geo4[d];
+    } else {
+        op.w = L.d_w32;
+    }
+    return op;
+}
+
+// ------------------------------------------------------------ the multigrid cycle
+template <typename T>
+void smooth_pre(Ctx *c, int l, const void *bvoid, bool b_is_fp64, T *&cur, T *&other, const Scal *sc)
+{
+    Level &L = c->lv[l];
+    const OpArgs<T> op = level_op<T>(c, l);
+    const int m = c->opt.smooth_degree;
+    T *d = (T *)L.d;
+    if (b_is_fp64) {
+        const double *b = (const double *)bvoid;
+        HIPCHK(launch_cheb_first<T, double>(op, L.topo(), b, cur, (T)c->cheb_c0, sc, c->stream));
+        for (int k = 1; k < m; ++k) {
+            HIPCHK(launch_cheb_step<T, double>(op, L.topo(), b, cur, other, k == 1 ? nullptr : d, k < m - 1 ? d : nullptr,
+                                               (T)c->cheb_c1[k], (T)c->cheb_c2[k], sc, c->stream));
+            T *t = cur; cur = other; other = t;
+        }
+    } else {
+        const T *b = (const T *)bvoid;
+        HIPCHK(launch_cheb_first<T, T>(op, L.topo(), b, cur, (T)c->cheb_c0, sc, c->stream));
+        for (int k = 1; k < m; ++k) {
+            HIPCHK(launch_cheb_step<T, T>(op, L.topo(), b, cur, other, k == 1 ? nullptr : d, k < m - 1 ? d : nullptr,
+                                          (T)c->cheb_c1[k], (T)c->cheb_c2[k], sc, c->stream));
+            T *t = cur; cur = other; other = t;
+        }
+    }
+}
+
+template <typename T>
+void smooth_post(Ctx *c, int l, const void *bvoid, bool b_is_fp64, T *&cur, T *&other, const Scal *sc)
+{
+    Level &L = c->lv[l];
+    const OpArgs<T> op = level_op<T>(c, l);
+    const int m = c->opt.smooth_degree;
+    T *d = (T *)L.d;
+    for (int k = 0; k < m; ++k) {
+        const T c1 = k == 0 ? T(0) : (T)c->cheb_c1[k];
+        const T c2 = k == 0 ? (T)c->cheb_c0 : (T)c->cheb_c2[k];
+        T *din = k == 0 ? nullptr : d;
+        T *dout = k < m - 1 ? d : nullptr;
+        if (b_is_fp64)
+            HIPCHK(launch_cheb_step<T, double>(op, L.topo(), (const double *)bvoid, cur, other, din, dout, c1, c2, sc, c->stream));
+        else
+            HIPCHK(launch_cheb_step<T, T>(op, L.topo(), (const T *)bvoid, cur, other, din, dout, c1, c2, sc, c->stream));
+        T *t = cur; cur = other; other = t;
+    }
+}
+
+// z = B r: one V-cycle (T = arithmetic of the cycle); r is the FP64 outer residual
+template <typename T>
+void vcycle(Ctx *c, const double *r, T *z, const Scal *sc)
+{
+    const int nl = (int)c->lv.size();
+    std::vector<T *> res(nl, nullptr);
+    if (nl == 1) {
+        // single level: the dense solve is exact
+        HIPCHK(launch_coarse_apply<T, double>(r, z, c->d_Ainv, c->d_cdof_node, c->ncoarse, sc, c->stream));
+        return;
+    }
+    // downward: pre-smooth, restrict the residual
+    for (int l = 0; l < nl - 1; ++l) {
+        Level &L = c->lv[l];
+        T *cur = (T *)L.x2;
+        T *other = l == 0 ? z : (T *)L.x;
+        const void *b = l == 0 ? (const void *)r : L.b;
+        smooth_pre<T>(c, l, b, l == 0, cur, other, sc);
+        res[l] = cur;
+        const OpArgs<T> op = level_op<T>(c, l);
+        Level &C = c->lv[l + 1];
+        if (l == 0)
+            HIPCHK(launch_resid_restrict<T, double>(op, L.topo(), r, cur, (T *)C.b, L.d_parent_slot, L.d_coord, sc, c->stream));
+        else
+            HIPCHK(launch_resid_restrict<T, T>(op, L.topo(), (const T *)L.b, cur, (T *)C.b, L.d_parent_slot, L.d_coord, sc,
+                                               c->stream));
+    }
+    // coarsest
+    {
+        Level &C = c->lv[nl - 1];
+        HIPCHK(launch_coarse_apply<T, T>((const T *)C.b, (T *)C.x, c->d_Ainv, c->d_cdof_node, c->ncoarse, sc, c->stream));
+    }
+    // upward: prolongate and correct, post-smooth
+    for (int l = nl - 2; l >= 0; --l) {
+        Level &L = c->lv[l];
+        Level &C = c->lv[l + 1];
+        T *cur = res[l];
+        T *other = (cur == (T *)L.x2) ? (l == 0 ? z : (T *)L.x) : (T *)L.x2;
+        HIPCHK(launch_prolong<T>(L.topo(), cur, (const T *)C.x, L.d_parent_slot, L.d_coord, (T)c->opt.coarse_scale, sc,
+                                 c->stream));
+        const void *b = l == 0 ? (const void *)r : L.b;
+        smooth_post<T>(c, l, b, l == 0, cur, other, sc);
+        // the result must end in the level's output buffer
+        T *want = l == 0 ? z : (T *)L.x;
+        if (cur != want) HIPCHK(hipMemcpyAsync(want, cur, L.nodes() * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    }
+}
+
+void set_defaults(spfd_amg_options &o)
+{
+    if (o.precision != SPFD_MIXED) o.precision = SPFD_FP64;
+    if (o.cycle != SPFD_CYCLE_K) o.cycle = SPFD_CYCLE_V;
+    if (o.smooth_degree <= 0) o.smooth_degree = 2;
+    if (o.smooth_degree > 4) o.smooth_degree = 4;
+    if (o.coarsest_max <= 0) o.coarsest_max = 400;
+    if (o.coarsest_max > 1024) o.coarsest_max = 1024;
+    if (!(o.cheby_ratio > 1.0)) o.cheby_ratio = 8.0;
+    if (!(o.coarse_scale > 0.0)) o.coarse_scale = 1.0;
+}
+
+void chebyshev_coefficients(Ctx *c)
+{
+    const double lmax = 2.0, lmin = lmax / c->opt.cheby_ratio;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+    const double sigma1 = theta / delta;
+    c->cheb_c0 = 1.0 / theta;
+    c->cheb_c1.assign(8, 0.0);
+    c->cheb_c2.assign(8, 0.0);
+    double rho_prev = 1.0 / sigma1;
+    for (int k = 1; k < 8; ++k) {
+        const double rho = 1.0 / (2.0 * sigma1 - rho_prev);
+        c->cheb_c1[k] = rho * rho_prev;
+        c->cheb_c2[k] = 2.0 * rho / delta;
+        rho_prev = rho;
+    }
+}
+
+void alloc_cycle_buffers(Ctx *c)
+{
+    const bool mixed = c->opt.precision == SPFD_MIXED;
+    const size_t w = mixed ? sizeof(float) : sizeof(double);
+    for (size_t l = 0; l < c->lv.size(); ++l) {
+        Level &L = c->lv[l];
+        const size_t n = (size_t)L.nodes();
+        L.x = dalloc<uint8_t>(c, c->hier_allocs, n * w);
+        L.x2 = dalloc<uint8_t>(c, c->hier_allocs, n * w);
+        L.d = dalloc<uint8_t>(c, c->hier_allocs, n * w);
+        L.b = dalloc<uint8_t>(c, c->hier_allocs, n * w);
+        HIPCHK(hipMemsetAsync(L.x, 0, n * w, c->stream));
+        HIPCHK(hipMemsetAsync(L.x2, 0, n * w, c->stream));
+        HIPCHK(hipMemsetAsync(L.d, 0, n * w, c->stream));
+        HIPCHK(hipMemsetAsync(L.b, 0, n * w, c->stream));
+    }
+    const size_t n0 = (size_t)c->lv[0].nodes();
+    c->d_x = dalloc<double>(c, c->hier_allocs, n0);
+    c->d_r = dalloc<double>(c, c->hier_allocs, n0);
+    c->d_p = dalloc<double>(c, c->hier_allocs, n0);
+    c->d_q = dalloc<double>(c, c->hier_allocs, n0);
+    c->d_z = dalloc<uint8_t>(c, c->hier_allocs, n0 * w);
+    HIPCHK(hipMemsetAsync(c->d_z, 0, n0 * w, c->stream));
+    HIPCHK(hipMemsetAsync(c->d_p, 0, n0 * sizeof(double), c->stream));
+    HIPCHK(hipMemsetAsync(c->d_q, 0, n0 * sizeof(double), c->stream));
+}
+
+spfd_status do_build(Ctx *c)
+{
+    free_all(c, c->hier_allocs);
+    free_all(c, c->rhs_allocs);
+    c->lv.clear();
+    c->d_b.clear();
+    c->has_source.clear();
+    c->nrhs = 0;
+    Grid &g = c->g;
+    // 1. bricks of the finest level + input validation
+    const size_t nbg = (size_t)g.Gx * g.Gy * g.Gz;
+    uint8_t *d_flags = dalloc<uint8_t>(c, c->hier_allocs, nbg);
+    HIPCHK(hipMemsetAsync(d_flags, 0, nbg, c->stream));
+    HIPCHK(hipMemsetAsync(c->d_ints, 0, 4 * sizeof(int), c->stream));
+    HIPCHK(launch_brick_flags(c->d_labels, c->d_table64, c->nlab, c->voxel_mode ? c->d_sigvox : nullptr, g, d_flags,
+                              c->d_ints, c->stream));
+    std::vector<uint8_t> flags(nbg);
+    HIPCHK(hipMemcpyAsync(flags.data(), d_flags, nbg, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_ints, c->d_ints, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->h_ints[0] == 1) return fail(c, SPFD_INVALID_ARG, "a voxel label is not covered by the sigma table");
+    if (c->h_ints[0] == 2) return fail(c, SPFD_INVALID_ARG, "per-voxel sigma must be finite and >= 0");
+    c->lv.emplace_back();
+    Level &L0 = c->lv[0];
+    L0.N[0] = g.Nx; L0.N[1] = g.Ny; L0.N[2] = g.Nz;
+    L0.G[0] = g.Gx; L0.G[1] = g.Gy; L0.G[2] = g.Gz;
+    build_topology(c, L0, flags, c->hier_allocs);
+    if (L0.nb == 0) return fail(c, SPFD_INVALID_ARG, "no conducting voxel");
+    if ((long long)L0.nb * BS > 0x7fffffffLL) return fail(c, SPFD_INVALID_ARG, "grid too large");
+    // 2. finest-level conductances (stored FP64 for setup; label tiles for the solve)
+    L0.d_w64 = dalloc<double>(c, c->hier_allocs, (size_t)3 * L0.nodes());
+    L0.d_w32 = dalloc<float>(c, c->hier_allocs, (size_t)3 * L0.nodes());
+    HIPCHK(launch_weights0(c->d_labels, c->d_table64, c->voxel_mode ? c->d_sigvox : nullptr, g, c->geo4, L0.d_coord,
+                           L0.nb, L0.d_w64, L0.d_w32, c->stream));
+    if (!c->voxel_mode) {
+        L0.d_tiles = dalloc<uint8_t>(c, c->hier_allocs, (size_t)L0.nb * TILE_BYTES);
+        HIPCHK(launch_label_tiles(c->d_labels, g, L0.d_coord, L0.nb, L0.d_tiles, c->stream));
+    }
+    // 3. connected components of the conductor (the gauge of Eq. (3))
+    {
+        const long long n = L0.nodes();
+        int *parent = dalloc<int>(c, c->hier_allocs, n);
+        int *flag = dalloc<int>(c, c->hier_allocs, n);
+        int *idx = dalloc<int>(c, c->hier_allocs, n);
+        int *tmp = dalloc<int>(c, c->hier_allocs, n / 2048 + 2);
+        c->d_comp = dalloc<int>(c, c->hier_allocs, n);
+        HIPCHK(launch_components(L0.d_w64, n, L0.topo(), parent, flag, idx, tmp, c->d_comp, nullptr, c->d_ints, c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_ints, c->d_ints, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        c->ncomp = c->h_ints[0];
+        c->d_counts = dalloc<int>(c, c->hier_allocs, c->ncomp + 1);
+        c->d_means = dalloc<double>(c, c->hier_allocs, c->ncomp + 1);
+        HIPCHK(hipMemsetAsync(c->d_counts, 0, (c->ncomp + 1) * sizeof(int), c->stream));
+        HIPCHK(launch_comp_counts(c->d_comp, n, c->d_counts, c->stream));
+    }
+    L0.dofs = count_dofs(c, L0);
+    // 4. coarsening: 2x2x2 aggregation until the level is small enough
+    while (c->lv.back().dofs > c->opt.coarsest_max && c->lv.size() < 20) {
+        Level &F = c->lv.back();
+        Level C;
+        for (int d = 0; d < 3; ++d) {
+            C.N[d] = (F.N[d] + 1) / 2;
+            C.G[d] = (C.N[d] + 7) / 8;
+        }
+        if (F.N[0] == 1 && F.N[1] == 1 && F.N[2] == 1) break;
+        std::vector<uint8_t> cflags((size_t)C.G[0] * C.G[1] * C.G[2], 0);
+        for (int s = 0; s < F.nb; ++s) {
+            const int4 q = F.coord[s];
+            cflags[(q.x >> 1) + (size_t)C.G[0] * ((q.y >> 1) + (size_t)C.G[1] * (q.z >> 1))] = 1;
+        }
+        build_topology(c, C, cflags, c->hier_allocs);
+        std::vector<int> ps(F.nb);
+        for (int s = 0; s < F.nb; ++s) {
+            const int4 q = F.coord[s];
+            ps[s] = C.slot_of[(q.x >> 1) + (size_t)C.G[0] * ((q.y >> 1) + (size_t)C.G[1] * (q.z >> 1))];
+        }
+        F.d_parent_slot = dalloc<int>(c, c->hier_allocs, F.nb);
+        HIPCHK(hipMemcpyAsync(F.d_parent_slot, ps.data(), ps.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        C.d_w64 = dalloc<double>(c, c->hier_allocs, (size_t)3 * C.nodes());
+        C.d_w32 = dalloc<float>(c, c->hier_allocs, (size_t)3 * C.nodes());
+        HIPCHK(launch_galerkin(F.d_w64, F.nodes(), F.d_slot_of, F.G[0], F.G[1], F.G[2], F.N[0], F.N[1], F.N[2], C.d_coord,
+                               C.nb, C.d_w64, C.d_w32, C.nodes(), c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        c->lv.push_back(std::move(C));
+        c->lv.back().dofs = count_dofs(c, c->lv.back());
+    }
+    // 5. coarsest level: dense pseudo-inverse
+    {
+        Level &C = c->lv.back();
+        const int maxd = 1024;
+        c->d_node_cdof = dalloc<int>(c, c->hier_allocs, C.nodes());
+        c->d_cdof_node = dalloc<int>(c, c->hier_allocs, maxd);
+        c->d_cadj = dalloc<int>(c, c->hier_allocs, (size_t)maxd * 6);
+        HIPCHK(launch_coarse_setup(C.d_w64, C.nodes(), C.topo(), c->d_node_cdof, c->d_cdof_node, c->d_cadj, c->d_ints,
+                                   maxd, c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_ints, c->d_ints, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        c->ncoarse = c->h_ints[0];
+        if (c->ncoarse > maxd)
+            return fail(c, SPFD_INVALID_ARG, "coarsest level too large (grid cannot be coarsened further)");
+        c->d_Ainv = dalloc<double>(c, c->hier_allocs, (size_t)c->ncoarse * c->ncoarse + 1);
+        c->d_cwork = dalloc<int>(c, c->hier_allocs, (size_t)5 * maxd + 8);
+        HIPCHK(launch_coarse_factor(C.d_w64, C.nodes(), C.topo(), c->d_node_cdof, c->d_cdof_node, c->d_cadj, c->ncoarse,
+                                    c->d_Ainv, c->d_cwork, c->stream));
+    }
+    chebyshev_coefficients(c);
+    alloc_cycle_buffers(c);
+    c->d_part = dalloc<double>(c, c->hier_allocs, (size_t)2 * c->lv[0].nb + 64);
+    c->d_counter = dalloc<int>(c, c->hier_allocs, 16);
+    HIPCHK(hipMemsetAsync(c->d_counter, 0, 16 * sizeof(int), c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return SPFD_OK;
+}
+
+spfd_status do_set_num_rhs(Ctx *c, int nrhs)
+{
+    free_all(c, c->rhs_allocs);
+    c->d_b.assign(nrhs, nullptr);
+    c->has_source.assign(nrhs, 0);
+    const size_t n0 = (size_t)c->lv[0].nodes();
+    for (int i = 0; i < nrhs; ++i) c->d_b[i] = dalloc<double>(c, c->rhs_allocs, n0);
+    c->d_scal = dalloc<Scal>(c, c->rhs_allocs, nrhs);
+    HIPCHK(hipMemsetAsync(c->d_scal, 0, nrhs * sizeof(Scal), c->stream));
+    if (c->h_scal) (void)hipHostFree(c->h_scal);
+    c->h_scal = nullptr;
+    HIPCHK(hipHostMalloc((void **)&c->h_scal, sizeof(Scal) * nrhs, hipHostMallocDefault));
+    c->nrhs = nrhs;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return SPFD_OK;
+}
+
+template <typename T>
+void pcg_iterations(Ctx *c, int rhs, const spfd_solve_options &so, bool first_pass)
+{
+    Level &L0 = c->lv[0];
+    const Topo topo = L0.topo();
+    const OpArgs<double> op = level_op<double>(c, 0);
+    Scal *sc = c->d_scal + rhs;
+    T *z = (T *)c->d_z;
+    (void)first_pass;
+    vcycle<T>(c, c->d_r, z, sc);
+    HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, c->d_counter, sc, 1, c->stream));
+    HIPCHK(launch_pupdate<T>(topo, z, c->d_p, sc, 1, c->stream));
+    const int chunk = 1;
+    for (int it = 0; it < so.max_iter + 1; it += chunk) {
+        for (int k = 0; k < chunk; ++k) {
+            HIPCHK(launch_spmv_dot(op, topo, c->d_p, c->d_q, c->d_part, c->d_counter, sc, c->stream));
+            HIPCHK(launch_update(topo, c->d_x, c->d_r, c->d_p, c->d_q, c->d_part, c->d_counter, sc, so.max_iter, c->stream));
+            vcycle<T>(c, c->d_r, z, sc);
+            HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, c->d_counter, sc, 0, c->stream));
+            HIPCHK(launch_pupdate<T>(topo, z, c->d_p, sc, 0, c->stream));
+        }
+        HIPCHK(hipMemcpyAsync(c->h_scal + rhs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (c->h_scal[rhs].done) break;
+    }
+}
+
+__global__ void k_rearm(Scal *sc, double tol2, int keep_iters)
+{
+    if (threadIdx.x == 0) {
+        sc->done = 0;
+        sc->status = 0;
+        sc->tol2 = tol2;
+        if (!keep_iters) sc->iters = 0;
+    }
+}
+
+spfd_status do_solve(Ctx *c, const spfd_solve_options &so, double *psi, spfd_rhs_info *info)
+{
+    Level &L0 = c->lv[0];
+    const Topo topo = L0.topo();
+    const OpArgs<double> op = level_op<double>(c, 0);
+    const long long n0 = L0.nodes();
+    const bool mixed = c->opt.precision == SPFD_MIXED;
+    const long long nn = (long long)c->g.Nx * c->g.Ny * c->g.Nz;
+    spfd_status worst = SPFD_OK;
+    for (int rhs = 0; rhs < c->nrhs; ++rhs) {
+        Scal *sc = c->d_scal + rhs;
+        double *psi_r = psi + (long long)rhs * nn;
+        // start: x0 = 0 (r = b) or the caller's iterate (r = b - A x0)
+        HIPCHK(launch_scal_init(sc, so.rel_tol, so.use_x0, c->stream));
+        if (so.use_x0) {
+            HIPCHK(launch_psi_in(psi_r, c->d_comp, L0.d_coord, L0.nb, c->g, c->d_x, c->stream));
+            HIPCHK(launch_resid(op, topo, c->d_b[rhs], c->d_x, c->d_r, c->d_part, c->d_counter, sc, 0, c->stream));
+        } else {
+            HIPCHK(hipMemsetAsync(c->d_x, 0, n0 * sizeof(double), c->stream));
+            HIPCHK(hipMemcpyAsync(c->d_r, c->d_b[rhs], n0 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        }
+        HIPCHK(hipMemcpyAsync(c->h_scal + rhs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        const double bb = c->h_scal[rhs].bb;
+        double relres = 0.0;
+        int status = 0, iters = 0;
+        if (bb > 0.0 && !c->h_scal[rhs].done) {
+            for (int pass = 0; pass < 3; ++pass) {
+                if (mixed)
+                    pcg_iterations<float>(c, rhs, so, pass == 0);
+                else
+                    pcg_iterations<double>(c, rhs, so, pass == 0);
+                // true residual of the iterate
+                HIPCHK(launch_resid(op, topo, c->d_b[rhs], c->d_x, c->d_r, c->d_part, c->d_counter, sc, 1, c->stream));
+                HIPCHK(hipMemcpyAsync(c->h_scal + rhs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+                HIPCHK(hipStreamSynchronize(c->stream));
+                const Scal &hs = c->h_scal[rhs];
+                relres = sqrt(hs.zq / bb);
+                status = hs.status;
+                iters = hs.iters;
+                if (status != 0 || relres <= so.rel_tol || iters >= so.max_iter) break;
+                // the recursive residual drifted from the true one: restart from the true residual
+                hipLaunchKernelGGL(k_rearm, dim3(1), dim3(64), 0, c->stream, sc, so.rel_tol * so.rel_tol * bb, 1);
+                HIPCHK(hipGetLastError());
+            }
+            if (status == 0 && relres > so.rel_tol) status = SPFD_NOT_CONVERGED;
+        } else if (bb > 0.0) {
+            // the start iterate already satisfies the criterion
+            HIPCHK(launch_resid(op, topo, c->d_b[rhs], c->d_x, nullptr, c->d_part, c->d_counter, sc, 1, c->stream));
+            HIPCHK(hipMemcpyAsync(c->h_scal + rhs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            relres = sqrt(c->h_scal[rhs].zq / bb);
+        }
+        // gauge: zero mean per connected component, 0 outside the conductor
+        HIPCHK(launch_comp_mean(topo, c->d_x, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_part, c->d_counter,
+                                c->stream));
+        HIPCHK(launch_psi_out(c->d_x, c->d_comp, c->d_means, L0.d_slot_of, c->g, psi_r, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (info) {
+            info[rhs].iterations = iters;
+            info[rhs].rel_residual = relres;
+            info[rhs].status = status;
+        }
+        if (status != 0 && worst == SPFD_OK) worst = (spfd_status)status;
+    }
+    if (worst != SPFD_OK)
+        c->err = worst == SPFD_BREAKDOWN ? "breakdown in CG (non-positive curvature or non-finite value)"
+                                         : "maximum iteration count reached";
+    return worst;
+}
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+// ============================================================================
+// C-ABI
+// ============================================================================
+struct spfd_ctx : Ctx {};
+
+#define API_GUARD(c)                                                                 \
+    catch (const HipFail &f)                                                         \
+    {                                                                                \
+        (c)->err = std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.e); \
+        return f.e == hipErrorOutOfMemory ? SPFD_OUT_OF_MEMORY : SPFD_HIP_ERROR;     \
+    }                                                                                \
+    catch (...)                                                                      \
+    {                                                                                \
+        (c)->err = "internal error";                                                 \
+        return SPFD_HIP_ERROR;                                                       \
+    }
+
+extern "C" {
+
+spfd_status spfd_create(int device, void *hip_stream, spfd_handle *out)
+{
+    if (!out) return SPFD_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SPFD_INVALID_ARG;
+    spfd_ctx *c = new (std::nothrow) spfd_ctx();
+    if (!c) return SPFD_OUT_OF_MEMORY;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    try {
+        HIPCHK(hipSetDevice(device));
+        c->d_ints = dalloc<int>(c, c->geo_allocs, 64);
+        HIPCHK(hipHostMalloc((void **)&c->h_ints, 64 * sizeof(int), hipHostMallocDefault));
+    } catch (const HipFail &f) {
+        delete c;
+        return f.e == hipErrorOutOfMemory ? SPFD_OUT_OF_MEMORY : SPFD_HIP_ERROR;
+    }
+    *out = c;
+    return SPFD_OK;
+}
+
+void spfd_destroy(spfd_handle h)
+{
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    free_all(h, h->rhs_allocs);
+    free_all(h, h->hier_allocs);
+    free_all(h, h->geo_allocs);
+    if (h->h_scal) (void)hipHostFree(h->h_scal);
+    if (h->h_ints) (void)hipHostFree(h->h_ints);
+    delete h;
+}
+
+const char *spfd_last_error(spfd_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+spfd_status spfd_set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, double hy, double hz,
+                              const uint8_t *labels)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (nx <= 0 || ny <= 0 || nz <= 0) return fail(h, SPFD_INVALID_ARG, "grid sizes must be positive");
+    if (!finite_pos(hx) || !finite_pos(hy) || !finite_pos(hz)) return fail(h, SPFD_INVALID_ARG, "voxel sizes must be finite and positive");
+    if (!labels) return fail(h, SPFD_INVALID_ARG, "labels is NULL");
+    const long long nvox = (long long)nx * ny * nz;
+    const long long nn = (long long)(nx + 1) * (ny + 1) * (nz + 1);
+    if (nn > 0x7fffffffLL * 4) return fail(h, SPFD_INVALID_ARG, "grid too large");
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        free_all(h, h->rhs_allocs);
+        free_all(h, h->hier_allocs);
+        for (void *p : h->geo_allocs) (void)hipFree(p);
+        h->geo_allocs.clear();
+        h->bytes = 0;
+        h->d_ints = dalloc<int>(h, h->geo_allocs, 64);
+        h->lv.clear();
+        h->g.nx = nx; h->g.ny = ny; h->g.nz = nz;
+        h->g.Nx = nx + 1; h->g.Ny = ny + 1; h->g.Nz = nz + 1;
+        h->g.Gx = (nx + 1 + 7) / 8; h->g.Gy = (ny + 1 + 7) / 8; h->g.Gz = (nz + 1 + 7) / 8;
+        h->h[0] = hx; h->h[1] = hy; h->h[2] = hz;
+        // dual facet area / edge length / 4 (one quarter per voxel sharing the edge)
+        h->geo4[0] = 0.25 * (hy * hz / hx);
+        h->geo4[1] = 0.25 * (hx * hz / hy);
+        h->geo4[2] = 0.25 * (hx * hy / hz);
+        h->d_labels = dalloc<uint8_t>(h, h->geo_allocs, nvox);
+        HIPCHK(hipMemcpyAsync(h->d_labels, labels, nvox, hipMemcpyDefault, h->stream));
+        h->d_table64 = dalloc<double>(h, h->geo_allocs, MAX_LABELS);
+        h->d_table32 = dalloc<float>(h, h->geo_allocs, MAX_LABELS);
+        h->d_sigvox = nullptr;
+        h->voxel_mode = false;
+        h->nlab = 0;
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->state = 1;
+        return SPFD_OK;
+    }
+    API_GUARD(h)
+}
+
+spfd_status spfd_set_sigma_table(spfd_handle h, const double *sigma, int n_labels)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (h->state < 1) return fail(h, SPFD_BAD_STATE, "set_geometry first");
+    if (!sigma || n_labels <= 0 || n_labels > MAX_LABELS) return fail(h, SPFD_INVALID_ARG, "need 1..256 labels");
+    for (int i = 0; i < n_labels; ++i)
+        if (!isfinite(sigma[i]) || sigma[i] < 0.0) return fail(h, SPFD_INVALID_ARG, "sigma must be finite and >= 0");
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        float t32[MAX_LABELS];
+        for (int i = 0; i < MAX_LABELS; ++i) {
+            h->table[i] = i < n_labels ? sigma[i] : 0.0;
+            t32[i] = (float)h->table[i];
+        }
+        HIPCHK(hipMemcpyAsync(h->d_table64, h->table, sizeof(double) * MAX_LABELS, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->d_table32, t32, sizeof(float) * MAX_LABELS, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->nlab = n_labels;
+        h->voxel_mode = false;
+        h->state = 2;
+        return SPFD_OK;
+    }
+    API_GUARD(h)
+}
+
+spfd_status spfd_set_sigma_voxel(spfd_handle h, const double *sigma_voxel)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (h->state < 1) return fail(h, SPFD_BAD_STATE, "set_geometry first");
+    if (!sigma_voxel) return fail(h, SPFD_INVALID_ARG, "sigma_voxel is NULL");
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        const long long nvox = (long long)h->g.nx * h->g.ny * h->g.nz;
+        if (!h->d_sigvox) h->d_sigvox = dalloc<double>(h, h->geo_allocs, nvox);
+        HIPCHK(hipMemcpyAsync(h->d_sigvox, sigma_voxel, nvox * sizeof(double), hipMemcpyDefault, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->voxel_mode = true;
+        if (h->nlab == 0) h->nlab = 1;
+        h->state = 2;
+        return SPFD_OK;
+    }
+    API_GUARD(h)
+}
+
+spfd_status spfd_build(spfd_handle h, const spfd_amg_options *opt)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (h->state < 2) return fail(h, SPFD_BAD_STATE, "set geometry and conductivities first");
+    spfd_amg_options o{};
+    if (opt) o = *opt;
+    set_defaults(o);
+    h->opt = o;
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        spfd_status s = do_build(h);
+        if (s != SPFD_OK) {
+            h->state = 2;
+            return s;
+        }
+        h->state = 3;
+        return do_set_num_rhs(h, 1);
+    }
+    API_GUARD(h)
+}
+
+spfd_status spfd_get_info(spfd_handle h, long long *n_dofs, int *n_components, int *n_levels, size_t *device_bytes)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (h->state < 3) return fail(h, SPFD_BAD_STATE, "build first");
+    if (n_dofs) *n_dofs = h->lv[0].dofs;
+    if (n_components) *n_components = h->ncomp;
+    if (n_levels) *n_levels = (int)h->lv.size();
+    if (device_bytes) *device_bytes = h->bytes;
+    return SPFD_OK;
+}
+
+spfd_status spfd_set_num_rhs(spfd_handle h, int nrhs)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (h->state < 3) return fail(h, SPFD_BAD_STATE, "build first");
+    if (nrhs <= 0 || nrhs > 4096) return fail(h, SPFD_INVALID_ARG, "nrhs must be in 1..4096");
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        return do_set_num_rhs(h, nrhs);
+    }
+    API_GUARD(h)
+}
+
+spfd_status spfd_set_source(spfd_handle h, int rhs, const double *a)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (h->state < 3) return fail(h, SPFD_BAD_STATE, "build first");
+    if (rhs < 0 || rhs >= h->nrhs) return fail(h, SPFD_INVALID_ARG, "rhs index out of range");
+    if (!a) return fail(h, SPFD_INVALID_ARG, "a is NULL");
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        Level &L0 = h->lv[0];
+        HIPCHK(hipMemsetAsync(h->d_scal + rhs, 0, sizeof(Scal), h->stream));
+        HIPCHK(launch_rhs(level_op<double>(h, 0), L0.topo(), L0.d_coord, h->g, a, h->d_b[rhs], h->d_part, h->d_counter,
+                          h->d_scal + rhs, h->stream));
+        HIPCHK(hipMemcpyAsync(h->h_scal + rhs, h->d_scal + rhs, sizeof(Scal), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (!isfinite(h->h_scal[rhs].bb)) return fail(h, SPFD_INVALID_ARG, "source potentials must be finite");
+        h->has_source[rhs] = 1;
+        h->state = 4;
+        return SPFD_OK;
+    }
+    API_GUARD(h)
+}
+
+spfd_status spfd_solve(spfd_handle h, const spfd_solve_options *opt, double *psi, spfd_rhs_info *info)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (h->state < 4) return fail(h, SPFD_BAD_STATE, "set the sources first");
+    for (int i = 0; i < h->nrhs; ++i)
+        if (!h->has_source[i]) return fail(h, SPFD_BAD_STATE, "a right-hand side has no source");
+    if (!psi) return fail(h, SPFD_INVALID_ARG, "psi is NULL");
+    spfd_solve_options so{};
+    so.rel_tol = 1e-8;
+    so.max_iter = 500;
+    if (opt) so = *opt;
+    if (!(so.rel_tol > 0.0) || !isfinite(so.rel_tol)) return fail(h, SPFD_INVALID_ARG, "rel_tol must be positive");
+    if (so.max_iter <= 0) return fail(h, SPFD_INVALID_ARG, "max_iter must be positive");
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        return do_solve(h, so, psi, info);
+    }
+    API_GUARD(h)
+}
+
+spfd_status spfd_efield(spfd_handle h, double omega, const double *a, const double *psi, double *u_edges, double *emag)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (h->state < 2) return fail(h, SPFD_BAD_STATE, "set geometry and conductivities first");
+    if (!a || !psi || !emag) return fail(h, SPFD_INVALID_ARG, "a, psi and emag are required");
+    if (!isfinite(omega)) return fail(h, SPFD_INVALID_ARG, "omega must be finite");
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        const double *sv = h->voxel_mode ? h->d_sigvox : nullptr;
+        HIPCHK(launch_efield(h->d_labels, h->d_table64, sv, h->g, h->h, omega, a, psi, emag, h->stream));
+        if (u_edges) HIPCHK(launch_uedges(h->d_labels, h->d_table64, sv, h->g, a, psi, u_edges, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return SPFD_OK;
+    }
+    API_GUARD(h)
+}
+
+}  // extern "C"

@@ -1,0 +1,1307 @@
+// HIP kernels of the SPFD library for gfx950 (CDNA4, wave64).
+//
+// Paper: Sec. II (Eqs. (1), (3)), Sec. III.A (unknowns only in conducting
+// voxels), Sec. III.F (voxel-averaged field).  The multigrid method replaces
+// the paper's closed-library algebraic multigrid; see engine.hip.
+#include <math.h>
+
+#include "kernels.h"
+
+namespace spfd {
+
+// ============================================================================
+// shared per-workgroup operator state
+// ============================================================================
+
+// LDS for a brick workgroup: neighbour slots, and for the label operator the
+// sigma table and the 9x9x9 conductivity tile of the brick's voxels.
+template <typename T>
+struct BrickLds {
+    int nb[6];
+    int flag;
+    double red[8];
+    T tab[MAX_LABELS];
+    T tile[TILE_VOX + 7];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_nbr(const Topo &topo, int b, BrickLds<T> &L)
+{
+    if (threadIdx.x < 6) L.nb[threadIdx.x] = topo.nbr[b * 6 + threadIdx.x];
+}
+
+template <typename T>
+__device__ __forceinline__ void load_tile(const OpArgs<T> &op, int b, BrickLds<T> &L)
+{
+    for (int i = threadIdx.x; i < op.nlab; i += blockDim.x) L.tab[i] = op.table[i];
+    __syncthreads();
+    const uint8_t *tl = op.tiles + (long long)b * TILE_BYTES;
+    for (int i = threadIdx.x; i < TILE_VOX; i += blockDim.x) {
+        const int lab = tl[i];
+        L.tile[i] = lab < op.nlab ? L.tab[lab] : T(0);
+    }
+}
+
+// weights of node t of brick b (after load_nbr/load_tile and a barrier)
+template <typename T>
+__device__ __forceinline__ void op_weights(const OpArgs<T> &op, const BrickLds<T> &L, long long base, int t, int tx,
+                                           int ty, int tz, T W[6])
+{
+    if (op.w) {
+        stored_weights(op.w, op.stride, base, t, tx, ty, tz, L.nb, W);
+    } else {
+        tile_weights(L.tile, tx, ty, tz, op.geo4, W);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void op_prepare(const OpArgs<T> &op, const Topo &topo, int b, BrickLds<T> &L)
+{
+    load_nbr(topo, b, L);
+    if (!op.w) load_tile(op, b, L);
+    __syncthreads();
+}
+
+// ============================================================================
+// setup kernels
+// ============================================================================
+
+// Mark the finest-level bricks that contain a node of a conducting voxel and
+// validate labels / conductivities (err: 1 = label out of table, 2 = bad sigma).
+__global__ void k_brick_flags(const uint8_t *__restrict__ labels, const double *__restrict__ table, int nlab,
+                              const double *__restrict__ sig_vox, Grid g, uint8_t *flags, int *err)
+{
+    const long long nvox = (long long)g.nx * g.ny * g.nz;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox;
+         v += (long long)gridDim.x * blockDim.x) {
+        double s;
+        if (sig_vox) {
+            s = sig_vox[v];
+            if (!(s >= 0.0) || !isfinite(s)) { *err = 2; continue; }
+        } else {
+            const int lab = labels[v];
+            if (lab >= nlab) { *err = 1; continue; }
+            s = table[lab];
+        }
+        if (!(s > 0.0)) continue;
+        const int i = (int)(v % g.nx), j = (int)((v / g.nx) % g.ny), k = (int)(v / ((long long)g.nx * g.ny));
+        for (int c = 0; c < 8; ++c) {
+            const int bi = (i + (c & 1)) >> 3, bj = (j + ((c >> 1) & 1)) >> 3, bk = (k + (c >> 2)) >> 3;
+            flags[bi + (long long)g.Gx * (bj + (long long)g.Gy * bk)] = 1;
+        }
+    }
+}
+
+hipError_t launch_brick_flags(const uint8_t *labels, const double *table, int nlab, const double *sig_vox,
+                              const Grid &g, uint8_t *flags, int *err, hipStream_t s)
+{
+    const long long nvox = (long long)g.nx * g.ny * g.nz;
+    long long blocks = (nvox + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_brick_flags, dim3((unsigned)blocks), dim3(256), 0, s, labels, table, nlab, sig_vox, g,
+                       flags, err);
+    return hipGetLastError();
+}
+
+// label tile of a brick: voxels (8*bx - 1 + a, 8*by - 1 + b, 8*bz - 1 + c), a,b,c in 0..8; outside = air (0)
+__global__ void k_label_tiles(const uint8_t *__restrict__ labels, Grid g, const int4 *__restrict__ coord,
+                              uint8_t *tiles)
+{
+    const int b = blockIdx.x;
+    const int4 c = coord[b];
+    for (int idx = threadIdx.x; idx < TILE_BYTES; idx += blockDim.x) {
+        uint8_t lab = 0;
+        if (idx < TILE_VOX) {
+            const int a = idx % 9, bb = (idx / 9) % 9, cc = idx / 81;
+            const int i = c.x * 8 - 1 + a, j = c.y * 8 - 1 + bb, k = c.z * 8 - 1 + cc;
+            if (i >= 0 && j >= 0 && k >= 0 && i < g.nx && j < g.ny && k < g.nz)
+                lab = labels[i + (long long)g.nx * (j + (long long)g.ny * k)];
+        }
+        tiles[(long long)b * TILE_BYTES + idx] = lab;
+    }
+}
+
+hipError_t launch_label_tiles(const uint8_t *labels, const Grid &g, const int4 *coord, int nb, uint8_t *tiles,
+                              hipStream_t s)
+{
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_label_tiles, dim3(nb), dim3(256), 0, s, labels, g, coord, tiles);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ double vox_sig(const uint8_t *labels, const double *table, const double *sig_vox,
+                                          const Grid &g, int i, int j, int k)
+{
+    if (i < 0 || j < 0 || k < 0 || i >= g.nx || j >= g.ny || k >= g.nz) return 0.0;
+    const long long v = i + (long long)g.nx * (j + (long long)g.ny * k);
+    return sig_vox ? sig_vox[v] : table[labels[v]];
+}
+
+// Stored finest-level conductances M_e (Eq. (3)) for the edges to +x, +y, +z
+// of every brick node: mean sigma of the 4 voxels sharing the edge times
+// dual area / length.
+__global__ void k_weights0(const uint8_t *__restrict__ labels, const double *__restrict__ table,
+                           const double *__restrict__ sig_vox, Grid g, double gx, double gy, double gz,
+                           const int4 *__restrict__ coord, double *w64, float *w32, long long stride)
+{
+    const int b = blockIdx.x, t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const int4 c = coord[b];
+    const int i = c.x * 8 + tx, j = c.y * 8 + ty, k = c.z * 8 + tz;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    if (i < g.Nx && j < g.Ny && k < g.Nz) {
+        sx = ((vox_sig(labels, table, sig_vox, g, i, j - 1, k - 1) + vox_sig(labels, table, sig_vox, g, i, j, k - 1)) +
+              vox_sig(labels, table, sig_vox, g, i, j - 1, k)) + vox_sig(labels, table, sig_vox, g, i, j, k);
+        sy = ((vox_sig(labels, table, sig_vox, g, i - 1, j, k - 1) + vox_sig(labels, table, sig_vox, g, i, j, k - 1)) +
+              vox_sig(labels, table, sig_vox, g, i - 1, j, k)) + vox_sig(labels, table, sig_vox, g, i, j, k);
+        sz = ((vox_sig(labels, table, sig_vox, g, i - 1, j - 1, k) + vox_sig(labels, table, sig_vox, g, i, j - 1, k)) +
+              vox_sig(labels, table, sig_vox, g, i - 1, j, k)) + vox_sig(labels, table, sig_vox, g, i, j, k);
+    }
+    const long long n = (long long)b * BS + t;
+    const double wx = sx * gx, wy = sy * gy, wz = sz * gz;
+    w64[n] = wx;
+    w64[stride + n] = wy;
+    w64[2 * stride + n] = wz;
+    if (w32) {
+        w32[n] = (float)wx;
+        w32[stride + n] = (float)wy;
+        w32[2 * stride + n] = (float)wz;
+    }
+}
+
+hipError_t launch_weights0(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,
+                           const double geo4[3], const int4 *coord, int nb, double *w64, float *w32, hipStream_t s)
+{
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_weights0, dim3(nb), dim3(NT), 0, s, labels, table, sig_vox, g, geo4[0], geo4[1], geo4[2],
+                       coord, w64, w32, (long long)nb * BS);
+    return hipGetLastError();
+}
+
+// Galerkin coarse operator for piecewise-constant aggregation of 2x2x2 nodes:
+// the coarse conductance between aggregates I and I+e_d is the sum of the four
+// fine conductances that cross their interface (fine edges from the fine
+// nodes 2I+1 along d).  P^T A P of a graph Laplacian is again one.
+__device__ __forceinline__ double fine_w(const double *wf, long long fstride, const int *slot_of, int fGx, int fGy,
+                                         int fGz, int fNx, int fNy, int fNz, int fi, int fj, int fk, int d)
+{
+    if (fi >= fNx || fj >= fNy || fk >= fNz) return 0.0;
+    const int bi = fi >> 3, bj = fj >> 3, bk = fk >> 3;
+    if (bi >= fGx || bj >= fGy || bk >= fGz) return 0.0;
+    const int sl = slot_of[bi + fGx * (bj + fGy * bk)];
+    if (sl < 0) return 0.0;
+    return wf[d * fstride + (long long)sl * BS + (fi & 7) + 8 * (fj & 7) + 64 * (fk & 7)];
+}
+
+__global__ void k_galerkin(const double *__restrict__ wf, long long fstride, const int *__restrict__ slot_of,
+                           int fGx, int fGy, int fGz, int fNx, int fNy, int fNz, const int4 *__restrict__ ccoord,
+                           double *wc64, float *wc32, long long cstride)
+{
+    const int b = blockIdx.x, t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const int4 c = ccoord[b];
+    const int I = c.x * 8 + tx, J = c.y * 8 + ty, K = c.z * 8 + tz;
+    double s[3];
+    s[0] = ((fine_w(wf, fstride, slot_of, fGx, fGy, fGz, fNx, fNy, fNz, 2 * I + 1, 2 * J, 2 * K, 0) +
+             fine_w(wf, fstride, slot_of, fGx, fGy, fGz, fNx, fNy, fNz, 2 * I + 1, 2 * J + 1, 2 * K, 0)) +
+            fine_w(wf, fstride, slot_of, fGx, fGy, fGz, fNx, fNy, fNz, 2 * I + 1, 2 * J, 2 * K + 1, 0)) +
+           fine_w(wf, fstride, slot_of, fGx, fGy, fGz, fNx, fNy, fNz, 2 * I + 1, 2 * J + 1, 2 * K + 1, 0);
+    s[1] = ((fine_w(wf, fstride, slot_of, fGx, fGy, fGz, fNx, fNy, fNz, 2 * I, 2 * J + 1, 2 * K, 1) +
+             fine_w(wf, fstride, slot_of, fGx, fGy, fGz, fNx, fNy, fNz, 2 * I + 1, 2 * J + 1, 2 * K, 1)) +
+            fine_w(wf, fstride, slot_of, fGx, fGy, fGz, fNx, fNy, fNz, 2 * I, 2 * J + 1, 2 * K + 1, 1)) +
+           fine_w(wf, fstride, slot_of, fGx, fGy, fGz, fNx, fNy, fNz, 2 * I + 1, 2 * J + 1, 2 * K + 1, 1);
+    s[2] = ((fine_w(wf, fstride, slot_of, fGx, fGy, fGz, fNx, fNy, fNz, 2 * I, 2 * J, 2 * K + 1, 2) +
+             fine_w(wf, fstride, slot_of, fGx, fGy, fGz, fNx, fNy, fNz, 2 * I + 1, 2 * J, 2 * K + 1, 2)) +
+            fine_w(wf, fstride, slot_of, fGx, fGy, fGz, fNx, fNy, fNz, 2 * I, 2 * J + 1, 2 * K + 1, 2)) +
+           fine_w(wf, fstride, slot_of, fGx, fGy, fGz, fNx, fNy, fNz, 2 * I + 1, 2 * J + 1, 2 * K + 1, 2);
+    const long long n = (long long)b * BS + t;
+    for (int d = 0; d < 3; ++d) {
+        wc64[d * cstride + n] = s[d];
+        wc32[d * cstride + n] = (float)s[d];
+    }
+}
+
+hipError_t launch_galerkin(const double *wf, long long fstride, const int *f_slot_of, int fGx, int fGy, int fGz,
+                           int fNx, int fNy, int fNz, const int4 *ccoord, int cnb, double *wc64, float *wc32,
+                           long long cstride, hipStream_t s)
+{
+    if (cnb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_galerkin, dim3(cnb), dim3(NT), 0, s, wf, fstride, f_slot_of, fGx, fGy, fGz, fNx, fNy, fNz,
+                       ccoord, wc64, wc32, cstride);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- connected components
+// Union-find over the nodes with D > 0 (hook the larger root under the smaller
+// with compare-and-swap, path halving on the way).  Loads and stores of the
+// parent array go through L2 (agent scope) so that every lane sees the hooks.
+__device__ __forceinline__ int pload(const int *p, int i)
+{
+    return __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int pfind(int *p, int x)
+{
+    int px = pload(p, x);
+    while (px != x) {
+        const int ppx = pload(p, px);
+        if (ppx != px) __hip_atomic_store(p + x, ppx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = px;
+        px = ppx;
+    }
+    return x;
+}
+
+__device__ __forceinline__ void punite(int *p, int a, int b)
+{
+    while (true) {
+        a = pfind(p, a);
+        b = pfind(p, b);
+        if (a == b) return;
+        if (a > b) { const int t = a; a = b; b = t; }
+        int expected = b;
+        if (__hip_atomic_compare_exchange_strong(p + b, &expected, a, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return;
+    }
+}
+
+__global__ void k_cc_init(const double *__restrict__ w, long long stride, Topo topo, int *parent)
+{
+    __shared__ BrickLds<double> L;
+    const int b = blockIdx.x, t = threadIdx.x;
+    load_nbr(topo, b, L);
+    __syncthreads();
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    double W[6];
+    const long long base = (long long)b * BS;
+    stored_weights(w, stride, base, t, tx, ty, tz, L.nb, W);
+    parent[base + t] = diag_of(W) > 0.0 ? (int)(base + t) : -1;
+}
+
+__global__ void k_cc_union(const double *__restrict__ w, long long stride, Topo topo, int *parent)
+{
+    __shared__ int nb[6];
+    const int b = blockIdx.x, t = threadIdx.x;
+    if (t < 6) nb[t] = topo.nbr[b * 6 + t];
+    __syncthreads();
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const long long base = (long long)b * BS;
+    const int me = (int)(base + t);
+    if (w[base + t] > 0.0) {
+        const int m = tx < 7 ? me + 1 : (nb[NPX] >= 0 ? nb[NPX] * BS + t - 7 : -1);
+        if (m >= 0) punite(parent, me, m);
+    }
+    if (w[stride + base + t] > 0.0) {
+        const int m = ty < 7 ? me + 8 : (nb[NPY] >= 0 ? nb[NPY] * BS + t - 56 : -1);
+        if (m >= 0) punite(parent, me, m);
+    }
+    if (w[2 * stride + base + t] > 0.0) {
+        const int m = tz < 7 ? me + 64 : (nb[NPZ] >= 0 ? nb[NPZ] * BS + t - 448 : -1);
+        if (m >= 0) punite(parent, me, m);
+    }
+}
+
+__global__ void k_cc_flatten(int *parent, long long n, int *flag)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        int r = -1;
+        if (pload(parent, (int)i) >= 0) r = pfind(parent, (int)i);
+        flag[i] = (r == (int)i) ? 1 : 0;
+    }
+}
+
+__global__ void k_cc_store_root(int *parent, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int p = pload(parent, (int)i);
+        if (p >= 0) parent[i] = pfind(parent, (int)i);
+    }
+}
+
+// exclusive scan of int flags in three passes (block sums, one-block scan of
+// the sums, offsets); SCAN_CHUNK elements per block
+constexpr int SCAN_CHUNK = 2048;
+
+__global__ void k_scan_blocks(const int *__restrict__ in, long long n, int *out, int *bsum)
+{
+    __shared__ int s[NT];
+    const long long off = (long long)blockIdx.x * SCAN_CHUNK;
+    const int t = threadIdx.x;
+    int v[4], tot = 0;
+    for (int q = 0; q < 4; ++q) {
+        const long long i = off + t * 4 + q;
+        v[q] = i < n ? in[i] : 0;
+        tot += v[q];
+    }
+    s[t] = tot;
+    __syncthreads();
+    for (int d = 1; d < NT; d <<= 1) {
+        const int add = t >= d ? s[t - d] : 0;
+        __syncthreads();
+        s[t] += add;
+        __syncthreads();
+    }
+    int run = s[t] - tot;
+    for (int q = 0; q < 4; ++q) {
+        const long long i = off + t * 4 + q;
+        if (i < n) out[i] = run;
+        run += v[q];
+    }
+    if (t == NT - 1) bsum[blockIdx.x] = s[t];
+}
+
+__global__ void k_scan_sums(int *bsum, int nblk, int *total)
+{
+    __shared__ int s[NT];
+    __shared__ int carry;
+    const int t = threadIdx.x;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nblk; base += NT) {
+        const int i = base + t;
+        const int v = i < nblk ? bsum[i] : 0;
+        s[t] = v;
+        __syncthreads();
+        for (int d = 1; d < NT; d <<= 1) {
+            const int add = t >= d ? s[t - d] : 0;
+            __syncthreads();
+            s[t] += add;
+            __syncthreads();
+        }
+        if (i < nblk) bsum[i] = carry + s[t] - v;
+        __syncthreads();
+        if (t == NT - 1) carry += s[t];
+        __syncthreads();
+    }
+    if (t == 0) *total = carry;
+}
+
+__global__ void k_scan_add(int *out, long long n, const int *bsum)
+{
+    const long long off = (long long)blockIdx.x * SCAN_CHUNK;
+    const int add = bsum[blockIdx.x];
+    for (int q = threadIdx.x; q < SCAN_CHUNK; q += blockDim.x) {
+        const long long i = off + q;
+        if (i < n) out[i] += add;
+    }
+}
+
+static hipError_t scan_exclusive(const int *in, long long n, int *out, int *bsum, int *total, hipStream_t s)
+{
+    const long long nblk = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nblk), dim3(NT), 0, s, in, n, out, bsum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(NT), 0, s, bsum, (int)nblk, total);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nblk), dim3(NT), 0, s, out, n, bsum);
+    return hipGetLastError();
+}
+
+__global__ void k_cc_assign(const int *__restrict__ parent, const int *__restrict__ idx, long long n, int *comp)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int p = parent[i];
+        comp[i] = p >= 0 ? idx[p] : -1;
+    }
+}
+
+// scan_tmp needs (n/2048 + 1) ints
+hipError_t launch_components(const double *w64, long long stride, Topo topo, int *parent, int *flag, int *idx,
+                             int *scan_tmp, int *comp, int *counts_or_null, int *ncomp_dev, hipStream_t s)
+{
+    (void)counts_or_null;
+    const int nb = topo.nb;
+    const long long n = (long long)nb * BS;
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cc_init, dim3(nb), dim3(NT), 0, s, w64, stride, topo, parent);
+    hipLaunchKernelGGL(k_cc_union, dim3(nb), dim3(NT), 0, s, w64, stride, topo, parent);
+    const unsigned gb = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
+    hipLaunchKernelGGL(k_cc_store_root, dim3(gb), dim3(256), 0, s, parent, n);
+    hipLaunchKernelGGL(k_cc_flatten, dim3(gb), dim3(256), 0, s, parent, n, flag);
+    hipError_t e = scan_exclusive(flag, n, idx, scan_tmp, ncomp_dev, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cc_assign, dim3(gb), dim3(256), 0, s, parent, idx, n, comp);
+    return hipGetLastError();
+}
+
+__global__ void k_comp_counts(const int *__restrict__ comp, long long n, int *counts)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int c = comp[i];
+        if (c >= 0) atomicAdd(counts + c, 1);
+    }
+}
+
+hipError_t launch_comp_counts(const int *comp, long long n, int *counts, hipStream_t s)
+{
+    const unsigned gb = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_comp_counts, dim3(gb), dim3(256), 0, s, comp, n, counts);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- coarsest level
+// Enumerate the unknowns (D > 0) of the coarsest level in node order, one
+// workgroup; adj[dof][6] = neighbour unknowns or -1.
+__global__ void k_coarse_enum(const double *__restrict__ w, long long stride, Topo topo, int *dof_of_node,
+                              int *node_of_dof, int *adj, int *ndof, int maxdof)
+{
+    __shared__ int s[1024];
+    __shared__ int carry;
+    const int t = threadIdx.x;
+    const long long n = (long long)topo.nb * BS;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (long long base = 0; base < n; base += 1024) {
+        const long long i = base + t;
+        int isdof = 0;
+        if (i < n) {
+            const int b = (int)(i / BS), tt = (int)(i % BS);
+            int tx, ty, tz;
+            brick_xyz(tt, tx, ty, tz);
+            double W[6];
+            stored_weights(w, stride, (long long)b * BS, tt, tx, ty, tz, topo.nbr + b * 6, W);
+            isdof = diag_of(W) > 0.0;
+        }
+        s[t] = isdof;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const int add = t >= d ? s[t - d] : 0;
+            __syncthreads();
+            s[t] += add;
+            __syncthreads();
+        }
+        const int id = carry + s[t] - isdof;
+        if (i < n) {
+            dof_of_node[i] = isdof ? id : -1;
+            if (isdof && id < maxdof) node_of_dof[id] = (int)i;
+        }
+        __syncthreads();
+        if (t == 1023) carry += s[t];
+        __syncthreads();
+    }
+    if (t == 0) *ndof = carry;
+    __syncthreads();
+    // adjacency among unknowns (only meaningful when ndof <= maxdof)
+    const int nd = carry < maxdof ? carry : maxdof;
+    for (int q = t; q < nd; q += blockDim.x) {
+        const int i = node_of_dof[q];
+        const int b = i / BS, tt = i % BS;
+        int tx, ty, tz;
+        brick_xyz(tt, tx, ty, tz);
+        const int *nb = topo.nbr + b * 6;
+        int m[6];
+        m[NMX] = tx > 0 ? i - 1 : (nb[NMX] >= 0 ? nb[NMX] * BS + tt + 7 : -1);
+        m[NPX] = tx < 7 ? i + 1 : (nb[NPX] >= 0 ? nb[NPX] * BS + tt - 7 : -1);
+        m[NMY] = ty > 0 ? i - 8 : (nb[NMY] >= 0 ? nb[NMY] * BS + tt + 56 : -1);
+        m[NPY] = ty < 7 ? i + 8 : (nb[NPY] >= 0 ? nb[NPY] * BS + tt - 56 : -1);
+        m[NMZ] = tz > 0 ? i - 64 : (nb[NMZ] >= 0 ? nb[NMZ] * BS + tt + 448 : -1);
+        m[NPZ] = tz < 7 ? i + 64 : (nb[NPZ] >= 0 ? nb[NPZ] * BS + tt - 448 : -1);
+        double W[6];
+        stored_weights(w, stride, (long long)b * BS, tt, tx, ty, tz, nb, W);
+        for (int k = 0; k < 6; ++k) adj[q * 6 + k] = (m[k] >= 0 && W[k] > 0.0) ? dof_of_node[m[k]] : -1;
+    }
+}
+
+hipError_t launch_coarse_setup(const double *w64, long long stride, Topo topo, int *dof_of_node, int *node_of_dof,
+                               int *adj, int *ndof_dev, int maxdof, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_coarse_enum, dim3(1), dim3(1024), 0, s, w64, stride, topo, dof_of_node, node_of_dof, adj,
+                       ndof_dev, maxdof);
+    return hipGetLastError();
+}
+
+// Dense pseudo-inverse of the coarsest (singular) operator: A_c + sum over
+// components c of alpha_c 1_c 1_c^T is SPD, and for a right side orthogonal to
+// every 1_c its solution has zero mean per component, i.e. equals A_c^+ r.
+// One workgroup: assemble, label components, regularise, invert in place by
+// Gauss-Jordan elimination (no pivoting needed for an SPD matrix).
+// work: 3*n ints + n doubles (column buffer).
+__global__ void k_coarse_factor(const double *__restrict__ w, long long stride, Topo topo,
+                                const int *__restrict__ node_of_dof, const int *__restrict__ adj, int n, double *A,
+                                int *work)
+{
+    const int t = threadIdx.x, nt = blockDim.x;
+    int *comp = work;
+    int *csize = work + n;
+    double *colk = (double *)(work + 3 * n + (3 * n & 1));
+    __shared__ int changed;
+    __shared__ double piv;
+    for (long long e = t; e < (long long)n * n; e += nt) A[e] = 0.0;
+    __syncthreads();
+    for (int q = t; q < n; q += nt) {
+        const int i = node_of_dof[q];
+        const int b = i / BS, tt = i % BS;
+        int tx, ty, tz;
+        brick_xyz(tt, tx, ty, tz);
+        double W[6];
+        stored_weights(w, stride, (long long)b * BS, tt, tx, ty, tz, topo.nbr + b * 6, W);
+        double d = 0.0;
+        for (int k = 0; k < 6; ++k) {
+            const int m = adj[q * 6 + k];
+            if (m >= 0) {
+                A[(long long)q * n + m] -= W[k];
+                d += W[k];
+            }
+        }
+        A[(long long)q * n + q] += d;
+        comp[q] = q;
+        csize[q] = 0;
+    }
+    __syncthreads();
+    // components: min-label propagation over the stencil graph
+    do {
+        __syncthreads();
+        if (t == 0) changed = 0;
+        __syncthreads();
+        for (int q = t; q < n; q += nt) {
+            int c = comp[q];
+            for (int k = 0; k < 6; ++k) {
+                const int m = adj[q * 6 + k];
+                if (m >= 0) {
+                    const int cm = __hip_atomic_load(comp + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (cm < c) c = cm;
+                }
+            }
+            if (c < comp[q]) {
+                __hip_atomic_store(comp + q, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                changed = 1;
+            }
+        }
+        __syncthreads();
+    } while (changed);
+    for (int q = t; q < n; q += nt) atomicAdd(csize + comp[q], 1);
+    __syncthreads();
+    // mean diagonal per component (serial per component root, small n)
+    double *cdiag = colk;  // reuse as scratch
+    for (int q = t; q < n; q += nt) cdiag[q] = 0.0;
+    __syncthreads();
+    if (t == 0)
+        for (int q = 0; q < n; ++q) cdiag[comp[q]] += A[(long long)q * n + q];
+    __syncthreads();
+    for (long long e = t; e < (long long)n * n; e += nt) {
+        const int i = (int)(e / n), j = (int)(e % n);
+        const int c = comp[i];
+        if (comp[j] == c) {
+            const double sz = (double)csize[c];
+            A[e] += (cdiag[c] / sz) / sz;
+        }
+    }
+    __syncthreads();
+    // in-place Gauss-Jordan inversion
+    for (int k = 0; k < n; ++k) {
+        if (t == 0) piv = 1.0 / A[(long long)k * n + k];
+        __syncthreads();
+        for (int j = t; j < n; j += nt) {
+            const double v = (j == k) ? 1.0 : A[(long long)k * n + j];
+            A[(long long)k * n + j] = v * piv;
+        }
+        for (int i = t; i < n; i += nt) colk[i] = A[(long long)i * n + k];
+        __syncthreads();
+        for (long long e = t; e < (long long)n * n; e += nt) {
+            const int i = (int)(e / n), j = (int)(e % n);
+            if (i == k) continue;
+            const double base = (j == k) ? 0.0 : A[e];
+            A[e] = base - colk[i] * A[(long long)k * n + j];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_coarse_factor(const double *w64, long long stride, Topo topo, const int *dof_of_node,
+                                const int *node_of_dof, int *adj, int n, double *A, int *work, hipStream_t s)
+{
+    (void)dof_of_node;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coarse_factor, dim3(1), dim3(1024), 0, s, w64, stride, topo, node_of_dof, adj, n, A, work);
+    return hipGetLastError();
+}
+
+// ============================================================================
+// solve kernels
+// ============================================================================
+
+template <typename T>
+__global__ void k_fill(T *x, long long n, T v)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+template <typename T>
+hipError_t launch_fill(T *x, long long n, T v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned gb = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
+    hipLaunchKernelGGL(k_fill<T>, dim3(gb), dim3(256), 0, s, x, n, v);
+    return hipGetLastError();
+}
+template hipError_t launch_fill<double>(double *, long long, double, hipStream_t);
+template hipError_t launch_fill<float>(float *, long long, float, hipStream_t);
+template hipError_t launch_fill<int>(int *, long long, int, hipStream_t);
+
+// start of a solve: keeps ||b||^2 from the right-side kernel, arms the stop test
+__global__ void k_scal_init(Scal *sc, double tol, int use_x0)
+{
+    (void)use_x0;
+    if (threadIdx.x == 0) {
+        const double bb = sc->bb;
+        sc->rz = 0.0; sc->pq = 0.0; sc->alpha = 0.0; sc->beta = 0.0; sc->zq = 0.0;
+        sc->rr = bb;
+        sc->tol2 = tol * tol * bb;
+        sc->done = bb > 0.0 ? 0 : 1;
+        sc->iters = 0; sc->status = 0; sc->pad = 0;
+    }
+}
+
+hipError_t launch_scal_init(Scal *sc, double tol, int use_x0, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scal_init, dim3(1), dim3(64), 0, s, sc, tol, use_x0);
+    return hipGetLastError();
+}
+
+// b = -G^T M a on the unknowns of the finest level (Eq. (3), right side):
+// b_n = sum over edges leaving n of M_e a_e - sum over edges entering n of M_e a_e,
+// and ||b||^2.  a is read only on conducting edges (M_e > 0), which all lie in the grid.
+template <bool LABEL>
+__global__ __launch_bounds__(NT) void k_rhs(OpArgs<double> op, Topo topo, const int4 *__restrict__ coord, Grid g,
+                                            const double *__restrict__ a, double *b, double *part, int *counter,
+                                            Scal *sc)
+{
+    __shared__ BrickLds<double> L;
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    op_prepare(op, topo, bk, L);
+    const int t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const long long base = (long long)bk * BS;
+    double W[6];
+    op_weights(op, L, base, t, tx, ty, tz, W);
+    const int4 c = coord[bk];
+    const long long i = c.x * 8 + tx, j = c.y * 8 + ty, k = c.z * 8 + tz;
+    const long long n = i + (long long)g.Nx * (j + (long long)g.Ny * k);
+    const long long nn = (long long)g.Nx * g.Ny * g.Nz;
+    double s = 0.0;
+    if (W[NPX] != 0.0) s += W[NPX] * a[n];
+    if (W[NMX] != 0.0) s -= W[NMX] * a[n - 1];
+    if (W[NPY] != 0.0) s += W[NPY] * a[nn + n];
+    if (W[NMY] != 0.0) s -= W[NMY] * a[nn + n - g.Nx];
+    if (W[NPZ] != 0.0) s += W[NPZ] * a[2 * nn + n];
+    if (W[NMZ] != 0.0) s -= W[NMZ] * a[2 * nn + n - (long long)g.Nx * g.Ny];
+    b[base + t] = s;
+    const double tot = block_sum(s * s, L.red);
+    if (t == 0) part[bk] = tot;
+    if (last_block(counter, topo.nb, &L.flag)) {
+        const double bb = sum_partials(part, topo.nb, L.red);
+        if (t == 0) sc->bb = bb;
+    }
+}
+
+template <typename T>
+static OpArgs<T> strip(const OpArgs<T> &op) { return op; }
+
+hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, const Grid &g, const double *a,
+                      double *b, double *part, int *counter, Scal *sc, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    if (op.w)
+        hipLaunchKernelGGL(k_rhs<false>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, coord, g, a, b, part,
+                           counter, sc);
+    else
+        hipLaunchKernelGGL(k_rhs<true>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, coord, g, a, b, part,
+                           counter, sc);
+    return hipGetLastError();
+}
+
+// q = A p and p.q; the last block forms alpha = r.z / p.q
+__global__ __launch_bounds__(NT) void k_spmv_dot(OpArgs<double> op, Topo topo, const double *__restrict__ p,
+                                                 double *__restrict__ q, double *part, int *counter, Scal *sc)
+{
+    __shared__ BrickLds<double> L;
+    if (__hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    op_prepare(op, topo, bk, L);
+    const int t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const long long base = (long long)bk * BS;
+    double W[6], X[6];
+    op_weights(op, L, base, t, tx, ty, tz, W);
+    nbr_vals(p, base, t, tx, ty, tz, L.nb, X);
+    const double p0 = p[base + t];
+    const double y = stencil_apply(p0, X, W);
+    q[base + t] = y;
+    const double tot = block_sum(p0 * y, L.red);
+    if (t == 0) part[bk] = tot;
+    if (last_block(counter, topo.nb, &L.flag)) {
+        const double pq = sum_partials(part, topo.nb, L.red);
+        if (t == 0) {
+            sc->pq = pq;
+            double alpha = sc->rz / pq;
+            if (!(pq > 0.0) || !isfinite(alpha)) {
+                alpha = 0.0;
+                sc->status = 6;
+                sc->done = 1;
+            }
+            sc->alpha = alpha;
+        }
+    }
+}
+
+hipError_t launch_spmv_dot(const OpArgs<double> &op, Topo topo, const double *p, double *q, double *part,
+                           int *counter, Scal *sc, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spmv_dot, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, p, q, part, counter, sc);
+    return hipGetLastError();
+}
+
+// x += alpha p, r -= alpha q, ||r||^2; the last block counts the iteration and
+// raises the stop flag at ||r|| <= tol ||b|| or at max_iter
+__global__ __launch_bounds__(NT) void k_update(Topo topo, double *__restrict__ x, double *__restrict__ r,
+                                               const double *__restrict__ p, const double *__restrict__ q,
+                                               double *part, int *counter, Scal *sc, int max_iter)
+{
+    __shared__ double red[8];
+    __shared__ int flag;
+    if (__hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    const double alpha = sc->alpha;
+    const long long n = (long long)bk * BS + threadIdx.x;
+    x[n] += alpha * p[n];
+    const double rn = r[n] - alpha * q[n];
+    r[n] = rn;
+    const double tot = block_sum(rn * rn, red);
+    if (threadIdx.x == 0) part[bk] = tot;
+    if (last_block(counter, topo.nb, &flag)) {
+        const double rr = sum_partials(part, topo.nb, red);
+        if (threadIdx.x == 0) {
+            sc->rr = rr;
+            sc->iters += 1;
+            if (rr <= sc->tol2) {
+                sc->done = 1;
+            } else if (!isfinite(rr)) {
+                sc->status = 6;
+                sc->done = 1;
+            } else if (sc->iters >= max_iter) {
+                sc->status = 5;
+                sc->done = 1;
+            }
+        }
+    }
+}
+
+hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const double *q, double *part,
+                         int *counter, Scal *sc, int max_iter, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, r, p, q, part, counter, sc,
+                       max_iter);
+    return hipGetLastError();
+}
+
+// r = b - A x and ||r||^2.  mode 0: start of a solve (sets rr); mode 1: final
+// check (stores the true relative residual in sc->zq as ||r||^2).
+__global__ __launch_bounds__(NT) void k_resid(OpArgs<double> op, Topo topo, const double *__restrict__ b,
+                                              const double *__restrict__ x, double *__restrict__ r, double *part,
+                                              int *counter, Scal *sc, int mode)
+{
+    __shared__ BrickLds<double> L;
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    op_prepare(op, topo, bk, L);
+    const int t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const long long base = (long long)bk * BS;
+    double W[6], X[6];
+    op_weights(op, L, base, t, tx, ty, tz, W);
+    nbr_vals(x, base, t, tx, ty, tz, L.nb, X);
+    const double rv = b[base + t] - stencil_apply(x[base + t], X, W);
+    if (r) r[base + t] = rv;
+    const double tot = block_sum(rv * rv, L.red);
+    if (t == 0) part[bk] = tot;
+    if (last_block(counter, topo.nb, &L.flag)) {
+        const double rr = sum_partials(part, topo.nb, L.red);
+        if (t == 0) {
+            if (mode == 0) {
+                sc->rr = rr;
+                if (rr <= sc->tol2) sc->done = 1;
+            } else {
+                sc->zq = rr;
+            }
+        }
+    }
+}
+
+hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,
+                        double *part, int *counter, Scal *sc, int mode, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_resid, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, b, x, r, part, counter, sc, mode);
+    return hipGetLastError();
+}
+
+// r.z and z.q; the last block forms the flexible (Polak-Ribiere) beta = -alpha z.q / (r.z)_old
+template <typename TZ>
+__global__ __launch_bounds__(NT) void k_dots(Topo topo, const TZ *__restrict__ z, const double *__restrict__ r,
+                                             const double *__restrict__ q, double *part, int *counter, Scal *sc,
+                                             int first)
+{
+    __shared__ double red[8];
+    __shared__ int flag;
+    if (__hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    const long long n = (long long)bk * BS + threadIdx.x;
+    const double zv = (double)z[n];
+    const double a = block_sum(zv * r[n], red);
+    const double c = first ? 0.0 : block_sum(zv * q[n], red);
+    if (threadIdx.x == 0) {
+        part[bk] = a;
+        part[topo.nb + bk] = c;
+    }
+    if (last_block(counter, topo.nb, &flag)) {
+        const double rz = sum_partials(part, topo.nb, red);
+        const double zq = first ? 0.0 : sum_partials(part + topo.nb, topo.nb, red);
+        if (threadIdx.x == 0) {
+            double beta = 0.0;
+            if (!first) beta = -sc->alpha * zq / sc->rz;
+            if (!(rz > 0.0) || !isfinite(beta)) {
+                sc->status = 6;
+                sc->done = 1;
+                beta = 0.0;
+            }
+            sc->zq = zq;
+            sc->rz = rz;
+            sc->beta = beta;
+        }
+    }
+}
+
+template <typename TZ>
+hipError_t launch_dots(Topo topo, const TZ *z, const double *r, const double *q, double *part, int *counter,
+                       Scal *sc, int first, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dots<TZ>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, z, r, q, part, counter, sc, first);
+    return hipGetLastError();
+}
+template hipError_t launch_dots<double>(Topo, const double *, const double *, const double *, double *, int *, Scal *,
+                                        int, hipStream_t);
+template hipError_t launch_dots<float>(Topo, const float *, const double *, const double *, double *, int *, Scal *,
+                                       int, hipStream_t);
+
+template <typename TZ>
+__global__ __launch_bounds__(NT) void k_pupdate(Topo topo, const TZ *__restrict__ z, double *__restrict__ p,
+                                                const Scal *sc, int first)
+{
+    if (__hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    const long long n = (long long)bk * BS + threadIdx.x;
+    const double zv = (double)z[n];
+    p[n] = first ? zv : zv + sc->beta * p[n];
+}
+
+template <typename TZ>
+hipError_t launch_pupdate(Topo topo, const TZ *z, double *p, const Scal *sc, int first, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pupdate<TZ>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, z, p, sc, first);
+    return hipGetLastError();
+}
+template hipError_t launch_pupdate<double>(Topo, const double *, double *, const Scal *, int, hipStream_t);
+template hipError_t launch_pupdate<float>(Topo, const float *, double *, const Scal *, int, hipStream_t);
+
+// ---------------------------------------------------------------- multigrid level kernels
+__device__ __forceinline__ bool stopped(const Scal *sc)
+{
+    return sc && __hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// first Chebyshev step from a zero start: x = c0 D^-1 b (0 where D = 0)
+template <typename T, typename TB>
+__global__ __launch_bounds__(NT) void k_cheb_first(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
+                                                   T *__restrict__ x, T c0, const Scal *sc)
+{
+    __shared__ BrickLds<T> L;
+    if (stopped(sc)) return;
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    op_prepare(op, topo, bk, L);
+    const int t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const long long base = (long long)bk * BS;
+    T W[6];
+    op_weights(op, L, base, t, tx, ty, tz, W);
+    const T D = diag_of(W);
+    x[base + t] = D > T(0) ? c0 * (T)b[base + t] / D : T(0);
+}
+
+// general Chebyshev step: r = b - A xin; d = c1 d_old + c2 D^-1 r; xout = xin + d
+// (d_old = xin when din == nullptr, i.e. right after a zero start)
+template <typename T, typename TB>
+__global__ __launch_bounds__(NT) void k_cheb_step(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
+                                                  const T *__restrict__ xin, T *__restrict__ xout,
+                                                  const T *__restrict__ din, T *__restrict__ dout, T c1, T c2,
+                                                  const Scal *sc)
+{
+    __shared__ BrickLds<T> L;
+    if (stopped(sc)) return;
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    op_prepare(op, topo, bk, L);
+    const int t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const long long base = (long long)bk * BS;
+    T W[6], X[6];
+    op_weights(op, L, base, t, tx, ty, tz, W);
+    nbr_vals(xin, base, t, tx, ty, tz, L.nb, X);
+    const T x0 = xin[base + t];
+    const T D = diag_of(W);
+    T xo = T(0), dn = T(0);
+    if (D > T(0)) {
+        const T r = (T)b[base + t] - stencil_apply(x0, X, W);
+        const T dold = din ? din[base + t] : x0;
+        dn = c1 * dold + c2 * r / D;
+        xo = x0 + dn;
+    }
+    xout[base + t] = xo;
+    if (dout) dout[base + t] = dn;
+}
+
+// coarse right side: b_c = P^T (b - A x), P = 2x2x2 piecewise-constant aggregation
+template <typename T, typename TB>
+__global__ __launch_bounds__(NT) void k_resid_restrict(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
+                                                       const T *__restrict__ x, T *__restrict__ bc,
+                                                       const int *__restrict__ parent_slot,
+                                                       const int4 *__restrict__ fcoord, const Scal *sc)
+{
+    __shared__ BrickLds<T> L;
+    __shared__ T rs[BS];
+    if (stopped(sc)) return;
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    op_prepare(op, topo, bk, L);
+    const int t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const long long base = (long long)bk * BS;
+    T W[6], X[6];
+    op_weights(op, L, base, t, tx, ty, tz, W);
+    nbr_vals(x, base, t, tx, ty, tz, L.nb, X);
+    rs[t] = (T)b[base + t] - stencil_apply(x[base + t], X, W);
+    __syncthreads();
+    if (t < 64) {
+        const int cx = t & 3, cy = (t >> 2) & 3, cz = t >> 4;
+        const int f = 2 * cx + 16 * cy + 128 * cz;
+        const T s = ((((((rs[f] + rs[f + 1]) + rs[f + 8]) + rs[f + 9]) + rs[f + 64]) + rs[f + 65]) + rs[f + 72]) +
+                    rs[f + 73];
+        const int4 c = fcoord[bk];
+        const int ox = (c.x & 1) * 4, oy = (c.y & 1) * 4, oz = (c.z & 1) * 4;
+        bc[(long long)parent_slot[bk] * BS + (ox + cx) + 8 * (oy + cy) + 64 * (oz + cz)] = s;
+    }
+}
+
+// x += s * P x_c
+template <typename T>
+__global__ __launch_bounds__(NT) void k_prolong(Topo topo, T *__restrict__ x, const T *__restrict__ xc,
+                                                const int *__restrict__ parent_slot, const int4 *__restrict__ fcoord,
+                                                T scale, const Scal *sc)
+{
+    if (stopped(sc)) return;
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    const int t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const int4 c = fcoord[bk];
+    const int cxl = (c.x & 1) * 4 + (tx >> 1), cyl = (c.y & 1) * 4 + (ty >> 1), czl = (c.z & 1) * 4 + (tz >> 1);
+    const long long n = (long long)bk * BS + t;
+    x[n] += scale * xc[(long long)parent_slot[bk] * BS + cxl + 8 * cyl + 64 * czl];
+}
+
+// coarsest solve z_c = A_c^+ r_c (dense FP64 GEMV); 4 rows per workgroup of 256
+template <typename T, typename TB>
+__global__ __launch_bounds__(256) void k_coarse_apply(const TB *__restrict__ bc, T *__restrict__ xc,
+                                                      const double *__restrict__ Ainv,
+                                                      const int *__restrict__ node_of_dof, int n, const Scal *sc)
+{
+    __shared__ double rv[1024];
+    if (stopped(sc)) return;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) rv[i] = (double)bc[node_of_dof[i]];
+    __syncthreads();
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + wv;
+    if (row >= n) return;
+    const double *a = Ainv + (long long)row * n;
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s += a[j] * rv[j];
+    s = wave_sum(s);
+    if (lane == 0) xc[node_of_dof[row]] = (T)s;
+}
+
+template <typename T, typename TB>
+hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, T c0, const Scal *sc, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_cheb_first<T, TB>), dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, b, x, c0, sc);
+    return hipGetLastError();
+}
+
+template <typename T, typename TB>
+hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din, T *dout,
+                            T c1, T c2, const Scal *sc, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_cheb_step<T, TB>), dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, b, xin, xout, din, dout,
+                       c1, c2, sc);
+    return hipGetLastError();
+}
+
+template <typename T, typename TB>
+hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, const T *x, T *bc, const int *parent_slot,
+                                 const int4 *fcoord, const Scal *sc, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_resid_restrict<T, TB>), dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, b, x, bc,
+                       parent_slot, fcoord, sc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong(Topo topo, T *x, const T *xc, const int *parent_slot, const int4 *fcoord, T scale,
+                          const Scal *sc, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prolong<T>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, xc, parent_slot, fcoord, scale,
+                       sc);
+    return hipGetLastError();
+}
+
+template <typename T, typename TB>
+hipError_t launch_coarse_apply(const TB *bc, T *xc, const double *Ainv, const int *node_of_dof, int n, const Scal *sc,
+                               hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (n > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_coarse_apply<T, TB>), dim3((n + 3) / 4), dim3(256), 0, s, bc, xc, Ainv, node_of_dof, n, sc);
+    return hipGetLastError();
+}
+
+#define SPFD_INST_LEVEL(T, TB)                                                                                      \
+    template hipError_t launch_cheb_first<T, TB>(const OpArgs<T> &, Topo, const TB *, T *, T, const Scal *,       \
+                                                 hipStream_t);                                                      \
+    template hipError_t launch_cheb_step<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *, const T *, T *, \
+                                                T, T, const Scal *, hipStream_t);                                   \
+    template hipError_t launch_resid_restrict<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *,           \
+                                                     const int *, const int4 *, const Scal *, hipStream_t);
+SPFD_INST_LEVEL(double, double)
+SPFD_INST_LEVEL(float, float)
+SPFD_INST_LEVEL(float, double)
+template hipError_t launch_prolong<double>(Topo, double *, const double *, const int *, const int4 *, double,
+                                           const Scal *, hipStream_t);
+template hipError_t launch_prolong<float>(Topo, float *, const float *, const int *, const int4 *, float, const Scal *,
+                                          hipStream_t);
+template hipError_t launch_coarse_apply<double, double>(const double *, double *, const double *, const int *, int,
+                                                        const Scal *, hipStream_t);
+template hipError_t launch_coarse_apply<float, float>(const float *, float *, const double *, const int *, int,
+                                                      const Scal *, hipStream_t);
+template hipError_t launch_coarse_apply<float, double>(const double *, float *, const double *, const int *, int,
+                                                       const Scal *, hipStream_t);
+
+// ============================================================================
+// gauge, output, post-processing
+// ============================================================================
+
+// mean of x over component c (deterministic two-stage sum), one launch per component
+__global__ __launch_bounds__(NT) void k_comp_sum(Topo topo, const double *__restrict__ x, const int *__restrict__ comp,
+                                                 int c, const int *counts, double *means, double *part, int *counter)
+{
+    __shared__ double red[8];
+    __shared__ int flag;
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    const long long n = (long long)bk * BS + threadIdx.x;
+    const double v = comp[n] == c ? x[n] : 0.0;
+    const double tot = block_sum(v, red);
+    if (threadIdx.x == 0) part[bk] = tot;
+    if (last_block(counter, topo.nb, &flag)) {
+        const double s = sum_partials(part, topo.nb, red);
+        if (threadIdx.x == 0) means[c] = counts[c] > 0 ? s / (double)counts[c] : 0.0;
+    }
+}
+
+// many components: FP64 atomics (order-dependent rounding) then division
+__global__ void k_comp_sum_atomic(long long n, const double *__restrict__ x, const int *__restrict__ comp, double *sums)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int c = comp[i];
+        if (c >= 0) atomicAdd(sums + c, x[i]);
+    }
+}
+
+__global__ void k_comp_div(int nc, const int *counts, double *means)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x)
+        means[c] = counts[c] > 0 ? means[c] / (double)counts[c] : 0.0;
+}
+
+hipError_t launch_comp_mean(Topo topo, const double *x, const int *comp, int ncomp, const int *counts, double *means,
+                            double *part, int *counter, hipStream_t s)
+{
+    if (topo.nb <= 0 || ncomp <= 0) return hipSuccess;
+    if (ncomp <= 16) {
+        for (int c = 0; c < ncomp; ++c)
+            hipLaunchKernelGGL(k_comp_sum, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, comp, c, counts, means,
+                               part, counter);
+    } else {
+        const long long n = (long long)topo.nb * BS;
+        hipError_t e = launch_fill<double>(means, ncomp, 0.0, s);
+        if (e != hipSuccess) return e;
+        const unsigned gb = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
+        hipLaunchKernelGGL(k_comp_sum_atomic, dim3(gb), dim3(256), 0, s, n, x, comp, means);
+        hipLaunchKernelGGL(k_comp_div, dim3((ncomp + 255) / 256), dim3(256), 0, s, ncomp, counts, means);
+    }
+    return hipGetLastError();
+}
+
+// dense node array from the brick layout: psi = x - mean(component), 0 outside the conductor
+__global__ void k_psi_out(const double *__restrict__ x, const int *__restrict__ comp, const double *__restrict__ means,
+                          const int *__restrict__ slot_of, Grid g, double *psi)
+{
+    const long long nn = (long long)g.Nx * g.Ny * g.Nz;
+    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(n % g.Nx), j = (int)((n / g.Nx) % g.Ny), k = (int)(n / ((long long)g.Nx * g.Ny));
+        const int sl = slot_of[(i >> 3) + g.Gx * ((j >> 3) + g.Gy * (k >> 3))];
+        double v = 0.0;
+        if (sl >= 0) {
+            const long long idx = (long long)sl * BS + (i & 7) + 8 * (j & 7) + 64 * (k & 7);
+            const int c = comp[idx];
+            if (c >= 0) v = x[idx] - means[c];
+        }
+        psi[n] = v;
+    }
+}
+
+hipError_t launch_psi_out(const double *x, const int *comp, const double *means, const int *slot_of, const Grid &g,
+                          double *psi, hipStream_t s)
+{
+    const long long nn = (long long)g.Nx * g.Ny * g.Nz;
+    const unsigned gb = (unsigned)((nn + 255) / 256 > 131072 ? 131072 : (nn + 255) / 256);
+    hipLaunchKernelGGL(k_psi_out, dim3(gb), dim3(256), 0, s, x, comp, means, slot_of, g, psi);
+    return hipGetLastError();
+}
+
+// brick layout from a dense node array (start iterate), 0 outside the conductor
+__global__ void k_psi_in(const double *__restrict__ psi, const int *__restrict__ comp, const int4 *__restrict__ coord,
+                         Grid g, double *x)
+{
+    const int b = blockIdx.x, t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const int4 c = coord[b];
+    const int i = c.x * 8 + tx, j = c.y * 8 + ty, k = c.z * 8 + tz;
+    const long long idx = (long long)b * BS + t;
+    double v = 0.0;
+    if (comp[idx] >= 0) v = psi[i + (long long)g.Nx * (j + (long long)g.Ny * k)];
+    x[idx] = v;
+}
+
+hipError_t launch_psi_in(const double *psi, const int *comp, const int4 *coord, int nb, const Grid &g, double *x,
+                         hipStream_t s)
+{
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_psi_in, dim3(nb), dim3(NT), 0, s, psi, comp, coord, g, x);
+    return hipGetLastError();
+}
+
+// Eq. (1) and the voxel average: for a conducting voxel, u = a + G psi on its
+// twelve edges (all conducting), ubar_d = mean of the four d-edges and
+// |E| = omega * sqrt(sum (ubar_d / h_d)^2); air voxels get 0.
+__global__ void k_efield(const uint8_t *__restrict__ labels, const double *__restrict__ table,
+                         const double *__restrict__ sig_vox, Grid g, double hx, double hy, double hz, double omega,
+                         const double *__restrict__ a, const double *__restrict__ psi, double *emag)
+{
+    const long long nvox = (long long)g.nx * g.ny * g.nz;
+    const long long nn = (long long)g.Nx * g.Ny * g.Nz;
+    const long long sy = g.Nx, sz = (long long)g.Nx * g.Ny;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (long long)gridDim.x * blockDim.x) {
+        const double s = sig_vox ? sig_vox[v] : table[labels[v]];
+        if (!(s > 0.0)) {
+            emag[v] = 0.0;
+            continue;
+        }
+        const long long i = v % g.nx, j = (v / g.nx) % g.ny, k = v / ((long long)g.nx * g.ny);
+        const long long n0 = i + g.Nx * (j + (long long)g.Ny * k);
+        // x-edges start at (i, j..j+1, k..k+1)
+        const long long ex[4] = {n0, n0 + sy, n0 + sz, n0 + sy + sz};
+        const long long ey[4] = {n0, n0 + 1, n0 + sz, n0 + 1 + sz};
+        const long long ez[4] = {n0, n0 + 1, n0 + sy, n0 + 1 + sy};
+        double ux = 0.0, uy = 0.0, uz = 0.0;
+        for (int q = 0; q < 4; ++q) {
+            ux += (a[ex[q]] + psi[ex[q] + 1]) - psi[ex[q]];
+            uy += (a[nn + ey[q]] + psi[ey[q] + sy]) - psi[ey[q]];
+            uz += (a[2 * nn + ez[q]] + psi[ez[q] + sz]) - psi[ez[q]];
+        }
+        const double fx = 0.25 * ux / hx, fy = 0.25 * uy / hy, fz = 0.25 * uz / hz;
+        emag[v] = omega * sqrt(fx * fx + fy * fy + fz * fz);
+    }
+}
+
+hipError_t launch_efield(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,
+                         const double h[3], double omega, const double *a, const double *psi, double *emag,
+                         hipStream_t s)
+{
+    const long long nvox = (long long)g.nx * g.ny * g.nz;
+    const unsigned gb = (unsigned)((nvox + 255) / 256 > 131072 ? 131072 : (nvox + 255) / 256);
+    hipLaunchKernelGGL(k_efield, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, h[0], h[1], h[2], omega, a, psi,
+                       emag);
+    return hipGetLastError();
+}
+
+// u = a + G psi on conducting edges (any of the four voxels around the edge conducts), 0 elsewhere
+__global__ void k_uedges(const uint8_t *__restrict__ labels, const double *__restrict__ table,
+                         const double *__restrict__ sig_vox, Grid g, const double *__restrict__ a,
+                         const double *__restrict__ psi, double *u)
+{
+    const long long nn = (long long)g.Nx * g.Ny * g.Nz;
+    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(n % g.Nx), j = (int)((n / g.Nx) % g.Ny), k = (int)(n / ((long long)g.Nx * g.Ny));
+        // x-edge: voxels (i, j-1..j, k-1..k)
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        if (i < g.nx)
+            sx = vox_sig(labels, table, sig_vox, g, i, j - 1, k - 1) + vox_sig(labels, table, sig_vox, g, i, j, k - 1) +
+                 vox_sig(labels, table, sig_vox, g, i, j - 1, k) + vox_sig(labels, table, sig_vox, g, i, j, k);
+        if (j < g.ny)
+            sy = vox_sig(labels, table, sig_vox, g, i - 1, j, k - 1) + vox_sig(labels, table, sig_vox, g, i, j, k - 1) +
+                 vox_sig(labels, table, sig_vox, g, i - 1, j, k) + vox_sig(labels, table, sig_vox, g, i, j, k);
+        if (k < g.nz)
+            sz = vox_sig(labels, table, sig_vox, g, i - 1, j - 1, k) + vox_sig(labels, table, sig_vox, g, i, j - 1, k) +
+                 vox_sig(labels, table, sig_vox, g, i - 1, j, k) + vox_sig(labels, table, sig_vox, g, i, j, k);
+        u[n] = sx > 0.0 ? (a[n] + psi[n + 1]) - psi[n] : 0.0;
+        u[nn + n] = sy > 0.0 ? (a[nn + n] + psi[n + g.Nx]) - psi[n] : 0.0;
+        u[2 * nn + n] = sz > 0.0 ? (a[2 * nn + n] + psi[n + (long long)g.Nx * g.Ny]) - psi[n] : 0.0;
+    }
+}
+
+hipError_t launch_uedges(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,
+                         const double *a, const double *psi, double *u, hipStream_t s)
+{
+    const long long nn = (long long)g.Nx * g.Ny * g.Nz;
+    const unsigned gb = (unsigned)((nn + 255) / 256 > 131072 ? 131072 : (nn + 255) / 256);
+    hipLaunchKernelGGL(k_uedges, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, a, psi, u);
+    return hipGetLastError();
+}
+
+}  // namespace spfd

@@ -1,0 +1,172 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle and with exact answers.
+
+Bars (relative 2-norm over all nodes / voxels), after both sides reach the
+matching residual criterion 1e-12: potential <= 1e-7 in FP64 and <= 1e-6 with
+the FP32 cycle; |E| (a pointwise map of the potential) to the same bar.  The
+E-field kernel alone, given the same potential, agrees with the oracle to 1e-12.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import discrete as D
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2010_12879_amd as P  # noqa: E402
+
+DEV = torch.device("cuda:0")
+BAR = {"fp64": 1e-7, "mixed": 1e-6}
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _solve(w, prec, tol=1e-12, a=None, max_iter=400, **kw):
+    s = P.Solver(_dev(w.labels), w.sigma_table, w.h, precision=prec, **kw)
+    a_np = w.a if a is None else a
+    ad = _dev(a_np)
+    psi, info = s.solve(ad, tol=tol, max_iter=max_iter)
+    emag = s.efield(ad, psi, w.omega)
+    out = (psi.cpu().numpy(), emag.cpu().numpy(), info, s.info())
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("seed,shape,fill", [(5, (4, 4, 4), 0.5), (6, (6, 5, 4), 0.35), (8, (6, 6, 6), 0.3),
+                                              (9, (17, 9, 11), 0.55), (10, (1, 1, 1), 1.0)])
+def test_tiny_against_dense_pinv(prec, seed, shape, fill):
+    print(f"case tiny seed={seed} shape={shape} {prec}", flush=True)
+    w = W.tiny_random_phantom(*shape, seed=seed, fill=fill)
+    sig = w.sigma_voxel()
+    if not np.any(sig > 0):
+        pytest.skip("no conductor")
+    A, b, node_of, comp = oracle.dense_system(sig, w.h, w.a, max_dof=5000)
+    x_ref = np.linalg.pinv(A) @ b
+    psi, emag, info, sinfo = _solve(w, prec)
+    assert info["status"] == "OK", info
+    assert sinfo["n_components"] == len(np.unique(comp))
+    x = psi.reshape(-1)[node_of]
+    assert _rel(x, x_ref) <= BAR[prec], _rel(x, x_ref)
+    others = np.setdiff1d(np.arange(psi.size), node_of)
+    assert np.all(psi.reshape(-1)[others] == 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_ellipsoid_against_oracle(prec):
+    print(f"case ellipsoid32 {prec}", flush=True)
+    w = W.config(0)
+    psi, emag, info, sinfo = _solve(w, prec)
+    psi_ref, oinfo = oracle.solve(w.sigma_voxel(), w.h, w.a, tol=1e-12)
+    _, e_ref = oracle.efield(w.sigma_voxel(), w.h, w.a, psi_ref, w.omega)
+    assert sinfo["n_dofs"] == 8400 and sinfo["n_components"] == 1
+    assert info["status"] == "OK" and info["rel_residual"] <= 1e-12
+    assert _rel(psi, psi_ref) <= BAR[prec]
+    assert _rel(emag, e_ref) <= BAR[prec]
+    print(f"ellipsoid {prec}: it={info['iterations']} levels={sinfo['n_levels']} "
+          f"psi err={_rel(psi, psi_ref):.2e} E err={_rel(emag, e_ref):.2e}", flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_heterogeneous_against_oracle(prec):
+    print(f"case ellipsoids128x96x256 {prec}", flush=True)
+    w = W.config(1)
+    psi, emag, info, sinfo = _solve(w, prec)
+    psi_ref, oinfo = oracle.solve(w.sigma_voxel(), w.h, w.a, tol=1e-12)
+    _, e_ref = oracle.efield(w.sigma_voxel(), w.h, w.a, psi_ref, w.omega)
+    assert info["status"] == "OK"
+    assert sinfo["n_dofs"] == oinfo["ndof"] and sinfo["n_components"] == oinfo["ncomp"]
+    print(f"hetero {prec}: it={info['iterations']} levels={sinfo['n_levels']} "
+          f"psi err={_rel(psi, psi_ref):.2e} E err={_rel(emag, e_ref):.2e}", flush=True)
+    assert _rel(psi, psi_ref) <= BAR[prec]
+    assert _rel(emag, e_ref) <= BAR[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_manufactured_solution(prec):
+    print(f"case manufactured {prec}", flush=True)
+    w = W.random_ellipsoid_phantom(64, 48, 96, seed=31, n_ell=20, semi_range=(4.0, 14.0))
+    sig = w.sigma_voxel()
+    M = oracle.edge_conductance(sig, w.h)
+    a, psi_star, u_exact = D.manufactured(M, sig > 0, np.random.default_rng(4))
+    s = P.Solver(_dev(w.labels), w.sigma_table, w.h, precision=prec)
+    ad = _dev(a)
+    psi, info = s.solve(ad, tol=1e-12, max_iter=400)
+    emag, u = s.efield(ad, psi, w.omega, want_u=True)
+    s.close()
+    comp, _ = oracle.components(sig, w.h)
+    expect = D.project_mean_zero(psi_star, comp)
+    assert _rel(psi.cpu().numpy(), expect) <= BAR[prec]
+    assert _rel(u.cpu().numpy(), u_exact) <= BAR[prec] * 10
+
+
+def test_efield_kernel_matches_oracle_given_psi():
+    print("case efield-only", flush=True)
+    w = W.config(1)
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal((w.nz + 1, w.ny + 1, w.nx + 1)) * 1e-6
+    s = P.Solver(_dev(w.labels), w.sigma_table, w.h)
+    emag, u = s.efield(_dev(w.a), _dev(psi), w.omega, want_u=True)
+    s.close()
+    u_ref, e_ref = oracle.efield(w.sigma_voxel(), w.h, w.a, psi, w.omega)
+    np.testing.assert_allclose(emag.cpu().numpy(), e_ref, rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(u.cpu().numpy(), u_ref, rtol=1e-12, atol=1e-25)
+
+
+def test_errors_and_status():
+    print("case errors", flush=True)
+    w = W.config(0)
+    lab = _dev(w.labels)
+    h = P.spfd_create(0)
+    try:
+        with pytest.raises(P.SPFDError) as e:
+            P.spfd_build(h)
+        assert e.value.status == 2  # bad state
+        with pytest.raises(P.SPFDError):
+            P.spfd_set_geometry(h, 31, 31, 31, -1.0, 1e-3, 1e-3, lab)
+        P.spfd_set_geometry(h, 31, 31, 31, *w.h, lab)
+        with pytest.raises(P.SPFDError):
+            P.spfd_set_sigma_table(h, [0.0, float("nan")])
+        P.spfd_set_sigma_table(h, [0.0])  # label 1 not covered
+        with pytest.raises(P.SPFDError) as e:
+            P.spfd_build(h)
+        assert e.value.status == 1
+        P.spfd_set_sigma_table(h, [0.0, 0.0])  # no conductor
+        with pytest.raises(P.SPFDError) as e:
+            P.spfd_build(h)
+        assert e.value.status == 1
+    finally:
+        P.spfd_destroy(h)
+    s = P.Solver(lab, w.sigma_table, w.h)
+    psi, info = s.solve(_dev(w.a), tol=1e-12, max_iter=1, check=False)
+    assert info["status"] == "NOT_CONVERGED" and info["iterations"] == 1
+    assert np.isfinite(psi.cpu().numpy()).all()
+    # zero source -> zero potential
+    psi0, info0 = s.solve(torch.zeros_like(_dev(w.a)), tol=1e-8)
+    assert info0["status"] == "OK" and float(psi0.abs().max()) == 0.0
+    s.close()
+
+
+def test_warm_start_and_determinism():
+    print("case warm start", flush=True)
+    w = W.config(1)
+    s = P.Solver(_dev(w.labels), w.sigma_table, w.h, precision="mixed")
+    a = _dev(w.a)
+    p1, i1 = s.solve(a, tol=1e-10)
+    p2, i2 = s.solve(a, tol=1e-10)
+    assert torch.equal(p1, p2) and i1 == i2
+    p3, i3 = s.solve(a, tol=1e-10, x0=p1)
+    assert i3["iterations"] <= 1
+    s.close()
