@@ -151,30 +151,4 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     return s;
 }
 
-// Ticket for the deterministic two-stage reduction: every brick block writes
-// its partial, then the block that arrives last sums the partials in brick
-// order.  Returns true in all threads of that last block (counter re-armed).
-__device__ __forceinline__ bool last_block(int *counter, int nblocks, int *flag_lds)
-{
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ticket = atomicAdd(counter, 1);
-        *flag_lds = (ticket == nblocks - 1);
-        if (*flag_lds) *counter = 0;
-    }
-    __syncthreads();
-    bool last = *flag_lds != 0;
-    if (last) __threadfence();
-    return last;
-}
-
-// fixed-order sum of n partials by one 512-thread block (valid in thread 0)
-__device__ __forceinline__ double sum_partials(const double *part, int n, double *lds)
-{
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return block_sum(s, lds);
-}
-
 }  // namespace spfd

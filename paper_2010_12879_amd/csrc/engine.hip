@@ -91,7 +91,6 @@ struct Ctx {
     Scal *d_scal = nullptr;
     Scal *h_scal = nullptr;   // pinned
     double *d_part = nullptr;
-    int *d_counter = nullptr;
     int *d_ints = nullptr;    // small scratch ints
     int *h_ints = nullptr;    // pinned
     // bookkeeping
@@ -501,8 +500,6 @@ spfd_status do_build(Ctx *c)
     chebyshev_coefficients(c);
     alloc_cycle_buffers(c);
     c->d_part = dalloc<double>(c, c->hier_allocs, (size_t)2 * c->lv[0].nb + 64);
-    c->d_counter = dalloc<int>(c, c->hier_allocs, 16);
-    HIPCHK(hipMemsetAsync(c->d_counter, 0, 16 * sizeof(int), c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return SPFD_OK;
 }
@@ -534,15 +531,15 @@ void pcg_iterations(Ctx *c, int rhs, const spfd_solve_options &so, bool first_pa
     T *z = (T *)c->d_z;
     (void)first_pass;
     vcycle<T>(c, c->d_r, z, sc);
-    HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, c->d_counter, sc, 1, c->stream));
+    HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 1, c->stream));
     HIPCHK(launch_pupdate<T>(topo, z, c->d_p, sc, 1, c->stream));
     const int chunk = 1;
     for (int it = 0; it < so.max_iter + 1; it += chunk) {
         for (int k = 0; k < chunk; ++k) {
-            HIPCHK(launch_spmv_dot(op, topo, c->d_p, c->d_q, c->d_part, c->d_counter, sc, c->stream));
-            HIPCHK(launch_update(topo, c->d_x, c->d_r, c->d_p, c->d_q, c->d_part, c->d_counter, sc, so.max_iter, c->stream));
+            HIPCHK(launch_spmv_dot(op, topo, c->d_p, c->d_q, c->d_part, sc, c->stream));
+            HIPCHK(launch_update(topo, c->d_x, c->d_r, c->d_p, c->d_q, c->d_part, sc, so.max_iter, c->stream));
             vcycle<T>(c, c->d_r, z, sc);
-            HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, c->d_counter, sc, 0, c->stream));
+            HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 0, c->stream));
             HIPCHK(launch_pupdate<T>(topo, z, c->d_p, sc, 0, c->stream));
         }
         HIPCHK(hipMemcpyAsync(c->h_scal + rhs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
@@ -577,7 +574,7 @@ spfd_status do_solve(Ctx *c, const spfd_solve_options &so, double *psi, spfd_rhs
         HIPCHK(launch_scal_init(sc, so.rel_tol, so.use_x0, c->stream));
         if (so.use_x0) {
             HIPCHK(launch_psi_in(psi_r, c->d_comp, L0.d_coord, L0.nb, c->g, c->d_x, c->stream));
-            HIPCHK(launch_resid(op, topo, c->d_b[rhs], c->d_x, c->d_r, c->d_part, c->d_counter, sc, 0, c->stream));
+            HIPCHK(launch_resid(op, topo, c->d_b[rhs], c->d_x, c->d_r, c->d_part, sc, 0, c->stream));
         } else {
             HIPCHK(hipMemsetAsync(c->d_x, 0, n0 * sizeof(double), c->stream));
             HIPCHK(hipMemcpyAsync(c->d_r, c->d_b[rhs], n0 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -594,7 +591,7 @@ spfd_status do_solve(Ctx *c, const spfd_solve_options &so, double *psi, spfd_rhs
                 else
                     pcg_iterations<double>(c, rhs, so, pass == 0);
                 // true residual of the iterate
-                HIPCHK(launch_resid(op, topo, c->d_b[rhs], c->d_x, c->d_r, c->d_part, c->d_counter, sc, 1, c->stream));
+                HIPCHK(launch_resid(op, topo, c->d_b[rhs], c->d_x, c->d_r, c->d_part, sc, 1, c->stream));
                 HIPCHK(hipMemcpyAsync(c->h_scal + rhs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
                 HIPCHK(hipStreamSynchronize(c->stream));
                 const Scal &hs = c->h_scal[rhs];
@@ -609,14 +606,13 @@ spfd_status do_solve(Ctx *c, const spfd_solve_options &so, double *psi, spfd_rhs
             if (status == 0 && relres > so.rel_tol) status = SPFD_NOT_CONVERGED;
         } else if (bb > 0.0) {
             // the start iterate already satisfies the criterion
-            HIPCHK(launch_resid(op, topo, c->d_b[rhs], c->d_x, nullptr, c->d_part, c->d_counter, sc, 1, c->stream));
+            HIPCHK(launch_resid(op, topo, c->d_b[rhs], c->d_x, nullptr, c->d_part, sc, 1, c->stream));
             HIPCHK(hipMemcpyAsync(c->h_scal + rhs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
             relres = sqrt(c->h_scal[rhs].zq / bb);
         }
         // gauge: zero mean per connected component, 0 outside the conductor
-        HIPCHK(launch_comp_mean(topo, c->d_x, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_part, c->d_counter,
-                                c->stream));
+        HIPCHK(launch_comp_mean(topo, c->d_x, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_part, c->stream));
         HIPCHK(launch_psi_out(c->d_x, c->d_comp, c->d_means, L0.d_slot_of, c->g, psi_r, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         if (info) {
@@ -832,7 +828,7 @@ spfd_status spfd_set_source(spfd_handle h, int rhs, const double *a)
         HIPCHK(hipSetDevice(h->device));
         Level &L0 = h->lv[0];
         HIPCHK(hipMemsetAsync(h->d_scal + rhs, 0, sizeof(Scal), h->stream));
-        HIPCHK(launch_rhs(level_op<double>(h, 0), L0.topo(), L0.d_coord, h->g, a, h->d_b[rhs], h->d_part, h->d_counter,
+        HIPCHK(launch_rhs(level_op<double>(h, 0), L0.topo(), L0.d_coord, h->g, a, h->d_b[rhs], h->d_part,
                           h->d_scal + rhs, h->stream));
         HIPCHK(hipMemcpyAsync(h->h_scal + rhs, h->d_scal + rhs, sizeof(Scal), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));

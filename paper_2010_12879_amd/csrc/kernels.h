@@ -48,17 +48,17 @@ template <typename T>
 hipError_t launch_fill(T *x, long long n, T v, hipStream_t s);
 
 hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, const Grid &g, const double *a,
-                      double *b, double *part, int *counter, Scal *sc, hipStream_t s);
+                      double *b, double *part, Scal *sc, hipStream_t s);
 hipError_t launch_scal_init(Scal *sc, double tol, int use_x0, hipStream_t s);
 hipError_t launch_spmv_dot(const OpArgs<double> &op, Topo topo, const double *p, double *q, double *part,
-                           int *counter, Scal *sc, hipStream_t s);
+                           Scal *sc, hipStream_t s);
 hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const double *q, double *part,
-                         int *counter, Scal *sc, int max_iter, hipStream_t s);
+                         Scal *sc, int max_iter, hipStream_t s);
 hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,
-                        double *part, int *counter, Scal *sc, int mode, hipStream_t s);
+                        double *part, Scal *sc, int mode, hipStream_t s);
 template <typename TZ>
-hipError_t launch_dots(Topo topo, const TZ *z, const double *r, const double *q, double *part, int *counter,
-                       Scal *sc, int first, hipStream_t s);
+hipError_t launch_dots(Topo topo, const TZ *z, const double *r, const double *q, double *part, Scal *sc,
+                       int first, hipStream_t s);
 template <typename TZ>
 hipError_t launch_pupdate(Topo topo, const TZ *z, double *p, const Scal *sc, int first, hipStream_t s);
 
@@ -80,7 +80,7 @@ hipError_t launch_coarse_apply(const TB *bc, T *xc, const double *Ainv, const in
 
 // ---------------------------------------------------------------- gauge, output, post-processing
 hipError_t launch_comp_mean(Topo topo, const double *x, const int *comp, int ncomp, const int *counts,
-                            double *sums, double *part, int *counter, hipStream_t s);
+                            double *sums, double *part, hipStream_t s);
 hipError_t launch_psi_out(const double *x, const int *comp, const double *means, const int *slot_of, const Grid &g,
                           double *psi, hipStream_t s);
 hipError_t launch_psi_in(const double *psi, const int *comp, const int4 *coord, int nb, const Grid &g, double *x,

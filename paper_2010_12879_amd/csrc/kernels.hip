@@ -430,15 +430,22 @@ hipError_t launch_components(const double *w64, long long stride, Topo topo, int
 
 __global__ void k_comp_counts(const int *__restrict__ comp, long long n, int *counts)
 {
+    // the first 16 component ids are counted in LDS, one global atomic per block and id
+    __shared__ int local[16];
+    if (threadIdx.x < 16) local[threadIdx.x] = 0;
+    __syncthreads();
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const int c = comp[i];
-        if (c >= 0) atomicAdd(counts + c, 1);
+        if (c >= 16) atomicAdd(counts + c, 1);
+        else if (c >= 0) atomicAdd(local + c, 1);
     }
+    __syncthreads();
+    if (threadIdx.x < 16 && local[threadIdx.x]) atomicAdd(counts + threadIdx.x, local[threadIdx.x]);
 }
 
 hipError_t launch_comp_counts(const int *comp, long long n, int *counts, hipStream_t s)
 {
-    const unsigned gb = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
+    const unsigned gb = (unsigned)((n + 255) / 256 > 4096 ? 4096 : (n + 255) / 256);
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_comp_counts, dim3(gb), dim3(256), 0, s, comp, n, counts);
     return hipGetLastError();
@@ -664,13 +671,119 @@ hipError_t launch_scal_init(Scal *sc, double tol, int use_x0, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- reductions
+// Every reduction is two-stage and deterministic: each brick workgroup stores
+// its partial sum with a plain store, and after the kernel boundary one
+// workgroup (k_finish) sums the partials in a fixed order and updates the
+// scalars of the solve.  No grid-wide fence is needed inside a kernel.
+enum {
+    FIN_BB = 0,       // ||b||^2 of a new right side
+    FIN_ALPHA = 1,    // alpha = r.z / p.q
+    FIN_RR = 2,       // ||r||^2, iteration count and stop test
+    FIN_BETA0 = 3,    // r.z of the first preconditioned residual
+    FIN_BETA = 4,     // flexible beta = -alpha z.q / (r.z)_old
+    FIN_RESID0 = 5,   // ||b - A x0||^2 at the start of a warm-started solve
+    FIN_RESID1 = 6,   // true ||b - A x||^2 at the end of a solve (kept in zq)
+    FIN_MEAN = 7      // mean of a component
+};
+
+__device__ __forceinline__ double block_sum_any(double v, double *lds)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) lds[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+        for (int i = 0; i < nw; ++i) s += lds[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+__global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part, int n, int mode, Scal *sc,
+                                                 int max_iter, double *means, const int *counts, int comp)
+{
+    __shared__ double red[16];
+    if (mode == FIN_ALPHA || mode == FIN_RR || mode == FIN_BETA0 || mode == FIN_BETA)
+        if (sc->done) return;
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a += part[i];
+    a = block_sum_any(a, red);
+    if (mode == FIN_BETA) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) b += part[n + i];
+        b = block_sum_any(b, red);
+    }
+    if (threadIdx.x != 0) return;
+    switch (mode) {
+    case FIN_BB:
+        sc->bb = a;
+        break;
+    case FIN_ALPHA: {
+        sc->pq = a;
+        double alpha = sc->rz / a;
+        if (!(a > 0.0) || !isfinite(alpha)) {
+            alpha = 0.0;
+            sc->status = 6;
+            sc->done = 1;
+        }
+        sc->alpha = alpha;
+        break;
+    }
+    case FIN_RR:
+        sc->rr = a;
+        sc->iters += 1;
+        if (a <= sc->tol2) {
+            sc->done = 1;
+        } else if (!isfinite(a)) {
+            sc->status = 6;
+            sc->done = 1;
+        } else if (sc->iters >= max_iter) {
+            sc->status = 5;
+            sc->done = 1;
+        }
+        break;
+    case FIN_BETA0:
+    case FIN_BETA: {
+        double beta = 0.0;
+        if (mode == FIN_BETA) beta = -sc->alpha * b / sc->rz;
+        if (!(a > 0.0) || !isfinite(beta)) {
+            sc->status = 6;
+            sc->done = 1;
+            beta = 0.0;
+        }
+        sc->zq = b;
+        sc->rz = a;
+        sc->beta = beta;
+        break;
+    }
+    case FIN_RESID0:
+        sc->rr = a;
+        if (a <= sc->tol2) sc->done = 1;
+        break;
+    case FIN_RESID1:
+        sc->zq = a;
+        break;
+    case FIN_MEAN:
+        means[comp] = counts[comp] > 0 ? a / (double)counts[comp] : 0.0;
+        break;
+    }
+}
+
+static hipError_t finish(const double *part, int n, int mode, Scal *sc, int max_iter, hipStream_t s,
+                         double *means = nullptr, const int *counts = nullptr, int comp = 0)
+{
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, part, n, mode, sc, max_iter, means, counts, comp);
+    return hipGetLastError();
+}
+
 // b = -G^T M a on the unknowns of the finest level (Eq. (3), right side):
 // b_n = sum over edges leaving n of M_e a_e - sum over edges entering n of M_e a_e,
 // and ||b||^2.  a is read only on conducting edges (M_e > 0), which all lie in the grid.
 template <bool LABEL>
 __global__ __launch_bounds__(NT) void k_rhs(OpArgs<double> op, Topo topo, const int4 *__restrict__ coord, Grid g,
-                                            const double *__restrict__ a, double *b, double *part, int *counter,
-                                            Scal *sc)
+                                            const double *__restrict__ a, double *b, double *part)
 {
     __shared__ BrickLds<double> L;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
@@ -696,34 +809,27 @@ __global__ __launch_bounds__(NT) void k_rhs(OpArgs<double> op, Topo topo, const 
     b[base + t] = s;
     const double tot = block_sum(s * s, L.red);
     if (t == 0) part[bk] = tot;
-    if (last_block(counter, topo.nb, &L.flag)) {
-        const double bb = sum_partials(part, topo.nb, L.red);
-        if (t == 0) sc->bb = bb;
-    }
 }
 
-template <typename T>
-static OpArgs<T> strip(const OpArgs<T> &op) { return op; }
-
 hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, const Grid &g, const double *a,
-                      double *b, double *part, int *counter, Scal *sc, hipStream_t s)
+                      double *b, double *part, Scal *sc, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
     if (op.w)
-        hipLaunchKernelGGL(k_rhs<false>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, coord, g, a, b, part,
-                           counter, sc);
+        hipLaunchKernelGGL(k_rhs<false>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, coord, g, a, b, part);
     else
-        hipLaunchKernelGGL(k_rhs<true>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, coord, g, a, b, part,
-                           counter, sc);
-    return hipGetLastError();
+        hipLaunchKernelGGL(k_rhs<true>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, coord, g, a, b, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finish(part, topo.nb, FIN_BB, sc, 0, s);
 }
 
-// q = A p and p.q; the last block forms alpha = r.z / p.q
+// q = A p and the partials of p.q (alpha follows in k_finish)
 __global__ __launch_bounds__(NT) void k_spmv_dot(OpArgs<double> op, Topo topo, const double *__restrict__ p,
-                                                 double *__restrict__ q, double *part, int *counter, Scal *sc)
+                                                 double *__restrict__ q, double *part, const Scal *sc)
 {
     __shared__ BrickLds<double> L;
-    if (__hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    if (sc->done) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
     op_prepare(op, topo, bk, L);
@@ -739,38 +845,25 @@ __global__ __launch_bounds__(NT) void k_spmv_dot(OpArgs<double> op, Topo topo, c
     q[base + t] = y;
     const double tot = block_sum(p0 * y, L.red);
     if (t == 0) part[bk] = tot;
-    if (last_block(counter, topo.nb, &L.flag)) {
-        const double pq = sum_partials(part, topo.nb, L.red);
-        if (t == 0) {
-            sc->pq = pq;
-            double alpha = sc->rz / pq;
-            if (!(pq > 0.0) || !isfinite(alpha)) {
-                alpha = 0.0;
-                sc->status = 6;
-                sc->done = 1;
-            }
-            sc->alpha = alpha;
-        }
-    }
 }
 
-hipError_t launch_spmv_dot(const OpArgs<double> &op, Topo topo, const double *p, double *q, double *part,
-                           int *counter, Scal *sc, hipStream_t s)
+hipError_t launch_spmv_dot(const OpArgs<double> &op, Topo topo, const double *p, double *q, double *part, Scal *sc,
+                           hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spmv_dot, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, p, q, part, counter, sc);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_spmv_dot, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, p, q, part, sc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finish(part, topo.nb, FIN_ALPHA, sc, 0, s);
 }
 
-// x += alpha p, r -= alpha q, ||r||^2; the last block counts the iteration and
-// raises the stop flag at ||r|| <= tol ||b|| or at max_iter
+// x += alpha p, r -= alpha q and the partials of ||r||^2 (stop test in k_finish)
 __global__ __launch_bounds__(NT) void k_update(Topo topo, double *__restrict__ x, double *__restrict__ r,
                                                const double *__restrict__ p, const double *__restrict__ q,
-                                               double *part, int *counter, Scal *sc, int max_iter)
+                                               double *part, const Scal *sc)
 {
     __shared__ double red[8];
-    __shared__ int flag;
-    if (__hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    if (sc->done) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
     const double alpha = sc->alpha;
@@ -780,38 +873,22 @@ __global__ __launch_bounds__(NT) void k_update(Topo topo, double *__restrict__ x
     r[n] = rn;
     const double tot = block_sum(rn * rn, red);
     if (threadIdx.x == 0) part[bk] = tot;
-    if (last_block(counter, topo.nb, &flag)) {
-        const double rr = sum_partials(part, topo.nb, red);
-        if (threadIdx.x == 0) {
-            sc->rr = rr;
-            sc->iters += 1;
-            if (rr <= sc->tol2) {
-                sc->done = 1;
-            } else if (!isfinite(rr)) {
-                sc->status = 6;
-                sc->done = 1;
-            } else if (sc->iters >= max_iter) {
-                sc->status = 5;
-                sc->done = 1;
-            }
-        }
-    }
 }
 
-hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const double *q, double *part,
-                         int *counter, Scal *sc, int max_iter, hipStream_t s)
+hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const double *q, double *part, Scal *sc,
+                         int max_iter, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_update, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, r, p, q, part, counter, sc,
-                       max_iter);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_update, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, r, p, q, part, sc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finish(part, topo.nb, FIN_RR, sc, max_iter, s);
 }
 
-// r = b - A x and ||r||^2.  mode 0: start of a solve (sets rr); mode 1: final
-// check (stores the true relative residual in sc->zq as ||r||^2).
+// r = b - A x (r may be null) and the partials of ||r||^2.  mode 0: start of a
+// warm-started solve; mode 1: true residual at the end (stored in sc->zq).
 __global__ __launch_bounds__(NT) void k_resid(OpArgs<double> op, Topo topo, const double *__restrict__ b,
-                                              const double *__restrict__ x, double *__restrict__ r, double *part,
-                                              int *counter, Scal *sc, int mode)
+                                              const double *__restrict__ x, double *__restrict__ r, double *part)
 {
     __shared__ BrickLds<double> L;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
@@ -828,36 +905,25 @@ __global__ __launch_bounds__(NT) void k_resid(OpArgs<double> op, Topo topo, cons
     if (r) r[base + t] = rv;
     const double tot = block_sum(rv * rv, L.red);
     if (t == 0) part[bk] = tot;
-    if (last_block(counter, topo.nb, &L.flag)) {
-        const double rr = sum_partials(part, topo.nb, L.red);
-        if (t == 0) {
-            if (mode == 0) {
-                sc->rr = rr;
-                if (rr <= sc->tol2) sc->done = 1;
-            } else {
-                sc->zq = rr;
-            }
-        }
-    }
 }
 
 hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,
-                        double *part, int *counter, Scal *sc, int mode, hipStream_t s)
+                        double *part, Scal *sc, int mode, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_resid, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, b, x, r, part, counter, sc, mode);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_resid, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, b, x, r, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finish(part, topo.nb, mode == 0 ? FIN_RESID0 : FIN_RESID1, sc, 0, s);
 }
 
-// r.z and z.q; the last block forms the flexible (Polak-Ribiere) beta = -alpha z.q / (r.z)_old
+// partials of r.z and z.q (flexible beta follows in k_finish)
 template <typename TZ>
 __global__ __launch_bounds__(NT) void k_dots(Topo topo, const TZ *__restrict__ z, const double *__restrict__ r,
-                                             const double *__restrict__ q, double *part, int *counter, Scal *sc,
-                                             int first)
+                                             const double *__restrict__ q, double *part, const Scal *sc, int first)
 {
     __shared__ double red[8];
-    __shared__ int flag;
-    if (__hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    if (sc->done) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
     const long long n = (long long)bk * BS + threadIdx.x;
@@ -868,42 +934,28 @@ __global__ __launch_bounds__(NT) void k_dots(Topo topo, const TZ *__restrict__ z
         part[bk] = a;
         part[topo.nb + bk] = c;
     }
-    if (last_block(counter, topo.nb, &flag)) {
-        const double rz = sum_partials(part, topo.nb, red);
-        const double zq = first ? 0.0 : sum_partials(part + topo.nb, topo.nb, red);
-        if (threadIdx.x == 0) {
-            double beta = 0.0;
-            if (!first) beta = -sc->alpha * zq / sc->rz;
-            if (!(rz > 0.0) || !isfinite(beta)) {
-                sc->status = 6;
-                sc->done = 1;
-                beta = 0.0;
-            }
-            sc->zq = zq;
-            sc->rz = rz;
-            sc->beta = beta;
-        }
-    }
 }
 
 template <typename TZ>
-hipError_t launch_dots(Topo topo, const TZ *z, const double *r, const double *q, double *part, int *counter,
-                       Scal *sc, int first, hipStream_t s)
+hipError_t launch_dots(Topo topo, const TZ *z, const double *r, const double *q, double *part, Scal *sc, int first,
+                       hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dots<TZ>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, z, r, q, part, counter, sc, first);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_dots<TZ>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, z, r, q, part, sc, first);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finish(part, topo.nb, first ? FIN_BETA0 : FIN_BETA, sc, 0, s);
 }
-template hipError_t launch_dots<double>(Topo, const double *, const double *, const double *, double *, int *, Scal *,
-                                        int, hipStream_t);
-template hipError_t launch_dots<float>(Topo, const float *, const double *, const double *, double *, int *, Scal *,
-                                       int, hipStream_t);
+template hipError_t launch_dots<double>(Topo, const double *, const double *, const double *, double *, Scal *, int,
+                                        hipStream_t);
+template hipError_t launch_dots<float>(Topo, const float *, const double *, const double *, double *, Scal *, int,
+                                       hipStream_t);
 
 template <typename TZ>
 __global__ __launch_bounds__(NT) void k_pupdate(Topo topo, const TZ *__restrict__ z, double *__restrict__ p,
                                                 const Scal *sc, int first)
 {
-    if (__hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    if (sc->done) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
     const long long n = (long long)bk * BS + threadIdx.x;
@@ -1124,22 +1176,17 @@ template hipError_t launch_coarse_apply<float, double>(const double *, float *, 
 // gauge, output, post-processing
 // ============================================================================
 
-// mean of x over component c (deterministic two-stage sum), one launch per component
+// partial sums of x over component c (deterministic two-stage sum, one pass per component)
 __global__ __launch_bounds__(NT) void k_comp_sum(Topo topo, const double *__restrict__ x, const int *__restrict__ comp,
-                                                 int c, const int *counts, double *means, double *part, int *counter)
+                                                 int c, double *part)
 {
     __shared__ double red[8];
-    __shared__ int flag;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
     const long long n = (long long)bk * BS + threadIdx.x;
     const double v = comp[n] == c ? x[n] : 0.0;
     const double tot = block_sum(v, red);
     if (threadIdx.x == 0) part[bk] = tot;
-    if (last_block(counter, topo.nb, &flag)) {
-        const double s = sum_partials(part, topo.nb, red);
-        if (threadIdx.x == 0) means[c] = counts[c] > 0 ? s / (double)counts[c] : 0.0;
-    }
 }
 
 // many components: FP64 atomics (order-dependent rounding) then division
@@ -1158,13 +1205,15 @@ __global__ void k_comp_div(int nc, const int *counts, double *means)
 }
 
 hipError_t launch_comp_mean(Topo topo, const double *x, const int *comp, int ncomp, const int *counts, double *means,
-                            double *part, int *counter, hipStream_t s)
+                            double *part, hipStream_t s)
 {
     if (topo.nb <= 0 || ncomp <= 0) return hipSuccess;
     if (ncomp <= 16) {
-        for (int c = 0; c < ncomp; ++c)
-            hipLaunchKernelGGL(k_comp_sum, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, comp, c, counts, means,
-                               part, counter);
+        for (int c = 0; c < ncomp; ++c) {
+            hipLaunchKernelGGL(k_comp_sum, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, comp, c, part);
+            hipError_t e = finish(part, topo.nb, FIN_MEAN, nullptr, 0, s, means, counts, c);
+            if (e != hipSuccess) return e;
+        }
     } else {
         const long long n = (long long)topo.nb * BS;
         hipError_t e = launch_fill<double>(means, ncomp, 0.0, s);
