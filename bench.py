@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark of the Co-Sim. SPFD hot path on one MI355X.
+
+Workload: the body-shaped 2 mm phantom (250x150x900 voxels, ~8.9 M unknowns,
+40 tissues, rectangular-loop source at 85 kHz), inputs resident in HBM.
+A step is one pass of the whole path on the GPU:
+  conductances + multigrid hierarchy (spfd_set_sigma_table + spfd_build),
+  right side b = -G^T M a (spfd_set_source),
+  AMG-preconditioned CG to relative residual 1e-8 (spfd_solve),
+  edge voltages and voxel-averaged |E| (spfd_efield).
+The headline value is the solve time with the FP32 cycle inside FP64 CG;
+the same steps are timed with the all-FP64 cycle for the speedup.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DOMINANT = 4          # SPFD_K_SMOOTH0: finest-level Chebyshev step (the cycle's hottest kernel)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=150, help="oracle iterations in the bounded CPU sample")
+    ap.add_argument("--precisions", default="mixed,fp64")
+    return ap.parse_args()
+
+
+def run_precision(prec, w, lab, a, args, P, torch):
+    dev = lab.device
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    h = P.spfd_create(dev.index or 0, stream)
+    nx, ny, nz = w.nx, w.ny, w.nz
+    P.spfd_set_geometry(h, nx, ny, nz, *w.h, lab)
+    opts = P.AmgOptions(P.MIXED if prec == "mixed" else P.FP64, P.CYCLE_V, 0, 0, 0.0, 0.0)
+    sopt = P.SolveOptions(args.tol, 500, 0)
+    psi = torch.empty((nz + 1, ny + 1, nx + 1), dtype=torch.float64, device=dev)
+    emag = torch.empty((nz, ny, nx), dtype=torch.float64, device=dev)
+    phases = {"setup": [], "rhs": [], "solve": [], "efield": [], "step": []}
+    info = None
+
+    def step(record):
+        nonlocal info
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.spfd_set_sigma_table(h, list(w.sigma_table))
+        P.spfd_build(h, opts)
+        t1 = time.perf_counter()
+        P.spfd_set_source(h, 0, a)
+        t2 = time.perf_counter()
+        st, inf = P.spfd_solve(h, sopt, psi, 1)
+        t3 = time.perf_counter()
+        P.spfd_efield(h, w.omega, a, psi, None, emag)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        if st != 0:
+            raise RuntimeError(f"solve failed: {inf}")
+        info = inf[0]
+        if record:
+            for k, v in (("setup", t1 - t0), ("rhs", t2 - t1), ("solve", t3 - t2), ("efield", t4 - t3),
+                         ("step", t4 - t0)):
+                phases[k].append(v)
+
+    for _ in range(args.warmup):
+        step(False)
+    P.spfd_timing(h, 1 << DOMINANT)
+    for _ in range(args.steps):
+        step(True)
+    stats = {name: P.spfd_timing_get(h, k) for k, name in enumerate(P.KERNEL_CLASSES)}
+    ndofs = P.spfd_get_info(h)
+    P.spfd_destroy(h)
+    return phases, info, stats, ndofs, psi.cpu().numpy(), emag
+
+
+def mean(v):
+    return sum(v) / len(v)
+
+
+def std(v):
+    m = mean(v)
+    return (sum((x - m) ** 2 for x in v) / max(len(v) - 1, 1)) ** 0.5
+
+
+def cpu_baseline(w, args, iters_full):
+    """The oracle (FP64 Jacobi-PCG on CSR) on a bounded sample of the same solve."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    psi, info = oracle.solve(w.sigma_voxel(), w.h, w.a, tol=args.tol, max_iter=args.cpu_iters, nthreads=threads)
+    wall = time.perf_counter() - t0
+    per_it = info["t_solve"] / max(info["iterations"], 1)
+    est = info["t_assemble"] + per_it * iters_full
+    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": (f"{info['iterations']} Jacobi-PCG iterations of the {info['ndof']}-unknown body solve "
+                       f"({wall:.1f} s wall incl. assembly {info['t_assemble']:.1f} s), scaled to the "
+                       f"{iters_full} iterations the oracle needs for rel. residual {args.tol:g}"),
+            "s_per_iteration": per_it, "iterations_full": iters_full}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_2010_12879_amd as P
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    w = W.config(2)
+    lab = torch.from_numpy(w.labels).to(dev)
+    a = torch.from_numpy(w.a).to(dev).contiguous()
+    t_gen = time.perf_counter() - t0
+    print(f"# inputs generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
+
+    res = {}
+    for prec in args.precisions.split(","):
+        res[prec] = run_precision(prec, w, lab, a, args, P, torch)
+        ph, info, stats, ninfo, _, _ = res[prec]
+        print(f"# {prec}: solve {mean(ph['solve'])*1e3:.2f} ms, {info['iterations']} it, "
+              f"relres {info['rel_residual']:.2e}", file=sys.stderr, flush=True)
+
+    head = "mixed" if "mixed" in res else list(res)[0]
+    ph, info, stats, ninfo, psi_head, _ = res[head]
+    solve_s = mean(ph["solve"])
+    # algorithmic HBM bytes of the solve: every kernel class except setup/rhs/efield, per step
+    solve_bytes = sum(v[2] for k, v in stats.items() if k not in ("rhs", "efield")) / args.steps
+    n_dom, ms_dom, by_dom = stats["smooth0"]
+    achieved = (by_dom / n_dom) / (ms_dom / n_dom * 1e-3) / 1e9 if n_dom and ms_dom > 0 else None
+
+    # independent check of the headline solution with the oracle's own assembly
+    import oracle
+    oracle_relres = oracle.residual(w.sigma_voxel(), w.h, w.a, psi_head)
+
+    out = {
+        "metric": "AMG-PCG solve time @8.9M DOF to 1e-8 rel res; HBM GB/s; mixed vs FP64 speedup",
+        "value": solve_s,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mean(ph["step"]) * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 cycle / f64 CG" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: 2 mm body phantom, {ninfo['n_dofs']} unknowns, 40 tissues, "
+                               f"rectangular loop 0.3x0.2 m at 85 kHz",
+                   "rel_tol": args.tol, "precision": head, "levels": ninfo["n_levels"]},
+        "solve_ms_mean": solve_s * 1e3,
+        "solve_ms_std": std(ph["solve"]) * 1e3,
+        "iterations": info["iterations"],
+        "rel_residual": info["rel_residual"],
+        "oracle_rel_residual": oracle_relres,
+        "setup_ms": mean(ph["setup"]) * 1e3,
+        "rhs_ms": mean(ph["rhs"]) * 1e3,
+        "efield_ms": mean(ph["efield"]) * 1e3,
+        "solve_hbm_gbs": solve_bytes / solve_s / 1e9,
+        "device_bytes": ninfo["device_bytes"],
+        "roofline": {"bound": "hbm", "kernel": "k_cheb_step (finest level)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "launches": n_dom, "avg_us": ms_dom / n_dom * 1e3 if n_dom else None,
+                     "algorithmic_bytes_per_launch": by_dom / n_dom if n_dom else None},
+    }
+    if "fp64" in res and head != "fp64":
+        ph64, info64, _, _, psi64, _ = res["fp64"]
+        out["fp64_solve_ms_mean"] = mean(ph64["solve"]) * 1e3
+        out["fp64_iterations"] = info64["iterations"]
+        out["mixed_vs_fp64_speedup"] = mean(ph64["solve"]) / solve_s
+        import numpy as np
+        out["mixed_vs_fp64_rel_diff"] = float(np.linalg.norm(psi_head - psi64) / np.linalg.norm(psi64))
+    if not args.no_cpu_baseline:
+        gold = os.path.join(ROOT, "tests", "golden", f"oracle_body_{args.tol:.0e}.json")
+        iters_full = json.load(open(gold))["iterations"] if os.path.exists(gold) else None
+        if iters_full:
+            out["cpu_baseline"] = cpu_baseline(w, args, iters_full)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

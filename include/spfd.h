@@ -67,9 +67,10 @@ typedef struct {
     int precision;        /* SPFD_FP64 (default) or SPFD_MIXED: FP32 cycle, FP64 outer CG, dots and coarsest solve */
     int cycle;            /* SPFD_CYCLE_V (default) or SPFD_CYCLE_K */
     int smooth_degree;    /* Chebyshev degree per pre/post smoothing, default 2, max 4 */
-    int coarsest_max;     /* coarsen until the coarsest level has <= this many unknowns, default 400, max 1024 */
+    int coarsest_max;     /* coarsen until the coarsest level has <= this many unknowns, default and max 1024 */
     double cheby_ratio;   /* smoothing interval [2/ratio, 2] of D^-1 A, default 8 */
-    double coarse_scale;  /* scaling of the coarse-grid correction, default 1 */
+    double coarse_scale;  /* scaling of the coarse-grid correction (over-correction of the piecewise-constant
+                             aggregation), default 1.8; keep below 2 */
 } spfd_amg_options;
 
 typedef struct {
@@ -123,6 +124,35 @@ spfd_status spfd_solve(spfd_handle h, const spfd_solve_options *opt, double *psi
  * conducting voxel, 0 in air.  a and psi as in spfd_set_source / spfd_solve. */
 spfd_status spfd_efield(spfd_handle h, double omega, const double *a, const double *psi,
                         double *u_edges, double *emag);
+
+/* Per-launch timing, a tracing aid.  Kernel classes: */
+enum {
+    SPFD_K_SPMV = 0,          /* outer CG: q = A p on the finest level (FP64) and p.q partials */
+    SPFD_K_UPDATE = 1,        /* outer CG: x += alpha p, r -= alpha q, ||r||^2 partials */
+    SPFD_K_DOTS = 2,          /* outer CG: r.z and z.q partials */
+    SPFD_K_PUPDATE = 3,       /* outer CG: p = z + beta p */
+    SPFD_K_SMOOTH0 = 4,       /* finest level: Chebyshev step with a stencil application */
+    SPFD_K_SMOOTH0_FIRST = 5, /* finest level: first Chebyshev step from zero (no stencil) */
+    SPFD_K_RESTRICT0 = 6,     /* finest level: residual and restriction */
+    SPFD_K_PROLONG0 = 7,      /* finest level: prolongation and correction */
+    SPFD_K_COARSE = 8,        /* every kernel of the coarser levels and the coarsest solve */
+    SPFD_K_FINISH = 9,        /* one-workgroup reduction finishers */
+    SPFD_K_RHS = 10,          /* right side b = -G^T M a */
+    SPFD_K_EFIELD = 11,       /* E-field and edge voltages */
+    SPFD_K_GAUGE = 12,        /* component means and the output of psi */
+    SPFD_K_COUNT = 13
+};
+/* Enable timing for the classes in the bit mask (1 << class); resets all
+ * counters.  While enabled, each launch of such a class is bracketed by two
+ * HIP events on the handle's stream. */
+spfd_status spfd_timing(spfd_handle h, unsigned int class_mask);
+/* Launch count, summed event time (ms) and algorithmic bytes of a class since
+ * the last spfd_timing call.  Algorithmic bytes count, per unknown of the level,
+ * one read or write of each array the kernel touches (1 byte per voxel label,
+ * 3 weights per node where weights are stored); bytes are counted whether or
+ * not timing is enabled for the class. */
+spfd_status spfd_timing_get(spfd_handle h, int kclass, long long *launches, double *total_ms,
+                            double *algorithmic_bytes);
 
 #ifdef __cplusplus
 }

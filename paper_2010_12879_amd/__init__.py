@@ -50,7 +50,10 @@ class RhsInfo(ctypes.Structure):
 _lib = None
 EXPORTS = ["spfd_create", "spfd_destroy", "spfd_last_error", "spfd_set_geometry", "spfd_set_sigma_table",
            "spfd_set_sigma_voxel", "spfd_build", "spfd_get_info", "spfd_set_num_rhs", "spfd_set_source",
-           "spfd_solve", "spfd_efield"]
+           "spfd_solve", "spfd_efield", "spfd_timing", "spfd_timing_get"]
+# kernel classes of spfd_timing / spfd_timing_get (order of the enum in spfd.h)
+KERNEL_CLASSES = ["spmv", "update", "dots", "pupdate", "smooth0", "smooth0_first", "restrict0", "prolong0", "coarse",
+                  "finish", "rhs", "efield", "gauge"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -79,6 +82,8 @@ def load_library(path: str = LIB_PATH):
     lib.spfd_set_source.argtypes = [H, I, P]
     lib.spfd_solve.argtypes = [H, ctypes.POINTER(SolveOptions), P, ctypes.POINTER(RhsInfo)]
     lib.spfd_efield.argtypes = [H, D, P, P, P, P]
+    lib.spfd_timing.argtypes = [H, ctypes.c_uint]
+    lib.spfd_timing_get.argtypes = [H, I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D), ctypes.POINTER(D)]
     for name in EXPORTS:
         if name not in ("spfd_destroy", "spfd_last_error"):
             getattr(lib, name).restype = I
@@ -183,6 +188,17 @@ def spfd_efield(h, omega, a, psi, u_edges, emag):
     return _check(h, load_library().spfd_efield(h, float(omega), _ptr(a), _ptr(psi), _ptr(u_edges), _ptr(emag)))
 
 
+def spfd_timing(h, class_mask: int):
+    return _check(h, load_library().spfd_timing(h, class_mask))
+
+
+def spfd_timing_get(h, kclass: int):
+    """(launches, total milliseconds, algorithmic bytes) of a kernel class."""
+    n, ms, by = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+    _check(h, load_library().spfd_timing_get(h, kclass, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    return n.value, ms.value, by.value
+
+
 # ---------------------------------------------------------------- convenience
 class Solver:
     """Eq. (3) solver on one voxel model; the hierarchy is reused for every source.
@@ -191,8 +207,8 @@ class Solver:
     normally) or a float64 CUDA tensor per voxel; h: voxel edge lengths (m).
     """
 
-    def __init__(self, labels, sigma, h, precision="fp64", device=None, smooth_degree=2, coarsest_max=400,
-                 cheby_ratio=8.0, coarse_scale=1.0, cycle="v"):
+    def __init__(self, labels, sigma, h, precision="fp64", device=None, smooth_degree=2, coarsest_max=1024,
+                 cheby_ratio=8.0, coarse_scale=1.8, cycle="v"):
         import torch
         self.device = labels.device if device is None else torch.device(device)
         self.nz, self.ny, self.nx = labels.shape

@@ -62,32 +62,52 @@ __device__ __forceinline__ void brick_xyz(int t, int &tx, int &ty, int &tz)
     tz = t >> 6;
 }
 
-// values of the six face neighbours of node t of brick b (0 where absent)
-template <typename T>
-__device__ __forceinline__ void nbr_vals(const T *__restrict__ x, long long base, int t, int tx, int ty, int tz,
-                                         const int *nb, T X[6])
+// Index of each face neighbour of node t of brick b.  A neighbour in an absent
+// brick is never a conductor node, and the edge to it has conductance 0, so
+// it is replaced by the node itself: every lane issues exactly one load per
+// direction and the stencil term w (x_n - x_n) vanishes.
+__device__ __forceinline__ void nbr_index(long long base, int t, int tx, int ty, int tz, const int *nb,
+                                          long long I[6])
 {
-    X[NMX] = tx > 0 ? x[base + t - 1] : (nb[NMX] >= 0 ? x[(long long)nb[NMX] * BS + t + 7] : T(0));
-    X[NPX] = tx < 7 ? x[base + t + 1] : (nb[NPX] >= 0 ? x[(long long)nb[NPX] * BS + t - 7] : T(0));
-    X[NMY] = ty > 0 ? x[base + t - 8] : (nb[NMY] >= 0 ? x[(long long)nb[NMY] * BS + t + 56] : T(0));
-    X[NPY] = ty < 7 ? x[base + t + 8] : (nb[NPY] >= 0 ? x[(long long)nb[NPY] * BS + t - 56] : T(0));
-    X[NMZ] = tz > 0 ? x[base + t - 64] : (nb[NMZ] >= 0 ? x[(long long)nb[NMZ] * BS + t + 448] : T(0));
-    X[NPZ] = tz < 7 ? x[base + t + 64] : (nb[NPZ] >= 0 ? x[(long long)nb[NPZ] * BS + t - 448] : T(0));
+    const long long self = base + t;
+    I[NMX] = tx > 0 ? self - 1 : (nb[NMX] >= 0 ? (long long)nb[NMX] * BS + t + 7 : self);
+    I[NPX] = tx < 7 ? self + 1 : (nb[NPX] >= 0 ? (long long)nb[NPX] * BS + t - 7 : self);
+    I[NMY] = ty > 0 ? self - 8 : (nb[NMY] >= 0 ? (long long)nb[NMY] * BS + t + 56 : self);
+    I[NPY] = ty < 7 ? self + 8 : (nb[NPY] >= 0 ? (long long)nb[NPY] * BS + t - 56 : self);
+    I[NMZ] = tz > 0 ? self - 64 : (nb[NMZ] >= 0 ? (long long)nb[NMZ] * BS + t + 448 : self);
+    I[NPZ] = tz < 7 ? self + 64 : (nb[NPZ] >= 0 ? (long long)nb[NPZ] * BS + t - 448 : self);
+}
+
+template <typename T>
+__device__ __forceinline__ void nbr_vals(const T *__restrict__ x, const long long I[6], T X[6])
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) X[k] = x[I[k]];
 }
 
 // edge weights of node t from stored arrays w[d*stride + node] (edge to +d);
 // the minus-side weights are the plus-side weights of the minus neighbours
+// (0 when that neighbour's brick is absent)
 template <typename T>
 __device__ __forceinline__ void stored_weights(const T *__restrict__ w, long long stride, long long base, int t,
-                                               int tx, int ty, int tz, const int *nb, T W[6])
+                                               const long long I[6], T W[6])
 {
     const long long n = base + t;
     W[NPX] = w[n];
     W[NPY] = w[stride + n];
     W[NPZ] = w[2 * stride + n];
-    W[NMX] = tx > 0 ? w[n - 1] : (nb[NMX] >= 0 ? w[(long long)nb[NMX] * BS + t + 7] : T(0));
-    W[NMY] = ty > 0 ? w[stride + n - 8] : (nb[NMY] >= 0 ? w[stride + (long long)nb[NMY] * BS + t + 56] : T(0));
-    W[NMZ] = tz > 0 ? w[2 * stride + n - 64] : (nb[NMZ] >= 0 ? w[2 * stride + (long long)nb[NMZ] * BS + t + 448] : T(0));
+    const T mx = w[I[NMX]], my = w[stride + I[NMY]], mz = w[2 * stride + I[NMZ]];
+    W[NMX] = I[NMX] != n ? mx : T(0);
+    W[NMY] = I[NMY] != n ? my : T(0);
+    W[NMZ] = I[NMZ] != n ? mz : T(0);
+}
+
+// the six neighbour slots of a brick (uniform across the workgroup: scalar loads)
+__device__ __forceinline__ void brick_nbrs(const int *nbr, int b, int nb[6])
+{
+    const int *p = nbr + b * 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) nb[k] = p[k];
 }
 
 // Conductances of the six edges of a node from the conductivities of its eight

@@ -93,8 +93,17 @@ struct Ctx {
     double *d_part = nullptr;
     int *d_ints = nullptr;    // small scratch ints
     int *h_ints = nullptr;    // pinned
-    // bookkeeping
+    // per-class launch timing (tracing aid)
+    unsigned tmask = 0;
+    std::vector<hipEvent_t> tev[SPFD_K_COUNT];
+    size_t tused[SPFD_K_COUNT] = {};
+    long long tlaunch[SPFD_K_COUNT] = {};
+    double tbytes[SPFD_K_COUNT] = {};
+    // bookkeeping: live allocations per owner, and released buffers kept for
+    // reuse (a rebuild with the same geometry allocates nothing)
     std::vector<void *> geo_allocs, hier_allocs, rhs_allocs;
+    std::vector<std::pair<size_t, void *>> pool;
+    std::vector<std::pair<void *, size_t>> sizes;
     size_t bytes = 0;
 };
 
@@ -109,23 +118,62 @@ struct HipFail {
         if (e_ != hipSuccess) throw HipFail{e_, #__VA_ARGS__};       \
     } while (0)
 
+size_t size_of(Ctx *c, void *p)
+{
+    for (auto &q : c->sizes)
+        if (q.first == p) return q.second;
+    return 0;
+}
+
 template <typename T>
 T *dalloc(Ctx *c, std::vector<void *> &owner, size_t count)
 {
-    void *p = nullptr;
     size_t bytes = count * sizeof(T);
-    if (bytes == 0) bytes = 256;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
+    bytes = bytes == 0 ? 256 : (bytes + 255) & ~(size_t)255;
+    void *p = nullptr;
+    for (size_t i = 0; i < c->pool.size(); ++i)
+        if (c->pool[i].first == bytes) {
+            p = c->pool[i].second;
+            c->pool.erase(c->pool.begin() + i);
+            break;
+        }
+    if (!p) {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            // give the cached buffers back and try once more
+            for (auto &q : c->pool) (void)hipFree(q.second);
+            c->pool.clear();
+            e = hipMalloc(&p, bytes);
+            if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
+        }
+        c->sizes.push_back({p, bytes});
+    }
     owner.push_back(p);
     c->bytes += bytes;
     return (T *)p;
 }
 
+// release an owner's buffers into the reuse pool
 void free_all(Ctx *c, std::vector<void *> &owner)
 {
-    for (void *p : owner) (void)hipFree(p);
+    for (void *p : owner) {
+        const size_t b = size_of(c, p);
+        c->bytes -= b;
+        c->pool.push_back({b, p});
+    }
     owner.clear();
+}
+
+// return every buffer to the device
+void release_device(Ctx *c)
+{
+    free_all(c, c->rhs_allocs);
+    free_all(c, c->hier_allocs);
+    free_all(c, c->geo_allocs);
+    for (auto &q : c->pool) (void)hipFree(q.second);
+    c->pool.clear();
+    c->sizes.clear();
+    c->bytes = 0;
 }
 
 spfd_status fail(Ctx *c, spfd_status s, const std::string &msg)
@@ -133,6 +181,37 @@ spfd_status fail(Ctx *c, spfd_status s, const std::string &msg)
     if (c) c->err = msg;
     return s;
 }
+
+// Brackets one launch of kernel class `cls` with HIP events when timing is on
+// for that class, and adds the launch's algorithmic bytes to the class counter.
+struct TScope {
+    Ctx *c;
+    int cls;
+    bool on;
+    TScope(Ctx *c_, int cls_, double bytes) : c(c_), cls(cls_), on((c_->tmask >> cls_) & 1u)
+    {
+        c->tlaunch[cls] += 1;
+        c->tbytes[cls] += bytes;
+        if (on) record();
+    }
+    ~TScope()
+    {
+        if (on) record();
+    }
+    void record()
+    {
+        std::vector<hipEvent_t> &v = c->tev[cls];
+        if (c->tused[cls] == v.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                on = false;
+                return;
+            }
+            v.push_back(e);
+        }
+        (void)hipEventRecord(v[c->tused[cls]++], c->stream);
+    }
+};
 
 // ------------------------------------------------------------ brick topology on the host
 void build_topology(Ctx *c, Level &L, const std::vector<uint8_t> &flags, std::vector<void *> &owner)
@@ -186,7 +265,9 @@ __global__ void k_count_dofs(const double *w, long long stride, Topo topo, int *
     int tx, ty, tz;
     brick_xyz(t, tx, ty, tz);
     double W[6];
-    stored_weights(w, stride, (long long)b * BS, t, tx, ty, tz, nb, W);
+    long long I[6];
+    nbr_index((long long)b * BS, t, tx, ty, tz, nb, I);
+    stored_weights(w, stride, (long long)b * BS, t, I, W);
     if (diag_of(W) > 0.0) atomicAdd(&cnt, 1);
     __syncthreads();
     if (t == 0 && cnt) atomicAdd(count, cnt);
@@ -242,50 +323,86 @@ OpArgs<float> level_op<float>(Ctx *c, int l)
 }
 
 // ------------------------------------------------------------ the multigrid cycle
+// algorithmic bytes per unknown of the operator: 1 label byte on the finest
+// level in label form, otherwise the three stored weights of the node
 template <typename T>
-void smooth_pre(Ctx *c, int l, const void *bvoid, bool b_is_fp64, T *&cur, T *&other, const Scal *sc)
+double op_bytes(Ctx *c, int l)
+{
+    return (l == 0 && !c->voxel_mode) ? 1.0 : 3.0 * sizeof(T);
+}
+
+template <typename T, typename TB>
+void cheb_first(Ctx *c, int l, const TB *b, T *x, const Scal *sc)
 {
     Level &L = c->lv[l];
-    const OpArgs<T> op = level_op<T>(c, l);
+    const double by = (double)L.dofs * (sizeof(TB) + op_bytes<T>(c, l) + sizeof(T));
+    TScope ts(c, l == 0 ? SPFD_K_SMOOTH0_FIRST : SPFD_K_COARSE, by);
+    HIPCHK(launch_cheb_first<T, TB>(level_op<T>(c, l), L.topo(), b, x, (T)c->cheb_c0, sc, c->stream));
+}
+
+template <typename T, typename TB>
+void cheb_step(Ctx *c, int l, const TB *b, const T *xin, T *xout, const T *din, T *dout, T c1, T c2, const Scal *sc)
+{
+    Level &L = c->lv[l];
+    const double per = sizeof(TB) + op_bytes<T>(c, l) + sizeof(T) * (2 + (din ? 1 : 0) + (dout ? 1 : 0));
+    TScope ts(c, l == 0 ? SPFD_K_SMOOTH0 : SPFD_K_COARSE, (double)L.dofs * per);
+    HIPCHK(launch_cheb_step<T, TB>(level_op<T>(c, l), L.topo(), b, xin, xout, din, dout, c1, c2, sc, c->stream));
+}
+
+template <typename T, typename TB>
+void smooth_pre(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc)
+{
     const int m = c->opt.smooth_degree;
-    T *d = (T *)L.d;
-    if (b_is_fp64) {
-        const double *b = (const double *)bvoid;
-        HIPCHK(launch_cheb_first<T, double>(op, L.topo(), b, cur, (T)c->cheb_c0, sc, c->stream));
-        for (int k = 1; k < m; ++k) {
-            HIPCHK(launch_cheb_step<T, double>(op, L.topo(), b, cur, other, k == 1 ? nullptr : d, k < m - 1 ? d : nullptr,
-                                               (T)c->cheb_c1[k], (T)c->cheb_c2[k], sc, c->stream));
-            T *t = cur; cur = other; other = t;
-        }
-    } else {
-        const T *b = (const T *)bvoid;
-        HIPCHK(launch_cheb_first<T, T>(op, L.topo(), b, cur, (T)c->cheb_c0, sc, c->stream));
-        for (int k = 1; k < m; ++k) {
-            HIPCHK(launch_cheb_step<T, T>(op, L.topo(), b, cur, other, k == 1 ? nullptr : d, k < m - 1 ? d : nullptr,
-                                          (T)c->cheb_c1[k], (T)c->cheb_c2[k], sc, c->stream));
-            T *t = cur; cur = other; other = t;
-        }
+    T *d = (T *)c->lv[l].d;
+    cheb_first<T, TB>(c, l, b, cur, sc);
+    for (int k = 1; k < m; ++k) {
+        cheb_step<T, TB>(c, l, b, cur, other, k == 1 ? nullptr : d, k < m - 1 ? d : nullptr, (T)c->cheb_c1[k],
+                         (T)c->cheb_c2[k], sc);
+        T *t = cur; cur = other; other = t;
     }
 }
 
-template <typename T>
-void smooth_post(Ctx *c, int l, const void *bvoid, bool b_is_fp64, T *&cur, T *&other, const Scal *sc)
+template <typename T, typename TB>
+void smooth_post(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc)
 {
-    Level &L = c->lv[l];
-    const OpArgs<T> op = level_op<T>(c, l);
     const int m = c->opt.smooth_degree;
-    T *d = (T *)L.d;
+    T *d = (T *)c->lv[l].d;
     for (int k = 0; k < m; ++k) {
         const T c1 = k == 0 ? T(0) : (T)c->cheb_c1[k];
         const T c2 = k == 0 ? (T)c->cheb_c0 : (T)c->cheb_c2[k];
-        T *din = k == 0 ? nullptr : d;
-        T *dout = k < m - 1 ? d : nullptr;
-        if (b_is_fp64)
-            HIPCHK(launch_cheb_step<T, double>(op, L.topo(), (const double *)bvoid, cur, other, din, dout, c1, c2, sc, c->stream));
-        else
-            HIPCHK(launch_cheb_step<T, T>(op, L.topo(), (const T *)bvoid, cur, other, din, dout, c1, c2, sc, c->stream));
+        cheb_step<T, TB>(c, l, b, cur, other, k == 0 ? nullptr : d, k < m - 1 ? d : nullptr, c1, c2, sc);
         T *t = cur; cur = other; other = t;
     }
+}
+
+template <typename T, typename TB>
+void restrict_level(Ctx *c, int l, const TB *b, const T *x, const Scal *sc)
+{
+    Level &L = c->lv[l];
+    Level &C = c->lv[l + 1];
+    const double by = (double)L.dofs * (sizeof(TB) + op_bytes<T>(c, l) + sizeof(T)) + (double)C.dofs * sizeof(T);
+    TScope ts(c, l == 0 ? SPFD_K_RESTRICT0 : SPFD_K_COARSE, by);
+    HIPCHK(launch_resid_restrict<T, TB>(level_op<T>(c, l), L.topo(), b, x, (T *)C.b, L.d_parent_slot, L.d_coord, sc,
+                                        c->stream));
+}
+
+template <typename T>
+void prolong_level(Ctx *c, int l, T *x, const Scal *sc)
+{
+    Level &L = c->lv[l];
+    Level &C = c->lv[l + 1];
+    const double by = (double)L.dofs * 2.0 * sizeof(T) + (double)C.dofs * sizeof(T);
+    TScope ts(c, l == 0 ? SPFD_K_PROLONG0 : SPFD_K_COARSE, by);
+    HIPCHK(launch_prolong<T>(L.topo(), x, (const T *)C.x, L.d_parent_slot, L.d_coord, (T)c->opt.coarse_scale, sc,
+                             c->stream));
+}
+
+template <typename T, typename TB>
+void coarse_solve(Ctx *c, const TB *b, T *x, const Scal *sc)
+{
+    const double n = (double)c->ncoarse;
+    TScope ts(c, SPFD_K_COARSE, n * n * 8.0 + n * (sizeof(TB) + sizeof(T)));
+    HIPCHK(launch_coarse_apply<T, TB>(b, x, c->d_Ainv, c->d_cdof_node, c->ncoarse, sc, c->stream));
 }
 
 // z = B r: one V-cycle (T = arithmetic of the cycle); r is the FP64 outer residual
@@ -295,45 +412,48 @@ void vcycle(Ctx *c, const double *r, T *z, const Scal *sc)
     const int nl = (int)c->lv.size();
     std::vector<T *> res(nl, nullptr);
     if (nl == 1) {
-        // single level: the dense solve is exact
-        HIPCHK(launch_coarse_apply<T, double>(r, z, c->d_Ainv, c->d_cdof_node, c->ncoarse, sc, c->stream));
+        coarse_solve<T, double>(c, r, z, sc);  // single level: the dense solve is exact
         return;
     }
-    // downward: pre-smooth, restrict the residual
+    // downward: pre-smooth, restrict the residual.  The smoother ping-pongs
+    // between two buffers; starting in x2 makes the (2m-1) swaps of a level end
+    // in the level's output buffer (z on the finest level, x below).
     for (int l = 0; l < nl - 1; ++l) {
         Level &L = c->lv[l];
         T *cur = (T *)L.x2;
         T *other = l == 0 ? z : (T *)L.x;
-        const void *b = l == 0 ? (const void *)r : L.b;
-        smooth_pre<T>(c, l, b, l == 0, cur, other, sc);
+        if (l == 0) {
+            smooth_pre<T, double>(c, l, r, cur, other, sc);
+            restrict_level<T, double>(c, l, r, cur, sc);
+        } else {
+            smooth_pre<T, T>(c, l, (const T *)L.b, cur, other, sc);
+            restrict_level<T, T>(c, l, (const T *)L.b, cur, sc);
+        }
         res[l] = cur;
-        const OpArgs<T> op = level_op<T>(c, l);
-        Level &C = c->lv[l + 1];
-        if (l == 0)
-            HIPCHK(launch_resid_restrict<T, double>(op, L.topo(), r, cur, (T *)C.b, L.d_parent_slot, L.d_coord, sc, c->stream));
-        else
-            HIPCHK(launch_resid_restrict<T, T>(op, L.topo(), (const T *)L.b, cur, (T *)C.b, L.d_parent_slot, L.d_coord, sc,
-                                               c->stream));
     }
-    // coarsest
     {
         Level &C = c->lv[nl - 1];
-        HIPCHK(launch_coarse_apply<T, T>((const T *)C.b, (T *)C.x, c->d_Ainv, c->d_cdof_node, c->ncoarse, sc, c->stream));
+        coarse_solve<T, T>(c, (const T *)C.b, (T *)C.x, sc);
     }
     // upward: prolongate and correct, post-smooth
     for (int l = nl - 2; l >= 0; --l) {
         Level &L = c->lv[l];
-        Level &C = c->lv[l + 1];
         T *cur = res[l];
         T *other = (cur == (T *)L.x2) ? (l == 0 ? z : (T *)L.x) : (T *)L.x2;
-        HIPCHK(launch_prolong<T>(L.topo(), cur, (const T *)C.x, L.d_parent_slot, L.d_coord, (T)c->opt.coarse_scale, sc,
-                                 c->stream));
-        const void *b = l == 0 ? (const void *)r : L.b;
-        smooth_post<T>(c, l, b, l == 0, cur, other, sc);
-        // the result must end in the level's output buffer
+        prolong_level<T>(c, l, cur, sc);
+        if (l == 0)
+            smooth_post<T, double>(c, l, r, cur, other, sc);
+        else
+            smooth_post<T, T>(c, l, (const T *)L.b, cur, other, sc);
         T *want = l == 0 ? z : (T *)L.x;
         if (cur != want) HIPCHK(hipMemcpyAsync(want, cur, L.nodes() * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
     }
+}
+
+void finish(Ctx *c, int n, int mode, Scal *sc, int max_iter)
+{
+    TScope ts(c, SPFD_K_FINISH, (double)n * 8.0 * (mode == FIN_BETA ? 2 : 1));
+    HIPCHK(launch_finish(c->d_part, n, mode, sc, max_iter, c->stream));
 }
 
 void set_defaults(spfd_amg_options &o)
@@ -342,10 +462,10 @@ void set_defaults(spfd_amg_options &o)
     if (o.cycle != SPFD_CYCLE_K) o.cycle = SPFD_CYCLE_V;
     if (o.smooth_degree <= 0) o.smooth_degree = 2;
     if (o.smooth_degree > 4) o.smooth_degree = 4;
-    if (o.coarsest_max <= 0) o.coarsest_max = 400;
+    if (o.coarsest_max <= 0) o.coarsest_max = 1024;
     if (o.coarsest_max > 1024) o.coarsest_max = 1024;
     if (!(o.cheby_ratio > 1.0)) o.cheby_ratio = 8.0;
-    if (!(o.coarse_scale > 0.0)) o.coarse_scale = 1.0;
+    if (!(o.coarse_scale > 0.0)) o.coarse_scale = 1.8;
 }
 
 void chebyshev_coefficients(Ctx *c)
@@ -522,30 +642,64 @@ spfd_status do_set_num_rhs(Ctx *c, int nrhs)
 }
 
 template <typename T>
-void pcg_iterations(Ctx *c, int rhs, const spfd_solve_options &so, bool first_pass)
+void pcg_iterations(Ctx *c, int rhs, const spfd_solve_options &so)
 {
     Level &L0 = c->lv[0];
     const Topo topo = L0.topo();
     const OpArgs<double> op = level_op<double>(c, 0);
     Scal *sc = c->d_scal + rhs;
     T *z = (T *)c->d_z;
-    (void)first_pass;
+    const double n0 = (double)L0.dofs;
+    const double wz = sizeof(T);
     vcycle<T>(c, c->d_r, z, sc);
-    HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 1, c->stream));
-    HIPCHK(launch_pupdate<T>(topo, z, c->d_p, sc, 1, c->stream));
+    {
+        TScope ts(c, SPFD_K_DOTS, n0 * (wz + 8.0));
+        HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 1, c->stream));
+    }
+    finish(c, topo.nb, FIN_BETA0, sc, 0);
+    {
+        TScope ts(c, SPFD_K_PUPDATE, n0 * (wz + 8.0));
+        HIPCHK(launch_pupdate<T>(topo, z, c->d_p, sc, 1, c->stream));
+    }
     const int chunk = 1;
     for (int it = 0; it < so.max_iter + 1; it += chunk) {
         for (int k = 0; k < chunk; ++k) {
-            HIPCHK(launch_spmv_dot(op, topo, c->d_p, c->d_q, c->d_part, sc, c->stream));
-            HIPCHK(launch_update(topo, c->d_x, c->d_r, c->d_p, c->d_q, c->d_part, sc, so.max_iter, c->stream));
+            {
+                TScope ts(c, SPFD_K_SPMV, n0 * (16.0 + op_bytes<double>(c, 0)));
+                HIPCHK(launch_spmv_dot(op, topo, c->d_p, c->d_q, c->d_part, sc, c->stream));
+            }
+            finish(c, topo.nb, FIN_ALPHA, sc, 0);
+            {
+                TScope ts(c, SPFD_K_UPDATE, n0 * 48.0);
+                HIPCHK(launch_update(topo, c->d_x, c->d_r, c->d_p, c->d_q, c->d_part, sc, so.max_iter, c->stream));
+            }
+            finish(c, topo.nb, FIN_RR, sc, so.max_iter);
             vcycle<T>(c, c->d_r, z, sc);
-            HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 0, c->stream));
-            HIPCHK(launch_pupdate<T>(topo, z, c->d_p, sc, 0, c->stream));
+            {
+                TScope ts(c, SPFD_K_DOTS, n0 * (wz + 16.0));
+                HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 0, c->stream));
+            }
+            finish(c, topo.nb, FIN_BETA, sc, 0);
+            {
+                TScope ts(c, SPFD_K_PUPDATE, n0 * (wz + 16.0));
+                HIPCHK(launch_pupdate<T>(topo, z, c->d_p, sc, 0, c->stream));
+            }
         }
         HIPCHK(hipMemcpyAsync(c->h_scal + rhs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         if (c->h_scal[rhs].done) break;
     }
+}
+
+void resid(Ctx *c, int rhs, double *r, int mode)
+{
+    Level &L0 = c->lv[0];
+    {
+        TScope ts(c, SPFD_K_SPMV, (double)L0.dofs * (16.0 + (r ? 8.0 : 0.0) + op_bytes<double>(c, 0)));
+        HIPCHK(launch_resid(level_op<double>(c, 0), L0.topo(), c->d_b[rhs], c->d_x, r, c->d_part, c->d_scal + rhs, mode,
+                            c->stream));
+    }
+    finish(c, L0.nb, mode == 0 ? FIN_RESID0 : FIN_RESID1, c->d_scal + rhs, 0);
 }
 
 __global__ void k_rearm(Scal *sc, double tol2, int keep_iters)
@@ -562,7 +716,6 @@ spfd_status do_solve(Ctx *c, const spfd_solve_options &so, double *psi, spfd_rhs
 {
     Level &L0 = c->lv[0];
     const Topo topo = L0.topo();
-    const OpArgs<double> op = level_op<double>(c, 0);
     const long long n0 = L0.nodes();
     const bool mixed = c->opt.precision == SPFD_MIXED;
     const long long nn = (long long)c->g.Nx * c->g.Ny * c->g.Nz;
@@ -574,7 +727,7 @@ spfd_status do_solve(Ctx *c, const spfd_solve_options &so, double *psi, spfd_rhs
         HIPCHK(launch_scal_init(sc, so.rel_tol, so.use_x0, c->stream));
         if (so.use_x0) {
             HIPCHK(launch_psi_in(psi_r, c->d_comp, L0.d_coord, L0.nb, c->g, c->d_x, c->stream));
-            HIPCHK(launch_resid(op, topo, c->d_b[rhs], c->d_x, c->d_r, c->d_part, sc, 0, c->stream));
+            resid(c, rhs, c->d_r, 0);
         } else {
             HIPCHK(hipMemsetAsync(c->d_x, 0, n0 * sizeof(double), c->stream));
             HIPCHK(hipMemcpyAsync(c->d_r, c->d_b[rhs], n0 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -587,11 +740,11 @@ spfd_status do_solve(Ctx *c, const spfd_solve_options &so, double *psi, spfd_rhs
         if (bb > 0.0 && !c->h_scal[rhs].done) {
             for (int pass = 0; pass < 3; ++pass) {
                 if (mixed)
-                    pcg_iterations<float>(c, rhs, so, pass == 0);
+                    pcg_iterations<float>(c, rhs, so);
                 else
-                    pcg_iterations<double>(c, rhs, so, pass == 0);
+                    pcg_iterations<double>(c, rhs, so);
                 // true residual of the iterate
-                HIPCHK(launch_resid(op, topo, c->d_b[rhs], c->d_x, c->d_r, c->d_part, sc, 1, c->stream));
+                resid(c, rhs, c->d_r, 1);
                 HIPCHK(hipMemcpyAsync(c->h_scal + rhs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
                 HIPCHK(hipStreamSynchronize(c->stream));
                 const Scal &hs = c->h_scal[rhs];
@@ -606,14 +759,17 @@ spfd_status do_solve(Ctx *c, const spfd_solve_options &so, double *psi, spfd_rhs
             if (status == 0 && relres > so.rel_tol) status = SPFD_NOT_CONVERGED;
         } else if (bb > 0.0) {
             // the start iterate already satisfies the criterion
-            HIPCHK(launch_resid(op, topo, c->d_b[rhs], c->d_x, nullptr, c->d_part, sc, 1, c->stream));
+            resid(c, rhs, nullptr, 1);
             HIPCHK(hipMemcpyAsync(c->h_scal + rhs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
             relres = sqrt(c->h_scal[rhs].zq / bb);
         }
         // gauge: zero mean per connected component, 0 outside the conductor
-        HIPCHK(launch_comp_mean(topo, c->d_x, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_part, c->stream));
-        HIPCHK(launch_psi_out(c->d_x, c->d_comp, c->d_means, L0.d_slot_of, c->g, psi_r, c->stream));
+        {
+            TScope ts(c, SPFD_K_GAUGE, (double)L0.dofs * (12.0 * (c->ncomp < 16 ? c->ncomp : 1) + 12.0) + nn * 8.0);
+            HIPCHK(launch_comp_mean(topo, c->d_x, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_part, c->stream));
+            HIPCHK(launch_psi_out(c->d_x, c->d_comp, c->d_means, L0.d_slot_of, c->g, psi_r, c->stream));
+        }
         HIPCHK(hipStreamSynchronize(c->stream));
         if (info) {
             info[rhs].iterations = iters;
@@ -678,11 +834,11 @@ void spfd_destroy(spfd_handle h)
     if (!h) return;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
-    free_all(h, h->rhs_allocs);
-    free_all(h, h->hier_allocs);
-    free_all(h, h->geo_allocs);
+    release_device(h);
     if (h->h_scal) (void)hipHostFree(h->h_scal);
     if (h->h_ints) (void)hipHostFree(h->h_ints);
+    for (int k = 0; k < SPFD_K_COUNT; ++k)
+        for (hipEvent_t e : h->tev[k]) (void)hipEventDestroy(e);
     delete h;
 }
 
@@ -703,9 +859,7 @@ spfd_status spfd_set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, 
         HIPCHK(hipStreamSynchronize(h->stream));
         free_all(h, h->rhs_allocs);
         free_all(h, h->hier_allocs);
-        for (void *p : h->geo_allocs) (void)hipFree(p);
-        h->geo_allocs.clear();
-        h->bytes = 0;
+        free_all(h, h->geo_allocs);
         h->d_ints = dalloc<int>(h, h->geo_allocs, 64);
         h->lv.clear();
         h->g.nx = nx; h->g.ny = ny; h->g.nz = nz;
@@ -828,8 +982,12 @@ spfd_status spfd_set_source(spfd_handle h, int rhs, const double *a)
         HIPCHK(hipSetDevice(h->device));
         Level &L0 = h->lv[0];
         HIPCHK(hipMemsetAsync(h->d_scal + rhs, 0, sizeof(Scal), h->stream));
-        HIPCHK(launch_rhs(level_op<double>(h, 0), L0.topo(), L0.d_coord, h->g, a, h->d_b[rhs], h->d_part,
-                          h->d_scal + rhs, h->stream));
+        {
+            TScope ts(h, SPFD_K_RHS, (double)L0.dofs * (24.0 + 8.0 + op_bytes<double>(h, 0)));
+            HIPCHK(launch_rhs(level_op<double>(h, 0), L0.topo(), L0.d_coord, h->g, a, h->d_b[rhs], h->d_part,
+                              h->d_scal + rhs, h->stream));
+        }
+        finish(h, L0.nb, FIN_BB, h->d_scal + rhs, 0);
         HIPCHK(hipMemcpyAsync(h->h_scal + rhs, h->d_scal + rhs, sizeof(Scal), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         if (!isfinite(h->h_scal[rhs].bb)) return fail(h, SPFD_INVALID_ARG, "source potentials must be finite");
@@ -869,9 +1027,58 @@ spfd_status spfd_efield(spfd_handle h, double omega, const double *a, const doub
     try {
         HIPCHK(hipSetDevice(h->device));
         const double *sv = h->voxel_mode ? h->d_sigvox : nullptr;
-        HIPCHK(launch_efield(h->d_labels, h->d_table64, sv, h->g, h->h, omega, a, psi, emag, h->stream));
-        if (u_edges) HIPCHK(launch_uedges(h->d_labels, h->d_table64, sv, h->g, a, psi, u_edges, h->stream));
+        const double nvox = (double)h->g.nx * h->g.ny * h->g.nz;
+        const double body = h->state >= 3 ? (double)h->lv[0].dofs : nvox;
+        {
+            // labels of all voxels, |E| of all voxels; psi (8 corners) and a (12 edges) counted once per body node
+            TScope ts(h, SPFD_K_EFIELD, nvox * (1.0 + 8.0) + body * (8.0 + 24.0));
+            HIPCHK(launch_efield(h->d_labels, h->d_table64, sv, h->g, h->h, omega, a, psi, emag, h->stream));
+        }
+        if (u_edges) {
+            const double nn = (double)h->g.Nx * h->g.Ny * h->g.Nz;
+            TScope ts(h, SPFD_K_EFIELD, nvox * 1.0 + nn * 24.0 + body * (8.0 + 24.0));
+            HIPCHK(launch_uedges(h->d_labels, h->d_table64, sv, h->g, a, psi, u_edges, h->stream));
+        }
         HIPCHK(hipStreamSynchronize(h->stream));
+        return SPFD_OK;
+    }
+    API_GUARD(h)
+}
+
+spfd_status spfd_timing(spfd_handle h, unsigned int class_mask)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->tmask = class_mask;
+        for (int k = 0; k < SPFD_K_COUNT; ++k) {
+            h->tused[k] = 0;
+            h->tlaunch[k] = 0;
+            h->tbytes[k] = 0.0;
+        }
+        return SPFD_OK;
+    }
+    API_GUARD(h)
+}
+
+spfd_status spfd_timing_get(spfd_handle h, int kclass, long long *launches, double *total_ms, double *algorithmic_bytes)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (kclass < 0 || kclass >= SPFD_K_COUNT) return fail(h, SPFD_INVALID_ARG, "unknown kernel class");
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        double ms = 0.0;
+        const std::vector<hipEvent_t> &v = h->tev[kclass];
+        for (size_t i = 0; i + 1 < h->tused[kclass]; i += 2) {
+            float e = 0.0f;
+            HIPCHK(hipEventElapsedTime(&e, v[i], v[i + 1]));
+            ms += e;
+        }
+        if (launches) *launches = h->tlaunch[kclass];
+        if (total_ms) *total_ms = ms;
+        if (algorithmic_bytes) *algorithmic_bytes = h->tbytes[kclass];
         return SPFD_OK;
     }
     API_GUARD(h)

@@ -44,6 +44,22 @@ hipError_t launch_coarse_factor(const double *w64, long long stride, Topo topo, 
                                 const int *node_of_dof, int *adj, int n, double *A, int *work, hipStream_t s);
 
 // ---------------------------------------------------------------- solve
+// Reductions are two-stage: a producer kernel stores one partial per brick
+// workgroup, then launch_finish (one workgroup) sums them in a fixed order and
+// updates the solve's scalars according to `mode`.
+enum {
+    FIN_BB = 0,       // ||b||^2 of a new right side
+    FIN_ALPHA = 1,    // alpha = r.z / p.q
+    FIN_RR = 2,       // ||r||^2, iteration count and stop test
+    FIN_BETA0 = 3,    // r.z of the first preconditioned residual
+    FIN_BETA = 4,     // flexible beta = -alpha z.q / (r.z)_old (partials of z.q follow those of r.z)
+    FIN_RESID0 = 5,   // ||b - A x0||^2 at the start of a warm-started solve
+    FIN_RESID1 = 6,   // true ||b - A x||^2 at the end of a solve (kept in zq)
+    FIN_MEAN = 7      // mean of one component
+};
+hipError_t launch_finish(const double *part, int n, int mode, Scal *sc, int max_iter, hipStream_t s,
+                         double *means = nullptr, const int *counts = nullptr, int comp = 0);
+
 template <typename T>
 hipError_t launch_fill(T *x, long long n, T v, hipStream_t s);
 

@@ -13,53 +13,39 @@ namespace spfd {
 // shared per-workgroup operator state
 // ============================================================================
 
-// LDS for a brick workgroup: neighbour slots, and for the label operator the
-// sigma table and the 9x9x9 conductivity tile of the brick's voxels.
+// Label-form operator, phase 1: stage the brick's 9x9x9 conductivity tile in
+// LDS (two voxels per thread; the sigma table has 256 entries, zero beyond the
+// labels in use, and is read through the cache).  A barrier must follow.
 template <typename T>
-struct BrickLds {
-    int nb[6];
-    int flag;
-    double red[8];
-    T tab[MAX_LABELS];
-    T tile[TILE_VOX + 7];
-};
-
-template <typename T>
-__device__ __forceinline__ void load_nbr(const Topo &topo, int b, BrickLds<T> &L)
+__device__ __forceinline__ void stage_tile(const OpArgs<T> &op, int b, T *tile)
 {
-    if (threadIdx.x < 6) L.nb[threadIdx.x] = topo.nbr[b * 6 + threadIdx.x];
-}
-
-template <typename T>
-__device__ __forceinline__ void load_tile(const OpArgs<T> &op, int b, BrickLds<T> &L)
-{
-    for (int i = threadIdx.x; i < op.nlab; i += blockDim.x) L.tab[i] = op.table[i];
-    __syncthreads();
     const uint8_t *tl = op.tiles + (long long)b * TILE_BYTES;
-    for (int i = threadIdx.x; i < TILE_VOX; i += blockDim.x) {
-        const int lab = tl[i];
-        L.tile[i] = lab < op.nlab ? L.tab[lab] : T(0);
-    }
+    const int i0 = threadIdx.x, i1 = threadIdx.x + NT;
+    const int l0 = tl[i0];
+    const int l1 = i1 < TILE_VOX ? tl[i1] : 0;
+    const T s0 = op.table[l0], s1 = op.table[l1];
+    tile[i0] = s0;
+    if (i1 < TILE_VOX) tile[i1] = s1;
 }
 
-// weights of node t of brick b (after load_nbr/load_tile and a barrier)
+// weights of node t (after stage_tile and a barrier for the label form)
 template <typename T>
-__device__ __forceinline__ void op_weights(const OpArgs<T> &op, const BrickLds<T> &L, long long base, int t, int tx,
-                                           int ty, int tz, T W[6])
+__device__ __forceinline__ void op_weights(const OpArgs<T> &op, const T *tile, long long base, int t, int tx, int ty,
+                                           int tz, const long long I[6], T W[6])
 {
-    if (op.w) {
-        stored_weights(op.w, op.stride, base, t, tx, ty, tz, L.nb, W);
-    } else {
-        tile_weights(L.tile, tx, ty, tz, op.geo4, W);
-    }
+    if (op.w)
+        stored_weights(op.w, op.stride, base, t, I, W);
+    else
+        tile_weights(tile, tx, ty, tz, op.geo4, W);
 }
 
 template <typename T>
-__device__ __forceinline__ void op_prepare(const OpArgs<T> &op, const Topo &topo, int b, BrickLds<T> &L)
+__device__ __forceinline__ void op_stage(const OpArgs<T> &op, int b, T *tile)
 {
-    load_nbr(topo, b, L);
-    if (!op.w) load_tile(op, b, L);
-    __syncthreads();
+    if (!op.w) {
+        stage_tile(op, b, tile);
+        __syncthreads();
+    }
 }
 
 // ============================================================================
@@ -270,15 +256,16 @@ __device__ __forceinline__ void punite(int *p, int a, int b)
 
 __global__ void k_cc_init(const double *__restrict__ w, long long stride, Topo topo, int *parent)
 {
-    __shared__ BrickLds<double> L;
     const int b = blockIdx.x, t = threadIdx.x;
-    load_nbr(topo, b, L);
-    __syncthreads();
+    int nb[6];
+    brick_nbrs(topo.nbr, b, nb);
     int tx, ty, tz;
     brick_xyz(t, tx, ty, tz);
     double W[6];
     const long long base = (long long)b * BS;
-    stored_weights(w, stride, base, t, tx, ty, tz, L.nb, W);
+    long long I[6];
+    nbr_index(base, t, tx, ty, tz, nb, I);
+    stored_weights(w, stride, base, t, I, W);
     parent[base + t] = diag_of(W) > 0.0 ? (int)(base + t) : -1;
 }
 
@@ -471,7 +458,9 @@ __global__ void k_coarse_enum(const double *__restrict__ w, long long stride, To
             int tx, ty, tz;
             brick_xyz(tt, tx, ty, tz);
             double W[6];
-            stored_weights(w, stride, (long long)b * BS, tt, tx, ty, tz, topo.nbr + b * 6, W);
+            long long I[6];
+            nbr_index((long long)b * BS, tt, tx, ty, tz, topo.nbr + b * 6, I);
+            stored_weights(w, stride, (long long)b * BS, tt, I, W);
             isdof = diag_of(W) > 0.0;
         }
         s[t] = isdof;
@@ -509,7 +498,9 @@ __global__ void k_coarse_enum(const double *__restrict__ w, long long stride, To
         m[NMZ] = tz > 0 ? i - 64 : (nb[NMZ] >= 0 ? nb[NMZ] * BS + tt + 448 : -1);
         m[NPZ] = tz < 7 ? i + 64 : (nb[NPZ] >= 0 ? nb[NPZ] * BS + tt - 448 : -1);
         double W[6];
-        stored_weights(w, stride, (long long)b * BS, tt, tx, ty, tz, nb, W);
+        long long I[6];
+        nbr_index((long long)b * BS, tt, tx, ty, tz, nb, I);
+        stored_weights(w, stride, (long long)b * BS, tt, I, W);
         for (int k = 0; k < 6; ++k) adj[q * 6 + k] = (m[k] >= 0 && W[k] > 0.0) ? dof_of_node[m[k]] : -1;
     }
 }
@@ -546,7 +537,9 @@ __global__ void k_coarse_factor(const double *__restrict__ w, long long stride, 
         int tx, ty, tz;
         brick_xyz(tt, tx, ty, tz);
         double W[6];
-        stored_weights(w, stride, (long long)b * BS, tt, tx, ty, tz, topo.nbr + b * 6, W);
+        long long I[6];
+        nbr_index((long long)b * BS, tt, tx, ty, tz, topo.nbr + b * 6, I);
+        stored_weights(w, stride, (long long)b * BS, tt, I, W);
         double d = 0.0;
         for (int k = 0; k < 6; ++k) {
             const int m = adj[q * 6 + k];
@@ -676,16 +669,6 @@ hipError_t launch_scal_init(Scal *sc, double tol, int use_x0, hipStream_t s)
 // its partial sum with a plain store, and after the kernel boundary one
 // workgroup (k_finish) sums the partials in a fixed order and updates the
 // scalars of the solve.  No grid-wide fence is needed inside a kernel.
-enum {
-    FIN_BB = 0,       // ||b||^2 of a new right side
-    FIN_ALPHA = 1,    // alpha = r.z / p.q
-    FIN_RR = 2,       // ||r||^2, iteration count and stop test
-    FIN_BETA0 = 3,    // r.z of the first preconditioned residual
-    FIN_BETA = 4,     // flexible beta = -alpha z.q / (r.z)_old
-    FIN_RESID0 = 5,   // ||b - A x0||^2 at the start of a warm-started solve
-    FIN_RESID1 = 6,   // true ||b - A x||^2 at the end of a solve (kept in zq)
-    FIN_MEAN = 7      // mean of a component
-};
 
 __device__ __forceinline__ double block_sum_any(double v, double *lds)
 {
@@ -771,8 +754,8 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
     }
 }
 
-static hipError_t finish(const double *part, int n, int mode, Scal *sc, int max_iter, hipStream_t s,
-                         double *means = nullptr, const int *counts = nullptr, int comp = 0)
+hipError_t launch_finish(const double *part, int n, int mode, Scal *sc, int max_iter, hipStream_t s, double *means,
+                         const int *counts, int comp)
 {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, part, n, mode, sc, max_iter, means, counts, comp);
     return hipGetLastError();
@@ -785,16 +768,21 @@ template <bool LABEL>
 __global__ __launch_bounds__(NT) void k_rhs(OpArgs<double> op, Topo topo, const int4 *__restrict__ coord, Grid g,
                                             const double *__restrict__ a, double *b, double *part)
 {
-    __shared__ BrickLds<double> L;
+    __shared__ double tile[TILE_VOX + 7];
+    __shared__ double red[8];
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
-    op_prepare(op, topo, bk, L);
+    int nb[6];
+    brick_nbrs(topo.nbr, bk, nb);
     const int t = threadIdx.x;
     int tx, ty, tz;
     brick_xyz(t, tx, ty, tz);
     const long long base = (long long)bk * BS;
+    long long I[6];
+    nbr_index(base, t, tx, ty, tz, nb, I);
+    op_stage(op, bk, tile);
     double W[6];
-    op_weights(op, L, base, t, tx, ty, tz, W);
+    op_weights(op, tile, base, t, tx, ty, tz, I, W);
     const int4 c = coord[bk];
     const long long i = c.x * 8 + tx, j = c.y * 8 + ty, k = c.z * 8 + tz;
     const long long n = i + (long long)g.Nx * (j + (long long)g.Ny * k);
@@ -807,7 +795,7 @@ __global__ __launch_bounds__(NT) void k_rhs(OpArgs<double> op, Topo topo, const 
     if (W[NPZ] != 0.0) s += W[NPZ] * a[2 * nn + n];
     if (W[NMZ] != 0.0) s -= W[NMZ] * a[2 * nn + n - (long long)g.Nx * g.Ny];
     b[base + t] = s;
-    const double tot = block_sum(s * s, L.red);
+    const double tot = block_sum(s * s, red);
     if (t == 0) part[bk] = tot;
 }
 
@@ -819,31 +807,35 @@ hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, co
         hipLaunchKernelGGL(k_rhs<false>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, coord, g, a, b, part);
     else
         hipLaunchKernelGGL(k_rhs<true>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, coord, g, a, b, part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return finish(part, topo.nb, FIN_BB, sc, 0, s);
+    return hipGetLastError();
 }
 
 // q = A p and the partials of p.q (alpha follows in k_finish)
 __global__ __launch_bounds__(NT) void k_spmv_dot(OpArgs<double> op, Topo topo, const double *__restrict__ p,
                                                  double *__restrict__ q, double *part, const Scal *sc)
 {
-    __shared__ BrickLds<double> L;
+    __shared__ double tile[TILE_VOX + 7];
+    __shared__ double red[8];
     if (sc->done) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
-    op_prepare(op, topo, bk, L);
+    int nb[6];
+    brick_nbrs(topo.nbr, bk, nb);
     const int t = threadIdx.x;
     int tx, ty, tz;
     brick_xyz(t, tx, ty, tz);
     const long long base = (long long)bk * BS;
-    double W[6], X[6];
-    op_weights(op, L, base, t, tx, ty, tz, W);
-    nbr_vals(p, base, t, tx, ty, tz, L.nb, X);
+    long long I[6];
+    nbr_index(base, t, tx, ty, tz, nb, I);
+    double X[6];
+    nbr_vals(p, I, X);
     const double p0 = p[base + t];
+    op_stage(op, bk, tile);
+    double W[6];
+    op_weights(op, tile, base, t, tx, ty, tz, I, W);
     const double y = stencil_apply(p0, X, W);
     q[base + t] = y;
-    const double tot = block_sum(p0 * y, L.red);
+    const double tot = block_sum(p0 * y, red);
     if (t == 0) part[bk] = tot;
 }
 
@@ -852,9 +844,7 @@ hipError_t launch_spmv_dot(const OpArgs<double> &op, Topo topo, const double *p,
 {
     if (topo.nb <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_spmv_dot, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, p, q, part, sc);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return finish(part, topo.nb, FIN_ALPHA, sc, 0, s);
+    return hipGetLastError();
 }
 
 // x += alpha p, r -= alpha q and the partials of ||r||^2 (stop test in k_finish)
@@ -880,9 +870,7 @@ hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const
 {
     if (topo.nb <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_update, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, r, p, q, part, sc);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return finish(part, topo.nb, FIN_RR, sc, max_iter, s);
+    return hipGetLastError();
 }
 
 // r = b - A x (r may be null) and the partials of ||r||^2.  mode 0: start of a
@@ -890,20 +878,27 @@ hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const
 __global__ __launch_bounds__(NT) void k_resid(OpArgs<double> op, Topo topo, const double *__restrict__ b,
                                               const double *__restrict__ x, double *__restrict__ r, double *part)
 {
-    __shared__ BrickLds<double> L;
+    __shared__ double tile[TILE_VOX + 7];
+    __shared__ double red[8];
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
-    op_prepare(op, topo, bk, L);
+    int nb[6];
+    brick_nbrs(topo.nbr, bk, nb);
     const int t = threadIdx.x;
     int tx, ty, tz;
     brick_xyz(t, tx, ty, tz);
     const long long base = (long long)bk * BS;
-    double W[6], X[6];
-    op_weights(op, L, base, t, tx, ty, tz, W);
-    nbr_vals(x, base, t, tx, ty, tz, L.nb, X);
-    const double rv = b[base + t] - stencil_apply(x[base + t], X, W);
+    long long I[6];
+    nbr_index(base, t, tx, ty, tz, nb, I);
+    double X[6];
+    nbr_vals(x, I, X);
+    const double x0 = x[base + t], bv = b[base + t];
+    op_stage(op, bk, tile);
+    double W[6];
+    op_weights(op, tile, base, t, tx, ty, tz, I, W);
+    const double rv = bv - stencil_apply(x0, X, W);
     if (r) r[base + t] = rv;
-    const double tot = block_sum(rv * rv, L.red);
+    const double tot = block_sum(rv * rv, red);
     if (t == 0) part[bk] = tot;
 }
 
@@ -912,9 +907,7 @@ hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, co
 {
     if (topo.nb <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_resid, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, b, x, r, part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return finish(part, topo.nb, mode == 0 ? FIN_RESID0 : FIN_RESID1, sc, 0, s);
+    return hipGetLastError();
 }
 
 // partials of r.z and z.q (flexible beta follows in k_finish)
@@ -942,9 +935,7 @@ hipError_t launch_dots(Topo topo, const TZ *z, const double *r, const double *q,
 {
     if (topo.nb <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_dots<TZ>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, z, r, q, part, sc, first);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return finish(part, topo.nb, first ? FIN_BETA0 : FIN_BETA, sc, 0, s);
+    return hipGetLastError();
 }
 template hipError_t launch_dots<double>(Topo, const double *, const double *, const double *, double *, Scal *, int,
                                         hipStream_t);
@@ -984,19 +975,24 @@ template <typename T, typename TB>
 __global__ __launch_bounds__(NT) void k_cheb_first(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
                                                    T *__restrict__ x, T c0, const Scal *sc)
 {
-    __shared__ BrickLds<T> L;
+    __shared__ T tile[TILE_VOX + 7];
     if (stopped(sc)) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
-    op_prepare(op, topo, bk, L);
+    int nb[6];
+    brick_nbrs(topo.nbr, bk, nb);
     const int t = threadIdx.x;
     int tx, ty, tz;
     brick_xyz(t, tx, ty, tz);
     const long long base = (long long)bk * BS;
+    long long I[6];
+    nbr_index(base, t, tx, ty, tz, nb, I);
+    const T bv = (T)b[base + t];
+    op_stage(op, bk, tile);
     T W[6];
-    op_weights(op, L, base, t, tx, ty, tz, W);
+    op_weights(op, tile, base, t, tx, ty, tz, I, W);
     const T D = diag_of(W);
-    x[base + t] = D > T(0) ? c0 * (T)b[base + t] / D : T(0);
+    x[base + t] = D > T(0) ? c0 * bv / D : T(0);
 }
 
 // general Chebyshev step: r = b - A xin; d = c1 d_old + c2 D^-1 r; xout = xin + d
@@ -1007,24 +1003,30 @@ __global__ __launch_bounds__(NT) void k_cheb_step(OpArgs<T> op, Topo topo, const
                                                   const T *__restrict__ din, T *__restrict__ dout, T c1, T c2,
                                                   const Scal *sc)
 {
-    __shared__ BrickLds<T> L;
+    __shared__ T tile[TILE_VOX + 7];
     if (stopped(sc)) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
-    op_prepare(op, topo, bk, L);
+    int nb[6];
+    brick_nbrs(topo.nbr, bk, nb);
     const int t = threadIdx.x;
     int tx, ty, tz;
     brick_xyz(t, tx, ty, tz);
     const long long base = (long long)bk * BS;
-    T W[6], X[6];
-    op_weights(op, L, base, t, tx, ty, tz, W);
-    nbr_vals(xin, base, t, tx, ty, tz, L.nb, X);
+    long long I[6];
+    nbr_index(base, t, tx, ty, tz, nb, I);
+    T X[6];
+    nbr_vals(xin, I, X);
     const T x0 = xin[base + t];
+    const T bv = (T)b[base + t];
+    const T dold = din ? din[base + t] : x0;
+    op_stage(op, bk, tile);
+    T W[6];
+    op_weights(op, tile, base, t, tx, ty, tz, I, W);
     const T D = diag_of(W);
     T xo = T(0), dn = T(0);
     if (D > T(0)) {
-        const T r = (T)b[base + t] - stencil_apply(x0, X, W);
-        const T dold = din ? din[base + t] : x0;
+        const T r = bv - stencil_apply(x0, X, W);
         dn = c1 * dold + c2 * r / D;
         xo = x0 + dn;
     }
@@ -1039,20 +1041,27 @@ __global__ __launch_bounds__(NT) void k_resid_restrict(OpArgs<T> op, Topo topo, 
                                                        const int *__restrict__ parent_slot,
                                                        const int4 *__restrict__ fcoord, const Scal *sc)
 {
-    __shared__ BrickLds<T> L;
+    __shared__ T tile[TILE_VOX + 7];
     __shared__ T rs[BS];
     if (stopped(sc)) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
-    op_prepare(op, topo, bk, L);
+    int nb[6];
+    brick_nbrs(topo.nbr, bk, nb);
     const int t = threadIdx.x;
     int tx, ty, tz;
     brick_xyz(t, tx, ty, tz);
     const long long base = (long long)bk * BS;
-    T W[6], X[6];
-    op_weights(op, L, base, t, tx, ty, tz, W);
-    nbr_vals(x, base, t, tx, ty, tz, L.nb, X);
-    rs[t] = (T)b[base + t] - stencil_apply(x[base + t], X, W);
+    long long I[6];
+    nbr_index(base, t, tx, ty, tz, nb, I);
+    T X[6];
+    nbr_vals(x, I, X);
+    const T x0 = x[base + t];
+    const T bv = (T)b[base + t];
+    op_stage(op, bk, tile);
+    T W[6];
+    op_weights(op, tile, base, t, tx, ty, tz, I, W);
+    rs[t] = bv - stencil_apply(x0, X, W);
     __syncthreads();
     if (t < 64) {
         const int cx = t & 3, cy = (t >> 2) & 3, cz = t >> 4;
@@ -1211,7 +1220,7 @@ hipError_t launch_comp_mean(Topo topo, const double *x, const int *comp, int nco
     if (ncomp <= 16) {
         for (int c = 0; c < ncomp; ++c) {
             hipLaunchKernelGGL(k_comp_sum, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, comp, c, part);
-            hipError_t e = finish(part, topo.nb, FIN_MEAN, nullptr, 0, s, means, counts, c);
+            hipError_t e = launch_finish(part, topo.nb, FIN_MEAN, nullptr, 0, s, means, counts, c);
             if (e != hipSuccess) return e;
         }
     } else {
