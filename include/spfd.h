@@ -71,6 +71,9 @@ typedef struct {
     double cheby_ratio;   /* smoothing interval [2/ratio, 2] of D^-1 A, default 8 */
     double coarse_scale;  /* scaling of the coarse-grid correction (over-correction of the piecewise-constant
                              aggregation), default 1.8; keep below 2 */
+    int split_level;      /* aggregates of this level and coarser ones are split into their connected pieces
+                             (coarse unknowns become unstructured), default 2 */
+    int no_split;         /* nonzero: never split aggregates (structured 7-point levels only) */
 } spfd_amg_options;
 
 typedef struct {
@@ -124,6 +127,21 @@ spfd_status spfd_solve(spfd_handle h, const spfd_solve_options *opt, double *psi
  * conducting voxel, 0 in air.  a and psi as in spfd_set_source / spfd_solve. */
 spfd_status spfd_efield(spfd_handle h, double omega, const double *a, const double *psi,
                         double *u_edges, double *emag);
+
+/* Adjoint gradient of a scalar objective J(|E|) with respect to the voxel
+ * conductivities, by one extra solve of Eq. (3) on the built hierarchy.
+ * Inputs: omega, a and psi of a forward solution (as for spfd_efield), and
+ * grad_emag [nvox] (device) = dJ/d|E_v|.  Computes g_e = dJ/du_e on the edges,
+ * solves A lambda = G^T g (opt as for spfd_solve, use_x0 ignored) and writes
+ *   grad_sigma_voxel [nvox] (device) = -sum over the 12 edges e of v of
+ *       (dual area / length / 4) (G lambda)_e u_e   (0 for air voxels);
+ *   grad_sigma_table (host, nullable) = per-label sums of grad_sigma_voxel
+ *       (n_labels entries of the sigma table; 256 in per-voxel mode).
+ * Follows from A Psi = -G^T M a, u = a + G Psi (Eqs. (1), (3)) and dA = G^T dM G.
+ * info (host, nullable) reports the adjoint solve. */
+spfd_status spfd_adjoint(spfd_handle h, double omega, const double *a, const double *psi, const double *grad_emag,
+                         const spfd_solve_options *opt, double *grad_sigma_voxel, double *grad_sigma_table,
+                         spfd_rhs_info *info);
 
 /* Per-launch timing, a tracing aid.  Kernel classes: */
 enum {

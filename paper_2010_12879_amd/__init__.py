@@ -33,7 +33,8 @@ class SPFDError(RuntimeError):
 
 class AmgOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("cycle", ctypes.c_int), ("smooth_degree", ctypes.c_int),
-                ("coarsest_max", ctypes.c_int), ("cheby_ratio", ctypes.c_double), ("coarse_scale", ctypes.c_double)]
+                ("coarsest_max", ctypes.c_int), ("cheby_ratio", ctypes.c_double), ("coarse_scale", ctypes.c_double),
+                ("split_level", ctypes.c_int), ("no_split", ctypes.c_int)]
 
 
 class SolveOptions(ctypes.Structure):
@@ -50,7 +51,7 @@ class RhsInfo(ctypes.Structure):
 _lib = None
 EXPORTS = ["spfd_create", "spfd_destroy", "spfd_last_error", "spfd_set_geometry", "spfd_set_sigma_table",
            "spfd_set_sigma_voxel", "spfd_build", "spfd_get_info", "spfd_set_num_rhs", "spfd_set_source",
-           "spfd_solve", "spfd_efield", "spfd_timing", "spfd_timing_get"]
+           "spfd_solve", "spfd_efield", "spfd_adjoint", "spfd_timing", "spfd_timing_get"]
 # kernel classes of spfd_timing / spfd_timing_get (order of the enum in spfd.h)
 KERNEL_CLASSES = ["spmv", "update", "dots", "pupdate", "smooth0", "smooth0_first", "restrict0", "prolong0", "coarse",
                   "finish", "rhs", "efield", "gauge"]
@@ -82,6 +83,7 @@ def load_library(path: str = LIB_PATH):
     lib.spfd_set_source.argtypes = [H, I, P]
     lib.spfd_solve.argtypes = [H, ctypes.POINTER(SolveOptions), P, ctypes.POINTER(RhsInfo)]
     lib.spfd_efield.argtypes = [H, D, P, P, P, P]
+    lib.spfd_adjoint.argtypes = [H, D, P, P, P, ctypes.POINTER(SolveOptions), P, P, ctypes.POINTER(RhsInfo)]
     lib.spfd_timing.argtypes = [H, ctypes.c_uint]
     lib.spfd_timing_get.argtypes = [H, I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D), ctypes.POINTER(D)]
     for name in EXPORTS:
@@ -188,6 +190,20 @@ def spfd_efield(h, omega, a, psi, u_edges, emag):
     return _check(h, load_library().spfd_efield(h, float(omega), _ptr(a), _ptr(psi), _ptr(u_edges), _ptr(emag)))
 
 
+def spfd_adjoint(h, omega, a, psi, grad_emag, opts: SolveOptions | None, grad_sigma_voxel, n_table: int = 0):
+    """Adjoint gradient: fills grad_sigma_voxel; returns (status, per-label sums or None, info)."""
+    import torch
+    for t, n in ((a, "a"), (psi, "psi"), (grad_emag, "grad_emag"), (grad_sigma_voxel, "grad_sigma_voxel")):
+        _require_cuda(t, torch.float64, None, n)
+    table = (ctypes.c_double * n_table)() if n_table else None
+    info = RhsInfo()
+    st = load_library().spfd_adjoint(h, float(omega), _ptr(a), _ptr(psi), _ptr(grad_emag),
+                                     ctypes.byref(opts) if opts is not None else None, _ptr(grad_sigma_voxel),
+                                     table, ctypes.byref(info))
+    _check(h, st, allow=(5, 6))
+    return st, (list(table) if table is not None else None), info.as_dict()
+
+
 def spfd_timing(h, class_mask: int):
     return _check(h, load_library().spfd_timing(h, class_mask))
 
@@ -208,7 +224,7 @@ class Solver:
     """
 
     def __init__(self, labels, sigma, h, precision="fp64", device=None, smooth_degree=2, coarsest_max=1024,
-                 cheby_ratio=8.0, coarse_scale=1.8, cycle="v"):
+                 cheby_ratio=8.0, coarse_scale=1.8, cycle="v", split_level=2, split=True):
         import torch
         self.device = labels.device if device is None else torch.device(device)
         self.nz, self.ny, self.nx = labels.shape
@@ -222,13 +238,38 @@ class Solver:
             else:
                 spfd_set_sigma_table(self.handle, list(sigma))
             self.opts = AmgOptions(MIXED if precision == "mixed" else FP64, CYCLE_K if cycle == "k" else CYCLE_V,
-                                   smooth_degree, coarsest_max, cheby_ratio, coarse_scale)
+                                   smooth_degree, coarsest_max, cheby_ratio, coarse_scale, split_level,
+                                   0 if split else 1)
             spfd_build(self.handle, self.opts)
         except Exception:
             spfd_destroy(self.handle)
             self.handle = None
             raise
         self.nrhs = 1
+        self.n_table = 0 if isinstance(sigma, torch.Tensor) else len(sigma)
+
+    def set_sigma(self, sigma):
+        """New conductivities (table sequence / 1-D tensor, or per-voxel CUDA tensor) and a rebuilt hierarchy."""
+        import torch
+        if isinstance(sigma, torch.Tensor) and sigma.dim() == 3:
+            spfd_set_sigma_voxel(self.handle, sigma.detach().to(torch.float64).contiguous())
+            self.n_table = 0
+        else:
+            vals = sigma.detach().cpu().tolist() if isinstance(sigma, torch.Tensor) else list(sigma)
+            spfd_set_sigma_table(self.handle, vals)
+            self.n_table = len(vals)
+        spfd_build(self.handle, self.opts)
+        self.nrhs = 1
+
+    def adjoint(self, a, psi, omega, grad_emag, tol=1e-8, max_iter=500):
+        """(dJ/dsigma per voxel (nz,ny,nx), per-label list or None, info) for dJ/d|E| = grad_emag."""
+        import torch
+        gvox = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        n_table = self.n_table if self.n_table else 256
+        st, gtab, info = spfd_adjoint(self.handle, omega, a.contiguous(), psi.contiguous(),
+                                      grad_emag.to(torch.float64).contiguous(), SolveOptions(tol, max_iter, 0), gvox,
+                                      n_table)
+        return gvox, gtab, info
 
     @property
     def node_shape(self):
@@ -281,3 +322,48 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def _autograd_function():
+    import torch
+
+    class SPFDField(torch.autograd.Function):
+        """|E| per voxel as a differentiable function of the conductivities.
+
+        forward(sigma, solver, a, omega, tol): sigma is a 1-D float64 tensor (one value
+        per label) or a (nz, ny, nx) float64 CUDA tensor (per voxel).  The solver's
+        hierarchy is rebuilt for sigma, Eq. (3) is solved and |E| returned.
+        backward: one adjoint solve (spfd_adjoint) gives dJ/dsigma.
+        """
+
+        @staticmethod
+        def forward(ctx, sigma, solver, a, omega, tol=1e-10):
+            solver.set_sigma(sigma)
+            psi, info = solver.solve(a, tol=tol)
+            emag = solver.efield(a, psi, omega)
+            ctx.solver, ctx.omega, ctx.tol = solver, omega, tol
+            ctx.per_voxel = sigma.dim() == 3
+            ctx.n = sigma.numel()
+            ctx.sigma_device, ctx.sigma_dtype = sigma.device, sigma.dtype
+            ctx.save_for_backward(a, psi)
+            return emag
+
+        @staticmethod
+        def backward(ctx, grad_emag):
+            a, psi = ctx.saved_tensors
+            gvox, gtab, info = ctx.solver.adjoint(a, psi, ctx.omega, grad_emag.contiguous(), tol=ctx.tol)
+            if ctx.per_voxel:
+                g = gvox.to(ctx.sigma_dtype)
+            else:
+                g = torch.tensor(gtab[:ctx.n], dtype=ctx.sigma_dtype, device=ctx.sigma_device)
+            return g, None, None, None, None
+
+    return SPFDField
+
+
+def __getattr__(name):
+    if name == "SPFDField":
+        fn = _autograd_function()
+        globals()["SPFDField"] = fn
+        return fn
+    raise AttributeError(name)

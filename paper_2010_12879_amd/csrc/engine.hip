@@ -47,8 +47,18 @@ struct Level {
     // cycle buffers (type of the cycle)
     void *x = nullptr, *x2 = nullptr, *d = nullptr, *b = nullptr;
     long long dofs = 0;
+    // unstructured (ELL) level: rows = split aggregates, K neighbours per row
+    bool ell = false;
+    int nrow = 0, K = 0;
+    int *d_col = nullptr;
+    double *d_val64 = nullptr;
+    float *d_val32 = nullptr;
+    int4 *d_pos = nullptr;          // grid position of each row at this level
+    int *d_mptr = nullptr;          // members of each row in the finer level (CSR)
+    int *d_mem = nullptr;
+    int *d_agg = nullptr;           // this level's unknown -> row of the next (split) level, -1 if none
     Topo topo() const { return Topo{nb, d_nbr}; }
-    long long nodes() const { return (long long)nb * BS; }
+    long long nodes() const { return ell ? (long long)nrow : (long long)nb * BS; }
 };
 
 struct Ctx {
@@ -84,13 +94,23 @@ struct Ctx {
     double cheb_c0 = 0.0;
     // outer CG state
     int nrhs = 0;
-    std::vector<double *> d_b;
+    double *d_bs = nullptr;   // right sides [nrhs][n0]
     std::vector<int> has_source;
     double *d_x = nullptr, *d_r = nullptr, *d_p = nullptr, *d_q = nullptr;
     void *d_z = nullptr;
     Scal *d_scal = nullptr;
-    Scal *h_scal = nullptr;   // pinned
+    Scal *h_scal = nullptr;   // pinned, one per right side plus one for the adjoint solve
+    // adjoint solve
+    double *d_adj_b = nullptr;
+    double *d_adj_c = nullptr;
+    double *d_adj_lam = nullptr;
+    double *d_adj_labpart = nullptr;
+    double *d_adj_labout = nullptr;
+    Scal *d_adj_scal = nullptr;
     double *d_part = nullptr;
+    int pstride = 0;          // partial sums per right side
+    int *d_again = nullptr;   // per right side: restart from the true residual
+    int nbat = 0;             // right sides the solve buffers hold
     int *d_ints = nullptr;    // small scratch ints
     int *h_ints = nullptr;    // pinned
     // per-class launch timing (tracing aid)
@@ -101,7 +121,7 @@ struct Ctx {
     double tbytes[SPFD_K_COUNT] = {};
     // bookkeeping: live allocations per owner, and released buffers kept for
     // reuse (a rebuild with the same geometry allocates nothing)
-    std::vector<void *> geo_allocs, hier_allocs, rhs_allocs;
+    std::vector<void *> geo_allocs, hier_allocs, rhs_allocs, src_allocs;
     std::vector<std::pair<size_t, void *>> pool;
     std::vector<std::pair<void *, size_t>> sizes;
     size_t bytes = 0;
@@ -331,88 +351,152 @@ double op_bytes(Ctx *c, int l)
     return (l == 0 && !c->voxel_mode) ? 1.0 : 3.0 * sizeof(T);
 }
 
+template <typename T>
+const T *ell_val(const Level &L);
+template <>
+const double *ell_val<double>(const Level &L) { return L.d_val64; }
+template <>
+const float *ell_val<float>(const Level &L) { return L.d_val32; }
+
+Batch level_batch(Ctx *c, int l, int n)
+{
+    Batch bt;
+    bt.n = n;
+    bt.vs = c->lv[l].nodes();
+    bt.vsc = l + 1 < (int)c->lv.size() ? c->lv[l + 1].nodes() : 0;
+    bt.ps = c->pstride;
+    return bt;
+}
+
 template <typename T, typename TB>
-void cheb_first(Ctx *c, int l, const TB *b, T *x, const Scal *sc)
+void cheb_first(Ctx *c, int l, const TB *b, T *x, const Scal *sc, int nb)
 {
     Level &L = c->lv[l];
-    const double by = (double)L.dofs * (sizeof(TB) + op_bytes<T>(c, l) + sizeof(T));
+    const Batch bt = level_batch(c, l, nb);
+    if (L.ell) {
+        TScope ts(c, SPFD_K_COARSE, nb * (double)L.nrow * (2.0 * sizeof(T) + L.K * (4.0 + sizeof(T))));
+        HIPCHK(launch_ell_cheb_first<T>(L.nrow, L.K, L.d_col, ell_val<T>(L), (const T *)b, x, (T)c->cheb_c0, sc, bt,
+                                        c->stream));
+        return;
+    }
+    const double by = nb * (double)L.dofs * (sizeof(TB) + op_bytes<T>(c, l) + sizeof(T));
     TScope ts(c, l == 0 ? SPFD_K_SMOOTH0_FIRST : SPFD_K_COARSE, by);
-    HIPCHK(launch_cheb_first<T, TB>(level_op<T>(c, l), L.topo(), b, x, (T)c->cheb_c0, sc, c->stream));
+    HIPCHK(launch_cheb_first<T, TB>(level_op<T>(c, l), L.topo(), b, x, (T)c->cheb_c0, sc, bt, c->stream));
 }
 
 template <typename T, typename TB>
-void cheb_step(Ctx *c, int l, const TB *b, const T *xin, T *xout, const T *din, T *dout, T c1, T c2, const Scal *sc)
+void cheb_step(Ctx *c, int l, const TB *b, const T *xin, T *xout, const T *din, T *dout, T c1, T c2, const Scal *sc,
+               int nb)
 {
     Level &L = c->lv[l];
+    const Batch bt = level_batch(c, l, nb);
+    if (L.ell) {
+        TScope ts(c, SPFD_K_COARSE, nb * (double)L.nrow * (4.0 * sizeof(T) + L.K * (4.0 + sizeof(T))));
+        HIPCHK(launch_ell_cheb_step<T>(L.nrow, L.K, L.d_col, ell_val<T>(L), (const T *)b, xin, xout, din, dout, c1, c2,
+                                       sc, bt, c->stream));
+        return;
+    }
     const double per = sizeof(TB) + op_bytes<T>(c, l) + sizeof(T) * (2 + (din ? 1 : 0) + (dout ? 1 : 0));
-    TScope ts(c, l == 0 ? SPFD_K_SMOOTH0 : SPFD_K_COARSE, (double)L.dofs * per);
-    HIPCHK(launch_cheb_step<T, TB>(level_op<T>(c, l), L.topo(), b, xin, xout, din, dout, c1, c2, sc, c->stream));
+    TScope ts(c, l == 0 ? SPFD_K_SMOOTH0 : SPFD_K_COARSE, nb * (double)L.dofs * per);
+    HIPCHK(launch_cheb_step<T, TB>(level_op<T>(c, l), L.topo(), b, xin, xout, din, dout, c1, c2, sc, bt, c->stream));
 }
 
 template <typename T, typename TB>
-void smooth_pre(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc)
+void smooth_pre(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc, int nb)
 {
     const int m = c->opt.smooth_degree;
     T *d = (T *)c->lv[l].d;
-    cheb_first<T, TB>(c, l, b, cur, sc);
+    cheb_first<T, TB>(c, l, b, cur, sc, nb);
     for (int k = 1; k < m; ++k) {
         cheb_step<T, TB>(c, l, b, cur, other, k == 1 ? nullptr : d, k < m - 1 ? d : nullptr, (T)c->cheb_c1[k],
-                         (T)c->cheb_c2[k], sc);
+                         (T)c->cheb_c2[k], sc, nb);
         T *t = cur; cur = other; other = t;
     }
 }
 
 template <typename T, typename TB>
-void smooth_post(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc)
+void smooth_post(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc, int nb)
 {
     const int m = c->opt.smooth_degree;
     T *d = (T *)c->lv[l].d;
     for (int k = 0; k < m; ++k) {
         const T c1 = k == 0 ? T(0) : (T)c->cheb_c1[k];
         const T c2 = k == 0 ? (T)c->cheb_c0 : (T)c->cheb_c2[k];
-        cheb_step<T, TB>(c, l, b, cur, other, k == 0 ? nullptr : d, k < m - 1 ? d : nullptr, c1, c2, sc);
+        cheb_step<T, TB>(c, l, b, cur, other, k == 0 ? nullptr : d, k < m - 1 ? d : nullptr, c1, c2, sc, nb);
         T *t = cur; cur = other; other = t;
     }
 }
 
+template <typename T>
+const T *stored_w(const Level &L);
+template <>
+const double *stored_w<double>(const Level &L) { return L.d_w64; }
+template <>
+const float *stored_w<float>(const Level &L) { return L.d_w32; }
+
 template <typename T, typename TB>
-void restrict_level(Ctx *c, int l, const TB *b, const T *x, const Scal *sc)
+void restrict_level(Ctx *c, int l, const TB *b, const T *x, const Scal *sc, int nb)
 {
     Level &L = c->lv[l];
     Level &C = c->lv[l + 1];
-    const double by = (double)L.dofs * (sizeof(TB) + op_bytes<T>(c, l) + sizeof(T)) + (double)C.dofs * sizeof(T);
+    const Batch bt = level_batch(c, l, nb);
+    if (C.ell) {
+        FineLevelT<T> f{};
+        if (L.ell) {
+            f.n = L.nrow;
+            f.K = L.K;
+            f.col = L.d_col;
+            f.val = ell_val<T>(L);
+        } else {
+            f.w = stored_w<T>(L);
+            f.stride = L.nodes();
+            f.nbr = L.d_nbr;
+        }
+        TScope ts(c, SPFD_K_COARSE, nb * ((double)L.dofs * 3.0 * sizeof(T) + (double)C.nrow * 8.0));
+        HIPCHK(launch_restrict_members<T>(f, (const T *)b, x, C.nrow, C.d_mptr, C.d_mem, (T *)C.b, sc, bt, c->stream));
+        return;
+    }
+    const double by = nb * ((double)L.dofs * (sizeof(TB) + op_bytes<T>(c, l) + sizeof(T)) + (double)C.dofs * sizeof(T));
     TScope ts(c, l == 0 ? SPFD_K_RESTRICT0 : SPFD_K_COARSE, by);
-    HIPCHK(launch_resid_restrict<T, TB>(level_op<T>(c, l), L.topo(), b, x, (T *)C.b, L.d_parent_slot, L.d_coord, sc,
+    HIPCHK(launch_resid_restrict<T, TB>(level_op<T>(c, l), L.topo(), b, x, (T *)C.b, L.d_parent_slot, L.d_coord, sc, bt,
                                         c->stream));
 }
 
 template <typename T>
-void prolong_level(Ctx *c, int l, T *x, const Scal *sc)
+void prolong_level(Ctx *c, int l, T *x, const Scal *sc, int nb)
 {
     Level &L = c->lv[l];
     Level &C = c->lv[l + 1];
-    const double by = (double)L.dofs * 2.0 * sizeof(T) + (double)C.dofs * sizeof(T);
+    const Batch bt = level_batch(c, l, nb);
+    if (C.ell) {
+        TScope ts(c, SPFD_K_COARSE, nb * (double)L.nodes() * (2.0 * sizeof(T) + 4.0));
+        HIPCHK(launch_prolong_agg<T>(L.nodes(), L.d_agg, x, (const T *)C.x, (T)c->opt.coarse_scale, sc, bt, c->stream));
+        return;
+    }
+    const double by = nb * ((double)L.dofs * 2.0 * sizeof(T) + (double)C.dofs * sizeof(T));
     TScope ts(c, l == 0 ? SPFD_K_PROLONG0 : SPFD_K_COARSE, by);
-    HIPCHK(launch_prolong<T>(L.topo(), x, (const T *)C.x, L.d_parent_slot, L.d_coord, (T)c->opt.coarse_scale, sc,
+    HIPCHK(launch_prolong<T>(L.topo(), x, (const T *)C.x, L.d_parent_slot, L.d_coord, (T)c->opt.coarse_scale, sc, bt,
                              c->stream));
 }
 
 template <typename T, typename TB>
-void coarse_solve(Ctx *c, const TB *b, T *x, const Scal *sc)
+void coarse_solve(Ctx *c, const TB *b, T *x, const Scal *sc, int nb)
 {
     const double n = (double)c->ncoarse;
-    TScope ts(c, SPFD_K_COARSE, n * n * 8.0 + n * (sizeof(TB) + sizeof(T)));
-    HIPCHK(launch_coarse_apply<T, TB>(b, x, c->d_Ainv, c->d_cdof_node, c->ncoarse, sc, c->stream));
+    const Batch bt = level_batch(c, (int)c->lv.size() - 1, nb);
+    TScope ts(c, SPFD_K_COARSE, n * n * 8.0 + nb * n * (sizeof(TB) + sizeof(T)));
+    HIPCHK(launch_coarse_apply<T, TB>(b, x, c->d_Ainv, c->d_cdof_node, c->ncoarse, sc, bt, c->stream));
 }
 
-// z = B r: one V-cycle (T = arithmetic of the cycle); r is the FP64 outer residual
+// z = B r for a batch of nb right sides: one V-cycle (T = arithmetic of the
+// cycle); r is the FP64 outer residual
 template <typename T>
-void vcycle(Ctx *c, const double *r, T *z, const Scal *sc)
+void vcycle(Ctx *c, const double *r, T *z, const Scal *sc, int nb)
 {
     const int nl = (int)c->lv.size();
     std::vector<T *> res(nl, nullptr);
     if (nl == 1) {
-        coarse_solve<T, double>(c, r, z, sc);  // single level: the dense solve is exact
+        coarse_solve<T, double>(c, r, z, sc, nb);  // single level: the dense solve is exact
         return;
     }
     // downward: pre-smooth, restrict the residual.  The smoother ping-pongs
@@ -423,37 +507,38 @@ void vcycle(Ctx *c, const double *r, T *z, const Scal *sc)
         T *cur = (T *)L.x2;
         T *other = l == 0 ? z : (T *)L.x;
         if (l == 0) {
-            smooth_pre<T, double>(c, l, r, cur, other, sc);
-            restrict_level<T, double>(c, l, r, cur, sc);
+            smooth_pre<T, double>(c, l, r, cur, other, sc, nb);
+            restrict_level<T, double>(c, l, r, cur, sc, nb);
         } else {
-            smooth_pre<T, T>(c, l, (const T *)L.b, cur, other, sc);
-            restrict_level<T, T>(c, l, (const T *)L.b, cur, sc);
+            smooth_pre<T, T>(c, l, (const T *)L.b, cur, other, sc, nb);
+            restrict_level<T, T>(c, l, (const T *)L.b, cur, sc, nb);
         }
         res[l] = cur;
     }
     {
         Level &C = c->lv[nl - 1];
-        coarse_solve<T, T>(c, (const T *)C.b, (T *)C.x, sc);
+        coarse_solve<T, T>(c, (const T *)C.b, (T *)C.x, sc, nb);
     }
     // upward: prolongate and correct, post-smooth
     for (int l = nl - 2; l >= 0; --l) {
         Level &L = c->lv[l];
         T *cur = res[l];
         T *other = (cur == (T *)L.x2) ? (l == 0 ? z : (T *)L.x) : (T *)L.x2;
-        prolong_level<T>(c, l, cur, sc);
+        prolong_level<T>(c, l, cur, sc, nb);
         if (l == 0)
-            smooth_post<T, double>(c, l, r, cur, other, sc);
+            smooth_post<T, double>(c, l, r, cur, other, sc, nb);
         else
-            smooth_post<T, T>(c, l, (const T *)L.b, cur, other, sc);
+            smooth_post<T, T>(c, l, (const T *)L.b, cur, other, sc, nb);
         T *want = l == 0 ? z : (T *)L.x;
-        if (cur != want) HIPCHK(hipMemcpyAsync(want, cur, L.nodes() * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+        if (cur != want)
+            HIPCHK(hipMemcpyAsync(want, cur, nb * L.nodes() * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
     }
 }
 
-void finish(Ctx *c, int n, int mode, Scal *sc, int max_iter)
+void finish(Ctx *c, int n, int mode, Scal *sc, int max_iter, int nb = 1)
 {
-    TScope ts(c, SPFD_K_FINISH, (double)n * 8.0 * (mode == FIN_BETA ? 2 : 1));
-    HIPCHK(launch_finish(c->d_part, n, mode, sc, max_iter, c->stream));
+    TScope ts(c, SPFD_K_FINISH, nb * (double)n * 8.0 * (mode == FIN_BETA ? 2 : 1));
+    HIPCHK(launch_finish(c->d_part, n, mode, sc, max_iter, c->stream, nullptr, nullptr, 0, nb, c->pstride));
 }
 
 void set_defaults(spfd_amg_options &o)
@@ -466,6 +551,7 @@ void set_defaults(spfd_amg_options &o)
     if (o.coarsest_max > 1024) o.coarsest_max = 1024;
     if (!(o.cheby_ratio > 1.0)) o.cheby_ratio = 8.0;
     if (!(o.coarse_scale > 0.0)) o.coarse_scale = 1.8;
+    if (o.split_level <= 0) o.split_level = 2;
 }
 
 void chebyshev_coefficients(Ctx *c)
@@ -485,39 +571,121 @@ void chebyshev_coefficients(Ctx *c)
     }
 }
 
-void alloc_cycle_buffers(Ctx *c)
+// solve buffers for nb right sides: cycle vectors of every level, the outer
+// CG vectors and the partial sums
+void alloc_cycle_buffers(Ctx *c, int nb)
 {
+    free_all(c, c->rhs_allocs);
     const bool mixed = c->opt.precision == SPFD_MIXED;
     const size_t w = mixed ? sizeof(float) : sizeof(double);
     for (size_t l = 0; l < c->lv.size(); ++l) {
         Level &L = c->lv[l];
-        const size_t n = (size_t)L.nodes();
-        L.x = dalloc<uint8_t>(c, c->hier_allocs, n * w);
-        L.x2 = dalloc<uint8_t>(c, c->hier_allocs, n * w);
-        L.d = dalloc<uint8_t>(c, c->hier_allocs, n * w);
-        L.b = dalloc<uint8_t>(c, c->hier_allocs, n * w);
+        const size_t n = (size_t)L.nodes() * nb;
+        L.x = dalloc<uint8_t>(c, c->rhs_allocs, n * w);
+        L.x2 = dalloc<uint8_t>(c, c->rhs_allocs, n * w);
+        L.d = dalloc<uint8_t>(c, c->rhs_allocs, n * w);
+        L.b = dalloc<uint8_t>(c, c->rhs_allocs, n * w);
         HIPCHK(hipMemsetAsync(L.x, 0, n * w, c->stream));
         HIPCHK(hipMemsetAsync(L.x2, 0, n * w, c->stream));
         HIPCHK(hipMemsetAsync(L.d, 0, n * w, c->stream));
         HIPCHK(hipMemsetAsync(L.b, 0, n * w, c->stream));
     }
-    const size_t n0 = (size_t)c->lv[0].nodes();
-    c->d_x = dalloc<double>(c, c->hier_allocs, n0);
-    c->d_r = dalloc<double>(c, c->hier_allocs, n0);
-    c->d_p = dalloc<double>(c, c->hier_allocs, n0);
-    c->d_q = dalloc<double>(c, c->hier_allocs, n0);
-    c->d_z = dalloc<uint8_t>(c, c->hier_allocs, n0 * w);
+    const size_t n0 = (size_t)c->lv[0].nodes() * nb;
+    c->d_x = dalloc<double>(c, c->rhs_allocs, n0);
+    c->d_r = dalloc<double>(c, c->rhs_allocs, n0);
+    c->d_p = dalloc<double>(c, c->rhs_allocs, n0);
+    c->d_q = dalloc<double>(c, c->rhs_allocs, n0);
+    c->d_z = dalloc<uint8_t>(c, c->rhs_allocs, n0 * w);
     HIPCHK(hipMemsetAsync(c->d_z, 0, n0 * w, c->stream));
     HIPCHK(hipMemsetAsync(c->d_p, 0, n0 * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(c->d_q, 0, n0 * sizeof(double), c->stream));
+    c->pstride = 2 * c->lv[0].nb + 64;
+    c->d_part = dalloc<double>(c, c->rhs_allocs, (size_t)c->pstride * nb);
+    c->nbat = nb;
+}
+
+// Coarse level whose unknowns are the connected pieces of the 2x2x2
+// aggregates of F (F structured or ELL), with its ELL Galerkin operator.
+Level split_level(Ctx *c, Level &F)
+{
+    Level C;
+    C.ell = true;
+    const long long nf = F.nodes();
+    int *parent = dalloc<int>(c, c->hier_allocs, nf);
+    int *flag = dalloc<int>(c, c->hier_allocs, nf);
+    int *idx = dalloc<int>(c, c->hier_allocs, nf);
+    int *tmp = dalloc<int>(c, c->hier_allocs, nf / 2048 + 2);
+    if (F.ell)
+        HIPCHK(launch_pieces_ell(F.nrow, F.K, F.d_col, F.d_val64, F.d_pos, parent, c->stream));
+    else
+        HIPCHK(launch_pieces_brick(F.d_w64, F.nodes(), F.topo(), F.d_coord, parent, c->stream));
+    HIPCHK(launch_pieces_finish(parent, nf, flag, c->stream));
+    HIPCHK(scan_exclusive_ints(flag, nf, idx, tmp, c->d_ints, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_ints, c->d_ints, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int nc = c->h_ints[0];
+    C.nrow = nc;
+    C.d_pos = dalloc<int4>(c, c->hier_allocs, nc + 1);
+    if (F.ell)
+        HIPCHK(launch_piece_pos_ell(F.nrow, parent, idx, F.d_pos, C.d_pos, c->stream));
+    else
+        HIPCHK(launch_piece_pos_brick(parent, idx, F.topo(), F.d_coord, C.d_pos, c->stream));
+    // fine -> coarse map and member lists
+    F.d_agg = dalloc<int>(c, c->hier_allocs, nf);
+    int *count = dalloc<int>(c, c->hier_allocs, nc + 1);
+    HIPCHK(hipMemsetAsync(count, 0, (nc + 1) * sizeof(int), c->stream));
+    HIPCHK(launch_pieces_assign(parent, idx, nf, F.d_agg, count, c->stream));
+    C.d_mptr = dalloc<int>(c, c->hier_allocs, nc + 1);
+    int *tmp2 = dalloc<int>(c, c->hier_allocs, nc / 2048 + 2);
+    HIPCHK(scan_exclusive_ints(count, nc + 1, C.d_mptr, tmp2, c->d_ints + 1, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_ints + 1, c->d_ints + 1, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int nmem = c->h_ints[1];
+    C.d_mem = dalloc<int>(c, c->hier_allocs, nmem + 1);
+    HIPCHK(hipMemsetAsync(count, 0, (nc + 1) * sizeof(int), c->stream));
+    HIPCHK(launch_members(F.d_agg, nf, nc, C.d_mptr, count, C.d_mem, c->stream));
+    // Galerkin rows: lengths, then the ELL arrays
+    FineLevelArgs fa{};
+    if (F.ell) {
+        fa.n = F.nrow;
+        fa.K = F.K;
+        fa.col = F.d_col;
+        fa.val = F.d_val64;
+    } else {
+        fa.w = F.d_w64;
+        fa.stride = F.nodes();
+        fa.nbr = F.d_nbr;
+    }
+    int *len = dalloc<int>(c, c->hier_allocs, nc + 1);
+    HIPCHK(hipMemsetAsync(c->d_ints + 2, 0, 2 * sizeof(int), c->stream));
+    HIPCHK(launch_galerkin_ell(fa, F.d_agg, nc, C.d_mptr, C.d_mem, 0, len, 0, nullptr, nullptr, nullptr, c->d_ints + 2,
+                               c->d_ints + 3, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_ints + 2, c->d_ints + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->h_ints[2]) throw HipFail{hipErrorInvalidValue, "split aggregate with too many coarse neighbours"};
+    C.K = c->h_ints[3] > 0 ? c->h_ints[3] : 1;
+    C.d_col = dalloc<int>(c, c->hier_allocs, (size_t)C.K * nc + 1);
+    C.d_val64 = dalloc<double>(c, c->hier_allocs, (size_t)C.K * nc + 1);
+    C.d_val32 = dalloc<float>(c, c->hier_allocs, (size_t)C.K * nc + 1);
+    HIPCHK(launch_galerkin_ell(fa, F.d_agg, nc, C.d_mptr, C.d_mem, 1, len, C.K, C.d_col, C.d_val64, C.d_val32,
+                               c->d_ints + 2, c->d_ints + 3, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    // unknowns of the new level: rows with a conducting connection
+    HIPCHK(launch_coarse_enum_ell(C.nrow, C.K, C.d_col, C.d_val64, flag, idx, c->d_ints, 0, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_ints, c->d_ints, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    C.dofs = c->h_ints[0];
+    return C;
 }
 
 spfd_status do_build(Ctx *c)
 {
     free_all(c, c->hier_allocs);
+    c->d_adj_b = c->d_adj_c = c->d_adj_lam = c->d_adj_labpart = c->d_adj_labout = nullptr;
+    c->d_adj_scal = nullptr;
     free_all(c, c->rhs_allocs);
+    free_all(c, c->src_allocs);
     c->lv.clear();
-    c->d_b.clear();
     c->has_source.clear();
     c->nrhs = 0;
     Grid &g = c->g;
@@ -568,15 +736,23 @@ spfd_status do_build(Ctx *c)
         HIPCHK(launch_comp_counts(c->d_comp, n, c->d_counts, c->stream));
     }
     L0.dofs = count_dofs(c, L0);
-    // 4. coarsening: 2x2x2 aggregation until the level is small enough
+    // 4. coarsening: 2x2x2 aggregation until the level is small enough; from
+    //    level split_level on, aggregates are split into their connected pieces
     while (c->lv.back().dofs > c->opt.coarsest_max && c->lv.size() < 20) {
-        Level &F = c->lv.back();
+        const int l = (int)c->lv.size() - 1;
+        Level &F = c->lv[l];
+        const bool split = !c->opt.no_split && (l >= c->opt.split_level || F.ell);
+        if (!F.ell && F.N[0] == 1 && F.N[1] == 1 && F.N[2] == 1) break;
+        if (split) {
+            Level C = split_level(c, F);
+            c->lv.push_back(std::move(C));
+            continue;
+        }
         Level C;
         for (int d = 0; d < 3; ++d) {
             C.N[d] = (F.N[d] + 1) / 2;
             C.G[d] = (C.N[d] + 7) / 8;
         }
-        if (F.N[0] == 1 && F.N[1] == 1 && F.N[2] == 1) break;
         std::vector<uint8_t> cflags((size_t)C.G[0] * C.G[1] * C.G[2], 0);
         for (int s = 0; s < F.nb; ++s) {
             const int4 q = F.coord[s];
@@ -605,8 +781,12 @@ spfd_status do_build(Ctx *c)
         c->d_node_cdof = dalloc<int>(c, c->hier_allocs, C.nodes());
         c->d_cdof_node = dalloc<int>(c, c->hier_allocs, maxd);
         c->d_cadj = dalloc<int>(c, c->hier_allocs, (size_t)maxd * 6);
-        HIPCHK(launch_coarse_setup(C.d_w64, C.nodes(), C.topo(), c->d_node_cdof, c->d_cdof_node, c->d_cadj, c->d_ints,
-                                   maxd, c->stream));
+        if (C.ell)
+            HIPCHK(launch_coarse_enum_ell(C.nrow, C.K, C.d_col, C.d_val64, c->d_node_cdof, c->d_cdof_node, c->d_ints,
+                                          maxd, c->stream));
+        else
+            HIPCHK(launch_coarse_setup(C.d_w64, C.nodes(), C.topo(), c->d_node_cdof, c->d_cdof_node, c->d_cadj,
+                                       c->d_ints, maxd, c->stream));
         HIPCHK(hipMemcpyAsync(c->h_ints, c->d_ints, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         c->ncoarse = c->h_ints[0];
@@ -614,170 +794,193 @@ spfd_status do_build(Ctx *c)
             return fail(c, SPFD_INVALID_ARG, "coarsest level too large (grid cannot be coarsened further)");
         c->d_Ainv = dalloc<double>(c, c->hier_allocs, (size_t)c->ncoarse * c->ncoarse + 1);
         c->d_cwork = dalloc<int>(c, c->hier_allocs, (size_t)5 * maxd + 8);
-        HIPCHK(launch_coarse_factor(C.d_w64, C.nodes(), C.topo(), c->d_node_cdof, c->d_cdof_node, c->d_cadj, c->ncoarse,
-                                    c->d_Ainv, c->d_cwork, c->stream));
+        if (C.ell)
+            HIPCHK(launch_coarse_dense_ell(C.nrow, C.K, C.d_col, C.d_val64, c->d_node_cdof, c->d_cdof_node, c->ncoarse,
+                                           c->d_Ainv, c->stream));
+        else
+            HIPCHK(launch_coarse_assemble_brick(C.d_w64, C.nodes(), C.topo(), c->d_cdof_node, c->d_cadj, c->ncoarse,
+                                                c->d_Ainv, c->stream));
+        HIPCHK(launch_coarse_factor(c->ncoarse, c->d_Ainv, c->d_cwork, c->stream));
     }
     chebyshev_coefficients(c);
-    alloc_cycle_buffers(c);
-    c->d_part = dalloc<double>(c, c->hier_allocs, (size_t)2 * c->lv[0].nb + 64);
     HIPCHK(hipStreamSynchronize(c->stream));
     return SPFD_OK;
 }
 
 spfd_status do_set_num_rhs(Ctx *c, int nrhs)
 {
-    free_all(c, c->rhs_allocs);
-    c->d_b.assign(nrhs, nullptr);
-    c->has_source.assign(nrhs, 0);
+    free_all(c, c->src_allocs);
     const size_t n0 = (size_t)c->lv[0].nodes();
-    for (int i = 0; i < nrhs; ++i) c->d_b[i] = dalloc<double>(c, c->rhs_allocs, n0);
-    c->d_scal = dalloc<Scal>(c, c->rhs_allocs, nrhs);
+    c->d_bs = dalloc<double>(c, c->src_allocs, n0 * nrhs);
+    c->has_source.assign(nrhs, 0);
+    c->d_scal = dalloc<Scal>(c, c->src_allocs, nrhs);
+    c->d_again = dalloc<int>(c, c->src_allocs, nrhs + 1);
     HIPCHK(hipMemsetAsync(c->d_scal, 0, nrhs * sizeof(Scal), c->stream));
     if (c->h_scal) (void)hipHostFree(c->h_scal);
     c->h_scal = nullptr;
-    HIPCHK(hipHostMalloc((void **)&c->h_scal, sizeof(Scal) * nrhs, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&c->h_scal, sizeof(Scal) * (nrhs + 1), hipHostMallocDefault));
     c->nrhs = nrhs;
+    alloc_cycle_buffers(c, nrhs);
     HIPCHK(hipStreamSynchronize(c->stream));
     return SPFD_OK;
 }
 
 template <typename T>
-void pcg_iterations(Ctx *c, int rhs, const spfd_solve_options &so)
+void pcg_iterations(Ctx *c, Scal *sc, Scal *hsc, int nb, const spfd_solve_options &so)
 {
     Level &L0 = c->lv[0];
     const Topo topo = L0.topo();
     const OpArgs<double> op = level_op<double>(c, 0);
-    Scal *sc = c->d_scal + rhs;
+    const Batch bt = level_batch(c, 0, nb);
     T *z = (T *)c->d_z;
-    const double n0 = (double)L0.dofs;
+    const double n0 = (double)L0.dofs * nb;
     const double wz = sizeof(T);
-    vcycle<T>(c, c->d_r, z, sc);
+    vcycle<T>(c, c->d_r, z, sc, nb);
     {
         TScope ts(c, SPFD_K_DOTS, n0 * (wz + 8.0));
-        HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 1, c->stream));
+        HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 1, bt, c->stream));
     }
-    finish(c, topo.nb, FIN_BETA0, sc, 0);
+    finish(c, topo.nb, FIN_BETA0, sc, 0, nb);
     {
         TScope ts(c, SPFD_K_PUPDATE, n0 * (wz + 8.0));
-        HIPCHK(launch_pupdate<T>(topo, z, c->d_p, sc, 1, c->stream));
+        HIPCHK(launch_pupdate<T>(topo, z, c->d_p, sc, 1, bt, c->stream));
     }
-    const int chunk = 1;
-    for (int it = 0; it < so.max_iter + 1; it += chunk) {
-        for (int k = 0; k < chunk; ++k) {
-            {
-                TScope ts(c, SPFD_K_SPMV, n0 * (16.0 + op_bytes<double>(c, 0)));
-                HIPCHK(launch_spmv_dot(op, topo, c->d_p, c->d_q, c->d_part, sc, c->stream));
-            }
-            finish(c, topo.nb, FIN_ALPHA, sc, 0);
-            {
-                TScope ts(c, SPFD_K_UPDATE, n0 * 48.0);
-                HIPCHK(launch_update(topo, c->d_x, c->d_r, c->d_p, c->d_q, c->d_part, sc, so.max_iter, c->stream));
-            }
-            finish(c, topo.nb, FIN_RR, sc, so.max_iter);
-            vcycle<T>(c, c->d_r, z, sc);
-            {
-                TScope ts(c, SPFD_K_DOTS, n0 * (wz + 16.0));
-                HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 0, c->stream));
-            }
-            finish(c, topo.nb, FIN_BETA, sc, 0);
-            {
-                TScope ts(c, SPFD_K_PUPDATE, n0 * (wz + 16.0));
-                HIPCHK(launch_pupdate<T>(topo, z, c->d_p, sc, 0, c->stream));
-            }
+    for (int it = 0; it < so.max_iter + 1; ++it) {
+        {
+            TScope ts(c, SPFD_K_SPMV, n0 * (16.0 + op_bytes<double>(c, 0)));
+            HIPCHK(launch_spmv_dot(op, topo, c->d_p, c->d_q, c->d_part, sc, bt, c->stream));
         }
-        HIPCHK(hipMemcpyAsync(c->h_scal + rhs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+        finish(c, topo.nb, FIN_ALPHA, sc, 0, nb);
+        {
+            TScope ts(c, SPFD_K_UPDATE, n0 * 48.0);
+            HIPCHK(launch_update(topo, c->d_x, c->d_r, c->d_p, c->d_q, c->d_part, sc, bt, c->stream));
+        }
+        finish(c, topo.nb, FIN_RR, sc, so.max_iter, nb);
+        vcycle<T>(c, c->d_r, z, sc, nb);
+        {
+            TScope ts(c, SPFD_K_DOTS, n0 * (wz + 16.0));
+            HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 0, bt, c->stream));
+        }
+        finish(c, topo.nb, FIN_BETA, sc, 0, nb);
+        {
+            TScope ts(c, SPFD_K_PUPDATE, n0 * (wz + 16.0));
+            HIPCHK(launch_pupdate<T>(topo, z, c->d_p, sc, 0, bt, c->stream));
+        }
+        HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        if (c->h_scal[rhs].done) break;
+        bool all = true;
+        for (int i = 0; i < nb; ++i) all = all && hsc[i].done;
+        if (all) break;
     }
 }
 
-void resid(Ctx *c, int rhs, double *r, int mode)
+// r = b - A x for the batch and ||r||^2 (mode 0: start of a warm-started solve,
+// mode 1: true residual kept in zq)
+void resid_b(Ctx *c, const double *b, long long bvs, Scal *sc, double *r, int mode, int nb)
 {
     Level &L0 = c->lv[0];
     {
-        TScope ts(c, SPFD_K_SPMV, (double)L0.dofs * (16.0 + (r ? 8.0 : 0.0) + op_bytes<double>(c, 0)));
-        HIPCHK(launch_resid(level_op<double>(c, 0), L0.topo(), c->d_b[rhs], c->d_x, r, c->d_part, c->d_scal + rhs, mode,
+        TScope ts(c, SPFD_K_SPMV, nb * (double)L0.dofs * (16.0 + (r ? 8.0 : 0.0) + op_bytes<double>(c, 0)));
+        HIPCHK(launch_resid(level_op<double>(c, 0), L0.topo(), b, c->d_x, r, c->d_part, bvs, level_batch(c, 0, nb),
                             c->stream));
     }
-    finish(c, L0.nb, mode == 0 ? FIN_RESID0 : FIN_RESID1, c->d_scal + rhs, 0);
+    finish(c, L0.nb, mode == 0 ? FIN_RESID0 : FIN_RESID1, sc, 0, nb);
 }
 
-__global__ void k_rearm(Scal *sc, double tol2, int keep_iters)
+
+__global__ void k_rearm_if(Scal *sc, double tol, int nb, const int *again)
 {
-    if (threadIdx.x == 0) {
-        sc->done = 0;
-        sc->status = 0;
-        sc->tol2 = tol2;
-        if (!keep_iters) sc->iters = 0;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb && again[i]) {
+        sc[i].done = 0;
+        sc[i].status = 0;
+        sc[i].tol2 = tol * tol * sc[i].bb;
     }
 }
 
-spfd_status do_solve(Ctx *c, const spfd_solve_options &so, double *psi, spfd_rhs_info *info)
+// Solve A x = b for a batch of nb right sides b[i] = b + i*bvs (brick layout,
+// FP64) whose scalars (with ||b||^2 from the right-side kernel) live in sc[i];
+// write the gauged solutions as dense node arrays psi + i*nn (also the start
+// iterates when use_x0).  Uses the handle's solve buffers (nb <= nbat).
+spfd_status solve_batch(Ctx *c, const double *b, long long bvs, Scal *sc, Scal *hsc, int nb,
+                        const spfd_solve_options &so, double *psi, spfd_rhs_info *info)
 {
     Level &L0 = c->lv[0];
     const Topo topo = L0.topo();
     const long long n0 = L0.nodes();
     const bool mixed = c->opt.precision == SPFD_MIXED;
     const long long nn = (long long)c->g.Nx * c->g.Ny * c->g.Nz;
-    spfd_status worst = SPFD_OK;
-    for (int rhs = 0; rhs < c->nrhs; ++rhs) {
-        Scal *sc = c->d_scal + rhs;
-        double *psi_r = psi + (long long)rhs * nn;
-        // start: x0 = 0 (r = b) or the caller's iterate (r = b - A x0)
-        HIPCHK(launch_scal_init(sc, so.rel_tol, so.use_x0, c->stream));
-        if (so.use_x0) {
-            HIPCHK(launch_psi_in(psi_r, c->d_comp, L0.d_coord, L0.nb, c->g, c->d_x, c->stream));
-            resid(c, rhs, c->d_r, 0);
-        } else {
-            HIPCHK(hipMemsetAsync(c->d_x, 0, n0 * sizeof(double), c->stream));
-            HIPCHK(hipMemcpyAsync(c->d_r, c->d_b[rhs], n0 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        }
-        HIPCHK(hipMemcpyAsync(c->h_scal + rhs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        const double bb = c->h_scal[rhs].bb;
-        double relres = 0.0;
-        int status = 0, iters = 0;
-        if (bb > 0.0 && !c->h_scal[rhs].done) {
-            for (int pass = 0; pass < 3; ++pass) {
-                if (mixed)
-                    pcg_iterations<float>(c, rhs, so);
-                else
-                    pcg_iterations<double>(c, rhs, so);
-                // true residual of the iterate
-                resid(c, rhs, c->d_r, 1);
-                HIPCHK(hipMemcpyAsync(c->h_scal + rhs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
-                HIPCHK(hipStreamSynchronize(c->stream));
-                const Scal &hs = c->h_scal[rhs];
-                relres = sqrt(hs.zq / bb);
-                status = hs.status;
-                iters = hs.iters;
-                if (status != 0 || relres <= so.rel_tol || iters >= so.max_iter) break;
-                // the recursive residual drifted from the true one: restart from the true residual
-                hipLaunchKernelGGL(k_rearm, dim3(1), dim3(64), 0, c->stream, sc, so.rel_tol * so.rel_tol * bb, 1);
-                HIPCHK(hipGetLastError());
-            }
-            if (status == 0 && relres > so.rel_tol) status = SPFD_NOT_CONVERGED;
-        } else if (bb > 0.0) {
-            // the start iterate already satisfies the criterion
-            resid(c, rhs, nullptr, 1);
-            HIPCHK(hipMemcpyAsync(c->h_scal + rhs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(hipStreamSynchronize(c->stream));
-            relres = sqrt(c->h_scal[rhs].zq / bb);
-        }
-        // gauge: zero mean per connected component, 0 outside the conductor
-        {
-            TScope ts(c, SPFD_K_GAUGE, (double)L0.dofs * (12.0 * (c->ncomp < 16 ? c->ncomp : 1) + 12.0) + nn * 8.0);
-            HIPCHK(launch_comp_mean(topo, c->d_x, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_part, c->stream));
-            HIPCHK(launch_psi_out(c->d_x, c->d_comp, c->d_means, L0.d_slot_of, c->g, psi_r, c->stream));
-        }
-        HIPCHK(hipStreamSynchronize(c->stream));
-        if (info) {
-            info[rhs].iterations = iters;
-            info[rhs].rel_residual = relres;
-            info[rhs].status = status;
-        }
-        if (status != 0 && worst == SPFD_OK) worst = (spfd_status)status;
+    HIPCHK(launch_scal_init(sc, so.rel_tol, so.use_x0, nb, c->stream));
+    if (so.use_x0) {
+        for (int i = 0; i < nb; ++i)
+            HIPCHK(launch_psi_in(psi + i * nn, c->d_comp, L0.d_coord, L0.nb, c->g, c->d_x + i * n0, c->stream));
+        resid_b(c, b, bvs, sc, c->d_r, 0, nb);
+    } else {
+        HIPCHK(hipMemsetAsync(c->d_x, 0, nb * n0 * sizeof(double), c->stream));
+        for (int i = 0; i < nb; ++i)
+            HIPCHK(hipMemcpyAsync(c->d_r + i * n0, b + i * bvs, n0 * sizeof(double), hipMemcpyDeviceToDevice,
+                                  c->stream));
     }
+    HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::vector<double> bb(nb), relres(nb, 0.0);
+    std::vector<int> status(nb, 0), iters(nb, 0);
+    bool any = false;
+    for (int i = 0; i < nb; ++i) {
+        bb[i] = hsc[i].bb;
+        any = any || !hsc[i].done;
+    }
+    int *again = c->d_again;
+    for (int pass = 0; pass < 3 && any; ++pass) {
+        if (mixed)
+            pcg_iterations<float>(c, sc, hsc, nb, so);
+        else
+            pcg_iterations<double>(c, sc, hsc, nb, so);
+        // true residual of every iterate (also of those that converged in an earlier pass)
+        resid_b(c, b, bvs, sc, c->d_r, 1, nb);
+        HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        any = false;
+        std::vector<int> redo(nb, 0);
+        for (int i = 0; i < nb; ++i) {
+            relres[i] = bb[i] > 0.0 ? sqrt(hsc[i].zq / bb[i]) : 0.0;
+            status[i] = hsc[i].status;
+            iters[i] = hsc[i].iters;
+            // the recursive residual drifted from the true one: restart from the true residual
+            if (bb[i] > 0.0 && status[i] == 0 && relres[i] > so.rel_tol && iters[i] < so.max_iter && pass < 2) {
+                redo[i] = 1;
+                any = true;
+            }
+        }
+        if (any) {
+            HIPCHK(hipMemcpyAsync(again, redo.data(), nb * sizeof(int), hipMemcpyHostToDevice, c->stream));
+            hipLaunchKernelGGL(k_rearm_if, dim3(1), dim3(64), 0, c->stream, sc, so.rel_tol, nb, again);
+            HIPCHK(hipGetLastError());
+        }
+    }
+    spfd_status worst = SPFD_OK;
+    for (int i = 0; i < nb; ++i) {
+        if (bb[i] > 0.0 && status[i] == 0 && relres[i] > so.rel_tol) status[i] = SPFD_NOT_CONVERGED;
+        if (status[i] != 0 && worst == SPFD_OK) worst = (spfd_status)status[i];
+        // gauge: zero mean per connected component, 0 outside the conductor
+        TScope ts(c, SPFD_K_GAUGE, (double)L0.dofs * (12.0 * (c->ncomp < 16 ? c->ncomp : 1) + 12.0) + nn * 8.0);
+        HIPCHK(launch_comp_mean(topo, c->d_x + i * n0, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_part,
+                                c->stream));
+        HIPCHK(launch_psi_out(c->d_x + i * n0, c->d_comp, c->d_means, L0.d_slot_of, c->g, psi + i * nn, c->stream));
+        if (info) {
+            info[i].iterations = iters[i];
+            info[i].rel_residual = relres[i];
+            info[i].status = status[i];
+        }
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return worst;
+}
+
+spfd_status do_solve(Ctx *c, const spfd_solve_options &so, double *psi, spfd_rhs_info *info)
+{
+    const long long n0 = c->lv[0].nodes();
+    spfd_status worst = solve_batch(c, c->d_bs, n0, c->d_scal, c->h_scal, c->nrhs, so, psi, info);
     if (worst != SPFD_OK)
         c->err = worst == SPFD_BREAKDOWN ? "breakdown in CG (non-positive curvature or non-finite value)"
                                          : "maximum iteration count reached";
@@ -860,6 +1063,8 @@ spfd_status spfd_set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, 
         free_all(h, h->rhs_allocs);
         free_all(h, h->hier_allocs);
         free_all(h, h->geo_allocs);
+        h->d_adj_b = h->d_adj_c = h->d_adj_lam = h->d_adj_labpart = h->d_adj_labout = nullptr;
+        h->d_adj_scal = nullptr;
         h->d_ints = dalloc<int>(h, h->geo_allocs, 64);
         h->lv.clear();
         h->g.nx = nx; h->g.ny = ny; h->g.nz = nz;
@@ -984,8 +1189,8 @@ spfd_status spfd_set_source(spfd_handle h, int rhs, const double *a)
         HIPCHK(hipMemsetAsync(h->d_scal + rhs, 0, sizeof(Scal), h->stream));
         {
             TScope ts(h, SPFD_K_RHS, (double)L0.dofs * (24.0 + 8.0 + op_bytes<double>(h, 0)));
-            HIPCHK(launch_rhs(level_op<double>(h, 0), L0.topo(), L0.d_coord, h->g, a, h->d_b[rhs], h->d_part,
-                              h->d_scal + rhs, h->stream));
+            HIPCHK(launch_rhs(level_op<double>(h, 0), L0.topo(), L0.d_coord, h->g, a, h->d_bs + rhs * L0.nodes(),
+                              h->d_part, h->d_scal + rhs, h->stream));
         }
         finish(h, L0.nb, FIN_BB, h->d_scal + rhs, 0);
         HIPCHK(hipMemcpyAsync(h->h_scal + rhs, h->d_scal + rhs, sizeof(Scal), hipMemcpyDeviceToHost, h->stream));
@@ -1041,6 +1246,66 @@ spfd_status spfd_efield(spfd_handle h, double omega, const double *a, const doub
         }
         HIPCHK(hipStreamSynchronize(h->stream));
         return SPFD_OK;
+    }
+    API_GUARD(h)
+}
+
+spfd_status spfd_adjoint(spfd_handle h, double omega, const double *a, const double *psi, const double *grad_emag,
+                         const spfd_solve_options *opt, double *grad_sigma_voxel, double *grad_sigma_table,
+                         spfd_rhs_info *info)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (h->state < 3) return fail(h, SPFD_BAD_STATE, "build first");
+    if (!a || !psi || !grad_emag || !grad_sigma_voxel)
+        return fail(h, SPFD_INVALID_ARG, "a, psi, grad_emag and grad_sigma_voxel are required");
+    if (!isfinite(omega)) return fail(h, SPFD_INVALID_ARG, "omega must be finite");
+    spfd_solve_options so{};
+    so.rel_tol = 1e-8;
+    so.max_iter = 500;
+    if (opt) so = *opt;
+    so.use_x0 = 0;
+    if (!(so.rel_tol > 0.0) || !isfinite(so.rel_tol)) return fail(h, SPFD_INVALID_ARG, "rel_tol must be positive");
+    if (so.max_iter <= 0) return fail(h, SPFD_INVALID_ARG, "max_iter must be positive");
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        Level &L0 = h->lv[0];
+        const Grid &g = h->g;
+        const long long nvox = (long long)g.nx * g.ny * g.nz;
+        const long long nn = (long long)g.Nx * g.Ny * g.Nz;
+        const int nlab = h->voxel_mode ? MAX_LABELS : h->nlab;
+        const int gb = adj_grad_blocks(g);
+        if (!h->d_adj_b) {
+            h->d_adj_b = dalloc<double>(h, h->hier_allocs, L0.nodes());
+            h->d_adj_c = dalloc<double>(h, h->hier_allocs, 3 * nvox);
+            h->d_adj_lam = dalloc<double>(h, h->hier_allocs, nn);
+            h->d_adj_labpart = dalloc<double>(h, h->hier_allocs, (size_t)gb * MAX_LABELS);
+            h->d_adj_labout = dalloc<double>(h, h->hier_allocs, MAX_LABELS);
+            h->d_adj_scal = dalloc<Scal>(h, h->hier_allocs, 1);
+        }
+        const double *sv = h->voxel_mode ? h->d_sigvox : nullptr;
+        HIPCHK(hipMemsetAsync(h->d_adj_scal, 0, sizeof(Scal), h->stream));
+        {
+            TScope ts(h, SPFD_K_RHS, (double)nvox * (1.0 + 8.0 + 24.0) + (double)L0.dofs * (32.0 + 24.0 + 8.0));
+            HIPCHK(launch_adj_voxel(h->d_labels, h->d_table64, sv, g, h->h, omega, a, psi, grad_emag, h->d_adj_c,
+                                    h->stream));
+            HIPCHK(launch_adj_rhs(L0.topo(), L0.d_coord, g, h->d_adj_c, h->d_adj_b, h->d_part, h->stream));
+        }
+        finish(h, L0.nb, FIN_BB, h->d_adj_scal, 0);
+        spfd_rhs_info inf{};
+        spfd_status st = solve_batch(h, h->d_adj_b, 0, h->d_adj_scal, h->h_scal + h->nrhs, 1, so, h->d_adj_lam, &inf);
+        {
+            TScope ts(h, SPFD_K_EFIELD, (double)nvox * (1.0 + 8.0) + (double)L0.dofs * (8.0 + 8.0 + 24.0));
+            HIPCHK(launch_adj_grad(h->d_labels, h->d_table64, sv, g, h->geo4, a, psi, h->d_adj_lam, grad_sigma_voxel,
+                                   h->d_adj_labpart, nlab, h->d_adj_labout, h->stream));
+        }
+        if (grad_sigma_table)
+            HIPCHK(hipMemcpyAsync(grad_sigma_table, h->d_adj_labout, nlab * sizeof(double), hipMemcpyDeviceToHost,
+                                  h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (info) *info = inf;
+        if (st != SPFD_OK)
+            h->err = st == SPFD_BREAKDOWN ? "breakdown in the adjoint CG" : "adjoint solve did not converge";
+        return st;
     }
     API_GUARD(h)
 }

@@ -19,6 +19,16 @@ struct OpArgs {
     T geo4[3];               // dual area / length / 4 per direction
 };
 
+// A batch of right sides solved together: launch grids get a y-dimension of
+// n, and block y offsets every vector by vs (the level's stride; vsc for the
+// coarser level's vectors), the partial sums by ps and the scalars by one Scal.
+struct Batch {
+    int n;
+    long long vs;
+    long long vsc;
+    int ps;
+};
+
 struct Grid {
     int nx, ny, nz;          // voxels
     int Nx, Ny, Nz;          // nodes
@@ -40,8 +50,10 @@ hipError_t launch_components(const double *w64, long long stride, Topo topo, int
 hipError_t launch_comp_counts(const int *comp, long long n, int *counts, hipStream_t s);
 hipError_t launch_coarse_setup(const double *w64, long long stride, Topo topo, int *dof_of_node, int *node_of_dof,
                                int *adj, int *ndof_dev, int maxdof, hipStream_t s);
-hipError_t launch_coarse_factor(const double *w64, long long stride, Topo topo, const int *dof_of_node,
-                                const int *node_of_dof, int *adj, int n, double *A, int *work, hipStream_t s);
+hipError_t launch_coarse_assemble_brick(const double *w64, long long stride, Topo topo, const int *node_of_dof,
+                                        const int *adj, int n, double *A, hipStream_t s);
+// dense pseudo-inverse in place; work: 2n ints + n doubles (+1 int of padding)
+hipError_t launch_coarse_factor(int n, double *A, int *work, hipStream_t s);
 
 // ---------------------------------------------------------------- solve
 // Reductions are two-stage: a producer kernel stores one partial per brick
@@ -58,41 +70,46 @@ enum {
     FIN_MEAN = 7      // mean of one component
 };
 hipError_t launch_finish(const double *part, int n, int mode, Scal *sc, int max_iter, hipStream_t s,
-                         double *means = nullptr, const int *counts = nullptr, int comp = 0);
+                         double *means = nullptr, const int *counts = nullptr, int comp = 0, int nbatch = 1,
+                         int ps = 0);
 
 template <typename T>
 hipError_t launch_fill(T *x, long long n, T v, hipStream_t s);
 
 hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, const Grid &g, const double *a,
                       double *b, double *part, Scal *sc, hipStream_t s);
-hipError_t launch_scal_init(Scal *sc, double tol, int use_x0, hipStream_t s);
+hipError_t launch_scal_init(Scal *sc, double tol, int use_x0, int nbatch, hipStream_t s);
 hipError_t launch_spmv_dot(const OpArgs<double> &op, Topo topo, const double *p, double *q, double *part,
-                           Scal *sc, hipStream_t s);
+                           Scal *sc, const Batch &bt, hipStream_t s);
 hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const double *q, double *part,
-                         Scal *sc, int max_iter, hipStream_t s);
+                         Scal *sc, const Batch &bt, hipStream_t s);
+// b has its own batch stride bvs (the right sides may live apart from the solve vectors)
 hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,
-                        double *part, Scal *sc, int mode, hipStream_t s);
+                        double *part, long long bvs, const Batch &bt, hipStream_t s);
 template <typename TZ>
 hipError_t launch_dots(Topo topo, const TZ *z, const double *r, const double *q, double *part, Scal *sc,
-                       int first, hipStream_t s);
+                       int first, const Batch &bt, hipStream_t s);
 template <typename TZ>
-hipError_t launch_pupdate(Topo topo, const TZ *z, double *p, const Scal *sc, int first, hipStream_t s);
+hipError_t launch_pupdate(Topo topo, const TZ *z, double *p, const Scal *sc, int first, const Batch &bt,
+                          hipStream_t s);
 
 // multigrid level kernels (T = arithmetic of the cycle, TB = type of the level's right side)
 template <typename T, typename TB>
-hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, T c0, const Scal *sc, hipStream_t s);
+hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, T c0, const Scal *sc,
+                             const Batch &bt, hipStream_t s);
 template <typename T, typename TB>
 hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din,
-                            T *dout, T c1, T c2, const Scal *sc, hipStream_t s);
+                            T *dout, T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s);
 template <typename T, typename TB>
 hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, const T *x, T *bc,
-                                 const int *parent_slot, const int4 *fcoord, const Scal *sc, hipStream_t s);
+                                 const int *parent_slot, const int4 *fcoord, const Scal *sc, const Batch &bt,
+                                 hipStream_t s);
 template <typename T>
 hipError_t launch_prolong(Topo topo, T *x, const T *xc, const int *parent_slot, const int4 *fcoord, T scale,
-                          const Scal *sc, hipStream_t s);
+                          const Scal *sc, const Batch &bt, hipStream_t s);
 template <typename T, typename TB>
 hipError_t launch_coarse_apply(const TB *bc, T *xc, const double *Ainv, const int *node_of_dof, int n,
-                               const Scal *sc, hipStream_t s);
+                               const Scal *sc, const Batch &bt, hipStream_t s);
 
 // ---------------------------------------------------------------- gauge, output, post-processing
 hipError_t launch_comp_mean(Topo topo, const double *x, const int *comp, int ncomp, const int *counts,
@@ -106,5 +123,68 @@ hipError_t launch_efield(const uint8_t *labels, const double *table, const doubl
                          hipStream_t s);
 hipError_t launch_uedges(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,
                          const double *a, const double *psi, double *u, hipStream_t s);
+
+// ---------------------------------------------------------------- unstructured (ELL) coarse levels
+// A fine level for the Galerkin product and the restriction: structured
+// (w != nullptr: stored weights of a brick level) or ELL (col/val, n rows, width K).
+struct FineLevelArgs {
+    const double *w;
+    long long stride;
+    const int *nbr;
+    int n, K;
+    const int *col;
+    const double *val;
+};
+template <typename T>
+struct FineLevelT {
+    const T *w;
+    long long stride;
+    const int *nbr;
+    int n, K;
+    const int *col;
+    const T *val;
+};
+// pieces = connected parts of each 2x2x2 aggregate; parent = union-find forest
+hipError_t launch_pieces_brick(const double *w64, long long stride, Topo topo, const int4 *coord, int *parent,
+                               hipStream_t s);
+hipError_t launch_pieces_ell(int n, int K, const int *col, const double *val, const int4 *pos, int *parent,
+                             hipStream_t s);
+hipError_t launch_pieces_finish(int *parent, long long n, int *flag, hipStream_t s);
+hipError_t launch_pieces_assign(const int *parent, const int *idx, long long n, int *agg, int *count, hipStream_t s);
+hipError_t launch_piece_pos_brick(const int *parent, const int *idx, Topo topo, const int4 *coord, int4 *pos,
+                                  hipStream_t s);
+hipError_t launch_piece_pos_ell(int n, const int *parent, const int *idx, const int4 *fpos, int4 *pos, hipStream_t s);
+hipError_t launch_members(const int *agg, long long n, int nc, const int *mptr, int *cursor, int *mem, hipStream_t s);
+hipError_t launch_galerkin_ell(const FineLevelArgs &fa, const int *agg, int nc, const int *mptr, const int *mem,
+                               int pass, int *len, int K, int *col, double *val64, float *val32, int *overflow,
+                               int *maxlen, hipStream_t s);
+hipError_t scan_exclusive_ints(const int *in, long long n, int *out, int *tmp, int *total, hipStream_t s);
+template <typename T>
+hipError_t launch_ell_cheb_first(int n, int K, const int *col, const T *val, const T *b, T *x, T c0, const Scal *sc,
+                                 const Batch &bt, hipStream_t s);
+template <typename T>
+hipError_t launch_ell_cheb_step(int n, int K, const int *col, const T *val, const T *b, const T *xin, T *xout,
+                                const T *din, T *dout, T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s);
+template <typename T>
+hipError_t launch_restrict_members(const FineLevelT<T> &f, const T *b, const T *x, int nc, const int *mptr,
+                                   const int *mem, T *bc, const Scal *sc, const Batch &bt, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_agg(long long n, const int *agg, T *x, const T *xc, T scale, const Scal *sc,
+                              const Batch &bt, hipStream_t s);
+hipError_t launch_coarse_enum_ell(int n, int K, const int *col, const double *val, int *dof_of_row, int *row_of_dof,
+                                  int *ndof, int maxdof, hipStream_t s);
+hipError_t launch_coarse_dense_ell(int nrow, int K, const int *col, const double *val, const int *dof_of_row,
+                                   const int *row_of_dof, int n, double *A, hipStream_t s);
+
+// ---------------------------------------------------------------- adjoint gradient
+hipError_t launch_adj_voxel(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,
+                            const double h[3], double omega, const double *a, const double *psi,
+                            const double *grad_emag, double *c, hipStream_t s);
+hipError_t launch_adj_rhs(Topo topo, const int4 *coord, const Grid &g, const double *c, double *b, double *part,
+                          hipStream_t s);
+int adj_grad_blocks(const Grid &g);
+hipError_t launch_adj_grad(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,
+                           const double geo4[3], const double *a, const double *psi, const double *lam, double *grad,
+                           double *lab_part, int nlab, double *lab_out, hipStream_t s);
 
 }  // namespace spfd

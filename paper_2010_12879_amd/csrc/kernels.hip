@@ -388,6 +388,11 @@ static hipError_t scan_exclusive(const int *in, long long n, int *out, int *bsum
     return hipGetLastError();
 }
 
+hipError_t scan_exclusive_ints(const int *in, long long n, int *out, int *tmp, int *total, hipStream_t s)
+{
+    return scan_exclusive(in, n, out, tmp, total, s);
+}
+
 __global__ void k_cc_assign(const int *__restrict__ parent, const int *__restrict__ idx, long long n, int *comp)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
@@ -513,22 +518,12 @@ hipError_t launch_coarse_setup(const double *w64, long long stride, Topo topo, i
     return hipGetLastError();
 }
 
-// Dense pseudo-inverse of the coarsest (singular) operator: A_c + sum over
-// components c of alpha_c 1_c 1_c^T is SPD, and for a right side orthogonal to
-// every 1_c its solution has zero mean per component, i.e. equals A_c^+ r.
-// One workgroup: assemble, label components, regularise, invert in place by
-// Gauss-Jordan elimination (no pivoting needed for an SPD matrix).
-// work: 3*n ints + n doubles (column buffer).
-__global__ void k_coarse_factor(const double *__restrict__ w, long long stride, Topo topo,
-                                const int *__restrict__ node_of_dof, const int *__restrict__ adj, int n, double *A,
-                                int *work)
+// Dense matrix of the coarsest structured level over its unknowns (row-major n x n).
+__global__ void k_coarse_assemble_brick(const double *__restrict__ w, long long stride, Topo topo,
+                                        const int *__restrict__ node_of_dof, const int *__restrict__ adj, int n,
+                                        double *A)
 {
     const int t = threadIdx.x, nt = blockDim.x;
-    int *comp = work;
-    int *csize = work + n;
-    double *colk = (double *)(work + 3 * n + (3 * n & 1));
-    __shared__ int changed;
-    __shared__ double piv;
     for (long long e = t; e < (long long)n * n; e += nt) A[e] = 0.0;
     __syncthreads();
     for (int q = t; q < n; q += nt) {
@@ -549,23 +544,39 @@ __global__ void k_coarse_factor(const double *__restrict__ w, long long stride, 
             }
         }
         A[(long long)q * n + q] += d;
+    }
+}
+
+// Dense pseudo-inverse of the coarsest (singular) operator, in place: A_c +
+// sum over components c of alpha_c 1_c 1_c^T is SPD, and for a right side
+// orthogonal to every 1_c its solution has zero mean per component, i.e.
+// equals A_c^+ r.  One workgroup: components by min-label propagation over
+// the nonzeros, regularisation with alpha_c = mean diagonal / size^2, and
+// Gauss-Jordan inversion (no pivoting needed for an SPD matrix).
+// work: 2n ints + n doubles.
+__global__ void k_coarse_factor(int n, double *A, int *work)
+{
+    const int t = threadIdx.x, nt = blockDim.x;
+    int *comp = work;
+    int *csize = work + n;
+    double *colk = (double *)(work + 2 * n + ((2 * n) & 1));
+    __shared__ int changed;
+    __shared__ double piv;
+    for (int q = t; q < n; q += nt) {
         comp[q] = q;
         csize[q] = 0;
     }
     __syncthreads();
-    // components: min-label propagation over the stencil graph
     do {
         __syncthreads();
         if (t == 0) changed = 0;
         __syncthreads();
         for (int q = t; q < n; q += nt) {
             int c = comp[q];
-            for (int k = 0; k < 6; ++k) {
-                const int m = adj[q * 6 + k];
-                if (m >= 0) {
-                    const int cm = __hip_atomic_load(comp + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if (cm < c) c = cm;
-                }
+            for (int m = 0; m < n; ++m) {
+                if (m == q || A[(long long)q * n + m] == 0.0) continue;
+                const int cm = __hip_atomic_load(comp + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (cm < c) c = cm;
             }
             if (c < comp[q]) {
                 __hip_atomic_store(comp + q, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -576,8 +587,7 @@ __global__ void k_coarse_factor(const double *__restrict__ w, long long stride, 
     } while (changed);
     for (int q = t; q < n; q += nt) atomicAdd(csize + comp[q], 1);
     __syncthreads();
-    // mean diagonal per component (serial per component root, small n)
-    double *cdiag = colk;  // reuse as scratch
+    double *cdiag = colk;  // scratch before the elimination
     for (int q = t; q < n; q += nt) cdiag[q] = 0.0;
     __syncthreads();
     if (t == 0)
@@ -592,7 +602,6 @@ __global__ void k_coarse_factor(const double *__restrict__ w, long long stride, 
         }
     }
     __syncthreads();
-    // in-place Gauss-Jordan inversion
     for (int k = 0; k < n; ++k) {
         if (t == 0) piv = 1.0 / A[(long long)k * n + k];
         __syncthreads();
@@ -612,12 +621,18 @@ __global__ void k_coarse_factor(const double *__restrict__ w, long long stride, 
     }
 }
 
-hipError_t launch_coarse_factor(const double *w64, long long stride, Topo topo, const int *dof_of_node,
-                                const int *node_of_dof, int *adj, int n, double *A, int *work, hipStream_t s)
+hipError_t launch_coarse_assemble_brick(const double *w64, long long stride, Topo topo, const int *node_of_dof,
+                                        const int *adj, int n, double *A, hipStream_t s)
 {
-    (void)dof_of_node;
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coarse_factor, dim3(1), dim3(1024), 0, s, w64, stride, topo, node_of_dof, adj, n, A, work);
+    hipLaunchKernelGGL(k_coarse_assemble_brick, dim3(1), dim3(1024), 0, s, w64, stride, topo, node_of_dof, adj, n, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_factor(int n, double *A, int *work, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coarse_factor, dim3(1), dim3(1024), 0, s, n, A, work);
     return hipGetLastError();
 }
 
@@ -648,6 +663,7 @@ template hipError_t launch_fill<int>(int *, long long, int, hipStream_t);
 __global__ void k_scal_init(Scal *sc, double tol, int use_x0)
 {
     (void)use_x0;
+    sc += blockIdx.x;
     if (threadIdx.x == 0) {
         const double bb = sc->bb;
         sc->rz = 0.0; sc->pq = 0.0; sc->alpha = 0.0; sc->beta = 0.0; sc->zq = 0.0;
@@ -658,9 +674,9 @@ __global__ void k_scal_init(Scal *sc, double tol, int use_x0)
     }
 }
 
-hipError_t launch_scal_init(Scal *sc, double tol, int use_x0, hipStream_t s)
+hipError_t launch_scal_init(Scal *sc, double tol, int use_x0, int nbatch, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scal_init, dim3(1), dim3(64), 0, s, sc, tol, use_x0);
+    hipLaunchKernelGGL(k_scal_init, dim3(nbatch), dim3(64), 0, s, sc, tol, use_x0);
     return hipGetLastError();
 }
 
@@ -686,9 +702,11 @@ __device__ __forceinline__ double block_sum_any(double v, double *lds)
 }
 
 __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part, int n, int mode, Scal *sc,
-                                                 int max_iter, double *means, const int *counts, int comp)
+                                                 int max_iter, double *means, const int *counts, int comp, int ps)
 {
     __shared__ double red[16];
+    part += (long long)blockIdx.x * ps;
+    if (sc) sc += blockIdx.x;
     if (mode == FIN_ALPHA || mode == FIN_RR || mode == FIN_BETA0 || mode == FIN_BETA)
         if (sc->done) return;
     double a = 0.0, b = 0.0;
@@ -755,9 +773,9 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
 }
 
 hipError_t launch_finish(const double *part, int n, int mode, Scal *sc, int max_iter, hipStream_t s, double *means,
-                         const int *counts, int comp)
+                         const int *counts, int comp, int nbatch, int ps)
 {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, part, n, mode, sc, max_iter, means, counts, comp);
+    hipLaunchKernelGGL(k_finish, dim3(nbatch), dim3(1024), 0, s, part, n, mode, sc, max_iter, means, counts, comp, ps);
     return hipGetLastError();
 }
 
@@ -812,11 +830,16 @@ hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, co
 
 // q = A p and the partials of p.q (alpha follows in k_finish)
 __global__ __launch_bounds__(NT) void k_spmv_dot(OpArgs<double> op, Topo topo, const double *__restrict__ p,
-                                                 double *__restrict__ q, double *part, const Scal *sc)
+                                                 double *__restrict__ q, double *part, const Scal *sc, long long vs,
+                                                 int ps)
 {
     __shared__ double tile[TILE_VOX + 7];
     __shared__ double red[8];
+    sc += blockIdx.y;
     if (sc->done) return;
+    p += blockIdx.y * vs;
+    q += blockIdx.y * vs;
+    part += (long long)blockIdx.y * ps;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
     int nb[6];
@@ -840,22 +863,29 @@ __global__ __launch_bounds__(NT) void k_spmv_dot(OpArgs<double> op, Topo topo, c
 }
 
 hipError_t launch_spmv_dot(const OpArgs<double> &op, Topo topo, const double *p, double *q, double *part, Scal *sc,
-                           hipStream_t s)
+                           const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spmv_dot, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, p, q, part, sc);
+    hipLaunchKernelGGL(k_spmv_dot, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, p, q, part, sc, bt.vs,
+                       bt.ps);
     return hipGetLastError();
 }
 
 // x += alpha p, r -= alpha q and the partials of ||r||^2 (stop test in k_finish)
 __global__ __launch_bounds__(NT) void k_update(Topo topo, double *__restrict__ x, double *__restrict__ r,
                                                const double *__restrict__ p, const double *__restrict__ q,
-                                               double *part, const Scal *sc)
+                                               double *part, const Scal *sc, long long vs, int ps)
 {
     __shared__ double red[8];
+    sc += blockIdx.y;
     if (sc->done) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
+    x += blockIdx.y * vs;
+    r += blockIdx.y * vs;
+    p += blockIdx.y * vs;
+    q += blockIdx.y * vs;
+    part += (long long)blockIdx.y * ps;
     const double alpha = sc->alpha;
     const long long n = (long long)bk * BS + threadIdx.x;
     x[n] += alpha * p[n];
@@ -866,22 +896,28 @@ __global__ __launch_bounds__(NT) void k_update(Topo topo, double *__restrict__ x
 }
 
 hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const double *q, double *part, Scal *sc,
-                         int max_iter, hipStream_t s)
+                         const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_update, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, r, p, q, part, sc);
+    hipLaunchKernelGGL(k_update, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, x, r, p, q, part, sc, bt.vs,
+                       bt.ps);
     return hipGetLastError();
 }
 
 // r = b - A x (r may be null) and the partials of ||r||^2.  mode 0: start of a
 // warm-started solve; mode 1: true residual at the end (stored in sc->zq).
 __global__ __launch_bounds__(NT) void k_resid(OpArgs<double> op, Topo topo, const double *__restrict__ b,
-                                              const double *__restrict__ x, double *__restrict__ r, double *part)
+                                              const double *__restrict__ x, double *__restrict__ r, double *part,
+                                              long long bvs, long long vs, int ps)
 {
     __shared__ double tile[TILE_VOX + 7];
     __shared__ double red[8];
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
+    b += blockIdx.y * bvs;
+    x += blockIdx.y * vs;
+    if (r) r += blockIdx.y * vs;
+    part += (long long)blockIdx.y * ps;
     int nb[6];
     brick_nbrs(topo.nbr, bk, nb);
     const int t = threadIdx.x;
@@ -903,22 +939,29 @@ __global__ __launch_bounds__(NT) void k_resid(OpArgs<double> op, Topo topo, cons
 }
 
 hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,
-                        double *part, Scal *sc, int mode, hipStream_t s)
+                        double *part, long long bvs, const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_resid, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, b, x, r, part);
+    hipLaunchKernelGGL(k_resid, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, b, x, r, part, bvs, bt.vs,
+                       bt.ps);
     return hipGetLastError();
 }
 
 // partials of r.z and z.q (flexible beta follows in k_finish)
 template <typename TZ>
 __global__ __launch_bounds__(NT) void k_dots(Topo topo, const TZ *__restrict__ z, const double *__restrict__ r,
-                                             const double *__restrict__ q, double *part, const Scal *sc, int first)
+                                             const double *__restrict__ q, double *part, const Scal *sc, int first,
+                                             long long vs, int ps)
 {
     __shared__ double red[8];
+    sc += blockIdx.y;
     if (sc->done) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
+    z += blockIdx.y * vs;
+    r += blockIdx.y * vs;
+    q += blockIdx.y * vs;
+    part += (long long)blockIdx.y * ps;
     const long long n = (long long)bk * BS + threadIdx.x;
     const double zv = (double)z[n];
     const double a = block_sum(zv * r[n], red);
@@ -931,54 +974,62 @@ __global__ __launch_bounds__(NT) void k_dots(Topo topo, const TZ *__restrict__ z
 
 template <typename TZ>
 hipError_t launch_dots(Topo topo, const TZ *z, const double *r, const double *q, double *part, Scal *sc, int first,
-                       hipStream_t s)
+                       const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dots<TZ>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, z, r, q, part, sc, first);
+    hipLaunchKernelGGL(k_dots<TZ>, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, z, r, q, part, sc, first, bt.vs,
+                       bt.ps);
     return hipGetLastError();
 }
 template hipError_t launch_dots<double>(Topo, const double *, const double *, const double *, double *, Scal *, int,
-                                        hipStream_t);
+                                        const Batch &, hipStream_t);
 template hipError_t launch_dots<float>(Topo, const float *, const double *, const double *, double *, Scal *, int,
-                                       hipStream_t);
+                                       const Batch &, hipStream_t);
 
 template <typename TZ>
 __global__ __launch_bounds__(NT) void k_pupdate(Topo topo, const TZ *__restrict__ z, double *__restrict__ p,
-                                                const Scal *sc, int first)
+                                                const Scal *sc, int first, long long vs)
 {
+    sc += blockIdx.y;
     if (sc->done) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
+    z += blockIdx.y * vs;
+    p += blockIdx.y * vs;
     const long long n = (long long)bk * BS + threadIdx.x;
     const double zv = (double)z[n];
     p[n] = first ? zv : zv + sc->beta * p[n];
 }
 
 template <typename TZ>
-hipError_t launch_pupdate(Topo topo, const TZ *z, double *p, const Scal *sc, int first, hipStream_t s)
+hipError_t launch_pupdate(Topo topo, const TZ *z, double *p, const Scal *sc, int first, const Batch &bt,
+                          hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pupdate<TZ>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, z, p, sc, first);
+    hipLaunchKernelGGL(k_pupdate<TZ>, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, z, p, sc, first, bt.vs);
     return hipGetLastError();
 }
-template hipError_t launch_pupdate<double>(Topo, const double *, double *, const Scal *, int, hipStream_t);
-template hipError_t launch_pupdate<float>(Topo, const float *, double *, const Scal *, int, hipStream_t);
+template hipError_t launch_pupdate<double>(Topo, const double *, double *, const Scal *, int, const Batch &,
+                                           hipStream_t);
+template hipError_t launch_pupdate<float>(Topo, const float *, double *, const Scal *, int, const Batch &, hipStream_t);
 
 // ---------------------------------------------------------------- multigrid level kernels
 __device__ __forceinline__ bool stopped(const Scal *sc)
 {
-    return sc && __hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return sc && __hip_atomic_load(&sc[blockIdx.y].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // first Chebyshev step from a zero start: x = c0 D^-1 b (0 where D = 0)
 template <typename T, typename TB>
 __global__ __launch_bounds__(NT) void k_cheb_first(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
-                                                   T *__restrict__ x, T c0, const Scal *sc)
+                                                   T *__restrict__ x, T c0, const Scal *sc, long long vs)
 {
     __shared__ T tile[TILE_VOX + 7];
     if (stopped(sc)) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
+    b += blockIdx.y * vs;
+    x += blockIdx.y * vs;
     int nb[6];
     brick_nbrs(topo.nbr, bk, nb);
     const int t = threadIdx.x;
@@ -1001,12 +1052,17 @@ template <typename T, typename TB>
 __global__ __launch_bounds__(NT) void k_cheb_step(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
                                                   const T *__restrict__ xin, T *__restrict__ xout,
                                                   const T *__restrict__ din, T *__restrict__ dout, T c1, T c2,
-                                                  const Scal *sc)
+                                                  const Scal *sc, long long vs)
 {
     __shared__ T tile[TILE_VOX + 7];
     if (stopped(sc)) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
+    b += blockIdx.y * vs;
+    xin += blockIdx.y * vs;
+    xout += blockIdx.y * vs;
+    if (din) din += blockIdx.y * vs;
+    if (dout) dout += blockIdx.y * vs;
     int nb[6];
     brick_nbrs(topo.nbr, bk, nb);
     const int t = threadIdx.x;
@@ -1039,13 +1095,17 @@ template <typename T, typename TB>
 __global__ __launch_bounds__(NT) void k_resid_restrict(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
                                                        const T *__restrict__ x, T *__restrict__ bc,
                                                        const int *__restrict__ parent_slot,
-                                                       const int4 *__restrict__ fcoord, const Scal *sc)
+                                                       const int4 *__restrict__ fcoord, const Scal *sc, long long vs,
+                                                       long long vsc)
 {
     __shared__ T tile[TILE_VOX + 7];
     __shared__ T rs[BS];
     if (stopped(sc)) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
+    b += blockIdx.y * vs;
+    x += blockIdx.y * vs;
+    bc += blockIdx.y * vsc;
     int nb[6];
     brick_nbrs(topo.nbr, bk, nb);
     const int t = threadIdx.x;
@@ -1078,11 +1138,13 @@ __global__ __launch_bounds__(NT) void k_resid_restrict(OpArgs<T> op, Topo topo, 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_prolong(Topo topo, T *__restrict__ x, const T *__restrict__ xc,
                                                 const int *__restrict__ parent_slot, const int4 *__restrict__ fcoord,
-                                                T scale, const Scal *sc)
+                                                T scale, const Scal *sc, long long vs, long long vsc)
 {
     if (stopped(sc)) return;
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
+    x += blockIdx.y * vs;
+    xc += blockIdx.y * vsc;
     const int t = threadIdx.x;
     int tx, ty, tz;
     brick_xyz(t, tx, ty, tz);
@@ -1096,10 +1158,13 @@ __global__ __launch_bounds__(NT) void k_prolong(Topo topo, T *__restrict__ x, co
 template <typename T, typename TB>
 __global__ __launch_bounds__(256) void k_coarse_apply(const TB *__restrict__ bc, T *__restrict__ xc,
                                                       const double *__restrict__ Ainv,
-                                                      const int *__restrict__ node_of_dof, int n, const Scal *sc)
+                                                      const int *__restrict__ node_of_dof, int n, const Scal *sc,
+                                                      long long vs)
 {
     __shared__ double rv[1024];
     if (stopped(sc)) return;
+    bc += blockIdx.y * vs;
+    xc += blockIdx.y * vs;
     for (int i = threadIdx.x; i < n; i += blockDim.x) rv[i] = (double)bc[node_of_dof[i]];
     __syncthreads();
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1113,73 +1178,77 @@ __global__ __launch_bounds__(256) void k_coarse_apply(const TB *__restrict__ bc,
 }
 
 template <typename T, typename TB>
-hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, T c0, const Scal *sc, hipStream_t s)
+hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, T c0, const Scal *sc, const Batch &bt,
+                             hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_cheb_first<T, TB>), dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, b, x, c0, sc);
+    hipLaunchKernelGGL((k_cheb_first<T, TB>), dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, b, x, c0, sc,
+                       bt.vs);
     return hipGetLastError();
 }
 
 template <typename T, typename TB>
 hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din, T *dout,
-                            T c1, T c2, const Scal *sc, hipStream_t s)
+                            T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_cheb_step<T, TB>), dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, b, xin, xout, din, dout,
-                       c1, c2, sc);
+    hipLaunchKernelGGL((k_cheb_step<T, TB>), dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, b, xin, xout, din,
+                       dout, c1, c2, sc, bt.vs);
     return hipGetLastError();
 }
 
 template <typename T, typename TB>
 hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, const T *x, T *bc, const int *parent_slot,
-                                 const int4 *fcoord, const Scal *sc, hipStream_t s)
+                                 const int4 *fcoord, const Scal *sc, const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_resid_restrict<T, TB>), dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, b, x, bc,
-                       parent_slot, fcoord, sc);
+    hipLaunchKernelGGL((k_resid_restrict<T, TB>), dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, b, x, bc,
+                       parent_slot, fcoord, sc, bt.vs, bt.vsc);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_prolong(Topo topo, T *x, const T *xc, const int *parent_slot, const int4 *fcoord, T scale,
-                          const Scal *sc, hipStream_t s)
+                          const Scal *sc, const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_prolong<T>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, xc, parent_slot, fcoord, scale,
-                       sc);
+    hipLaunchKernelGGL(k_prolong<T>, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, x, xc, parent_slot, fcoord,
+                       scale, sc, bt.vs, bt.vsc);
     return hipGetLastError();
 }
 
 template <typename T, typename TB>
 hipError_t launch_coarse_apply(const TB *bc, T *xc, const double *Ainv, const int *node_of_dof, int n, const Scal *sc,
-                               hipStream_t s)
+                               const Batch &bt, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     if (n > 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_coarse_apply<T, TB>), dim3((n + 3) / 4), dim3(256), 0, s, bc, xc, Ainv, node_of_dof, n, sc);
+    hipLaunchKernelGGL((k_coarse_apply<T, TB>), dim3((n + 3) / 4, bt.n), dim3(256), 0, s, bc, xc, Ainv, node_of_dof, n,
+                       sc, bt.vs);
     return hipGetLastError();
 }
 
 #define SPFD_INST_LEVEL(T, TB)                                                                                      \
     template hipError_t launch_cheb_first<T, TB>(const OpArgs<T> &, Topo, const TB *, T *, T, const Scal *,       \
-                                                 hipStream_t);                                                      \
+                                                 const Batch &, hipStream_t);                                       \
     template hipError_t launch_cheb_step<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *, const T *, T *, \
-                                                T, T, const Scal *, hipStream_t);                                   \
+                                                T, T, const Scal *, const Batch &, hipStream_t);                    \
     template hipError_t launch_resid_restrict<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *,           \
-                                                     const int *, const int4 *, const Scal *, hipStream_t);
+                                                     const int *, const int4 *, const Scal *, const Batch &,        \
+                                                     hipStream_t);
 SPFD_INST_LEVEL(double, double)
 SPFD_INST_LEVEL(float, float)
 SPFD_INST_LEVEL(float, double)
 template hipError_t launch_prolong<double>(Topo, double *, const double *, const int *, const int4 *, double,
-                                           const Scal *, hipStream_t);
+                                           const Scal *, const Batch &, hipStream_t);
 template hipError_t launch_prolong<float>(Topo, float *, const float *, const int *, const int4 *, float, const Scal *,
-                                          hipStream_t);
+                                          const Batch &, hipStream_t);
 template hipError_t launch_coarse_apply<double, double>(const double *, double *, const double *, const int *, int,
-                                                        const Scal *, hipStream_t);
+                                                        const Scal *, const Batch &, hipStream_t);
 template hipError_t launch_coarse_apply<float, float>(const float *, float *, const double *, const int *, int,
-                                                      const Scal *, hipStream_t);
+                                                      const Scal *, const Batch &, hipStream_t);
 template hipError_t launch_coarse_apply<float, double>(const double *, float *, const double *, const int *, int,
-                                                       const Scal *, hipStream_t);
+                                                       const Scal *, const Batch &, hipStream_t);
 
 // ============================================================================
 // gauge, output, post-processing
@@ -1220,7 +1289,7 @@ hipError_t launch_comp_mean(Topo topo, const double *x, const int *comp, int nco
     if (ncomp <= 16) {
         for (int c = 0; c < ncomp; ++c) {
             hipLaunchKernelGGL(k_comp_sum, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, comp, c, part);
-            hipError_t e = launch_finish(part, topo.nb, FIN_MEAN, nullptr, 0, s, means, counts, c);
+            hipError_t e = launch_finish(part, topo.nb, FIN_MEAN, nullptr, 0, s, means, counts, c, 1, 0);
             if (e != hipSuccess) return e;
         }
     } else {
@@ -1359,6 +1428,179 @@ hipError_t launch_uedges(const uint8_t *labels, const double *table, const doubl
     const long long nn = (long long)g.Nx * g.Ny * g.Nz;
     const unsigned gb = (unsigned)((nn + 255) / 256 > 131072 ? 131072 : (nn + 255) / 256);
     hipLaunchKernelGGL(k_uedges, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, a, psi, u);
+    return hipGetLastError();
+}
+
+}  // namespace spfd
+
+namespace spfd {
+
+// ============================================================================
+// adjoint gradient of an objective J(|E|) with respect to the conductivities
+// ============================================================================
+// With A Psi = -G^T M a, u = a + G Psi and dA = G^T dM G, a change of M gives
+// A dPsi = -G^T dM u; for dJ = g^T du = (G^T g)^T dPsi the adjoint solve
+// A lambda = G^T g yields dJ = -(G lambda)^T dM u, and dM_e/dsigma_v = (dual
+// area / length)/4 for the four voxels v around edge e.
+
+// per conducting voxel: c_d = dJ/d|E| * omega^2 * ubar_d / (4 h_d^2 |E|), the
+// derivative of J with respect to each of the voxel's four d-edge voltages
+__global__ void k_adj_voxel(const uint8_t *__restrict__ labels, const double *__restrict__ table,
+                            const double *__restrict__ sig_vox, Grid g, double hx, double hy, double hz, double omega,
+                            const double *__restrict__ a, const double *__restrict__ psi,
+                            const double *__restrict__ grad_emag, double *c)
+{
+    const long long nvox = (long long)g.nx * g.ny * g.nz;
+    const long long nn = (long long)g.Nx * g.Ny * g.Nz;
+    const long long sy = g.Nx, sz = (long long)g.Nx * g.Ny;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (long long)gridDim.x * blockDim.x) {
+        const double s = sig_vox ? sig_vox[v] : table[labels[v]];
+        double cx = 0.0, cy = 0.0, cz = 0.0;
+        if (s > 0.0) {
+            const long long i = v % g.nx, j = (v / g.nx) % g.ny, k = v / ((long long)g.nx * g.ny);
+            const long long n0 = i + g.Nx * (j + (long long)g.Ny * k);
+            const long long ex[4] = {n0, n0 + sy, n0 + sz, n0 + sy + sz};
+            const long long ey[4] = {n0, n0 + 1, n0 + sz, n0 + 1 + sz};
+            const long long ez[4] = {n0, n0 + 1, n0 + sy, n0 + 1 + sy};
+            double ux = 0.0, uy = 0.0, uz = 0.0;
+            for (int q = 0; q < 4; ++q) {
+                ux += (a[ex[q]] + psi[ex[q] + 1]) - psi[ex[q]];
+                uy += (a[nn + ey[q]] + psi[ey[q] + sy]) - psi[ey[q]];
+                uz += (a[2 * nn + ez[q]] + psi[ez[q] + sz]) - psi[ez[q]];
+            }
+            const double fx = 0.25 * ux / hx, fy = 0.25 * uy / hy, fz = 0.25 * uz / hz;
+            const double E = omega * sqrt(fx * fx + fy * fy + fz * fz);
+            if (E > 0.0) {
+                const double ge = grad_emag[v];
+                cx = ge * omega * omega * (0.25 * ux) / (4.0 * hx * hx * E);
+                cy = ge * omega * omega * (0.25 * uy) / (4.0 * hy * hy * E);
+                cz = ge * omega * omega * (0.25 * uz) / (4.0 * hz * hz * E);
+            }
+        }
+        c[v] = cx;
+        c[nvox + v] = cy;
+        c[2 * nvox + v] = cz;
+    }
+}
+
+// adjoint right side at the nodes: (G^T g)_n, where each of the 8 voxels
+// around n passes its d-edge through n; n is the head of that edge when the
+// voxel lies on the minus side along d (+c) and its tail otherwise (-c)
+__global__ __launch_bounds__(NT) void k_adj_rhs(Topo topo, const int4 *__restrict__ coord, Grid g,
+                                                const double *__restrict__ c, double *b, double *part)
+{
+    __shared__ double red[8];
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    const int t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const int4 q = coord[bk];
+    const int i = q.x * 8 + tx, j = q.y * 8 + ty, k = q.z * 8 + tz;
+    const long long nvox = (long long)g.nx * g.ny * g.nz;
+    double s = 0.0;
+    for (int oz = -1; oz <= 0; ++oz)
+        for (int oy = -1; oy <= 0; ++oy)
+            for (int ox = -1; ox <= 0; ++ox) {
+                const int vi = i + ox, vj = j + oy, vk = k + oz;
+                if (vi < 0 || vj < 0 || vk < 0 || vi >= g.nx || vj >= g.ny || vk >= g.nz) continue;
+                const long long v = vi + (long long)g.nx * (vj + (long long)g.ny * vk);
+                s += (ox < 0 ? c[v] : -c[v]);
+                s += (oy < 0 ? c[nvox + v] : -c[nvox + v]);
+                s += (oz < 0 ? c[2 * nvox + v] : -c[2 * nvox + v]);
+            }
+    b[(long long)bk * BS + t] = s;
+    const double tot = block_sum(s * s, red);
+    if (t == 0) part[bk] = tot;
+}
+
+// dJ/dsigma_v = -sum over the 12 edges of v of (area/length/4) (G lambda)_e u_e,
+// and per-block partial sums per label (LDS atomics, then a fixed-order sum)
+__global__ __launch_bounds__(256) void k_adj_grad(const uint8_t *__restrict__ labels, const double *__restrict__ table,
+                                                  const double *__restrict__ sig_vox, Grid g, double gx, double gy,
+                                                  double gz, const double *__restrict__ a,
+                                                  const double *__restrict__ psi, const double *__restrict__ lam,
+                                                  double *grad, double *lab_part, int nlab)
+{
+    __shared__ double hist[MAX_LABELS];
+    for (int l = threadIdx.x; l < nlab; l += blockDim.x) hist[l] = 0.0;
+    __syncthreads();
+    const long long nvox = (long long)g.nx * g.ny * g.nz;
+    const long long nn = (long long)g.Nx * g.Ny * g.Nz;
+    const long long sy = g.Nx, sz = (long long)g.Nx * g.Ny;
+    const double geo[3] = {gx, gy, gz};
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (long long)gridDim.x * blockDim.x) {
+        const double s = sig_vox ? sig_vox[v] : table[labels[v]];
+        double out = 0.0;
+        if (s > 0.0) {
+            const long long i = v % g.nx, j = (v / g.nx) % g.ny, k = v / ((long long)g.nx * g.ny);
+            const long long n0 = i + g.Nx * (j + (long long)g.Ny * k);
+            const long long e[3][4] = {{n0, n0 + sy, n0 + sz, n0 + sy + sz},
+                                       {n0, n0 + 1, n0 + sz, n0 + 1 + sz},
+                                       {n0, n0 + 1, n0 + sy, n0 + 1 + sy}};
+            const long long st[3] = {1, sy, sz};
+            double acc = 0.0;
+            for (int d = 0; d < 3; ++d)
+                for (int q = 0; q < 4; ++q) {
+                    const long long n = e[d][q];
+                    const double glam = lam[n + st[d]] - lam[n];
+                    const double u = (a[d * nn + n] + psi[n + st[d]]) - psi[n];
+                    acc += geo[d] * glam * u;
+                }
+            out = -acc;
+            if (labels[v] < nlab) atomicAdd(hist + labels[v], out);
+        }
+        grad[v] = out;
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < nlab; l += blockDim.x) lab_part[(long long)blockIdx.x * nlab + l] = hist[l];
+}
+
+// per-label totals: fixed-order sum of the block partials
+__global__ void k_adj_labsum(const double *__restrict__ lab_part, int nblocks, int nlab, double *out)
+{
+    const int l = blockIdx.x;
+    __shared__ double red[8];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += lab_part[(long long)b * nlab + l];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[l] = s;
+}
+
+hipError_t launch_adj_voxel(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,
+                            const double h[3], double omega, const double *a, const double *psi,
+                            const double *grad_emag, double *c, hipStream_t s)
+{
+    const long long nvox = (long long)g.nx * g.ny * g.nz;
+    const unsigned gb = (unsigned)((nvox + 255) / 256 > 131072 ? 131072 : (nvox + 255) / 256);
+    hipLaunchKernelGGL(k_adj_voxel, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, h[0], h[1], h[2], omega, a,
+                       psi, grad_emag, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_rhs(Topo topo, const int4 *coord, const Grid &g, const double *c, double *b, double *part,
+                          hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_rhs, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, coord, g, c, b, part);
+    return hipGetLastError();
+}
+
+int adj_grad_blocks(const Grid &g)
+{
+    const long long nvox = (long long)g.nx * g.ny * g.nz;
+    const long long b = (nvox + 255) / 256;
+    return (int)(b > 8192 ? 8192 : b);
+}
+
+hipError_t launch_adj_grad(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,
+                           const double geo4[3], const double *a, const double *psi, const double *lam, double *grad,
+                           double *lab_part, int nlab, double *lab_out, hipStream_t s)
+{
+    const int gb = adj_grad_blocks(g);
+    hipLaunchKernelGGL(k_adj_grad, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, geo4[0], geo4[1], geo4[2], a,
+                       psi, lam, grad, lab_part, nlab);
+    hipLaunchKernelGGL(k_adj_labsum, dim3(nlab), dim3(NT), 0, s, lab_part, gb, nlab, lab_out);
     return hipGetLastError();
 }
 

@@ -1,0 +1,626 @@
+// Unstructured (ELL) coarse levels of the aggregation multigrid.
+//
+// On the coarse end of the hierarchy, 2x2x2 aggregates are split into the
+// pieces that are connected inside the aggregate, so that one coarse unknown
+// never glues together conductor regions that touch only through air (an arm
+// and the torso across a thin gap, two legs).  A coarse unknown is then no
+// longer a grid node: these levels store, per unknown, its grid position and
+// up to K neighbours with conductances (ELL, column-major: entry k of row i at
+// k*n + i, column -1 = empty).  The Galerkin product for piecewise-constant
+// aggregation is still exact: the coarse conductance between two pieces is
+// the sum of the fine conductances that join them.
+#include <math.h>
+
+#include "kernels.h"
+
+namespace spfd {
+
+// ---------------------------------------------------------------- union-find helpers (agent-scope, lock-free)
+__device__ __forceinline__ int uf_load(const int *p, int i)
+{
+    return __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int uf_find(int *p, int x)
+{
+    int px = uf_load(p, x);
+    while (px != x) {
+        const int ppx = uf_load(p, px);
+        if (ppx != px) __hip_atomic_store(p + x, ppx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = px;
+        px = ppx;
+    }
+    return x;
+}
+
+__device__ __forceinline__ void uf_unite(int *p, int a, int b)
+{
+    while (true) {
+        a = uf_find(p, a);
+        b = uf_find(p, b);
+        if (a == b) return;
+        if (a > b) { const int t = a; a = b; b = t; }
+        int expected = b;
+        if (__hip_atomic_compare_exchange_strong(p + b, &expected, a, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return;
+    }
+}
+
+// ---------------------------------------------------------------- pieces of a structured (brick) level
+// parent[n] = n for unknowns (D > 0), -1 otherwise
+__global__ void k_piece_init_brick(const double *__restrict__ w, long long stride, Topo topo, int *parent)
+{
+    const int b = blockIdx.x, t = threadIdx.x;
+    int nb[6];
+    brick_nbrs(topo.nbr, b, nb);
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const long long base = (long long)b * BS;
+    long long I[6];
+    nbr_index(base, t, tx, ty, tz, nb, I);
+    double W[6];
+    stored_weights(w, stride, base, t, I, W);
+    parent[base + t] = diag_of(W) > 0.0 ? (int)(base + t) : -1;
+}
+
+// unite across the edges that stay inside a 2x2x2 aggregate: the +d edge of a
+// node with an even grid coordinate along d (bricks start at multiples of 8,
+// so both ends are in the same brick)
+__global__ void k_piece_union_brick(const double *__restrict__ w, long long stride, Topo topo, int *parent)
+{
+    const int b = blockIdx.x, t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const long long base = (long long)b * BS;
+    const int me = (int)(base + t);
+    if ((tx & 1) == 0 && w[base + t] > 0.0) uf_unite(parent, me, me + 1);
+    if ((ty & 1) == 0 && w[stride + base + t] > 0.0) uf_unite(parent, me, me + 8);
+    if ((tz & 1) == 0 && w[2 * stride + base + t] > 0.0) uf_unite(parent, me, me + 64);
+}
+
+// position (at the coarse level) of the piece rooted at node n
+__global__ void k_piece_pos_brick(const int *__restrict__ parent, const int *__restrict__ idx, Topo topo,
+                                  const int4 *__restrict__ coord, int4 *pos)
+{
+    const int b = blockIdx.x, t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const long long n = (long long)b * BS + t;
+    if (parent[n] == (int)n) {
+        const int4 c = coord[b];
+        pos[idx[n]] = make_int4((c.x * 8 + tx) >> 1, (c.y * 8 + ty) >> 1, (c.z * 8 + tz) >> 1, 0);
+    }
+}
+
+// ---------------------------------------------------------------- pieces of an ELL level
+__global__ void k_piece_init_ell(int n, int K, const int *__restrict__ col, const double *__restrict__ val,
+                                 int *parent)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double d = 0.0;
+        for (int k = 0; k < K; ++k)
+            if (col[(long long)k * n + i] >= 0) d += val[(long long)k * n + i];
+        parent[i] = d > 0.0 ? i : -1;
+    }
+}
+
+__global__ void k_piece_union_ell(int n, int K, const int *__restrict__ col, const double *__restrict__ val,
+                                  const int4 *__restrict__ pos, int *parent)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (parent[i] < 0) continue;
+        const int4 pi = pos[i];
+        for (int k = 0; k < K; ++k) {
+            const int j = col[(long long)k * n + i];
+            if (j <= i || !(val[(long long)k * n + i] > 0.0)) continue;
+            const int4 pj = pos[j];
+            if ((pi.x >> 1) == (pj.x >> 1) && (pi.y >> 1) == (pj.y >> 1) && (pi.z >> 1) == (pj.z >> 1))
+                uf_unite(parent, i, j);
+        }
+    }
+}
+
+__global__ void k_piece_pos_ell(int n, const int *__restrict__ parent, const int *__restrict__ idx,
+                                const int4 *__restrict__ fpos, int4 *pos)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        if (parent[i] == i) {
+            const int4 p = fpos[i];
+            pos[idx[i]] = make_int4(p.x >> 1, p.y >> 1, p.z >> 1, 0);
+        }
+}
+
+// ---------------------------------------------------------------- shared steps
+__global__ void k_piece_flatten(int *parent, long long n, int *flag)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        int r = -1;
+        if (uf_load(parent, (int)i) >= 0) r = uf_find(parent, (int)i);
+        flag[i] = (r == (int)i) ? 1 : 0;
+    }
+}
+
+__global__ void k_piece_store_root(int *parent, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int p = uf_load(parent, (int)i);
+        if (p >= 0) parent[i] = uf_find(parent, (int)i);
+    }
+}
+
+__global__ void k_piece_assign(const int *__restrict__ parent, const int *__restrict__ idx, long long n, int *agg,
+                               int *count)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int p = parent[i];
+        const int a = p >= 0 ? idx[p] : -1;
+        agg[i] = a;
+        if (a >= 0) atomicAdd(count + a, 1);
+    }
+}
+
+// members of each coarse unknown, in increasing fine index (deterministic order)
+__global__ void k_members_fill(const int *__restrict__ agg, long long n, const int *__restrict__ mptr, int *cursor,
+                               int *mem)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int a = agg[i];
+        if (a >= 0) mem[mptr[a] + atomicAdd(cursor + a, 1)] = (int)i;
+    }
+}
+
+__global__ void k_members_sort(int nc, const int *__restrict__ mptr, int *mem)
+{
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
+        const int b = mptr[p], e = mptr[p + 1];
+        for (int i = b + 1; i < e; ++i) {
+            const int v = mem[i];
+            int j = i - 1;
+            while (j >= b && mem[j] > v) {
+                mem[j + 1] = mem[j];
+                --j;
+            }
+            mem[j + 1] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- Galerkin rows
+constexpr int GAL_MAX = 48;   // distinct coarse neighbours a row may collect
+
+// visit the edges of fine unknown i: f(j, w) for every neighbour j with w > 0
+struct FineLevel {
+    // structured
+    const double *w;
+    long long stride;
+    const int *nbr;
+    // ELL
+    int n, K;
+    const int *col;
+    const double *val;
+};
+
+template <typename F>
+__device__ __forceinline__ void fine_edges(const FineLevel &f, int i, F &&fn)
+{
+    if (f.w) {
+        const int b = i / BS, t = i % BS;
+        int tx, ty, tz;
+        brick_xyz(t, tx, ty, tz);
+        int nb[6];
+        brick_nbrs(f.nbr, b, nb);
+        long long I[6];
+        nbr_index((long long)b * BS, t, tx, ty, tz, nb, I);
+        double W[6];
+        stored_weights(f.w, f.stride, (long long)b * BS, t, I, W);
+        for (int k = 0; k < 6; ++k)
+            if (W[k] > 0.0 && I[k] != i) fn((int)I[k], W[k]);
+    } else {
+        for (int k = 0; k < f.K; ++k) {
+            const int j = f.col[(long long)k * f.n + i];
+            if (j >= 0 && f.val[(long long)k * f.n + i] > 0.0) fn(j, f.val[(long long)k * f.n + i]);
+        }
+    }
+}
+
+// pass 0: row lengths (len[p]); pass 1: fill ELL with width K (entries in
+// order of first appearance over members and their edges; sums in that order)
+__global__ void k_galerkin_rows(FineLevel f, const int *__restrict__ agg, int nc, const int *__restrict__ mptr,
+                                const int *__restrict__ mem, int pass, int *len, int K, int *col, double *val64,
+                                float *val32, int *overflow)
+{
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
+        int cols[GAL_MAX];
+        double ws[GAL_MAX];
+        int m = 0;
+        bool over = false;
+        for (int q = mptr[p]; q < mptr[p + 1]; ++q) {
+            const int i = mem[q];
+            fine_edges(f, i, [&](int j, double wj) {
+                const int a = agg[j];
+                if (a < 0 || a == p) return;
+                int s = 0;
+                while (s < m && cols[s] != a) ++s;
+                if (s == m) {
+                    if (m == GAL_MAX) { over = true; return; }
+                    cols[m] = a;
+                    ws[m] = 0.0;
+                    ++m;
+                }
+                ws[s] += wj;
+            });
+        }
+        if (over) *overflow = 1;
+        if (pass == 0) {
+            len[p] = m;
+        } else {
+            for (int k = 0; k < K; ++k) {
+                const long long e = (long long)k * nc + p;
+                if (k < m) {
+                    col[e] = cols[k];
+                    val64[e] = ws[k];
+                    val32[e] = (float)ws[k];
+                } else {
+                    col[e] = -1;
+                    val64[e] = 0.0;
+                    val32[e] = 0.0f;
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_max_int(const int *__restrict__ v, int n, int *out)
+{
+    __shared__ int s[256];
+    int m = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = max(m, v[i]);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if (threadIdx.x < d) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + d]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+static unsigned gblocks(long long n, int bs = 256, long long cap = 65536)
+{
+    long long b = (n + bs - 1) / bs;
+    if (b < 1) b = 1;
+    return (unsigned)(b > cap ? cap : b);
+}
+
+hipError_t launch_pieces_brick(const double *w64, long long stride, Topo topo, const int4 *coord, int *parent,
+                               hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_piece_init_brick, dim3(topo.nb), dim3(NT), 0, s, w64, stride, topo, parent);
+    hipLaunchKernelGGL(k_piece_union_brick, dim3(topo.nb), dim3(NT), 0, s, w64, stride, topo, parent);
+    (void)coord;
+    return hipGetLastError();
+}
+
+hipError_t launch_pieces_ell(int n, int K, const int *col, const double *val, const int4 *pos, int *parent,
+                             hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_piece_init_ell, dim3(gblocks(n)), dim3(256), 0, s, n, K, col, val, parent);
+    hipLaunchKernelGGL(k_piece_union_ell, dim3(gblocks(n)), dim3(256), 0, s, n, K, col, val, pos, parent);
+    return hipGetLastError();
+}
+
+hipError_t launch_pieces_finish(int *parent, long long n, int *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_piece_store_root, dim3(gblocks(n)), dim3(256), 0, s, parent, n);
+    hipLaunchKernelGGL(k_piece_flatten, dim3(gblocks(n)), dim3(256), 0, s, parent, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_pieces_assign(const int *parent, const int *idx, long long n, int *agg, int *count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_piece_assign, dim3(gblocks(n)), dim3(256), 0, s, parent, idx, n, agg, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_piece_pos_brick(const int *parent, const int *idx, Topo topo, const int4 *coord, int4 *pos,
+                                  hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_piece_pos_brick, dim3(topo.nb), dim3(NT), 0, s, parent, idx, topo, coord, pos);
+    return hipGetLastError();
+}
+
+hipError_t launch_piece_pos_ell(int n, const int *parent, const int *idx, const int4 *fpos, int4 *pos, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_piece_pos_ell, dim3(gblocks(n)), dim3(256), 0, s, n, parent, idx, fpos, pos);
+    return hipGetLastError();
+}
+
+hipError_t launch_members(const int *agg, long long n, int nc, const int *mptr, int *cursor, int *mem, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_members_fill, dim3(gblocks(n)), dim3(256), 0, s, agg, n, mptr, cursor, mem);
+    if (nc > 0) hipLaunchKernelGGL(k_members_sort, dim3(gblocks(nc)), dim3(256), 0, s, nc, mptr, mem);
+    return hipGetLastError();
+}
+
+hipError_t launch_galerkin_ell(const FineLevelArgs &fa, const int *agg, int nc, const int *mptr, const int *mem,
+                               int pass, int *len, int K, int *col, double *val64, float *val32, int *overflow,
+                               int *maxlen, hipStream_t s)
+{
+    FineLevel f;
+    f.w = fa.w;
+    f.stride = fa.stride;
+    f.nbr = fa.nbr;
+    f.n = fa.n;
+    f.K = fa.K;
+    f.col = fa.col;
+    f.val = fa.val;
+    if (nc <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_galerkin_rows, dim3(gblocks(nc, 128)), dim3(128), 0, s, f, agg, nc, mptr, mem, pass, len, K,
+                       col, val64, val32, overflow);
+    if (pass == 0) hipLaunchKernelGGL(k_max_int, dim3(1), dim3(256), 0, s, len, nc, maxlen);
+    return hipGetLastError();
+}
+
+// ============================================================================
+// cycle kernels on ELL levels (T = arithmetic of the cycle)
+// ============================================================================
+__device__ __forceinline__ bool ell_stopped(const Scal *sc)
+{
+    return sc && __hip_atomic_load(&sc[blockIdx.y].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T ell_row(int n, int K, const int *__restrict__ col, const T *__restrict__ val,
+                                     const T *__restrict__ x, int i, T xi, T &D)
+{
+    T y = T(0), d = T(0);
+    for (int k = 0; k < K; ++k) {
+        const int j = col[(long long)k * n + i];
+        if (j >= 0) {
+            const T w = val[(long long)k * n + i];
+            d += w;
+            y += w * (xi - x[j]);
+        }
+    }
+    D = d;
+    return y;
+}
+
+template <typename T>
+__global__ void k_ell_cheb_first(int n, int K, const int *__restrict__ col, const T *__restrict__ val,
+                                 const T *__restrict__ b, T *__restrict__ x, T c0, const Scal *sc, long long vs)
+{
+    if (ell_stopped(sc)) return;
+    b += blockIdx.y * vs;
+    x += blockIdx.y * vs;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        T d = T(0);
+        for (int k = 0; k < K; ++k)
+            if (col[(long long)k * n + i] >= 0) d += val[(long long)k * n + i];
+        x[i] = d > T(0) ? c0 * b[i] / d : T(0);
+    }
+}
+
+template <typename T>
+__global__ void k_ell_cheb_step(int n, int K, const int *__restrict__ col, const T *__restrict__ val,
+                                const T *__restrict__ b, const T *__restrict__ xin, T *__restrict__ xout,
+                                const T *__restrict__ din, T *__restrict__ dout, T c1, T c2, const Scal *sc,
+                                long long vs)
+{
+    if (ell_stopped(sc)) return;
+    b += blockIdx.y * vs;
+    xin += blockIdx.y * vs;
+    xout += blockIdx.y * vs;
+    if (din) din += blockIdx.y * vs;
+    if (dout) dout += blockIdx.y * vs;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const T xi = xin[i];
+        T D;
+        const T ax = ell_row(n, K, col, val, xin, i, xi, D);
+        T xo = T(0), dn = T(0);
+        if (D > T(0)) {
+            const T dold = din ? din[i] : xi;
+            dn = c1 * dold + c2 * (b[i] - ax) / D;
+            xo = xi + dn;
+        }
+        xout[i] = xo;
+        if (dout) dout[i] = dn;
+    }
+}
+
+// coarse right side b_c[p] = sum over the members i of p of (b - A x)_i
+template <typename T>
+__global__ void k_restrict_members(FineLevelT<T> f, const T *__restrict__ b, const T *__restrict__ x, int nc,
+                                   const int *__restrict__ mptr, const int *__restrict__ mem, T *__restrict__ bc,
+                                   const Scal *sc, long long vs, long long vsc)
+{
+    if (ell_stopped(sc)) return;
+    b += blockIdx.y * vs;
+    x += blockIdx.y * vs;
+    bc += blockIdx.y * vsc;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
+        T s = T(0);
+        for (int q = mptr[p]; q < mptr[p + 1]; ++q) {
+            const int i = mem[q];
+            const T xi = x[i];
+            T ax;
+            if (f.w) {
+                const int bk = i / BS, t = i % BS;
+                int tx, ty, tz;
+                brick_xyz(t, tx, ty, tz);
+                int nb[6];
+                brick_nbrs(f.nbr, bk, nb);
+                long long I[6];
+                nbr_index((long long)bk * BS, t, tx, ty, tz, nb, I);
+                T W[6], X[6];
+                stored_weights(f.w, f.stride, (long long)bk * BS, t, I, W);
+                nbr_vals(x, I, X);
+                ax = stencil_apply(xi, X, W);
+            } else {
+                T D;
+                ax = ell_row(f.n, f.K, f.col, f.val, x, i, xi, D);
+            }
+            s += b[i] - ax;
+        }
+        bc[p] = s;
+    }
+}
+
+// x_f += scale * x_c[agg]
+template <typename T>
+__global__ void k_prolong_agg(long long n, const int *__restrict__ agg, T *__restrict__ x, const T *__restrict__ xc,
+                              T scale, const Scal *sc, long long vs, long long vsc)
+{
+    if (ell_stopped(sc)) return;
+    x += blockIdx.y * vs;
+    xc += blockIdx.y * vsc;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int a = agg[i];
+        if (a >= 0) x[i] += scale * xc[a];
+    }
+}
+
+template <typename T>
+hipError_t launch_ell_cheb_first(int n, int K, const int *col, const T *val, const T *b, T *x, T c0, const Scal *sc,
+                                 const Batch &bt, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ell_cheb_first<T>, dim3(gblocks(n), bt.n), dim3(256), 0, s, n, K, col, val, b, x, c0, sc,
+                       bt.vs);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ell_cheb_step(int n, int K, const int *col, const T *val, const T *b, const T *xin, T *xout,
+                                const T *din, T *dout, T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ell_cheb_step<T>, dim3(gblocks(n), bt.n), dim3(256), 0, s, n, K, col, val, b, xin, xout, din,
+                       dout, c1, c2, sc, bt.vs);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict_members(const FineLevelT<T> &f, const T *b, const T *x, int nc, const int *mptr,
+                                   const int *mem, T *bc, const Scal *sc, const Batch &bt, hipStream_t s)
+{
+    if (nc <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_restrict_members<T>, dim3(gblocks(nc, 128), bt.n), dim3(128), 0, s, f, b, x, nc, mptr, mem,
+                       bc, sc, bt.vs, bt.vsc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong_agg(long long n, const int *agg, T *x, const T *xc, T scale, const Scal *sc,
+                              const Batch &bt, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prolong_agg<T>, dim3(gblocks(n), bt.n), dim3(256), 0, s, n, agg, x, xc, scale, sc, bt.vs,
+                       bt.vsc);
+    return hipGetLastError();
+}
+
+#define SPFD_INST_ELL(T)                                                                                            \
+    template hipError_t launch_ell_cheb_first<T>(int, int, const int *, const T *, const T *, T *, T, const Scal *, \
+                                                 const Batch &, hipStream_t);                                       \
+    template hipError_t launch_ell_cheb_step<T>(int, int, const int *, const T *, const T *, const T *, T *,         \
+                                                const T *, T *, T, T, const Scal *, const Batch &, hipStream_t);    \
+    template hipError_t launch_restrict_members<T>(const FineLevelT<T> &, const T *, const T *, int, const int *,   \
+                                                   const int *, T *, const Scal *, const Batch &, hipStream_t);     \
+    template hipError_t launch_prolong_agg<T>(long long, const int *, T *, const T *, T, const Scal *,             \
+                                              const Batch &, hipStream_t);
+SPFD_INST_ELL(double)
+SPFD_INST_ELL(float)
+
+// ---------------------------------------------------------------- coarsest level given as ELL
+// unknowns = rows with D > 0, in row order; adjacency among them
+__global__ void k_coarse_enum_ell(int n, int K, const int *__restrict__ col, const double *__restrict__ val,
+                                  int *dof_of_row, int *row_of_dof, int *ndof, int maxdof)
+{
+    __shared__ int s[1024];
+    __shared__ int carry;
+    const int t = threadIdx.x;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += 1024) {
+        const int i = base + t;
+        int isdof = 0;
+        if (i < n) {
+            double d = 0.0;
+            for (int k = 0; k < K; ++k)
+                if (col[(long long)k * n + i] >= 0) d += val[(long long)k * n + i];
+            isdof = d > 0.0;
+        }
+        s[t] = isdof;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const int add = t >= d ? s[t - d] : 0;
+            __syncthreads();
+            s[t] += add;
+            __syncthreads();
+        }
+        const int id = carry + s[t] - isdof;
+        if (i < n) {
+            dof_of_row[i] = isdof ? id : -1;
+            if (isdof && id < maxdof) row_of_dof[id] = i;
+        }
+        __syncthreads();
+        if (t == 1023) carry += s[t];
+        __syncthreads();
+    }
+    if (t == 0) *ndof = carry;
+}
+
+hipError_t launch_coarse_enum_ell(int n, int K, const int *col, const double *val, int *dof_of_row, int *row_of_dof,
+                                  int *ndof, int maxdof, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_coarse_enum_ell, dim3(1), dim3(1024), 0, s, n, K, col, val, dof_of_row, row_of_dof, ndof,
+                       maxdof);
+    return hipGetLastError();
+}
+
+// dense matrix of the coarsest ELL level over its unknowns (row-major n x n)
+__global__ void k_coarse_dense_ell(int nrow, int K, const int *__restrict__ col, const double *__restrict__ val,
+                                   const int *__restrict__ dof_of_row, const int *__restrict__ row_of_dof, int n,
+                                   double *A)
+{
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < (long long)n * n;
+         e += (long long)gridDim.x * blockDim.x)
+        A[e] = 0.0;
+}
+
+__global__ void k_coarse_fill_ell(int nrow, int K, const int *__restrict__ col, const double *__restrict__ val,
+                                  const int *__restrict__ dof_of_row, const int *__restrict__ row_of_dof, int n,
+                                  double *A)
+{
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        const int i = row_of_dof[q];
+        double d = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const int j = col[(long long)k * nrow + i];
+            if (j < 0) continue;
+            const double w = val[(long long)k * nrow + i];
+            d += w;
+            const int m = dof_of_row[j];
+            if (m >= 0) A[(long long)q * n + m] -= w;
+        }
+        A[(long long)q * n + q] += d;
+    }
+}
+
+hipError_t launch_coarse_dense_ell(int nrow, int K, const int *col, const double *val, const int *dof_of_row,
+                                   const int *row_of_dof, int n, double *A, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coarse_dense_ell, dim3(gblocks((long long)n * n)), dim3(256), 0, s, nrow, K, col, val,
+                       dof_of_row, row_of_dof, n, A);
+    hipLaunchKernelGGL(k_coarse_fill_ell, dim3(gblocks(n)), dim3(256), 0, s, nrow, K, col, val, dof_of_row,
+                       row_of_dof, n, A);
+    return hipGetLastError();
+}
+
+}  // namespace spfd

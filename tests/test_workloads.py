@@ -175,3 +175,21 @@ def test_body_phantom_dof_count_and_tissues():
 
 def test_uneven_sizes():
     assert W.uneven_phantom_sizes() == [64, 73, 81, 90, 98, 107, 115, 124, 132, 141, 149, 158, 166, 175, 183, 192]
+
+
+def test_shifted_loop_sources_are_translations():
+    offs = [(3, -2), (-4, 1)]
+    gen = W.ShiftedLoopSources(offs, grid=(40, 30, 20))
+    h = 2e-3
+    for k, (dx, dy) in enumerate(offs):
+        a = gen.source(k)
+        ref = W.rect_loop_edge_potentials(40, 30, 20, (h, h, h), ((125.0 + 60.0 + dx) * h, (75.0 + dy) * h, -20.0 * h),
+                                          (150 * h, 100 * h))
+        assert np.abs(a - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_multi_source_offsets():
+    offs = W.multi_source_offsets()
+    assert len(offs) == 64
+    assert all(isinstance(v, int) for o in offs for v in o)
+    assert max(abs(o[0]) for o in offs) <= 72 and max(abs(o[1]) for o in offs) <= 37

@@ -440,16 +440,47 @@ def body_loop_source(offset=(0.0, 0.0), grid=(250, 150, 900), h=2e-3):
 
 
 def multi_source_offsets(seed=SEED_BASE + 3, n=8):
-    """8x8 coil offsets (voxels): dx in {-70,-50,...,70}, dy in {-35,-25,...,35}, + U[-2,2] jitter."""
+    """8x8 coil offsets in whole voxels: dx in {-70,-50,...,70}, dy in {-35,-25,...,35},
+    plus a jitter drawn from U{-2,...,2} per coordinate (row-major over dy, then dx)."""
     rng = np.random.default_rng(seed)
-    dxs = np.linspace(-70.0, 70.0, n)
-    dys = np.linspace(-35.0, 35.0, n)
+    dxs = np.linspace(-70.0, 70.0, n).round().astype(int)
+    dys = np.linspace(-35.0, 35.0, n).round().astype(int)
     out = []
     for dy in dys:
         for dx in dxs:
-            j = rng.uniform(-2.0, 2.0, 2)
-            out.append((dx + j[0], dy + j[1]))
+            j = rng.integers(-2, 3, 2)
+            out.append((int(dx + j[0]), int(dy + j[1])))
     return out
+
+
+class ShiftedLoopSources:
+    """Edge potentials of the body-phantom loop translated by whole voxels.
+
+    The field of a coil moved by (dx, dy) voxels in its plane is the field of the
+    unmoved coil translated by (dx, dy): a_dx,dy(i, j, k) = a_0(i - dx, j - dy, k).
+    The unmoved field is computed once on a grid padded by the largest shift;
+    each source is then a slice of it.
+    """
+
+    def __init__(self, offsets, grid=(250, 150, 900), h=2e-3):
+        nx, ny, nz = grid
+        self.grid = grid
+        self.px = max(abs(o[0]) for o in offsets)
+        self.py = max(abs(o[1]) for o in offsets)
+        big = rect_loop_edge_potentials(nx + 2 * self.px, ny + 2 * self.py, nz, (h, h, h),
+                                        ((125.0 + 60.0 + self.px) * h, (75.0 + self.py) * h, -20.0 * h),
+                                        (150 * h, 100 * h))
+        self.big = big
+        self.offsets = offsets
+
+    def source(self, idx):
+        dx, dy = self.offsets[idx]
+        nx, ny, nz = self.grid
+        x0, y0 = self.px - dx, self.py - dy
+        a = self.big[:, :, y0:y0 + ny + 1, x0:x0 + nx + 1].copy()
+        a[0, :, :, nx] = 0.0     # edges that leave the grid
+        a[1, :, ny, :] = 0.0
+        return a
 
 
 def uneven_phantom_sizes(n=16, lo=64, span=128):
