@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=150, help="oracle iterations in the bounded CPU sample")
     ap.add_argument("--precisions", default="mixed,fp64")
+    ap.add_argument("--no-batch", action="store_true", help="skip the multi-source and multi-phantom runs")
     return ap.parse_args()
 
 
@@ -107,6 +108,87 @@ def cpu_baseline(w, args, iters_full):
                        f"({wall:.1f} s wall incl. assembly {info['t_assemble']:.1f} s), scaled to the "
                        f"{iters_full} iterations the oracle needs for rel. residual {args.tol:g}"),
             "s_per_iteration": per_it, "iterations_full": iters_full}
+
+
+def batch_sources(w, lab, P, torch, args):
+    """64 coil positions on an 8x8 offset grid sharing one hierarchy (batched solve)."""
+    import workloads as W
+    dev = lab.device
+    offs = W.multi_source_offsets()
+    t0 = time.perf_counter()
+    gen = W.ShiftedLoopSources(offs)
+    t_gen = time.perf_counter() - t0
+    s = P.Solver(lab, w.sigma_table, w.h, precision="mixed")
+    P.spfd_set_num_rhs(s.handle, len(offs))
+    s.nrhs = len(offs)
+    abuf = torch.empty((3, w.nz + 1, w.ny + 1, w.nx + 1), dtype=torch.float64, device=dev)
+    for k in range(len(offs)):
+        abuf.copy_(torch.from_numpy(gen.source(k)))
+        P.spfd_set_source(s.handle, k, abuf)
+    del gen
+    psi = torch.empty((len(offs), w.nz + 1, w.ny + 1, w.nx + 1), dtype=torch.float64, device=dev)
+    times, info = [], None
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, info = P.spfd_solve(s.handle, P.SolveOptions(args.tol, 500, 0), psi, len(offs))
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    its = [i["iterations"] for i in info]
+    ok = all(i["status"] == "OK" for i in info)
+    # the same sources one at a time through the same hierarchy, for comparison (first 8)
+    P.spfd_set_num_rhs(s.handle, 1)
+    s.nrhs = 1
+    seq = []
+    for k in range(8):
+        gk = W.rect_loop_edge_potentials(w.nx, w.ny, w.nz, w.h, ((125.0 + 60.0 + offs[k][0]) * w.h[0],
+                                         (75.0 + offs[k][1]) * w.h[1], -20.0 * w.h[2]), (150 * w.h[0], 100 * w.h[1]))
+        abuf.copy_(torch.from_numpy(gk))
+        P.spfd_set_source(s.handle, 0, abuf)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        P.spfd_solve(s.handle, P.SolveOptions(args.tol, 500, 0), psi[:1], 1)
+        torch.cuda.synchronize()
+        seq.append(time.perf_counter() - t)
+    s.close()
+    return {"workload": f"{w.name}, 64 coil positions (8x8 offsets), one hierarchy, mixed precision",
+            "sources": len(offs), "batched_solve_s": min(times), "solves_per_s": len(offs) / min(times),
+            "iterations_min": min(its), "iterations_max": max(its), "all_ok": ok,
+            "sequential_solve_s_per_source": sum(seq) / len(seq),
+            "batch_speedup_vs_sequential": (sum(seq) / len(seq)) * len(offs) / min(times),
+            "source_generation_s": t_gen}
+
+
+def batch_phantoms(P, torch, args):
+    """16 phantoms of 64^3 ... 192^3 voxels, each with its own hierarchy and stream, solved in lockstep."""
+    import workloads as W
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    ws = W.uneven_phantoms()
+    t_gen = time.perf_counter() - t0
+    solvers, srcs = [], []
+    for w in ws:
+        st = torch.cuda.Stream(dev)
+        solvers.append(P.Solver(torch.from_numpy(w.labels).to(dev), w.sigma_table, w.h, precision="mixed", stream=st))
+        srcs.append(torch.from_numpy(w.a).to(dev))
+    dofs = sum(s.info()["n_dofs"] for s in solvers)
+    P.solve_many(solvers, srcs, tol=args.tol)            # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    psis, infos = P.solve_many(solvers, srcs, tol=args.tol)
+    torch.cuda.synchronize()
+    t_many = time.perf_counter() - t
+    t = time.perf_counter()
+    for s_, a_ in zip(solvers, srcs):
+        s_.solve(a_, tol=args.tol)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t
+    for s_ in solvers:
+        s_.close()
+    return {"workload": "16 ellipsoid-union phantoms, cubes of 64^3 ... 192^3 voxels at 2 mm, own hierarchies",
+            "phantoms": len(ws), "unknowns_total": dofs, "lockstep_solve_s": t_many, "sequential_solve_s": t_seq,
+            "lockstep_speedup": t_seq / t_many, "all_ok": all(i["status"] == "OK" for i in infos),
+            "iterations": [i["iterations"] for i in infos], "generation_s": t_gen}
 
 
 def main():
@@ -188,6 +270,11 @@ def main():
         out["mixed_vs_fp64_speedup"] = mean(ph64["solve"]) / solve_s
         import numpy as np
         out["mixed_vs_fp64_rel_diff"] = float(np.linalg.norm(psi_head - psi64) / np.linalg.norm(psi64))
+    if not args.no_batch:
+        out["batch_sources"] = batch_sources(w, lab, P, torch, args)
+        print(f"# batch sources: {out['batch_sources']['batched_solve_s']:.3f} s", file=sys.stderr, flush=True)
+        out["batch_phantoms"] = batch_phantoms(P, torch, args)
+        print(f"# batch phantoms: {out['batch_phantoms']['lockstep_solve_s']:.3f} s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         gold = os.path.join(ROOT, "tests", "golden", f"oracle_body_{args.tol:.0e}.json")
         iters_full = json.load(open(gold))["iterations"] if os.path.exists(gold) else None

@@ -128,6 +128,15 @@ spfd_status spfd_solve(spfd_handle h, const spfd_solve_options *opt, double *psi
 spfd_status spfd_efield(spfd_handle h, double omega, const double *a, const double *psi,
                         double *u_edges, double *emag);
 
+/* Solve Eq. (3) on several voxel models at once (each handle built, with its
+ * sources set, on the same device).  The CG iterations of all handles advance
+ * in lockstep, each handle's kernels on its own stream, so that problems of
+ * uneven size share the GPU.  psi[k] is handle k's output as in spfd_solve;
+ * info (host, nullable) holds the right sides of all handles in order.
+ * opt as in spfd_solve (use_x0 ignored).  Errors are reported on hs[0]. */
+spfd_status spfd_solve_many(spfd_handle *hs, int n, const spfd_solve_options *opt, double **psi,
+                            spfd_rhs_info *info);
+
 /* Adjoint gradient of a scalar objective J(|E|) with respect to the voxel
  * conductivities, by one extra solve of Eq. (3) on the built hierarchy.
  * Inputs: omega, a and psi of a forward solution (as for spfd_efield), and

@@ -51,7 +51,7 @@ class RhsInfo(ctypes.Structure):
 _lib = None
 EXPORTS = ["spfd_create", "spfd_destroy", "spfd_last_error", "spfd_set_geometry", "spfd_set_sigma_table",
            "spfd_set_sigma_voxel", "spfd_build", "spfd_get_info", "spfd_set_num_rhs", "spfd_set_source",
-           "spfd_solve", "spfd_efield", "spfd_adjoint", "spfd_timing", "spfd_timing_get"]
+           "spfd_solve", "spfd_solve_many", "spfd_efield", "spfd_adjoint", "spfd_timing", "spfd_timing_get"]
 # kernel classes of spfd_timing / spfd_timing_get (order of the enum in spfd.h)
 KERNEL_CLASSES = ["spmv", "update", "dots", "pupdate", "smooth0", "smooth0_first", "restrict0", "prolong0", "coarse",
                   "finish", "rhs", "efield", "gauge"]
@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     lib.spfd_solve.argtypes = [H, ctypes.POINTER(SolveOptions), P, ctypes.POINTER(RhsInfo)]
     lib.spfd_efield.argtypes = [H, D, P, P, P, P]
     lib.spfd_adjoint.argtypes = [H, D, P, P, P, ctypes.POINTER(SolveOptions), P, P, ctypes.POINTER(RhsInfo)]
+    lib.spfd_solve_many.argtypes = [ctypes.POINTER(H), I, ctypes.POINTER(SolveOptions), ctypes.POINTER(P),
+                                    ctypes.POINTER(RhsInfo)]
     lib.spfd_timing.argtypes = [H, ctypes.c_uint]
     lib.spfd_timing_get.argtypes = [H, I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D), ctypes.POINTER(D)]
     for name in EXPORTS:
@@ -181,6 +183,33 @@ def spfd_solve(h, opts: SolveOptions | None, psi, nrhs: int):
     return st, [i.as_dict() for i in info]
 
 
+def spfd_solve_many(handles, opts: SolveOptions | None, psis, nrhs_total: int):
+    """Solve several built handles together; psis[k] is handle k's output tensor."""
+    import torch
+    for t in psis:
+        _require_cuda(t, torch.float64, None, "psi")
+    n = len(handles)
+    harr = (ctypes.c_void_p * n)(*[h.value for h in handles])
+    parr = (ctypes.c_void_p * n)(*[t.data_ptr() for t in psis])
+    info = (RhsInfo * nrhs_total)()
+    st = load_library().spfd_solve_many(harr, n, ctypes.byref(opts) if opts is not None else None, parr, info)
+    _check(handles[0], st, allow=(5, 6))
+    return st, [i.as_dict() for i in info]
+
+
+def solve_many(solvers, sources, tol=1e-8, max_iter=500):
+    """Solve one source per Solver (each with its own stream) in lockstep; returns (psis, infos)."""
+    import torch
+    torch.cuda.current_stream().synchronize()   # inputs written on the current stream are complete
+    psis = []
+    for s, a in zip(solvers, sources):
+        s.set_sources(a)
+        psis.append(torch.empty((s.nrhs,) + s.node_shape, dtype=torch.float64, device=s.device))
+    st, info = spfd_solve_many([s.handle for s in solvers], SolveOptions(tol, max_iter, 0), psis,
+                               sum(s.nrhs for s in solvers))
+    return [p[0] if p.shape[0] == 1 else p for p in psis], info
+
+
 def spfd_efield(h, omega, a, psi, u_edges, emag):
     import torch
     for t, n in ((a, "a"), (psi, "psi"), (emag, "emag")):
@@ -224,12 +253,13 @@ class Solver:
     """
 
     def __init__(self, labels, sigma, h, precision="fp64", device=None, smooth_degree=2, coarsest_max=1024,
-                 cheby_ratio=8.0, coarse_scale=1.8, cycle="v", split_level=2, split=True):
+                 cheby_ratio=8.0, coarse_scale=1.8, cycle="v", split_level=2, split=True, stream=None):
         import torch
         self.device = labels.device if device is None else torch.device(device)
         self.nz, self.ny, self.nx = labels.shape
         self.h = tuple(float(v) for v in h)
-        stream = torch.cuda.current_stream(self.device).cuda_stream
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        stream = self.stream.cuda_stream
         self.handle = spfd_create(self.device.index or 0, stream)
         try:
             spfd_set_geometry(self.handle, self.nx, self.ny, self.nz, *self.h, labels)

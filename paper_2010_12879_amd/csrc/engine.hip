@@ -96,8 +96,9 @@ struct Ctx {
     int nrhs = 0;
     double *d_bs = nullptr;   // right sides [nrhs][n0]
     std::vector<int> has_source;
-    double *d_x = nullptr, *d_r = nullptr, *d_p = nullptr, *d_q = nullptr;
+    double *d_x = nullptr, *d_r = nullptr, *d_p = nullptr, *d_p2 = nullptr, *d_q = nullptr;
     void *d_z = nullptr;
+    float *d_r32 = nullptr;
     Scal *d_scal = nullptr;
     Scal *h_scal = nullptr;   // pinned, one per right side plus one for the adjoint solve
     // adjoint solve
@@ -489,14 +490,14 @@ void coarse_solve(Ctx *c, const TB *b, T *x, const Scal *sc, int nb)
 }
 
 // z = B r for a batch of nb right sides: one V-cycle (T = arithmetic of the
-// cycle); r is the FP64 outer residual
-template <typename T>
-void vcycle(Ctx *c, const double *r, T *z, const Scal *sc, int nb)
+// cycle); r is the outer residual (FP64, or its FP32 copy for an FP32 cycle)
+template <typename T, typename TR>
+void vcycle(Ctx *c, const TR *r, T *z, const Scal *sc, int nb)
 {
     const int nl = (int)c->lv.size();
     std::vector<T *> res(nl, nullptr);
     if (nl == 1) {
-        coarse_solve<T, double>(c, r, z, sc, nb);  // single level: the dense solve is exact
+        coarse_solve<T, TR>(c, r, z, sc, nb);  // single level: the dense solve is exact
         return;
     }
     // downward: pre-smooth, restrict the residual.  The smoother ping-pongs
@@ -507,8 +508,8 @@ void vcycle(Ctx *c, const double *r, T *z, const Scal *sc, int nb)
         T *cur = (T *)L.x2;
         T *other = l == 0 ? z : (T *)L.x;
         if (l == 0) {
-            smooth_pre<T, double>(c, l, r, cur, other, sc, nb);
-            restrict_level<T, double>(c, l, r, cur, sc, nb);
+            smooth_pre<T, TR>(c, l, r, cur, other, sc, nb);
+            restrict_level<T, TR>(c, l, r, cur, sc, nb);
         } else {
             smooth_pre<T, T>(c, l, (const T *)L.b, cur, other, sc, nb);
             restrict_level<T, T>(c, l, (const T *)L.b, cur, sc, nb);
@@ -526,7 +527,7 @@ void vcycle(Ctx *c, const double *r, T *z, const Scal *sc, int nb)
         T *other = (cur == (T *)L.x2) ? (l == 0 ? z : (T *)L.x) : (T *)L.x2;
         prolong_level<T>(c, l, cur, sc, nb);
         if (l == 0)
-            smooth_post<T, double>(c, l, r, cur, other, sc, nb);
+            smooth_post<T, TR>(c, l, r, cur, other, sc, nb);
         else
             smooth_post<T, T>(c, l, (const T *)L.b, cur, other, sc, nb);
         T *want = l == 0 ? z : (T *)L.x;
@@ -594,10 +595,13 @@ void alloc_cycle_buffers(Ctx *c, int nb)
     c->d_x = dalloc<double>(c, c->rhs_allocs, n0);
     c->d_r = dalloc<double>(c, c->rhs_allocs, n0);
     c->d_p = dalloc<double>(c, c->rhs_allocs, n0);
+    c->d_p2 = dalloc<double>(c, c->rhs_allocs, n0);
     c->d_q = dalloc<double>(c, c->rhs_allocs, n0);
     c->d_z = dalloc<uint8_t>(c, c->rhs_allocs, n0 * w);
+    c->d_r32 = mixed ? dalloc<float>(c, c->rhs_allocs, n0) : nullptr;
     HIPCHK(hipMemsetAsync(c->d_z, 0, n0 * w, c->stream));
     HIPCHK(hipMemsetAsync(c->d_p, 0, n0 * sizeof(double), c->stream));
+    HIPCHK(hipMemsetAsync(c->d_p2, 0, n0 * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(c->d_q, 0, n0 * sizeof(double), c->stream));
     c->pstride = 2 * c->lv[0].nb + 64;
     c->d_part = dalloc<double>(c, c->rhs_allocs, (size_t)c->pstride * nb);
@@ -825,8 +829,27 @@ spfd_status do_set_num_rhs(Ctx *c, int nrhs)
     return SPFD_OK;
 }
 
+// The flexible CG of a batch, split into phases so that a driver can advance
+// several handles in lockstep: begin (z0 = B r0, r0.z0), step (one iteration),
+// end (the deferred x update).
 template <typename T>
-void pcg_iterations(Ctx *c, Scal *sc, Scal *hsc, int nb, const spfd_solve_options &so)
+void pcg_begin(Ctx *c, Scal *sc, int nb)
+{
+    Level &L0 = c->lv[0];
+    const Topo topo = L0.topo();
+    const Batch bt = level_batch(c, 0, nb);
+    T *z = (T *)c->d_z;
+    const double n0 = (double)L0.dofs * nb;
+    vcycle<T, double>(c, c->d_r, z, sc, nb);
+    {
+        TScope ts(c, SPFD_K_DOTS, n0 * (sizeof(T) + 8.0));
+        HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 1, bt, c->stream));
+    }
+    finish(c, topo.nb, FIN_BETA0, sc, 0, nb);
+}
+
+template <typename T>
+void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
 {
     Level &L0 = c->lv[0];
     const Topo topo = L0.topo();
@@ -835,43 +858,69 @@ void pcg_iterations(Ctx *c, Scal *sc, Scal *hsc, int nb, const spfd_solve_option
     T *z = (T *)c->d_z;
     const double n0 = (double)L0.dofs * nb;
     const double wz = sizeof(T);
-    vcycle<T>(c, c->d_r, z, sc, nb);
+    // an FP32 cycle reads an FP32 copy of the residual, written by the update kernel
+    float *r32 = sizeof(T) == sizeof(float) ? c->d_r32 : nullptr;
+    double *pbuf[2] = {c->d_p, c->d_p2};
+    // p_k = z_k + beta p_{k-1}, x_k = x_{k-1} + alpha p_{k-1}, q_k = A p_k
+    const int par = it & 1;
     {
-        TScope ts(c, SPFD_K_DOTS, n0 * (wz + 8.0));
-        HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 1, bt, c->stream));
+        TScope ts(c, SPFD_K_SPMV, n0 * (wz + (it ? 40.0 : 16.0) + op_bytes<double>(c, 0)));
+        HIPCHK(launch_cg_step<T>(op, topo, z, pbuf[par ^ 1], pbuf[par], c->d_x, c->d_q, c->d_part, sc, it == 0, par, bt,
+                                 c->stream));
     }
-    finish(c, topo.nb, FIN_BETA0, sc, 0, nb);
+    finish(c, topo.nb, FIN_ALPHA, sc, 0, nb);
     {
-        TScope ts(c, SPFD_K_PUPDATE, n0 * (wz + 8.0));
-        HIPCHK(launch_pupdate<T>(topo, z, c->d_p, sc, 1, bt, c->stream));
+        TScope ts(c, SPFD_K_UPDATE, n0 * (24.0 + (r32 ? 4.0 : 0.0)));
+        HIPCHK(launch_rupdate(topo, c->d_r, c->d_q, c->d_part, sc, bt, r32, c->stream));
     }
+    finish(c, topo.nb, FIN_RR, sc, max_iter, nb);
+    if (r32)
+        vcycle<T, float>(c, r32, z, sc, nb);
+    else
+        vcycle<T, double>(c, c->d_r, z, sc, nb);
+    {
+        TScope ts(c, SPFD_K_DOTS, n0 * (wz + 16.0));
+        HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 0, bt, c->stream));
+    }
+    finish(c, topo.nb, FIN_BETA, sc, 0, nb);
+}
+
+void pcg_end(Ctx *c, Scal *sc, int nb)
+{
+    // the update x += alpha p deferred by the last step of each right side
+    Level &L0 = c->lv[0];
+    TScope ts(c, SPFD_K_UPDATE, (double)L0.dofs * nb * 24.0);
+    HIPCHK(launch_x_final(L0.topo(), c->d_x, c->d_p, c->d_p2, sc, level_batch(c, 0, nb), c->stream));
+}
+
+void pcg_begin_any(Ctx *c, Scal *sc, int nb)
+{
+    if (c->opt.precision == SPFD_MIXED)
+        pcg_begin<float>(c, sc, nb);
+    else
+        pcg_begin<double>(c, sc, nb);
+}
+
+void pcg_step_any(Ctx *c, Scal *sc, int nb, int it, int max_iter)
+{
+    if (c->opt.precision == SPFD_MIXED)
+        pcg_step<float>(c, sc, nb, it, max_iter);
+    else
+        pcg_step<double>(c, sc, nb, it, max_iter);
+}
+
+void pcg_iterations(Ctx *c, Scal *sc, Scal *hsc, int nb, const spfd_solve_options &so)
+{
+    pcg_begin_any(c, sc, nb);
     for (int it = 0; it < so.max_iter + 1; ++it) {
-        {
-            TScope ts(c, SPFD_K_SPMV, n0 * (16.0 + op_bytes<double>(c, 0)));
-            HIPCHK(launch_spmv_dot(op, topo, c->d_p, c->d_q, c->d_part, sc, bt, c->stream));
-        }
-        finish(c, topo.nb, FIN_ALPHA, sc, 0, nb);
-        {
-            TScope ts(c, SPFD_K_UPDATE, n0 * 48.0);
-            HIPCHK(launch_update(topo, c->d_x, c->d_r, c->d_p, c->d_q, c->d_part, sc, bt, c->stream));
-        }
-        finish(c, topo.nb, FIN_RR, sc, so.max_iter, nb);
-        vcycle<T>(c, c->d_r, z, sc, nb);
-        {
-            TScope ts(c, SPFD_K_DOTS, n0 * (wz + 16.0));
-            HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 0, bt, c->stream));
-        }
-        finish(c, topo.nb, FIN_BETA, sc, 0, nb);
-        {
-            TScope ts(c, SPFD_K_PUPDATE, n0 * (wz + 16.0));
-            HIPCHK(launch_pupdate<T>(topo, z, c->d_p, sc, 0, bt, c->stream));
-        }
+        pcg_step_any(c, sc, nb, it, so.max_iter);
         HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         bool all = true;
         for (int i = 0; i < nb; ++i) all = all && hsc[i].done;
         if (all) break;
     }
+    pcg_end(c, sc, nb);
 }
 
 // r = b - A x for the batch and ||r||^2 (mode 0: start of a warm-started solve,
@@ -908,7 +957,6 @@ spfd_status solve_batch(Ctx *c, const double *b, long long bvs, Scal *sc, Scal *
     Level &L0 = c->lv[0];
     const Topo topo = L0.topo();
     const long long n0 = L0.nodes();
-    const bool mixed = c->opt.precision == SPFD_MIXED;
     const long long nn = (long long)c->g.Nx * c->g.Ny * c->g.Nz;
     HIPCHK(launch_scal_init(sc, so.rel_tol, so.use_x0, nb, c->stream));
     if (so.use_x0) {
@@ -932,10 +980,7 @@ spfd_status solve_batch(Ctx *c, const double *b, long long bvs, Scal *sc, Scal *
     }
     int *again = c->d_again;
     for (int pass = 0; pass < 3 && any; ++pass) {
-        if (mixed)
-            pcg_iterations<float>(c, sc, hsc, nb, so);
-        else
-            pcg_iterations<double>(c, sc, hsc, nb, so);
+        pcg_iterations(c, sc, hsc, nb, so);
         // true residual of every iterate (also of those that converged in an earlier pass)
         resid_b(c, b, bvs, sc, c->d_r, 1, nb);
         HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
@@ -984,6 +1029,105 @@ spfd_status do_solve(Ctx *c, const spfd_solve_options &so, double *psi, spfd_rhs
     if (worst != SPFD_OK)
         c->err = worst == SPFD_BREAKDOWN ? "breakdown in CG (non-positive curvature or non-finite value)"
                                          : "maximum iteration count reached";
+    return worst;
+}
+
+// Several handles (each with its own hierarchy, sources and stream) advanced
+// in lockstep: every iteration enqueues one CG step per unfinished handle on
+// that handle's stream, so the kernels of small problems run side by side on
+// the GPU, and one host poll serves all.  Handles that need a restart from the
+// true residual finish alone with solve_batch.
+spfd_status solve_many(Ctx **hs, int n, const spfd_solve_options &so, double **psi, spfd_rhs_info *info)
+{
+    std::vector<int> active(n, 0), steps(n, 0), off(n, 0);
+    int tot = 0;
+    for (int k = 0; k < n; ++k) {
+        off[k] = tot;
+        tot += hs[k]->nrhs;
+    }
+    // start: x0 = 0, r = b
+    for (int k = 0; k < n; ++k) {
+        Ctx *c = hs[k];
+        const long long n0 = c->lv[0].nodes();
+        HIPCHK(hipSetDevice(c->device));
+        HIPCHK(launch_scal_init(c->d_scal, so.rel_tol, 0, c->nrhs, c->stream));
+        HIPCHK(hipMemsetAsync(c->d_x, 0, c->nrhs * n0 * sizeof(double), c->stream));
+        HIPCHK(hipMemcpyAsync(c->d_r, c->d_bs, c->nrhs * n0 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_scal, c->d_scal, c->nrhs * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+    }
+    for (int k = 0; k < n; ++k) {
+        Ctx *c = hs[k];
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < c->nrhs; ++i) active[k] = active[k] || !c->h_scal[i].done;
+        if (active[k]) pcg_begin_any(c, c->d_scal, c->nrhs);
+    }
+    int left = 0;
+    for (int k = 0; k < n; ++k) left += active[k];
+    for (int it = 0; it < so.max_iter + 1 && left > 0; ++it) {
+        for (int k = 0; k < n; ++k)
+            if (active[k]) {
+                Ctx *c = hs[k];
+                pcg_step_any(c, c->d_scal, c->nrhs, steps[k]++, so.max_iter);
+                HIPCHK(hipMemcpyAsync(c->h_scal, c->d_scal, c->nrhs * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+            }
+        for (int k = 0; k < n; ++k)
+            if (active[k]) {
+                Ctx *c = hs[k];
+                HIPCHK(hipStreamSynchronize(c->stream));
+                bool all = true;
+                for (int i = 0; i < c->nrhs; ++i) all = all && c->h_scal[i].done;
+                if (all) {
+                    pcg_end(c, c->d_scal, c->nrhs);
+                    active[k] = 0;
+                    --left;
+                }
+            }
+    }
+    for (int k = 0; k < n; ++k)
+        if (active[k]) pcg_end(hs[k], hs[k]->d_scal, hs[k]->nrhs);
+    // true residuals, restarts, gauge and output
+    spfd_status worst = SPFD_OK;
+    for (int k = 0; k < n; ++k) {
+        Ctx *c = hs[k];
+        const int nb = c->nrhs;
+        const long long n0 = c->lv[0].nodes();
+        const long long nn = (long long)c->g.Nx * c->g.Ny * c->g.Nz;
+        resid_b(c, c->d_bs, n0, c->d_scal, c->d_r, 1, nb);
+        HIPCHK(hipMemcpyAsync(c->h_scal, c->d_scal, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        bool redo = false;
+        for (int i = 0; i < nb; ++i) {
+            const double bb = c->h_scal[i].bb;
+            const double rel = bb > 0.0 ? sqrt(c->h_scal[i].zq / bb) : 0.0;
+            if (bb > 0.0 && c->h_scal[i].status == 0 && rel > so.rel_tol && c->h_scal[i].iters < so.max_iter) redo = true;
+        }
+        spfd_status st;
+        if (redo) {
+            st = solve_batch(c, c->d_bs, n0, c->d_scal, c->h_scal, nb, so, psi[k], info ? info + off[k] : nullptr);
+        } else {
+            st = SPFD_OK;
+            const Level &L0 = c->lv[0];
+            for (int i = 0; i < nb; ++i) {
+                const double bb = c->h_scal[i].bb;
+                int status = c->h_scal[i].status;
+                const double rel = bb > 0.0 ? sqrt(c->h_scal[i].zq / bb) : 0.0;
+                if (bb > 0.0 && status == 0 && rel > so.rel_tol) status = SPFD_NOT_CONVERGED;
+                if (status != 0 && st == SPFD_OK) st = (spfd_status)status;
+                TScope ts(c, SPFD_K_GAUGE, (double)L0.dofs * 24.0 + nn * 8.0);
+                HIPCHK(launch_comp_mean(L0.topo(), c->d_x + i * n0, c->d_comp, c->ncomp, c->d_counts, c->d_means,
+                                        c->d_part, c->stream));
+                HIPCHK(launch_psi_out(c->d_x + i * n0, c->d_comp, c->d_means, L0.d_slot_of, c->g, psi[k] + i * nn,
+                                      c->stream));
+                if (info) {
+                    info[off[k] + i].iterations = c->h_scal[i].iters;
+                    info[off[k] + i].rel_residual = rel;
+                    info[off[k] + i].status = status;
+                }
+            }
+        }
+        if (st != SPFD_OK && worst == SPFD_OK) worst = st;
+    }
+    for (int k = 0; k < n; ++k) HIPCHK(hipStreamSynchronize(hs[k]->stream));
     return worst;
 }
 
@@ -1308,6 +1452,36 @@ spfd_status spfd_adjoint(spfd_handle h, double omega, const double *a, const dou
         return st;
     }
     API_GUARD(h)
+}
+
+spfd_status spfd_solve_many(spfd_handle *hs, int n, const spfd_solve_options *opt, double **psi, spfd_rhs_info *info)
+{
+    if (!hs || n <= 0 || !psi) return SPFD_INVALID_ARG;
+    for (int k = 0; k < n; ++k) {
+        if (!hs[k]) return SPFD_INVALID_ARG;
+        if (hs[k]->state < 4) return fail(hs[k], SPFD_BAD_STATE, "set the sources first");
+        for (int i = 0; i < hs[k]->nrhs; ++i)
+            if (!hs[k]->has_source[i]) return fail(hs[k], SPFD_BAD_STATE, "a right-hand side has no source");
+        if (!psi[k]) return fail(hs[k], SPFD_INVALID_ARG, "psi is NULL");
+        if (hs[k]->device != hs[0]->device) return fail(hs[k], SPFD_INVALID_ARG, "all handles must share one device");
+        for (int j = 0; j < k; ++j)
+            if (hs[j] == hs[k]) return fail(hs[k], SPFD_INVALID_ARG, "a handle appears twice");
+    }
+    spfd_solve_options so{};
+    so.rel_tol = 1e-8;
+    so.max_iter = 500;
+    if (opt) so = *opt;
+    so.use_x0 = 0;
+    if (!(so.rel_tol > 0.0) || !isfinite(so.rel_tol)) return fail(hs[0], SPFD_INVALID_ARG, "rel_tol must be positive");
+    if (so.max_iter <= 0) return fail(hs[0], SPFD_INVALID_ARG, "max_iter must be positive");
+    std::vector<Ctx *> cs(hs, hs + n);
+    try {
+        HIPCHK(hipSetDevice(hs[0]->device));
+        spfd_status st = solve_many(cs.data(), n, so, psi, info);
+        if (st != SPFD_OK) hs[0]->err = "a right-hand side did not converge or broke down";
+        return st;
+    }
+    API_GUARD(hs[0])
 }
 
 spfd_status spfd_timing(spfd_handle h, unsigned int class_mask)

@@ -81,8 +81,19 @@ hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, co
 hipError_t launch_scal_init(Scal *sc, double tol, int use_x0, int nbatch, hipStream_t s);
 hipError_t launch_spmv_dot(const OpArgs<double> &op, Topo topo, const double *p, double *q, double *part,
                            Scal *sc, const Batch &bt, hipStream_t s);
+// r32 (nullable): FP32 copy of the new residual for an FP32 cycle
 hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const double *q, double *part,
-                         Scal *sc, const Batch &bt, hipStream_t s);
+                         Scal *sc, const Batch &bt, float *r32, hipStream_t s);
+// fused CG step: p = z + beta p (p = z when first), x += alpha p_old (deferred), q = A p, p.q partials;
+// pin and pout are different buffers (neighbours read p_old)
+template <typename TZ>
+hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, const double *pin, double *pout,
+                          double *x, double *q, double *part, Scal *sc, int first, int parity, const Batch &bt,
+                          hipStream_t s);
+hipError_t launch_x_final(Topo topo, double *x, const double *pa, const double *pb, const Scal *sc, const Batch &bt,
+                          hipStream_t s);
+hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, Scal *sc, const Batch &bt, float *r32,
+                          hipStream_t s);
 // b has its own batch stride bvs (the right sides may live apart from the solve vectors)
 hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,
                         double *part, long long bvs, const Batch &bt, hipStream_t s);

@@ -747,6 +747,7 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
         break;
     case FIN_BETA0:
     case FIN_BETA: {
+        if (mode == FIN_BETA0) sc->pad = 0;
         double beta = 0.0;
         if (mode == FIN_BETA) beta = -sc->alpha * b / sc->rz;
         if (!(a > 0.0) || !isfinite(beta)) {
@@ -862,6 +863,126 @@ __global__ __launch_bounds__(NT) void k_spmv_dot(OpArgs<double> op, Topo topo, c
     if (t == 0) part[bk] = tot;
 }
 
+// Fused outer CG step (flexible CG with the x update deferred by one step):
+//   x_k   = x_{k-1} + alpha_{k-1} p_{k-1}        (skipped on the first step)
+//   p_k   = z_k + beta_{k-1} p_{k-1}             (p_k = z_k on the first step)
+//   q_k   = A p_k, and the partials of p_k.q_k
+// p_k at the six neighbours is formed on the fly from z and p_{k-1}.
+// pin and pout are different buffers (neighbours read p_{k-1} while others
+// write p_k); the step records in sc->pad which buffer holds the pending p
+// (1 + parity), so that the deferred update finds it per right side.
+template <typename TZ>
+__global__ __launch_bounds__(NT) void k_cg_step(OpArgs<double> op, Topo topo, const TZ *__restrict__ z,
+                                                const double *__restrict__ pin, double *__restrict__ pout,
+                                                double *__restrict__ x, double *__restrict__ q, double *part,
+                                                Scal *sc, int first, int parity, long long vs, int ps)
+{
+    __shared__ double tile[TILE_VOX + 7];
+    __shared__ double red[8];
+    sc += blockIdx.y;
+    if (sc->done) return;
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    z += blockIdx.y * vs;
+    pin += blockIdx.y * vs;
+    pout += blockIdx.y * vs;
+    x += blockIdx.y * vs;
+    q += blockIdx.y * vs;
+    part += (long long)blockIdx.y * ps;
+    int nb[6];
+    brick_nbrs(topo.nbr, bk, nb);
+    const int t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const long long base = (long long)bk * BS;
+    long long I[6];
+    nbr_index(base, t, tx, ty, tz, nb, I);
+    const double beta = first ? 0.0 : sc->beta;
+    const double alpha = first ? 0.0 : sc->alpha;
+    double P[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) P[k] = first ? (double)z[I[k]] : (double)z[I[k]] + beta * pin[I[k]];
+    const double pold = first ? 0.0 : pin[base + t];
+    const double p0 = (double)z[base + t] + beta * pold;
+    const double x0 = x[base + t];
+    op_stage(op, bk, tile);
+    double W[6];
+    op_weights(op, tile, base, t, tx, ty, tz, I, W);
+    const double y = stencil_apply(p0, P, W);
+    if (!first) x[base + t] = x0 + alpha * pold;
+    if (blockIdx.x == 0 && t == 0) sc->pad = 1 + parity;
+    pout[base + t] = p0;
+    q[base + t] = y;
+    const double tot = block_sum(p0 * y, red);
+    if (t == 0) part[bk] = tot;
+}
+
+// x += alpha p: the update deferred by k_cg_step, applied once after the last
+// step of a pass, from the buffer that step wrote (sc->pad: 0 = none pending)
+__global__ __launch_bounds__(NT) void k_x_final(Topo topo, double *__restrict__ x, const double *__restrict__ pa,
+                                                const double *__restrict__ pb, const Scal *sc, long long vs)
+{
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    sc += blockIdx.y;
+    const int pend = sc->pad;
+    if (pend == 0) return;
+    const double *p = pend == 1 ? pa : pb;
+    const long long n = blockIdx.y * vs + (long long)bk * BS + threadIdx.x;
+    x[n] += sc->alpha * p[n];
+}
+
+template <typename TZ>
+hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, const double *pin, double *pout,
+                          double *x, double *q, double *part, Scal *sc, int first, int parity, const Batch &bt,
+                          hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    if (pin == pout) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cg_step<TZ>, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, z, pin, pout, x, q,
+                       part, sc, first, parity, bt.vs, bt.ps);
+    return hipGetLastError();
+}
+template hipError_t launch_cg_step<double>(const OpArgs<double> &, Topo, const double *, const double *, double *,
+                                           double *, double *, double *, Scal *, int, int, const Batch &, hipStream_t);
+template hipError_t launch_cg_step<float>(const OpArgs<double> &, Topo, const float *, const double *, double *,
+                                          double *, double *, double *, Scal *, int, int, const Batch &, hipStream_t);
+
+hipError_t launch_x_final(Topo topo, double *x, const double *pa, const double *pb, const Scal *sc, const Batch &bt,
+                          hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_x_final, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, x, pa, pb, sc, bt.vs);
+    return hipGetLastError();
+}
+
+// r -= alpha q, ||r||^2 partials and the FP32 copy of r (x is updated by k_cg_step)
+__global__ __launch_bounds__(NT) void k_rupdate(Topo topo, double *__restrict__ r, const double *__restrict__ q,
+                                                double *part, const Scal *sc, long long vs, int ps,
+                                                float *__restrict__ r32)
+{
+    __shared__ double red[8];
+    sc += blockIdx.y;
+    if (sc->done) return;
+    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    if (bk < 0) return;
+    const long long n = blockIdx.y * vs + (long long)bk * BS + threadIdx.x;
+    const double rn = r[n] - sc->alpha * q[n];
+    r[n] = rn;
+    if (r32) r32[n] = (float)rn;
+    const double tot = block_sum(rn * rn, red);
+    if (threadIdx.x == 0) part[(long long)blockIdx.y * ps + bk] = tot;
+}
+
+hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, Scal *sc, const Batch &bt, float *r32,
+                          hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rupdate, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, r, q, part, sc, bt.vs, bt.ps,
+                       r32);
+    return hipGetLastError();
+}
+
 hipError_t launch_spmv_dot(const OpArgs<double> &op, Topo topo, const double *p, double *q, double *part, Scal *sc,
                            const Batch &bt, hipStream_t s)
 {
@@ -874,7 +995,8 @@ hipError_t launch_spmv_dot(const OpArgs<double> &op, Topo topo, const double *p,
 // x += alpha p, r -= alpha q and the partials of ||r||^2 (stop test in k_finish)
 __global__ __launch_bounds__(NT) void k_update(Topo topo, double *__restrict__ x, double *__restrict__ r,
                                                const double *__restrict__ p, const double *__restrict__ q,
-                                               double *part, const Scal *sc, long long vs, int ps)
+                                               double *part, const Scal *sc, long long vs, int ps,
+                                               float *__restrict__ r32)
 {
     __shared__ double red[8];
     sc += blockIdx.y;
@@ -891,16 +1013,17 @@ __global__ __launch_bounds__(NT) void k_update(Topo topo, double *__restrict__ x
     x[n] += alpha * p[n];
     const double rn = r[n] - alpha * q[n];
     r[n] = rn;
+    if (r32) r32[blockIdx.y * vs + n] = (float)rn;
     const double tot = block_sum(rn * rn, red);
     if (threadIdx.x == 0) part[bk] = tot;
 }
 
 hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const double *q, double *part, Scal *sc,
-                         const Batch &bt, hipStream_t s)
+                         const Batch &bt, float *r32, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_update, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, x, r, p, q, part, sc, bt.vs,
-                       bt.ps);
+                       bt.ps, r32);
     return hipGetLastError();
 }
 

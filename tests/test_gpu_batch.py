@@ -68,3 +68,27 @@ def test_batch_with_zero_source_and_uneven_convergence():
         rel = oracle.residual(w.sigma_voxel(), w.h, srcs[i], psi[i].cpu().numpy())
         assert rel <= 1e-10 * 1.01, (i, rel)
     s.close()
+
+
+def test_solve_many_uneven_phantoms_equals_single():
+    print("case solve-many", flush=True)
+    sizes = [20, 28, 36, 44]
+    solvers, srcs, ws = [], [], []
+    for i, m in enumerate(sizes):
+        w = W.random_ellipsoid_phantom(m, m, m, seed=200 + i, n_ell=6, semi_range=(3.0, 8.0), name=f"e{m}")
+        ws.append(w)
+        st = torch.cuda.Stream(DEV)
+        solvers.append(P.Solver(_dev(w.labels), w.sigma_table, w.h, precision="mixed", stream=st))
+        srcs.append(_dev(w.a))
+    torch.cuda.synchronize()
+    psis, infos = P.solve_many(solvers, srcs, tol=1e-11)
+    assert all(i["status"] == "OK" for i in infos)
+    for k, (s, w) in enumerate(zip(solvers, ws)):
+        p1, i1 = s.solve(srcs[k], tol=1e-11)
+        torch.cuda.synchronize()
+        assert i1["iterations"] == infos[k]["iterations"]
+        assert torch.equal(p1, psis[k]), k
+        rel = oracle.residual(w.sigma_voxel(), w.h, w.a, psis[k].cpu().numpy())
+        assert rel <= 1e-11 * 1.01
+    for s in solvers:
+        s.close()
