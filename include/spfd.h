@@ -128,6 +128,15 @@ spfd_status spfd_solve(spfd_handle h, const spfd_solve_options *opt, double *psi
 spfd_status spfd_efield(spfd_handle h, double omega, const double *a, const double *psi,
                         double *u_edges, double *emag);
 
+/* Nearest-rank q-quantile of the voxel field |E| (step 6 of the paper's
+ * technical summary, Sec. II.A: the 99th percentile of the voxel-averaged
+ * field, Sec. III.F, q = 0.99): among the n conducting voxels (sigma > 0) the
+ * value of rank ceil(q n) in ascending order.  emag [nvox] (device), e.g. from
+ * spfd_efield.  out_body (host): whole body; out_labels (host, nullable): one
+ * value per label of the sigma table (256 in per-voxel mode), NaN for labels
+ * without conducting voxels.  Exact (radix selection on the FP64 values). */
+spfd_status spfd_percentile(spfd_handle h, const double *emag, double q, double *out_body, double *out_labels);
+
 /* Solve Eq. (3) on several voxel models at once (each handle built, with its
  * sources set, on the same device).  The CG iterations of all handles advance
  * in lockstep, each handle's kernels on its own stream, so that problems of

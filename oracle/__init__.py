@@ -186,3 +186,25 @@ def pnorm_objective(emag, p=8):
     J = float(np.sum(e ** p) ** (1.0 / p))
     g = (e / J) ** (p - 1) if J > 0 else np.zeros_like(e)
     return J, g
+
+
+def percentile_nearest_rank(emag, labels, q=0.99, n_labels=None):
+    """Nearest-rank q-quantile of the voxel |E| over the conducting voxels (step 6 of the
+    paper's technical summary, Sec. II.A; the voxel-averaged field, Sec. III.F), whole body
+    and per label: sort the n values ascending and take the one of rank ceil(q n) (1-based).
+    Air voxels (|E| = 0 with label 0) are excluded; a label without voxels gets NaN.
+    Returns (whole-body value, per-label array)."""
+    e = np.asarray(emag, dtype=np.float64).reshape(-1)
+    lab = np.asarray(labels).reshape(-1)
+    body = lab > 0
+
+    def nearest_rank(v):
+        if v.size == 0:
+            return float("nan")
+        v = np.sort(v)
+        r = int(np.ceil(q * v.size))
+        return float(v[max(r, 1) - 1])
+
+    n_labels = int(lab.max()) + 1 if n_labels is None else n_labels
+    per = np.array([nearest_rank(e[lab == t]) if t > 0 else float("nan") for t in range(n_labels)])
+    return nearest_rank(e[body]), per

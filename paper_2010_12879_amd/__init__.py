@@ -51,7 +51,7 @@ class RhsInfo(ctypes.Structure):
 _lib = None
 EXPORTS = ["spfd_create", "spfd_destroy", "spfd_last_error", "spfd_set_geometry", "spfd_set_sigma_table",
            "spfd_set_sigma_voxel", "spfd_build", "spfd_get_info", "spfd_set_num_rhs", "spfd_set_source",
-           "spfd_solve", "spfd_solve_many", "spfd_efield", "spfd_adjoint", "spfd_timing", "spfd_timing_get"]
+           "spfd_solve", "spfd_solve_many", "spfd_efield", "spfd_percentile", "spfd_adjoint", "spfd_timing", "spfd_timing_get"]
 # kernel classes of spfd_timing / spfd_timing_get (order of the enum in spfd.h)
 KERNEL_CLASSES = ["spmv", "update", "dots", "pupdate", "smooth0", "smooth0_first", "restrict0", "prolong0", "coarse",
                   "finish", "rhs", "efield", "gauge"]
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
     lib.spfd_solve.argtypes = [H, ctypes.POINTER(SolveOptions), P, ctypes.POINTER(RhsInfo)]
     lib.spfd_efield.argtypes = [H, D, P, P, P, P]
     lib.spfd_adjoint.argtypes = [H, D, P, P, P, ctypes.POINTER(SolveOptions), P, P, ctypes.POINTER(RhsInfo)]
+    lib.spfd_percentile.argtypes = [H, P, D, ctypes.POINTER(D), P]
     lib.spfd_solve_many.argtypes = [ctypes.POINTER(H), I, ctypes.POINTER(SolveOptions), ctypes.POINTER(P),
                                     ctypes.POINTER(RhsInfo)]
     lib.spfd_timing.argtypes = [H, ctypes.c_uint]
@@ -233,6 +234,16 @@ def spfd_adjoint(h, omega, a, psi, grad_emag, opts: SolveOptions | None, grad_si
     return st, (list(table) if table is not None else None), info.as_dict()
 
 
+def spfd_percentile(h, emag, q=0.99, n_labels=0):
+    """(whole-body quantile, per-label list or None) of the voxel |E| (nearest rank)."""
+    import torch
+    _require_cuda(emag, torch.float64, None, "emag")
+    body = ctypes.c_double()
+    labs = (ctypes.c_double * n_labels)() if n_labels else None
+    _check(h, load_library().spfd_percentile(h, _ptr(emag), float(q), ctypes.byref(body), labs))
+    return body.value, (list(labs) if labs is not None else None)
+
+
 def spfd_timing(h, class_mask: int):
     return _check(h, load_library().spfd_timing(h, class_mask))
 
@@ -341,6 +352,12 @@ class Solver:
         u = torch.empty((3,) + self.node_shape, dtype=torch.float64, device=self.device) if want_u else None
         spfd_efield(self.handle, omega, a.contiguous(), psi.contiguous(), u, emag)
         return (emag, u) if want_u else emag
+
+    def percentile(self, emag, q=0.99):
+        """(whole body, per-label list) nearest-rank q-quantile of |E| over conducting voxels."""
+        if emag.numel() != self.nx * self.ny * self.nz:
+            raise ValueError(f"emag must hold {self.nx * self.ny * self.nz} voxel values")
+        return spfd_percentile(self.handle, emag.contiguous(), q, self.n_table if self.n_table else 256)
 
     def close(self):
         if getattr(self, "handle", None) is not None:

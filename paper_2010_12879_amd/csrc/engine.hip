@@ -108,6 +108,9 @@ struct Ctx {
     double *d_adj_labpart = nullptr;
     double *d_adj_labout = nullptr;
     Scal *d_adj_scal = nullptr;
+    // quantile selection
+    uint8_t *d_sel_work = nullptr;
+    double *d_sel_out = nullptr;
     double *d_part = nullptr;
     int pstride = 0;          // partial sums per right side
     int *d_again = nullptr;   // per right side: restart from the true residual
@@ -1209,6 +1212,8 @@ spfd_status spfd_set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, 
         free_all(h, h->geo_allocs);
         h->d_adj_b = h->d_adj_c = h->d_adj_lam = h->d_adj_labpart = h->d_adj_labout = nullptr;
         h->d_adj_scal = nullptr;
+        h->d_sel_work = nullptr;
+        h->d_sel_out = nullptr;
         h->d_ints = dalloc<int>(h, h->geo_allocs, 64);
         h->lv.clear();
         h->g.nx = nx; h->g.ny = ny; h->g.nz = nz;
@@ -1482,6 +1487,37 @@ spfd_status spfd_solve_many(spfd_handle *hs, int n, const spfd_solve_options *op
         return st;
     }
     API_GUARD(hs[0])
+}
+
+spfd_status spfd_percentile(spfd_handle h, const double *emag, double q, double *out_body, double *out_labels)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (h->state < 2) return fail(h, SPFD_BAD_STATE, "set geometry and conductivities first");
+    if (!emag || !out_body) return fail(h, SPFD_INVALID_ARG, "emag and out_body are required");
+    if (!(q > 0.0 && q <= 1.0)) return fail(h, SPFD_INVALID_ARG, "q must be in (0, 1]");
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        const int nlab = h->voxel_mode ? MAX_LABELS : h->nlab;
+        const int ng = 1 + nlab;
+        if (!h->d_sel_work) {
+            h->d_sel_work = dalloc<uint8_t>(h, h->geo_allocs, sel_work_bytes(1 + MAX_LABELS));
+            h->d_sel_out = dalloc<double>(h, h->geo_allocs, 1 + MAX_LABELS);
+        }
+        const long long nvox = (long long)h->g.nx * h->g.ny * h->g.nz;
+        {
+            TScope ts(h, SPFD_K_EFIELD, 8.0 * nvox * 9.0);
+            HIPCHK(launch_quantiles(h->d_labels, h->d_table64, h->voxel_mode ? h->d_sigvox : nullptr, nvox, emag, ng, q,
+                                    h->d_sel_work, h->d_sel_out, h->stream));
+        }
+        double out[1 + MAX_LABELS];
+        HIPCHK(hipMemcpyAsync(out, h->d_sel_out, ng * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        *out_body = out[0];
+        if (out_labels)
+            for (int l = 0; l < nlab; ++l) out_labels[l] = out[1 + l];
+        return SPFD_OK;
+    }
+    API_GUARD(h)
 }
 
 spfd_status spfd_timing(spfd_handle h, unsigned int class_mask)

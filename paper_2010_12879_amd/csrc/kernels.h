@@ -187,6 +187,13 @@ hipError_t launch_coarse_enum_ell(int n, int K, const int *col, const double *va
 hipError_t launch_coarse_dense_ell(int nrow, int K, const int *col, const double *val, const int *dof_of_row,
                                    const int *row_of_dof, int n, double *A, hipStream_t s);
 
+// ---------------------------------------------------------------- quantiles of |E|
+size_t sel_work_bytes(int ngroups);
+// nearest-rank q-quantile over the conducting voxels: out[0] whole body,
+// out[1 + l] voxels with label l (NaN when empty); out and work on the device
+hipError_t launch_quantiles(const uint8_t *labels, const double *table, const double *sig_vox, long long nvox,
+                            const double *emag, int ngroups, double q, void *work, double *out, hipStream_t s);
+
 // ---------------------------------------------------------------- adjoint gradient
 hipError_t launch_adj_voxel(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,
                             const double h[3], double omega, const double *a, const double *psi,

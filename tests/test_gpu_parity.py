@@ -170,3 +170,23 @@ def test_warm_start_and_determinism():
     p3, i3 = s.solve(a, tol=1e-10, x0=p1)
     assert i3["iterations"] <= 1
     s.close()
+
+
+@pytest.mark.parametrize("q", [0.99, 0.5, 1.0])
+def test_percentile_matches_oracle(q):
+    print(f"case percentile q={q}", flush=True)
+    w = W.config(1)
+    s = P.Solver(_dev(w.labels), w.sigma_table, w.h)
+    a = _dev(w.a)
+    psi, info = s.solve(a, tol=1e-10)
+    emag = s.efield(a, psi, w.omega)
+    body, per = s.percentile(emag, q)
+    s.close()
+    e = emag.cpu().numpy()
+    ref, ref_per = oracle.percentile_nearest_rank(e, w.labels, q, n_labels=len(w.sigma_table))
+    assert body == ref
+    for t in range(1, len(w.sigma_table)):
+        if np.isnan(ref_per[t]):
+            assert np.isnan(per[t])
+        else:
+            assert per[t] == ref_per[t], t

@@ -339,3 +339,27 @@ def test_adjoint_against_finite_differences():
     for t in range(len(table)):
         assert abs(gt[t] - gs[labels == t].sum()) <= 1e-12 * (np.abs(gs).sum() + 1e-300)
     assert np.all(gs[sig == 0] == 0)
+
+
+# ---------------------------------------------------------------------------- percentile (step 6)
+def test_percentile_nearest_rank_by_hand():
+    # 10 values 1..10 in scrambled order: rank ceil(0.99*10) = 10 -> 10; q = 0.5 -> rank 5 -> 5
+    e = np.array([[[7.0, 2.0, 9.0, 1.0, 10.0, 3.0, 5.0, 8.0, 4.0, 6.0, 0.0]]])
+    lab = np.array([[[1, 1, 2, 1, 2, 1, 1, 2, 1, 1, 0]]])
+    p99, per = oracle.percentile_nearest_rank(e, lab, 0.99)
+    assert p99 == 10.0
+    p50, per50 = oracle.percentile_nearest_rank(e, lab, 0.5)
+    assert p50 == 5.0
+    # label 2 holds 9, 10, 8 -> rank ceil(0.5*3) = 2 -> 9; label 1 holds 7,2,1,3,5,4,6 -> rank 4 -> 4
+    assert per50[2] == 9.0 and per50[1] == 4.0 and np.isnan(per50[0])
+
+
+def test_percentile_matches_inverted_cdf():
+    rng = np.random.default_rng(5)
+    e = rng.lognormal(size=(7, 9, 11))
+    lab = rng.integers(0, 4, size=e.shape)
+    e[lab == 0] = 0.0
+    p, per = oracle.percentile_nearest_rank(e, lab, 0.99)
+    assert p == np.percentile(e[lab > 0], 99, method="inverted_cdf")
+    for t in range(1, 4):
+        assert per[t] == np.percentile(e[lab == t], 99, method="inverted_cdf")
