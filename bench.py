@@ -36,7 +36,26 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=150, help="oracle iterations in the bounded CPU sample")
     ap.add_argument("--precisions", default="mixed,fp64")
     ap.add_argument("--no-batch", action="store_true", help="skip the multi-source and multi-phantom runs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the runs, copy a MIB-sized device buffer 3 times (a plain copy kernel of known "
+                         "size, to scale hardware byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration(mib, torch):
+    """Device-to-device copies of a known size: reads and writes mib MiB each."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter() - t0)
+    return {"bytes_read": n * 8, "bytes_written": n * 8, "copies": 3,
+            "best_gbs": 2 * n * 8 / min(t) / 1e9}
 
 
 def run_precision(prec, w, lab, a, args, P, torch):
@@ -275,6 +294,8 @@ def main():
         print(f"# batch sources: {out['batch_sources']['batched_solve_s']:.3f} s", file=sys.stderr, flush=True)
         out["batch_phantoms"] = batch_phantoms(P, torch, args)
         print(f"# batch phantoms: {out['batch_phantoms']['lockstep_solve_s']:.3f} s", file=sys.stderr, flush=True)
+    if args.copy_calibration:
+        out["copy_calibration"] = copy_calibration(args.copy_calibration, torch)
     if not args.no_cpu_baseline:
         gold = os.path.join(ROOT, "tests", "golden", f"oracle_body_{args.tol:.0e}.json")
         iters_full = json.load(open(gold))["iterations"] if os.path.exists(gold) else None
