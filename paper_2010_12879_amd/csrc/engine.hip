@@ -871,7 +871,7 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
         HIPCHK(launch_cg_step<T>(op, topo, z, pbuf[par ^ 1], pbuf[par], c->d_x, c->d_q, c->d_part, sc, it == 0, par, bt,
                                  c->stream));
     }
-    finish(c, topo.nb, FIN_ALPHA, sc, 0, nb);
+    finish(c, cg_step_parts(topo.nb), FIN_ALPHA, sc, 0, nb);
     {
         TScope ts(c, SPFD_K_UPDATE, n0 * (24.0 + (r32 ? 4.0 : 0.0)));
         HIPCHK(launch_rupdate(topo, c->d_r, c->d_q, c->d_part, sc, bt, r32, c->stream));

@@ -86,6 +86,8 @@ hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const
                          Scal *sc, const Batch &bt, float *r32, hipStream_t s);
 // fused CG step: p = z + beta p (p = z when first), x += alpha p_old (deferred), q = A p, p.q partials;
 // pin and pout are different buffers (neighbours read p_old)
+// number of partial sums launch_cg_step writes per right side
+int cg_step_parts(int nb);
 template <typename TZ>
 hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, const double *pin, double *pout,
                           double *x, double *q, double *part, Scal *sc, int first, int parity, const Batch &bt,

@@ -863,60 +863,6 @@ __global__ __launch_bounds__(NT) void k_spmv_dot(OpArgs<double> op, Topo topo, c
     if (t == 0) part[bk] = tot;
 }
 
-// Fused outer CG step (flexible CG with the x update deferred by one step):
-//   x_k   = x_{k-1} + alpha_{k-1} p_{k-1}        (skipped on the first step)
-//   p_k   = z_k + beta_{k-1} p_{k-1}             (p_k = z_k on the first step)
-//   q_k   = A p_k, and the partials of p_k.q_k
-// p_k at the six neighbours is formed on the fly from z and p_{k-1}.
-// pin and pout are different buffers (neighbours read p_{k-1} while others
-// write p_k); the step records in sc->pad which buffer holds the pending p
-// (1 + parity), so that the deferred update finds it per right side.
-template <typename TZ>
-__global__ __launch_bounds__(NT) void k_cg_step(OpArgs<double> op, Topo topo, const TZ *__restrict__ z,
-                                                const double *__restrict__ pin, double *__restrict__ pout,
-                                                double *__restrict__ x, double *__restrict__ q, double *part,
-                                                Scal *sc, int first, int parity, long long vs, int ps)
-{
-    __shared__ double tile[TILE_VOX + 7];
-    __shared__ double red[8];
-    sc += blockIdx.y;
-    if (sc->done) return;
-    const int bk = xcd_brick(blockIdx.x, topo.nb);
-    if (bk < 0) return;
-    z += blockIdx.y * vs;
-    pin += blockIdx.y * vs;
-    pout += blockIdx.y * vs;
-    x += blockIdx.y * vs;
-    q += blockIdx.y * vs;
-    part += (long long)blockIdx.y * ps;
-    int nb[6];
-    brick_nbrs(topo.nbr, bk, nb);
-    const int t = threadIdx.x;
-    int tx, ty, tz;
-    brick_xyz(t, tx, ty, tz);
-    const long long base = (long long)bk * BS;
-    long long I[6];
-    nbr_index(base, t, tx, ty, tz, nb, I);
-    const double beta = first ? 0.0 : sc->beta;
-    const double alpha = first ? 0.0 : sc->alpha;
-    double P[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) P[k] = first ? (double)z[I[k]] : (double)z[I[k]] + beta * pin[I[k]];
-    const double pold = first ? 0.0 : pin[base + t];
-    const double p0 = (double)z[base + t] + beta * pold;
-    const double x0 = x[base + t];
-    op_stage(op, bk, tile);
-    double W[6];
-    op_weights(op, tile, base, t, tx, ty, tz, I, W);
-    const double y = stencil_apply(p0, P, W);
-    if (!first) x[base + t] = x0 + alpha * pold;
-    if (blockIdx.x == 0 && t == 0) sc->pad = 1 + parity;
-    pout[base + t] = p0;
-    q[base + t] = y;
-    const double tot = block_sum(p0 * y, red);
-    if (t == 0) part[bk] = tot;
-}
-
 // x += alpha p: the update deferred by k_cg_step, applied once after the last
 // step of a pass, from the buffer that step wrote (sc->pad: 0 = none pending)
 __global__ __launch_bounds__(NT) void k_x_final(Topo topo, double *__restrict__ x, const double *__restrict__ pa,
@@ -931,22 +877,6 @@ __global__ __launch_bounds__(NT) void k_x_final(Topo topo, double *__restrict__ 
     const long long n = blockIdx.y * vs + (long long)bk * BS + threadIdx.x;
     x[n] += sc->alpha * p[n];
 }
-
-template <typename TZ>
-hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, const double *pin, double *pout,
-                          double *x, double *q, double *part, Scal *sc, int first, int parity, const Batch &bt,
-                          hipStream_t s)
-{
-    if (topo.nb <= 0) return hipSuccess;
-    if (pin == pout) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_cg_step<TZ>, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, z, pin, pout, x, q,
-                       part, sc, first, parity, bt.vs, bt.ps);
-    return hipGetLastError();
-}
-template hipError_t launch_cg_step<double>(const OpArgs<double> &, Topo, const double *, const double *, double *,
-                                           double *, double *, double *, Scal *, int, int, const Batch &, hipStream_t);
-template hipError_t launch_cg_step<float>(const OpArgs<double> &, Topo, const float *, const double *, double *,
-                                          double *, double *, double *, Scal *, int, int, const Batch &, hipStream_t);
 
 hipError_t launch_x_final(Topo topo, double *x, const double *pa, const double *pb, const Scal *sc, const Batch &bt,
                           hipStream_t s)
@@ -1142,121 +1072,6 @@ __device__ __forceinline__ bool stopped(const Scal *sc)
     return sc && __hip_atomic_load(&sc[blockIdx.y].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// first Chebyshev step from a zero start: x = c0 D^-1 b (0 where D = 0)
-template <typename T, typename TB>
-__global__ __launch_bounds__(NT) void k_cheb_first(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
-                                                   T *__restrict__ x, T c0, const Scal *sc, long long vs)
-{
-    __shared__ T tile[TILE_VOX + 7];
-    if (stopped(sc)) return;
-    const int bk = xcd_brick(blockIdx.x, topo.nb);
-    if (bk < 0) return;
-    b += blockIdx.y * vs;
-    x += blockIdx.y * vs;
-    int nb[6];
-    brick_nbrs(topo.nbr, bk, nb);
-    const int t = threadIdx.x;
-    int tx, ty, tz;
-    brick_xyz(t, tx, ty, tz);
-    const long long base = (long long)bk * BS;
-    long long I[6];
-    nbr_index(base, t, tx, ty, tz, nb, I);
-    const T bv = (T)b[base + t];
-    op_stage(op, bk, tile);
-    T W[6];
-    op_weights(op, tile, base, t, tx, ty, tz, I, W);
-    const T D = diag_of(W);
-    x[base + t] = D > T(0) ? c0 * bv / D : T(0);
-}
-
-// general Chebyshev step: r = b - A xin; d = c1 d_old + c2 D^-1 r; xout = xin + d
-// (d_old = xin when din == nullptr, i.e. right after a zero start)
-template <typename T, typename TB>
-__global__ __launch_bounds__(NT) void k_cheb_step(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
-                                                  const T *__restrict__ xin, T *__restrict__ xout,
-                                                  const T *__restrict__ din, T *__restrict__ dout, T c1, T c2,
-                                                  const Scal *sc, long long vs)
-{
-    __shared__ T tile[TILE_VOX + 7];
-    if (stopped(sc)) return;
-    const int bk = xcd_brick(blockIdx.x, topo.nb);
-    if (bk < 0) return;
-    b += blockIdx.y * vs;
-    xin += blockIdx.y * vs;
-    xout += blockIdx.y * vs;
-    if (din) din += blockIdx.y * vs;
-    if (dout) dout += blockIdx.y * vs;
-    int nb[6];
-    brick_nbrs(topo.nbr, bk, nb);
-    const int t = threadIdx.x;
-    int tx, ty, tz;
-    brick_xyz(t, tx, ty, tz);
-    const long long base = (long long)bk * BS;
-    long long I[6];
-    nbr_index(base, t, tx, ty, tz, nb, I);
-    T X[6];
-    nbr_vals(xin, I, X);
-    const T x0 = xin[base + t];
-    const T bv = (T)b[base + t];
-    const T dold = din ? din[base + t] : x0;
-    op_stage(op, bk, tile);
-    T W[6];
-    op_weights(op, tile, base, t, tx, ty, tz, I, W);
-    const T D = diag_of(W);
-    T xo = T(0), dn = T(0);
-    if (D > T(0)) {
-        const T r = bv - stencil_apply(x0, X, W);
-        dn = c1 * dold + c2 * r / D;
-        xo = x0 + dn;
-    }
-    xout[base + t] = xo;
-    if (dout) dout[base + t] = dn;
-}
-
-// coarse right side: b_c = P^T (b - A x), P = 2x2x2 piecewise-constant aggregation
-template <typename T, typename TB>
-__global__ __launch_bounds__(NT) void k_resid_restrict(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
-                                                       const T *__restrict__ x, T *__restrict__ bc,
-                                                       const int *__restrict__ parent_slot,
-                                                       const int4 *__restrict__ fcoord, const Scal *sc, long long vs,
-                                                       long long vsc)
-{
-    __shared__ T tile[TILE_VOX + 7];
-    __shared__ T rs[BS];
-    if (stopped(sc)) return;
-    const int bk = xcd_brick(blockIdx.x, topo.nb);
-    if (bk < 0) return;
-    b += blockIdx.y * vs;
-    x += blockIdx.y * vs;
-    bc += blockIdx.y * vsc;
-    int nb[6];
-    brick_nbrs(topo.nbr, bk, nb);
-    const int t = threadIdx.x;
-    int tx, ty, tz;
-    brick_xyz(t, tx, ty, tz);
-    const long long base = (long long)bk * BS;
-    long long I[6];
-    nbr_index(base, t, tx, ty, tz, nb, I);
-    T X[6];
-    nbr_vals(x, I, X);
-    const T x0 = x[base + t];
-    const T bv = (T)b[base + t];
-    op_stage(op, bk, tile);
-    T W[6];
-    op_weights(op, tile, base, t, tx, ty, tz, I, W);
-    rs[t] = bv - stencil_apply(x0, X, W);
-    __syncthreads();
-    if (t < 64) {
-        const int cx = t & 3, cy = (t >> 2) & 3, cz = t >> 4;
-        const int f = 2 * cx + 16 * cy + 128 * cz;
-        const T s = ((((((rs[f] + rs[f + 1]) + rs[f + 8]) + rs[f + 9]) + rs[f + 64]) + rs[f + 65]) + rs[f + 72]) +
-                    rs[f + 73];
-        const int4 c = fcoord[bk];
-        const int ox = (c.x & 1) * 4, oy = (c.y & 1) * 4, oz = (c.z & 1) * 4;
-        bc[(long long)parent_slot[bk] * BS + (ox + cx) + 8 * (oy + cy) + 64 * (oz + cz)] = s;
-    }
-}
-
 // x += s * P x_c
 template <typename T>
 __global__ __launch_bounds__(NT) void k_prolong(Topo topo, T *__restrict__ x, const T *__restrict__ xc,
@@ -1300,36 +1115,6 @@ __global__ __launch_bounds__(256) void k_coarse_apply(const TB *__restrict__ bc,
     if (lane == 0) xc[node_of_dof[row]] = (T)s;
 }
 
-template <typename T, typename TB>
-hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, T c0, const Scal *sc, const Batch &bt,
-                             hipStream_t s)
-{
-    if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_cheb_first<T, TB>), dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, b, x, c0, sc,
-                       bt.vs);
-    return hipGetLastError();
-}
-
-template <typename T, typename TB>
-hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din, T *dout,
-                            T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s)
-{
-    if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_cheb_step<T, TB>), dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, b, xin, xout, din,
-                       dout, c1, c2, sc, bt.vs);
-    return hipGetLastError();
-}
-
-template <typename T, typename TB>
-hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, const T *x, T *bc, const int *parent_slot,
-                                 const int4 *fcoord, const Scal *sc, const Batch &bt, hipStream_t s)
-{
-    if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_resid_restrict<T, TB>), dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, b, x, bc,
-                       parent_slot, fcoord, sc, bt.vs, bt.vsc);
-    return hipGetLastError();
-}
-
 template <typename T>
 hipError_t launch_prolong(Topo topo, T *x, const T *xc, const int *parent_slot, const int4 *fcoord, T scale,
                           const Scal *sc, const Batch &bt, hipStream_t s)
@@ -1351,17 +1136,6 @@ hipError_t launch_coarse_apply(const TB *bc, T *xc, const double *Ainv, const in
     return hipGetLastError();
 }
 
-#define SPFD_INST_LEVEL(T, TB)                                                                                      \
-    template hipError_t launch_cheb_first<T, TB>(const OpArgs<T> &, Topo, const TB *, T *, T, const Scal *,       \
-                                                 const Batch &, hipStream_t);                                       \
-    template hipError_t launch_cheb_step<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *, const T *, T *, \
-                                                T, T, const Scal *, const Batch &, hipStream_t);                    \
-    template hipError_t launch_resid_restrict<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *,           \
-                                                     const int *, const int4 *, const Scal *, const Batch &,        \
-                                                     hipStream_t);
-SPFD_INST_LEVEL(double, double)
-SPFD_INST_LEVEL(float, float)
-SPFD_INST_LEVEL(float, double)
 template hipError_t launch_prolong<double>(Topo, double *, const double *, const int *, const int4 *, double,
                                            const Scal *, const Batch &, hipStream_t);
 template hipError_t launch_prolong<float>(Topo, float *, const float *, const int *, const int4 *, float, const Scal *,

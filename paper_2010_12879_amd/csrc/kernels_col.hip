@@ -1,0 +1,554 @@
+// Stencil kernels of the structured multigrid levels in column form.
+//
+// One wave owns a column segment of a brick: lane (tx, ty) = (lane & 7,
+// lane >> 3) holds the nodes (tx, ty, z0 .. z0+ZPL-1) in registers.  The z
+// neighbours of a node come from the lane's own registers, the four lateral
+// neighbours are plain loads (cache hits inside the brick), and every load of
+// the wave is independent of the others, so a wave has all of them in flight
+// at once.  The stencil needs no workgroup barrier: this is what keeps HBM
+// busy (a 512-thread brick workgroup with a barrier holds too few bytes in
+// flight per compute unit for the latency of HBM3E).
+//
+// Operator forms (Eq. (3), the matrix G^T M_sigma G):
+//  * label form (finest level): the conductivities of the voxel planes the
+//    segment touches are staged per wave in LDS, label -> sigma through a
+//    per-wave copy of the sigma table, and the six edge conductances of a node
+//    are formed on the fly with the same summation order as the setup kernel;
+//  * stored form (coarser structured levels, or per-voxel conductivities):
+//    three weight arrays (edge to +x, +y, +z); the minus-side weights are the
+//    plus-side weights of the minus neighbours.
+#include <math.h>
+
+#include "kernels.h"
+
+namespace spfd {
+
+constexpr int CWAVES = 4;                 // waves per workgroup
+constexpr int CTHREADS = 64 * CWAVES;
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ bool col_stopped(const Scal *sc)
+{
+    return sc && __hip_atomic_load(&sc[blockIdx.y].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Where a wave's segment lies.  Absent neighbour bricks hold no unknowns and
+// the edges into them have conductance 0; their slots are replaced by slots
+// of the lane's own column so that every lane issues the same loads.
+template <int ZPL>
+struct Seg {
+    static constexpr int WPB = 8 / ZPL;           // waves per brick
+    static constexpr int BPG = CWAVES / WPB;      // bricks per workgroup
+    int bk;                                       // brick (-1: this wave has none)
+    int grp;                                      // brick group of the workgroup (-1: padding)
+    int z0, lane, tx, ty;
+    long long self;                               // slot of (tx, ty, z0)
+    long long lat[4];                             // x-, x+, y-, y+ neighbours of (tx, ty, z0)
+    long long zm, zp;                             // (tx, ty, z0-1) and (tx, ty, z0+ZPL)
+    bool has[6];                                  // neighbour slot exists
+};
+
+template <int ZPL>
+__host__ __device__ __forceinline__ int col_ngroups(int nb)
+{
+    return (nb + Seg<ZPL>::BPG - 1) / Seg<ZPL>::BPG;
+}
+
+template <int ZPL>
+__device__ __forceinline__ Seg<ZPL> make_seg(const Topo &topo)
+{
+    Seg<ZPL> s;
+    const int ng = col_ngroups<ZPL>(topo.nb);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    s.grp = xcd_brick(blockIdx.x, ng);
+    s.lane = threadIdx.x & 63;
+    s.tx = s.lane & 7;
+    s.ty = s.lane >> 3;
+    s.z0 = (wave % Seg<ZPL>::WPB) * ZPL;
+    const int b = s.grp < 0 ? -1 : s.grp * Seg<ZPL>::BPG + wave / Seg<ZPL>::WPB;
+    s.bk = b < topo.nb ? b : -1;
+    if (s.bk < 0) return s;
+    int nb[6];
+    brick_nbrs(topo.nbr, s.bk, nb);
+    const long long base = (long long)s.bk * BS;
+    const int t0 = s.lane + 64 * s.z0;
+    s.self = base + t0;
+    s.has[NMX] = s.tx > 0 || nb[NMX] >= 0;
+    s.has[NPX] = s.tx < 7 || nb[NPX] >= 0;
+    s.has[NMY] = s.ty > 0 || nb[NMY] >= 0;
+    s.has[NPY] = s.ty < 7 || nb[NPY] >= 0;
+    s.lat[0] = s.tx > 0 ? s.self - 1 : (nb[NMX] >= 0 ? (long long)nb[NMX] * BS + t0 + 7 : s.self);
+    s.lat[1] = s.tx < 7 ? s.self + 1 : (nb[NPX] >= 0 ? (long long)nb[NPX] * BS + t0 - 7 : s.self);
+    s.lat[2] = s.ty > 0 ? s.self - 8 : (nb[NMY] >= 0 ? (long long)nb[NMY] * BS + t0 + 56 : s.self);
+    s.lat[3] = s.ty < 7 ? s.self + 8 : (nb[NPY] >= 0 ? (long long)nb[NPY] * BS + t0 - 56 : s.self);
+    if (s.z0 > 0) {
+        s.has[NMZ] = true;
+        s.zm = s.self - 64;
+    } else {
+        s.has[NMZ] = nb[NMZ] >= 0;
+        s.zm = s.has[NMZ] ? (long long)nb[NMZ] * BS + s.lane + 448 : s.self;
+    }
+    if (s.z0 + ZPL < 8) {
+        s.has[NPZ] = true;
+        s.zp = s.self + 64 * ZPL;
+    } else {
+        s.has[NPZ] = nb[NPZ] >= 0;
+        s.zp = s.has[NPZ] ? (long long)nb[NPZ] * BS + s.lane : s.self + 64 * (ZPL - 1);
+    }
+    return s;
+}
+
+// LDS per wave of the label form: sigma table copy + sigma of ZPL+1 voxel planes
+template <typename T, int ZPL>
+struct ColLds {
+    static constexpr int NE = 81 * (ZPL + 1);
+    static constexpr int PER_WAVE = MAX_LABELS + ((NE + 3) & ~3);
+};
+
+template <typename T, int ZPL, bool LABEL>
+struct SegOp;
+
+// Label form.  Plane c of the wave holds the voxels of tile plane z0 + c
+// (tile plane k = voxel layer below node layer k of the brick).
+template <typename T, int ZPL>
+struct SegOp<T, ZPL, true> {
+    static constexpr int NE = ColLds<T, ZPL>::NE;
+    static constexpr int NWD = (NE + 3) / 4;      // label dwords (81 z0 is a multiple of 4)
+    static constexpr int NLD = (NWD + 63) / 64;
+    uint32_t lab[NLD];
+    T tv[4];
+    T *tab, *sig;
+    T g[3];
+    T lo[4];
+
+    __device__ __forceinline__ void load(const OpArgs<T> &op, const Seg<ZPL> &s, T *lds)
+    {
+        tab = lds + (threadIdx.x >> 6) * ColLds<T, ZPL>::PER_WAVE;
+        sig = tab + MAX_LABELS;
+        g[0] = op.geo4[0];
+        g[1] = op.geo4[1];
+        g[2] = op.geo4[2];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) tv[k] = (s.lane + 64 * k < op.nlab) ? op.table[s.lane + 64 * k] : T(0);
+        const uint32_t *tl = (const uint32_t *)(op.tiles + (long long)s.bk * TILE_BYTES + 81 * s.z0);
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) lab[k] = (s.lane + 64 * k < NWD) ? tl[s.lane + 64 * k] : 0u;
+    }
+
+    __device__ __forceinline__ void stage(const OpArgs<T> &op, const Seg<ZPL> &s)
+    {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (s.lane + 64 * k < op.nlab) tab[s.lane + 64 * k] = tv[k];
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int e = 4 * (s.lane + 64 * k);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (e + m < NE) sig[e + m] = tab[(lab[k] >> (8 * m)) & 255u];
+        }
+        wave_sync();
+        plane(s, 0, lo);
+    }
+
+    __device__ __forceinline__ void plane(const Seg<ZPL> &s, int c, T q[4]) const
+    {
+        const T *p = sig + 81 * c + s.tx + 9 * s.ty;
+        q[0] = p[0];
+        q[1] = p[1];
+        q[2] = p[9];
+        q[3] = p[10];
+    }
+
+    // weights of node z0+z (call with z = 0, 1, ... in order); the sums keep the
+    // order of the setup kernel: (j-1,k-1), (j,k-1), (j-1,k), (j,k) of the other axes
+    __device__ __forceinline__ void weights(const Seg<ZPL> &s, int z, T W[6])
+    {
+        T hi[4];
+        plane(s, z + 1, hi);
+        W[NPX] = (((lo[1] + lo[3]) + hi[1]) + hi[3]) * g[0];
+        W[NMX] = (((lo[0] + lo[2]) + hi[0]) + hi[2]) * g[0];
+        W[NPY] = (((lo[2] + lo[3]) + hi[2]) + hi[3]) * g[1];
+        W[NMY] = (((lo[0] + lo[1]) + hi[0]) + hi[1]) * g[1];
+        W[NPZ] = (((hi[0] + hi[1]) + hi[2]) + hi[3]) * g[2];
+        W[NMZ] = (((lo[0] + lo[1]) + lo[2]) + lo[3]) * g[2];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lo[k] = hi[k];
+    }
+};
+
+// Stored form: w[d*stride + n] = conductance of the edge from n to +d.
+template <typename T, int ZPL>
+struct SegOp<T, ZPL, false> {
+    T wp[3][ZPL], wmx[ZPL], wmy[ZPL], wmz;
+
+    __device__ __forceinline__ void load(const OpArgs<T> &op, const Seg<ZPL> &s, T *)
+    {
+        const T *w = op.w;
+        const long long st = op.stride;
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) {
+            wp[0][z] = w[s.self + 64 * z];
+            wp[1][z] = w[st + s.self + 64 * z];
+            wp[2][z] = w[2 * st + s.self + 64 * z];
+            wmx[z] = w[s.lat[0] + 64 * z];
+            wmy[z] = w[st + s.lat[2] + 64 * z];
+        }
+        wmz = w[2 * st + s.zm];
+    }
+
+    __device__ __forceinline__ void stage(const OpArgs<T> &, const Seg<ZPL> &) {}
+
+    __device__ __forceinline__ void weights(const Seg<ZPL> &s, int z, T W[6])
+    {
+        W[NPX] = wp[0][z];
+        W[NPY] = wp[1][z];
+        W[NPZ] = wp[2][z];
+        W[NMX] = s.has[NMX] ? wmx[z] : T(0);
+        W[NMY] = s.has[NMY] ? wmy[z] : T(0);
+        W[NMZ] = z > 0 ? wp[2][z - 1] : (s.has[NMZ] ? wmz : T(0));
+    }
+};
+
+// values of x along the segment, its four lateral neighbour columns and the two z ends
+template <typename T, int ZPL>
+struct SegVals {
+    T c[ZPL], l[4][ZPL], zm, zp;
+
+    __device__ __forceinline__ void load(const T *__restrict__ x, const Seg<ZPL> &s)
+    {
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) {
+            c[z] = x[s.self + 64 * z];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) l[k][z] = x[s.lat[k] + 64 * z];
+        }
+        zm = x[s.zm];
+        zp = x[s.zp];
+    }
+
+    __device__ __forceinline__ void nbrs(int z, T N[6]) const
+    {
+        N[NMX] = l[0][z];
+        N[NPX] = l[1][z];
+        N[NMY] = l[2][z];
+        N[NPY] = l[3][z];
+        N[NMZ] = z > 0 ? c[z - 1] : zm;
+        N[NPZ] = z < ZPL - 1 ? c[z + 1] : zp;
+    }
+};
+
+template <typename T, int ZPL, bool LABEL>
+__device__ __forceinline__ T *col_lds()
+{
+    if constexpr (LABEL) {
+        __shared__ T lds[CWAVES * ColLds<T, ZPL>::PER_WAVE];
+        return lds;
+    } else {
+        return nullptr;
+    }
+}
+
+// ---------------------------------------------------------------- Chebyshev smoothing
+// first step from a zero start: x = c0 D^-1 b (0 where D = 0)
+template <typename T, typename TB, int ZPL, bool LABEL>
+__global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
+                                                             T *__restrict__ x, T c0, const Scal *sc, long long vs)
+{
+    T *lds = col_lds<T, ZPL, LABEL>();
+    if (col_stopped(sc)) return;
+    const Seg<ZPL> s = make_seg<ZPL>(topo);
+    if (s.bk < 0) return;
+    b += blockIdx.y * vs;
+    x += blockIdx.y * vs;
+    SegOp<T, ZPL, LABEL> A;
+    A.load(op, s, lds);
+    T bv[ZPL];
+#pragma unroll
+    for (int z = 0; z < ZPL; ++z) bv[z] = (T)b[s.self + 64 * z];
+    A.stage(op, s);
+#pragma unroll
+    for (int z = 0; z < ZPL; ++z) {
+        T W[6];
+        A.weights(s, z, W);
+        const T D = diag_of(W);
+        x[s.self + 64 * z] = D > T(0) ? c0 * bv[z] / D : T(0);
+    }
+}
+
+// general step: r = b - A xin; d = c1 d_old + c2 D^-1 r; xout = xin + d
+// (d_old = xin when din == nullptr, i.e. right after a zero start)
+template <typename T, typename TB, int ZPL, bool LABEL>
+__global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
+                                                            const T *__restrict__ xin, T *__restrict__ xout,
+                                                            const T *__restrict__ din, T *__restrict__ dout, T c1,
+                                                            T c2, const Scal *sc, long long vs)
+{
+    T *lds = col_lds<T, ZPL, LABEL>();
+    if (col_stopped(sc)) return;
+    const Seg<ZPL> s = make_seg<ZPL>(topo);
+    if (s.bk < 0) return;
+    b += blockIdx.y * vs;
+    xin += blockIdx.y * vs;
+    xout += blockIdx.y * vs;
+    if (din) din += blockIdx.y * vs;
+    if (dout) dout += blockIdx.y * vs;
+    SegOp<T, ZPL, LABEL> A;
+    A.load(op, s, lds);
+    SegVals<T, ZPL> X;
+    X.load(xin, s);
+    T bv[ZPL], dv[ZPL];
+#pragma unroll
+    for (int z = 0; z < ZPL; ++z) {
+        bv[z] = (T)b[s.self + 64 * z];
+        dv[z] = din ? din[s.self + 64 * z] : X.c[z];
+    }
+    A.stage(op, s);
+#pragma unroll
+    for (int z = 0; z < ZPL; ++z) {
+        T W[6], N[6];
+        A.weights(s, z, W);
+        X.nbrs(z, N);
+        const T D = diag_of(W);
+        T xo = T(0), dn = T(0);
+        if (D > T(0)) {
+            const T r = bv[z] - stencil_apply(X.c[z], N, W);
+            dn = c1 * dv[z] + c2 * r / D;
+            xo = X.c[z] + dn;
+        }
+        xout[s.self + 64 * z] = xo;
+        if (dout) dout[s.self + 64 * z] = dn;
+    }
+}
+
+// coarse right side b_c = P^T (b - A x), P = 2x2x2 piecewise-constant
+// aggregation: z pairs add in the lane, x pairs across lanes l, l+1, y pairs
+// across l, l+8; the lane of the even corner stores the aggregate
+template <typename T, typename TB, int ZPL, bool LABEL>
+__global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
+                                                                 const T *__restrict__ x, T *__restrict__ bc,
+                                                                 const int *__restrict__ parent_slot,
+                                                                 const int4 *__restrict__ fcoord, const Scal *sc,
+                                                                 long long vs, long long vsc)
+{
+    T *lds = col_lds<T, ZPL, LABEL>();
+    if (col_stopped(sc)) return;
+    const Seg<ZPL> s = make_seg<ZPL>(topo);
+    if (s.bk < 0) return;
+    b += blockIdx.y * vs;
+    x += blockIdx.y * vs;
+    bc += blockIdx.y * vsc;
+    SegOp<T, ZPL, LABEL> A;
+    A.load(op, s, lds);
+    SegVals<T, ZPL> X;
+    X.load(x, s);
+    T bv[ZPL];
+#pragma unroll
+    for (int z = 0; z < ZPL; ++z) bv[z] = (T)b[s.self + 64 * z];
+    const int4 fc = fcoord[s.bk];
+    const long long pbase = (long long)parent_slot[s.bk] * BS;
+    A.stage(op, s);
+    T r[ZPL];
+#pragma unroll
+    for (int z = 0; z < ZPL; ++z) {
+        T W[6], N[6];
+        A.weights(s, z, W);
+        X.nbrs(z, N);
+        r[z] = bv[z] - stencil_apply(X.c[z], N, W);
+    }
+    const int ox = (fc.x & 1) * 4 + (s.tx >> 1), oy = (fc.y & 1) * 4 + (s.ty >> 1);
+    const int oz = (fc.z & 1) * 4 + (s.z0 >> 1);
+    const bool corner = ((s.tx | s.ty) & 1) == 0;
+#pragma unroll
+    for (int k = 0; k < ZPL / 2; ++k) {
+        T a = r[2 * k] + r[2 * k + 1];
+        a += __shfl_down(a, 1, 64);
+        a += __shfl_down(a, 8, 64);
+        if (corner) bc[pbase + ox + 8 * oy + 64 * (oz + k)] = a;
+    }
+}
+
+// ---------------------------------------------------------------- outer CG step
+// Fused flexible-CG step with the x update deferred by one step:
+//   x_k = x_{k-1} + alpha_{k-1} p_{k-1}   (skipped on the first step)
+//   p_k = z_k + beta_{k-1} p_{k-1}        (p_k = z_k on the first step)
+//   q_k = A p_k and the partials of p_k.q_k (one per workgroup)
+// p_k at the neighbours is formed from z and p_{k-1}; pin and pout are
+// different buffers.  The step records in sc->pad which buffer holds the
+// pending p (1 + parity) for the final deferred update.
+template <typename TZ, int ZPL, bool LABEL>
+__global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Topo topo, const TZ *__restrict__ zv,
+                                                          const double *__restrict__ pin, double *__restrict__ pout,
+                                                          double *__restrict__ x, double *__restrict__ q,
+                                                          double *part, Scal *sc, int first, int parity, long long vs,
+                                                          int ps)
+{
+    double *lds = col_lds<double, ZPL, LABEL>();
+    __shared__ double red[CWAVES];
+    sc += blockIdx.y;
+    if (sc->done) return;
+    const Seg<ZPL> s = make_seg<ZPL>(topo);
+    if (s.grp < 0) return;
+    zv += blockIdx.y * vs;
+    pin += blockIdx.y * vs;
+    pout += blockIdx.y * vs;
+    x += blockIdx.y * vs;
+    q += blockIdx.y * vs;
+    part += (long long)blockIdx.y * ps;
+    double dot = 0.0;
+    if (s.bk >= 0) {
+        SegOp<double, ZPL, LABEL> A;
+        A.load(op, s, lds);
+        SegVals<TZ, ZPL> Z;
+        Z.load(zv, s);
+        SegVals<double, ZPL> Pi;
+        double xv[ZPL];
+        if (!first) {
+            Pi.load(pin, s);
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) xv[z] = x[s.self + 64 * z];
+        }
+        const double beta = first ? 0.0 : sc->beta;
+        const double alpha = first ? 0.0 : sc->alpha;
+        // p_k on the segment and its neighbours
+        SegVals<double, ZPL> P;
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) {
+            P.c[z] = first ? (double)Z.c[z] : (double)Z.c[z] + beta * Pi.c[z];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) P.l[k][z] = first ? (double)Z.l[k][z] : (double)Z.l[k][z] + beta * Pi.l[k][z];
+        }
+        P.zm = first ? (double)Z.zm : (double)Z.zm + beta * Pi.zm;
+        P.zp = first ? (double)Z.zp : (double)Z.zp + beta * Pi.zp;
+        A.stage(op, s);
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) {
+            double W[6], N[6];
+            A.weights(s, z, W);
+            P.nbrs(z, N);
+            const double y = stencil_apply(P.c[z], N, W);
+            const long long n = s.self + 64 * z;
+            if (!first) x[n] = xv[z] + alpha * Pi.c[z];
+            pout[n] = P.c[z];
+            q[n] = y;
+            dot += P.c[z] * y;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->pad = 1 + parity;
+    dot = wave_sum(dot);
+    if (s.lane == 0) red[threadIdx.x >> 6] = dot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < CWAVES; ++w) t += red[w];
+        part[s.grp] = t;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+// segment lengths: 8 nodes per lane in FP32 (one wave per brick), 4 in FP64
+// and in the CG step (two waves per brick), which hold twice the registers per node
+template <typename T>
+constexpr int zpl_cycle() { return sizeof(T) == 4 ? 8 : 4; }
+constexpr int ZPL_CG = 4;
+
+int cg_step_parts(int nb) { return col_ngroups<ZPL_CG>(nb); }
+
+template <int ZPL>
+static dim3 col_grid(int nb, int nbatch)
+{
+    return dim3(xcd_grid(col_ngroups<ZPL>(nb)), nbatch);
+}
+
+template <typename T, typename TB>
+hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, T c0, const Scal *sc, const Batch &bt,
+                             hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    constexpr int ZPL_CYCLE = zpl_cycle<T>();
+    const dim3 g = col_grid<ZPL_CYCLE>(topo.nb, bt.n);
+    if (op.w)
+        hipLaunchKernelGGL((k_col_cheb_first<T, TB, ZPL_CYCLE, false>), g, dim3(CTHREADS), 0, s, op, topo, b, x, c0, sc,
+                           bt.vs);
+    else
+        hipLaunchKernelGGL((k_col_cheb_first<T, TB, ZPL_CYCLE, true>), g, dim3(CTHREADS), 0, s, op, topo, b, x, c0, sc,
+                           bt.vs);
+    return hipGetLastError();
+}
+
+template <typename T, typename TB>
+hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din, T *dout,
+                            T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    if (xin == xout) return hipErrorInvalidValue;
+    constexpr int ZPL_CYCLE = zpl_cycle<T>();
+    const dim3 g = col_grid<ZPL_CYCLE>(topo.nb, bt.n);
+    if (op.w)
+        hipLaunchKernelGGL((k_col_cheb_step<T, TB, ZPL_CYCLE, false>), g, dim3(CTHREADS), 0, s, op, topo, b, xin, xout,
+                           din, dout, c1, c2, sc, bt.vs);
+    else
+        hipLaunchKernelGGL((k_col_cheb_step<T, TB, ZPL_CYCLE, true>), g, dim3(CTHREADS), 0, s, op, topo, b, xin, xout,
+                           din, dout, c1, c2, sc, bt.vs);
+    return hipGetLastError();
+}
+
+template <typename T, typename TB>
+hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, const T *x, T *bc, const int *parent_slot,
+                                 const int4 *fcoord, const Scal *sc, const Batch &bt, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    constexpr int ZPL_CYCLE = zpl_cycle<T>();
+    const dim3 g = col_grid<ZPL_CYCLE>(topo.nb, bt.n);
+    if (op.w)
+        hipLaunchKernelGGL((k_col_resid_restrict<T, TB, ZPL_CYCLE, false>), g, dim3(CTHREADS), 0, s, op, topo, b, x,
+                           bc, parent_slot, fcoord, sc, bt.vs, bt.vsc);
+    else
+        hipLaunchKernelGGL((k_col_resid_restrict<T, TB, ZPL_CYCLE, true>), g, dim3(CTHREADS), 0, s, op, topo, b, x,
+                           bc, parent_slot, fcoord, sc, bt.vs, bt.vsc);
+    return hipGetLastError();
+}
+
+template <typename TZ>
+hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, const double *pin, double *pout,
+                          double *x, double *q, double *part, Scal *sc, int first, int parity, const Batch &bt,
+                          hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    if (pin == pout) return hipErrorInvalidValue;
+    const dim3 g = col_grid<ZPL_CG>(topo.nb, bt.n);
+    if (op.w)
+        hipLaunchKernelGGL((k_col_cg_step<TZ, ZPL_CG, false>), g, dim3(CTHREADS), 0, s, op, topo, z, pin, pout, x, q,
+                           part, sc, first, parity, bt.vs, bt.ps);
+    else
+        hipLaunchKernelGGL((k_col_cg_step<TZ, ZPL_CG, true>), g, dim3(CTHREADS), 0, s, op, topo, z, pin, pout, x, q,
+                           part, sc, first, parity, bt.vs, bt.ps);
+    return hipGetLastError();
+}
+
+#define SPFD_INST_COL(T, TB)                                                                                          \
+    template hipError_t launch_cheb_first<T, TB>(const OpArgs<T> &, Topo, const TB *, T *, T, const Scal *,       \
+                                                 const Batch &, hipStream_t);                                       \
+    template hipError_t launch_cheb_step<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *, const T *, T *, \
+                                                T, T, const Scal *, const Batch &, hipStream_t);                    \
+    template hipError_t launch_resid_restrict<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *,           \
+                                                     const int *, const int4 *, const Scal *, const Batch &,        \
+                                                     hipStream_t);
+SPFD_INST_COL(double, double)
+SPFD_INST_COL(float, float)
+SPFD_INST_COL(float, double)
+
+template hipError_t launch_cg_step<double>(const OpArgs<double> &, Topo, const double *, const double *, double *,
+                                           double *, double *, double *, Scal *, int, int, const Batch &, hipStream_t);
+template hipError_t launch_cg_step<float>(const OpArgs<double> &, Topo, const float *, const double *, double *,
+                                          double *, double *, double *, Scal *, int, int, const Batch &, hipStream_t);
+
+}  // namespace spfd
