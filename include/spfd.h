@@ -80,6 +80,8 @@ typedef struct {
     double rel_tol;       /* stop when ||b - A Psi||_2 <= rel_tol * ||b||_2 (true residual at exit); default 1e-8 */
     int max_iter;         /* default 500 */
     int use_x0;           /* nonzero: psi holds the start iterate on entry */
+    int eager;            /* nonzero: launch every kernel from the host instead of replaying the
+                             captured HIP graph of a CG iteration (same kernels, same results) */
 } spfd_solve_options;
 
 typedef struct {
@@ -163,14 +165,14 @@ spfd_status spfd_adjoint(spfd_handle h, double omega, const double *a, const dou
 
 /* Per-launch timing, a tracing aid.  Kernel classes: */
 enum {
-    SPFD_K_SPMV = 0,          /* outer CG: q = A p on the finest level (FP64) and p.q partials */
-    SPFD_K_UPDATE = 1,        /* outer CG: x += alpha p, r -= alpha q, ||r||^2 partials */
-    SPFD_K_DOTS = 2,          /* outer CG: r.z and z.q partials */
-    SPFD_K_PUPDATE = 3,       /* outer CG: p = z + beta p */
+    SPFD_K_SPMV = 0,          /* outer CG: p = z + beta p, deferred x += alpha p, q = A p, p.q partials (FP64) */
+    SPFD_K_UPDATE = 1,        /* outer CG: r -= alpha q, ||r||^2 partials, FP32 copy of r; final x update */
+    SPFD_K_DOTS = 2,          /* outer CG: last finest-level smoothing step with the r.z and z.q partials */
+    SPFD_K_PUPDATE = 3,       /* (unused: p is formed inside the SPMV step) */
     SPFD_K_SMOOTH0 = 4,       /* finest level: Chebyshev step with a stencil application */
     SPFD_K_SMOOTH0_FIRST = 5, /* finest level: first Chebyshev step from zero (no stencil) */
     SPFD_K_RESTRICT0 = 6,     /* finest level: residual and restriction */
-    SPFD_K_PROLONG0 = 7,      /* finest level: prolongation and correction */
+    SPFD_K_PROLONG0 = 7,      /* finest level: first post-smoothing step with the prolongation */
     SPFD_K_COARSE = 8,        /* every kernel of the coarser levels and the coarsest solve */
     SPFD_K_FINISH = 9,        /* one-workgroup reduction finishers */
     SPFD_K_RHS = 10,          /* right side b = -G^T M a */
@@ -179,16 +181,19 @@ enum {
     SPFD_K_COUNT = 13
 };
 /* Enable timing for the classes in the bit mask (1 << class); resets all
- * counters.  While enabled, each launch of such a class is bracketed by two
- * HIP events on the handle's stream. */
+ * counters.  While enabled, the launches of such a class in the second CG
+ * iteration of every solve (run from the host, not from the captured graph)
+ * are bracketed by two HIP events on the handle's stream: a sample of every
+ * solve, at the cost of one eagerly launched iteration. */
 spfd_status spfd_timing(spfd_handle h, unsigned int class_mask);
-/* Launch count, summed event time (ms) and algorithmic bytes of a class since
- * the last spfd_timing call.  Algorithmic bytes count, per unknown of the level,
- * one read or write of each array the kernel touches (1 byte per voxel label,
- * 3 weights per node where weights are stored); bytes are counted whether or
- * not timing is enabled for the class. */
-spfd_status spfd_timing_get(spfd_handle h, int kclass, long long *launches, double *total_ms,
-                            double *algorithmic_bytes);
+/* Counters of a class since the last spfd_timing call: all launches and their
+ * algorithmic bytes (counted whether or not the class is timed), and the timed
+ * launches with their summed event time (ms) and algorithmic bytes.
+ * Algorithmic bytes count, per unknown of the level, one read or write of each
+ * array the kernel touches (1 byte per voxel label, 3 weights per node where
+ * weights are stored).  Any output pointer may be NULL. */
+spfd_status spfd_timing_get(spfd_handle h, int kclass, long long *launches, double *algorithmic_bytes,
+                            long long *timed_launches, double *timed_ms, double *timed_bytes);
 
 #ifdef __cplusplus
 }

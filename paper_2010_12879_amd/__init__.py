@@ -38,7 +38,8 @@ class AmgOptions(ctypes.Structure):
 
 
 class SolveOptions(ctypes.Structure):
-    _fields_ = [("rel_tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("use_x0", ctypes.c_int)]
+    _fields_ = [("rel_tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("use_x0", ctypes.c_int),
+                ("eager", ctypes.c_int)]
 
 
 class RhsInfo(ctypes.Structure):
@@ -88,7 +89,8 @@ def load_library(path: str = LIB_PATH):
     lib.spfd_solve_many.argtypes = [ctypes.POINTER(H), I, ctypes.POINTER(SolveOptions), ctypes.POINTER(P),
                                     ctypes.POINTER(RhsInfo)]
     lib.spfd_timing.argtypes = [H, ctypes.c_uint]
-    lib.spfd_timing_get.argtypes = [H, I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D), ctypes.POINTER(D)]
+    LL = ctypes.POINTER(ctypes.c_longlong)
+    lib.spfd_timing_get.argtypes = [H, I, LL, ctypes.POINTER(D), LL, ctypes.POINTER(D), ctypes.POINTER(D)]
     for name in EXPORTS:
         if name not in ("spfd_destroy", "spfd_last_error"):
             getattr(lib, name).restype = I
@@ -249,10 +251,14 @@ def spfd_timing(h, class_mask: int):
 
 
 def spfd_timing_get(h, kclass: int):
-    """(launches, total milliseconds, algorithmic bytes) of a kernel class."""
-    n, ms, by = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
-    _check(h, load_library().spfd_timing_get(h, kclass, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
-    return n.value, ms.value, by.value
+    """Counters of a kernel class: dict with launches, bytes (algorithmic, all launches),
+    timed_launches, timed_ms and timed_bytes (the event-timed sample)."""
+    n, by, tn, tms, tby = (ctypes.c_longlong(), ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double(),
+                           ctypes.c_double())
+    _check(h, load_library().spfd_timing_get(h, kclass, ctypes.byref(n), ctypes.byref(by), ctypes.byref(tn),
+                                             ctypes.byref(tms), ctypes.byref(tby)))
+    return {"launches": n.value, "bytes": by.value, "timed_launches": tn.value, "timed_ms": tms.value,
+            "timed_bytes": tby.value}
 
 
 # ---------------------------------------------------------------- convenience
@@ -330,8 +336,8 @@ class Solver:
         for r in range(a.shape[0]):
             spfd_set_source(self.handle, r, a[r].contiguous())
 
-    def solve(self, a=None, tol=1e-8, max_iter=500, x0=None, check=True):
-        """Psi (nrhs or none, Nz, Ny, Nx) and the per-source info dicts."""
+    def solve(self, a=None, tol=1e-8, max_iter=500, x0=None, check=True, eager=False):
+        """Psi (nrhs or none, Nz, Ny, Nx) and the per-source info dicts (eager: no graph replay)."""
         import torch
         squeeze = a is not None and a.dim() == 4
         if a is not None:
@@ -340,7 +346,8 @@ class Solver:
             psi = x0.reshape((self.nrhs,) + self.node_shape).clone().contiguous()
         else:
             psi = torch.empty((self.nrhs,) + self.node_shape, dtype=torch.float64, device=self.device)
-        st, info = spfd_solve(self.handle, SolveOptions(tol, max_iter, 1 if x0 is not None else 0), psi, self.nrhs)
+        st, info = spfd_solve(self.handle, SolveOptions(tol, max_iter, 1 if x0 is not None else 0, 1 if eager else 0),
+                              psi, self.nrhs)
         if check and st != 0:
             raise SPFDError(st, spfd_last_error(self.handle))
         return (psi[0] if squeeze else psi), (info[0] if squeeze else info)

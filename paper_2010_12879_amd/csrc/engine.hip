@@ -117,12 +117,27 @@ struct Ctx {
     int nbat = 0;             // right sides the solve buffers hold
     int *d_ints = nullptr;    // small scratch ints
     int *h_ints = nullptr;    // pinned
+    // the library's own stream (all work) and the caller's stream it follows
+    hipStream_t user_stream = nullptr;
+    hipEvent_t ev_user = nullptr;
+    // captured CG iterations (one per buffer parity), replayed with hipGraphLaunch
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        long long launch[SPFD_K_COUNT] = {};
+        double bytes[SPFD_K_COUNT] = {};
+    };
+    StepGraph sg[2];
+    int sg_nb = -1, sg_max_iter = -1;
+    const Scal *sg_sc = nullptr;
+    StepGraph *capturing = nullptr;
     // per-class launch timing (tracing aid)
     unsigned tmask = 0;
     std::vector<hipEvent_t> tev[SPFD_K_COUNT];
     size_t tused[SPFD_K_COUNT] = {};
     long long tlaunch[SPFD_K_COUNT] = {};
     double tbytes[SPFD_K_COUNT] = {};
+    long long ttimed[SPFD_K_COUNT] = {};    // launches with events, and their bytes
+    double ttbytes[SPFD_K_COUNT] = {};
     // bookkeeping: live allocations per owner, and released buffers kept for
     // reuse (a rebuild with the same geometry allocates nothing)
     std::vector<void *> geo_allocs, hier_allocs, rhs_allocs, src_allocs;
@@ -141,6 +156,15 @@ struct HipFail {
         hipError_t e_ = (__VA_ARGS__);                               \
         if (e_ != hipSuccess) throw HipFail{e_, #__VA_ARGS__};       \
     } while (0)
+
+void drop_graphs(Ctx *c);
+
+// order the library's stream after the work the caller has queued on its stream
+void enter(Ctx *c)
+{
+    HIPCHK(hipEventRecord(c->ev_user, c->user_stream));
+    HIPCHK(hipStreamWaitEvent(c->stream, c->ev_user, 0));
+}
 
 size_t size_of(Ctx *c, void *p)
 {
@@ -212,11 +236,21 @@ struct TScope {
     Ctx *c;
     int cls;
     bool on;
-    TScope(Ctx *c_, int cls_, double bytes) : c(c_), cls(cls_), on((c_->tmask >> cls_) & 1u)
+    TScope(Ctx *c_, int cls_, double bytes) : c(c_), cls(cls_), on(((c_->tmask >> cls_) & 1u) && !c_->capturing)
     {
+        if (c->capturing) {
+            // counted once per replay of the graph being captured
+            c->capturing->launch[cls] += 1;
+            c->capturing->bytes[cls] += bytes;
+            return;
+        }
         c->tlaunch[cls] += 1;
         c->tbytes[cls] += bytes;
-        if (on) record();
+        if (on) {
+            c->ttimed[cls] += 1;
+            c->ttbytes[cls] += bytes;
+            record();
+        }
     }
     ~TScope()
     {
@@ -388,9 +422,18 @@ void cheb_first(Ctx *c, int l, const TB *b, T *x, const Scal *sc, int nb)
     HIPCHK(launch_cheb_first<T, TB>(level_op<T>(c, l), L.topo(), b, x, (T)c->cheb_c0, sc, bt, c->stream));
 }
 
+// with_prolong: the step first adds coarse_scale * P x_c of the structured
+// level l+1 to xin (the prolongation fused into the first post-smoothing step)
+// CG dot products formed by the last finest-level smoothing step
+struct CycleDots {
+    const double *r = nullptr;
+    const double *q = nullptr;
+    double *part = nullptr;
+};
+
 template <typename T, typename TB>
 void cheb_step(Ctx *c, int l, const TB *b, const T *xin, T *xout, const T *din, T *dout, T c1, T c2, const Scal *sc,
-               int nb)
+               int nb, bool with_prolong = false, const CycleDots *dots = nullptr)
 {
     Level &L = c->lv[l];
     const Batch bt = level_batch(c, l, nb);
@@ -400,9 +443,16 @@ void cheb_step(Ctx *c, int l, const TB *b, const T *xin, T *xout, const T *din, 
                                        sc, bt, c->stream));
         return;
     }
-    const double per = sizeof(TB) + op_bytes<T>(c, l) + sizeof(T) * (2 + (din ? 1 : 0) + (dout ? 1 : 0));
-    TScope ts(c, l == 0 ? SPFD_K_SMOOTH0 : SPFD_K_COARSE, nb * (double)L.dofs * per);
-    HIPCHK(launch_cheb_step<T, TB>(level_op<T>(c, l), L.topo(), b, xin, xout, din, dout, c1, c2, sc, bt, c->stream));
+    double per = sizeof(TB) + op_bytes<T>(c, l) + sizeof(T) * (2 + (din ? 1 : 0) + (dout ? 1 : 0));
+    if (with_prolong) per += sizeof(T) / 8.0;
+    if (dots) per += 16.0;
+    const int cls = l == 0 ? (with_prolong ? SPFD_K_PROLONG0 : dots ? SPFD_K_DOTS : SPFD_K_SMOOTH0) : SPFD_K_COARSE;
+    TScope ts(c, cls, nb * (double)L.dofs * per);
+    const T *xc = nullptr;
+    if (with_prolong) xc = (const T *)c->lv[l + 1].x;
+    HIPCHK(launch_cheb_step<T, TB>(level_op<T>(c, l), L.topo(), b, xin, xout, din, dout, c1, c2, sc, bt, c->stream, xc,
+                                   L.d_parent_slot, L.d_coord, (T)c->opt.coarse_scale, dots ? dots->r : nullptr,
+                                   dots ? dots->q : nullptr, dots ? dots->part : nullptr));
 }
 
 template <typename T, typename TB>
@@ -419,14 +469,16 @@ void smooth_pre(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc, 
 }
 
 template <typename T, typename TB>
-void smooth_post(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc, int nb)
+void smooth_post(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc, int nb, bool with_prolong,
+                 const CycleDots *dots = nullptr)
 {
     const int m = c->opt.smooth_degree;
     T *d = (T *)c->lv[l].d;
     for (int k = 0; k < m; ++k) {
         const T c1 = k == 0 ? T(0) : (T)c->cheb_c1[k];
         const T c2 = k == 0 ? (T)c->cheb_c0 : (T)c->cheb_c2[k];
-        cheb_step<T, TB>(c, l, b, cur, other, k == 0 ? nullptr : d, k < m - 1 ? d : nullptr, c1, c2, sc, nb);
+        cheb_step<T, TB>(c, l, b, cur, other, k == 0 ? nullptr : d, k < m - 1 ? d : nullptr, c1, c2, sc, nb,
+                         with_prolong && k == 0, k == m - 1 ? dots : nullptr);
         T *t = cur; cur = other; other = t;
     }
 }
@@ -457,7 +509,9 @@ void restrict_level(Ctx *c, int l, const TB *b, const T *x, const Scal *sc, int 
             f.nbr = L.d_nbr;
         }
         TScope ts(c, SPFD_K_COARSE, nb * ((double)L.dofs * 3.0 * sizeof(T) + (double)C.nrow * 8.0));
-        HIPCHK(launch_restrict_members<T>(f, (const T *)b, x, C.nrow, C.d_mptr, C.d_mem, (T *)C.b, sc, bt, c->stream));
+        // the fine level's Chebyshev direction is free between pre- and post-smoothing
+        HIPCHK(launch_restrict_members<T>(f, L.nodes(), (const T *)b, x, (T *)L.d, C.nrow, C.d_mptr, C.d_mem,
+                                          (T *)C.b, sc, bt, c->stream));
         return;
     }
     const double by = nb * ((double)L.dofs * (sizeof(TB) + op_bytes<T>(c, l) + sizeof(T)) + (double)C.dofs * sizeof(T));
@@ -494,14 +548,17 @@ void coarse_solve(Ctx *c, const TB *b, T *x, const Scal *sc, int nb)
 
 // z = B r for a batch of nb right sides: one V-cycle (T = arithmetic of the
 // cycle); r is the outer residual (FP64, or its FP32 copy for an FP32 cycle)
+// dots (optional): the finest post-smoothing step also writes the partials of
+// z.r and z.q (cheb_dot_parts<T> per right side); returns false when the
+// cycle has no smoothing step to carry them (single level)
 template <typename T, typename TR>
-void vcycle(Ctx *c, const TR *r, T *z, const Scal *sc, int nb)
+bool vcycle(Ctx *c, const TR *r, T *z, const Scal *sc, int nb, const CycleDots *dots = nullptr)
 {
     const int nl = (int)c->lv.size();
     std::vector<T *> res(nl, nullptr);
     if (nl == 1) {
         coarse_solve<T, TR>(c, r, z, sc, nb);  // single level: the dense solve is exact
-        return;
+        return false;
     }
     // downward: pre-smooth, restrict the residual.  The smoother ping-pongs
     // between two buffers; starting in x2 makes the (2m-1) swaps of a level end
@@ -528,15 +585,18 @@ void vcycle(Ctx *c, const TR *r, T *z, const Scal *sc, int nb)
         Level &L = c->lv[l];
         T *cur = res[l];
         T *other = (cur == (T *)L.x2) ? (l == 0 ? z : (T *)L.x) : (T *)L.x2;
-        prolong_level<T>(c, l, cur, sc, nb);
+        // between two structured levels the prolongation rides on the first post-smoothing step
+        const bool fused = !L.ell && !c->lv[l + 1].ell;
+        if (!fused) prolong_level<T>(c, l, cur, sc, nb);
         if (l == 0)
-            smooth_post<T, TR>(c, l, r, cur, other, sc, nb);
+            smooth_post<T, TR>(c, l, r, cur, other, sc, nb, fused, dots);
         else
-            smooth_post<T, T>(c, l, (const T *)L.b, cur, other, sc, nb);
+            smooth_post<T, T>(c, l, (const T *)L.b, cur, other, sc, nb, fused);
         T *want = l == 0 ? z : (T *)L.x;
         if (cur != want)
             HIPCHK(hipMemcpyAsync(want, cur, nb * L.nodes() * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
     }
+    return dots != nullptr;
 }
 
 void finish(Ctx *c, int n, int mode, Scal *sc, int max_iter, int nb = 1)
@@ -579,6 +639,7 @@ void chebyshev_coefficients(Ctx *c)
 // CG vectors and the partial sums
 void alloc_cycle_buffers(Ctx *c, int nb)
 {
+    drop_graphs(c);
     free_all(c, c->rhs_allocs);
     const bool mixed = c->opt.precision == SPFD_MIXED;
     const size_t w = mixed ? sizeof(float) : sizeof(double);
@@ -687,6 +748,7 @@ Level split_level(Ctx *c, Level &F)
 
 spfd_status do_build(Ctx *c)
 {
+    drop_graphs(c);
     free_all(c, c->hier_allocs);
     c->d_adj_b = c->d_adj_c = c->d_adj_lam = c->d_adj_labpart = c->d_adj_labout = nullptr;
     c->d_adj_scal = nullptr;
@@ -843,7 +905,11 @@ void pcg_begin(Ctx *c, Scal *sc, int nb)
     const Batch bt = level_batch(c, 0, nb);
     T *z = (T *)c->d_z;
     const double n0 = (double)L0.dofs * nb;
-    vcycle<T, double>(c, c->d_r, z, sc, nb);
+    CycleDots dots{c->d_r, c->d_q, c->d_part};
+    if (vcycle<T, double>(c, c->d_r, z, sc, nb, &dots)) {
+        finish(c, cheb_dot_parts<T>(topo.nb), FIN_BETA0, sc, 0, nb);
+        return;
+    }
     {
         TScope ts(c, SPFD_K_DOTS, n0 * (sizeof(T) + 8.0));
         HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 1, bt, c->stream));
@@ -877,10 +943,13 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
         HIPCHK(launch_rupdate(topo, c->d_r, c->d_q, c->d_part, sc, bt, r32, c->stream));
     }
     finish(c, topo.nb, FIN_RR, sc, max_iter, nb);
-    if (r32)
-        vcycle<T, float>(c, r32, z, sc, nb);
-    else
-        vcycle<T, double>(c, c->d_r, z, sc, nb);
+    // z = B r, with the dot products z.r and z.q formed by the cycle's last step
+    CycleDots dots{c->d_r, c->d_q, c->d_part};
+    const bool fused = r32 ? vcycle<T, float>(c, r32, z, sc, nb, &dots) : vcycle<T, double>(c, c->d_r, z, sc, nb, &dots);
+    if (fused) {
+        finish(c, cheb_dot_parts<T>(topo.nb), FIN_BETA, sc, 0, nb);
+        return;
+    }
     {
         TScope ts(c, SPFD_K_DOTS, n0 * (wz + 16.0));
         HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 0, bt, c->stream));
@@ -912,12 +981,70 @@ void pcg_step_any(Ctx *c, Scal *sc, int nb, int it, int max_iter)
         pcg_step<double>(c, sc, nb, it, max_iter);
 }
 
+void drop_graphs(Ctx *c)
+{
+    for (auto &g : c->sg) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = Ctx::StepGraph{};
+    }
+    c->sg_nb = -1;
+    c->sg_sc = nullptr;
+    c->sg_max_iter = -1;
+}
+
+// Enqueue CG step `it` (and the copy of the scalars to hsc).  Steps after the
+// first have fixed kernel arguments per buffer parity, so they are captured
+// once into a HIP graph and replayed: one host call instead of some fifty
+// launches, which keeps the short coarse-level kernels back to back.  The
+// first step, eager solves and the step sampled by the launch timing run
+// eagerly.  The graphs hold no memset nodes.
+void pcg_step_enqueue(Ctx *c, Scal *sc, Scal *hsc, int nb, int it, int max_iter, bool eager)
+{
+    const bool timed_sample = c->tmask != 0 && it == 1;
+    if (eager || it == 0 || timed_sample) {
+        pcg_step_any(c, sc, nb, it, max_iter);
+        HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+        return;
+    }
+    if (c->sg_nb != nb || c->sg_sc != sc || c->sg_max_iter != max_iter) {
+        drop_graphs(c);
+        c->sg_nb = nb;
+        c->sg_sc = sc;
+        c->sg_max_iter = max_iter;
+    }
+    Ctx::StepGraph &g = c->sg[it & 1];
+    if (!g.exec) {
+        g = Ctx::StepGraph{};
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        c->capturing = &g;
+        try {
+            pcg_step_any(c, sc, nb, it, max_iter);
+            HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+        } catch (...) {
+            c->capturing = nullptr;
+            (void)hipStreamEndCapture(c->stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        c->capturing = nullptr;
+        HIPCHK(hipStreamEndCapture(c->stream, &graph));
+        const hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(e);
+    }
+    HIPCHK(hipGraphLaunch(g.exec, c->stream));
+    for (int k = 0; k < SPFD_K_COUNT; ++k) {
+        c->tlaunch[k] += g.launch[k];
+        c->tbytes[k] += g.bytes[k];
+    }
+}
+
 void pcg_iterations(Ctx *c, Scal *sc, Scal *hsc, int nb, const spfd_solve_options &so)
 {
     pcg_begin_any(c, sc, nb);
     for (int it = 0; it < so.max_iter + 1; ++it) {
-        pcg_step_any(c, sc, nb, it, so.max_iter);
-        HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+        pcg_step_enqueue(c, sc, hsc, nb, it, so.max_iter, so.eager != 0);
         HIPCHK(hipStreamSynchronize(c->stream));
         bool all = true;
         for (int i = 0; i < nb; ++i) all = all && hsc[i].done;
@@ -1070,8 +1197,7 @@ spfd_status solve_many(Ctx **hs, int n, const spfd_solve_options &so, double **p
         for (int k = 0; k < n; ++k)
             if (active[k]) {
                 Ctx *c = hs[k];
-                pcg_step_any(c, c->d_scal, c->nrhs, steps[k]++, so.max_iter);
-                HIPCHK(hipMemcpyAsync(c->h_scal, c->d_scal, c->nrhs * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+                pcg_step_enqueue(c, c->d_scal, c->h_scal, c->nrhs, steps[k]++, so.max_iter, so.eager != 0);
             }
         for (int k = 0; k < n; ++k)
             if (active[k]) {
@@ -1166,12 +1292,17 @@ spfd_status spfd_create(int device, void *hip_stream, spfd_handle *out)
     spfd_ctx *c = new (std::nothrow) spfd_ctx();
     if (!c) return SPFD_OUT_OF_MEMORY;
     c->device = device;
-    c->stream = (hipStream_t)hip_stream;
+    c->user_stream = (hipStream_t)hip_stream;
     try {
         HIPCHK(hipSetDevice(device));
+        // own stream (default priority, no implicit sync with the null stream), ordered after the caller's
+        HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&c->ev_user, hipEventDisableTiming));
         c->d_ints = dalloc<int>(c, c->geo_allocs, 64);
         HIPCHK(hipHostMalloc((void **)&c->h_ints, 64 * sizeof(int), hipHostMallocDefault));
     } catch (const HipFail &f) {
+        if (c->ev_user) (void)hipEventDestroy(c->ev_user);
+        if (c->stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return f.e == hipErrorOutOfMemory ? SPFD_OUT_OF_MEMORY : SPFD_HIP_ERROR;
     }
@@ -1184,11 +1315,14 @@ void spfd_destroy(spfd_handle h)
     if (!h) return;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
     release_device(h);
     if (h->h_scal) (void)hipHostFree(h->h_scal);
     if (h->h_ints) (void)hipHostFree(h->h_ints);
     for (int k = 0; k < SPFD_K_COUNT; ++k)
         for (hipEvent_t e : h->tev[k]) (void)hipEventDestroy(e);
+    if (h->ev_user) (void)hipEventDestroy(h->ev_user);
+    if (h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }
 
@@ -1206,6 +1340,7 @@ spfd_status spfd_set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, 
     if (nn > 0x7fffffffLL * 4) return fail(h, SPFD_INVALID_ARG, "grid too large");
     try {
         HIPCHK(hipSetDevice(h->device));
+        enter(h);
         HIPCHK(hipStreamSynchronize(h->stream));
         free_all(h, h->rhs_allocs);
         free_all(h, h->hier_allocs);
@@ -1247,6 +1382,7 @@ spfd_status spfd_set_sigma_table(spfd_handle h, const double *sigma, int n_label
         if (!isfinite(sigma[i]) || sigma[i] < 0.0) return fail(h, SPFD_INVALID_ARG, "sigma must be finite and >= 0");
     try {
         HIPCHK(hipSetDevice(h->device));
+        enter(h);
         float t32[MAX_LABELS];
         for (int i = 0; i < MAX_LABELS; ++i) {
             h->table[i] = i < n_labels ? sigma[i] : 0.0;
@@ -1270,6 +1406,7 @@ spfd_status spfd_set_sigma_voxel(spfd_handle h, const double *sigma_voxel)
     if (!sigma_voxel) return fail(h, SPFD_INVALID_ARG, "sigma_voxel is NULL");
     try {
         HIPCHK(hipSetDevice(h->device));
+        enter(h);
         const long long nvox = (long long)h->g.nx * h->g.ny * h->g.nz;
         if (!h->d_sigvox) h->d_sigvox = dalloc<double>(h, h->geo_allocs, nvox);
         HIPCHK(hipMemcpyAsync(h->d_sigvox, sigma_voxel, nvox * sizeof(double), hipMemcpyDefault, h->stream));
@@ -1292,6 +1429,7 @@ spfd_status spfd_build(spfd_handle h, const spfd_amg_options *opt)
     h->opt = o;
     try {
         HIPCHK(hipSetDevice(h->device));
+        enter(h);
         spfd_status s = do_build(h);
         if (s != SPFD_OK) {
             h->state = 2;
@@ -1321,6 +1459,7 @@ spfd_status spfd_set_num_rhs(spfd_handle h, int nrhs)
     if (nrhs <= 0 || nrhs > 4096) return fail(h, SPFD_INVALID_ARG, "nrhs must be in 1..4096");
     try {
         HIPCHK(hipSetDevice(h->device));
+        enter(h);
         return do_set_num_rhs(h, nrhs);
     }
     API_GUARD(h)
@@ -1334,6 +1473,7 @@ spfd_status spfd_set_source(spfd_handle h, int rhs, const double *a)
     if (!a) return fail(h, SPFD_INVALID_ARG, "a is NULL");
     try {
         HIPCHK(hipSetDevice(h->device));
+        enter(h);
         Level &L0 = h->lv[0];
         HIPCHK(hipMemsetAsync(h->d_scal + rhs, 0, sizeof(Scal), h->stream));
         {
@@ -1367,6 +1507,7 @@ spfd_status spfd_solve(spfd_handle h, const spfd_solve_options *opt, double *psi
     if (so.max_iter <= 0) return fail(h, SPFD_INVALID_ARG, "max_iter must be positive");
     try {
         HIPCHK(hipSetDevice(h->device));
+        enter(h);
         return do_solve(h, so, psi, info);
     }
     API_GUARD(h)
@@ -1380,6 +1521,7 @@ spfd_status spfd_efield(spfd_handle h, double omega, const double *a, const doub
     if (!isfinite(omega)) return fail(h, SPFD_INVALID_ARG, "omega must be finite");
     try {
         HIPCHK(hipSetDevice(h->device));
+        enter(h);
         const double *sv = h->voxel_mode ? h->d_sigvox : nullptr;
         const double nvox = (double)h->g.nx * h->g.ny * h->g.nz;
         const double body = h->state >= 3 ? (double)h->lv[0].dofs : nvox;
@@ -1417,6 +1559,7 @@ spfd_status spfd_adjoint(spfd_handle h, double omega, const double *a, const dou
     if (so.max_iter <= 0) return fail(h, SPFD_INVALID_ARG, "max_iter must be positive");
     try {
         HIPCHK(hipSetDevice(h->device));
+        enter(h);
         Level &L0 = h->lv[0];
         const Grid &g = h->g;
         const long long nvox = (long long)g.nx * g.ny * g.nz;
@@ -1482,6 +1625,7 @@ spfd_status spfd_solve_many(spfd_handle *hs, int n, const spfd_solve_options *op
     std::vector<Ctx *> cs(hs, hs + n);
     try {
         HIPCHK(hipSetDevice(hs[0]->device));
+        for (Ctx *c : cs) enter(c);
         spfd_status st = solve_many(cs.data(), n, so, psi, info);
         if (st != SPFD_OK) hs[0]->err = "a right-hand side did not converge or broke down";
         return st;
@@ -1497,6 +1641,7 @@ spfd_status spfd_percentile(spfd_handle h, const double *emag, double q, double 
     if (!(q > 0.0 && q <= 1.0)) return fail(h, SPFD_INVALID_ARG, "q must be in (0, 1]");
     try {
         HIPCHK(hipSetDevice(h->device));
+        enter(h);
         const int nlab = h->voxel_mode ? MAX_LABELS : h->nlab;
         const int ng = 1 + nlab;
         if (!h->d_sel_work) {
@@ -1531,13 +1676,16 @@ spfd_status spfd_timing(spfd_handle h, unsigned int class_mask)
             h->tused[k] = 0;
             h->tlaunch[k] = 0;
             h->tbytes[k] = 0.0;
+            h->ttimed[k] = 0;
+            h->ttbytes[k] = 0.0;
         }
         return SPFD_OK;
     }
     API_GUARD(h)
 }
 
-spfd_status spfd_timing_get(spfd_handle h, int kclass, long long *launches, double *total_ms, double *algorithmic_bytes)
+spfd_status spfd_timing_get(spfd_handle h, int kclass, long long *launches, double *algorithmic_bytes,
+                            long long *timed_launches, double *timed_ms, double *timed_bytes)
 {
     if (!h) return SPFD_INVALID_ARG;
     if (kclass < 0 || kclass >= SPFD_K_COUNT) return fail(h, SPFD_INVALID_ARG, "unknown kernel class");
@@ -1552,8 +1700,10 @@ spfd_status spfd_timing_get(spfd_handle h, int kclass, long long *launches, doub
             ms += e;
         }
         if (launches) *launches = h->tlaunch[kclass];
-        if (total_ms) *total_ms = ms;
         if (algorithmic_bytes) *algorithmic_bytes = h->tbytes[kclass];
+        if (timed_launches) *timed_launches = h->ttimed[kclass];
+        if (timed_ms) *timed_ms = ms;
+        if (timed_bytes) *timed_bytes = h->ttbytes[kclass];
         return SPFD_OK;
     }
     API_GUARD(h)

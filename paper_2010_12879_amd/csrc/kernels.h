@@ -110,9 +110,19 @@ hipError_t launch_pupdate(Topo topo, const TZ *z, double *p, const Scal *sc, int
 template <typename T, typename TB>
 hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, T c0, const Scal *sc,
                              const Batch &bt, hipStream_t s);
+// xc != nullptr: xin is first corrected by pscale * P xc from the structured
+// coarser level (parent_slot / fcoord of this level), i.e. the prolongation
+// fused into the step.  dot_part != nullptr: the step also writes the
+// partials of xout.dot_r (dot_part[g]) and xout.dot_q (dot_part[n + g]),
+// n = cheb_dot_parts<T>(nb), for the outer CG.
 template <typename T, typename TB>
 hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din,
-                            T *dout, T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s);
+                            T *dout, T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s,
+                            const T *xc = nullptr, const int *parent_slot = nullptr, const int4 *fcoord = nullptr,
+                            T pscale = T(0), const double *dot_r = nullptr, const double *dot_q = nullptr,
+                            double *dot_part = nullptr);
+template <typename T>
+int cheb_dot_parts(int nb);
 template <typename T, typename TB>
 hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, const T *x, T *bc,
                                  const int *parent_slot, const int4 *fcoord, const Scal *sc, const Batch &bt,
@@ -178,9 +188,11 @@ hipError_t launch_ell_cheb_first(int n, int K, const int *col, const T *val, con
 template <typename T>
 hipError_t launch_ell_cheb_step(int n, int K, const int *col, const T *val, const T *b, const T *xin, T *xout,
                                 const T *din, T *dout, T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s);
+// b_c = P^T (b - A x) onto an ELL level: r (nrows per right side) receives the fine residual
 template <typename T>
-hipError_t launch_restrict_members(const FineLevelT<T> &f, const T *b, const T *x, int nc, const int *mptr,
-                                   const int *mem, T *bc, const Scal *sc, const Batch &bt, hipStream_t s);
+hipError_t launch_restrict_members(const FineLevelT<T> &f, long long nrows, const T *b, const T *x, T *r, int nc,
+                                   const int *mptr, const int *mem, T *bc, const Scal *sc, const Batch &bt,
+                                   hipStream_t s);
 template <typename T>
 hipError_t launch_prolong_agg(long long n, const int *agg, T *x, const T *xc, T scale, const Scal *sc,
                               const Batch &bt, hipStream_t s);

@@ -709,13 +709,25 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
     if (sc) sc += blockIdx.x;
     if (mode == FIN_ALPHA || mode == FIN_RR || mode == FIN_BETA0 || mode == FIN_BETA)
         if (sc->done) return;
+    // four independent loads in flight per thread and round (fixed order: deterministic)
+    const int nt = blockDim.x;
     double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) a += part[i];
-    a = block_sum_any(a, red);
-    if (mode == FIN_BETA) {
-        for (int i = threadIdx.x; i < n; i += blockDim.x) b += part[n + i];
-        b = block_sum_any(b, red);
+    for (int i = threadIdx.x; i < n; i += 4 * nt) {
+        const double v0 = part[i];
+        const double v1 = i + nt < n ? part[i + nt] : 0.0;
+        const double v2 = i + 2 * nt < n ? part[i + 2 * nt] : 0.0;
+        const double v3 = i + 3 * nt < n ? part[i + 3 * nt] : 0.0;
+        a += (v0 + v1) + (v2 + v3);
+        if (mode == FIN_BETA) {
+            const double w0 = part[n + i];
+            const double w1 = i + nt < n ? part[n + i + nt] : 0.0;
+            const double w2 = i + 2 * nt < n ? part[n + i + 2 * nt] : 0.0;
+            const double w3 = i + 3 * nt < n ? part[n + i + 3 * nt] : 0.0;
+            b += (w0 + w1) + (w2 + w3);
+        }
     }
+    a = block_sum_any(a, red);
+    if (mode == FIN_BETA) b = block_sum_any(b, red);
     if (threadIdx.x != 0) return;
     switch (mode) {
     case FIN_BB:

@@ -263,9 +263,9 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo 
                                                              T *__restrict__ x, T c0, const Scal *sc, long long vs)
 {
     T *lds = col_lds<T, ZPL, LABEL>();
-    if (col_stopped(sc)) return;
     const Seg<ZPL> s = make_seg<ZPL>(topo);
     if (s.bk < 0) return;
+    const bool done = col_stopped(sc);
     b += blockIdx.y * vs;
     x += blockIdx.y * vs;
     SegOp<T, ZPL, LABEL> A;
@@ -274,6 +274,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo 
 #pragma unroll
     for (int z = 0; z < ZPL; ++z) bv[z] = (T)b[s.self + 64 * z];
     A.stage(op, s);
+    if (done) return;
 #pragma unroll
     for (int z = 0; z < ZPL; ++z) {
         T W[6];
@@ -283,48 +284,162 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo 
     }
 }
 
+// Coarse-grid correction of a structured level, x += scale * P x_c, applied
+// to the values a segment reads: the coarse node of fine node (tx,ty,tz) of
+// brick b is node (4 (f.x & 1) + tx/2, ...) of the parent brick, f = coord of b.
+struct Prolong {
+    const void *xc;
+    const int *parent_slot;
+    const int4 *fcoord;
+    double scale;
+    long long vsc;
+};
+
+__device__ __forceinline__ long long coarse_slot(const Prolong &pr, int b, int tx, int ty, int tz)
+{
+    const int4 f = pr.fcoord[b];
+    return (long long)pr.parent_slot[b] * BS + ((f.x & 1) * 4 + (tx >> 1)) + 8 * ((f.y & 1) * 4 + (ty >> 1)) +
+           64 * ((f.z & 1) * 4 + (tz >> 1));
+}
+
+template <typename T, int ZPL>
+__device__ __forceinline__ void apply_prolong(const Prolong &pr, const Topo &topo, const Seg<ZPL> &s,
+                                              SegVals<T, ZPL> &X)
+{
+    const T *xc = (const T *)pr.xc + blockIdx.y * pr.vsc;
+    const T sc = (T)pr.scale;
+    int nb[6];
+    brick_nbrs(topo.nbr, s.bk, nb);
+    const int tx = s.tx, ty = s.ty, z0 = s.z0;
+    // the brick and local node of every column the segment reads (absent -> own column)
+    long long cs[5];
+    cs[0] = coarse_slot(pr, s.bk, tx, ty, z0);
+    cs[1] = tx > 0 ? coarse_slot(pr, s.bk, tx - 1, ty, z0) : (nb[NMX] >= 0 ? coarse_slot(pr, nb[NMX], 7, ty, z0) : cs[0]);
+    cs[2] = tx < 7 ? coarse_slot(pr, s.bk, tx + 1, ty, z0) : (nb[NPX] >= 0 ? coarse_slot(pr, nb[NPX], 0, ty, z0) : cs[0]);
+    cs[3] = ty > 0 ? coarse_slot(pr, s.bk, tx, ty - 1, z0) : (nb[NMY] >= 0 ? coarse_slot(pr, nb[NMY], tx, 7, z0) : cs[0]);
+    cs[4] = ty < 7 ? coarse_slot(pr, s.bk, tx, ty + 1, z0) : (nb[NPY] >= 0 ? coarse_slot(pr, nb[NPY], tx, 0, z0) : cs[0]);
+    const long long czm = z0 > 0 ? coarse_slot(pr, s.bk, tx, ty, z0 - 1)
+                                 : (nb[NMZ] >= 0 ? coarse_slot(pr, nb[NMZ], tx, ty, 7) : cs[0]);
+    const int ze = z0 + ZPL;
+    const long long czp = ze < 8 ? coarse_slot(pr, s.bk, tx, ty, ze)
+                                 : (nb[NPZ] >= 0 ? coarse_slot(pr, nb[NPZ], tx, ty, 0) : cs[0] + 64 * ((ZPL - 1) >> 1));
+    T v[5][ZPL / 2];
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+        for (int h = 0; h < ZPL / 2; ++h) v[k][h] = xc[cs[k] + 64 * h];
+    const T vm = xc[czm], vp = xc[czp];
+#pragma unroll
+    for (int z = 0; z < ZPL; ++z) {
+        X.c[z] += sc * v[0][z >> 1];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) X.l[k][z] += sc * v[k + 1][z >> 1];
+    }
+    X.zm += sc * vm;
+    X.zp += sc * vp;
+}
+
+// Dot products of the outer flexible CG that ride on the last finest-level
+// smoothing step: partials (one per workgroup) of z.r into part[g] and of
+// z.q into part[nparts + g], z being the step's output.
+struct Dots {
+    const double *r;
+    const double *q;
+    double *part;
+    int ps;        // partial stride per right side
+    int nparts;
+};
+
 // general step: r = b - A xin; d = c1 d_old + c2 D^-1 r; xout = xin + d
-// (d_old = xin when din == nullptr, i.e. right after a zero start)
-template <typename T, typename TB, int ZPL, bool LABEL>
+// (d_old = xin when din == nullptr, i.e. right after a zero start).  With PRO,
+// xin is first corrected from the coarser level (the prolongation of the
+// upward leg, fused into the first post-smoothing step); with DOT the step
+// also forms the CG dot products of its output.
+template <typename T, typename TB, int ZPL, bool LABEL, bool PRO, bool DOT>
 __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
                                                             const T *__restrict__ xin, T *__restrict__ xout,
                                                             const T *__restrict__ din, T *__restrict__ dout, T c1,
-                                                            T c2, const Scal *sc, long long vs)
+                                                            T c2, const Scal *sc, long long vs, Prolong pr, Dots dt)
 {
     T *lds = col_lds<T, ZPL, LABEL>();
-    if (col_stopped(sc)) return;
+    __shared__ double red[2][CWAVES];
     const Seg<ZPL> s = make_seg<ZPL>(topo);
-    if (s.bk < 0) return;
-    b += blockIdx.y * vs;
-    xin += blockIdx.y * vs;
-    xout += blockIdx.y * vs;
-    if (din) din += blockIdx.y * vs;
-    if (dout) dout += blockIdx.y * vs;
-    SegOp<T, ZPL, LABEL> A;
-    A.load(op, s, lds);
-    SegVals<T, ZPL> X;
-    X.load(xin, s);
-    T bv[ZPL], dv[ZPL];
+    if (DOT ? s.grp < 0 : s.bk < 0) return;
+    const bool done = col_stopped(sc);
+    double dzr = 0.0, dzq = 0.0;
+    if (s.bk >= 0) {
+        b += blockIdx.y * vs;
+        xin += blockIdx.y * vs;
+        xout += blockIdx.y * vs;
+        if (din) din += blockIdx.y * vs;
+        if (dout) dout += blockIdx.y * vs;
+        SegOp<T, ZPL, LABEL> A;
+        A.load(op, s, lds);
+        SegVals<T, ZPL> X;
+        X.load(xin, s);
+        T bv[ZPL], dv[ZPL];
 #pragma unroll
-    for (int z = 0; z < ZPL; ++z) {
-        bv[z] = (T)b[s.self + 64 * z];
-        dv[z] = din ? din[s.self + 64 * z] : X.c[z];
-    }
-    A.stage(op, s);
-#pragma unroll
-    for (int z = 0; z < ZPL; ++z) {
-        T W[6], N[6];
-        A.weights(s, z, W);
-        X.nbrs(z, N);
-        const T D = diag_of(W);
-        T xo = T(0), dn = T(0);
-        if (D > T(0)) {
-            const T r = bv[z] - stencil_apply(X.c[z], N, W);
-            dn = c1 * dv[z] + c2 * r / D;
-            xo = X.c[z] + dn;
+        for (int z = 0; z < ZPL; ++z) {
+            bv[z] = (T)b[s.self + 64 * z];
+            if (din) dv[z] = din[s.self + 64 * z];
         }
-        xout[s.self + 64 * z] = xo;
-        if (dout) dout[s.self + 64 * z] = dn;
+        double rv[DOT ? ZPL : 1], qv[DOT ? ZPL : 1];
+        if constexpr (DOT) {
+            const double *r = dt.r + blockIdx.y * vs, *q = dt.q + blockIdx.y * vs;
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) {
+                rv[z] = r[s.self + 64 * z];
+                qv[z] = q[s.self + 64 * z];
+            }
+        }
+        if constexpr (PRO) apply_prolong<T, ZPL>(pr, topo, s, X);
+        if (!din) {
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) dv[z] = X.c[z];
+        }
+        A.stage(op, s);
+        if (!done) {
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) {
+                T W[6], N[6];
+                A.weights(s, z, W);
+                X.nbrs(z, N);
+                const T D = diag_of(W);
+                T xo = T(0), dn = T(0);
+                if (D > T(0)) {
+                    const T r = bv[z] - stencil_apply(X.c[z], N, W);
+                    dn = c1 * dv[z] + c2 * r / D;
+                    xo = X.c[z] + dn;
+                }
+                xout[s.self + 64 * z] = xo;
+                if (dout) dout[s.self + 64 * z] = dn;
+                if constexpr (DOT) {
+                    dzr += (double)xo * rv[z];
+                    dzq += (double)xo * qv[z];
+                }
+            }
+        }
+    }
+    if constexpr (DOT) {
+        if (done) return;
+        dzr = wave_sum(dzr);
+        dzq = wave_sum(dzq);
+        if (s.lane == 0) {
+            red[0][threadIdx.x >> 6] = dzr;
+            red[1][threadIdx.x >> 6] = dzq;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a = 0.0, c = 0.0;
+#pragma unroll
+            for (int w = 0; w < CWAVES; ++w) {
+                a += red[0][w];
+                c += red[1][w];
+            }
+            double *part = dt.part + (long long)blockIdx.y * dt.ps;
+            part[s.grp] = a;
+            part[dt.nparts + s.grp] = c;
+        }
     }
 }
 
@@ -339,9 +454,9 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
                                                                  long long vs, long long vsc)
 {
     T *lds = col_lds<T, ZPL, LABEL>();
-    if (col_stopped(sc)) return;
     const Seg<ZPL> s = make_seg<ZPL>(topo);
     if (s.bk < 0) return;
+    const bool done = col_stopped(sc);
     b += blockIdx.y * vs;
     x += blockIdx.y * vs;
     bc += blockIdx.y * vsc;
@@ -365,7 +480,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
     }
     const int ox = (fc.x & 1) * 4 + (s.tx >> 1), oy = (fc.y & 1) * 4 + (s.ty >> 1);
     const int oz = (fc.z & 1) * 4 + (s.z0 >> 1);
-    const bool corner = ((s.tx | s.ty) & 1) == 0;
+    const bool corner = ((s.tx | s.ty) & 1) == 0 && !done;
 #pragma unroll
     for (int k = 0; k < ZPL / 2; ++k) {
         T a = r[2 * k] + r[2 * k + 1];
@@ -393,9 +508,9 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
     double *lds = col_lds<double, ZPL, LABEL>();
     __shared__ double red[CWAVES];
     sc += blockIdx.y;
-    if (sc->done) return;
     const Seg<ZPL> s = make_seg<ZPL>(topo);
     if (s.grp < 0) return;
+    const int done = __hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     zv += blockIdx.y * vs;
     pin += blockIdx.y * vs;
     pout += blockIdx.y * vs;
@@ -428,19 +543,22 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
         P.zm = first ? (double)Z.zm : (double)Z.zm + beta * Pi.zm;
         P.zp = first ? (double)Z.zp : (double)Z.zp + beta * Pi.zp;
         A.stage(op, s);
+        if (!done) {
 #pragma unroll
-        for (int z = 0; z < ZPL; ++z) {
-            double W[6], N[6];
-            A.weights(s, z, W);
-            P.nbrs(z, N);
-            const double y = stencil_apply(P.c[z], N, W);
-            const long long n = s.self + 64 * z;
-            if (!first) x[n] = xv[z] + alpha * Pi.c[z];
-            pout[n] = P.c[z];
-            q[n] = y;
-            dot += P.c[z] * y;
+            for (int z = 0; z < ZPL; ++z) {
+                double W[6], N[6];
+                A.weights(s, z, W);
+                P.nbrs(z, N);
+                const double y = stencil_apply(P.c[z], N, W);
+                const long long n = s.self + 64 * z;
+                if (!first) x[n] = xv[z] + alpha * Pi.c[z];
+                pout[n] = P.c[z];
+                q[n] = y;
+                dot += P.c[z] * y;
+            }
         }
     }
+    if (done) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->pad = 1 + parity;
     dot = wave_sum(dot);
     if (s.lane == 0) red[threadIdx.x >> 6] = dot;
@@ -486,20 +604,45 @@ hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, 
 
 template <typename T, typename TB>
 hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din, T *dout,
-                            T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s)
+                            T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s, const T *xc,
+                            const int *parent_slot, const int4 *fcoord, T pscale, const double *dot_r,
+                            const double *dot_q, double *dot_part)
 {
     if (topo.nb <= 0) return hipSuccess;
     if (xin == xout) return hipErrorInvalidValue;
-    constexpr int ZPL_CYCLE = zpl_cycle<T>();
-    const dim3 g = col_grid<ZPL_CYCLE>(topo.nb, bt.n);
-    if (op.w)
-        hipLaunchKernelGGL((k_col_cheb_step<T, TB, ZPL_CYCLE, false>), g, dim3(CTHREADS), 0, s, op, topo, b, xin, xout,
-                           din, dout, c1, c2, sc, bt.vs);
-    else
-        hipLaunchKernelGGL((k_col_cheb_step<T, TB, ZPL_CYCLE, true>), g, dim3(CTHREADS), 0, s, op, topo, b, xin, xout,
-                           din, dout, c1, c2, sc, bt.vs);
+    if (xc && !(parent_slot && fcoord)) return hipErrorInvalidValue;
+    if (dot_part && !(dot_r && dot_q)) return hipErrorInvalidValue;
+    constexpr int ZPL = zpl_cycle<T>();
+    const dim3 g = col_grid<ZPL>(topo.nb, bt.n);
+    const Prolong pr{xc, parent_slot, fcoord, (double)pscale, bt.vsc};
+    const Dots dt{dot_r, dot_q, dot_part, bt.ps, col_ngroups<ZPL>(topo.nb)};
+    const int sel = (op.w ? 0 : 4) | (xc ? 2 : 0) | (dot_part ? 1 : 0);
+#define SPFD_CHEB_CASE(K, LAB, PRO, DOT)                                                                              \
+    case K:                                                                                                           \
+        hipLaunchKernelGGL((k_col_cheb_step<T, TB, ZPL, LAB, PRO, DOT>), g, dim3(CTHREADS), 0, s, op, topo, b, xin,  \
+                           xout, din, dout, c1, c2, sc, bt.vs, pr, dt);                                               \
+        break;
+    switch (sel) {
+        SPFD_CHEB_CASE(0, false, false, false)
+        SPFD_CHEB_CASE(1, false, false, true)
+        SPFD_CHEB_CASE(2, false, true, false)
+        SPFD_CHEB_CASE(3, false, true, true)
+        SPFD_CHEB_CASE(4, true, false, false)
+        SPFD_CHEB_CASE(5, true, false, true)
+        SPFD_CHEB_CASE(6, true, true, false)
+        SPFD_CHEB_CASE(7, true, true, true)
+    }
+#undef SPFD_CHEB_CASE
     return hipGetLastError();
 }
+
+template <typename T>
+int cheb_dot_parts(int nb)
+{
+    return col_ngroups<zpl_cycle<T>()>(nb);
+}
+template int cheb_dot_parts<float>(int);
+template int cheb_dot_parts<double>(int);
 
 template <typename T, typename TB>
 hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, const T *x, T *bc, const int *parent_slot,
@@ -538,7 +681,9 @@ hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, cons
     template hipError_t launch_cheb_first<T, TB>(const OpArgs<T> &, Topo, const TB *, T *, T, const Scal *,       \
                                                  const Batch &, hipStream_t);                                       \
     template hipError_t launch_cheb_step<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *, const T *, T *, \
-                                                T, T, const Scal *, const Batch &, hipStream_t);                    \
+                                                T, T, const Scal *, const Batch &, hipStream_t, const T *,          \
+                                                const int *, const int4 *, T, const double *, const double *,        \
+                                                double *);                                                          \
     template hipError_t launch_resid_restrict<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *,           \
                                                      const int *, const int4 *, const Scal *, const Batch &,        \
                                                      hipStream_t);

@@ -378,6 +378,7 @@ __device__ __forceinline__ T ell_row(int n, int K, const int *__restrict__ col, 
                                      const T *__restrict__ x, int i, T xi, T &D)
 {
     T y = T(0), d = T(0);
+#pragma unroll 4
     for (int k = 0; k < K; ++k) {
         const int j = col[(long long)k * n + i];
         if (j >= 0) {
@@ -432,41 +433,55 @@ __global__ void k_ell_cheb_step(int n, int K, const int *__restrict__ col, const
     }
 }
 
-// coarse right side b_c[p] = sum over the members i of p of (b - A x)_i
+// Coarse right side b_c[p] = sum over the members i of p of (b - A x)_i, in
+// two passes: the fine residual of every row in parallel (into r), then the
+// member sums (one thread per aggregate, members in list order).
 template <typename T>
-__global__ void k_restrict_members(FineLevelT<T> f, const T *__restrict__ b, const T *__restrict__ x, int nc,
-                                   const int *__restrict__ mptr, const int *__restrict__ mem, T *__restrict__ bc,
-                                   const Scal *sc, long long vs, long long vsc)
+__global__ void k_resid_rows(FineLevelT<T> f, long long nrows, const T *__restrict__ b, const T *__restrict__ x,
+                             T *__restrict__ r, const Scal *sc, long long vs)
 {
-    if (ell_stopped(sc)) return;
+    const bool done = ell_stopped(sc);
     b += blockIdx.y * vs;
     x += blockIdx.y * vs;
+    r += blockIdx.y * vs;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nrows;
+         i += (long long)gridDim.x * blockDim.x) {
+        const T xi = x[i];
+        T ax;
+        if (f.w) {
+            const int bk = (int)(i / BS), t = (int)(i % BS);
+            int tx, ty, tz;
+            brick_xyz(t, tx, ty, tz);
+            int nb[6];
+            brick_nbrs(f.nbr, bk, nb);
+            long long I[6];
+            nbr_index((long long)bk * BS, t, tx, ty, tz, nb, I);
+            T W[6], X[6];
+            stored_weights(f.w, f.stride, (long long)bk * BS, t, I, W);
+            nbr_vals(x, I, X);
+            ax = stencil_apply(xi, X, W);
+        } else {
+            T D;
+            ax = ell_row(f.n, f.K, f.col, f.val, x, (int)i, xi, D);
+        }
+        if (!done) r[i] = b[i] - ax;
+    }
+}
+
+template <typename T>
+__global__ void k_sum_members(int nc, const int *__restrict__ mptr, const int *__restrict__ mem,
+                              const T *__restrict__ r, T *__restrict__ bc, const Scal *sc, long long vs,
+                              long long vsc)
+{
+    const bool done = ell_stopped(sc);
+    r += blockIdx.y * vs;
     bc += blockIdx.y * vsc;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
+        const int q0 = mptr[p], q1 = mptr[p + 1];
         T s = T(0);
-        for (int q = mptr[p]; q < mptr[p + 1]; ++q) {
-            const int i = mem[q];
-            const T xi = x[i];
-            T ax;
-            if (f.w) {
-                const int bk = i / BS, t = i % BS;
-                int tx, ty, tz;
-                brick_xyz(t, tx, ty, tz);
-                int nb[6];
-                brick_nbrs(f.nbr, bk, nb);
-                long long I[6];
-                nbr_index((long long)bk * BS, t, tx, ty, tz, nb, I);
-                T W[6], X[6];
-                stored_weights(f.w, f.stride, (long long)bk * BS, t, I, W);
-                nbr_vals(x, I, X);
-                ax = stencil_apply(xi, X, W);
-            } else {
-                T D;
-                ax = ell_row(f.n, f.K, f.col, f.val, x, i, xi, D);
-            }
-            s += b[i] - ax;
-        }
-        bc[p] = s;
+#pragma unroll 4
+        for (int q = q0; q < q1; ++q) s += r[mem[q]];
+        if (!done) bc[p] = s;
     }
 }
 
@@ -505,12 +520,15 @@ hipError_t launch_ell_cheb_step(int n, int K, const int *col, const T *val, cons
 }
 
 template <typename T>
-hipError_t launch_restrict_members(const FineLevelT<T> &f, const T *b, const T *x, int nc, const int *mptr,
-                                   const int *mem, T *bc, const Scal *sc, const Batch &bt, hipStream_t s)
+hipError_t launch_restrict_members(const FineLevelT<T> &f, long long nrows, const T *b, const T *x, T *r, int nc,
+                                   const int *mptr, const int *mem, T *bc, const Scal *sc, const Batch &bt,
+                                   hipStream_t s)
 {
-    if (nc <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_restrict_members<T>, dim3(gblocks(nc, 128), bt.n), dim3(128), 0, s, f, b, x, nc, mptr, mem,
-                       bc, sc, bt.vs, bt.vsc);
+    if (nc <= 0 || nrows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_resid_rows<T>, dim3(gblocks(nrows, 256), bt.n), dim3(256), 0, s, f, nrows, b, x, r, sc,
+                       bt.vs);
+    hipLaunchKernelGGL(k_sum_members<T>, dim3(gblocks(nc, 64), bt.n), dim3(64), 0, s, nc, mptr, mem, r, bc, sc, bt.vs,
+                       bt.vsc);
     return hipGetLastError();
 }
 
@@ -529,8 +547,9 @@ hipError_t launch_prolong_agg(long long n, const int *agg, T *x, const T *xc, T 
                                                  const Batch &, hipStream_t);                                       \
     template hipError_t launch_ell_cheb_step<T>(int, int, const int *, const T *, const T *, const T *, T *,         \
                                                 const T *, T *, T, T, const Scal *, const Batch &, hipStream_t);    \
-    template hipError_t launch_restrict_members<T>(const FineLevelT<T> &, const T *, const T *, int, const int *,   \
-                                                   const int *, T *, const Scal *, const Batch &, hipStream_t);     \
+    template hipError_t launch_restrict_members<T>(const FineLevelT<T> &, long long, const T *, const T *, T *, int, \
+                                                   const int *, const int *, T *, const Scal *, const Batch &,      \
+                                                   hipStream_t);                                                    \
     template hipError_t launch_prolong_agg<T>(long long, const int *, T *, const T *, T, const Scal *,             \
                                               const Batch &, hipStream_t);
 SPFD_INST_ELL(double)

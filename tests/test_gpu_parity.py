@@ -190,3 +190,27 @@ def test_percentile_matches_oracle(q):
             assert np.isnan(per[t])
         else:
             assert per[t] == ref_per[t], t
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replay_matches_eager(prec):
+    """CG iterations replayed from captured HIP graphs give bit-identical results to
+    host-launched ones, on every replay, with unrelated eager work in between."""
+    print(f"case graph replay {prec}", flush=True)
+    w = W.config(1)
+    s = P.Solver(_dev(w.labels), w.sigma_table, w.h, precision=prec)
+    a = _dev(w.a)
+    pe, ie = s.solve(a, tol=1e-10, eager=True)
+    outs = []
+    for rep in range(3):
+        pg, ig = s.solve(a, tol=1e-10)
+        outs.append((pg.clone(), ig))
+        junk = torch.randn(4096, device=DEV, dtype=torch.float64)
+        float(junk.sum())
+        torch.cuda.synchronize()
+    pe2, ie2 = s.solve(a, tol=1e-10, eager=True)
+    s.close()
+    assert torch.equal(pe, pe2) and ie == ie2
+    for pg, ig in outs:
+        assert ig == ie, (ig, ie)
+        assert torch.equal(pg, pe)
