@@ -101,6 +101,8 @@ struct Ctx {
     float *d_r32 = nullptr;
     Scal *d_scal = nullptr;
     Scal *h_scal = nullptr;   // pinned, one per right side plus one for the adjoint solve
+    Scal *h_ring = nullptr;   // pinned, 2 x (nrhs + 1): scalars of the last two enqueued CG steps
+    hipEvent_t ev_it[2] = {nullptr, nullptr};
     // adjoint solve
     double *d_adj_b = nullptr;
     double *d_adj_c = nullptr;
@@ -130,6 +132,7 @@ struct Ctx {
     int sg_nb = -1, sg_max_iter = -1;
     const Scal *sg_sc = nullptr;
     StepGraph *capturing = nullptr;
+    int step_ctx = 0;   // 0: outside the CG loop, 1: in an untimed CG step, 2: in the sampled step
     // per-class launch timing (tracing aid)
     unsigned tmask = 0;
     std::vector<hipEvent_t> tev[SPFD_K_COUNT];
@@ -236,7 +239,8 @@ struct TScope {
     Ctx *c;
     int cls;
     bool on;
-    TScope(Ctx *c_, int cls_, double bytes) : c(c_), cls(cls_), on(((c_->tmask >> cls_) & 1u) && !c_->capturing)
+    TScope(Ctx *c_, int cls_, double bytes)
+        : c(c_), cls(cls_), on(((c_->tmask >> cls_) & 1u) && !c_->capturing && c_->step_ctx != 1)
     {
         if (c->capturing) {
             // counted once per replay of the graph being captured
@@ -887,7 +891,10 @@ spfd_status do_set_num_rhs(Ctx *c, int nrhs)
     HIPCHK(hipMemsetAsync(c->d_scal, 0, nrhs * sizeof(Scal), c->stream));
     if (c->h_scal) (void)hipHostFree(c->h_scal);
     c->h_scal = nullptr;
+    if (c->h_ring) (void)hipHostFree(c->h_ring);
+    c->h_ring = nullptr;
     HIPCHK(hipHostMalloc((void **)&c->h_scal, sizeof(Scal) * (nrhs + 1), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&c->h_ring, sizeof(Scal) * 2 * (nrhs + 1), hipHostMallocDefault));
     c->nrhs = nrhs;
     alloc_cycle_buffers(c, nrhs);
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1002,7 +1009,9 @@ void pcg_step_enqueue(Ctx *c, Scal *sc, Scal *hsc, int nb, int it, int max_iter,
 {
     const bool timed_sample = c->tmask != 0 && it == 1;
     if (eager || it == 0 || timed_sample) {
+        c->step_ctx = timed_sample ? 2 : 1;
         pcg_step_any(c, sc, nb, it, max_iter);
+        c->step_ctx = 0;
         HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
         return;
     }
@@ -1040,14 +1049,27 @@ void pcg_step_enqueue(Ctx *c, Scal *sc, Scal *hsc, int nb, int it, int max_iter,
     }
 }
 
-void pcg_iterations(Ctx *c, Scal *sc, Scal *hsc, int nb, const spfd_solve_options &so)
+// Host loop of the CG iterations, one step ahead: step it+1 is enqueued before
+// the host waits for the scalars of step it, so the GPU never idles on the
+// host's poll.  When step it converged, the already enqueued step it+1 finds
+// the stop flag and writes nothing (its loads are the only cost).
+void pcg_iterations(Ctx *c, Scal *sc, int nb, const spfd_solve_options &so)
 {
+    Scal *ring[2] = {c->h_ring, c->h_ring + nb};
+    const bool eager = so.eager != 0;
+    c->step_ctx = 1;
     pcg_begin_any(c, sc, nb);
-    for (int it = 0; it < so.max_iter + 1; ++it) {
-        pcg_step_enqueue(c, sc, hsc, nb, it, so.max_iter, so.eager != 0);
-        HIPCHK(hipStreamSynchronize(c->stream));
+    c->step_ctx = 0;
+    pcg_step_enqueue(c, sc, ring[0], nb, 0, so.max_iter, eager);
+    HIPCHK(hipEventRecord(c->ev_it[0], c->stream));
+    for (int it = 0; it <= so.max_iter; ++it) {
+        if (it + 1 <= so.max_iter) {
+            pcg_step_enqueue(c, sc, ring[(it + 1) & 1], nb, it + 1, so.max_iter, eager);
+            HIPCHK(hipEventRecord(c->ev_it[(it + 1) & 1], c->stream));
+        }
+        HIPCHK(hipEventSynchronize(c->ev_it[it & 1]));
         bool all = true;
-        for (int i = 0; i < nb; ++i) all = all && hsc[i].done;
+        for (int i = 0; i < nb; ++i) all = all && ring[it & 1][i].done;
         if (all) break;
     }
     pcg_end(c, sc, nb);
@@ -1110,7 +1132,7 @@ spfd_status solve_batch(Ctx *c, const double *b, long long bvs, Scal *sc, Scal *
     }
     int *again = c->d_again;
     for (int pass = 0; pass < 3 && any; ++pass) {
-        pcg_iterations(c, sc, hsc, nb, so);
+        pcg_iterations(c, sc, nb, so);
         // true residual of every iterate (also of those that converged in an earlier pass)
         resid_b(c, b, bvs, sc, c->d_r, 1, nb);
         HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
@@ -1189,22 +1211,33 @@ spfd_status solve_many(Ctx **hs, int n, const spfd_solve_options &so, double **p
         Ctx *c = hs[k];
         HIPCHK(hipStreamSynchronize(c->stream));
         for (int i = 0; i < c->nrhs; ++i) active[k] = active[k] || !c->h_scal[i].done;
-        if (active[k]) pcg_begin_any(c, c->d_scal, c->nrhs);
+        if (active[k]) {
+            c->step_ctx = 1;
+            pcg_begin_any(c, c->d_scal, c->nrhs);
+            c->step_ctx = 0;
+        }
     }
     int left = 0;
     for (int k = 0; k < n; ++k) left += active[k];
+    // every handle one step ahead, as in pcg_iterations
+    auto enqueue = [&](int k) {
+        Ctx *c = hs[k];
+        const int it = steps[k]++;
+        pcg_step_enqueue(c, c->d_scal, c->h_ring + (it & 1) * c->nrhs, c->nrhs, it, so.max_iter, so.eager != 0);
+        HIPCHK(hipEventRecord(c->ev_it[it & 1], c->stream));
+    };
+    for (int k = 0; k < n; ++k)
+        if (active[k]) enqueue(k);
     for (int it = 0; it < so.max_iter + 1 && left > 0; ++it) {
         for (int k = 0; k < n; ++k)
-            if (active[k]) {
-                Ctx *c = hs[k];
-                pcg_step_enqueue(c, c->d_scal, c->h_scal, c->nrhs, steps[k]++, so.max_iter, so.eager != 0);
-            }
+            if (active[k] && it + 1 <= so.max_iter) enqueue(k);
         for (int k = 0; k < n; ++k)
             if (active[k]) {
                 Ctx *c = hs[k];
-                HIPCHK(hipStreamSynchronize(c->stream));
+                HIPCHK(hipEventSynchronize(c->ev_it[it & 1]));
+                const Scal *hs_it = c->h_ring + (it & 1) * c->nrhs;
                 bool all = true;
-                for (int i = 0; i < c->nrhs; ++i) all = all && c->h_scal[i].done;
+                for (int i = 0; i < c->nrhs; ++i) all = all && hs_it[i].done;
                 if (all) {
                     pcg_end(c, c->d_scal, c->nrhs);
                     active[k] = 0;
@@ -1298,10 +1331,13 @@ spfd_status spfd_create(int device, void *hip_stream, spfd_handle *out)
         // own stream (default priority, no implicit sync with the null stream), ordered after the caller's
         HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&c->ev_user, hipEventDisableTiming));
+        for (hipEvent_t &e : c->ev_it) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         c->d_ints = dalloc<int>(c, c->geo_allocs, 64);
         HIPCHK(hipHostMalloc((void **)&c->h_ints, 64 * sizeof(int), hipHostMallocDefault));
     } catch (const HipFail &f) {
         if (c->ev_user) (void)hipEventDestroy(c->ev_user);
+        for (hipEvent_t e : c->ev_it)
+            if (e) (void)hipEventDestroy(e);
         if (c->stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return f.e == hipErrorOutOfMemory ? SPFD_OUT_OF_MEMORY : SPFD_HIP_ERROR;
@@ -1318,6 +1354,9 @@ void spfd_destroy(spfd_handle h)
     drop_graphs(h);
     release_device(h);
     if (h->h_scal) (void)hipHostFree(h->h_scal);
+    if (h->h_ring) (void)hipHostFree(h->h_ring);
+    for (hipEvent_t e : h->ev_it)
+        if (e) (void)hipEventDestroy(e);
     if (h->h_ints) (void)hipHostFree(h->h_ints);
     for (int k = 0; k < SPFD_K_COUNT; ++k)
         for (hipEvent_t e : h->tev[k]) (void)hipEventDestroy(e);
