@@ -166,9 +166,9 @@ spfd_status spfd_adjoint(spfd_handle h, double omega, const double *a, const dou
 /* Per-launch timing, a tracing aid.  Kernel classes: */
 enum {
     SPFD_K_SPMV = 0,          /* outer CG: p = z + beta p, deferred x += alpha p, q = A p, p.q partials (FP64) */
-    SPFD_K_UPDATE = 1,        /* outer CG: r -= alpha q, ||r||^2 partials, FP32 copy of r; final x update */
+    SPFD_K_UPDATE = 1,        /* outer CG: r -= alpha q, ||r||^2 partials, FP32 copy of r */
     SPFD_K_DOTS = 2,          /* outer CG: last finest-level smoothing step with the r.z and z.q partials */
-    SPFD_K_PUPDATE = 3,       /* (unused: p is formed inside the SPMV step) */
+    SPFD_K_PUPDATE = 3,       /* outer CG: the deferred x += alpha p after the last step */
     SPFD_K_SMOOTH0 = 4,       /* finest level: Chebyshev step with a stencil application */
     SPFD_K_SMOOTH0_FIRST = 5, /* finest level: first Chebyshev step from zero (no stencil) */
     SPFD_K_RESTRICT0 = 6,     /* finest level: residual and restriction */
@@ -178,7 +178,8 @@ enum {
     SPFD_K_RHS = 10,          /* right side b = -G^T M a */
     SPFD_K_EFIELD = 11,       /* E-field and edge voltages */
     SPFD_K_GAUGE = 12,        /* component means and the output of psi */
-    SPFD_K_COUNT = 13
+    SPFD_K_RESID = 13,        /* true residual b - A x on the finest level (start, restart, exit) */
+    SPFD_K_COUNT = 14
 };
 /* Enable timing for the classes in the bit mask (1 << class); resets all
  * counters.  While enabled, the launches of such a class in the second CG

@@ -55,7 +55,7 @@ EXPORTS = ["spfd_create", "spfd_destroy", "spfd_last_error", "spfd_set_geometry"
            "spfd_solve", "spfd_solve_many", "spfd_efield", "spfd_percentile", "spfd_adjoint", "spfd_timing", "spfd_timing_get"]
 # kernel classes of spfd_timing / spfd_timing_get (order of the enum in spfd.h)
 KERNEL_CLASSES = ["spmv", "update", "dots", "pupdate", "smooth0", "smooth0_first", "restrict0", "prolong0", "coarse",
-                  "finish", "rhs", "efield", "gauge"]
+                  "finish", "rhs", "efield", "gauge", "resid"]
 
 
 def load_library(path: str = LIB_PATH):

@@ -873,7 +873,8 @@ spfd_status do_build(Ctx *c)
         else
             HIPCHK(launch_coarse_assemble_brick(C.d_w64, C.nodes(), C.topo(), c->d_cdof_node, c->d_cadj, c->ncoarse,
                                                 c->d_Ainv, c->stream));
-        HIPCHK(launch_coarse_factor(c->ncoarse, c->d_Ainv, c->d_cwork, c->stream));
+        double *dwork = dalloc<double>(c, c->hier_allocs, dense_inverse_work_doubles(c->ncoarse));
+        HIPCHK(launch_coarse_factor(c->ncoarse, c->d_Ainv, c->d_cwork, dwork, c->stream));
     }
     chebyshev_coefficients(c);
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -968,7 +969,7 @@ void pcg_end(Ctx *c, Scal *sc, int nb)
 {
     // the update x += alpha p deferred by the last step of each right side
     Level &L0 = c->lv[0];
-    TScope ts(c, SPFD_K_UPDATE, (double)L0.dofs * nb * 24.0);
+    TScope ts(c, SPFD_K_PUPDATE, (double)L0.dofs * nb * 24.0);
     HIPCHK(launch_x_final(L0.topo(), c->d_x, c->d_p, c->d_p2, sc, level_batch(c, 0, nb), c->stream));
 }
 
@@ -1081,7 +1082,7 @@ void resid_b(Ctx *c, const double *b, long long bvs, Scal *sc, double *r, int mo
 {
     Level &L0 = c->lv[0];
     {
-        TScope ts(c, SPFD_K_SPMV, nb * (double)L0.dofs * (16.0 + (r ? 8.0 : 0.0) + op_bytes<double>(c, 0)));
+        TScope ts(c, SPFD_K_RESID, nb * (double)L0.dofs * (16.0 + (r ? 8.0 : 0.0) + op_bytes<double>(c, 0)));
         HIPCHK(launch_resid(level_op<double>(c, 0), L0.topo(), b, c->d_x, r, c->d_part, bvs, level_batch(c, 0, nb),
                             c->stream));
     }

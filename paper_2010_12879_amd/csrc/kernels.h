@@ -7,6 +7,13 @@
 
 namespace spfd {
 
+#define HIP_RETURN_IF(...)                        \
+    do {                                          \
+        hipError_t e_ = (__VA_ARGS__);            \
+        if (e_ != hipSuccess) return e_;          \
+    } while (0)
+
+
 // Operator of one level: stored edge weights (w != nullptr) or, on the finest
 // level, conductances rebuilt from the per-brick label tiles and a sigma table.
 template <typename T>
@@ -53,7 +60,11 @@ hipError_t launch_coarse_setup(const double *w64, long long stride, Topo topo, i
 hipError_t launch_coarse_assemble_brick(const double *w64, long long stride, Topo topo, const int *node_of_dof,
                                         const int *adj, int n, double *A, hipStream_t s);
 // dense pseudo-inverse in place; work: 2n ints + n doubles (+1 int of padding)
-hipError_t launch_coarse_factor(int n, double *A, int *work, hipStream_t s);
+// A <- inverse of the regularised coarsest matrix (work: 5n ints; dwork:
+// dense_inverse_work_doubles(n) doubles)
+hipError_t launch_coarse_factor(int n, double *A, int *work, double *dwork, hipStream_t s);
+size_t dense_inverse_work_doubles(int n);
+hipError_t launch_dense_inverse(int n, double *A, double *work, hipStream_t s);
 
 // ---------------------------------------------------------------- solve
 // Reductions are two-stage: a producer kernel stores one partial per brick

@@ -554,14 +554,18 @@ __global__ void k_coarse_assemble_brick(const double *__restrict__ w, long long 
 // the nonzeros, regularisation with alpha_c = mean diagonal / size^2, and
 // Gauss-Jordan inversion (no pivoting needed for an SPD matrix).
 // work: 2n ints + n doubles.
-__global__ void k_coarse_factor(int n, double *A, int *work)
+// Make the coarsest matrix definite: A += sum over its connected components c
+// of (mean diagonal of c / |c|) 1_c 1_c^T.  For right sides with zero sum per
+// component the inverse of the result applies the pseudo-inverse and returns
+// the solution with zero sum per component.  (One workgroup: the components
+// by repeated minimum-label propagation over the dense pattern.)
+__global__ void k_coarse_regularize(int n, double *A, int *work)
 {
     const int t = threadIdx.x, nt = blockDim.x;
     int *comp = work;
     int *csize = work + n;
     double *colk = (double *)(work + 2 * n + ((2 * n) & 1));
     __shared__ int changed;
-    __shared__ double piv;
     for (int q = t; q < n; q += nt) {
         comp[q] = q;
         csize[q] = 0;
@@ -601,24 +605,6 @@ __global__ void k_coarse_factor(int n, double *A, int *work)
             A[e] += (cdiag[c] / sz) / sz;
         }
     }
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        if (t == 0) piv = 1.0 / A[(long long)k * n + k];
-        __syncthreads();
-        for (int j = t; j < n; j += nt) {
-            const double v = (j == k) ? 1.0 : A[(long long)k * n + j];
-            A[(long long)k * n + j] = v * piv;
-        }
-        for (int i = t; i < n; i += nt) colk[i] = A[(long long)i * n + k];
-        __syncthreads();
-        for (long long e = t; e < (long long)n * n; e += nt) {
-            const int i = (int)(e / n), j = (int)(e % n);
-            if (i == k) continue;
-            const double base = (j == k) ? 0.0 : A[e];
-            A[e] = base - colk[i] * A[(long long)k * n + j];
-        }
-        __syncthreads();
-    }
 }
 
 hipError_t launch_coarse_assemble_brick(const double *w64, long long stride, Topo topo, const int *node_of_dof,
@@ -629,10 +615,12 @@ hipError_t launch_coarse_assemble_brick(const double *w64, long long stride, Top
     return hipGetLastError();
 }
 
-hipError_t launch_coarse_factor(int n, double *A, int *work, hipStream_t s)
+hipError_t launch_coarse_factor(int n, double *A, int *work, double *dwork, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coarse_factor, dim3(1), dim3(1024), 0, s, n, A, work);
+    hipLaunchKernelGGL(k_coarse_regularize, dim3(1), dim3(1024), 0, s, n, A, work);
+    HIP_RETURN_IF(hipGetLastError());
+    return launch_dense_inverse(n, A, dwork, s);
     return hipGetLastError();
 }
 
