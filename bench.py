@@ -32,6 +32,31 @@ FINE_CLASSES = {0: "k_col_cg_step (outer CG: p, deferred x, q = A p, p.q)",
                 5: "k_col_cheb_first (first Chebyshev step)",
                 6: "k_col_resid_restrict (residual + restriction)",
                 7: "k_col_cheb_step + prolongation (first post-smoothing step)"}
+# rocprofv3 summaries under profiles/ (HBM bytes per launch from FETCH_SIZE / WRITE_SIZE)
+PROFILE_OF = {0: "k_col_cg_step", 1: "k_rupdate", 2: "k_col_cheb_step_dots", 4: "k_col_cheb_step",
+              5: "k_col_cheb_first", 6: "k_col_resid_restrict", 7: "k_col_cheb_step_prolong"}
+KERNEL_SOURCES = ["paper_2010_12879_amd/csrc/kernels_col.hip", "paper_2010_12879_amd/csrc/kernels.hip",
+                  "paper_2010_12879_amd/csrc/common.h", "paper_2010_12879_amd/csrc/kernels.h"]
+
+
+def measured_traffic(name, workload):
+    """HBM bytes per launch from the committed counter summary, or None when the summary is
+    missing or the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{name}_{workload}.md")
+    if not os.path.exists(path):
+        return None, None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("    ") and not line.strip().startswith("rocprofv3"):
+            k, v = line.strip().split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if fields.get("kernel_source_sha256") != h.hexdigest() or "hbm_bytes_per_launch" not in fields:
+        return None, fields.get("median_duration_us")
+    return float(fields["hbm_bytes_per_launch"]), fields.get("median_duration_us")
 
 
 def parse():
@@ -263,6 +288,8 @@ def main():
                          "bytes_per_launch": v["timed_bytes"] / v["timed_launches"]}
     dom = max(kernels, key=lambda d: kernels[d]["est_ms_per_solve"]) if kernels else None
     achieved = kernels[dom]["algorithmic_gbs"] if dom else None
+    dom_class = next((k for k, d in FINE_CLASSES.items() if d == dom), None)
+    traffic, prof_us = measured_traffic(PROFILE_OF[dom_class], w.name) if dom_class is not None else (None, None)
 
     # independent check of the headline solution with the oracle's own assembly
     import oracle
@@ -296,7 +323,9 @@ def main():
         "device_bytes": ninfo["device_bytes"],
         "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
+                     "traffic_gbs": traffic / (kernels[dom]["avg_us"] * 1e-6) / 1e9 if traffic else None,
+                     "rocprof_median_us": float(prof_us) if prof_us else None,
                      "avg_us": kernels[dom]["avg_us"] if dom else None,
                      "algorithmic_bytes_per_launch": kernels[dom]["bytes_per_launch"] if dom else None},
         "finest_level_kernels": kernels,

@@ -39,8 +39,10 @@ struct Scal {
 };
 
 struct Topo {
-    int nb;              // active bricks
-    const int *nbr;      // [nb*6]
+    int nb;                                    // active bricks
+    const int *nbr;                            // [nb*6]
+    const unsigned long long *cmask = nullptr; // [nb]: bit tx + 8 ty set when the node column (tx,ty,*)
+                                               // holds an unknown (nullptr: all columns)
 };
 
 // XCD-aware workgroup -> brick map: the hardware hands consecutive workgroup

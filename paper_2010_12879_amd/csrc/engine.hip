@@ -57,7 +57,8 @@ struct Level {
     int *d_mptr = nullptr;          // members of each row in the finer level (CSR)
     int *d_mem = nullptr;
     int *d_agg = nullptr;           // this level's unknown -> row of the next (split) level, -1 if none
-    Topo topo() const { return Topo{nb, d_nbr}; }
+    unsigned long long *d_cmask = nullptr;  // node columns with unknowns, per brick (structured levels)
+    Topo topo() const { return Topo{nb, d_nbr, d_cmask}; }
     long long nodes() const { return ell ? (long long)nrow : (long long)nb * BS; }
 };
 
@@ -162,6 +163,16 @@ struct HipFail {
 
 void drop_graphs(Ctx *c);
 
+}  // namespace
+
+LaunchEvents &spfd::next_launch_events()
+{
+    static thread_local LaunchEvents ev;
+    return ev;
+}
+
+namespace {
+
 // order the library's stream after the work the caller has queued on its stream
 void enter(Ctx *c)
 {
@@ -251,28 +262,41 @@ struct TScope {
         c->tlaunch[cls] += 1;
         c->tbytes[cls] += bytes;
         if (on) {
+            // the launch inside the scope records both events itself
+            hipEvent_t e0 = event(), e1 = event();
+            if (!e0 || !e1) {
+                on = false;
+                return;
+            }
+            c->tused[cls] += 2;
             c->ttimed[cls] += 1;
             c->ttbytes[cls] += bytes;
-            record();
+            next_launch_events() = LaunchEvents{e0, e1};
+            this->bytes = bytes;
         }
     }
     ~TScope()
     {
-        if (on) record();
+        if (on && next_launch_events().start) {
+            // nothing was launched in the scope: drop the sample
+            next_launch_events() = LaunchEvents{};
+            c->tused[cls] -= 2;
+            c->ttimed[cls] -= 1;
+            c->ttbytes[cls] -= bytes;
+        }
     }
-    void record()
+    double bytes = 0.0;
+    hipEvent_t event()
     {
         std::vector<hipEvent_t> &v = c->tev[cls];
-        if (c->tused[cls] == v.size()) {
+        while (v.size() < c->tused[cls] + 2) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) {
-                on = false;
-                return;
-            }
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
             v.push_back(e);
         }
-        (void)hipEventRecord(v[c->tused[cls]++], c->stream);
+        return v[c->tused[cls] + (next_pending++)];
     }
+    int next_pending = 0;
 };
 
 // ------------------------------------------------------------ brick topology on the host
@@ -866,7 +890,7 @@ spfd_status do_build(Ctx *c)
         if (c->ncoarse > maxd)
             return fail(c, SPFD_INVALID_ARG, "coarsest level too large (grid cannot be coarsened further)");
         c->d_Ainv = dalloc<double>(c, c->hier_allocs, (size_t)c->ncoarse * c->ncoarse + 1);
-        c->d_cwork = dalloc<int>(c, c->hier_allocs, (size_t)5 * maxd + 8);
+        c->d_cwork = dalloc<int>(c, c->hier_allocs, coarse_factor_work_ints(maxd));
         if (C.ell)
             HIPCHK(launch_coarse_dense_ell(C.nrow, C.K, C.d_col, C.d_val64, c->d_node_cdof, c->d_cdof_node, c->ncoarse,
                                            c->d_Ainv, c->stream));
@@ -876,6 +900,12 @@ spfd_status do_build(Ctx *c)
         double *dwork = dalloc<double>(c, c->hier_allocs, dense_inverse_work_doubles(c->ncoarse));
         HIPCHK(launch_coarse_factor(c->ncoarse, c->d_Ainv, c->d_cwork, dwork, c->stream));
     }
+    // column masks of the structured levels (the stencil kernels skip columns without unknowns)
+    for (Level &L : c->lv)
+        if (!L.ell && L.nb > 0) {
+            L.d_cmask = dalloc<unsigned long long>(c, c->hier_allocs, L.nb);
+            HIPCHK(launch_col_masks(L.d_w64, L.nodes(), L.topo(), L.d_cmask, c->stream));
+        }
     chebyshev_coefficients(c);
     HIPCHK(hipStreamSynchronize(c->stream));
     return SPFD_OK;

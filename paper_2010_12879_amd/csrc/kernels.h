@@ -3,9 +3,31 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace spfd {
+
+// Timing events for the next kernel launch, set by the host's timing scope and
+// consumed by that launch: the dispatch itself records the start and stop
+// times (no separate marker packets in the stream).
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchEvents &next_launch_events();
+
+#define SPFD_LAUNCH(kernel, grid, block, shmem, stream, ...)                                                \
+    do {                                                                                                    \
+        LaunchEvents &le_ = next_launch_events();                                                           \
+        if (le_.start) {                                                                                    \
+            const LaunchEvents ev_ = le_;                                                                   \
+            le_ = LaunchEvents{};                                                                           \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ev_.start, ev_.stop, 0, __VA_ARGS__); \
+        } else {                                                                                            \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                            \
+        }                                                                                                   \
+    } while (0)
 
 #define HIP_RETURN_IF(...)                        \
     do {                                          \
@@ -60,8 +82,11 @@ hipError_t launch_coarse_setup(const double *w64, long long stride, Topo topo, i
 hipError_t launch_coarse_assemble_brick(const double *w64, long long stride, Topo topo, const int *node_of_dof,
                                         const int *adj, int n, double *A, hipStream_t s);
 // dense pseudo-inverse in place; work: 2n ints + n doubles (+1 int of padding)
-// A <- inverse of the regularised coarsest matrix (work: 5n ints; dwork:
-// dense_inverse_work_doubles(n) doubles)
+// per brick, the node columns (tx,ty) that hold unknowns (bit tx + 8 ty)
+hipError_t launch_col_masks(const double *w64, long long stride, Topo topo, unsigned long long *mask, hipStream_t s);
+// A <- inverse of the regularised coarsest matrix (work: coarse_factor_work_ints(n)
+// ints; dwork: dense_inverse_work_doubles(n) doubles)
+size_t coarse_factor_work_ints(int n);
 hipError_t launch_coarse_factor(int n, double *A, int *work, double *dwork, hipStream_t s);
 size_t dense_inverse_work_doubles(int n);
 hipError_t launch_dense_inverse(int n, double *A, double *work, hipStream_t s);

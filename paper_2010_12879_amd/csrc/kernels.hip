@@ -84,7 +84,7 @@ hipError_t launch_brick_flags(const uint8_t *labels, const double *table, int nl
     const long long nvox = (long long)g.nx * g.ny * g.nz;
     long long blocks = (nvox + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_brick_flags, dim3((unsigned)blocks), dim3(256), 0, s, labels, table, nlab, sig_vox, g,
+    SPFD_LAUNCH(k_brick_flags, dim3((unsigned)blocks), dim3(256), 0, s, labels, table, nlab, sig_vox, g,
                        flags, err);
     return hipGetLastError();
 }
@@ -111,7 +111,7 @@ hipError_t launch_label_tiles(const uint8_t *labels, const Grid &g, const int4 *
                               hipStream_t s)
 {
     if (nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_label_tiles, dim3(nb), dim3(256), 0, s, labels, g, coord, tiles);
+    SPFD_LAUNCH(k_label_tiles, dim3(nb), dim3(256), 0, s, labels, g, coord, tiles);
     return hipGetLastError();
 }
 
@@ -160,7 +160,7 @@ hipError_t launch_weights0(const uint8_t *labels, const double *table, const dou
                            const double geo4[3], const int4 *coord, int nb, double *w64, float *w32, hipStream_t s)
 {
     if (nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_weights0, dim3(nb), dim3(NT), 0, s, labels, table, sig_vox, g, geo4[0], geo4[1], geo4[2],
+    SPFD_LAUNCH(k_weights0, dim3(nb), dim3(NT), 0, s, labels, table, sig_vox, g, geo4[0], geo4[1], geo4[2],
                        coord, w64, w32, (long long)nb * BS);
     return hipGetLastError();
 }
@@ -214,7 +214,7 @@ hipError_t launch_galerkin(const double *wf, long long fstride, const int *f_slo
                            long long cstride, hipStream_t s)
 {
     if (cnb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_galerkin, dim3(cnb), dim3(NT), 0, s, wf, fstride, f_slot_of, fGx, fGy, fGz, fNx, fNy, fNz,
+    SPFD_LAUNCH(k_galerkin, dim3(cnb), dim3(NT), 0, s, wf, fstride, f_slot_of, fGx, fGy, fGz, fNx, fNy, fNz,
                        ccoord, wc64, wc32, cstride);
     return hipGetLastError();
 }
@@ -382,9 +382,9 @@ static hipError_t scan_exclusive(const int *in, long long n, int *out, int *bsum
 {
     const long long nblk = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nblk), dim3(NT), 0, s, in, n, out, bsum);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(NT), 0, s, bsum, (int)nblk, total);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nblk), dim3(NT), 0, s, out, n, bsum);
+    SPFD_LAUNCH(k_scan_blocks, dim3((unsigned)nblk), dim3(NT), 0, s, in, n, out, bsum);
+    SPFD_LAUNCH(k_scan_sums, dim3(1), dim3(NT), 0, s, bsum, (int)nblk, total);
+    SPFD_LAUNCH(k_scan_add, dim3((unsigned)nblk), dim3(NT), 0, s, out, n, bsum);
     return hipGetLastError();
 }
 
@@ -409,14 +409,14 @@ hipError_t launch_components(const double *w64, long long stride, Topo topo, int
     const int nb = topo.nb;
     const long long n = (long long)nb * BS;
     if (nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cc_init, dim3(nb), dim3(NT), 0, s, w64, stride, topo, parent);
-    hipLaunchKernelGGL(k_cc_union, dim3(nb), dim3(NT), 0, s, w64, stride, topo, parent);
+    SPFD_LAUNCH(k_cc_init, dim3(nb), dim3(NT), 0, s, w64, stride, topo, parent);
+    SPFD_LAUNCH(k_cc_union, dim3(nb), dim3(NT), 0, s, w64, stride, topo, parent);
     const unsigned gb = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
-    hipLaunchKernelGGL(k_cc_store_root, dim3(gb), dim3(256), 0, s, parent, n);
-    hipLaunchKernelGGL(k_cc_flatten, dim3(gb), dim3(256), 0, s, parent, n, flag);
+    SPFD_LAUNCH(k_cc_store_root, dim3(gb), dim3(256), 0, s, parent, n);
+    SPFD_LAUNCH(k_cc_flatten, dim3(gb), dim3(256), 0, s, parent, n, flag);
     hipError_t e = scan_exclusive(flag, n, idx, scan_tmp, ncomp_dev, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cc_assign, dim3(gb), dim3(256), 0, s, parent, idx, n, comp);
+    SPFD_LAUNCH(k_cc_assign, dim3(gb), dim3(256), 0, s, parent, idx, n, comp);
     return hipGetLastError();
 }
 
@@ -439,7 +439,7 @@ hipError_t launch_comp_counts(const int *comp, long long n, int *counts, hipStre
 {
     const unsigned gb = (unsigned)((n + 255) / 256 > 4096 ? 4096 : (n + 255) / 256);
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_comp_counts, dim3(gb), dim3(256), 0, s, comp, n, counts);
+    SPFD_LAUNCH(k_comp_counts, dim3(gb), dim3(256), 0, s, comp, n, counts);
     return hipGetLastError();
 }
 
@@ -513,7 +513,7 @@ __global__ void k_coarse_enum(const double *__restrict__ w, long long stride, To
 hipError_t launch_coarse_setup(const double *w64, long long stride, Topo topo, int *dof_of_node, int *node_of_dof,
                                int *adj, int *ndof_dev, int maxdof, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_coarse_enum, dim3(1), dim3(1024), 0, s, w64, stride, topo, dof_of_node, node_of_dof, adj,
+    SPFD_LAUNCH(k_coarse_enum, dim3(1), dim3(1024), 0, s, w64, stride, topo, dof_of_node, node_of_dof, adj,
                        ndof_dev, maxdof);
     return hipGetLastError();
 }
@@ -554,35 +554,87 @@ __global__ void k_coarse_assemble_brick(const double *__restrict__ w, long long 
 // the nonzeros, regularisation with alpha_c = mean diagonal / size^2, and
 // Gauss-Jordan inversion (no pivoting needed for an SPD matrix).
 // work: 2n ints + n doubles.
+// Column masks of a structured level: bit tx + 8 ty of brick b is set when a
+// node (tx,ty,*) of the brick has a positive diagonal (is an unknown).
+__global__ __launch_bounds__(NT) void k_col_masks(const double *__restrict__ w, long long stride, Topo topo,
+                                                  unsigned long long *__restrict__ mask)
+{
+    __shared__ unsigned long long m;
+    const int bk = blockIdx.x;
+    const int t = threadIdx.x;
+    if (t == 0) m = 0ull;
+    __syncthreads();
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    int nb[6];
+    brick_nbrs(topo.nbr, bk, nb);
+    const long long base = (long long)bk * BS;
+    long long I[6];
+    nbr_index(base, t, tx, ty, tz, nb, I);
+    double W[6];
+    stored_weights(w, stride, base, t, I, W);
+    if (diag_of(W) > 0.0) atomicOr(&m, 1ull << (t & 63));
+    __syncthreads();
+    if (t == 0) mask[bk] = m;
+}
+
+hipError_t launch_col_masks(const double *w64, long long stride, Topo topo, unsigned long long *mask, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    Topo tp{topo.nb, topo.nbr, nullptr};
+    SPFD_LAUNCH(k_col_masks, dim3(topo.nb), dim3(NT), 0, s, w64, stride, tp, mask);
+    return hipGetLastError();
+}
+
 // Make the coarsest matrix definite: A += sum over its connected components c
 // of (mean diagonal of c / |c|) 1_c 1_c^T.  For right sides with zero sum per
 // component the inverse of the result applies the pseudo-inverse and returns
 // the solution with zero sum per component.  (One workgroup: the components
 // by repeated minimum-label propagation over the dense pattern.)
+constexpr int CMAXADJ = 64;
+
 __global__ void k_coarse_regularize(int n, double *A, int *work)
 {
     const int t = threadIdx.x, nt = blockDim.x;
     int *comp = work;
     int *csize = work + n;
     double *colk = (double *)(work + 2 * n + ((2 * n) & 1));
+    int *deg = work + 4 * n + 2;          // row degree (-1: more than CMAXADJ, scan the dense row)
+    int *adj = deg + n;                   // [n][CMAXADJ] off-diagonal nonzero columns
     __shared__ int changed;
+    // the pattern once, as adjacency lists
     for (int q = t; q < n; q += nt) {
         comp[q] = q;
         csize[q] = 0;
+        int d = 0;
+        for (int m = 0; m < n && d >= 0; ++m) {
+            if (m == q || A[(long long)q * n + m] == 0.0) continue;
+            if (d < CMAXADJ)
+                adj[(long long)q * CMAXADJ + d++] = m;
+            else
+                d = -1;
+        }
+        deg[q] = d;
     }
     __syncthreads();
+    // minimum label over each component: neighbour minima plus pointer jumping
     do {
         __syncthreads();
         if (t == 0) changed = 0;
         __syncthreads();
         for (int q = t; q < n; q += nt) {
-            int c = comp[q];
-            for (int m = 0; m < n; ++m) {
-                if (m == q || A[(long long)q * n + m] == 0.0) continue;
+            int c = __hip_atomic_load(comp + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int d = deg[q];
+            const int cnt = d >= 0 ? d : n;
+            for (int k = 0; k < cnt; ++k) {
+                const int m = d >= 0 ? adj[(long long)q * CMAXADJ + k] : k;
+                if (d < 0 && (m == q || A[(long long)q * n + m] == 0.0)) continue;
                 const int cm = __hip_atomic_load(comp + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (cm < c) c = cm;
             }
-            if (c < comp[q]) {
+            const int cc = __hip_atomic_load(comp + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (cc < c) c = cc;
+            if (c < __hip_atomic_load(comp + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
                 __hip_atomic_store(comp + q, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 changed = 1;
             }
@@ -611,14 +663,16 @@ hipError_t launch_coarse_assemble_brick(const double *w64, long long stride, Top
                                         const int *adj, int n, double *A, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coarse_assemble_brick, dim3(1), dim3(1024), 0, s, w64, stride, topo, node_of_dof, adj, n, A);
+    SPFD_LAUNCH(k_coarse_assemble_brick, dim3(1), dim3(1024), 0, s, w64, stride, topo, node_of_dof, adj, n, A);
     return hipGetLastError();
 }
+
+size_t coarse_factor_work_ints(int n) { return (size_t)(5 + CMAXADJ) * n + 8; }
 
 hipError_t launch_coarse_factor(int n, double *A, int *work, double *dwork, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coarse_regularize, dim3(1), dim3(1024), 0, s, n, A, work);
+    SPFD_LAUNCH(k_coarse_regularize, dim3(1), dim3(1024), 0, s, n, A, work);
     HIP_RETURN_IF(hipGetLastError());
     return launch_dense_inverse(n, A, dwork, s);
     return hipGetLastError();
@@ -640,7 +694,7 @@ hipError_t launch_fill(T *x, long long n, T v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const unsigned gb = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
-    hipLaunchKernelGGL(k_fill<T>, dim3(gb), dim3(256), 0, s, x, n, v);
+    SPFD_LAUNCH(k_fill<T>, dim3(gb), dim3(256), 0, s, x, n, v);
     return hipGetLastError();
 }
 template hipError_t launch_fill<double>(double *, long long, double, hipStream_t);
@@ -664,7 +718,7 @@ __global__ void k_scal_init(Scal *sc, double tol, int use_x0)
 
 hipError_t launch_scal_init(Scal *sc, double tol, int use_x0, int nbatch, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scal_init, dim3(nbatch), dim3(64), 0, s, sc, tol, use_x0);
+    SPFD_LAUNCH(k_scal_init, dim3(nbatch), dim3(64), 0, s, sc, tol, use_x0);
     return hipGetLastError();
 }
 
@@ -776,7 +830,7 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
 hipError_t launch_finish(const double *part, int n, int mode, Scal *sc, int max_iter, hipStream_t s, double *means,
                          const int *counts, int comp, int nbatch, int ps)
 {
-    hipLaunchKernelGGL(k_finish, dim3(nbatch), dim3(1024), 0, s, part, n, mode, sc, max_iter, means, counts, comp, ps);
+    SPFD_LAUNCH(k_finish, dim3(nbatch), dim3(1024), 0, s, part, n, mode, sc, max_iter, means, counts, comp, ps);
     return hipGetLastError();
 }
 
@@ -823,9 +877,9 @@ hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, co
 {
     if (topo.nb <= 0) return hipSuccess;
     if (op.w)
-        hipLaunchKernelGGL(k_rhs<false>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, coord, g, a, b, part);
+        SPFD_LAUNCH(k_rhs<false>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, coord, g, a, b, part);
     else
-        hipLaunchKernelGGL(k_rhs<true>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, coord, g, a, b, part);
+        SPFD_LAUNCH(k_rhs<true>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, coord, g, a, b, part);
     return hipGetLastError();
 }
 
@@ -882,7 +936,7 @@ hipError_t launch_x_final(Topo topo, double *x, const double *pa, const double *
                           hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_x_final, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, x, pa, pb, sc, bt.vs);
+    SPFD_LAUNCH(k_x_final, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, x, pa, pb, sc, bt.vs);
     return hipGetLastError();
 }
 
@@ -908,7 +962,7 @@ hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, S
                           hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rupdate, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, r, q, part, sc, bt.vs, bt.ps,
+    SPFD_LAUNCH(k_rupdate, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, r, q, part, sc, bt.vs, bt.ps,
                        r32);
     return hipGetLastError();
 }
@@ -917,7 +971,7 @@ hipError_t launch_spmv_dot(const OpArgs<double> &op, Topo topo, const double *p,
                            const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spmv_dot, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, p, q, part, sc, bt.vs,
+    SPFD_LAUNCH(k_spmv_dot, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, p, q, part, sc, bt.vs,
                        bt.ps);
     return hipGetLastError();
 }
@@ -952,7 +1006,7 @@ hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const
                          const Batch &bt, float *r32, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_update, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, x, r, p, q, part, sc, bt.vs,
+    SPFD_LAUNCH(k_update, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, x, r, p, q, part, sc, bt.vs,
                        bt.ps, r32);
     return hipGetLastError();
 }
@@ -995,7 +1049,7 @@ hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, co
                         double *part, long long bvs, const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_resid, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, b, x, r, part, bvs, bt.vs,
+    SPFD_LAUNCH(k_resid, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, b, x, r, part, bvs, bt.vs,
                        bt.ps);
     return hipGetLastError();
 }
@@ -1030,7 +1084,7 @@ hipError_t launch_dots(Topo topo, const TZ *z, const double *r, const double *q,
                        const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dots<TZ>, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, z, r, q, part, sc, first, bt.vs,
+    SPFD_LAUNCH(k_dots<TZ>, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, z, r, q, part, sc, first, bt.vs,
                        bt.ps);
     return hipGetLastError();
 }
@@ -1059,7 +1113,7 @@ hipError_t launch_pupdate(Topo topo, const TZ *z, double *p, const Scal *sc, int
                           hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pupdate<TZ>, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, z, p, sc, first, bt.vs);
+    SPFD_LAUNCH(k_pupdate<TZ>, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, z, p, sc, first, bt.vs);
     return hipGetLastError();
 }
 template hipError_t launch_pupdate<double>(Topo, const double *, double *, const Scal *, int, const Batch &,
@@ -1120,7 +1174,7 @@ hipError_t launch_prolong(Topo topo, T *x, const T *xc, const int *parent_slot, 
                           const Scal *sc, const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_prolong<T>, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, x, xc, parent_slot, fcoord,
+    SPFD_LAUNCH(k_prolong<T>, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, x, xc, parent_slot, fcoord,
                        scale, sc, bt.vs, bt.vsc);
     return hipGetLastError();
 }
@@ -1131,7 +1185,7 @@ hipError_t launch_coarse_apply(const TB *bc, T *xc, const double *Ainv, const in
 {
     if (n <= 0) return hipSuccess;
     if (n > 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_coarse_apply<T, TB>), dim3((n + 3) / 4, bt.n), dim3(256), 0, s, bc, xc, Ainv, node_of_dof, n,
+    SPFD_LAUNCH((k_coarse_apply<T, TB>), dim3((n + 3) / 4, bt.n), dim3(256), 0, s, bc, xc, Ainv, node_of_dof, n,
                        sc, bt.vs);
     return hipGetLastError();
 }
@@ -1185,7 +1239,7 @@ hipError_t launch_comp_mean(Topo topo, const double *x, const int *comp, int nco
     if (topo.nb <= 0 || ncomp <= 0) return hipSuccess;
     if (ncomp <= 16) {
         for (int c = 0; c < ncomp; ++c) {
-            hipLaunchKernelGGL(k_comp_sum, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, comp, c, part);
+            SPFD_LAUNCH(k_comp_sum, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, comp, c, part);
             hipError_t e = launch_finish(part, topo.nb, FIN_MEAN, nullptr, 0, s, means, counts, c, 1, 0);
             if (e != hipSuccess) return e;
         }
@@ -1194,8 +1248,8 @@ hipError_t launch_comp_mean(Topo topo, const double *x, const int *comp, int nco
         hipError_t e = launch_fill<double>(means, ncomp, 0.0, s);
         if (e != hipSuccess) return e;
         const unsigned gb = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
-        hipLaunchKernelGGL(k_comp_sum_atomic, dim3(gb), dim3(256), 0, s, n, x, comp, means);
-        hipLaunchKernelGGL(k_comp_div, dim3((ncomp + 255) / 256), dim3(256), 0, s, ncomp, counts, means);
+        SPFD_LAUNCH(k_comp_sum_atomic, dim3(gb), dim3(256), 0, s, n, x, comp, means);
+        SPFD_LAUNCH(k_comp_div, dim3((ncomp + 255) / 256), dim3(256), 0, s, ncomp, counts, means);
     }
     return hipGetLastError();
 }
@@ -1223,7 +1277,7 @@ hipError_t launch_psi_out(const double *x, const int *comp, const double *means,
 {
     const long long nn = (long long)g.Nx * g.Ny * g.Nz;
     const unsigned gb = (unsigned)((nn + 255) / 256 > 131072 ? 131072 : (nn + 255) / 256);
-    hipLaunchKernelGGL(k_psi_out, dim3(gb), dim3(256), 0, s, x, comp, means, slot_of, g, psi);
+    SPFD_LAUNCH(k_psi_out, dim3(gb), dim3(256), 0, s, x, comp, means, slot_of, g, psi);
     return hipGetLastError();
 }
 
@@ -1246,7 +1300,7 @@ hipError_t launch_psi_in(const double *psi, const int *comp, const int4 *coord, 
                          hipStream_t s)
 {
     if (nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_psi_in, dim3(nb), dim3(NT), 0, s, psi, comp, coord, g, x);
+    SPFD_LAUNCH(k_psi_in, dim3(nb), dim3(NT), 0, s, psi, comp, coord, g, x);
     return hipGetLastError();
 }
 
@@ -1289,7 +1343,7 @@ hipError_t launch_efield(const uint8_t *labels, const double *table, const doubl
 {
     const long long nvox = (long long)g.nx * g.ny * g.nz;
     const unsigned gb = (unsigned)((nvox + 255) / 256 > 131072 ? 131072 : (nvox + 255) / 256);
-    hipLaunchKernelGGL(k_efield, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, h[0], h[1], h[2], omega, a, psi,
+    SPFD_LAUNCH(k_efield, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, h[0], h[1], h[2], omega, a, psi,
                        emag);
     return hipGetLastError();
 }
@@ -1324,7 +1378,7 @@ hipError_t launch_uedges(const uint8_t *labels, const double *table, const doubl
 {
     const long long nn = (long long)g.Nx * g.Ny * g.Nz;
     const unsigned gb = (unsigned)((nn + 255) / 256 > 131072 ? 131072 : (nn + 255) / 256);
-    hipLaunchKernelGGL(k_uedges, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, a, psi, u);
+    SPFD_LAUNCH(k_uedges, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, a, psi, u);
     return hipGetLastError();
 }
 
@@ -1470,7 +1524,7 @@ hipError_t launch_adj_voxel(const uint8_t *labels, const double *table, const do
 {
     const long long nvox = (long long)g.nx * g.ny * g.nz;
     const unsigned gb = (unsigned)((nvox + 255) / 256 > 131072 ? 131072 : (nvox + 255) / 256);
-    hipLaunchKernelGGL(k_adj_voxel, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, h[0], h[1], h[2], omega, a,
+    SPFD_LAUNCH(k_adj_voxel, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, h[0], h[1], h[2], omega, a,
                        psi, grad_emag, c);
     return hipGetLastError();
 }
@@ -1479,7 +1533,7 @@ hipError_t launch_adj_rhs(Topo topo, const int4 *coord, const Grid &g, const dou
                           hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adj_rhs, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, coord, g, c, b, part);
+    SPFD_LAUNCH(k_adj_rhs, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, coord, g, c, b, part);
     return hipGetLastError();
 }
 
@@ -1495,9 +1549,9 @@ hipError_t launch_adj_grad(const uint8_t *labels, const double *table, const dou
                            double *lab_part, int nlab, double *lab_out, hipStream_t s)
 {
     const int gb = adj_grad_blocks(g);
-    hipLaunchKernelGGL(k_adj_grad, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, geo4[0], geo4[1], geo4[2], a,
+    SPFD_LAUNCH(k_adj_grad, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, geo4[0], geo4[1], geo4[2], a,
                        psi, lam, grad, lab_part, nlab);
-    hipLaunchKernelGGL(k_adj_labsum, dim3(nlab), dim3(NT), 0, s, lab_part, gb, nlab, lab_out);
+    SPFD_LAUNCH(k_adj_labsum, dim3(nlab), dim3(NT), 0, s, lab_part, gb, nlab, lab_out);
     return hipGetLastError();
 }
 

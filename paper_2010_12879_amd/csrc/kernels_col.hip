@@ -52,6 +52,7 @@ struct Seg {
     long long lat[4];                             // x-, x+, y-, y+ neighbours of (tx, ty, z0)
     long long zm, zp;                             // (tx, ty, z0-1) and (tx, ty, z0+ZPL)
     bool has[6];                                  // neighbour slot exists
+    bool active;                                  // the lane's node column holds an unknown
 };
 
 template <int ZPL>
@@ -73,7 +74,11 @@ __device__ __forceinline__ Seg<ZPL> make_seg(const Topo &topo)
     s.z0 = (wave % Seg<ZPL>::WPB) * ZPL;
     const int b = s.grp < 0 ? -1 : s.grp * Seg<ZPL>::BPG + wave / Seg<ZPL>::WPB;
     s.bk = b < topo.nb ? b : -1;
+    s.active = false;
     if (s.bk < 0) return s;
+    // a column without unknowns neither loads nor stores: its slots stay zero,
+    // and edges into them have conductance 0
+    s.active = !topo.cmask || ((topo.cmask[s.bk] >> s.lane) & 1ull);
     int nb[6];
     brick_nbrs(topo.nbr, s.bk, nb);
     const long long base = (long long)s.bk * BS;
@@ -269,12 +274,13 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo 
     b += blockIdx.y * vs;
     x += blockIdx.y * vs;
     SegOp<T, ZPL, LABEL> A;
-    A.load(op, s, lds);
+    if (LABEL || s.active) A.load(op, s, lds);
     T bv[ZPL];
+    if (s.active)
 #pragma unroll
-    for (int z = 0; z < ZPL; ++z) bv[z] = (T)b[s.self + 64 * z];
+        for (int z = 0; z < ZPL; ++z) bv[z] = (T)b[s.self + 64 * z];
     A.stage(op, s);
-    if (done) return;
+    if (done || !s.active) return;
 #pragma unroll
     for (int z = 0; z < ZPL; ++z) {
         T W[6];
@@ -374,31 +380,33 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo t
         if (din) din += blockIdx.y * vs;
         if (dout) dout += blockIdx.y * vs;
         SegOp<T, ZPL, LABEL> A;
-        A.load(op, s, lds);
+        if (LABEL || s.active) A.load(op, s, lds);
         SegVals<T, ZPL> X;
-        X.load(xin, s);
         T bv[ZPL], dv[ZPL];
-#pragma unroll
-        for (int z = 0; z < ZPL; ++z) {
-            bv[z] = (T)b[s.self + 64 * z];
-            if (din) dv[z] = din[s.self + 64 * z];
-        }
         double rv[DOT ? ZPL : 1], qv[DOT ? ZPL : 1];
-        if constexpr (DOT) {
-            const double *r = dt.r + blockIdx.y * vs, *q = dt.q + blockIdx.y * vs;
+        if (s.active) {
+            X.load(xin, s);
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) {
-                rv[z] = r[s.self + 64 * z];
-                qv[z] = q[s.self + 64 * z];
+                bv[z] = (T)b[s.self + 64 * z];
+                if (din) dv[z] = din[s.self + 64 * z];
+            }
+            if constexpr (DOT) {
+                const double *r = dt.r + blockIdx.y * vs, *q = dt.q + blockIdx.y * vs;
+#pragma unroll
+                for (int z = 0; z < ZPL; ++z) {
+                    rv[z] = r[s.self + 64 * z];
+                    qv[z] = q[s.self + 64 * z];
+                }
+            }
+            if constexpr (PRO) apply_prolong<T, ZPL>(pr, topo, s, X);
+            if (!din) {
+#pragma unroll
+                for (int z = 0; z < ZPL; ++z) dv[z] = X.c[z];
             }
         }
-        if constexpr (PRO) apply_prolong<T, ZPL>(pr, topo, s, X);
-        if (!din) {
-#pragma unroll
-            for (int z = 0; z < ZPL; ++z) dv[z] = X.c[z];
-        }
         A.stage(op, s);
-        if (!done) {
+        if (!done && s.active) {
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) {
                 T W[6], N[6];
@@ -461,23 +469,28 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
     x += blockIdx.y * vs;
     bc += blockIdx.y * vsc;
     SegOp<T, ZPL, LABEL> A;
-    A.load(op, s, lds);
+    if (LABEL || s.active) A.load(op, s, lds);
     SegVals<T, ZPL> X;
-    X.load(x, s);
     T bv[ZPL];
+    if (s.active) {
+        X.load(x, s);
 #pragma unroll
-    for (int z = 0; z < ZPL; ++z) bv[z] = (T)b[s.self + 64 * z];
+        for (int z = 0; z < ZPL; ++z) bv[z] = (T)b[s.self + 64 * z];
+    }
     const int4 fc = fcoord[s.bk];
     const long long pbase = (long long)parent_slot[s.bk] * BS;
     A.stage(op, s);
     T r[ZPL];
 #pragma unroll
-    for (int z = 0; z < ZPL; ++z) {
-        T W[6], N[6];
-        A.weights(s, z, W);
-        X.nbrs(z, N);
-        r[z] = bv[z] - stencil_apply(X.c[z], N, W);
-    }
+    for (int z = 0; z < ZPL; ++z) r[z] = T(0);
+    if (s.active)
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) {
+            T W[6], N[6];
+            A.weights(s, z, W);
+            X.nbrs(z, N);
+            r[z] = bv[z] - stencil_apply(X.c[z], N, W);
+        }
     const int ox = (fc.x & 1) * 4 + (s.tx >> 1), oy = (fc.y & 1) * 4 + (s.ty >> 1);
     const int oz = (fc.z & 1) * 4 + (s.z0 >> 1);
     const bool corner = ((s.tx | s.ty) & 1) == 0 && !done;
@@ -520,15 +533,17 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
     double dot = 0.0;
     if (s.bk >= 0) {
         SegOp<double, ZPL, LABEL> A;
-        A.load(op, s, lds);
+        if (LABEL || s.active) A.load(op, s, lds);
         SegVals<TZ, ZPL> Z;
-        Z.load(zv, s);
         SegVals<double, ZPL> Pi;
         double xv[ZPL];
-        if (!first) {
-            Pi.load(pin, s);
+        if (s.active) {
+            Z.load(zv, s);
+            if (!first) {
+                Pi.load(pin, s);
 #pragma unroll
-            for (int z = 0; z < ZPL; ++z) xv[z] = x[s.self + 64 * z];
+                for (int z = 0; z < ZPL; ++z) xv[z] = x[s.self + 64 * z];
+            }
         }
         const double beta = first ? 0.0 : sc->beta;
         const double alpha = first ? 0.0 : sc->alpha;
@@ -543,7 +558,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
         P.zm = first ? (double)Z.zm : (double)Z.zm + beta * Pi.zm;
         P.zp = first ? (double)Z.zp : (double)Z.zp + beta * Pi.zp;
         A.stage(op, s);
-        if (!done) {
+        if (!done && s.active) {
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) {
                 double W[6], N[6];
@@ -594,10 +609,10 @@ hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, 
     constexpr int ZPL_CYCLE = zpl_cycle<T>();
     const dim3 g = col_grid<ZPL_CYCLE>(topo.nb, bt.n);
     if (op.w)
-        hipLaunchKernelGGL((k_col_cheb_first<T, TB, ZPL_CYCLE, false>), g, dim3(CTHREADS), 0, s, op, topo, b, x, c0, sc,
+        SPFD_LAUNCH((k_col_cheb_first<T, TB, ZPL_CYCLE, false>), g, dim3(CTHREADS), 0, s, op, topo, b, x, c0, sc,
                            bt.vs);
     else
-        hipLaunchKernelGGL((k_col_cheb_first<T, TB, ZPL_CYCLE, true>), g, dim3(CTHREADS), 0, s, op, topo, b, x, c0, sc,
+        SPFD_LAUNCH((k_col_cheb_first<T, TB, ZPL_CYCLE, true>), g, dim3(CTHREADS), 0, s, op, topo, b, x, c0, sc,
                            bt.vs);
     return hipGetLastError();
 }
@@ -619,7 +634,7 @@ hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T
     const int sel = (op.w ? 0 : 4) | (xc ? 2 : 0) | (dot_part ? 1 : 0);
 #define SPFD_CHEB_CASE(K, LAB, PRO, DOT)                                                                              \
     case K:                                                                                                           \
-        hipLaunchKernelGGL((k_col_cheb_step<T, TB, ZPL, LAB, PRO, DOT>), g, dim3(CTHREADS), 0, s, op, topo, b, xin,  \
+        SPFD_LAUNCH((k_col_cheb_step<T, TB, ZPL, LAB, PRO, DOT>), g, dim3(CTHREADS), 0, s, op, topo, b, xin,  \
                            xout, din, dout, c1, c2, sc, bt.vs, pr, dt);                                               \
         break;
     switch (sel) {
@@ -652,10 +667,10 @@ hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, co
     constexpr int ZPL_CYCLE = zpl_cycle<T>();
     const dim3 g = col_grid<ZPL_CYCLE>(topo.nb, bt.n);
     if (op.w)
-        hipLaunchKernelGGL((k_col_resid_restrict<T, TB, ZPL_CYCLE, false>), g, dim3(CTHREADS), 0, s, op, topo, b, x,
+        SPFD_LAUNCH((k_col_resid_restrict<T, TB, ZPL_CYCLE, false>), g, dim3(CTHREADS), 0, s, op, topo, b, x,
                            bc, parent_slot, fcoord, sc, bt.vs, bt.vsc);
     else
-        hipLaunchKernelGGL((k_col_resid_restrict<T, TB, ZPL_CYCLE, true>), g, dim3(CTHREADS), 0, s, op, topo, b, x,
+        SPFD_LAUNCH((k_col_resid_restrict<T, TB, ZPL_CYCLE, true>), g, dim3(CTHREADS), 0, s, op, topo, b, x,
                            bc, parent_slot, fcoord, sc, bt.vs, bt.vsc);
     return hipGetLastError();
 }
@@ -669,10 +684,10 @@ hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, cons
     if (pin == pout) return hipErrorInvalidValue;
     const dim3 g = col_grid<ZPL_CG>(topo.nb, bt.n);
     if (op.w)
-        hipLaunchKernelGGL((k_col_cg_step<TZ, ZPL_CG, false>), g, dim3(CTHREADS), 0, s, op, topo, z, pin, pout, x, q,
+        SPFD_LAUNCH((k_col_cg_step<TZ, ZPL_CG, false>), g, dim3(CTHREADS), 0, s, op, topo, z, pin, pout, x, q,
                            part, sc, first, parity, bt.vs, bt.ps);
     else
-        hipLaunchKernelGGL((k_col_cg_step<TZ, ZPL_CG, true>), g, dim3(CTHREADS), 0, s, op, topo, z, pin, pout, x, q,
+        SPFD_LAUNCH((k_col_cg_step<TZ, ZPL_CG, true>), g, dim3(CTHREADS), 0, s, op, topo, z, pin, pout, x, q,
                            part, sc, first, parity, bt.vs, bt.ps);
     return hipGetLastError();
 }

@@ -162,14 +162,14 @@ hipError_t launch_dense_inverse(int n, double *A, double *work, hipStream_t s)
     const int nt = ld / GT;
     double *W = work, *C = work + (long long)ld * ld, *P = C + (long long)ld * GT;
     auto blocks = [](long long m) { return (unsigned)((m + 255) / 256 > 65536 ? 65536 : (m + 255) / 256); };
-    hipLaunchKernelGGL(k_gj_pad, dim3(blocks((long long)ld * ld)), dim3(256), 0, s, n, ld, A, W);
+    SPFD_LAUNCH(k_gj_pad, dim3(blocks((long long)ld * ld)), dim3(256), 0, s, n, ld, A, W);
     for (int k = 0; k < nt; ++k) {
         const int k0 = k * GT;
-        hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, s, ld, k0, W, P);
-        hipLaunchKernelGGL(k_gj_row, dim3(nt), dim3(256), 0, s, ld, k0, W, P, C);
-        hipLaunchKernelGGL(k_gj_update, dim3(nt, nt), dim3(256), 0, s, ld, k0, W, P, C);
+        SPFD_LAUNCH(k_gj_diag, dim3(1), dim3(256), 0, s, ld, k0, W, P);
+        SPFD_LAUNCH(k_gj_row, dim3(nt), dim3(256), 0, s, ld, k0, W, P, C);
+        SPFD_LAUNCH(k_gj_update, dim3(nt, nt), dim3(256), 0, s, ld, k0, W, P, C);
     }
-    hipLaunchKernelGGL(k_gj_unpad, dim3(blocks((long long)n * n)), dim3(256), 0, s, n, ld, W, A);
+    SPFD_LAUNCH(k_gj_unpad, dim3(blocks((long long)n * n)), dim3(256), 0, s, n, ld, W, A);
     return hipGetLastError();
 }
 

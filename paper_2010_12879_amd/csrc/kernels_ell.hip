@@ -296,8 +296,8 @@ hipError_t launch_pieces_brick(const double *w64, long long stride, Topo topo, c
                                hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_piece_init_brick, dim3(topo.nb), dim3(NT), 0, s, w64, stride, topo, parent);
-    hipLaunchKernelGGL(k_piece_union_brick, dim3(topo.nb), dim3(NT), 0, s, w64, stride, topo, parent);
+    SPFD_LAUNCH(k_piece_init_brick, dim3(topo.nb), dim3(NT), 0, s, w64, stride, topo, parent);
+    SPFD_LAUNCH(k_piece_union_brick, dim3(topo.nb), dim3(NT), 0, s, w64, stride, topo, parent);
     (void)coord;
     return hipGetLastError();
 }
@@ -306,21 +306,21 @@ hipError_t launch_pieces_ell(int n, int K, const int *col, const double *val, co
                              hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_piece_init_ell, dim3(gblocks(n)), dim3(256), 0, s, n, K, col, val, parent);
-    hipLaunchKernelGGL(k_piece_union_ell, dim3(gblocks(n)), dim3(256), 0, s, n, K, col, val, pos, parent);
+    SPFD_LAUNCH(k_piece_init_ell, dim3(gblocks(n)), dim3(256), 0, s, n, K, col, val, parent);
+    SPFD_LAUNCH(k_piece_union_ell, dim3(gblocks(n)), dim3(256), 0, s, n, K, col, val, pos, parent);
     return hipGetLastError();
 }
 
 hipError_t launch_pieces_finish(int *parent, long long n, int *flag, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_piece_store_root, dim3(gblocks(n)), dim3(256), 0, s, parent, n);
-    hipLaunchKernelGGL(k_piece_flatten, dim3(gblocks(n)), dim3(256), 0, s, parent, n, flag);
+    SPFD_LAUNCH(k_piece_store_root, dim3(gblocks(n)), dim3(256), 0, s, parent, n);
+    SPFD_LAUNCH(k_piece_flatten, dim3(gblocks(n)), dim3(256), 0, s, parent, n, flag);
     return hipGetLastError();
 }
 
 hipError_t launch_pieces_assign(const int *parent, const int *idx, long long n, int *agg, int *count, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_piece_assign, dim3(gblocks(n)), dim3(256), 0, s, parent, idx, n, agg, count);
+    SPFD_LAUNCH(k_piece_assign, dim3(gblocks(n)), dim3(256), 0, s, parent, idx, n, agg, count);
     return hipGetLastError();
 }
 
@@ -328,21 +328,21 @@ hipError_t launch_piece_pos_brick(const int *parent, const int *idx, Topo topo, 
                                   hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_piece_pos_brick, dim3(topo.nb), dim3(NT), 0, s, parent, idx, topo, coord, pos);
+    SPFD_LAUNCH(k_piece_pos_brick, dim3(topo.nb), dim3(NT), 0, s, parent, idx, topo, coord, pos);
     return hipGetLastError();
 }
 
 hipError_t launch_piece_pos_ell(int n, const int *parent, const int *idx, const int4 *fpos, int4 *pos, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_piece_pos_ell, dim3(gblocks(n)), dim3(256), 0, s, n, parent, idx, fpos, pos);
+    SPFD_LAUNCH(k_piece_pos_ell, dim3(gblocks(n)), dim3(256), 0, s, n, parent, idx, fpos, pos);
     return hipGetLastError();
 }
 
 hipError_t launch_members(const int *agg, long long n, int nc, const int *mptr, int *cursor, int *mem, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_members_fill, dim3(gblocks(n)), dim3(256), 0, s, agg, n, mptr, cursor, mem);
-    if (nc > 0) hipLaunchKernelGGL(k_members_sort, dim3(gblocks(nc)), dim3(256), 0, s, nc, mptr, mem);
+    SPFD_LAUNCH(k_members_fill, dim3(gblocks(n)), dim3(256), 0, s, agg, n, mptr, cursor, mem);
+    if (nc > 0) SPFD_LAUNCH(k_members_sort, dim3(gblocks(nc)), dim3(256), 0, s, nc, mptr, mem);
     return hipGetLastError();
 }
 
@@ -359,9 +359,9 @@ hipError_t launch_galerkin_ell(const FineLevelArgs &fa, const int *agg, int nc, 
     f.col = fa.col;
     f.val = fa.val;
     if (nc <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_galerkin_rows, dim3(gblocks(nc, 128)), dim3(128), 0, s, f, agg, nc, mptr, mem, pass, len, K,
+    SPFD_LAUNCH(k_galerkin_rows, dim3(gblocks(nc, 128)), dim3(128), 0, s, f, agg, nc, mptr, mem, pass, len, K,
                        col, val64, val32, overflow);
-    if (pass == 0) hipLaunchKernelGGL(k_max_int, dim3(1), dim3(256), 0, s, len, nc, maxlen);
+    if (pass == 0) SPFD_LAUNCH(k_max_int, dim3(1), dim3(256), 0, s, len, nc, maxlen);
     return hipGetLastError();
 }
 
@@ -504,7 +504,7 @@ hipError_t launch_ell_cheb_first(int n, int K, const int *col, const T *val, con
                                  const Batch &bt, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ell_cheb_first<T>, dim3(gblocks(n), bt.n), dim3(256), 0, s, n, K, col, val, b, x, c0, sc,
+    SPFD_LAUNCH(k_ell_cheb_first<T>, dim3(gblocks(n), bt.n), dim3(256), 0, s, n, K, col, val, b, x, c0, sc,
                        bt.vs);
     return hipGetLastError();
 }
@@ -514,7 +514,7 @@ hipError_t launch_ell_cheb_step(int n, int K, const int *col, const T *val, cons
                                 const T *din, T *dout, T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ell_cheb_step<T>, dim3(gblocks(n), bt.n), dim3(256), 0, s, n, K, col, val, b, xin, xout, din,
+    SPFD_LAUNCH(k_ell_cheb_step<T>, dim3(gblocks(n), bt.n), dim3(256), 0, s, n, K, col, val, b, xin, xout, din,
                        dout, c1, c2, sc, bt.vs);
     return hipGetLastError();
 }
@@ -525,9 +525,9 @@ hipError_t launch_restrict_members(const FineLevelT<T> &f, long long nrows, cons
                                    hipStream_t s)
 {
     if (nc <= 0 || nrows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_resid_rows<T>, dim3(gblocks(nrows, 256), bt.n), dim3(256), 0, s, f, nrows, b, x, r, sc,
+    SPFD_LAUNCH(k_resid_rows<T>, dim3(gblocks(nrows, 256), bt.n), dim3(256), 0, s, f, nrows, b, x, r, sc,
                        bt.vs);
-    hipLaunchKernelGGL(k_sum_members<T>, dim3(gblocks(nc, 64), bt.n), dim3(64), 0, s, nc, mptr, mem, r, bc, sc, bt.vs,
+    SPFD_LAUNCH(k_sum_members<T>, dim3(gblocks(nc, 64), bt.n), dim3(64), 0, s, nc, mptr, mem, r, bc, sc, bt.vs,
                        bt.vsc);
     return hipGetLastError();
 }
@@ -537,7 +537,7 @@ hipError_t launch_prolong_agg(long long n, const int *agg, T *x, const T *xc, T 
                               const Batch &bt, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_prolong_agg<T>, dim3(gblocks(n), bt.n), dim3(256), 0, s, n, agg, x, xc, scale, sc, bt.vs,
+    SPFD_LAUNCH(k_prolong_agg<T>, dim3(gblocks(n), bt.n), dim3(256), 0, s, n, agg, x, xc, scale, sc, bt.vs,
                        bt.vsc);
     return hipGetLastError();
 }
@@ -597,7 +597,7 @@ __global__ void k_coarse_enum_ell(int n, int K, const int *__restrict__ col, con
 hipError_t launch_coarse_enum_ell(int n, int K, const int *col, const double *val, int *dof_of_row, int *row_of_dof,
                                   int *ndof, int maxdof, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_coarse_enum_ell, dim3(1), dim3(1024), 0, s, n, K, col, val, dof_of_row, row_of_dof, ndof,
+    SPFD_LAUNCH(k_coarse_enum_ell, dim3(1), dim3(1024), 0, s, n, K, col, val, dof_of_row, row_of_dof, ndof,
                        maxdof);
     return hipGetLastError();
 }
@@ -635,9 +635,9 @@ hipError_t launch_coarse_dense_ell(int nrow, int K, const int *col, const double
                                    const int *row_of_dof, int n, double *A, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coarse_dense_ell, dim3(gblocks((long long)n * n)), dim3(256), 0, s, nrow, K, col, val,
+    SPFD_LAUNCH(k_coarse_dense_ell, dim3(gblocks((long long)n * n)), dim3(256), 0, s, nrow, K, col, val,
                        dof_of_row, row_of_dof, n, A);
-    hipLaunchKernelGGL(k_coarse_fill_ell, dim3(gblocks(n)), dim3(256), 0, s, nrow, K, col, val, dof_of_row,
+    SPFD_LAUNCH(k_coarse_fill_ell, dim3(gblocks(n)), dim3(256), 0, s, nrow, K, col, val, dof_of_row,
                        row_of_dof, n, A);
     return hipGetLastError();
 }

@@ -112,11 +112,11 @@ hipError_t launch_quantiles(const uint8_t *labels, const double *table, const do
     const size_t lds = (size_t)ngroups * SEL_BINS * sizeof(unsigned int);
     const int use_lds = lds <= 64 * 1024;
     for (int shift = 56; shift >= 0; shift -= 8) {
-        hipLaunchKernelGGL(k_sel_hist, dim3((unsigned)blocks), dim3(256), use_lds ? lds : 0, s, labels, table, sig_vox,
+        SPFD_LAUNCH(k_sel_hist, dim3((unsigned)blocks), dim3(256), use_lds ? lds : 0, s, labels, table, sig_vox,
                            nvox, emag, ngroups, shift, st, hist, use_lds);
-        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, s, ngroups, shift, q, st, hist);
+        SPFD_LAUNCH(k_sel_pick, dim3(1), dim3(256), 0, s, ngroups, shift, q, st, hist);
     }
-    hipLaunchKernelGGL(k_sel_out, dim3(1), dim3(256), 0, s, ngroups, st, out);
+    SPFD_LAUNCH(k_sel_out, dim3(1), dim3(256), 0, s, ngroups, st, out);
     return hipGetLastError();
 }
 
