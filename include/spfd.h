@@ -58,14 +58,14 @@ typedef enum {
 } spfd_status;
 
 enum { SPFD_FP64 = 0, SPFD_MIXED = 1 };          /* precision of the multigrid cycle */
-enum { SPFD_CYCLE_V = 0, SPFD_CYCLE_K = 1 };
+enum { SPFD_CYCLE_V = 0 };
 
 /* Multigrid preconditioner (the paper uses an algebraic multigrid
  * preconditioner inside a Krylov solver, Sec. III; its configuration is not
  * given).  Zero-initialised options select the defaults. */
 typedef struct {
     int precision;        /* SPFD_FP64 (default) or SPFD_MIXED: FP32 cycle, FP64 outer CG, dots and coarsest solve */
-    int cycle;            /* SPFD_CYCLE_V (default) or SPFD_CYCLE_K */
+    int cycle;            /* SPFD_CYCLE_V (the only cycle; any other value is rejected) */
     int smooth_degree;    /* Chebyshev degree per pre/post smoothing, default 2, max 4 */
     int coarsest_max;     /* coarsen until the coarsest level has <= this many unknowns, default and max 1024 */
     double cheby_ratio;   /* smoothing interval [2/ratio, 2] of D^-1 A, default 8 */

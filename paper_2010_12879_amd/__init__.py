@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libspfd.so")
 
 FP64, MIXED = 0, 1
-CYCLE_V, CYCLE_K = 0, 1
+CYCLE_V = 0
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "BAD_STATE", 3: "OUT_OF_MEMORY", 4: "HIP_ERROR", 5: "NOT_CONVERGED",
           6: "BREAKDOWN"}
 
@@ -270,7 +270,7 @@ class Solver:
     """
 
     def __init__(self, labels, sigma, h, precision="fp64", device=None, smooth_degree=2, coarsest_max=1024,
-                 cheby_ratio=8.0, coarse_scale=1.8, cycle="v", split_level=2, split=True, stream=None):
+                 cheby_ratio=8.0, coarse_scale=1.8, split_level=2, split=True, stream=None):
         import torch
         self.device = labels.device if device is None else torch.device(device)
         self.nz, self.ny, self.nx = labels.shape
@@ -284,7 +284,7 @@ class Solver:
                 spfd_set_sigma_voxel(self.handle, sigma)
             else:
                 spfd_set_sigma_table(self.handle, list(sigma))
-            self.opts = AmgOptions(MIXED if precision == "mixed" else FP64, CYCLE_K if cycle == "k" else CYCLE_V,
+            self.opts = AmgOptions(MIXED if precision == "mixed" else FP64, CYCLE_V,
                                    smooth_degree, coarsest_max, cheby_ratio, coarse_scale, split_level,
                                    0 if split else 1)
             spfd_build(self.handle, self.opts)

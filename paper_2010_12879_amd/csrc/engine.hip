@@ -636,7 +636,6 @@ void finish(Ctx *c, int n, int mode, Scal *sc, int max_iter, int nb = 1)
 void set_defaults(spfd_amg_options &o)
 {
     if (o.precision != SPFD_MIXED) o.precision = SPFD_FP64;
-    if (o.cycle != SPFD_CYCLE_K) o.cycle = SPFD_CYCLE_V;
     if (o.smooth_degree <= 0) o.smooth_degree = 2;
     if (o.smooth_degree > 4) o.smooth_degree = 4;
     if (o.coarsest_max <= 0) o.coarsest_max = 1024;
@@ -1495,6 +1494,7 @@ spfd_status spfd_build(spfd_handle h, const spfd_amg_options *opt)
     if (h->state < 2) return fail(h, SPFD_BAD_STATE, "set geometry and conductivities first");
     spfd_amg_options o{};
     if (opt) o = *opt;
+    if (o.cycle != SPFD_CYCLE_V) return fail(h, SPFD_INVALID_ARG, "unknown cycle (only SPFD_CYCLE_V)");
     set_defaults(o);
     h->opt = o;
     try {

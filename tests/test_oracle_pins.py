@@ -363,3 +363,20 @@ def test_percentile_matches_inverted_cdf():
     assert p == np.percentile(e[lab > 0], 99, method="inverted_cdf")
     for t in range(1, 4):
         assert per[t] == np.percentile(e[lab == t], 99, method="inverted_cdf")
+
+
+def test_percentile_ties_and_extremes():
+    # ties: values 1,1,2,2,2,3 -> rank ceil(0.5*6) = 3 -> 2; q = 1 -> maximum; q tiny -> minimum
+    e = np.array([[[2.0, 1.0, 2.0, 3.0, 1.0, 2.0]]])
+    lab = np.ones_like(e, dtype=np.uint8)
+    assert oracle.percentile_nearest_rank(e, lab, 0.5)[0] == 2.0
+    assert oracle.percentile_nearest_rank(e, lab, 1.0)[0] == 3.0
+    assert oracle.percentile_nearest_rank(e, lab, 1e-9)[0] == 1.0
+    # brute force on random data: the result r satisfies #(v <= r) >= k and #(v < r) < k, k = ceil(q n)
+    rng = np.random.default_rng(11)
+    v = np.round(rng.random(997) * 50) / 7.0
+    lab = np.ones((1, 1, v.size), np.uint8)
+    for q in (0.01, 0.37, 0.99, 1.0):
+        r = oracle.percentile_nearest_rank(v.reshape(1, 1, -1), lab, q)[0]
+        k = int(np.ceil(q * v.size))
+        assert np.sum(v <= r) >= k and np.sum(v < r) < k
