@@ -82,7 +82,12 @@ typedef struct {
     int use_x0;           /* nonzero: psi holds the start iterate on entry */
     int eager;            /* nonzero: launch every kernel from the host instead of replaying the
                              captured HIP graph of a CG iteration (same kernels, same results) */
+    int method;           /* SPFD_CG (default): flexible preconditioned CG; SPFD_FGMRES: flexible GMRES
+                             (the paper's Krylov method, Sec. III), one right side per handle only */
+    int restart;          /* FGMRES basis vectors per cycle, 1..32, default 30 */
 } spfd_solve_options;
+
+enum { SPFD_CG = 0, SPFD_FGMRES = 1 };
 
 typedef struct {
     int iterations;

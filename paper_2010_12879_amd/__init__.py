@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libspfd.so")
 
 FP64, MIXED = 0, 1
 CYCLE_V = 0
+CG, FGMRES = 0, 1
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "BAD_STATE", 3: "OUT_OF_MEMORY", 4: "HIP_ERROR", 5: "NOT_CONVERGED",
           6: "BREAKDOWN"}
 
@@ -39,7 +40,7 @@ class AmgOptions(ctypes.Structure):
 
 class SolveOptions(ctypes.Structure):
     _fields_ = [("rel_tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("use_x0", ctypes.c_int),
-                ("eager", ctypes.c_int)]
+                ("eager", ctypes.c_int), ("method", ctypes.c_int), ("restart", ctypes.c_int)]
 
 
 class RhsInfo(ctypes.Structure):
@@ -336,8 +337,9 @@ class Solver:
         for r in range(a.shape[0]):
             spfd_set_source(self.handle, r, a[r].contiguous())
 
-    def solve(self, a=None, tol=1e-8, max_iter=500, x0=None, check=True, eager=False):
-        """Psi (nrhs or none, Nz, Ny, Nx) and the per-source info dicts (eager: no graph replay)."""
+    def solve(self, a=None, tol=1e-8, max_iter=500, x0=None, check=True, eager=False, method="cg", restart=30):
+        """Psi (nrhs or none, Nz, Ny, Nx) and the per-source info dicts (eager: no graph replay;
+        method "cg" or "fgmres" with `restart` basis vectors per cycle)."""
         import torch
         squeeze = a is not None and a.dim() == 4
         if a is not None:
@@ -346,8 +348,9 @@ class Solver:
             psi = x0.reshape((self.nrhs,) + self.node_shape).clone().contiguous()
         else:
             psi = torch.empty((self.nrhs,) + self.node_shape, dtype=torch.float64, device=self.device)
-        st, info = spfd_solve(self.handle, SolveOptions(tol, max_iter, 1 if x0 is not None else 0, 1 if eager else 0),
-                              psi, self.nrhs)
+        opts = SolveOptions(tol, max_iter, 1 if x0 is not None else 0, 1 if eager else 0,
+                            FGMRES if method == "fgmres" else CG, restart)
+        st, info = spfd_solve(self.handle, opts, psi, self.nrhs)
         if check and st != 0:
             raise SPFDError(st, spfd_last_error(self.handle))
         return (psi[0] if squeeze else psi), (info[0] if squeeze else info)

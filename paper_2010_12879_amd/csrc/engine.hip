@@ -111,6 +111,12 @@ struct Ctx {
     double *d_adj_labpart = nullptr;
     double *d_adj_labout = nullptr;
     Scal *d_adj_scal = nullptr;
+    // flexible GMRES: basis V [(m+1)][n0], preconditioned vectors Z [m][n0], least-squares state, partials
+    double *d_fgV = nullptr;
+    void *d_fgZ = nullptr;
+    FGState *d_fgst = nullptr;
+    double *d_fgpart = nullptr;
+    int fg_m = 0;
     // quantile selection
     uint8_t *d_sel_work = nullptr;
     double *d_sel_out = nullptr;
@@ -162,6 +168,18 @@ struct HipFail {
     } while (0)
 
 void drop_graphs(Ctx *c);
+
+// method / restart of the solve options (nrhs: right sides solved together)
+const char *check_method(spfd_solve_options &so, int nrhs)
+{
+    if (so.method != SPFD_CG && so.method != SPFD_FGMRES) return "unknown method (SPFD_CG or SPFD_FGMRES)";
+    if (so.method == SPFD_FGMRES) {
+        if (so.restart == 0) so.restart = 30;
+        if (so.restart < 1 || so.restart > FG_MAXM) return "restart must be in 1..32";
+        if (nrhs != 1) return "FGMRES solves one right side per handle";
+    }
+    return nullptr;
+}
 
 }  // namespace
 
@@ -668,6 +686,11 @@ void alloc_cycle_buffers(Ctx *c, int nb)
 {
     drop_graphs(c);
     free_all(c, c->rhs_allocs);
+    c->d_fgV = nullptr;
+    c->d_fgZ = nullptr;
+    c->d_fgst = nullptr;
+    c->d_fgpart = nullptr;
+    c->fg_m = 0;
     const bool mixed = c->opt.precision == SPFD_MIXED;
     const size_t w = mixed ? sizeof(float) : sizeof(double);
     for (size_t l = 0; l < c->lv.size(); ++l) {
@@ -1105,6 +1128,123 @@ void pcg_iterations(Ctx *c, Scal *sc, int nb, const spfd_solve_options &so)
     pcg_end(c, sc, nb);
 }
 
+void resid_b(Ctx *c, const double *b, long long bvs, Scal *sc, double *r, int mode, int nb);
+
+// Flexible GMRES (one right side): from x and its residual r in c->d_r, cycles
+// of up to m columns with the same multigrid cycle as the CG, each column
+// z_j = B v_j, w = A z_j, two classical Gram-Schmidt passes, Givens rotation;
+// x += Z y at the end of a cycle, restart from the true residual b - A x.
+template <typename T>
+void fgmres_iterations(Ctx *c, const double *b, long long bvs, Scal *sc, const spfd_solve_options &so)
+{
+    Level &L0 = c->lv[0];
+    const long long n0 = L0.nodes();
+    const int m = so.restart;
+    const bool mixed = sizeof(T) == sizeof(float);
+    if (c->fg_m < m) {
+        c->d_fgV = dalloc<double>(c, c->rhs_allocs, (size_t)(m + 1) * n0);
+        c->d_fgZ = dalloc<uint8_t>(c, c->rhs_allocs, (size_t)m * n0 * sizeof(T));
+        if (!c->d_fgst) c->d_fgst = (FGState *)dalloc<uint8_t>(c, c->rhs_allocs, sizeof(FGState));
+        if (!c->d_fgpart) c->d_fgpart = dalloc<double>(c, c->rhs_allocs, (size_t)FG_MAXM * FG_PARTS);
+        HIPCHK(hipMemsetAsync(c->d_fgV, 0, (size_t)(m + 1) * n0 * sizeof(double), c->stream));
+        HIPCHK(hipMemsetAsync(c->d_fgZ, 0, (size_t)m * n0 * sizeof(T), c->stream));
+        c->fg_m = m;
+    }
+    double *V = c->d_fgV;
+    T *Z = (T *)c->d_fgZ;
+    FGState *st = c->d_fgst;
+    double *part = c->d_fgpart;
+    double *w = c->d_q;
+    float *v32 = mixed ? c->d_r32 : nullptr;
+    const int ng = fg_parts(n0);
+    const OpArgs<double> op = level_op<double>(c, 0);
+    const Topo topo = L0.topo();
+    const Batch bt = level_batch(c, 0, 1);
+    const double nd = (double)L0.dofs;
+    Scal *hs = c->h_ring;
+    auto poll = [&]() {
+        HIPCHK(hipMemcpyAsync(hs, sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return hs->done != 0;
+    };
+    // ||r||^2 and the stop test of the start
+    {
+        TScope ts(c, SPFD_K_DOTS, nd * 8.0);
+        HIPCHK(launch_mdot(c->d_r, n0, c->d_r, n0, 1, part, sc, c->stream));
+    }
+    HIPCHK(launch_finish(part, ng, FIN_RESID0, sc, 0, c->stream, nullptr, nullptr, 0, 1, 0));
+    HIPCHK(launch_fg_start(st, sc, c->stream));
+    {
+        TScope ts(c, SPFD_K_UPDATE, nd * (16.0 + (mixed ? 4.0 : 0.0)));
+        HIPCHK(launch_fg_scale(c->d_r, V, v32, n0, st, sc, c->stream));
+    }
+    if (poll()) return;
+    int j = 0;
+    for (;;) {
+        T *zj = Z + (long long)j * n0;
+        if (mixed)
+            vcycle<T, float>(c, v32, zj, sc, 1);
+        else
+            vcycle<T, double>(c, V + (long long)j * n0, zj, sc, 1);
+        {
+            TScope ts(c, SPFD_K_SPMV, nd * (sizeof(T) + 8.0 + op_bytes<double>(c, 0)));
+            HIPCHK(launch_spmv<T>(op, topo, zj, w, sc, bt, c->stream));
+        }
+        const int nv = j + 1;
+        {
+            TScope ts(c, SPFD_K_DOTS, nd * 8.0 * (nv + 1));
+            HIPCHK(launch_mdot(V, n0, w, n0, nv, part, sc, c->stream));
+        }
+        HIPCHK(launch_msum(part, ng, nv, st->h1, sc, c->stream));
+        {
+            TScope ts(c, SPFD_K_DOTS, nd * 8.0 * (nv + 2));
+            HIPCHK(launch_mupdate(V, n0, w, n0, nv, st->h1, 0, part, sc, c->stream));
+        }
+        HIPCHK(launch_msum(part, ng, nv, st->h2, sc, c->stream));
+        {
+            TScope ts(c, SPFD_K_DOTS, nd * 8.0 * (nv + 2));
+            HIPCHK(launch_mupdate(V, n0, w, n0, nv, st->h2, 1, part, sc, c->stream));
+        }
+        HIPCHK(launch_msum(part, ng, 1, &st->hnext, sc, c->stream));
+        HIPCHK(launch_fg_column(st, sc, j, so.max_iter, c->stream));
+        {
+            TScope ts(c, SPFD_K_UPDATE, nd * (16.0 + (mixed ? 4.0 : 0.0)));
+            HIPCHK(launch_fg_scale(w, V + (long long)nv * n0, v32, n0, st, sc, c->stream));
+        }
+        const bool done = poll();
+        j = nv;
+        if (!done && j < m) continue;
+        // end of a cycle: x += Z y
+        HIPCHK(launch_fg_ysolve(st, j, c->stream));
+        {
+            TScope ts(c, SPFD_K_UPDATE, nd * (16.0 + j * (double)sizeof(T)));
+            HIPCHK(launch_fg_xupdate<T>(c->d_x, Z, n0, n0, j, st, c->stream));
+        }
+        if (done) return;
+        // restart from the true residual
+        resid_b(c, b, bvs, sc, c->d_r, 0, 1);
+        HIPCHK(launch_fg_start(st, sc, c->stream));
+        {
+            TScope ts(c, SPFD_K_UPDATE, nd * (16.0 + (mixed ? 4.0 : 0.0)));
+            HIPCHK(launch_fg_scale(c->d_r, V, v32, n0, st, sc, c->stream));
+        }
+        if (poll()) return;
+        j = 0;
+    }
+}
+
+void krylov_iterations(Ctx *c, const double *b, long long bvs, Scal *sc, int nb, const spfd_solve_options &so)
+{
+    if (so.method == SPFD_FGMRES) {
+        if (c->opt.precision == SPFD_MIXED)
+            fgmres_iterations<float>(c, b, bvs, sc, so);
+        else
+            fgmres_iterations<double>(c, b, bvs, sc, so);
+        return;
+    }
+    pcg_iterations(c, sc, nb, so);
+}
+
 // r = b - A x for the batch and ||r||^2 (mode 0: start of a warm-started solve,
 // mode 1: true residual kept in zq)
 void resid_b(Ctx *c, const double *b, long long bvs, Scal *sc, double *r, int mode, int nb)
@@ -1162,7 +1302,7 @@ spfd_status solve_batch(Ctx *c, const double *b, long long bvs, Scal *sc, Scal *
     }
     int *again = c->d_again;
     for (int pass = 0; pass < 3 && any; ++pass) {
-        pcg_iterations(c, sc, nb, so);
+        krylov_iterations(c, b, bvs, sc, nb, so);
         // true residual of every iterate (also of those that converged in an earlier pass)
         resid_b(c, b, bvs, sc, c->d_r, 1, nb);
         HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
@@ -1418,6 +1558,11 @@ spfd_status spfd_set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, 
         h->d_adj_scal = nullptr;
         h->d_sel_work = nullptr;
         h->d_sel_out = nullptr;
+        h->d_fgV = nullptr;
+        h->d_fgZ = nullptr;
+        h->d_fgst = nullptr;
+        h->d_fgpart = nullptr;
+        h->fg_m = 0;
         h->d_ints = dalloc<int>(h, h->geo_allocs, 64);
         h->lv.clear();
         h->g.nx = nx; h->g.ny = ny; h->g.nz = nz;
@@ -1575,6 +1720,7 @@ spfd_status spfd_solve(spfd_handle h, const spfd_solve_options *opt, double *psi
     if (opt) so = *opt;
     if (!(so.rel_tol > 0.0) || !isfinite(so.rel_tol)) return fail(h, SPFD_INVALID_ARG, "rel_tol must be positive");
     if (so.max_iter <= 0) return fail(h, SPFD_INVALID_ARG, "max_iter must be positive");
+    if (const char *e = check_method(so, h->nrhs)) return fail(h, SPFD_INVALID_ARG, e);
     try {
         HIPCHK(hipSetDevice(h->device));
         enter(h);
@@ -1627,6 +1773,7 @@ spfd_status spfd_adjoint(spfd_handle h, double omega, const double *a, const dou
     so.use_x0 = 0;
     if (!(so.rel_tol > 0.0) || !isfinite(so.rel_tol)) return fail(h, SPFD_INVALID_ARG, "rel_tol must be positive");
     if (so.max_iter <= 0) return fail(h, SPFD_INVALID_ARG, "max_iter must be positive");
+    if (const char *e = check_method(so, 1)) return fail(h, SPFD_INVALID_ARG, e);
     try {
         HIPCHK(hipSetDevice(h->device));
         enter(h);
@@ -1692,6 +1839,7 @@ spfd_status spfd_solve_many(spfd_handle *hs, int n, const spfd_solve_options *op
     so.use_x0 = 0;
     if (!(so.rel_tol > 0.0) || !isfinite(so.rel_tol)) return fail(hs[0], SPFD_INVALID_ARG, "rel_tol must be positive");
     if (so.max_iter <= 0) return fail(hs[0], SPFD_INVALID_ARG, "max_iter must be positive");
+    if (so.method != SPFD_CG) return fail(hs[0], SPFD_INVALID_ARG, "the lockstep solve uses CG (method SPFD_CG)");
     std::vector<Ctx *> cs(hs, hs + n);
     try {
         HIPCHK(hipSetDevice(hs[0]->device));

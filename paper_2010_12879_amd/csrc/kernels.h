@@ -122,6 +122,37 @@ hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const
                          Scal *sc, const Batch &bt, float *r32, hipStream_t s);
 // fused CG step: p = z + beta p (p = z when first), x += alpha p_old (deferred), q = A p, p.q partials;
 // pin and pout are different buffers (neighbours read p_old)
+// ---------------------------------------------------------------- flexible GMRES
+constexpr int FG_MAXM = 32;     // largest restart length (basis vectors per cycle)
+constexpr int FG_PARTS = 1024;  // partial sums per dot product
+// least-squares state of one cycle (device memory): H column-major with leading dimension FG_MAXM + 1
+struct FGState {
+    double H[FG_MAXM * (FG_MAXM + 1)];
+    double cs[FG_MAXM], sn[FG_MAXM], g[FG_MAXM + 1], y[FG_MAXM];
+    double h1[FG_MAXM], h2[FG_MAXM];
+    double hnext;   // ||w||^2 after the second Gram-Schmidt pass
+    double beta;    // norm of the cycle's start residual
+    double scale;   // 1 / norm of the vector to be stored next
+};
+int fg_parts(long long n);
+hipError_t launch_mdot(const double *V, long long ldv, const double *w, long long n, int nv, double *part,
+                       const Scal *sc, hipStream_t s);
+hipError_t launch_mupdate(const double *V, long long ldv, double *w, long long n, int nv, const double *h, int mode,
+                          double *part, const Scal *sc, hipStream_t s);
+hipError_t launch_msum(const double *part, int ng, int nv, double *out, const Scal *sc, hipStream_t s);
+hipError_t launch_fg_start(FGState *st, const Scal *sc, hipStream_t s);
+hipError_t launch_fg_column(FGState *st, Scal *sc, int j, int max_iter, hipStream_t s);
+hipError_t launch_fg_ysolve(FGState *st, int k, hipStream_t s);
+hipError_t launch_fg_scale(const double *src, double *v, float *v32, long long n, const FGState *st, const Scal *sc,
+                           hipStream_t s);
+template <typename TZ>
+hipError_t launch_fg_xupdate(double *x, const TZ *Z, long long ldz, long long n, int k, const FGState *st,
+                             hipStream_t s);
+
+// w = A z on the finest level (FP64 operator)
+template <typename TZ>
+hipError_t launch_spmv(const OpArgs<double> &op, Topo topo, const TZ *z, double *w, const Scal *sc, const Batch &bt,
+                       hipStream_t s);
 // number of partial sums launch_cg_step writes per right side
 int cg_step_parts(int nb);
 template <typename TZ>

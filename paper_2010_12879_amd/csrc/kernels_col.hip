@@ -586,6 +586,37 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
     }
 }
 
+// ---------------------------------------------------------------- plain operator application
+// w = A z (FP64 operator, z in the cycle's precision): the Krylov vector of
+// the flexible GMRES outer solver
+template <typename TZ, int ZPL, bool LABEL>
+__global__ __launch_bounds__(CTHREADS) void k_col_spmv(OpArgs<double> op, Topo topo, const TZ *__restrict__ zv,
+                                                       double *__restrict__ w, const Scal *sc, long long vs)
+{
+    double *lds = col_lds<double, ZPL, LABEL>();
+    const Seg<ZPL> s = make_seg<ZPL>(topo);
+    if (s.bk < 0) return;
+    const bool done = col_stopped(sc);
+    zv += blockIdx.y * vs;
+    w += blockIdx.y * vs;
+    SegOp<double, ZPL, LABEL> A;
+    if (LABEL || s.active) A.load(op, s, lds);
+    SegVals<TZ, ZPL> Z;
+    if (s.active) Z.load(zv, s);
+    A.stage(op, s);
+    if (done || !s.active) return;
+#pragma unroll
+    for (int z = 0; z < ZPL; ++z) {
+        double W[6], P[6];
+        TZ N[6];
+        A.weights(s, z, W);
+        Z.nbrs(z, N);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) P[k] = (double)N[k];
+        w[s.self + 64 * z] = stencil_apply((double)Z.c[z], P, W);
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 // segment lengths: 8 nodes per lane in FP32 (one wave per brick), 4 in FP64
 // and in the CG step (two waves per brick), which hold twice the registers per node
@@ -691,6 +722,23 @@ hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, cons
                            part, sc, first, parity, bt.vs, bt.ps);
     return hipGetLastError();
 }
+
+template <typename TZ>
+hipError_t launch_spmv(const OpArgs<double> &op, Topo topo, const TZ *z, double *w, const Scal *sc, const Batch &bt,
+                       hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    const dim3 g = col_grid<ZPL_CG>(topo.nb, bt.n);
+    if (op.w)
+        SPFD_LAUNCH((k_col_spmv<TZ, ZPL_CG, false>), g, dim3(CTHREADS), 0, s, op, topo, z, w, sc, bt.vs);
+    else
+        SPFD_LAUNCH((k_col_spmv<TZ, ZPL_CG, true>), g, dim3(CTHREADS), 0, s, op, topo, z, w, sc, bt.vs);
+    return hipGetLastError();
+}
+template hipError_t launch_spmv<double>(const OpArgs<double> &, Topo, const double *, double *, const Scal *,
+                                        const Batch &, hipStream_t);
+template hipError_t launch_spmv<float>(const OpArgs<double> &, Topo, const float *, double *, const Scal *,
+                                       const Batch &, hipStream_t);
 
 #define SPFD_INST_COL(T, TB)                                                                                          \
     template hipError_t launch_cheb_first<T, TB>(const OpArgs<T> &, Topo, const TB *, T *, T, const Scal *,       \

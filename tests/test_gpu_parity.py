@@ -214,3 +214,39 @@ def test_graph_replay_matches_eager(prec):
     for pg, ig in outs:
         assert ig == ie, (ig, ie)
         assert torch.equal(pg, pe)
+
+
+@pytest.mark.parametrize("prec,restart", [("fp64", 30), ("mixed", 30), ("mixed", 4)])
+def test_fgmres_against_oracle(prec, restart):
+    """The paper's Krylov method (flexible GMRES, Sec. III) with the same multigrid cycle reaches the
+    same mean-zero solution as the oracle; a short restart exercises the restarts from b - A x."""
+    print(f"case fgmres {prec} m={restart}", flush=True)
+    w = W.config(1)
+    s = P.Solver(_dev(w.labels), w.sigma_table, w.h, precision=prec)
+    a = _dev(w.a)
+    psi, info = s.solve(a, tol=1e-12, max_iter=400, method="fgmres", restart=restart)
+    pcg, icg = s.solve(a, tol=1e-12, max_iter=400)
+    s.close()
+    psi_ref, _ = oracle.solve(w.sigma_voxel(), w.h, w.a, tol=1e-12)
+    assert info["status"] == "OK" and info["rel_residual"] <= 1e-12
+    err = _rel(psi.cpu().numpy(), psi_ref)
+    print(f"fgmres {prec} m={restart}: it={info['iterations']} (cg {icg['iterations']}) err={err:.2e}", flush=True)
+    assert err <= BAR[prec]
+
+
+def test_fgmres_option_errors():
+    print("case fgmres errors", flush=True)
+    w = W.config(0)
+    s = P.Solver(_dev(w.labels), w.sigma_table, w.h)
+    a = _dev(w.a)
+    with pytest.raises(P.SPFDError) as e:
+        s.solve(a, method="fgmres", restart=33)
+    assert e.value.status == 1
+    s2 = P.Solver(_dev(w.labels), w.sigma_table, w.h)
+    P.spfd_set_num_rhs(s2.handle, 2)
+    s2.nrhs = 2
+    with pytest.raises(P.SPFDError) as e:
+        s2.solve(torch.stack([a, a]), method="fgmres")
+    assert e.value.status == 1
+    s.close()
+    s2.close()
