@@ -135,6 +135,19 @@ spfd_status spfd_solve(spfd_handle h, const spfd_solve_options *opt, double *psi
 spfd_status spfd_efield(spfd_handle h, double omega, const double *a, const double *psi,
                         double *u_edges, double *emag);
 
+/* Edge potentials from facet fluxes, Eq. (2) b = C a, solved in a tree-cotree
+ * gauge (technical summary of Sec. II.A, step 3).  flux [3][Nz][Ny][Nx]
+ * (device): magnetic flux through each voxel facet, normal d, anchored at the
+ * facet's lowest corner node (entries beyond the grid are ignored); it must be
+ * discretely divergence-free (zero net flux out of every voxel), else the
+ * z-facets above the bottom node plane are not reproduced.  a [3][Nz][Ny][Nx]
+ * (device, written): edge potentials in the layout of spfd_set_source, zero on
+ * the tree (every z-edge, the y-edges of the plane k = 0, the x-edges of the
+ * line j = k = 0) and on entries beyond the grid.  Any two solutions differ by
+ * a discrete gradient, which leaves the field of Eq. (1) unchanged.  Needs the
+ * geometry only. */
+spfd_status spfd_edge_potentials(spfd_handle h, const double *flux, double *a);
+
 /* Nearest-rank q-quantile of the voxel field |E| (step 6 of the paper's
  * technical summary, Sec. II.A: the 99th percentile of the voxel-averaged
  * field, Sec. III.F, q = 0.99): among the n conducting voxels (sigma > 0) the

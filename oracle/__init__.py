@@ -208,3 +208,27 @@ def percentile_nearest_rank(emag, labels, q=0.99, n_labels=None):
     n_labels = int(lab.max()) + 1 if n_labels is None else n_labels
     per = np.array([nearest_rank(e[lab == t]) if t > 0 else float("nan") for t in range(n_labels)])
     return nearest_rank(e[body]), per
+
+
+def tree_cotree_potentials(flux):
+    """Edge potentials a with C a = flux (Eq. (2)) in a tree-cotree gauge (technical summary
+    of Sec. II.A, step 3).  flux is a (3, Nz, Ny, Nx) array of facet fluxes (normal d, anchored at
+    the facet's lowest corner node, as in tests/discrete.py) and must be discretely divergence-free.
+
+    Tree (a = 0 there): every z-edge, the y-edges of the node plane k = 0 and the x-edges of the node
+    line j = k = 0.  Each cotree edge closes exactly one facet whose other edges are known:
+      z-facets of the plane k = 0:  a_x(i, j+1, 0) = a_x(i, j, 0) - flux_z(i, j, 0),
+      y-facets:                     a_x(i, j, k+1) = a_x(i, j, k) + flux_y(i, j, k),
+      x-facets:                     a_y(i, j, k+1) = a_y(i, j, k) - flux_x(i, j, k);
+    the z-facets above the bottom plane then hold because every cell's outgoing flux sums to zero.
+    The recurrences are evaluated in this order (sequential sums)."""
+    f = np.asarray(flux, dtype=np.float64)
+    _, Nz, Ny, Nx = f.shape
+    nx, ny, nz = Nx - 1, Ny - 1, Nz - 1
+    a = np.zeros_like(f)
+    for j in range(ny):
+        a[0, 0, j + 1, :nx] = a[0, 0, j, :nx] - f[2, 0, j, :nx]
+    for k in range(nz):
+        a[0, k + 1, :, :nx] = a[0, k, :, :nx] + f[1, k, :, :nx]
+        a[1, k + 1, :ny, :] = a[1, k, :ny, :] - f[0, k, :ny, :]
+    return a

@@ -53,7 +53,7 @@ class RhsInfo(ctypes.Structure):
 _lib = None
 EXPORTS = ["spfd_create", "spfd_destroy", "spfd_last_error", "spfd_set_geometry", "spfd_set_sigma_table",
            "spfd_set_sigma_voxel", "spfd_build", "spfd_get_info", "spfd_set_num_rhs", "spfd_set_source",
-           "spfd_solve", "spfd_solve_many", "spfd_efield", "spfd_percentile", "spfd_adjoint", "spfd_timing", "spfd_timing_get"]
+           "spfd_solve", "spfd_solve_many", "spfd_efield", "spfd_edge_potentials", "spfd_percentile", "spfd_adjoint", "spfd_timing", "spfd_timing_get"]
 # kernel classes of spfd_timing / spfd_timing_get (order of the enum in spfd.h)
 KERNEL_CLASSES = ["spmv", "update", "dots", "pupdate", "smooth0", "smooth0_first", "restrict0", "prolong0", "coarse",
                   "finish", "rhs", "efield", "gauge", "resid"]
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
     lib.spfd_efield.argtypes = [H, D, P, P, P, P]
     lib.spfd_adjoint.argtypes = [H, D, P, P, P, ctypes.POINTER(SolveOptions), P, P, ctypes.POINTER(RhsInfo)]
     lib.spfd_percentile.argtypes = [H, P, D, ctypes.POINTER(D), P]
+    lib.spfd_edge_potentials.argtypes = [H, P, P]
     lib.spfd_solve_many.argtypes = [ctypes.POINTER(H), I, ctypes.POINTER(SolveOptions), ctypes.POINTER(P),
                                     ctypes.POINTER(RhsInfo)]
     lib.spfd_timing.argtypes = [H, ctypes.c_uint]
@@ -237,6 +238,14 @@ def spfd_adjoint(h, omega, a, psi, grad_emag, opts: SolveOptions | None, grad_si
     return st, (list(table) if table is not None else None), info.as_dict()
 
 
+def spfd_edge_potentials(h, flux, a):
+    """a = edge potentials with C a = flux in the tree-cotree gauge (both (3, Nz, Ny, Nx) float64 CUDA)."""
+    import torch
+    _require_cuda(flux, torch.float64, None, "flux")
+    _require_cuda(a, torch.float64, None, "a")
+    return _check(h, load_library().spfd_edge_potentials(h, _ptr(flux), _ptr(a)))
+
+
 def spfd_percentile(h, emag, q=0.99, n_labels=0):
     """(whole-body quantile, per-label list or None) of the voxel |E| (nearest rank)."""
     import torch
@@ -362,6 +371,15 @@ class Solver:
         u = torch.empty((3,) + self.node_shape, dtype=torch.float64, device=self.device) if want_u else None
         spfd_efield(self.handle, omega, a.contiguous(), psi.contiguous(), u, emag)
         return (emag, u) if want_u else emag
+
+    def edge_potentials(self, flux):
+        """Edge potentials (3, Nz, Ny, Nx) from facet fluxes of the same shape (tree-cotree gauge)."""
+        import torch
+        if tuple(flux.shape) != (3,) + self.node_shape:
+            raise ValueError(f"flux must have shape (3,) + {self.node_shape}")
+        a = torch.empty_like(flux, dtype=torch.float64)
+        spfd_edge_potentials(self.handle, flux.to(torch.float64).contiguous(), a)
+        return a
 
     def percentile(self, emag, q=0.99):
         """(whole body, per-label list) nearest-rank q-quantile of |E| over conducting voxels."""

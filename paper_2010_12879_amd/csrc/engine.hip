@@ -1851,6 +1851,26 @@ spfd_status spfd_solve_many(spfd_handle *hs, int n, const spfd_solve_options *op
     API_GUARD(hs[0])
 }
 
+spfd_status spfd_edge_potentials(spfd_handle h, const double *flux, double *a)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (h->state < 1) return fail(h, SPFD_BAD_STATE, "set the geometry first");
+    if (!flux || !a) return fail(h, SPFD_INVALID_ARG, "flux and a are required");
+    if (flux == a) return fail(h, SPFD_INVALID_ARG, "flux and a must not alias");
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        enter(h);
+        const double nn = (double)h->g.Nx * h->g.Ny * h->g.Nz;
+        {
+            TScope ts(h, SPFD_K_RHS, nn * (16.0 + 24.0));
+            HIPCHK(launch_tree_cotree(flux, a, h->g, h->stream));
+        }
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return SPFD_OK;
+    }
+    API_GUARD(h)
+}
+
 spfd_status spfd_percentile(spfd_handle h, const double *emag, double q, double *out_body, double *out_labels)
 {
     if (!h) return SPFD_INVALID_ARG;

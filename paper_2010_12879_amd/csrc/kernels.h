@@ -122,6 +122,9 @@ hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const
                          Scal *sc, const Batch &bt, float *r32, hipStream_t s);
 // fused CG step: p = z + beta p (p = z when first), x += alpha p_old (deferred), q = A p, p.q partials;
 // pin and pout are different buffers (neighbours read p_old)
+// edge potentials a [3][Nz][Ny][Nx] from divergence-free facet fluxes (tree-cotree gauge)
+hipError_t launch_tree_cotree(const double *flux, double *a, const Grid &g, hipStream_t s);
+
 // ---------------------------------------------------------------- flexible GMRES
 constexpr int FG_MAXM = 32;     // largest restart length (basis vectors per cycle)
 constexpr int FG_PARTS = 1024;  // partial sums per dot product

@@ -380,3 +380,64 @@ def test_percentile_ties_and_extremes():
         r = oracle.percentile_nearest_rank(v.reshape(1, 1, -1), lab, q)[0]
         k = int(np.ceil(q * v.size))
         assert np.sum(v <= r) >= k and np.sum(v < r) < k
+
+
+# ---------------------------------------------------------------------------- tree-cotree gauge (Eq. (2))
+def test_tree_cotree_single_voxel_uniform_bz():
+    # one voxel in a uniform B_z: flux phi through both z-facets, none through the others
+    phi = 3.0e-6
+    f = np.zeros((3, 2, 2, 2))
+    f[2, 0, 0, 0] = f[2, 1, 0, 0] = phi
+    a = oracle.tree_cotree_potentials(f)
+    assert a[0, 0, 1, 0] == -phi and a[0, 1, 1, 0] == -phi          # cotree x-edges at j = 1
+    assert a[0, 0, 0, 0] == 0.0 and a[0, 1, 0, 0] == 0.0            # the line j = 0 (tree at k = 0)
+    assert np.all(a[2] == 0.0) and np.all(a[1, 0] == 0.0)           # tree: z-edges, y-edges at k = 0
+    assert np.array_equal(D.curl(a), f)
+
+
+def _random_divfree_flux(shape, seed):
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    a0 = rng.standard_normal((3, nz + 1, ny + 1, nx + 1))
+    a0[0, :, :, nx] = 0.0
+    a0[1, :, ny, :] = 0.0
+    a0[2, nz, :, :] = 0.0
+    return a0, D.curl(a0)
+
+
+def test_tree_cotree_reproduces_fluxes_and_differs_by_a_gradient():
+    a0, f = _random_divfree_flux((5, 6, 7), 21)
+    a = oracle.tree_cotree_potentials(f)
+    c = D.curl(a)
+    assert np.abs(c - f).max() <= 1e-12 * np.abs(f).max()
+    # tree edges are zero
+    assert np.all(a[2] == 0.0) and np.all(a[1, 0] == 0.0) and np.all(a[0, 0, 0] == 0.0)
+    # a - a0 = G phi: integrate the difference along the tree from node (0,0,0), then check every edge
+    d = a - a0
+    Nz, Ny, Nx = d.shape[1:]
+    phi = np.zeros((Nz, Ny, Nx))
+    for i in range(1, Nx):
+        phi[0, 0, i] = phi[0, 0, i - 1] + d[0, 0, 0, i - 1]
+    for j in range(1, Ny):
+        phi[0, j, :] = phi[0, j - 1, :] + d[1, 0, j - 1, :]
+    for k in range(1, Nz):
+        phi[k] = phi[k - 1] + d[2, k - 1]
+    g = np.zeros_like(d)
+    g[0, :, :, :-1] = phi[:, :, 1:] - phi[:, :, :-1]
+    g[1, :, :-1, :] = phi[:, 1:, :] - phi[:, :-1, :]
+    g[2, :-1, :, :] = phi[1:] - phi[:-1]
+    assert np.abs(g - d).max() <= 1e-11 * np.abs(d).max()
+
+
+def test_tree_cotree_gauge_leaves_the_field_unchanged():
+    # |E| from the tree-cotree potentials equals |E| from the analytic edge integrals (the
+    # difference is a discrete gradient, absorbed by Psi)
+    w = W.random_ellipsoid_phantom(14, 12, 16, seed=7, n_ell=6, semi_range=(2.0, 5.0))
+    sig = w.sigma_voxel()
+    a_tc = oracle.tree_cotree_potentials(D.curl(w.a))
+    p0, _ = oracle.solve(sig, w.h, w.a, tol=1e-13)
+    p1, _ = oracle.solve(sig, w.h, a_tc, tol=1e-13)
+    _, e0 = oracle.efield(sig, w.h, w.a, p0, w.omega)
+    _, e1 = oracle.efield(sig, w.h, a_tc, p1, w.omega)
+    assert np.linalg.norm(e1 - e0) <= 1e-9 * np.linalg.norm(e0)
+    assert np.linalg.norm(p1 - p0) > 1e-3 * np.linalg.norm(p0)   # the potentials themselves do differ
