@@ -193,3 +193,9 @@ def test_multi_source_offsets():
     assert len(offs) == 64
     assert all(isinstance(v, int) for o in offs for v in o)
     assert max(abs(o[0]) for o in offs) <= 72 and max(abs(o[1]) for o in offs) <= 37
+
+
+def test_body_phantom_1mm_dof_count():
+    m = W.body_mask(W.BODY_RADIAL_SCALE_1MM, (1800, 300, 500), refine=2)
+    n = W.count_body_nodes(m)
+    assert abs(n - 69.8e6) <= 0.005 * 69.8e6, n

@@ -38,6 +38,9 @@ SEED_BASE = 12879
 # Radial scale of the body-shaped phantom, chosen once by bisection so that the
 # number of body nodes is 8.9 M +- 0.5 % (the 2 mm "Duke" DOF count, Sec. I).
 BODY_RADIAL_SCALE = 0.9755
+# The same body on a 1 mm grid (500x300x1800 voxels), scale bisected to 69.73 M body nodes:
+# the 1 mm count of the paper's model (69.8 M, Sec. III) within 0.5 %.
+BODY_RADIAL_SCALE_1MM = 0.9734375
 
 
 @dataclasses.dataclass
@@ -139,19 +142,22 @@ def rect_loop_edge_potentials(nx, ny, nz, h, centre, size, current=1.0) -> np.nd
     Y = _node_coords(ny, hy)
     Z = _node_coords(nz, hz)
     a = np.zeros((3, nz + 1, ny + 1, nx + 1))
-    dz = (Z - z0)[:, None, None]
-    # x-directed segments: at y = ys[0] current flows +x, at y = ys[1] flows -x
-    for yseg, sgn in ((ys[0], 1.0), (ys[1], -1.0)):
-        d = np.sqrt(dz * dz + ((Y - yseg) ** 2)[None, :, None])          # (nz+1, ny+1, 1)
-        u = X[None, None, :]
-        phi = _parallel_filament(u - xs[0], d) - _parallel_filament(u - xs[1], d)
-        a[0, :, :, :nx] += sgn * c * (phi[:, :, 1:] - phi[:, :, :-1])
-    # y-directed segments: at x = xs[1] current flows +y, at x = xs[0] flows -y
-    for xseg, sgn in ((xs[1], 1.0), (xs[0], -1.0)):
-        d = np.sqrt(dz * dz + ((X - xseg) ** 2)[None, None, :])          # (nz+1, 1, nx+1)
-        u = Y[None, :, None]
-        phi = _parallel_filament(u - ys[0], d) - _parallel_filament(u - ys[1], d)
-        a[1, :, :ny, :] += sgn * c * (phi[:, 1:, :] - phi[:, :-1, :])
+    # slabs of node planes keep the temporaries small on large grids (elementwise: same values)
+    for k0 in range(0, nz + 1, 64):
+        k1 = min(k0 + 64, nz + 1)
+        dz = (Z[k0:k1] - z0)[:, None, None]
+        # x-directed segments: at y = ys[0] current flows +x, at y = ys[1] flows -x
+        for yseg, sgn in ((ys[0], 1.0), (ys[1], -1.0)):
+            d = np.sqrt(dz * dz + ((Y - yseg) ** 2)[None, :, None])      # (planes, ny+1, 1)
+            u = X[None, None, :]
+            phi = _parallel_filament(u - xs[0], d) - _parallel_filament(u - xs[1], d)
+            a[0, k0:k1, :, :nx] += sgn * c * (phi[:, :, 1:] - phi[:, :, :-1])
+        # y-directed segments: at x = xs[1] current flows +y, at x = xs[0] flows -y
+        for xseg, sgn in ((xs[1], 1.0), (xs[0], -1.0)):
+            d = np.sqrt(dz * dz + ((X - xseg) ** 2)[None, None, :])      # (planes, 1, nx+1)
+            u = Y[None, :, None]
+            phi = _parallel_filament(u - ys[0], d) - _parallel_filament(u - ys[1], d)
+            a[1, k0:k1, :ny, :] += sgn * c * (phi[:, 1:, :] - phi[:, :-1, :])
     return a
 
 
@@ -269,8 +275,24 @@ def random_ellipsoid_phantom(nx=128, ny=96, nz=256, h=2e-3, seed=SEED_BASE + 1, 
 
 # ---- body-shaped phantom -------------------------------------------------
 
-def _body_shapes(s):
-    """Primitive shapes of the standing body (voxel units, z up); s = radial scale."""
+def _body_shapes(s, refine=1):
+    """Primitive shapes of the standing body (voxel units of 2 mm / refine, z up); s = radial scale."""
+    shapes, bones = _body_shapes_2mm(s)
+    if refine == 1:
+        return shapes, bones
+
+    def scaled(p):
+        q = {}
+        for k, v in p.items():
+            q[k] = tuple(refine * x for x in v) if isinstance(v, tuple) else refine * v
+        return q
+
+    shapes = [(k, scaled(p)) for k, p in shapes]
+    bones = [(k, scaled(p), r0, r1) for k, p, r0, r1 in bones]
+    return shapes, bones
+
+
+def _body_shapes_2mm(s):
     xc, yc = 125.0, 75.0
     shapes = [
         ("ellipsoid", dict(c=(xc, yc, 830.0), r=(40 * s, 50 * s, 55.0))),             # head
@@ -339,9 +361,9 @@ def _paint(mask, kind, p, rmin, rmax):
     mask[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] |= sel
 
 
-def body_mask(s=BODY_RADIAL_SCALE, shape=(900, 150, 250)):
+def body_mask(s=BODY_RADIAL_SCALE, shape=(900, 150, 250), refine=1):
     mask = np.zeros(shape, bool)
-    shapes, _ = _body_shapes(s)
+    shapes, _ = _body_shapes(s, refine)
     for kind, p in shapes:
         _paint(mask, kind, p, 0.0, 1.0)
     return mask
@@ -375,7 +397,7 @@ def _skin(mask):
     return mask & ~inner
 
 
-def body_phantom_labels(seed=SEED_BASE + 2, s=BODY_RADIAL_SCALE, n_sites=380, grid=(250, 150, 900)):
+def body_phantom_labels(seed=SEED_BASE + 2, s=BODY_RADIAL_SCALE, n_sites=380, grid=(250, 150, 900), refine=1):
     """Body-shaped phantom labels and the 40-class sigma table.
 
     Classes: 0 skin (body voxels with an air 6-neighbour), 1 bone (2-voxel
@@ -388,10 +410,10 @@ def body_phantom_labels(seed=SEED_BASE + 2, s=BODY_RADIAL_SCALE, n_sites=380, gr
     from scipy.spatial import cKDTree
     nx, ny, nz = grid
     rng = np.random.default_rng(seed)
-    mask = body_mask(s, (nz, ny, nx))
+    mask = body_mask(s, (nz, ny, nx), refine)
     skin = _skin(mask)
     bone = np.zeros_like(mask)
-    _, bones = _body_shapes(s)
+    _, bones = _body_shapes(s, refine)
     for kind, p, r0, r1 in bones:
         _paint(bone, kind, p, r0, r1)
     bone &= mask & ~skin
@@ -431,6 +453,20 @@ def body_phantom(seed=SEED_BASE + 2, loop_offset=(0.0, 0.0), with_source=True):
         a = body_loop_source(loop_offset)
     return Workload("body250x150x900", nx, ny, nz, (h, h, h), labels, table, a,
                     meta={"seed": seed, "loop_offset": loop_offset})
+
+
+def body_phantom_1mm(seed=SEED_BASE + 5, with_source=True):
+    """The body phantom on a 1 mm grid: 500x300x1800 voxels, ~69.7 M body nodes, 40 tissues
+    (shapes of the 2 mm phantom with coordinates doubled, radial scale BODY_RADIAL_SCALE_1MM, the
+    same class rules and 380 Voronoi sites), and the same 0.3 m x 0.2 m loop 40 mm below the feet."""
+    nx, ny, nz = 500, 300, 1800
+    h = 1e-3
+    labels, table = body_phantom_labels(seed, BODY_RADIAL_SCALE_1MM, 380, (nx, ny, nz), refine=2)
+    a = None
+    if with_source:
+        a = rect_loop_edge_potentials(nx, ny, nz, (h, h, h), (370.0 * h, 150.0 * h, -40.0 * h),
+                                      (300.0 * h, 200.0 * h))
+    return Workload("body500x300x1800", nx, ny, nz, (h, h, h), labels, table, a, meta={"seed": seed})
 
 
 def body_loop_source(offset=(0.0, 0.0), grid=(250, 150, 900), h=2e-3):
