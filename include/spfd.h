@@ -70,7 +70,7 @@ typedef struct {
     int coarsest_max;     /* coarsen until the coarsest level has <= this many unknowns, default and max 1024 */
     double cheby_ratio;   /* smoothing interval [2/ratio, 2] of D^-1 A, default 8 */
     double coarse_scale;  /* scaling of the coarse-grid correction (over-correction of the piecewise-constant
-                             aggregation), default 1.8; keep below 2 */
+                             aggregation), default 1.9; keep below 2 */
     int split_level;      /* aggregates of this level and coarser ones are split into their connected pieces
                              (coarse unknowns become unstructured), default 2 */
     int no_split;         /* nonzero: never split aggregates (structured 7-point levels only) */

@@ -280,7 +280,7 @@ class Solver:
     """
 
     def __init__(self, labels, sigma, h, precision="fp64", device=None, smooth_degree=2, coarsest_max=1024,
-                 cheby_ratio=8.0, coarse_scale=1.8, split_level=2, split=True, stream=None):
+                 cheby_ratio=8.0, coarse_scale=1.9, split_level=2, split=True, stream=None):
         import torch
         self.device = labels.device if device is None else torch.device(device)
         self.nz, self.ny, self.nx = labels.shape

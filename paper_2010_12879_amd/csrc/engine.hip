@@ -58,6 +58,8 @@ struct Level {
     int *d_mem = nullptr;
     int *d_agg = nullptr;           // this level's unknown -> row of the next (split) level, -1 if none
     unsigned long long *d_cmask = nullptr;  // node columns with unknowns, per brick (structured levels)
+    double *d_dinv64 = nullptr;             // inverse diagonal (0 where it vanishes), FP64 and FP32
+    float *d_dinv32 = nullptr;
     Topo topo() const { return Topo{nb, d_nbr, d_cmask}; }
     long long nodes() const { return ell ? (long long)nrow : (long long)nb * BS; }
 };
@@ -470,6 +472,13 @@ void cheb_first(Ctx *c, int l, const TB *b, T *x, const Scal *sc, int nb)
 
 // with_prolong: the step first adds coarse_scale * P x_c of the structured
 // level l+1 to xin (the prolongation fused into the first post-smoothing step)
+template <typename T>
+const T *dinv_of(const Level &L);
+template <>
+const double *dinv_of<double>(const Level &L) { return L.d_dinv64; }
+template <>
+const float *dinv_of<float>(const Level &L) { return L.d_dinv32; }
+
 // CG dot products formed by the last finest-level smoothing step
 struct CycleDots {
     const double *r = nullptr;
@@ -485,8 +494,10 @@ void cheb_step(Ctx *c, int l, const TB *b, const T *xin, T *xout, const T *din, 
     const Batch bt = level_batch(c, l, nb);
     if (L.ell) {
         TScope ts(c, SPFD_K_COARSE, nb * (double)L.nrow * (4.0 * sizeof(T) + L.K * (4.0 + sizeof(T))));
+        const bool pro = with_prolong && c->lv[l + 1].ell;
         HIPCHK(launch_ell_cheb_step<T>(L.nrow, L.K, L.d_col, ell_val<T>(L), (const T *)b, xin, xout, din, dout, c1, c2,
-                                       sc, bt, c->stream));
+                                       sc, bt, c->stream, pro ? L.d_agg : nullptr,
+                                       pro ? (const T *)c->lv[l + 1].x : nullptr, (T)c->opt.coarse_scale));
         return;
     }
     double per = sizeof(TB) + op_bytes<T>(c, l) + sizeof(T) * (2 + (din ? 1 : 0) + (dout ? 1 : 0));
@@ -502,11 +513,14 @@ void cheb_step(Ctx *c, int l, const TB *b, const T *xin, T *xout, const T *din, 
 }
 
 template <typename T, typename TB>
-void smooth_pre(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc, int nb)
+void smooth_pre(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc, int nb, bool first_done)
 {
+    // first_done: the restriction that produced b already stored the first step in cur
     const int m = c->opt.smooth_degree;
     T *d = (T *)c->lv[l].d;
-    cheb_first<T, TB>(c, l, b, cur, sc, nb);
+    // (folding the first step into the second on the finest level, x = c0 D^-1 b formed at every node
+    // read, was measured slower: it doubles the lateral loads)
+    if (!first_done) cheb_first<T, TB>(c, l, b, cur, sc, nb);
     for (int k = 1; k < m; ++k) {
         cheb_step<T, TB>(c, l, b, cur, other, k == 1 ? nullptr : d, k < m - 1 ? d : nullptr, (T)c->cheb_c1[k],
                          (T)c->cheb_c2[k], sc, nb);
@@ -537,11 +551,16 @@ template <>
 const float *stored_w<float>(const Level &L) { return L.d_w32; }
 
 template <typename T, typename TB>
-void restrict_level(Ctx *c, int l, const TB *b, const T *x, const Scal *sc, int nb)
+void restrict_level(Ctx *c, int l, const TB *b, const T *x, const Scal *sc, int nb, bool fuse_first)
 {
+    // fuse_first: also the first Chebyshev step of level l+1 into its x2 (where its smoothing starts)
     Level &L = c->lv[l];
     Level &C = c->lv[l + 1];
     const Batch bt = level_batch(c, l, nb);
+    T *xc = fuse_first ? (T *)C.x2 : nullptr;
+    const T *dc = fuse_first ? dinv_of<T>(C) : nullptr;
+    const T c0 = (T)c->cheb_c0;
+    const double fb = fuse_first ? nb * (double)C.dofs * 2.0 * sizeof(T) : 0.0;
     if (C.ell) {
         FineLevelT<T> f{};
         if (L.ell) {
@@ -554,16 +573,16 @@ void restrict_level(Ctx *c, int l, const TB *b, const T *x, const Scal *sc, int 
             f.stride = L.nodes();
             f.nbr = L.d_nbr;
         }
-        TScope ts(c, SPFD_K_COARSE, nb * ((double)L.dofs * 3.0 * sizeof(T) + (double)C.nrow * 8.0));
+        TScope ts(c, SPFD_K_COARSE, nb * ((double)L.dofs * 3.0 * sizeof(T) + (double)C.nrow * 8.0) + fb);
         // the fine level's Chebyshev direction is free between pre- and post-smoothing
         HIPCHK(launch_restrict_members<T>(f, L.nodes(), (const T *)b, x, (T *)L.d, C.nrow, C.d_mptr, C.d_mem,
-                                          (T *)C.b, sc, bt, c->stream));
+                                          (T *)C.b, sc, bt, c->stream, xc, dc, c0));
         return;
     }
     const double by = nb * ((double)L.dofs * (sizeof(TB) + op_bytes<T>(c, l) + sizeof(T)) + (double)C.dofs * sizeof(T));
-    TScope ts(c, l == 0 ? SPFD_K_RESTRICT0 : SPFD_K_COARSE, by);
+    TScope ts(c, l == 0 ? SPFD_K_RESTRICT0 : SPFD_K_COARSE, by + fb);
     HIPCHK(launch_resid_restrict<T, TB>(level_op<T>(c, l), L.topo(), b, x, (T *)C.b, L.d_parent_slot, L.d_coord, sc, bt,
-                                        c->stream));
+                                        c->stream, xc, dc, c0));
 }
 
 template <typename T>
@@ -613,12 +632,14 @@ bool vcycle(Ctx *c, const TR *r, T *z, const Scal *sc, int nb, const CycleDots *
         Level &L = c->lv[l];
         T *cur = (T *)L.x2;
         T *other = l == 0 ? z : (T *)L.x;
+        // the restriction stores the next level's first Chebyshev step unless that level is the coarsest
+        const bool fuse = l + 2 < nl;
         if (l == 0) {
-            smooth_pre<T, TR>(c, l, r, cur, other, sc, nb);
-            restrict_level<T, TR>(c, l, r, cur, sc, nb);
+            smooth_pre<T, TR>(c, l, r, cur, other, sc, nb, false);
+            restrict_level<T, TR>(c, l, r, cur, sc, nb, fuse);
         } else {
-            smooth_pre<T, T>(c, l, (const T *)L.b, cur, other, sc, nb);
-            restrict_level<T, T>(c, l, (const T *)L.b, cur, sc, nb);
+            smooth_pre<T, T>(c, l, (const T *)L.b, cur, other, sc, nb, true);
+            restrict_level<T, T>(c, l, (const T *)L.b, cur, sc, nb, fuse);
         }
         res[l] = cur;
     }
@@ -631,8 +652,8 @@ bool vcycle(Ctx *c, const TR *r, T *z, const Scal *sc, int nb, const CycleDots *
         Level &L = c->lv[l];
         T *cur = res[l];
         T *other = (cur == (T *)L.x2) ? (l == 0 ? z : (T *)L.x) : (T *)L.x2;
-        // between two structured levels the prolongation rides on the first post-smoothing step
-        const bool fused = !L.ell && !c->lv[l + 1].ell;
+        // between two structured or two ELL levels the prolongation rides on the first post-smoothing step
+        const bool fused = L.ell == c->lv[l + 1].ell;
         if (!fused) prolong_level<T>(c, l, cur, sc, nb);
         if (l == 0)
             smooth_post<T, TR>(c, l, r, cur, other, sc, nb, fused, dots);
@@ -659,7 +680,7 @@ void set_defaults(spfd_amg_options &o)
     if (o.coarsest_max <= 0) o.coarsest_max = 1024;
     if (o.coarsest_max > 1024) o.coarsest_max = 1024;
     if (!(o.cheby_ratio > 1.0)) o.cheby_ratio = 8.0;
-    if (!(o.coarse_scale > 0.0)) o.coarse_scale = 1.8;
+    if (!(o.coarse_scale > 0.0)) o.coarse_scale = 1.9;
     if (o.split_level <= 0) o.split_level = 2;
 }
 
@@ -922,12 +943,19 @@ spfd_status do_build(Ctx *c)
         double *dwork = dalloc<double>(c, c->hier_allocs, dense_inverse_work_doubles(c->ncoarse));
         HIPCHK(launch_coarse_factor(c->ncoarse, c->d_Ainv, c->d_cwork, dwork, c->stream));
     }
-    // column masks of the structured levels (the stencil kernels skip columns without unknowns)
-    for (Level &L : c->lv)
-        if (!L.ell && L.nb > 0) {
+    // column masks of the structured levels (the stencil kernels skip columns without unknowns) and
+    // the inverse diagonals (first Chebyshev steps folded into neighbouring kernels)
+    for (Level &L : c->lv) {
+        L.d_dinv64 = dalloc<double>(c, c->hier_allocs, L.nodes());
+        L.d_dinv32 = dalloc<float>(c, c->hier_allocs, L.nodes());
+        if (L.ell) {
+            HIPCHK(launch_dinv_ell(L.nrow, L.K, L.d_col, L.d_val64, L.d_dinv64, L.d_dinv32, c->stream));
+        } else if (L.nb > 0) {
             L.d_cmask = dalloc<unsigned long long>(c, c->hier_allocs, L.nb);
             HIPCHK(launch_col_masks(L.d_w64, L.nodes(), L.topo(), L.d_cmask, c->stream));
+            HIPCHK(launch_dinv_struct(L.d_w64, L.nodes(), Topo{L.nb, L.d_nbr}, L.d_dinv64, L.d_dinv32, c->stream));
         }
+    }
     chebyshev_coefficients(c);
     HIPCHK(hipStreamSynchronize(c->stream));
     return SPFD_OK;

@@ -193,10 +193,11 @@ hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T
                             double *dot_part = nullptr);
 template <typename T>
 int cheb_dot_parts(int nb);
+// xc != nullptr: also the coarse level's first Chebyshev step, xc = c0 dinv_c bc
 template <typename T, typename TB>
 hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, const T *x, T *bc,
                                  const int *parent_slot, const int4 *fcoord, const Scal *sc, const Batch &bt,
-                                 hipStream_t s);
+                                 hipStream_t s, T *xc = nullptr, const T *dinv_c = nullptr, T c0 = T(0));
 template <typename T>
 hipError_t launch_prolong(Topo topo, T *x, const T *xc, const int *parent_slot, const int4 *fcoord, T scale,
                           const Scal *sc, const Batch &bt, hipStream_t s);
@@ -255,14 +256,21 @@ hipError_t scan_exclusive_ints(const int *in, long long n, int *out, int *tmp, i
 template <typename T>
 hipError_t launch_ell_cheb_first(int n, int K, const int *col, const T *val, const T *b, T *x, T c0, const Scal *sc,
                                  const Batch &bt, hipStream_t s);
+// agg != nullptr: the prolongation xin += scale xc[agg] from the coarser ELL level is applied to every value read
 template <typename T>
 hipError_t launch_ell_cheb_step(int n, int K, const int *col, const T *val, const T *b, const T *xin, T *xout,
-                                const T *din, T *dout, T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s);
-// b_c = P^T (b - A x) onto an ELL level: r (nrows per right side) receives the fine residual
+                                const T *din, T *dout, T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s,
+                                const int *agg = nullptr, const T *xc = nullptr, T scale = T(0));
+// b_c = P^T (b - A x) onto an ELL level: r (nrows per right side) receives the fine residual;
+// xc != nullptr: also the coarse level's first Chebyshev step, xc = c0 dinv_c b_c
 template <typename T>
 hipError_t launch_restrict_members(const FineLevelT<T> &f, long long nrows, const T *b, const T *x, T *r, int nc,
                                    const int *mptr, const int *mem, T *bc, const Scal *sc, const Batch &bt,
-                                   hipStream_t s);
+                                   hipStream_t s, T *xc = nullptr, const T *dinv_c = nullptr, T c0 = T(0));
+// inverse diagonals (0 where the diagonal vanishes): ELL level, structured level
+hipError_t launch_dinv_ell(int n, int K, const int *col, const double *val, double *d64, float *d32, hipStream_t s);
+hipError_t launch_dinv_struct(const double *w64, long long stride, Topo topo, double *d64, float *d32,
+                              hipStream_t s);
 template <typename T>
 hipError_t launch_prolong_agg(long long n, const int *agg, T *x, const T *xc, T scale, const Scal *sc,
                               const Batch &bt, hipStream_t s);

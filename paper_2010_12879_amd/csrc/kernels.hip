@@ -578,6 +578,34 @@ __global__ __launch_bounds__(NT) void k_col_masks(const double *__restrict__ w, 
     if (t == 0) mask[bk] = m;
 }
 
+// inverse diagonals of a structured level from its stored weights (0 where the diagonal vanishes)
+__global__ __launch_bounds__(NT) void k_dinv_struct(const double *__restrict__ w, long long stride, Topo topo,
+                                                    double *__restrict__ d64, float *__restrict__ d32)
+{
+    const int bk = blockIdx.x;
+    const int t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    int nb[6];
+    brick_nbrs(topo.nbr, bk, nb);
+    const long long base = (long long)bk * BS;
+    long long I[6];
+    nbr_index(base, t, tx, ty, tz, nb, I);
+    double W[6];
+    stored_weights(w, stride, base, t, I, W);
+    const double D = diag_of(W);
+    const double v = D > 0.0 ? 1.0 / D : 0.0;
+    d64[base + t] = v;
+    d32[base + t] = (float)v;
+}
+
+hipError_t launch_dinv_struct(const double *w64, long long stride, Topo topo, double *d64, float *d32, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    SPFD_LAUNCH(k_dinv_struct, dim3(topo.nb), dim3(NT), 0, s, w64, stride, topo, d64, d32);
+    return hipGetLastError();
+}
+
 hipError_t launch_col_masks(const double *w64, long long stride, Topo topo, unsigned long long *mask, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;

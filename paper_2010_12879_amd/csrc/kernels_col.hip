@@ -459,7 +459,8 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
                                                                  const T *__restrict__ x, T *__restrict__ bc,
                                                                  const int *__restrict__ parent_slot,
                                                                  const int4 *__restrict__ fcoord, const Scal *sc,
-                                                                 long long vs, long long vsc)
+                                                                 long long vs, long long vsc, T *__restrict__ xc,
+                                                                 const T *__restrict__ dinv_c, T c0)
 {
     T *lds = col_lds<T, ZPL, LABEL>();
     const Seg<ZPL> s = make_seg<ZPL>(topo);
@@ -479,6 +480,14 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
     }
     const int4 fc = fcoord[s.bk];
     const long long pbase = (long long)parent_slot[s.bk] * BS;
+    const int ox = (fc.x & 1) * 4 + (s.tx >> 1), oy = (fc.y & 1) * 4 + (s.ty >> 1);
+    const int oz = (fc.z & 1) * 4 + (s.z0 >> 1);
+    const bool corner = ((s.tx | s.ty) & 1) == 0 && !done;
+    // inverse diagonals of the coarse nodes this lane may store (loaded early: no tail latency)
+    T dc[ZPL / 2];
+    if (xc && corner)
+#pragma unroll
+        for (int k = 0; k < ZPL / 2; ++k) dc[k] = dinv_c[pbase + ox + 8 * oy + 64 * (oz + k)];
     A.stage(op, s);
     T r[ZPL];
 #pragma unroll
@@ -491,15 +500,17 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
             X.nbrs(z, N);
             r[z] = bv[z] - stencil_apply(X.c[z], N, W);
         }
-    const int ox = (fc.x & 1) * 4 + (s.tx >> 1), oy = (fc.y & 1) * 4 + (s.ty >> 1);
-    const int oz = (fc.z & 1) * 4 + (s.z0 >> 1);
-    const bool corner = ((s.tx | s.ty) & 1) == 0 && !done;
 #pragma unroll
     for (int k = 0; k < ZPL / 2; ++k) {
         T a = r[2 * k] + r[2 * k + 1];
         a += __shfl_down(a, 1, 64);
         a += __shfl_down(a, 8, 64);
-        if (corner) bc[pbase + ox + 8 * oy + 64 * (oz + k)] = a;
+        if (corner) {
+            const long long n = pbase + ox + 8 * oy + 64 * (oz + k);
+            bc[n] = a;
+            // the coarse level's first Chebyshev step from zero: x_c = c0 D_c^-1 b_c
+            if (xc) xc[blockIdx.y * vsc + n] = c0 * a * dc[k];
+        }
     }
 }
 
@@ -665,8 +676,8 @@ hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T
     const int sel = (op.w ? 0 : 4) | (xc ? 2 : 0) | (dot_part ? 1 : 0);
 #define SPFD_CHEB_CASE(K, LAB, PRO, DOT)                                                                              \
     case K:                                                                                                           \
-        SPFD_LAUNCH((k_col_cheb_step<T, TB, ZPL, LAB, PRO, DOT>), g, dim3(CTHREADS), 0, s, op, topo, b, xin,  \
-                           xout, din, dout, c1, c2, sc, bt.vs, pr, dt);                                               \
+        SPFD_LAUNCH((k_col_cheb_step<T, TB, ZPL, LAB, PRO, DOT>), g, dim3(CTHREADS), 0, s, op, topo, b, xin, xout,   \
+                    din, dout, c1, c2, sc, bt.vs, pr, dt);                                                            \
         break;
     switch (sel) {
         SPFD_CHEB_CASE(0, false, false, false)
@@ -692,17 +703,19 @@ template int cheb_dot_parts<double>(int);
 
 template <typename T, typename TB>
 hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, const T *x, T *bc, const int *parent_slot,
-                                 const int4 *fcoord, const Scal *sc, const Batch &bt, hipStream_t s)
+                                 const int4 *fcoord, const Scal *sc, const Batch &bt, hipStream_t s, T *xc,
+                                 const T *dinv_c, T c0)
 {
+    if (xc && !dinv_c) return hipErrorInvalidValue;
     if (topo.nb <= 0) return hipSuccess;
     constexpr int ZPL_CYCLE = zpl_cycle<T>();
     const dim3 g = col_grid<ZPL_CYCLE>(topo.nb, bt.n);
     if (op.w)
         SPFD_LAUNCH((k_col_resid_restrict<T, TB, ZPL_CYCLE, false>), g, dim3(CTHREADS), 0, s, op, topo, b, x,
-                           bc, parent_slot, fcoord, sc, bt.vs, bt.vsc);
+                           bc, parent_slot, fcoord, sc, bt.vs, bt.vsc, xc, dinv_c, c0);
     else
         SPFD_LAUNCH((k_col_resid_restrict<T, TB, ZPL_CYCLE, true>), g, dim3(CTHREADS), 0, s, op, topo, b, x,
-                           bc, parent_slot, fcoord, sc, bt.vs, bt.vsc);
+                           bc, parent_slot, fcoord, sc, bt.vs, bt.vsc, xc, dinv_c, c0);
     return hipGetLastError();
 }
 
@@ -749,7 +762,7 @@ template hipError_t launch_spmv<float>(const OpArgs<double> &, Topo, const float
                                                 double *);                                                          \
     template hipError_t launch_resid_restrict<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *,           \
                                                      const int *, const int4 *, const Scal *, const Batch &,        \
-                                                     hipStream_t);
+                                                     hipStream_t, T *, const T *, T);
 SPFD_INST_COL(double, double)
 SPFD_INST_COL(float, float)
 SPFD_INST_COL(float, double)

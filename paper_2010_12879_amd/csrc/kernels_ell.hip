@@ -406,11 +406,26 @@ __global__ void k_ell_cheb_first(int n, int K, const int *__restrict__ col, cons
     }
 }
 
+// x with the coarse-grid correction of the prolongation applied: x_i + s x_c[agg_i] (agg_i < 0: none)
+template <typename T>
+__device__ __forceinline__ T corrected(const T *__restrict__ x, const int *__restrict__ agg, const T *__restrict__ xc,
+                                       T scale, int i)
+{
+    const T v = x[i];
+    if (!agg) return v;
+    const int a = agg[i];
+    return a >= 0 ? v + scale * xc[a] : v;
+}
+
+// general Chebyshev step on an ELL level; with agg the prolongation from the
+// coarser ELL level (x += s x_c[agg]) is applied to every value read (the
+// first post-smoothing step)
 template <typename T>
 __global__ void k_ell_cheb_step(int n, int K, const int *__restrict__ col, const T *__restrict__ val,
                                 const T *__restrict__ b, const T *__restrict__ xin, T *__restrict__ xout,
                                 const T *__restrict__ din, T *__restrict__ dout, T c1, T c2, const Scal *sc,
-                                long long vs)
+                                long long vs, const int *__restrict__ agg, const T *__restrict__ xc, T scale,
+                                long long vsc)
 {
     if (ell_stopped(sc)) return;
     b += blockIdx.y * vs;
@@ -418,10 +433,27 @@ __global__ void k_ell_cheb_step(int n, int K, const int *__restrict__ col, const
     xout += blockIdx.y * vs;
     if (din) din += blockIdx.y * vs;
     if (dout) dout += blockIdx.y * vs;
+    if (agg) xc += blockIdx.y * vsc;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const T xi = xin[i];
+        const T xi = corrected(xin, agg, xc, scale, i);
         T D;
-        const T ax = ell_row(n, K, col, val, xin, i, xi, D);
+        T ax;
+        if (agg) {
+            T y = T(0), d = T(0);
+#pragma unroll 4
+            for (int k = 0; k < K; ++k) {
+                const int j = col[(long long)k * n + i];
+                if (j >= 0) {
+                    const T w = val[(long long)k * n + i];
+                    d += w;
+                    y += w * (xi - corrected(xin, agg, xc, scale, j));
+                }
+            }
+            D = d;
+            ax = y;
+        } else {
+            ax = ell_row(n, K, col, val, xin, i, xi, D);
+        }
         T xo = T(0), dn = T(0);
         if (D > T(0)) {
             const T dold = din ? din[i] : xi;
@@ -468,21 +500,47 @@ __global__ void k_resid_rows(FineLevelT<T> f, long long nrows, const T *__restri
     }
 }
 
+// (with xc: also the coarse level's first Chebyshev step, xc = c0 D^-1 b_c)
 template <typename T>
 __global__ void k_sum_members(int nc, const int *__restrict__ mptr, const int *__restrict__ mem,
                               const T *__restrict__ r, T *__restrict__ bc, const Scal *sc, long long vs,
-                              long long vsc)
+                              long long vsc, T *__restrict__ xc, const T *__restrict__ dinv, T c0)
 {
     const bool done = ell_stopped(sc);
     r += blockIdx.y * vs;
     bc += blockIdx.y * vsc;
+    if (xc) xc += blockIdx.y * vsc;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
         const int q0 = mptr[p], q1 = mptr[p + 1];
         T s = T(0);
 #pragma unroll 4
         for (int q = q0; q < q1; ++q) s += r[mem[q]];
-        if (!done) bc[p] = s;
+        if (!done) {
+            bc[p] = s;
+            if (xc) xc[p] = c0 * s * dinv[p];
+        }
     }
+}
+
+// inverse diagonals (0 where the diagonal vanishes) of an ELL level
+__global__ void k_dinv_ell(int n, int K, const int *__restrict__ col, const double *__restrict__ val,
+                           double *__restrict__ d64, float *__restrict__ d32)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double d = 0.0;
+        for (int k = 0; k < K; ++k)
+            if (col[(long long)k * n + i] >= 0) d += val[(long long)k * n + i];
+        const double v = d > 0.0 ? 1.0 / d : 0.0;
+        d64[i] = v;
+        d32[i] = (float)v;
+    }
+}
+
+hipError_t launch_dinv_ell(int n, int K, const int *col, const double *val, double *d64, float *d32, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    SPFD_LAUNCH(k_dinv_ell, dim3(gblocks(n)), dim3(256), 0, s, n, K, col, val, d64, d32);
+    return hipGetLastError();
 }
 
 // x_f += scale * x_c[agg]
@@ -511,24 +569,27 @@ hipError_t launch_ell_cheb_first(int n, int K, const int *col, const T *val, con
 
 template <typename T>
 hipError_t launch_ell_cheb_step(int n, int K, const int *col, const T *val, const T *b, const T *xin, T *xout,
-                                const T *din, T *dout, T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s)
+                                const T *din, T *dout, T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s,
+                                const int *agg, const T *xc, T scale)
 {
     if (n <= 0) return hipSuccess;
-    SPFD_LAUNCH(k_ell_cheb_step<T>, dim3(gblocks(n), bt.n), dim3(256), 0, s, n, K, col, val, b, xin, xout, din,
-                       dout, c1, c2, sc, bt.vs);
+    if (agg && !xc) return hipErrorInvalidValue;
+    SPFD_LAUNCH(k_ell_cheb_step<T>, dim3(gblocks(n), bt.n), dim3(256), 0, s, n, K, col, val, b, xin, xout, din, dout,
+                c1, c2, sc, bt.vs, agg, xc, scale, bt.vsc);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_restrict_members(const FineLevelT<T> &f, long long nrows, const T *b, const T *x, T *r, int nc,
                                    const int *mptr, const int *mem, T *bc, const Scal *sc, const Batch &bt,
-                                   hipStream_t s)
+                                   hipStream_t s, T *xc, const T *dinv_c, T c0)
 {
     if (nc <= 0 || nrows <= 0) return hipSuccess;
+    if (xc && !dinv_c) return hipErrorInvalidValue;
     SPFD_LAUNCH(k_resid_rows<T>, dim3(gblocks(nrows, 256), bt.n), dim3(256), 0, s, f, nrows, b, x, r, sc,
-                       bt.vs);
+                bt.vs);
     SPFD_LAUNCH(k_sum_members<T>, dim3(gblocks(nc, 64), bt.n), dim3(64), 0, s, nc, mptr, mem, r, bc, sc, bt.vs,
-                       bt.vsc);
+                bt.vsc, xc, dinv_c, c0);
     return hipGetLastError();
 }
 
@@ -546,10 +607,11 @@ hipError_t launch_prolong_agg(long long n, const int *agg, T *x, const T *xc, T 
     template hipError_t launch_ell_cheb_first<T>(int, int, const int *, const T *, const T *, T *, T, const Scal *, \
                                                  const Batch &, hipStream_t);                                       \
     template hipError_t launch_ell_cheb_step<T>(int, int, const int *, const T *, const T *, const T *, T *,         \
-                                                const T *, T *, T, T, const Scal *, const Batch &, hipStream_t);    \
+                                                const T *, T *, T, T, const Scal *, const Batch &, hipStream_t,     \
+                                                const int *, const T *, T);                                         \
     template hipError_t launch_restrict_members<T>(const FineLevelT<T> &, long long, const T *, const T *, T *, int, \
                                                    const int *, const int *, T *, const Scal *, const Batch &,      \
-                                                   hipStream_t);                                                    \
+                                                   hipStream_t, T *, const T *, T);                                 \
     template hipError_t launch_prolong_agg<T>(long long, const int *, T *, const T *, T, const Scal *,             \
                                               const Batch &, hipStream_t);
 SPFD_INST_ELL(double)
