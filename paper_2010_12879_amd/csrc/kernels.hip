@@ -269,28 +269,63 @@ __global__ void k_cc_init(const double *__restrict__ w, long long stride, Topo t
     parent[base + t] = diag_of(W) > 0.0 ? (int)(base + t) : -1;
 }
 
+// union-find in LDS over the conducting edges inside one brick
+__device__ __forceinline__ int lfind(int *p, int x)
+{
+    int px = __hip_atomic_load(p + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    while (px != x) {
+        x = px;
+        px = __hip_atomic_load(p + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    return x;
+}
+
+__device__ __forceinline__ void lunite(int *p, int a, int b)
+{
+    while (true) {
+        a = lfind(p, a);
+        b = lfind(p, b);
+        if (a == b) return;
+        if (a > b) { const int t = a; a = b; b = t; }
+        int expected = b;
+        if (__hip_atomic_compare_exchange_strong(p + b, &expected, a, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
+    }
+}
+
+// Components in two stages: first inside each brick (LDS, workgroup atomics),
+// storing every node's brick-local root as its parent; then, after the kernel
+// boundary, across the brick faces only (global union-find), so the
+// device-wide atomics see short chains.
+__global__ void k_cc_local(const double *__restrict__ w, long long stride, int *parent)
+{
+    __shared__ int lp[BS];
+    const int b = blockIdx.x, t = threadIdx.x;
+    int tx, ty, tz;
+    brick_xyz(t, tx, ty, tz);
+    const long long base = (long long)b * BS;
+    lp[t] = parent[base + t] >= 0 ? t : -1;
+    __syncthreads();
+    if (tx < 7 && w[base + t] > 0.0) lunite(lp, t, t + 1);
+    if (ty < 7 && w[stride + base + t] > 0.0) lunite(lp, t, t + 8);
+    if (tz < 7 && w[2 * stride + base + t] > 0.0) lunite(lp, t, t + 64);
+    __syncthreads();
+    if (lp[t] >= 0) parent[base + t] = (int)base + lfind(lp, t);
+}
+
 __global__ void k_cc_union(const double *__restrict__ w, long long stride, Topo topo, int *parent)
 {
-    __shared__ int nb[6];
     const int b = blockIdx.x, t = threadIdx.x;
-    if (t < 6) nb[t] = topo.nbr[b * 6 + t];
-    __syncthreads();
+    int nb[6];
+    brick_nbrs(topo.nbr, b, nb);
     int tx, ty, tz;
     brick_xyz(t, tx, ty, tz);
     const long long base = (long long)b * BS;
     const int me = (int)(base + t);
-    if (w[base + t] > 0.0) {
-        const int m = tx < 7 ? me + 1 : (nb[NPX] >= 0 ? nb[NPX] * BS + t - 7 : -1);
-        if (m >= 0) punite(parent, me, m);
-    }
-    if (w[stride + base + t] > 0.0) {
-        const int m = ty < 7 ? me + 8 : (nb[NPY] >= 0 ? nb[NPY] * BS + t - 56 : -1);
-        if (m >= 0) punite(parent, me, m);
-    }
-    if (w[2 * stride + base + t] > 0.0) {
-        const int m = tz < 7 ? me + 64 : (nb[NPZ] >= 0 ? nb[NPZ] * BS + t - 448 : -1);
-        if (m >= 0) punite(parent, me, m);
-    }
+    if (tx == 7 && nb[NPX] >= 0 && w[base + t] > 0.0) punite(parent, me, nb[NPX] * BS + t - 7);
+    if (ty == 7 && nb[NPY] >= 0 && w[stride + base + t] > 0.0) punite(parent, me, nb[NPY] * BS + t - 56);
+    if (tz == 7 && nb[NPZ] >= 0 && w[2 * stride + base + t] > 0.0) punite(parent, me, nb[NPZ] * BS + t - 448);
 }
 
 __global__ void k_cc_flatten(int *parent, long long n, int *flag)
@@ -410,6 +445,7 @@ hipError_t launch_components(const double *w64, long long stride, Topo topo, int
     const long long n = (long long)nb * BS;
     if (nb <= 0) return hipSuccess;
     SPFD_LAUNCH(k_cc_init, dim3(nb), dim3(NT), 0, s, w64, stride, topo, parent);
+    SPFD_LAUNCH(k_cc_local, dim3(nb), dim3(NT), 0, s, w64, stride, parent);
     SPFD_LAUNCH(k_cc_union, dim3(nb), dim3(NT), 0, s, w64, stride, topo, parent);
     const unsigned gb = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
     SPFD_LAUNCH(k_cc_store_root, dim3(gb), dim3(256), 0, s, parent, n);
@@ -630,19 +666,24 @@ __global__ void k_coarse_regularize(int n, double *A, int *work)
     int *deg = work + 4 * n + 2;          // row degree (-1: more than CMAXADJ, scan the dense row)
     int *adj = deg + n;                   // [n][CMAXADJ] off-diagonal nonzero columns
     __shared__ int changed;
-    // the pattern once, as adjacency lists
-    for (int q = t; q < n; q += nt) {
-        comp[q] = q;
-        csize[q] = 0;
-        int d = 0;
-        for (int m = 0; m < n && d >= 0; ++m) {
-            if (m == q || A[(long long)q * n + m] == 0.0) continue;
-            if (d < CMAXADJ)
-                adj[(long long)q * CMAXADJ + d++] = m;
-            else
-                d = -1;
+    // the pattern once, as adjacency lists: one wave per row, 64 columns per step
+    const int lane = t & 63, nw = nt >> 6;
+    for (int q = t >> 6; q < n; q += nw) {
+        if (lane == 0) {
+            comp[q] = q;
+            csize[q] = 0;
         }
-        deg[q] = d;
+        int d = 0;
+        for (int m0 = 0; m0 < n; m0 += 64) {
+            const int m = m0 + lane;
+            const bool nz = m < n && m != q && A[(long long)q * n + m] != 0.0;
+            const unsigned long long bal = __ballot(nz);
+            const int pos = d + __popcll(bal & ((1ull << lane) - 1ull));
+            if (nz && d >= 0 && pos < CMAXADJ) adj[(long long)q * CMAXADJ + pos] = m;
+            if (d >= 0) d += __popcll(bal);
+            if (d > CMAXADJ) d = -1;
+        }
+        if (lane == 0) deg[q] = d;
     }
     __syncthreads();
     // minimum label over each component: neighbour minima plus pointer jumping
@@ -674,15 +715,26 @@ __global__ void k_coarse_regularize(int n, double *A, int *work)
     double *cdiag = colk;  // scratch before the elimination
     for (int q = t; q < n; q += nt) cdiag[q] = 0.0;
     __syncthreads();
+    // per-component diagonal sums in a fixed order (deterministic): diagonal and labels staged in LDS
+    __shared__ double sdiag[1024], ssum[1024];
+    __shared__ int scomp[1024];
+    for (int q = t; q < n; q += nt) {
+        sdiag[q] = A[(long long)q * n + q];
+        scomp[q] = comp[q];
+        ssum[q] = 0.0;
+    }
+    __syncthreads();
     if (t == 0)
-        for (int q = 0; q < n; ++q) cdiag[comp[q]] += A[(long long)q * n + q];
+        for (int q = 0; q < n; ++q) ssum[scomp[q]] += sdiag[q];
+    __syncthreads();
+    for (int q = t; q < n; q += nt) cdiag[q] = ssum[q];
     __syncthreads();
     for (long long e = t; e < (long long)n * n; e += nt) {
         const int i = (int)(e / n), j = (int)(e % n);
-        const int c = comp[i];
-        if (comp[j] == c) {
+        const int c = scomp[i];
+        if (scomp[j] == c) {
             const double sz = (double)csize[c];
-            A[e] += (cdiag[c] / sz) / sz;
+            A[e] += (ssum[c] / sz) / sz;
         }
     }
 }

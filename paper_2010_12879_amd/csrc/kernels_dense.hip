@@ -66,29 +66,40 @@ __device__ __forceinline__ void tile_mul(const double *a, const double *b, doubl
     }
 }
 
-// P = A_kk^-1 by in-place Gauss-Jordan in LDS: for pivot p with a = A_pp,
-// A_pp <- 1/a, A_pj <- A_pj / a, A_ip <- -A_ip / a, A_ij <- A_ij - A_ip A_pj / a
-__global__ __launch_bounds__(256) void k_gj_diag(int ld, int k0, const double *__restrict__ W, double *__restrict__ P)
+// P = A_kk^-1 by Gauss-Jordan: for pivot p with a = A_pp,
+// A_pp <- 1/a, A_pj <- A_pj / a, A_ip <- -A_ip / a, A_ij <- A_ij - A_ip A_pj / a.
+// 1024 threads hold four entries each in registers (row i = t/16, columns
+// 4 (t%16) .. +3); per pivot only row p and column p pass through LDS.
+__global__ __launch_bounds__(1024) void k_gj_diag(int ld, int k0, const double *__restrict__ W, double *__restrict__ P)
 {
-    __shared__ double t[GT * GS];
-    __shared__ double col[GT], row[GT];
-    tile_load(W, ld, k0, k0, t);
-    __syncthreads();
+    __shared__ double row[GT], col[GT];
+    const int t = threadIdx.x;
+    const int i = t >> 4, j0 = (t & 15) * 4;
+    double a[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = W[(long long)(k0 + i) * ld + k0 + j0 + q];
     for (int p = 0; p < GT; ++p) {
-        if (threadIdx.x < GT) {
-            col[threadIdx.x] = t[threadIdx.x * GS + p];
-            row[threadIdx.x] = t[p * GS + threadIdx.x];
+        if (i == p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) row[j0 + q] = a[q];
+        if (p >= j0 && p < j0 + 4) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (j0 + q == p) col[i] = a[q];
         }
         __syncthreads();
         const double piv = 1.0 / row[p];
-        for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) {
-            const int i = e / GT, j = e % GT;
+        const double ci = col[i];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = j0 + q;
             const double rpj = (j == p) ? 1.0 : row[j];
-            t[i * GS + j] = (i == p) ? rpj * piv : (j == p ? 0.0 : t[i * GS + j]) - col[i] * piv * rpj;
+            a[q] = (i == p) ? rpj * piv : (j == p ? 0.0 : a[q]) - ci * piv * rpj;
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) P[e] = t[(e / GT) * GS + e % GT];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) P[i * GT + j0 + q] = a[q];
 }
 
 // row block k <- P A_k*, A_kk <- P; and the old column block (rows outside k) into C [ld][64]
@@ -165,7 +176,7 @@ hipError_t launch_dense_inverse(int n, double *A, double *work, hipStream_t s)
     SPFD_LAUNCH(k_gj_pad, dim3(blocks((long long)ld * ld)), dim3(256), 0, s, n, ld, A, W);
     for (int k = 0; k < nt; ++k) {
         const int k0 = k * GT;
-        SPFD_LAUNCH(k_gj_diag, dim3(1), dim3(256), 0, s, ld, k0, W, P);
+        SPFD_LAUNCH(k_gj_diag, dim3(1), dim3(1024), 0, s, ld, k0, W, P);
         SPFD_LAUNCH(k_gj_row, dim3(nt), dim3(256), 0, s, ld, k0, W, P, C);
         SPFD_LAUNCH(k_gj_update, dim3(nt, nt), dim3(256), 0, s, ld, k0, W, P, C);
     }
