@@ -135,6 +135,7 @@ def run_precision(prec, w, lab, a, args, P, torch):
         step(True)
     stats = {name: P.spfd_timing_get(h, k) for k, name in enumerate(P.KERNEL_CLASSES)}
     ndofs = P.spfd_get_info(h)
+    ndofs["hierarchy"] = [P.spfd_level_info(h, lv) for lv in range(ndofs["n_levels"])]
     P.spfd_destroy(h)
     return phases, info, stats, ndofs, psi.cpu().numpy(), emag
 
@@ -388,6 +389,7 @@ def main():
         "efield_ms": mean(ph["efield"]) * 1e3,
         "solve_hbm_gbs": solve_bytes / solve_s / 1e9,
         "device_bytes": ninfo["device_bytes"],
+        "hierarchy": ninfo["hierarchy"],
         "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,

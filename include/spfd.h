@@ -117,6 +117,14 @@ spfd_status spfd_build(spfd_handle h, const spfd_amg_options *opt);
  * components, multigrid levels, device bytes held by the handle. */
 spfd_status spfd_get_info(spfd_handle h, long long *n_dofs, int *n_components, int *n_levels,
                           size_t *device_bytes);
+/* One level of the multigrid hierarchy after build (0 = finest; any pointer
+ * may be NULL): kind 0 = structured brick level (7-point stencil), 1 =
+ * unstructured level (rows of the split aggregation, ELL storage); its
+ * unknowns; the slots of its vectors (bricks x 512, or rows); the entries per
+ * matrix row (7, or 1 + the ELL width).  The last level is the one solved
+ * directly.  SPFD_INVALID_ARG for a level outside [0, n_levels). */
+spfd_status spfd_level_info(spfd_handle h, int level, int *kind, long long *unknowns, long long *slots,
+                            int *row_entries);
 /* Number of right-hand sides solved together (default 1); resets the sources. */
 spfd_status spfd_set_num_rhs(spfd_handle h, int nrhs);
 /* Right-hand side of Eq. (3) for source `rhs`: b = -G^T M_kappa a, with

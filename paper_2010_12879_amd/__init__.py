@@ -52,7 +52,7 @@ class RhsInfo(ctypes.Structure):
 
 _lib = None
 EXPORTS = ["spfd_create", "spfd_destroy", "spfd_last_error", "spfd_set_geometry", "spfd_set_sigma_table",
-           "spfd_set_sigma_voxel", "spfd_build", "spfd_get_info", "spfd_set_num_rhs", "spfd_set_source",
+           "spfd_set_sigma_voxel", "spfd_build", "spfd_get_info", "spfd_level_info", "spfd_set_num_rhs", "spfd_set_source",
            "spfd_solve", "spfd_solve_many", "spfd_efield", "spfd_edge_potentials", "spfd_percentile", "spfd_adjoint", "spfd_timing", "spfd_timing_get"]
 # kernel classes of spfd_timing / spfd_timing_get (order of the enum in spfd.h)
 KERNEL_CLASSES = ["spmv", "update", "dots", "pupdate", "smooth0", "smooth0_first", "restrict0", "prolong0", "coarse",
@@ -81,6 +81,8 @@ def load_library(path: str = LIB_PATH):
     lib.spfd_build.argtypes = [H, ctypes.POINTER(AmgOptions)]
     lib.spfd_get_info.argtypes = [H, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I), ctypes.POINTER(I),
                                   ctypes.POINTER(ctypes.c_size_t)]
+    lib.spfd_level_info.argtypes = [H, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_longlong),
+                                    ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I)]
     lib.spfd_set_num_rhs.argtypes = [H, I]
     lib.spfd_set_source.argtypes = [H, I, P]
     lib.spfd_solve.argtypes = [H, ctypes.POINTER(SolveOptions), P, ctypes.POINTER(RhsInfo)]
@@ -167,6 +169,15 @@ def spfd_get_info(h):
     nd, nc, nl, nbytes = ctypes.c_longlong(), ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
     _check(h, load_library().spfd_get_info(h, ctypes.byref(nd), ctypes.byref(nc), ctypes.byref(nl), ctypes.byref(nbytes)))
     return {"n_dofs": nd.value, "n_components": nc.value, "n_levels": nl.value, "device_bytes": nbytes.value}
+
+
+def spfd_level_info(h, level):
+    """kind ("structured" or "ell"), unknowns, slots and entries per row of one level."""
+    k, n, sl, re = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
+    _check(h, load_library().spfd_level_info(h, level, ctypes.byref(k), ctypes.byref(n), ctypes.byref(sl),
+                                             ctypes.byref(re)))
+    return {"kind": "ell" if k.value else "structured", "unknowns": n.value, "slots": sl.value,
+            "row_entries": re.value}
 
 
 def spfd_set_num_rhs(h, nrhs):

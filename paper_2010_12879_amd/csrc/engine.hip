@@ -21,6 +21,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -105,6 +106,8 @@ struct Ctx {
     Scal *d_scal = nullptr;
     Scal *h_scal = nullptr;   // pinned, one per right side plus one for the adjoint solve
     Scal *h_ring = nullptr;   // pinned, 2 x (nrhs + 1): scalars of the last two enqueued CG steps
+    Scal *h_ring_dev = nullptr;   // device address of h_ring (written by the last kernel of a CG step)
+    Scal *step_mirror = nullptr;  // where the CG step being enqueued leaves its scalars
     hipEvent_t ev_it[2] = {nullptr, nullptr};
     // adjoint solve
     double *d_adj_b = nullptr;
@@ -134,6 +137,7 @@ struct Ctx {
     // captured CG iterations (one per buffer parity), replayed with hipGraphLaunch
     struct StepGraph {
         hipGraphExec_t exec = nullptr;
+        const Scal *mirror = nullptr;
         long long launch[SPFD_K_COUNT] = {};
         double bytes[SPFD_K_COUNT] = {};
     };
@@ -479,9 +483,10 @@ const double *dinv_of<double>(const Level &L) { return L.d_dinv64; }
 template <>
 const float *dinv_of<float>(const Level &L) { return L.d_dinv32; }
 
-// CG dot products formed by the last finest-level smoothing step
+// CG dot products formed by the last finest-level smoothing step: z.b with
+// the cycle's right side b (the residual, or its FP32 copy in an FP32 cycle)
+// and z.q
 struct CycleDots {
-    const double *r = nullptr;
     const double *q = nullptr;
     double *part = nullptr;
 };
@@ -502,14 +507,14 @@ void cheb_step(Ctx *c, int l, const TB *b, const T *xin, T *xout, const T *din, 
     }
     double per = sizeof(TB) + op_bytes<T>(c, l) + sizeof(T) * (2 + (din ? 1 : 0) + (dout ? 1 : 0));
     if (with_prolong) per += sizeof(T) / 8.0;
-    if (dots) per += 16.0;
+    if (dots) per += 8.0;
     const int cls = l == 0 ? (with_prolong ? SPFD_K_PROLONG0 : dots ? SPFD_K_DOTS : SPFD_K_SMOOTH0) : SPFD_K_COARSE;
     TScope ts(c, cls, nb * (double)L.dofs * per);
     const T *xc = nullptr;
     if (with_prolong) xc = (const T *)c->lv[l + 1].x;
     HIPCHK(launch_cheb_step<T, TB>(level_op<T>(c, l), L.topo(), b, xin, xout, din, dout, c1, c2, sc, bt, c->stream, xc,
-                                   L.d_parent_slot, L.d_coord, (T)c->opt.coarse_scale, dots ? dots->r : nullptr,
-                                   dots ? dots->q : nullptr, dots ? dots->part : nullptr));
+                                   L.d_parent_slot, L.d_coord, (T)c->opt.coarse_scale, dots ? dots->q : nullptr,
+                                   dots ? dots->part : nullptr));
 }
 
 template <typename T, typename TB>
@@ -574,8 +579,7 @@ void restrict_level(Ctx *c, int l, const TB *b, const T *x, const Scal *sc, int 
             f.nbr = L.d_nbr;
         }
         TScope ts(c, SPFD_K_COARSE, nb * ((double)L.dofs * 3.0 * sizeof(T) + (double)C.nrow * 8.0) + fb);
-        // the fine level's Chebyshev direction is free between pre- and post-smoothing
-        HIPCHK(launch_restrict_members<T>(f, L.nodes(), (const T *)b, x, (T *)L.d, C.nrow, C.d_mptr, C.d_mem,
+        HIPCHK(launch_restrict_members<T>(f, L.nodes(), (const T *)b, x, C.nrow, C.d_mptr, C.d_mem,
                                           (T *)C.b, sc, bt, c->stream, xc, dc, c0));
         return;
     }
@@ -666,10 +670,10 @@ bool vcycle(Ctx *c, const TR *r, T *z, const Scal *sc, int nb, const CycleDots *
     return dots != nullptr;
 }
 
-void finish(Ctx *c, int n, int mode, Scal *sc, int max_iter, int nb = 1)
+void finish(Ctx *c, int n, int mode, Scal *sc, int max_iter, int nb = 1, Scal *mirror = nullptr)
 {
     TScope ts(c, SPFD_K_FINISH, nb * (double)n * 8.0 * (mode == FIN_BETA ? 2 : 1));
-    HIPCHK(launch_finish(c->d_part, n, mode, sc, max_iter, c->stream, nullptr, nullptr, 0, nb, c->pstride));
+    HIPCHK(launch_finish(c->d_part, n, mode, sc, max_iter, c->stream, nullptr, nullptr, 0, nb, c->pstride, mirror));
 }
 
 void set_defaults(spfd_amg_options &o)
@@ -975,7 +979,11 @@ spfd_status do_set_num_rhs(Ctx *c, int nrhs)
     if (c->h_ring) (void)hipHostFree(c->h_ring);
     c->h_ring = nullptr;
     HIPCHK(hipHostMalloc((void **)&c->h_scal, sizeof(Scal) * (nrhs + 1), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void **)&c->h_ring, sizeof(Scal) * 2 * (nrhs + 1), hipHostMallocDefault));
+    // coherent: the step's last kernel stores the scalars here, the host reads them after an event
+    HIPCHK(hipHostMalloc((void **)&c->h_ring, sizeof(Scal) * 2 * (nrhs + 1),
+                         hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void **)&c->h_ring_dev, c->h_ring, 0));
+    drop_graphs(c);
     c->nrhs = nrhs;
     alloc_cycle_buffers(c, nrhs);
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -993,7 +1001,7 @@ void pcg_begin(Ctx *c, Scal *sc, int nb)
     const Batch bt = level_batch(c, 0, nb);
     T *z = (T *)c->d_z;
     const double n0 = (double)L0.dofs * nb;
-    CycleDots dots{c->d_r, c->d_q, c->d_part};
+    CycleDots dots{c->d_q, c->d_part};
     if (vcycle<T, double>(c, c->d_r, z, sc, nb, &dots)) {
         finish(c, cheb_dot_parts<T>(topo.nb), FIN_BETA0, sc, 0, nb);
         return;
@@ -1032,17 +1040,17 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
     }
     finish(c, topo.nb, FIN_RR, sc, max_iter, nb);
     // z = B r, with the dot products z.r and z.q formed by the cycle's last step
-    CycleDots dots{c->d_r, c->d_q, c->d_part};
+    CycleDots dots{c->d_q, c->d_part};
     const bool fused = r32 ? vcycle<T, float>(c, r32, z, sc, nb, &dots) : vcycle<T, double>(c, c->d_r, z, sc, nb, &dots);
     if (fused) {
-        finish(c, cheb_dot_parts<T>(topo.nb), FIN_BETA, sc, 0, nb);
+        finish(c, cheb_dot_parts<T>(topo.nb), FIN_BETA, sc, 0, nb, c->step_mirror);
         return;
     }
     {
         TScope ts(c, SPFD_K_DOTS, n0 * (wz + 16.0));
         HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 0, bt, c->stream));
     }
-    finish(c, topo.nb, FIN_BETA, sc, 0, nb);
+    finish(c, topo.nb, FIN_BETA, sc, 0, nb, c->step_mirror);
 }
 
 void pcg_end(Ctx *c, Scal *sc, int nb)
@@ -1080,20 +1088,28 @@ void drop_graphs(Ctx *c)
     c->sg_max_iter = -1;
 }
 
-// Enqueue CG step `it` (and the copy of the scalars to hsc).  Steps after the
-// first have fixed kernel arguments per buffer parity, so they are captured
-// once into a HIP graph and replayed: one host call instead of some fifty
-// launches, which keeps the short coarse-level kernels back to back.  The
-// first step, eager solves and the step sampled by the launch timing run
-// eagerly.  The graphs hold no memset nodes.
+// Enqueue CG step `it`; its last kernel also stores the scalars into hsc (a
+// slot of the pinned ring).  Steps after the first have fixed kernel
+// arguments per buffer parity, so they are captured once into a HIP graph and
+// replayed: one host call instead of some fifty launches, which keeps the
+// short coarse-level kernels back to back.  The first step, eager solves and
+// the step sampled by the launch timing run eagerly.  The graphs hold no
+// memset nodes.
 void pcg_step_enqueue(Ctx *c, Scal *sc, Scal *hsc, int nb, int it, int max_iter, bool eager)
 {
+    if (!c->h_ring || hsc < c->h_ring || hsc + nb > c->h_ring + 2 * (c->nrhs + 1))
+        throw HipFail{hipErrorInvalidValue, "CG step scalars outside the pinned ring"};
+    Scal *mirror = c->h_ring_dev + (hsc - c->h_ring);
+    struct MirrorScope {
+        Ctx *c;
+        MirrorScope(Ctx *c_, Scal *m) : c(c_) { c->step_mirror = m; }
+        ~MirrorScope() { c->step_mirror = nullptr; }
+    } ms(c, mirror);
     const bool timed_sample = c->tmask != 0 && it == 1;
     if (eager || it == 0 || timed_sample) {
         c->step_ctx = timed_sample ? 2 : 1;
         pcg_step_any(c, sc, nb, it, max_iter);
         c->step_ctx = 0;
-        HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
         return;
     }
     if (c->sg_nb != nb || c->sg_sc != sc || c->sg_max_iter != max_iter) {
@@ -1103,14 +1119,18 @@ void pcg_step_enqueue(Ctx *c, Scal *sc, Scal *hsc, int nb, int it, int max_iter,
         c->sg_max_iter = max_iter;
     }
     Ctx::StepGraph &g = c->sg[it & 1];
+    if (g.exec && g.mirror != mirror) {
+        (void)hipGraphExecDestroy(g.exec);
+        g = Ctx::StepGraph{};
+    }
     if (!g.exec) {
         g = Ctx::StepGraph{};
+        g.mirror = mirror;
         hipGraph_t graph = nullptr;
         HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         c->capturing = &g;
         try {
             pcg_step_any(c, sc, nb, it, max_iter);
-            HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
         } catch (...) {
             c->capturing = nullptr;
             (void)hipStreamEndCapture(c->stream, &graph);
@@ -1132,8 +1152,14 @@ void pcg_step_enqueue(Ctx *c, Scal *sc, Scal *hsc, int nb, int it, int max_iter,
 
 // Host loop of the CG iterations, one step ahead: step it+1 is enqueued before
 // the host waits for the scalars of step it, so the GPU never idles on the
-// host's poll.  When step it converged, the already enqueued step it+1 finds
-// the stop flag and writes nothing (its loads are the only cost).
+// host's poll.  When step it converged, an already enqueued step it+1 finds
+// the stop flag and writes nothing, but its kernels still launch and load.
+// So when the residual history predicts that step it is the last one (the
+// ratio of the last two ||r||^2 carried one step further reaches the
+// tolerance within a margin), step it+1 is held back until step it is seen:
+// a wrong guess costs the host's round trip, a right one saves a whole step.
+constexpr double HOLD_MARGIN = 4.0;
+
 void pcg_iterations(Ctx *c, Scal *sc, int nb, const spfd_solve_options &so)
 {
     Scal *ring[2] = {c->h_ring, c->h_ring + nb};
@@ -1141,16 +1167,46 @@ void pcg_iterations(Ctx *c, Scal *sc, int nb, const spfd_solve_options &so)
     c->step_ctx = 1;
     pcg_begin_any(c, sc, nb);
     c->step_ctx = 0;
-    pcg_step_enqueue(c, sc, ring[0], nb, 0, so.max_iter, eager);
-    HIPCHK(hipEventRecord(c->ev_it[0], c->stream));
+    auto enqueue = [&](int k) {
+        pcg_step_enqueue(c, sc, ring[k & 1], nb, k, so.max_iter, eager);
+        HIPCHK(hipEventRecord(c->ev_it[k & 1], c->stream));
+    };
+    // ||r||^2 after the last two steps seen by the host (< 0: not seen yet)
+    std::vector<double> rr1(nb, -1.0), rr2(nb, -1.0), tol2(nb, 0.0);
+    std::vector<int> seen_done(nb, 0);
+    int seen_iters = 0;
+    auto likely_last = [&]() {
+        if (seen_iters + 1 >= so.max_iter) return true;
+        for (int i = 0; i < nb; ++i) {
+            if (seen_done[i]) continue;
+            if (!(rr1[i] > 0.0 && rr2[i] > 0.0)) return false;
+            const double next = rr1[i] * (rr1[i] / rr2[i]);
+            if (!(next <= HOLD_MARGIN * tol2[i])) return false;
+        }
+        return true;
+    };
+    enqueue(0);
+    int queued = 0;
     for (int it = 0; it <= so.max_iter; ++it) {
-        if (it + 1 <= so.max_iter) {
-            pcg_step_enqueue(c, sc, ring[(it + 1) & 1], nb, it + 1, so.max_iter, eager);
-            HIPCHK(hipEventRecord(c->ev_it[(it + 1) & 1], c->stream));
+        if (queued < it) {
+            enqueue(it);
+            queued = it;
+        }
+        if (it + 1 <= so.max_iter && !likely_last()) {
+            enqueue(it + 1);
+            queued = it + 1;
         }
         HIPCHK(hipEventSynchronize(c->ev_it[it & 1]));
+        const Scal *hs = ring[it & 1];
         bool all = true;
-        for (int i = 0; i < nb; ++i) all = all && ring[it & 1][i].done;
+        for (int i = 0; i < nb; ++i) {
+            all = all && hs[i].done;
+            seen_done[i] = hs[i].done;
+            rr2[i] = rr1[i];
+            rr1[i] = hs[i].rr;
+            tol2[i] = hs[i].tol2;
+            seen_iters = std::max(seen_iters, hs[i].iters);
+        }
         if (all) break;
     }
     pcg_end(c, sc, nb);
@@ -1692,6 +1748,20 @@ spfd_status spfd_get_info(spfd_handle h, long long *n_dofs, int *n_components, i
     if (n_components) *n_components = h->ncomp;
     if (n_levels) *n_levels = (int)h->lv.size();
     if (device_bytes) *device_bytes = h->bytes;
+    return SPFD_OK;
+}
+
+spfd_status spfd_level_info(spfd_handle h, int level, int *kind, long long *unknowns, long long *slots,
+                            int *row_entries)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (h->state < 3) return fail(h, SPFD_BAD_STATE, "build first");
+    if (level < 0 || level >= (int)h->lv.size()) return fail(h, SPFD_INVALID_ARG, "level out of range");
+    const Level &L = h->lv[level];
+    if (kind) *kind = L.ell ? 1 : 0;
+    if (unknowns) *unknowns = L.ell ? (long long)L.nrow : L.dofs;
+    if (slots) *slots = L.nodes();
+    if (row_entries) *row_entries = L.ell ? 1 + L.K : 7;
     return SPFD_OK;
 }
 

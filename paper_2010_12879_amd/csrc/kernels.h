@@ -105,9 +105,12 @@ enum {
     FIN_RESID1 = 6,   // true ||b - A x||^2 at the end of a solve (kept in zq)
     FIN_MEAN = 7      // mean of one component
 };
+// mirror != nullptr: the scalars of right side i are also written to
+// mirror[i] (host-visible memory) when the kernel ends, also when the solve
+// had already stopped: the host reads them after the stream has passed here.
 hipError_t launch_finish(const double *part, int n, int mode, Scal *sc, int max_iter, hipStream_t s,
                          double *means = nullptr, const int *counts = nullptr, int comp = 0, int nbatch = 1,
-                         int ps = 0);
+                         int ps = 0, Scal *mirror = nullptr);
 
 template <typename T>
 hipError_t launch_fill(T *x, long long n, T v, hipStream_t s);
@@ -183,14 +186,13 @@ hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, 
 // xc != nullptr: xin is first corrected by pscale * P xc from the structured
 // coarser level (parent_slot / fcoord of this level), i.e. the prolongation
 // fused into the step.  dot_part != nullptr: the step also writes the
-// partials of xout.dot_r (dot_part[g]) and xout.dot_q (dot_part[n + g]),
+// partials of xout.b (dot_part[g]) and xout.dot_q (dot_part[n + g]),
 // n = cheb_dot_parts<T>(nb), for the outer CG.
 template <typename T, typename TB>
 hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din,
                             T *dout, T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s,
                             const T *xc = nullptr, const int *parent_slot = nullptr, const int4 *fcoord = nullptr,
-                            T pscale = T(0), const double *dot_r = nullptr, const double *dot_q = nullptr,
-                            double *dot_part = nullptr);
+                            T pscale = T(0), const double *dot_q = nullptr, double *dot_part = nullptr);
 template <typename T>
 int cheb_dot_parts(int nb);
 // xc != nullptr: also the coarse level's first Chebyshev step, xc = c0 dinv_c bc
@@ -261,10 +263,10 @@ template <typename T>
 hipError_t launch_ell_cheb_step(int n, int K, const int *col, const T *val, const T *b, const T *xin, T *xout,
                                 const T *din, T *dout, T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s,
                                 const int *agg = nullptr, const T *xc = nullptr, T scale = T(0));
-// b_c = P^T (b - A x) onto an ELL level: r (nrows per right side) receives the fine residual;
+// b_c = P^T (b - A x) onto an ELL level (nrows rows of the finer level, nc aggregates);
 // xc != nullptr: also the coarse level's first Chebyshev step, xc = c0 dinv_c b_c
 template <typename T>
-hipError_t launch_restrict_members(const FineLevelT<T> &f, long long nrows, const T *b, const T *x, T *r, int nc,
+hipError_t launch_restrict_members(const FineLevelT<T> &f, long long nrows, const T *b, const T *x, int nc,
                                    const int *mptr, const int *mem, T *bc, const Scal *sc, const Batch &bt,
                                    hipStream_t s, T *xc = nullptr, const T *dinv_c = nullptr, T c0 = T(0));
 // inverse diagonals (0 where the diagonal vanishes): ELL level, structured level

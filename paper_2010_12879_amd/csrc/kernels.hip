@@ -823,14 +823,23 @@ __device__ __forceinline__ double block_sum_any(double v, double *lds)
     return s;
 }
 
+__device__ __forceinline__ void store_mirror(Scal *mirror, const Scal *sc)
+{
+    if (mirror) mirror[blockIdx.x] = *sc;
+}
+
 __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part, int n, int mode, Scal *sc,
-                                                 int max_iter, double *means, const int *counts, int comp, int ps)
+                                                 int max_iter, double *means, const int *counts, int comp, int ps,
+                                                 Scal *mirror)
 {
     __shared__ double red[16];
     part += (long long)blockIdx.x * ps;
     if (sc) sc += blockIdx.x;
     if (mode == FIN_ALPHA || mode == FIN_RR || mode == FIN_BETA0 || mode == FIN_BETA)
-        if (sc->done) return;
+        if (sc->done) {
+            if (threadIdx.x == 0) store_mirror(mirror, sc);
+            return;
+        }
     // four independent loads in flight per thread and round (fixed order: deterministic)
     const int nt = blockDim.x;
     double a = 0.0, b = 0.0;
@@ -905,12 +914,15 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
         means[comp] = counts[comp] > 0 ? a / (double)counts[comp] : 0.0;
         break;
     }
+    if (sc) store_mirror(mirror, sc);
 }
 
 hipError_t launch_finish(const double *part, int n, int mode, Scal *sc, int max_iter, hipStream_t s, double *means,
-                         const int *counts, int comp, int nbatch, int ps)
+                         const int *counts, int comp, int nbatch, int ps, Scal *mirror)
 {
-    SPFD_LAUNCH(k_finish, dim3(nbatch), dim3(1024), 0, s, part, n, mode, sc, max_iter, means, counts, comp, ps);
+    if (mirror && !sc) return hipErrorInvalidValue;
+    SPFD_LAUNCH(k_finish, dim3(nbatch), dim3(1024), 0, s, part, n, mode, sc, max_iter, means, counts, comp, ps,
+                mirror);
     return hipGetLastError();
 }
 

@@ -2,12 +2,22 @@
 //
 // One wave owns a column segment of a brick: lane (tx, ty) = (lane & 7,
 // lane >> 3) holds the nodes (tx, ty, z0 .. z0+ZPL-1) in registers.  The z
-// neighbours of a node come from the lane's own registers, the four lateral
-// neighbours are plain loads (cache hits inside the brick), and every load of
-// the wave is independent of the others, so a wave has all of them in flight
-// at once.  The stencil needs no workgroup barrier: this is what keeps HBM
-// busy (a 512-thread brick workgroup with a barrier holds too few bytes in
-// flight per compute unit for the latency of HBM3E).
+// neighbours of a node come from the lane's own registers.  The lateral
+// neighbours come in one of two ways (PERM):
+//  * loads (false): four more column loads per lane, cache hits inside the
+//    brick;
+//  * permutes (true): the lanes l-1, l+1, l-8, l+8 hold the neighbours inside
+//    the brick (cross-lane permutes, no memory access), and only the lanes on
+//    an x or y face of the brick load one extra column from the neighbour
+//    brick.  This frees registers and cache bandwidth; it pays for FP32 values
+//    (one permute per neighbour) and not for FP64 ones next to the LDS reads
+//    of the conductivity planes (measured).
+// Every load of the wave is independent of the others, so a wave has all of
+// them in flight at once.  The stencil needs no workgroup barrier: this is
+// what keeps HBM busy (a 512-thread brick workgroup with a barrier holds too
+// few bytes in flight per compute unit for the latency of HBM3E).  The
+// permutes need all 64 lanes: the stencil loops run in wave-uniform control
+// flow and only the stores depend on the lane.
 //
 // Operator forms (Eq. (3), the matrix G^T M_sigma G):
 //  * label form (finest level): the conductivities of the voxel planes the
@@ -38,9 +48,16 @@ __device__ __forceinline__ bool col_stopped(const Scal *sc)
     return sc && __hip_atomic_load(&sc[blockIdx.y].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// value of v in lane `src` of the wave (src taken modulo 64)
+template <typename T>
+__device__ __forceinline__ T lane_get(T v, int src)
+{
+    return __shfl(v, src & 63, 64);
+}
+
 // Where a wave's segment lies.  Absent neighbour bricks hold no unknowns and
-// the edges into them have conductance 0; their slots are replaced by slots
-// of the lane's own column so that every lane issues the same loads.
+// the edges into them have conductance 0: their values are never loaded and
+// read as 0.  Columns without unknowns likewise read as 0.
 template <int ZPL>
 struct Seg {
     static constexpr int WPB = 8 / ZPL;           // waves per brick
@@ -49,9 +66,11 @@ struct Seg {
     int grp;                                      // brick group of the workgroup (-1: padding)
     int z0, lane, tx, ty;
     long long self;                               // slot of (tx, ty, z0)
-    long long lat[4];                             // x-, x+, y-, y+ neighbours of (tx, ty, z0)
+    long long xe, ye;                             // lanes with tx = 0 or 7 (ty = 0 or 7): slot of the x (y)
+                                                  // neighbour of (tx, ty, z0) in the next brick
     long long zm, zp;                             // (tx, ty, z0-1) and (tx, ty, z0+ZPL)
     bool has[6];                                  // neighbour slot exists
+    bool bx, by;                                  // xe (ye) is to be read: face lane, neighbour brick present
     bool active;                                  // the lane's node column holds an unknown
 };
 
@@ -88,10 +107,12 @@ __device__ __forceinline__ Seg<ZPL> make_seg(const Topo &topo)
     s.has[NPX] = s.tx < 7 || nb[NPX] >= 0;
     s.has[NMY] = s.ty > 0 || nb[NMY] >= 0;
     s.has[NPY] = s.ty < 7 || nb[NPY] >= 0;
-    s.lat[0] = s.tx > 0 ? s.self - 1 : (nb[NMX] >= 0 ? (long long)nb[NMX] * BS + t0 + 7 : s.self);
-    s.lat[1] = s.tx < 7 ? s.self + 1 : (nb[NPX] >= 0 ? (long long)nb[NPX] * BS + t0 - 7 : s.self);
-    s.lat[2] = s.ty > 0 ? s.self - 8 : (nb[NMY] >= 0 ? (long long)nb[NMY] * BS + t0 + 56 : s.self);
-    s.lat[3] = s.ty < 7 ? s.self + 8 : (nb[NPY] >= 0 ? (long long)nb[NPY] * BS + t0 - 56 : s.self);
+    const int ex = s.tx == 0 ? nb[NMX] : (s.tx == 7 ? nb[NPX] : -1);
+    const int ey = s.ty == 0 ? nb[NMY] : (s.ty == 7 ? nb[NPY] : -1);
+    s.bx = ex >= 0;
+    s.by = ey >= 0;
+    s.xe = s.bx ? (long long)ex * BS + t0 + (s.tx == 0 ? 7 : -7) : s.self;
+    s.ye = s.by ? (long long)ey * BS + t0 + (s.ty == 0 ? 56 : -56) : s.self;
     if (s.z0 > 0) {
         s.has[NMZ] = true;
         s.zm = s.self - 64;
@@ -109,6 +130,19 @@ __device__ __forceinline__ Seg<ZPL> make_seg(const Topo &topo)
     return s;
 }
 
+// slot of the lateral neighbour k (x-, x+, y-, y+) of (tx, ty, z0); an absent
+// neighbour brick gives the lane's own slot (edge conductance 0)
+template <int ZPL>
+__device__ __forceinline__ long long lat_slot(const Seg<ZPL> &s, int k)
+{
+    switch (k) {
+    case 0: return s.tx > 0 ? s.self - 1 : s.xe;
+    case 1: return s.tx < 7 ? s.self + 1 : s.xe;
+    case 2: return s.ty > 0 ? s.self - 8 : s.ye;
+    default: return s.ty < 7 ? s.self + 8 : s.ye;
+    }
+}
+
 // LDS per wave of the label form: sigma table copy + sigma of ZPL+1 voxel planes
 template <typename T, int ZPL>
 struct ColLds {
@@ -116,13 +150,13 @@ struct ColLds {
     static constexpr int PER_WAVE = MAX_LABELS + ((NE + 3) & ~3);
 };
 
-template <typename T, int ZPL, bool LABEL>
+template <typename T, int ZPL, bool LABEL, bool PERM>
 struct SegOp;
 
 // Label form.  Plane c of the wave holds the voxels of tile plane z0 + c
 // (tile plane k = voxel layer below node layer k of the brick).
-template <typename T, int ZPL>
-struct SegOp<T, ZPL, true> {
+template <typename T, int ZPL, bool PERM>
+struct SegOp<T, ZPL, true, PERM> {
     static constexpr int NE = ColLds<T, ZPL>::NE;
     static constexpr int NWD = (NE + 3) / 4;      // label dwords (81 z0 is a multiple of 4)
     static constexpr int NLD = (NWD + 63) / 64;
@@ -189,62 +223,118 @@ struct SegOp<T, ZPL, true> {
     }
 };
 
-// Stored form: w[d*stride + n] = conductance of the edge from n to +d.
-template <typename T, int ZPL>
-struct SegOp<T, ZPL, false> {
+// Stored form: w[d*stride + n] = conductance of the edge from n to +d; the
+// minus-side weights are the plus-side weights of the minus neighbours, loaded
+// (PERM false) or, inside the brick, taken from lanes l-1 and l-8 with the
+// lanes on the minus faces loading them from the neighbour brick (PERM true).
+// Columns without unknowns read as 0 (every edge at such a node has
+// conductance 0).
+template <typename T, int ZPL, bool PERM>
+struct SegOp<T, ZPL, false, PERM> {
     T wp[3][ZPL], wmx[ZPL], wmy[ZPL], wmz;
 
     __device__ __forceinline__ void load(const OpArgs<T> &op, const Seg<ZPL> &s, T *)
     {
         const T *w = op.w;
         const long long st = op.stride;
+        const bool mx = s.active && (PERM ? s.bx && s.tx == 0 : s.has[NMX]);
+        const bool my = s.active && (PERM ? s.by && s.ty == 0 : s.has[NMY]);
+        const long long ax = PERM ? s.xe : lat_slot(s, 0), ay = PERM ? s.ye : lat_slot(s, 2);
 #pragma unroll
         for (int z = 0; z < ZPL; ++z) {
-            wp[0][z] = w[s.self + 64 * z];
-            wp[1][z] = w[st + s.self + 64 * z];
-            wp[2][z] = w[2 * st + s.self + 64 * z];
-            wmx[z] = w[s.lat[0] + 64 * z];
-            wmy[z] = w[st + s.lat[2] + 64 * z];
+            wp[0][z] = s.active ? w[s.self + 64 * z] : T(0);
+            wp[1][z] = s.active ? w[st + s.self + 64 * z] : T(0);
+            wp[2][z] = s.active ? w[2 * st + s.self + 64 * z] : T(0);
+            wmx[z] = mx ? w[ax + 64 * z] : T(0);
+            wmy[z] = my ? w[st + ay + 64 * z] : T(0);
         }
-        wmz = w[2 * st + s.zm];
+        wmz = s.active && s.has[NMZ] ? w[2 * st + s.zm] : T(0);
     }
 
     __device__ __forceinline__ void stage(const OpArgs<T> &, const Seg<ZPL> &) {}
 
+    // with PERM, all 64 lanes of the wave must call this
     __device__ __forceinline__ void weights(const Seg<ZPL> &s, int z, T W[6])
     {
         W[NPX] = wp[0][z];
         W[NPY] = wp[1][z];
         W[NPZ] = wp[2][z];
-        W[NMX] = s.has[NMX] ? wmx[z] : T(0);
-        W[NMY] = s.has[NMY] ? wmy[z] : T(0);
-        W[NMZ] = z > 0 ? wp[2][z - 1] : (s.has[NMZ] ? wmz : T(0));
+        if constexpr (PERM) {
+            const T mx = lane_get(wp[0][z], s.lane - 1), my = lane_get(wp[1][z], s.lane - 8);
+            W[NMX] = s.tx > 0 ? mx : wmx[z];
+            W[NMY] = s.ty > 0 ? my : wmy[z];
+        } else {
+            W[NMX] = wmx[z];
+            W[NMY] = wmy[z];
+        }
+        W[NMZ] = z > 0 ? wp[2][z - 1] : wmz;
     }
 };
 
-// values of x along the segment, its four lateral neighbour columns and the two z ends
+template <typename T, int ZPL, bool PERM>
+struct SegVals;
+
+// values of x along the segment, its four lateral neighbour columns and the
+// two z ends
 template <typename T, int ZPL>
-struct SegVals {
+struct SegVals<T, ZPL, false> {
     T c[ZPL], l[4][ZPL], zm, zp;
 
+    // a lane of a column without unknowns loads nothing: no other lane reads its values
     __device__ __forceinline__ void load(const T *__restrict__ x, const Seg<ZPL> &s)
     {
+        if (!s.active) return;
+        long long a[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] = lat_slot(s, k);
 #pragma unroll
         for (int z = 0; z < ZPL; ++z) {
             c[z] = x[s.self + 64 * z];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) l[k][z] = x[s.lat[k] + 64 * z];
+            for (int k = 0; k < 4; ++k) l[k][z] = x[a[k] + 64 * z];
         }
         zm = x[s.zm];
         zp = x[s.zp];
     }
 
-    __device__ __forceinline__ void nbrs(int z, T N[6]) const
+    __device__ __forceinline__ void nbrs(const Seg<ZPL> &, int z, T N[6]) const
     {
         N[NMX] = l[0][z];
         N[NPX] = l[1][z];
         N[NMY] = l[2][z];
         N[NPY] = l[3][z];
+        N[NMZ] = z > 0 ? c[z - 1] : zm;
+        N[NPZ] = z < ZPL - 1 ? c[z + 1] : zp;
+    }
+};
+
+// values of x along the segment, the face lanes' columns in the neighbour
+// bricks (ex, ey) and the two z ends; 0 where nothing is to be read
+template <typename T, int ZPL>
+struct SegVals<T, ZPL, true> {
+    T c[ZPL], ex[ZPL], ey[ZPL], zm, zp;
+
+    __device__ __forceinline__ void load(const T *__restrict__ x, const Seg<ZPL> &s)
+    {
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) {
+            c[z] = s.active ? x[s.self + 64 * z] : T(0);
+            ex[z] = s.active && s.bx ? x[s.xe + 64 * z] : T(0);
+            ey[z] = s.active && s.by ? x[s.ye + 64 * z] : T(0);
+        }
+        zm = s.active && s.has[NMZ] ? x[s.zm] : T(0);
+        zp = s.active && s.has[NPZ] ? x[s.zp] : T(0);
+    }
+
+    // the six neighbours of node z0+z; all 64 lanes of the wave must call this
+    __device__ __forceinline__ void nbrs(const Seg<ZPL> &s, int z, T N[6]) const
+    {
+        const T xm = lane_get(c[z], s.lane - 1), xp = lane_get(c[z], s.lane + 1);
+        const T ym = lane_get(c[z], s.lane - 8), yp = lane_get(c[z], s.lane + 8);
+        N[NMX] = s.tx > 0 ? xm : ex[z];
+        N[NPX] = s.tx < 7 ? xp : ex[z];
+        N[NMY] = s.ty > 0 ? ym : ey[z];
+        N[NPY] = s.ty < 7 ? yp : ey[z];
         N[NMZ] = z > 0 ? c[z - 1] : zm;
         N[NPZ] = z < ZPL - 1 ? c[z + 1] : zp;
     }
@@ -261,6 +351,10 @@ __device__ __forceinline__ T *col_lds()
     }
 }
 
+// neighbour access of the cycle kernels (see the top of this file)
+template <typename T>
+constexpr bool perm_cycle() { return sizeof(T) == 4; }
+
 // ---------------------------------------------------------------- Chebyshev smoothing
 // first step from a zero start: x = c0 D^-1 b (0 where D = 0)
 template <typename T, typename TB, int ZPL, bool LABEL>
@@ -273,26 +367,28 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo 
     const bool done = col_stopped(sc);
     b += blockIdx.y * vs;
     x += blockIdx.y * vs;
-    SegOp<T, ZPL, LABEL> A;
-    if (LABEL || s.active) A.load(op, s, lds);
+    SegOp<T, ZPL, LABEL, perm_cycle<T>()> A;
+    A.load(op, s, lds);
     T bv[ZPL];
-    if (s.active)
 #pragma unroll
-        for (int z = 0; z < ZPL; ++z) bv[z] = (T)b[s.self + 64 * z];
+    for (int z = 0; z < ZPL; ++z) bv[z] = s.active ? (T)b[s.self + 64 * z] : T(0);
     A.stage(op, s);
-    if (done || !s.active) return;
+    if (done) return;
 #pragma unroll
     for (int z = 0; z < ZPL; ++z) {
         T W[6];
         A.weights(s, z, W);
         const T D = diag_of(W);
-        x[s.self + 64 * z] = D > T(0) ? c0 * bv[z] / D : T(0);
+        if (s.active) x[s.self + 64 * z] = D > T(0) ? c0 * bv[z] / D : T(0);
     }
 }
 
 // Coarse-grid correction of a structured level, x += scale * P x_c, applied
 // to the values a segment reads: the coarse node of fine node (tx,ty,tz) of
 // brick b is node (4 (f.x & 1) + tx/2, ...) of the parent brick, f = coord of b.
+// (From an unstructured coarser level the correction is a kernel of its own:
+// fused here, its dependent index and gather loads made the step slower than
+// the two kernels, measured.)
 struct Prolong {
     const void *xc;
     const int *parent_slot;
@@ -308,39 +404,60 @@ __device__ __forceinline__ long long coarse_slot(const Prolong &pr, int b, int t
            64 * ((f.z & 1) * 4 + (tz >> 1));
 }
 
-template <typename T, int ZPL>
+template <typename T, int ZPL, bool PERM>
 __device__ __forceinline__ void apply_prolong(const Prolong &pr, const Topo &topo, const Seg<ZPL> &s,
-                                              SegVals<T, ZPL> &X)
+                                              SegVals<T, ZPL, PERM> &X)
 {
+    if (!s.active) return;
     const T *xc = (const T *)pr.xc + blockIdx.y * pr.vsc;
     const T sc = (T)pr.scale;
     int nb[6];
     brick_nbrs(topo.nbr, s.bk, nb);
     const int tx = s.tx, ty = s.ty, z0 = s.z0;
-    // the brick and local node of every column the segment reads (absent -> own column)
-    long long cs[5];
-    cs[0] = coarse_slot(pr, s.bk, tx, ty, z0);
-    cs[1] = tx > 0 ? coarse_slot(pr, s.bk, tx - 1, ty, z0) : (nb[NMX] >= 0 ? coarse_slot(pr, nb[NMX], 7, ty, z0) : cs[0]);
-    cs[2] = tx < 7 ? coarse_slot(pr, s.bk, tx + 1, ty, z0) : (nb[NPX] >= 0 ? coarse_slot(pr, nb[NPX], 0, ty, z0) : cs[0]);
-    cs[3] = ty > 0 ? coarse_slot(pr, s.bk, tx, ty - 1, z0) : (nb[NMY] >= 0 ? coarse_slot(pr, nb[NMY], tx, 7, z0) : cs[0]);
-    cs[4] = ty < 7 ? coarse_slot(pr, s.bk, tx, ty + 1, z0) : (nb[NPY] >= 0 ? coarse_slot(pr, nb[NPY], tx, 0, z0) : cs[0]);
+    // coarse slots of the lane's own column and of the two z ends (absent -> own column, never read)
+    const long long c0 = coarse_slot(pr, s.bk, tx, ty, z0);
     const long long czm = z0 > 0 ? coarse_slot(pr, s.bk, tx, ty, z0 - 1)
-                                 : (nb[NMZ] >= 0 ? coarse_slot(pr, nb[NMZ], tx, ty, 7) : cs[0]);
+                                 : (nb[NMZ] >= 0 ? coarse_slot(pr, nb[NMZ], tx, ty, 7) : c0);
     const int ze = z0 + ZPL;
-    const long long czp = ze < 8 ? coarse_slot(pr, s.bk, tx, ty, ze)
-                                 : (nb[NPZ] >= 0 ? coarse_slot(pr, nb[NPZ], tx, ty, 0) : cs[0] + 64 * ((ZPL - 1) >> 1));
-    T v[5][ZPL / 2];
+    const long long czp = ze < 8 ? coarse_slot(pr, s.bk, tx, ty, ze) : (nb[NPZ] >= 0 ? coarse_slot(pr, nb[NPZ], tx, ty, 0) : c0);
+    T v0[ZPL / 2];
 #pragma unroll
-    for (int k = 0; k < 5; ++k)
+    for (int h = 0; h < ZPL / 2; ++h) v0[h] = xc[c0 + 64 * h];
+    const T vm = s.has[NMZ] ? xc[czm] : T(0), vp = s.has[NPZ] ? xc[czp] : T(0);
+    if constexpr (PERM) {
+        // the face column in the x (y) neighbour brick
+        const long long cx = s.bx ? coarse_slot(pr, tx == 0 ? nb[NMX] : nb[NPX], tx == 0 ? 7 : 0, ty, z0) : c0;
+        const long long cy = s.by ? coarse_slot(pr, ty == 0 ? nb[NMY] : nb[NPY], tx, ty == 0 ? 7 : 0, z0) : c0;
+        T vx[ZPL / 2], vy[ZPL / 2];
 #pragma unroll
-        for (int h = 0; h < ZPL / 2; ++h) v[k][h] = xc[cs[k] + 64 * h];
-    const T vm = xc[czm], vp = xc[czp];
+        for (int h = 0; h < ZPL / 2; ++h) {
+            vx[h] = s.bx ? xc[cx + 64 * h] : T(0);
+            vy[h] = s.by ? xc[cy + 64 * h] : T(0);
+        }
 #pragma unroll
-    for (int z = 0; z < ZPL; ++z) {
-        X.c[z] += sc * v[0][z >> 1];
+        for (int z = 0; z < ZPL; ++z) {
+            X.ex[z] += sc * vx[z >> 1];
+            X.ey[z] += sc * vy[z >> 1];
+        }
+    } else {
+        // the four lateral columns
+        long long cl[4];
+        cl[0] = tx > 0 ? coarse_slot(pr, s.bk, tx - 1, ty, z0) : (nb[NMX] >= 0 ? coarse_slot(pr, nb[NMX], 7, ty, z0) : c0);
+        cl[1] = tx < 7 ? coarse_slot(pr, s.bk, tx + 1, ty, z0) : (nb[NPX] >= 0 ? coarse_slot(pr, nb[NPX], 0, ty, z0) : c0);
+        cl[2] = ty > 0 ? coarse_slot(pr, s.bk, tx, ty - 1, z0) : (nb[NMY] >= 0 ? coarse_slot(pr, nb[NMY], tx, 7, z0) : c0);
+        cl[3] = ty < 7 ? coarse_slot(pr, s.bk, tx, ty + 1, z0) : (nb[NPY] >= 0 ? coarse_slot(pr, nb[NPY], tx, 0, z0) : c0);
+        T vl[4][ZPL / 2];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) X.l[k][z] += sc * v[k + 1][z >> 1];
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int h = 0; h < ZPL / 2; ++h) vl[k][h] = xc[cl[k] + 64 * h];
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) X.l[k][z] += sc * vl[k][z >> 1];
     }
+#pragma unroll
+    for (int z = 0; z < ZPL; ++z) X.c[z] += sc * v0[z >> 1];
     X.zm += sc * vm;
     X.zp += sc * vp;
 }
@@ -349,7 +466,6 @@ __device__ __forceinline__ void apply_prolong(const Prolong &pr, const Topo &top
 // smoothing step: partials (one per workgroup) of z.r into part[g] and of
 // z.q into part[nparts + g], z being the step's output.
 struct Dots {
-    const double *r;
     const double *q;
     double *part;
     int ps;        // partial stride per right side
@@ -360,7 +476,8 @@ struct Dots {
 // (d_old = xin when din == nullptr, i.e. right after a zero start).  With PRO,
 // xin is first corrected from the coarser level (the prolongation of the
 // upward leg, fused into the first post-smoothing step); with DOT the step
-// also forms the CG dot products of its output.
+// also forms the CG dot products of its output with b (the residual the
+// cycle was given, as the cycle reads it) and with q.
 template <typename T, typename TB, int ZPL, bool LABEL, bool PRO, bool DOT>
 __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
                                                             const T *__restrict__ xin, T *__restrict__ xout,
@@ -379,51 +496,50 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo t
         xout += blockIdx.y * vs;
         if (din) din += blockIdx.y * vs;
         if (dout) dout += blockIdx.y * vs;
-        SegOp<T, ZPL, LABEL> A;
-        if (LABEL || s.active) A.load(op, s, lds);
-        SegVals<T, ZPL> X;
+        SegOp<T, ZPL, LABEL, perm_cycle<T>()> A;
+        A.load(op, s, lds);
+        SegVals<T, ZPL, perm_cycle<T>()> X;
+        X.load(xin, s);
         T bv[ZPL], dv[ZPL];
-        double rv[DOT ? ZPL : 1], qv[DOT ? ZPL : 1];
+        double qv[DOT ? ZPL : 1];
         if (s.active) {
-            X.load(xin, s);
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) {
                 bv[z] = (T)b[s.self + 64 * z];
                 if (din) dv[z] = din[s.self + 64 * z];
             }
             if constexpr (DOT) {
-                const double *r = dt.r + blockIdx.y * vs, *q = dt.q + blockIdx.y * vs;
+                const double *q = dt.q + blockIdx.y * vs;
 #pragma unroll
-                for (int z = 0; z < ZPL; ++z) {
-                    rv[z] = r[s.self + 64 * z];
-                    qv[z] = q[s.self + 64 * z];
-                }
-            }
-            if constexpr (PRO) apply_prolong<T, ZPL>(pr, topo, s, X);
-            if (!din) {
-#pragma unroll
-                for (int z = 0; z < ZPL; ++z) dv[z] = X.c[z];
+                for (int z = 0; z < ZPL; ++z) qv[z] = q[s.self + 64 * z];
             }
         }
+        if constexpr (PRO) apply_prolong(pr, topo, s, X);
+        if (!din) {
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) dv[z] = X.c[z];
+        }
         A.stage(op, s);
-        if (!done && s.active) {
+        if (!done) {
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) {
                 T W[6], N[6];
                 A.weights(s, z, W);
-                X.nbrs(z, N);
+                X.nbrs(s, z, N);
                 const T D = diag_of(W);
                 T xo = T(0), dn = T(0);
-                if (D > T(0)) {
+                if (s.active && D > T(0)) {
                     const T r = bv[z] - stencil_apply(X.c[z], N, W);
                     dn = c1 * dv[z] + c2 * r / D;
                     xo = X.c[z] + dn;
                 }
-                xout[s.self + 64 * z] = xo;
-                if (dout) dout[s.self + 64 * z] = dn;
-                if constexpr (DOT) {
-                    dzr += (double)xo * rv[z];
-                    dzq += (double)xo * qv[z];
+                if (s.active) {
+                    xout[s.self + 64 * z] = xo;
+                    if (dout) dout[s.self + 64 * z] = dn;
+                    if constexpr (DOT) {
+                        dzr += (double)xo * (double)bv[z];
+                        dzq += (double)xo * qv[z];
+                    }
                 }
             }
         }
@@ -469,15 +585,13 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
     b += blockIdx.y * vs;
     x += blockIdx.y * vs;
     bc += blockIdx.y * vsc;
-    SegOp<T, ZPL, LABEL> A;
-    if (LABEL || s.active) A.load(op, s, lds);
-    SegVals<T, ZPL> X;
+    SegOp<T, ZPL, LABEL, perm_cycle<T>()> A;
+    A.load(op, s, lds);
+    SegVals<T, ZPL, perm_cycle<T>()> X;
+    X.load(x, s);
     T bv[ZPL];
-    if (s.active) {
-        X.load(x, s);
 #pragma unroll
-        for (int z = 0; z < ZPL; ++z) bv[z] = (T)b[s.self + 64 * z];
-    }
+    for (int z = 0; z < ZPL; ++z) bv[z] = s.active ? (T)b[s.self + 64 * z] : T(0);
     const int4 fc = fcoord[s.bk];
     const long long pbase = (long long)parent_slot[s.bk] * BS;
     const int ox = (fc.x & 1) * 4 + (s.tx >> 1), oy = (fc.y & 1) * 4 + (s.ty >> 1);
@@ -491,15 +605,13 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
     A.stage(op, s);
     T r[ZPL];
 #pragma unroll
-    for (int z = 0; z < ZPL; ++z) r[z] = T(0);
-    if (s.active)
-#pragma unroll
-        for (int z = 0; z < ZPL; ++z) {
-            T W[6], N[6];
-            A.weights(s, z, W);
-            X.nbrs(z, N);
-            r[z] = bv[z] - stencil_apply(X.c[z], N, W);
-        }
+    for (int z = 0; z < ZPL; ++z) {
+        T W[6], N[6];
+        A.weights(s, z, W);
+        X.nbrs(s, z, N);
+        const T rz = bv[z] - stencil_apply(X.c[z], N, W);
+        r[z] = s.active ? rz : T(0);
+    }
 #pragma unroll
     for (int k = 0; k < ZPL / 2; ++k) {
         T a = r[2 * k] + r[2 * k + 1];
@@ -543,23 +655,22 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
     part += (long long)blockIdx.y * ps;
     double dot = 0.0;
     if (s.bk >= 0) {
-        SegOp<double, ZPL, LABEL> A;
-        if (LABEL || s.active) A.load(op, s, lds);
-        SegVals<TZ, ZPL> Z;
-        SegVals<double, ZPL> Pi;
+        SegOp<double, ZPL, LABEL, false> A;
+        A.load(op, s, lds);
+        SegVals<TZ, ZPL, false> Z;
+        Z.load(zv, s);
+        SegVals<double, ZPL, false> Pi;
         double xv[ZPL];
-        if (s.active) {
-            Z.load(zv, s);
-            if (!first) {
-                Pi.load(pin, s);
+        if (!first) {
+            Pi.load(pin, s);
+            if (s.active)
 #pragma unroll
                 for (int z = 0; z < ZPL; ++z) xv[z] = x[s.self + 64 * z];
-            }
         }
         const double beta = first ? 0.0 : sc->beta;
         const double alpha = first ? 0.0 : sc->alpha;
         // p_k on the segment and its neighbours
-        SegVals<double, ZPL> P;
+        SegVals<double, ZPL, false> P;
 #pragma unroll
         for (int z = 0; z < ZPL; ++z) {
             P.c[z] = first ? (double)Z.c[z] : (double)Z.c[z] + beta * Pi.c[z];
@@ -569,12 +680,13 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
         P.zm = first ? (double)Z.zm : (double)Z.zm + beta * Pi.zm;
         P.zp = first ? (double)Z.zp : (double)Z.zp + beta * Pi.zp;
         A.stage(op, s);
+        // (load mode: no cross-lane access, lanes of empty columns skip the loop)
         if (!done && s.active) {
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) {
                 double W[6], N[6];
                 A.weights(s, z, W);
-                P.nbrs(z, N);
+                P.nbrs(s, z, N);
                 const double y = stencil_apply(P.c[z], N, W);
                 const long long n = s.self + 64 * z;
                 if (!first) x[n] = xv[z] + alpha * Pi.c[z];
@@ -610,10 +722,10 @@ __global__ __launch_bounds__(CTHREADS) void k_col_spmv(OpArgs<double> op, Topo t
     const bool done = col_stopped(sc);
     zv += blockIdx.y * vs;
     w += blockIdx.y * vs;
-    SegOp<double, ZPL, LABEL> A;
-    if (LABEL || s.active) A.load(op, s, lds);
-    SegVals<TZ, ZPL> Z;
-    if (s.active) Z.load(zv, s);
+    SegOp<double, ZPL, LABEL, false> A;
+    A.load(op, s, lds);
+    SegVals<TZ, ZPL, false> Z;
+    Z.load(zv, s);
     A.stage(op, s);
     if (done || !s.active) return;
 #pragma unroll
@@ -621,7 +733,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_spmv(OpArgs<double> op, Topo t
         double W[6], P[6];
         TZ N[6];
         A.weights(s, z, W);
-        Z.nbrs(z, N);
+        Z.nbrs(s, z, N);
 #pragma unroll
         for (int k = 0; k < 6; ++k) P[k] = (double)N[k];
         w[s.self + 64 * z] = stencil_apply((double)Z.c[z], P, W);
@@ -662,17 +774,17 @@ hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, 
 template <typename T, typename TB>
 hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din, T *dout,
                             T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s, const T *xc,
-                            const int *parent_slot, const int4 *fcoord, T pscale, const double *dot_r,
-                            const double *dot_q, double *dot_part)
+                            const int *parent_slot, const int4 *fcoord, T pscale, const double *dot_q,
+                            double *dot_part)
 {
     if (topo.nb <= 0) return hipSuccess;
     if (xin == xout) return hipErrorInvalidValue;
     if (xc && !(parent_slot && fcoord)) return hipErrorInvalidValue;
-    if (dot_part && !(dot_r && dot_q)) return hipErrorInvalidValue;
+    if (dot_part && !dot_q) return hipErrorInvalidValue;
     constexpr int ZPL = zpl_cycle<T>();
     const dim3 g = col_grid<ZPL>(topo.nb, bt.n);
     const Prolong pr{xc, parent_slot, fcoord, (double)pscale, bt.vsc};
-    const Dots dt{dot_r, dot_q, dot_part, bt.ps, col_ngroups<ZPL>(topo.nb)};
+    const Dots dt{dot_q, dot_part, bt.ps, col_ngroups<ZPL>(topo.nb)};
     const int sel = (op.w ? 0 : 4) | (xc ? 2 : 0) | (dot_part ? 1 : 0);
 #define SPFD_CHEB_CASE(K, LAB, PRO, DOT)                                                                              \
     case K:                                                                                                           \
@@ -758,8 +870,7 @@ template hipError_t launch_spmv<float>(const OpArgs<double> &, Topo, const float
                                                  const Batch &, hipStream_t);                                       \
     template hipError_t launch_cheb_step<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *, const T *, T *, \
                                                 T, T, const Scal *, const Batch &, hipStream_t, const T *,          \
-                                                const int *, const int4 *, T, const double *, const double *,        \
-                                                double *);                                                          \
+                                                const int *, const int4 *, T, const double *, double *);             \
     template hipError_t launch_resid_restrict<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *,           \
                                                      const int *, const int4 *, const Scal *, const Batch &,        \
                                                      hipStream_t, T *, const T *, T);

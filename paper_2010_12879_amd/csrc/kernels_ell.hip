@@ -465,57 +465,61 @@ __global__ void k_ell_cheb_step(int n, int K, const int *__restrict__ col, const
     }
 }
 
-// Coarse right side b_c[p] = sum over the members i of p of (b - A x)_i, in
-// two passes: the fine residual of every row in parallel (into r), then the
-// member sums (one thread per aggregate, members in list order).
+// (b - A x)_i of row i of the finer level (structured stencil or ELL rows)
 template <typename T>
-__global__ void k_resid_rows(FineLevelT<T> f, long long nrows, const T *__restrict__ b, const T *__restrict__ x,
-                             T *__restrict__ r, const Scal *sc, long long vs)
+__device__ __forceinline__ T fine_resid(const FineLevelT<T> &f, const T *__restrict__ b, const T *__restrict__ x,
+                                        long long i)
+{
+    const T xi = x[i];
+    T ax;
+    if (f.w) {
+        const int bk = (int)(i / BS), t = (int)(i % BS);
+        int tx, ty, tz;
+        brick_xyz(t, tx, ty, tz);
+        int nb[6];
+        brick_nbrs(f.nbr, bk, nb);
+        long long I[6];
+        nbr_index((long long)bk * BS, t, tx, ty, tz, nb, I);
+        T W[6], X[6];
+        stored_weights(f.w, f.stride, (long long)bk * BS, t, I, W);
+        nbr_vals(x, I, X);
+        ax = stencil_apply(xi, X, W);
+    } else {
+        T D;
+        ax = ell_row(f.n, f.K, f.col, f.val, x, (int)i, xi, D);
+    }
+    return b[i] - ax;
+}
+
+// Coarse right side b_c[p] = sum over the members i of p of (b - A x)_i.
+// Eight lanes per aggregate (an aggregate of the split 2x2x2 aggregation has
+// at most eight members): lane j forms the residuals of members j, j+8, ...
+// and the eight partial sums meet in a fixed butterfly, so the result does not
+// depend on scheduling.  With xc: also the coarse level's first Chebyshev
+// step, xc = c0 D^-1 b_c.
+constexpr int RLANES = 8;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_rows(FineLevelT<T> f, int nc, const int *__restrict__ mptr,
+                                                       const int *__restrict__ mem, const T *__restrict__ b,
+                                                       const T *__restrict__ x, T *__restrict__ bc, const Scal *sc,
+                                                       long long vs, long long vsc, T *__restrict__ xc,
+                                                       const T *__restrict__ dinv, T c0)
 {
     const bool done = ell_stopped(sc);
     b += blockIdx.y * vs;
     x += blockIdx.y * vs;
-    r += blockIdx.y * vs;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nrows;
-         i += (long long)gridDim.x * blockDim.x) {
-        const T xi = x[i];
-        T ax;
-        if (f.w) {
-            const int bk = (int)(i / BS), t = (int)(i % BS);
-            int tx, ty, tz;
-            brick_xyz(t, tx, ty, tz);
-            int nb[6];
-            brick_nbrs(f.nbr, bk, nb);
-            long long I[6];
-            nbr_index((long long)bk * BS, t, tx, ty, tz, nb, I);
-            T W[6], X[6];
-            stored_weights(f.w, f.stride, (long long)bk * BS, t, I, W);
-            nbr_vals(x, I, X);
-            ax = stencil_apply(xi, X, W);
-        } else {
-            T D;
-            ax = ell_row(f.n, f.K, f.col, f.val, x, (int)i, xi, D);
-        }
-        if (!done) r[i] = b[i] - ax;
-    }
-}
-
-// (with xc: also the coarse level's first Chebyshev step, xc = c0 D^-1 b_c)
-template <typename T>
-__global__ void k_sum_members(int nc, const int *__restrict__ mptr, const int *__restrict__ mem,
-                              const T *__restrict__ r, T *__restrict__ bc, const Scal *sc, long long vs,
-                              long long vsc, T *__restrict__ xc, const T *__restrict__ dinv, T c0)
-{
-    const bool done = ell_stopped(sc);
-    r += blockIdx.y * vs;
     bc += blockIdx.y * vsc;
     if (xc) xc += blockIdx.y * vsc;
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
+    const int j = threadIdx.x % RLANES;
+    // the eight lanes of a group share p, so they run the same rounds (the butterfly needs all of them)
+    for (int p = (blockIdx.x * blockDim.x + threadIdx.x) / RLANES; p < nc; p += gridDim.x * blockDim.x / RLANES) {
         const int q0 = mptr[p], q1 = mptr[p + 1];
         T s = T(0);
-#pragma unroll 4
-        for (int q = q0; q < q1; ++q) s += r[mem[q]];
-        if (!done) {
+        for (int q = q0 + j; q < q1; q += RLANES) s += fine_resid(f, b, x, mem[q]);
+#pragma unroll
+        for (int m = 1; m < RLANES; m <<= 1) s += __shfl_xor(s, m, RLANES);
+        if (j == 0 && !done) {
             bc[p] = s;
             if (xc) xc[p] = c0 * s * dinv[p];
         }
@@ -580,16 +584,14 @@ hipError_t launch_ell_cheb_step(int n, int K, const int *col, const T *val, cons
 }
 
 template <typename T>
-hipError_t launch_restrict_members(const FineLevelT<T> &f, long long nrows, const T *b, const T *x, T *r, int nc,
+hipError_t launch_restrict_members(const FineLevelT<T> &f, long long nrows, const T *b, const T *x, int nc,
                                    const int *mptr, const int *mem, T *bc, const Scal *sc, const Batch &bt,
                                    hipStream_t s, T *xc, const T *dinv_c, T c0)
 {
     if (nc <= 0 || nrows <= 0) return hipSuccess;
     if (xc && !dinv_c) return hipErrorInvalidValue;
-    SPFD_LAUNCH(k_resid_rows<T>, dim3(gblocks(nrows, 256), bt.n), dim3(256), 0, s, f, nrows, b, x, r, sc,
-                bt.vs);
-    SPFD_LAUNCH(k_sum_members<T>, dim3(gblocks(nc, 64), bt.n), dim3(64), 0, s, nc, mptr, mem, r, bc, sc, bt.vs,
-                bt.vsc, xc, dinv_c, c0);
+    SPFD_LAUNCH(k_restrict_rows<T>, dim3(gblocks((long long)nc * RLANES, 256), bt.n), dim3(256), 0, s, f, nc, mptr,
+                mem, b, x, bc, sc, bt.vs, bt.vsc, xc, dinv_c, c0);
     return hipGetLastError();
 }
 
@@ -609,7 +611,7 @@ hipError_t launch_prolong_agg(long long n, const int *agg, T *x, const T *xc, T 
     template hipError_t launch_ell_cheb_step<T>(int, int, const int *, const T *, const T *, const T *, T *,         \
                                                 const T *, T *, T, T, const Scal *, const Batch &, hipStream_t,     \
                                                 const int *, const T *, T);                                         \
-    template hipError_t launch_restrict_members<T>(const FineLevelT<T> &, long long, const T *, const T *, T *, int, \
+    template hipError_t launch_restrict_members<T>(const FineLevelT<T> &, long long, const T *, const T *, int,      \
                                                    const int *, const int *, T *, const Scal *, const Batch &,      \
                                                    hipStream_t, T *, const T *, T);                                 \
     template hipError_t launch_prolong_agg<T>(long long, const int *, T *, const T *, T, const Scal *,             \

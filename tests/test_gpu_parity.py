@@ -159,6 +159,35 @@ def test_errors_and_status():
     s.close()
 
 
+def test_level_info():
+    print("case level info", flush=True)
+    w = W.config(1)
+    h = P.spfd_create(0)
+    try:
+        P.spfd_set_geometry(h, w.nx, w.ny, w.nz, *w.h, _dev(w.labels))
+        P.spfd_set_sigma_table(h, list(w.sigma_table))
+        with pytest.raises(P.SPFDError):
+            P.spfd_level_info(h, 0)  # before build
+        P.spfd_build(h)
+        info = P.spfd_get_info(h)
+        levels = [P.spfd_level_info(h, l) for l in range(info["n_levels"])]
+        assert levels[0]["kind"] == "structured" and levels[0]["unknowns"] == info["n_dofs"]
+        kinds = [lv["kind"] for lv in levels]
+        assert kinds == sorted(kinds, key=lambda k: k == "ell")  # structured levels first
+        for a, b in zip(levels, levels[1:]):
+            assert b["unknowns"] < a["unknowns"]
+        for lv in levels:
+            assert lv["slots"] >= lv["unknowns"] > 0
+            assert lv["row_entries"] == 7 if lv["kind"] == "structured" else lv["row_entries"] >= 2
+        assert levels[-1]["unknowns"] <= 1024
+        for bad in (-1, info["n_levels"]):
+            with pytest.raises(P.SPFDError) as e:
+                P.spfd_level_info(h, bad)
+            assert e.value.status == 1
+    finally:
+        P.spfd_destroy(h)
+
+
 def test_warm_start_and_determinism():
     print("case warm start", flush=True)
     w = W.config(1)
