@@ -2,18 +2,15 @@
 //
 // One wave owns a column segment of a brick: lane (tx, ty) = (lane & 7,
 // lane >> 3) holds the nodes (tx, ty, z0 .. z0+ZPL-1) in registers.  The z
-// neighbours of a node come from the lane's own registers.  The lateral
-// neighbours come in one of two ways (PERM):
-//  * loads (false): four more column loads per lane, cache hits inside the
-//    brick;
-//  * permutes (true): the lanes l-1, l+1, l-8, l+8 hold the neighbours inside
-//    the brick (cross-lane permutes, no memory access), and only the lanes on
-//    an x or y face of the brick load one extra column from the neighbour
-//    brick.  This frees registers and cache bandwidth; it pays for FP32 values
-//    (one permute per neighbour) and not for FP64 ones next to the LDS reads
-//    of the conductivity planes (measured).
-// Every load of the wave is independent of the others, so a wave has all of
-// them in flight at once.  The stencil needs no workgroup barrier: this is
+// neighbours of a node come from the lane's own registers; the lateral
+// neighbours inside the brick from the lanes l-1, l+1, l-8, l+8 (cross-lane
+// permutes, no memory access), and only the lanes on an x or y face of the
+// brick load one extra column from the neighbour brick.  Compared with four
+// lateral column loads per lane (cache hits), this frees registers, i.e.
+// more HBM bytes in flight per register, and cache bandwidth: the CG step
+// went from 118 to 99-104 us on the 8.9M-unknown body, the smoothing steps
+// by 5-15 % (measured).  Every load of the wave is independent of the
+// others, so a wave has all of them in flight at once.  The stencil needs no workgroup barrier: this is
 // what keeps HBM busy (a 512-thread brick workgroup with a barrier holds too
 // few bytes in flight per compute unit for the latency of HBM3E).  The
 // permutes need all 64 lanes: the stencil loops run in wave-uniform control
@@ -130,19 +127,6 @@ __device__ __forceinline__ Seg<ZPL> make_seg(const Topo &topo)
     return s;
 }
 
-// slot of the lateral neighbour k (x-, x+, y-, y+) of (tx, ty, z0); an absent
-// neighbour brick gives the lane's own slot (edge conductance 0)
-template <int ZPL>
-__device__ __forceinline__ long long lat_slot(const Seg<ZPL> &s, int k)
-{
-    switch (k) {
-    case 0: return s.tx > 0 ? s.self - 1 : s.xe;
-    case 1: return s.tx < 7 ? s.self + 1 : s.xe;
-    case 2: return s.ty > 0 ? s.self - 8 : s.ye;
-    default: return s.ty < 7 ? s.self + 8 : s.ye;
-    }
-}
-
 // LDS per wave of the label form: sigma table copy + sigma of ZPL+1 voxel planes
 template <typename T, int ZPL>
 struct ColLds {
@@ -150,13 +134,13 @@ struct ColLds {
     static constexpr int PER_WAVE = MAX_LABELS + ((NE + 3) & ~3);
 };
 
-template <typename T, int ZPL, bool LABEL, bool PERM>
+template <typename T, int ZPL, bool LABEL>
 struct SegOp;
 
 // Label form.  Plane c of the wave holds the voxels of tile plane z0 + c
 // (tile plane k = voxel layer below node layer k of the brick).
-template <typename T, int ZPL, bool PERM>
-struct SegOp<T, ZPL, true, PERM> {
+template <typename T, int ZPL>
+struct SegOp<T, ZPL, true> {
     static constexpr int NE = ColLds<T, ZPL>::NE;
     static constexpr int NWD = (NE + 3) / 4;      // label dwords (81 z0 is a multiple of 4)
     static constexpr int NLD = (NWD + 63) / 64;
@@ -224,106 +208,82 @@ struct SegOp<T, ZPL, true, PERM> {
 };
 
 // Stored form: w[d*stride + n] = conductance of the edge from n to +d; the
-// minus-side weights are the plus-side weights of the minus neighbours, loaded
-// (PERM false) or, inside the brick, taken from lanes l-1 and l-8 with the
-// lanes on the minus faces loading them from the neighbour brick (PERM true).
-// Columns without unknowns read as 0 (every edge at such a node has
-// conductance 0).
-template <typename T, int ZPL, bool PERM>
-struct SegOp<T, ZPL, false, PERM> {
+// minus-side weights are the plus-side weights of the minus neighbours, inside
+// the brick taken from lanes l-1 and l-8, on the minus faces loaded from the
+// neighbour brick.  Columns without unknowns read as 0 (every edge at such a
+// node has conductance 0).
+template <typename T, int ZPL>
+struct SegOp<T, ZPL, false> {
     T wp[3][ZPL], wmx[ZPL], wmy[ZPL], wmz;
 
+    // Every lane loads (the slots stand in for absent ones) and the values
+    // are masked afterwards: a load under a per-lane condition becomes a
+    // branch, and a use of its value sunk into that branch waits for it
+    // there, one load at a time.
     __device__ __forceinline__ void load(const OpArgs<T> &op, const Seg<ZPL> &s, T *)
     {
         const T *w = op.w;
         const long long st = op.stride;
-        const bool mx = s.active && (PERM ? s.bx && s.tx == 0 : s.has[NMX]);
-        const bool my = s.active && (PERM ? s.by && s.ty == 0 : s.has[NMY]);
-        const long long ax = PERM ? s.xe : lat_slot(s, 0), ay = PERM ? s.ye : lat_slot(s, 2);
 #pragma unroll
         for (int z = 0; z < ZPL; ++z) {
-            wp[0][z] = s.active ? w[s.self + 64 * z] : T(0);
-            wp[1][z] = s.active ? w[st + s.self + 64 * z] : T(0);
-            wp[2][z] = s.active ? w[2 * st + s.self + 64 * z] : T(0);
-            wmx[z] = mx ? w[ax + 64 * z] : T(0);
-            wmy[z] = my ? w[st + ay + 64 * z] : T(0);
+            wp[0][z] = w[s.self + 64 * z];
+            wp[1][z] = w[st + s.self + 64 * z];
+            wp[2][z] = w[2 * st + s.self + 64 * z];
+            wmx[z] = w[s.xe + 64 * z];
+            wmy[z] = w[st + s.ye + 64 * z];
         }
-        wmz = s.active && s.has[NMZ] ? w[2 * st + s.zm] : T(0);
+        wmz = w[2 * st + s.zm];
+        const bool mx = s.active && s.bx && s.tx == 0, my = s.active && s.by && s.ty == 0;
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) wp[d][z] = s.active ? wp[d][z] : T(0);
+            wmx[z] = mx ? wmx[z] : T(0);
+            wmy[z] = my ? wmy[z] : T(0);
+        }
+        wmz = s.active && s.has[NMZ] ? wmz : T(0);
     }
 
     __device__ __forceinline__ void stage(const OpArgs<T> &, const Seg<ZPL> &) {}
 
-    // with PERM, all 64 lanes of the wave must call this
+    // all 64 lanes of the wave must call this
     __device__ __forceinline__ void weights(const Seg<ZPL> &s, int z, T W[6])
     {
+        const T mx = lane_get(wp[0][z], s.lane - 1), my = lane_get(wp[1][z], s.lane - 8);
         W[NPX] = wp[0][z];
         W[NPY] = wp[1][z];
         W[NPZ] = wp[2][z];
-        if constexpr (PERM) {
-            const T mx = lane_get(wp[0][z], s.lane - 1), my = lane_get(wp[1][z], s.lane - 8);
-            W[NMX] = s.tx > 0 ? mx : wmx[z];
-            W[NMY] = s.ty > 0 ? my : wmy[z];
-        } else {
-            W[NMX] = wmx[z];
-            W[NMY] = wmy[z];
-        }
+        W[NMX] = s.tx > 0 ? mx : wmx[z];
+        W[NMY] = s.ty > 0 ? my : wmy[z];
         W[NMZ] = z > 0 ? wp[2][z - 1] : wmz;
-    }
-};
-
-template <typename T, int ZPL, bool PERM>
-struct SegVals;
-
-// values of x along the segment, its four lateral neighbour columns and the
-// two z ends
-template <typename T, int ZPL>
-struct SegVals<T, ZPL, false> {
-    T c[ZPL], l[4][ZPL], zm, zp;
-
-    // a lane of a column without unknowns loads nothing: no other lane reads its values
-    __device__ __forceinline__ void load(const T *__restrict__ x, const Seg<ZPL> &s)
-    {
-        if (!s.active) return;
-        long long a[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) a[k] = lat_slot(s, k);
-#pragma unroll
-        for (int z = 0; z < ZPL; ++z) {
-            c[z] = x[s.self + 64 * z];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) l[k][z] = x[a[k] + 64 * z];
-        }
-        zm = x[s.zm];
-        zp = x[s.zp];
-    }
-
-    __device__ __forceinline__ void nbrs(const Seg<ZPL> &, int z, T N[6]) const
-    {
-        N[NMX] = l[0][z];
-        N[NPX] = l[1][z];
-        N[NMY] = l[2][z];
-        N[NPY] = l[3][z];
-        N[NMZ] = z > 0 ? c[z - 1] : zm;
-        N[NPZ] = z < ZPL - 1 ? c[z + 1] : zp;
     }
 };
 
 // values of x along the segment, the face lanes' columns in the neighbour
 // bricks (ex, ey) and the two z ends; 0 where nothing is to be read
 template <typename T, int ZPL>
-struct SegVals<T, ZPL, true> {
+struct SegVals {
     T c[ZPL], ex[ZPL], ey[ZPL], zm, zp;
 
+    // unconditional loads, masked afterwards (as in the stored-form operator)
     __device__ __forceinline__ void load(const T *__restrict__ x, const Seg<ZPL> &s)
     {
 #pragma unroll
         for (int z = 0; z < ZPL; ++z) {
-            c[z] = s.active ? x[s.self + 64 * z] : T(0);
-            ex[z] = s.active && s.bx ? x[s.xe + 64 * z] : T(0);
-            ey[z] = s.active && s.by ? x[s.ye + 64 * z] : T(0);
+            c[z] = x[s.self + 64 * z];
+            ex[z] = x[s.xe + 64 * z];
+            ey[z] = x[s.ye + 64 * z];
         }
-        zm = s.active && s.has[NMZ] ? x[s.zm] : T(0);
-        zp = s.active && s.has[NPZ] ? x[s.zp] : T(0);
+        zm = x[s.zm];
+        zp = x[s.zp];
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) {
+            c[z] = s.active ? c[z] : T(0);
+            ex[z] = s.active && s.bx ? ex[z] : T(0);
+            ey[z] = s.active && s.by ? ey[z] : T(0);
+        }
+        zm = s.active && s.has[NMZ] ? zm : T(0);
+        zp = s.active && s.has[NPZ] ? zp : T(0);
     }
 
     // the six neighbours of node z0+z; all 64 lanes of the wave must call this
@@ -351,10 +311,6 @@ __device__ __forceinline__ T *col_lds()
     }
 }
 
-// neighbour access of the cycle kernels (see the top of this file)
-template <typename T>
-constexpr bool perm_cycle() { return sizeof(T) == 4; }
-
 // ---------------------------------------------------------------- Chebyshev smoothing
 // first step from a zero start: x = c0 D^-1 b (0 where D = 0)
 template <typename T, typename TB, int ZPL, bool LABEL>
@@ -367,11 +323,14 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo 
     const bool done = col_stopped(sc);
     b += blockIdx.y * vs;
     x += blockIdx.y * vs;
-    SegOp<T, ZPL, LABEL, perm_cycle<T>()> A;
+    SegOp<T, ZPL, LABEL> A;
     A.load(op, s, lds);
+    TB braw[ZPL];
+#pragma unroll
+    for (int z = 0; z < ZPL; ++z) braw[z] = b[s.self + 64 * z];
     T bv[ZPL];
 #pragma unroll
-    for (int z = 0; z < ZPL; ++z) bv[z] = s.active ? (T)b[s.self + 64 * z] : T(0);
+    for (int z = 0; z < ZPL; ++z) bv[z] = s.active ? (T)braw[z] : T(0);
     A.stage(op, s);
     if (done) return;
 #pragma unroll
@@ -404,62 +363,42 @@ __device__ __forceinline__ long long coarse_slot(const Prolong &pr, int b, int t
            64 * ((f.z & 1) * 4 + (tz >> 1));
 }
 
-template <typename T, int ZPL, bool PERM>
+template <typename T, int ZPL>
 __device__ __forceinline__ void apply_prolong(const Prolong &pr, const Topo &topo, const Seg<ZPL> &s,
-                                              SegVals<T, ZPL, PERM> &X)
+                                              SegVals<T, ZPL> &X)
 {
-    if (!s.active) return;
+    // every lane loads, the corrections are masked (see SegVals::load)
     const T *xc = (const T *)pr.xc + blockIdx.y * pr.vsc;
     const T sc = (T)pr.scale;
     int nb[6];
     brick_nbrs(topo.nbr, s.bk, nb);
     const int tx = s.tx, ty = s.ty, z0 = s.z0;
-    // coarse slots of the lane's own column and of the two z ends (absent -> own column, never read)
+    // coarse slots of the lane's own column, of its face column in the x (y)
+    // neighbour brick and of the two z ends (absent -> own column, never read)
     const long long c0 = coarse_slot(pr, s.bk, tx, ty, z0);
+    const long long cx = s.bx ? coarse_slot(pr, tx == 0 ? nb[NMX] : nb[NPX], tx == 0 ? 7 : 0, ty, z0) : c0;
+    const long long cy = s.by ? coarse_slot(pr, ty == 0 ? nb[NMY] : nb[NPY], tx, ty == 0 ? 7 : 0, z0) : c0;
     const long long czm = z0 > 0 ? coarse_slot(pr, s.bk, tx, ty, z0 - 1)
                                  : (nb[NMZ] >= 0 ? coarse_slot(pr, nb[NMZ], tx, ty, 7) : c0);
     const int ze = z0 + ZPL;
     const long long czp = ze < 8 ? coarse_slot(pr, s.bk, tx, ty, ze) : (nb[NPZ] >= 0 ? coarse_slot(pr, nb[NPZ], tx, ty, 0) : c0);
-    T v0[ZPL / 2];
+    T v0[ZPL / 2], vx[ZPL / 2], vy[ZPL / 2];
 #pragma unroll
-    for (int h = 0; h < ZPL / 2; ++h) v0[h] = xc[c0 + 64 * h];
-    const T vm = s.has[NMZ] ? xc[czm] : T(0), vp = s.has[NPZ] ? xc[czp] : T(0);
-    if constexpr (PERM) {
-        // the face column in the x (y) neighbour brick
-        const long long cx = s.bx ? coarse_slot(pr, tx == 0 ? nb[NMX] : nb[NPX], tx == 0 ? 7 : 0, ty, z0) : c0;
-        const long long cy = s.by ? coarse_slot(pr, ty == 0 ? nb[NMY] : nb[NPY], tx, ty == 0 ? 7 : 0, z0) : c0;
-        T vx[ZPL / 2], vy[ZPL / 2];
-#pragma unroll
-        for (int h = 0; h < ZPL / 2; ++h) {
-            vx[h] = s.bx ? xc[cx + 64 * h] : T(0);
-            vy[h] = s.by ? xc[cy + 64 * h] : T(0);
-        }
-#pragma unroll
-        for (int z = 0; z < ZPL; ++z) {
-            X.ex[z] += sc * vx[z >> 1];
-            X.ey[z] += sc * vy[z >> 1];
-        }
-    } else {
-        // the four lateral columns
-        long long cl[4];
-        cl[0] = tx > 0 ? coarse_slot(pr, s.bk, tx - 1, ty, z0) : (nb[NMX] >= 0 ? coarse_slot(pr, nb[NMX], 7, ty, z0) : c0);
-        cl[1] = tx < 7 ? coarse_slot(pr, s.bk, tx + 1, ty, z0) : (nb[NPX] >= 0 ? coarse_slot(pr, nb[NPX], 0, ty, z0) : c0);
-        cl[2] = ty > 0 ? coarse_slot(pr, s.bk, tx, ty - 1, z0) : (nb[NMY] >= 0 ? coarse_slot(pr, nb[NMY], tx, 7, z0) : c0);
-        cl[3] = ty < 7 ? coarse_slot(pr, s.bk, tx, ty + 1, z0) : (nb[NPY] >= 0 ? coarse_slot(pr, nb[NPY], tx, 0, z0) : c0);
-        T vl[4][ZPL / 2];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int h = 0; h < ZPL / 2; ++h) vl[k][h] = xc[cl[k] + 64 * h];
-#pragma unroll
-        for (int z = 0; z < ZPL; ++z)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) X.l[k][z] += sc * vl[k][z >> 1];
+    for (int h = 0; h < ZPL / 2; ++h) {
+        v0[h] = xc[c0 + 64 * h];
+        vx[h] = xc[cx + 64 * h];
+        vy[h] = xc[cy + 64 * h];
     }
+    const T vm = xc[czm], vp = xc[czp];
+    const bool a = s.active;
 #pragma unroll
-    for (int z = 0; z < ZPL; ++z) X.c[z] += sc * v0[z >> 1];
-    X.zm += sc * vm;
-    X.zp += sc * vp;
+    for (int z = 0; z < ZPL; ++z) {
+        X.c[z] += a ? sc * v0[z >> 1] : T(0);
+        X.ex[z] += a && s.bx ? sc * vx[z >> 1] : T(0);
+        X.ey[z] += a && s.by ? sc * vy[z >> 1] : T(0);
+    }
+    X.zm += a && s.has[NMZ] ? sc * vm : T(0);
+    X.zp += a && s.has[NPZ] ? sc * vp : T(0);
 }
 
 // Dot products of the outer flexible CG that ride on the last finest-level
@@ -496,24 +435,27 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo t
         xout += blockIdx.y * vs;
         if (din) din += blockIdx.y * vs;
         if (dout) dout += blockIdx.y * vs;
-        SegOp<T, ZPL, LABEL, perm_cycle<T>()> A;
+        SegOp<T, ZPL, LABEL> A;
         A.load(op, s, lds);
-        SegVals<T, ZPL, perm_cycle<T>()> X;
+        SegVals<T, ZPL> X;
         X.load(xin, s);
-        T bv[ZPL], dv[ZPL];
+        // (loaded by every lane, used only where the column holds unknowns)
+        TB braw[ZPL];
+        T dv[ZPL];
         double qv[DOT ? ZPL : 1];
-        if (s.active) {
 #pragma unroll
-            for (int z = 0; z < ZPL; ++z) {
-                bv[z] = (T)b[s.self + 64 * z];
-                if (din) dv[z] = din[s.self + 64 * z];
-            }
-            if constexpr (DOT) {
-                const double *q = dt.q + blockIdx.y * vs;
-#pragma unroll
-                for (int z = 0; z < ZPL; ++z) qv[z] = q[s.self + 64 * z];
-            }
+        for (int z = 0; z < ZPL; ++z) {
+            braw[z] = b[s.self + 64 * z];
+            if (din) dv[z] = din[s.self + 64 * z];
         }
+        if constexpr (DOT) {
+            const double *q = dt.q + blockIdx.y * vs;
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) qv[z] = q[s.self + 64 * z];
+        }
+        T bv[ZPL];
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) bv[z] = (T)braw[z];
         if constexpr (PRO) apply_prolong(pr, topo, s, X);
         if (!din) {
 #pragma unroll
@@ -585,13 +527,16 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
     b += blockIdx.y * vs;
     x += blockIdx.y * vs;
     bc += blockIdx.y * vsc;
-    SegOp<T, ZPL, LABEL, perm_cycle<T>()> A;
+    SegOp<T, ZPL, LABEL> A;
     A.load(op, s, lds);
-    SegVals<T, ZPL, perm_cycle<T>()> X;
+    SegVals<T, ZPL> X;
     X.load(x, s);
+    TB braw[ZPL];
+#pragma unroll
+    for (int z = 0; z < ZPL; ++z) braw[z] = b[s.self + 64 * z];
     T bv[ZPL];
 #pragma unroll
-    for (int z = 0; z < ZPL; ++z) bv[z] = s.active ? (T)b[s.self + 64 * z] : T(0);
+    for (int z = 0; z < ZPL; ++z) bv[z] = s.active ? (T)braw[z] : T(0);
     const int4 fc = fcoord[s.bk];
     const long long pbase = (long long)parent_slot[s.bk] * BS;
     const int ox = (fc.x & 1) * 4 + (s.tx >> 1), oy = (fc.y & 1) * 4 + (s.ty >> 1);
@@ -655,11 +600,11 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
     part += (long long)blockIdx.y * ps;
     double dot = 0.0;
     if (s.bk >= 0) {
-        SegOp<double, ZPL, LABEL, false> A;
+        SegOp<double, ZPL, LABEL> A;
         A.load(op, s, lds);
-        SegVals<TZ, ZPL, false> Z;
+        SegVals<TZ, ZPL> Z;
         Z.load(zv, s);
-        SegVals<double, ZPL, false> Pi;
+        SegVals<double, ZPL> Pi;
         double xv[ZPL];
         if (!first) {
             Pi.load(pin, s);
@@ -669,30 +614,31 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
         }
         const double beta = first ? 0.0 : sc->beta;
         const double alpha = first ? 0.0 : sc->alpha;
-        // p_k on the segment and its neighbours
-        SegVals<double, ZPL, false> P;
+        // p_k on the segment, the face columns and the z ends
+        SegVals<double, ZPL> P;
 #pragma unroll
         for (int z = 0; z < ZPL; ++z) {
             P.c[z] = first ? (double)Z.c[z] : (double)Z.c[z] + beta * Pi.c[z];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) P.l[k][z] = first ? (double)Z.l[k][z] : (double)Z.l[k][z] + beta * Pi.l[k][z];
+            P.ex[z] = first ? (double)Z.ex[z] : (double)Z.ex[z] + beta * Pi.ex[z];
+            P.ey[z] = first ? (double)Z.ey[z] : (double)Z.ey[z] + beta * Pi.ey[z];
         }
         P.zm = first ? (double)Z.zm : (double)Z.zm + beta * Pi.zm;
         P.zp = first ? (double)Z.zp : (double)Z.zp + beta * Pi.zp;
         A.stage(op, s);
-        // (load mode: no cross-lane access, lanes of empty columns skip the loop)
-        if (!done && s.active) {
+        if (!done) {
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) {
                 double W[6], N[6];
                 A.weights(s, z, W);
                 P.nbrs(s, z, N);
                 const double y = stencil_apply(P.c[z], N, W);
-                const long long n = s.self + 64 * z;
-                if (!first) x[n] = xv[z] + alpha * Pi.c[z];
-                pout[n] = P.c[z];
-                q[n] = y;
-                dot += P.c[z] * y;
+                if (s.active) {
+                    const long long n = s.self + 64 * z;
+                    if (!first) x[n] = xv[z] + alpha * Pi.c[z];
+                    pout[n] = P.c[z];
+                    q[n] = y;
+                    dot += P.c[z] * y;
+                }
             }
         }
     }
@@ -722,12 +668,12 @@ __global__ __launch_bounds__(CTHREADS) void k_col_spmv(OpArgs<double> op, Topo t
     const bool done = col_stopped(sc);
     zv += blockIdx.y * vs;
     w += blockIdx.y * vs;
-    SegOp<double, ZPL, LABEL, false> A;
+    SegOp<double, ZPL, LABEL> A;
     A.load(op, s, lds);
-    SegVals<TZ, ZPL, false> Z;
+    SegVals<TZ, ZPL> Z;
     Z.load(zv, s);
     A.stage(op, s);
-    if (done || !s.active) return;
+    if (done) return;
 #pragma unroll
     for (int z = 0; z < ZPL; ++z) {
         double W[6], P[6];
@@ -736,7 +682,8 @@ __global__ __launch_bounds__(CTHREADS) void k_col_spmv(OpArgs<double> op, Topo t
         Z.nbrs(s, z, N);
 #pragma unroll
         for (int k = 0; k < 6; ++k) P[k] = (double)N[k];
-        w[s.self + 64 * z] = stencil_apply((double)Z.c[z], P, W);
+        const double y = stencil_apply((double)Z.c[z], P, W);
+        if (s.active) w[s.self + 64 * z] = y;
     }
 }
 
