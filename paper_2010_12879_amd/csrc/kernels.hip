@@ -1246,17 +1246,29 @@ __global__ __launch_bounds__(256) void k_coarse_apply(const TB *__restrict__ bc,
                                                       long long vs)
 {
     __shared__ double rv[1024];
-    if (stopped(sc)) return;
     bc += blockIdx.y * vs;
     xc += blockIdx.y * vs;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) rv[i] = (double)bc[node_of_dof[i]];
-    __syncthreads();
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = blockIdx.x * 4 + wv;
-    if (row >= n) return;
-    const double *a = Ainv + (long long)row * n;
+    // the wave's row of the inverse is loaded first (n <= 1024: 16 values per
+    // lane), in flight together with the gather of b_c and the stop flag
+    const double *a = Ainv + (long long)(row < n ? row : n - 1) * n;
+    double av[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int j = lane + 64 * k;
+        av[k] = a[j < n ? j : n - 1];
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) rv[i] = (double)bc[node_of_dof[i]];
+    const bool stop = stopped(sc);
+    __syncthreads();
+    if (stop || row >= n) return;
     double s = 0.0;
-    for (int j = lane; j < n; j += 64) s += a[j] * rv[j];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int j = lane + 64 * k;
+        if (j < n) s += av[k] * rv[j];
+    }
     s = wave_sum(s);
     if (lane == 0) xc[node_of_dof[row]] = (T)s;
 }

@@ -373,19 +373,23 @@ __device__ __forceinline__ bool ell_stopped(const Scal *sc)
     return sc && __hip_atomic_load(&sc[blockIdx.y].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// (A x)_i and the diagonal D of an ELL row.  Padding entries (col < 0) read
+// the row's own value and count with weight 0: every load is unconditional,
+// so a thread has all of its row's loads in flight at once (a load under a
+// condition becomes a branch that waits for it).
 template <typename T>
 __device__ __forceinline__ T ell_row(int n, int K, const int *__restrict__ col, const T *__restrict__ val,
                                      const T *__restrict__ x, int i, T xi, T &D)
 {
     T y = T(0), d = T(0);
-#pragma unroll 4
+#pragma unroll 8
     for (int k = 0; k < K; ++k) {
         const int j = col[(long long)k * n + i];
-        if (j >= 0) {
-            const T w = val[(long long)k * n + i];
-            d += w;
-            y += w * (xi - x[j]);
-        }
+        const T v = val[(long long)k * n + i];
+        const T xj = x[j >= 0 ? j : i];
+        const T w = j >= 0 ? v : T(0);
+        d += w;
+        y += w * (xi - xj);
     }
     D = d;
     return y;
@@ -399,10 +403,15 @@ __global__ void k_ell_cheb_first(int n, int K, const int *__restrict__ col, cons
     b += blockIdx.y * vs;
     x += blockIdx.y * vs;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const T bi = b[i];
         T d = T(0);
-        for (int k = 0; k < K; ++k)
-            if (col[(long long)k * n + i] >= 0) d += val[(long long)k * n + i];
-        x[i] = d > T(0) ? c0 * b[i] / d : T(0);
+#pragma unroll 8
+        for (int k = 0; k < K; ++k) {
+            const int j = col[(long long)k * n + i];
+            const T v = val[(long long)k * n + i];
+            d += j >= 0 ? v : T(0);
+        }
+        x[i] = d > T(0) ? c0 * bi / d : T(0);
     }
 }
 
@@ -412,9 +421,9 @@ __device__ __forceinline__ T corrected(const T *__restrict__ x, const int *__res
                                        T scale, int i)
 {
     const T v = x[i];
-    if (!agg) return v;
     const int a = agg[i];
-    return a >= 0 ? v + scale * xc[a] : v;
+    const T c = xc[a >= 0 ? a : 0];
+    return a >= 0 ? v + scale * c : v;
 }
 
 // general Chebyshev step on an ELL level; with agg the prolongation from the
@@ -435,19 +444,22 @@ __global__ void k_ell_cheb_step(int n, int K, const int *__restrict__ col, const
     if (dout) dout += blockIdx.y * vs;
     if (agg) xc += blockIdx.y * vsc;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const T xi = corrected(xin, agg, xc, scale, i);
+        const T xi = agg ? corrected(xin, agg, xc, scale, i) : xin[i];
+        const T bi = b[i];
+        const T di = din ? din[i] : T(0);
         T D;
         T ax;
         if (agg) {
+            // as ell_row, with every value read corrected (unconditional loads)
             T y = T(0), d = T(0);
-#pragma unroll 4
+#pragma unroll 8
             for (int k = 0; k < K; ++k) {
                 const int j = col[(long long)k * n + i];
-                if (j >= 0) {
-                    const T w = val[(long long)k * n + i];
-                    d += w;
-                    y += w * (xi - corrected(xin, agg, xc, scale, j));
-                }
+                const T v = val[(long long)k * n + i];
+                const T xj = corrected(xin, agg, xc, scale, j >= 0 ? j : i);
+                const T w = j >= 0 ? v : T(0);
+                d += w;
+                y += w * (xi - xj);
             }
             D = d;
             ax = y;
@@ -456,8 +468,8 @@ __global__ void k_ell_cheb_step(int n, int K, const int *__restrict__ col, const
         }
         T xo = T(0), dn = T(0);
         if (D > T(0)) {
-            const T dold = din ? din[i] : xi;
-            dn = c1 * dold + c2 * (b[i] - ax) / D;
+            const T dold = din ? di : xi;
+            dn = c1 * dold + c2 * (bi - ax) / D;
             xo = xi + dn;
         }
         xout[i] = xo;
