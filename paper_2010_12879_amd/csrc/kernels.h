@@ -118,11 +118,6 @@ hipError_t launch_fill(T *x, long long n, T v, hipStream_t s);
 hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, const Grid &g, const double *a,
                       double *b, double *part, Scal *sc, hipStream_t s);
 hipError_t launch_scal_init(Scal *sc, double tol, int use_x0, int nbatch, hipStream_t s);
-hipError_t launch_spmv_dot(const OpArgs<double> &op, Topo topo, const double *p, double *q, double *part,
-                           Scal *sc, const Batch &bt, hipStream_t s);
-// r32 (nullable): FP32 copy of the new residual for an FP32 cycle
-hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const double *q, double *part,
-                         Scal *sc, const Batch &bt, float *r32, hipStream_t s);
 // fused CG step: p = z + beta p (p = z when first), x += alpha p_old (deferred), q = A p, p.q partials;
 // pin and pout are different buffers (neighbours read p_old)
 // edge potentials a [3][Nz][Ny][Nx] from divergence-free facet fluxes (tree-cotree gauge)

@@ -975,41 +975,7 @@ hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, co
     return hipGetLastError();
 }
 
-// q = A p and the partials of p.q (alpha follows in k_finish)
-__global__ __launch_bounds__(NT) void k_spmv_dot(OpArgs<double> op, Topo topo, const double *__restrict__ p,
-                                                 double *__restrict__ q, double *part, const Scal *sc, long long vs,
-                                                 int ps)
-{
-    __shared__ double tile[TILE_VOX + 7];
-    __shared__ double red[8];
-    sc += blockIdx.y;
-    if (sc->done) return;
-    p += blockIdx.y * vs;
-    q += blockIdx.y * vs;
-    part += (long long)blockIdx.y * ps;
-    const int bk = xcd_brick(blockIdx.x, topo.nb);
-    if (bk < 0) return;
-    int nb[6];
-    brick_nbrs(topo.nbr, bk, nb);
-    const int t = threadIdx.x;
-    int tx, ty, tz;
-    brick_xyz(t, tx, ty, tz);
-    const long long base = (long long)bk * BS;
-    long long I[6];
-    nbr_index(base, t, tx, ty, tz, nb, I);
-    double X[6];
-    nbr_vals(p, I, X);
-    const double p0 = p[base + t];
-    op_stage(op, bk, tile);
-    double W[6];
-    op_weights(op, tile, base, t, tx, ty, tz, I, W);
-    const double y = stencil_apply(p0, X, W);
-    q[base + t] = y;
-    const double tot = block_sum(p0 * y, red);
-    if (t == 0) part[bk] = tot;
-}
-
-// x += alpha p: the update deferred by k_cg_step, applied once after the last
+// x += alpha p: the update deferred by the CG step, applied once after the last
 // step of a pass, from the buffer that step wrote (sc->pad: 0 = none pending)
 __global__ __launch_bounds__(NT) void k_x_final(Topo topo, double *__restrict__ x, const double *__restrict__ pa,
                                                 const double *__restrict__ pb, const Scal *sc, long long vs)
@@ -1056,50 +1022,6 @@ hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, S
     if (topo.nb <= 0) return hipSuccess;
     SPFD_LAUNCH(k_rupdate, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, r, q, part, sc, bt.vs, bt.ps,
                        r32);
-    return hipGetLastError();
-}
-
-hipError_t launch_spmv_dot(const OpArgs<double> &op, Topo topo, const double *p, double *q, double *part, Scal *sc,
-                           const Batch &bt, hipStream_t s)
-{
-    if (topo.nb <= 0) return hipSuccess;
-    SPFD_LAUNCH(k_spmv_dot, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, p, q, part, sc, bt.vs,
-                       bt.ps);
-    return hipGetLastError();
-}
-
-// x += alpha p, r -= alpha q and the partials of ||r||^2 (stop test in k_finish)
-__global__ __launch_bounds__(NT) void k_update(Topo topo, double *__restrict__ x, double *__restrict__ r,
-                                               const double *__restrict__ p, const double *__restrict__ q,
-                                               double *part, const Scal *sc, long long vs, int ps,
-                                               float *__restrict__ r32)
-{
-    __shared__ double red[8];
-    sc += blockIdx.y;
-    if (sc->done) return;
-    const int bk = xcd_brick(blockIdx.x, topo.nb);
-    if (bk < 0) return;
-    x += blockIdx.y * vs;
-    r += blockIdx.y * vs;
-    p += blockIdx.y * vs;
-    q += blockIdx.y * vs;
-    part += (long long)blockIdx.y * ps;
-    const double alpha = sc->alpha;
-    const long long n = (long long)bk * BS + threadIdx.x;
-    x[n] += alpha * p[n];
-    const double rn = r[n] - alpha * q[n];
-    r[n] = rn;
-    if (r32) r32[blockIdx.y * vs + n] = (float)rn;
-    const double tot = block_sum(rn * rn, red);
-    if (threadIdx.x == 0) part[bk] = tot;
-}
-
-hipError_t launch_update(Topo topo, double *x, double *r, const double *p, const double *q, double *part, Scal *sc,
-                         const Batch &bt, float *r32, hipStream_t s)
-{
-    if (topo.nb <= 0) return hipSuccess;
-    SPFD_LAUNCH(k_update, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, x, r, p, q, part, sc, bt.vs,
-                       bt.ps, r32);
     return hipGetLastError();
 }
 
