@@ -998,7 +998,7 @@ hipError_t launch_x_final(Topo topo, double *x, const double *pa, const double *
     return hipGetLastError();
 }
 
-// r -= alpha q, ||r||^2 partials and the FP32 copy of r (x is updated by k_cg_step)
+// r -= alpha q, ||r||^2 partials and the FP32 copy of r (x is updated by the CG step)
 __global__ __launch_bounds__(NT) void k_rupdate(Topo topo, double *__restrict__ r, const double *__restrict__ q,
                                                 double *part, const Scal *sc, long long vs, int ps,
                                                 float *__restrict__ r32)
