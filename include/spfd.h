@@ -74,6 +74,9 @@ typedef struct {
     int split_level;      /* aggregates of this level and coarser ones are split into their connected pieces
                              (coarse unknowns become unstructured), default 2 */
     int no_split;         /* nonzero: never split aggregates (structured 7-point levels only) */
+    int level1_degree;    /* Chebyshev degree per pre/post smoothing on the first coarse level, default 4,
+                             max 8 (that level costs about an eighth of the finest one per step, and
+                             smoothing it harder lowers the iteration count) */
 } spfd_amg_options;
 
 typedef struct {

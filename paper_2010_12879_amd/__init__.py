@@ -35,7 +35,7 @@ class SPFDError(RuntimeError):
 class AmgOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("cycle", ctypes.c_int), ("smooth_degree", ctypes.c_int),
                 ("coarsest_max", ctypes.c_int), ("cheby_ratio", ctypes.c_double), ("coarse_scale", ctypes.c_double),
-                ("split_level", ctypes.c_int), ("no_split", ctypes.c_int)]
+                ("split_level", ctypes.c_int), ("no_split", ctypes.c_int), ("level1_degree", ctypes.c_int)]
 
 
 class SolveOptions(ctypes.Structure):
@@ -291,7 +291,7 @@ class Solver:
     """
 
     def __init__(self, labels, sigma, h, precision="fp64", device=None, smooth_degree=2, coarsest_max=1024,
-                 cheby_ratio=8.0, coarse_scale=1.9, split_level=2, split=True, stream=None):
+                 cheby_ratio=8.0, coarse_scale=1.9, split_level=2, split=True, stream=None, level1_degree=4):
         import torch
         self.device = labels.device if device is None else torch.device(device)
         self.nz, self.ny, self.nx = labels.shape
@@ -307,7 +307,7 @@ class Solver:
                 spfd_set_sigma_table(self.handle, list(sigma))
             self.opts = AmgOptions(MIXED if precision == "mixed" else FP64, CYCLE_V,
                                    smooth_degree, coarsest_max, cheby_ratio, coarse_scale, split_level,
-                                   0 if split else 1)
+                                   0 if split else 1, level1_degree)
             spfd_build(self.handle, self.opts)
         except Exception:
             spfd_destroy(self.handle)

@@ -517,11 +517,18 @@ void cheb_step(Ctx *c, int l, const TB *b, const T *xin, T *xout, const T *din, 
                                    dots ? dots->part : nullptr));
 }
 
+// Chebyshev degree of level l (any degree keeps the buffer parity of the
+// cycle: a level does 2m-1 buffer swaps)
+int level_degree(const Ctx *c, int l)
+{
+    return l == 1 ? c->opt.level1_degree : c->opt.smooth_degree;
+}
+
 template <typename T, typename TB>
 void smooth_pre(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc, int nb, bool first_done)
 {
     // first_done: the restriction that produced b already stored the first step in cur
-    const int m = c->opt.smooth_degree;
+    const int m = level_degree(c, l);
     T *d = (T *)c->lv[l].d;
     // (folding the first step into the second on the finest level, x = c0 D^-1 b formed at every node
     // read, was measured slower: it doubles the lateral loads)
@@ -537,7 +544,7 @@ template <typename T, typename TB>
 void smooth_post(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc, int nb, bool with_prolong,
                  const CycleDots *dots = nullptr)
 {
-    const int m = c->opt.smooth_degree;
+    const int m = level_degree(c, l);
     T *d = (T *)c->lv[l].d;
     for (int k = 0; k < m; ++k) {
         const T c1 = k == 0 ? T(0) : (T)c->cheb_c1[k];
@@ -686,6 +693,8 @@ void set_defaults(spfd_amg_options &o)
     if (!(o.cheby_ratio > 1.0)) o.cheby_ratio = 8.0;
     if (!(o.coarse_scale > 0.0)) o.coarse_scale = 1.9;
     if (o.split_level <= 0) o.split_level = 2;
+    if (o.level1_degree <= 0) o.level1_degree = 4;
+    if (o.level1_degree > 8) o.level1_degree = 8;
 }
 
 void chebyshev_coefficients(Ctx *c)
