@@ -31,60 +31,84 @@ __device__ __forceinline__ double block_reduce(double v, double *lds)
     return s;
 }
 
-// partials (one per workgroup g, stored at part[i*ng + g]) of V_i . w, i < nv
-__global__ __launch_bounds__(KT) void k_mdot(const double *__restrict__ V, long long ldv, const double *__restrict__ w,
-                                             long long n, int nv, double *__restrict__ part, const Scal *sc)
+// partials of NV rows at once: row i of the workgroup into part[i*gridDim.x + blockIdx.x], i < nv
+template <int NV>
+__device__ __forceinline__ void rows_reduce(double (&acc)[NV], int nv, double *__restrict__ part)
 {
-    __shared__ double lds[KT / 64];
-    if (sc->done) return;
-    double acc[FG_MAXM];
+    __shared__ double lds[NV][KT / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int i = 0; i < FG_MAXM; ++i) acc[i] = 0.0;
-    for (long long e = (long long)blockIdx.x * KT + threadIdx.x; e < n; e += (long long)gridDim.x * KT) {
-        const double wv = w[e];
-#pragma unroll
-        for (int i = 0; i < FG_MAXM; ++i)
-            if (i < nv) acc[i] += V[i * ldv + e] * wv;
+    for (int i = 0; i < NV; ++i) {
+        const double t = wave_sum(acc[i]);
+        if (lane == 0) lds[i][wv] = t;
     }
-    for (int i = 0; i < nv; ++i) {
-        const double t = block_reduce(acc[i], lds);
-        if (threadIdx.x == 0) part[(long long)i * gridDim.x + blockIdx.x] = t;
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < KT / 64; ++k) t += lds[threadIdx.x][k];
+        part[(long long)threadIdx.x * gridDim.x + blockIdx.x] = t;
     }
 }
 
+// The basis kernels are templated on NV >= nv, the smallest of 4, 8, 16, 32:
+// every thread loads rows 0..NV-1 (rows from nv on repeat row nv-1, cache
+// hits) before it uses any of them, so all loads of an element are in flight
+// together; rows from nv on are masked out.  (A load under a condition on its
+// row index becomes a branch that waits for it inside, one row at a time.)
+
+// partials (one per workgroup g, stored at part[i*ng + g]) of V_i . w, i < nv
+template <int NV>
+__global__ __launch_bounds__(KT) void k_mdot(const double *__restrict__ V, long long ldv, const double *__restrict__ w,
+                                             long long n, int nv, double *__restrict__ part, const Scal *sc)
+{
+    if (sc->done) return;
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (long long e = (long long)blockIdx.x * KT + threadIdx.x; e < n; e += (long long)gridDim.x * KT) {
+        const double wv = w[e];
+        double v[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = V[(i < nv ? i : nv - 1) * ldv + e];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += v[i] * wv;
+    }
+    rows_reduce<NV>(acc, nv, part);
+}
+
 // w -= sum_i h_i V_i; then either the partials of V_i . w (mode 0) or of w.w (mode 1)
+template <int NV>
 __global__ __launch_bounds__(KT) void k_mupdate(const double *__restrict__ V, long long ldv, double *__restrict__ w,
                                                 long long n, int nv, const double *__restrict__ h, int mode,
                                                 double *__restrict__ part, const Scal *sc)
 {
     __shared__ double lds[KT / 64];
     if (sc->done) return;
-    double hv[FG_MAXM], acc[FG_MAXM];
+    double hv[NV], acc[NV];
 #pragma unroll
-    for (int i = 0; i < FG_MAXM; ++i) {
+    for (int i = 0; i < NV; ++i) {
         hv[i] = i < nv ? h[i] : 0.0;
         acc[i] = 0.0;
     }
     double nrm = 0.0;
     for (long long e = (long long)blockIdx.x * KT + threadIdx.x; e < n; e += (long long)gridDim.x * KT) {
         double wv = w[e];
+        double v[NV];
 #pragma unroll
-        for (int i = 0; i < FG_MAXM; ++i)
-            if (i < nv) wv -= hv[i] * V[i * ldv + e];
+        for (int i = 0; i < NV; ++i) v[i] = V[(i < nv ? i : nv - 1) * ldv + e];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) wv -= hv[i] * v[i];
         w[e] = wv;
         if (mode == 0) {
 #pragma unroll
-            for (int i = 0; i < FG_MAXM; ++i)
-                if (i < nv) acc[i] += V[i * ldv + e] * wv;
+            for (int i = 0; i < NV; ++i) acc[i] += v[i] * wv;
         } else {
             nrm += wv * wv;
         }
     }
     if (mode == 0) {
-        for (int i = 0; i < nv; ++i) {
-            const double t = block_reduce(acc[i], lds);
-            if (threadIdx.x == 0) part[(long long)i * gridDim.x + blockIdx.x] = t;
-        }
+        rows_reduce<NV>(acc, nv, part);
     } else {
         const double t = block_reduce(nrm, lds);
         if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -178,20 +202,28 @@ __global__ __launch_bounds__(KT) void k_fg_scale(const double *__restrict__ src,
 }
 
 // x += sum_{i<k} y_i Z_i (runs also after the stop flag is set)
-template <typename TZ>
+template <typename TZ, int NV>
 __global__ __launch_bounds__(KT) void k_fg_xupdate(double *__restrict__ x, const TZ *__restrict__ Z, long long ldz,
                                                    long long n, int k, const FGState *st)
 {
-    double y[FG_MAXM];
+    double y[NV];
 #pragma unroll
-    for (int i = 0; i < FG_MAXM; ++i) y[i] = i < k ? st->y[i] : 0.0;
+    for (int i = 0; i < NV; ++i) y[i] = i < k ? st->y[i] : 0.0;
     for (long long e = (long long)blockIdx.x * KT + threadIdx.x; e < n; e += (long long)gridDim.x * KT) {
         double t = x[e];
+        TZ zv[NV];
 #pragma unroll
-        for (int i = 0; i < FG_MAXM; ++i)
-            if (i < k) t += y[i] * (double)Z[i * ldz + e];
+        for (int i = 0; i < NV; ++i) zv[i] = Z[(i < k ? i : k - 1) * ldz + e];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) t += y[i] * (double)zv[i];
         x[e] = t;
     }
+}
+
+// smallest of 4, 8, 16, 32 that holds m rows
+static int nv_bucket(int m)
+{
+    return m <= 4 ? 4 : m <= 8 ? 8 : m <= 16 ? 16 : 32;
 }
 
 static unsigned kgrid(long long n)
@@ -207,7 +239,12 @@ hipError_t launch_mdot(const double *V, long long ldv, const double *w, long lon
                        const Scal *sc, hipStream_t s)
 {
     if (nv < 1 || nv > FG_MAXM) return hipErrorInvalidValue;
-    SPFD_LAUNCH(k_mdot, dim3(kgrid(n)), dim3(KT), 0, s, V, ldv, w, n, nv, part, sc);
+    switch (nv_bucket(nv)) {
+    case 4: SPFD_LAUNCH(k_mdot<4>, dim3(kgrid(n)), dim3(KT), 0, s, V, ldv, w, n, nv, part, sc); break;
+    case 8: SPFD_LAUNCH(k_mdot<8>, dim3(kgrid(n)), dim3(KT), 0, s, V, ldv, w, n, nv, part, sc); break;
+    case 16: SPFD_LAUNCH(k_mdot<16>, dim3(kgrid(n)), dim3(KT), 0, s, V, ldv, w, n, nv, part, sc); break;
+    default: SPFD_LAUNCH(k_mdot<32>, dim3(kgrid(n)), dim3(KT), 0, s, V, ldv, w, n, nv, part, sc); break;
+    }
     return hipGetLastError();
 }
 
@@ -215,7 +252,12 @@ hipError_t launch_mupdate(const double *V, long long ldv, double *w, long long n
                           double *part, const Scal *sc, hipStream_t s)
 {
     if (nv < 1 || nv > FG_MAXM) return hipErrorInvalidValue;
-    SPFD_LAUNCH(k_mupdate, dim3(kgrid(n)), dim3(KT), 0, s, V, ldv, w, n, nv, h, mode, part, sc);
+    switch (nv_bucket(nv)) {
+    case 4: SPFD_LAUNCH(k_mupdate<4>, dim3(kgrid(n)), dim3(KT), 0, s, V, ldv, w, n, nv, h, mode, part, sc); break;
+    case 8: SPFD_LAUNCH(k_mupdate<8>, dim3(kgrid(n)), dim3(KT), 0, s, V, ldv, w, n, nv, h, mode, part, sc); break;
+    case 16: SPFD_LAUNCH(k_mupdate<16>, dim3(kgrid(n)), dim3(KT), 0, s, V, ldv, w, n, nv, h, mode, part, sc); break;
+    default: SPFD_LAUNCH(k_mupdate<32>, dim3(kgrid(n)), dim3(KT), 0, s, V, ldv, w, n, nv, h, mode, part, sc); break;
+    }
     return hipGetLastError();
 }
 
@@ -258,7 +300,12 @@ hipError_t launch_fg_xupdate(double *x, const TZ *Z, long long ldz, long long n,
 {
     if (k < 0 || k > FG_MAXM) return hipErrorInvalidValue;
     if (k == 0) return hipSuccess;
-    SPFD_LAUNCH((k_fg_xupdate<TZ>), dim3(kgrid(n)), dim3(KT), 0, s, x, Z, ldz, n, k, st);
+    switch (nv_bucket(k)) {
+    case 4: SPFD_LAUNCH((k_fg_xupdate<TZ, 4>), dim3(kgrid(n)), dim3(KT), 0, s, x, Z, ldz, n, k, st); break;
+    case 8: SPFD_LAUNCH((k_fg_xupdate<TZ, 8>), dim3(kgrid(n)), dim3(KT), 0, s, x, Z, ldz, n, k, st); break;
+    case 16: SPFD_LAUNCH((k_fg_xupdate<TZ, 16>), dim3(kgrid(n)), dim3(KT), 0, s, x, Z, ldz, n, k, st); break;
+    default: SPFD_LAUNCH((k_fg_xupdate<TZ, 32>), dim3(kgrid(n)), dim3(KT), 0, s, x, Z, ldz, n, k, st); break;
+    }
     return hipGetLastError();
 }
 template hipError_t launch_fg_xupdate<double>(double *, const double *, long long, long long, int, const FGState *,
