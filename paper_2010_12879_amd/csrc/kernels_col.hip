@@ -702,20 +702,43 @@ static dim3 col_grid(int nb, int nbatch)
     return dim3(xcd_grid(col_ngroups<ZPL>(nb)), nbatch);
 }
 
+// Coarser structured levels (stored weights) with few bricks run shorter
+// segments: all their waves are resident at once, so a kernel lasts about one
+// wave's load-to-store latency, which shrinks with the segment (body phantom:
+// 8 -> 4 nodes per lane saves 0.3 ms per solve, 2 is no better than 4).
+constexpr int SMALL_NB = 8192;
+constexpr int ZPL_SMALL = 4;
+
+template <typename T, typename TB, int ZPL, bool LABEL>
+static void cheb_first_z(const OpArgs<T> &op, Topo topo, const TB *b, T *x, T c0, const Scal *sc, const Batch &bt,
+                         hipStream_t s)
+{
+    SPFD_LAUNCH((k_col_cheb_first<T, TB, ZPL, LABEL>), col_grid<ZPL>(topo.nb, bt.n), dim3(CTHREADS), 0, s, op, topo,
+                b, x, c0, sc, bt.vs);
+}
+
 template <typename T, typename TB>
 hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, T c0, const Scal *sc, const Batch &bt,
                              hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    constexpr int ZPL_CYCLE = zpl_cycle<T>();
-    const dim3 g = col_grid<ZPL_CYCLE>(topo.nb, bt.n);
-    if (op.w)
-        SPFD_LAUNCH((k_col_cheb_first<T, TB, ZPL_CYCLE, false>), g, dim3(CTHREADS), 0, s, op, topo, b, x, c0, sc,
-                           bt.vs);
+    constexpr int Z = zpl_cycle<T>();
+    if (!op.w)
+        cheb_first_z<T, TB, Z, true>(op, topo, b, x, c0, sc, bt, s);
+    else if (topo.nb < SMALL_NB)
+        cheb_first_z<T, TB, ZPL_SMALL, false>(op, topo, b, x, c0, sc, bt, s);
     else
-        SPFD_LAUNCH((k_col_cheb_first<T, TB, ZPL_CYCLE, true>), g, dim3(CTHREADS), 0, s, op, topo, b, x, c0, sc,
-                           bt.vs);
+        cheb_first_z<T, TB, Z, false>(op, topo, b, x, c0, sc, bt, s);
     return hipGetLastError();
+}
+
+template <typename T, typename TB, int ZPL, bool LAB, bool PRO, bool DOT>
+static void cheb_step_z(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din, T *dout,
+                        T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s, const Prolong &pr, Dots dt)
+{
+    dt.nparts = col_ngroups<ZPL>(topo.nb);
+    SPFD_LAUNCH((k_col_cheb_step<T, TB, ZPL, LAB, PRO, DOT>), col_grid<ZPL>(topo.nb, bt.n), dim3(CTHREADS), 0, s, op,
+                topo, b, xin, xout, din, dout, c1, c2, sc, bt.vs, pr, dt);
 }
 
 template <typename T, typename TB>
@@ -728,25 +751,28 @@ hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T
     if (xin == xout) return hipErrorInvalidValue;
     if (xc && !(parent_slot && fcoord)) return hipErrorInvalidValue;
     if (dot_part && !dot_q) return hipErrorInvalidValue;
-    constexpr int ZPL = zpl_cycle<T>();
-    const dim3 g = col_grid<ZPL>(topo.nb, bt.n);
+    constexpr int Z = zpl_cycle<T>();
     const Prolong pr{xc, parent_slot, fcoord, (double)pscale, bt.vsc};
-    const Dots dt{dot_q, dot_part, bt.ps, col_ngroups<ZPL>(topo.nb)};
-    const int sel = (op.w ? 0 : 4) | (xc ? 2 : 0) | (dot_part ? 1 : 0);
-#define SPFD_CHEB_CASE(K, LAB, PRO, DOT)                                                                              \
+    const Dots dt{dot_q, dot_part, bt.ps, 0};
+    // the dot-product partials are counted by cheb_dot_parts (segment length Z)
+    const bool small = op.w && !dot_part && topo.nb < SMALL_NB;
+    const int sel = (small ? 8 : 0) | (op.w ? 0 : 4) | (xc ? 2 : 0) | (dot_part ? 1 : 0);
+#define SPFD_CHEB_CASE(K, ZZ, LAB, PRO, DOT)                                                                          \
     case K:                                                                                                           \
-        SPFD_LAUNCH((k_col_cheb_step<T, TB, ZPL, LAB, PRO, DOT>), g, dim3(CTHREADS), 0, s, op, topo, b, xin, xout,   \
-                    din, dout, c1, c2, sc, bt.vs, pr, dt);                                                            \
+        cheb_step_z<T, TB, ZZ, LAB, PRO, DOT>(op, topo, b, xin, xout, din, dout, c1, c2, sc, bt, s, pr, dt);         \
         break;
     switch (sel) {
-        SPFD_CHEB_CASE(0, false, false, false)
-        SPFD_CHEB_CASE(1, false, false, true)
-        SPFD_CHEB_CASE(2, false, true, false)
-        SPFD_CHEB_CASE(3, false, true, true)
-        SPFD_CHEB_CASE(4, true, false, false)
-        SPFD_CHEB_CASE(5, true, false, true)
-        SPFD_CHEB_CASE(6, true, true, false)
-        SPFD_CHEB_CASE(7, true, true, true)
+        SPFD_CHEB_CASE(0, Z, false, false, false)
+        SPFD_CHEB_CASE(1, Z, false, false, true)
+        SPFD_CHEB_CASE(2, Z, false, true, false)
+        SPFD_CHEB_CASE(3, Z, false, true, true)
+        SPFD_CHEB_CASE(4, Z, true, false, false)
+        SPFD_CHEB_CASE(5, Z, true, false, true)
+        SPFD_CHEB_CASE(6, Z, true, true, false)
+        SPFD_CHEB_CASE(7, Z, true, true, true)
+        SPFD_CHEB_CASE(8, ZPL_SMALL, false, false, false)
+        SPFD_CHEB_CASE(10, ZPL_SMALL, false, true, false)
+    default: return hipErrorInvalidValue;
     }
 #undef SPFD_CHEB_CASE
     return hipGetLastError();
@@ -760,6 +786,15 @@ int cheb_dot_parts(int nb)
 template int cheb_dot_parts<float>(int);
 template int cheb_dot_parts<double>(int);
 
+template <typename T, typename TB, int ZPL, bool LABEL>
+static void resid_restrict_z(const OpArgs<T> &op, Topo topo, const TB *b, const T *x, T *bc, const int *parent_slot,
+                             const int4 *fcoord, const Scal *sc, const Batch &bt, hipStream_t s, T *xc,
+                             const T *dinv_c, T c0)
+{
+    SPFD_LAUNCH((k_col_resid_restrict<T, TB, ZPL, LABEL>), col_grid<ZPL>(topo.nb, bt.n), dim3(CTHREADS), 0, s, op,
+                topo, b, x, bc, parent_slot, fcoord, sc, bt.vs, bt.vsc, xc, dinv_c, c0);
+}
+
 template <typename T, typename TB>
 hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, const T *x, T *bc, const int *parent_slot,
                                  const int4 *fcoord, const Scal *sc, const Batch &bt, hipStream_t s, T *xc,
@@ -767,14 +802,13 @@ hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, co
 {
     if (xc && !dinv_c) return hipErrorInvalidValue;
     if (topo.nb <= 0) return hipSuccess;
-    constexpr int ZPL_CYCLE = zpl_cycle<T>();
-    const dim3 g = col_grid<ZPL_CYCLE>(topo.nb, bt.n);
-    if (op.w)
-        SPFD_LAUNCH((k_col_resid_restrict<T, TB, ZPL_CYCLE, false>), g, dim3(CTHREADS), 0, s, op, topo, b, x,
-                           bc, parent_slot, fcoord, sc, bt.vs, bt.vsc, xc, dinv_c, c0);
+    constexpr int Z = zpl_cycle<T>();
+    if (!op.w)
+        resid_restrict_z<T, TB, Z, true>(op, topo, b, x, bc, parent_slot, fcoord, sc, bt, s, xc, dinv_c, c0);
+    else if (topo.nb < SMALL_NB)
+        resid_restrict_z<T, TB, ZPL_SMALL, false>(op, topo, b, x, bc, parent_slot, fcoord, sc, bt, s, xc, dinv_c, c0);
     else
-        SPFD_LAUNCH((k_col_resid_restrict<T, TB, ZPL_CYCLE, true>), g, dim3(CTHREADS), 0, s, op, topo, b, x,
-                           bc, parent_slot, fcoord, sc, bt.vs, bt.vsc, xc, dinv_c, c0);
+        resid_restrict_z<T, TB, Z, false>(op, topo, b, x, bc, parent_slot, fcoord, sc, bt, s, xc, dinv_c, c0);
     return hipGetLastError();
 }
 
