@@ -1348,7 +1348,7 @@ void resid_b(Ctx *c, const double *b, long long bvs, Scal *sc, double *r, int mo
         HIPCHK(launch_resid(level_op<double>(c, 0), L0.topo(), b, c->d_x, r, c->d_part, bvs, level_batch(c, 0, nb),
                             c->stream));
     }
-    finish(c, L0.nb, mode == 0 ? FIN_RESID0 : FIN_RESID1, sc, 0, nb);
+    finish(c, cg_step_parts(L0.nb), mode == 0 ? FIN_RESID0 : FIN_RESID1, sc, 0, nb);
 }
 
 
@@ -1384,25 +1384,23 @@ spfd_status solve_batch(Ctx *c, const double *b, long long bvs, Scal *sc, Scal *
             HIPCHK(hipMemcpyAsync(c->d_r + i * n0, b + i * bvs, n0 * sizeof(double), hipMemcpyDeviceToDevice,
                                   c->stream));
     }
-    HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    // no host round trip here: a right side that is already done (b = 0, or an exact x0) stops the
+    // kernels through its device-side flag, and ||b||^2 comes back with the final scalars
     std::vector<double> bb(nb), relres(nb, 0.0);
     std::vector<int> status(nb, 0), iters(nb, 0);
-    bool any = false;
-    for (int i = 0; i < nb; ++i) {
-        bb[i] = hsc[i].bb;
-        any = any || !hsc[i].done;
-    }
+    bool any = true;
     int *again = c->d_again;
     for (int pass = 0; pass < 3 && any; ++pass) {
         krylov_iterations(c, b, bvs, sc, nb, so);
-        // true residual of every iterate (also of those that converged in an earlier pass)
-        resid_b(c, b, bvs, sc, c->d_r, 1, nb);
+        // true residual of every iterate (also of those that converged in an earlier pass); r itself is
+        // only needed for a restart and is formed again then
+        resid_b(c, b, bvs, sc, nullptr, 1, nb);
         HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         any = false;
         std::vector<int> redo(nb, 0);
         for (int i = 0; i < nb; ++i) {
+            bb[i] = hsc[i].bb;
             relres[i] = bb[i] > 0.0 ? sqrt(hsc[i].zq / bb[i]) : 0.0;
             status[i] = hsc[i].status;
             iters[i] = hsc[i].iters;
@@ -1413,6 +1411,7 @@ spfd_status solve_batch(Ctx *c, const double *b, long long bvs, Scal *sc, Scal *
             }
         }
         if (any) {
+            resid_b(c, b, bvs, sc, c->d_r, 1, nb);
             HIPCHK(hipMemcpyAsync(again, redo.data(), nb * sizeof(int), hipMemcpyHostToDevice, c->stream));
             hipLaunchKernelGGL(k_rearm_if, dim3(1), dim3(64), 0, c->stream, sc, so.rel_tol, nb, again);
             HIPCHK(hipGetLastError());

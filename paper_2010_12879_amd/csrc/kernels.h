@@ -164,7 +164,8 @@ hipError_t launch_x_final(Topo topo, double *x, const double *pa, const double *
                           hipStream_t s);
 hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, Scal *sc, const Batch &bt, float *r32,
                           hipStream_t s);
-// b has its own batch stride bvs (the right sides may live apart from the solve vectors)
+// r = b - A x (r nullable) and the partials of ||r||^2 (cg_step_parts(nb) per right side).  b has its own
+// batch stride bvs (the right sides may live apart from the solve vectors).
 hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,
                         double *part, long long bvs, const Batch &bt, hipStream_t s);
 template <typename TZ>

@@ -1025,49 +1025,6 @@ hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, S
     return hipGetLastError();
 }
 
-// r = b - A x (r may be null) and the partials of ||r||^2.  mode 0: start of a
-// warm-started solve; mode 1: true residual at the end (stored in sc->zq).
-__global__ __launch_bounds__(NT) void k_resid(OpArgs<double> op, Topo topo, const double *__restrict__ b,
-                                              const double *__restrict__ x, double *__restrict__ r, double *part,
-                                              long long bvs, long long vs, int ps)
-{
-    __shared__ double tile[TILE_VOX + 7];
-    __shared__ double red[8];
-    const int bk = xcd_brick(blockIdx.x, topo.nb);
-    if (bk < 0) return;
-    b += blockIdx.y * bvs;
-    x += blockIdx.y * vs;
-    if (r) r += blockIdx.y * vs;
-    part += (long long)blockIdx.y * ps;
-    int nb[6];
-    brick_nbrs(topo.nbr, bk, nb);
-    const int t = threadIdx.x;
-    int tx, ty, tz;
-    brick_xyz(t, tx, ty, tz);
-    const long long base = (long long)bk * BS;
-    long long I[6];
-    nbr_index(base, t, tx, ty, tz, nb, I);
-    double X[6];
-    nbr_vals(x, I, X);
-    const double x0 = x[base + t], bv = b[base + t];
-    op_stage(op, bk, tile);
-    double W[6];
-    op_weights(op, tile, base, t, tx, ty, tz, I, W);
-    const double rv = bv - stencil_apply(x0, X, W);
-    if (r) r[base + t] = rv;
-    const double tot = block_sum(rv * rv, red);
-    if (t == 0) part[bk] = tot;
-}
-
-hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,
-                        double *part, long long bvs, const Batch &bt, hipStream_t s)
-{
-    if (topo.nb <= 0) return hipSuccess;
-    SPFD_LAUNCH(k_resid, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, op, topo, b, x, r, part, bvs, bt.vs,
-                       bt.ps);
-    return hipGetLastError();
-}
-
 // partials of r.z and z.q (flexible beta follows in k_finish)
 template <typename TZ>
 __global__ __launch_bounds__(NT) void k_dots(Topo topo, const TZ *__restrict__ z, const double *__restrict__ r,
@@ -1288,13 +1245,12 @@ __global__ void k_psi_out(const double *__restrict__ x, const int *__restrict__ 
     for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
         const int i = (int)(n % g.Nx), j = (int)((n / g.Nx) % g.Ny), k = (int)(n / ((long long)g.Nx * g.Ny));
         const int sl = slot_of[(i >> 3) + g.Gx * ((j >> 3) + g.Gy * (k >> 3))];
-        double v = 0.0;
-        if (sl >= 0) {
-            const long long idx = (long long)sl * BS + (i & 7) + 8 * (j & 7) + 64 * (k & 7);
-            const int c = comp[idx];
-            if (c >= 0) v = x[idx] - means[c];
-        }
-        psi[n] = v;
+        // both loads issued together (slot 0 stands in outside the bricks), then masked
+        const long long idx = sl >= 0 ? (long long)sl * BS + (i & 7) + 8 * (j & 7) + 64 * (k & 7) : 0;
+        const int c = comp[idx];
+        const double xv = x[idx];
+        const double m = means[c >= 0 ? c : 0];
+        psi[n] = (sl >= 0 && c >= 0) ? xv - m : 0.0;
     }
 }
 

@@ -655,6 +655,55 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
     }
 }
 
+// ---------------------------------------------------------------- true residual
+// r = b - A x (FP64 operator, r nullable) and the partials of ||r||^2, one per
+// workgroup.  (The CG's deferred x update is applied before this kernel: here
+// waves read x at the neighbours of their segments while others would store.)
+template <int ZPL, bool LABEL>
+__global__ __launch_bounds__(CTHREADS) void k_col_resid(OpArgs<double> op, Topo topo, const double *__restrict__ b,
+                                                        const double *__restrict__ x, double *__restrict__ r,
+                                                        double *part, long long bvs, long long vs, int ps)
+{
+    double *lds = col_lds<double, ZPL, LABEL>();
+    __shared__ double red[CWAVES];
+    const Seg<ZPL> s = make_seg<ZPL>(topo);
+    if (s.grp < 0) return;
+    double rr = 0.0;
+    if (s.bk >= 0) {
+        b += blockIdx.y * bvs;
+        x += blockIdx.y * vs;
+        if (r) r += blockIdx.y * vs;
+        SegOp<double, ZPL, LABEL> A;
+        A.load(op, s, lds);
+        SegVals<double, ZPL> X;
+        X.load(x, s);
+        double bv[ZPL];
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) bv[z] = b[s.self + 64 * z];
+        A.stage(op, s);
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) {
+            double W[6], N[6];
+            A.weights(s, z, W);
+            X.nbrs(s, z, N);
+            const double rv = bv[z] - stencil_apply(X.c[z], N, W);
+            if (s.active) {
+                if (r) r[s.self + 64 * z] = rv;
+                rr += rv * rv;
+            }
+        }
+    }
+    rr = wave_sum(rr);
+    if (s.lane == 0) red[threadIdx.x >> 6] = rr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < CWAVES; ++w) t += red[w];
+        part[(long long)blockIdx.y * ps + s.grp] = t;
+    }
+}
+
 // ---------------------------------------------------------------- plain operator application
 // w = A z (FP64 operator, z in the cycle's precision): the Krylov vector of
 // the flexible GMRES outer solver
@@ -826,6 +875,18 @@ hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, cons
     else
         SPFD_LAUNCH((k_col_cg_step<TZ, ZPL_CG, true>), g, dim3(CTHREADS), 0, s, op, topo, z, pin, pout, x, q,
                            part, sc, first, parity, bt.vs, bt.ps);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,
+                        double *part, long long bvs, const Batch &bt, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    const dim3 g = col_grid<ZPL_CG>(topo.nb, bt.n);
+    if (op.w)
+        SPFD_LAUNCH((k_col_resid<ZPL_CG, false>), g, dim3(CTHREADS), 0, s, op, topo, b, x, r, part, bvs, bt.vs, bt.ps);
+    else
+        SPFD_LAUNCH((k_col_resid<ZPL_CG, true>), g, dim3(CTHREADS), 0, s, op, topo, b, x, r, part, bvs, bt.vs, bt.ps);
     return hipGetLastError();
 }
 
