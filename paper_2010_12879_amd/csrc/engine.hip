@@ -530,10 +530,22 @@ void smooth_pre(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc, 
     // first_done: the restriction that produced b already stored the first step in cur
     const int m = level_degree(c, l);
     T *d = (T *)c->lv[l].d;
-    // (folding the first step into the second on the finest level, x = c0 D^-1 b formed at every node
-    // read, was measured slower: it doubles the lateral loads)
-    if (!first_done) cheb_first<T, TB>(c, l, b, cur, sc, nb);
-    for (int k = 1; k < m; ++k) {
+    int k0 = 1;
+    if (!first_done && l == 0 && m >= 2) {
+        // the first two steps in one pass on the finest level (x1 formed where read: one kernel and one
+        // write and read of x1 less; 53 -> 45 us per cycle on the body phantom)
+        Level &L = c->lv[0];
+        TScope ts(c, SPFD_K_SMOOTH0, nb * (double)L.dofs * (sizeof(TB) + op_bytes<T>(c, 0) + 2.0 * sizeof(T)) +
+                                         nb * (double)L.dofs * (m > 2 ? sizeof(T) : 0.0));
+        HIPCHK(launch_cheb_first2<T, TB>(level_op<T>(c, 0), L.topo(), b, dinv_of<T>(L), other, m > 2 ? d : nullptr,
+                                         (T)c->cheb_c0, (T)c->cheb_c1[1], (T)c->cheb_c2[1], sc, level_batch(c, 0, nb),
+                                         c->stream));
+        T *t = cur; cur = other; other = t;
+        k0 = 2;
+    } else if (!first_done) {
+        cheb_first<T, TB>(c, l, b, cur, sc, nb);
+    }
+    for (int k = k0; k < m; ++k) {
         cheb_step<T, TB>(c, l, b, cur, other, k == 1 ? nullptr : d, k < m - 1 ? d : nullptr, (T)c->cheb_c1[k],
                          (T)c->cheb_c2[k], sc, nb);
         T *t = cur; cur = other; other = t;

@@ -179,6 +179,10 @@ hipError_t launch_pupdate(Topo topo, const TZ *z, double *p, const Scal *sc, int
 template <typename T, typename TB>
 hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, T c0, const Scal *sc,
                              const Batch &bt, hipStream_t s);
+// the first two Chebyshev steps from zero in one pass (x1 = c0 dinv b formed where read, never stored)
+template <typename T, typename TB>
+hipError_t launch_cheb_first2(const OpArgs<T> &op, Topo topo, const TB *b, const T *dinv, T *xout, T *dout, T c0,
+                              T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s);
 // xc != nullptr: xin is first corrected by pscale * P xc from the structured
 // coarser level (parent_slot / fcoord of this level), i.e. the prolongation
 // fused into the step.  dot_part != nullptr: the step also writes the

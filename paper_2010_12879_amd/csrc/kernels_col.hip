@@ -342,6 +342,61 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo 
     }
 }
 
+// The first two Chebyshev steps from a zero start in one pass: the first step
+// x1 = c0 D^-1 b is formed wherever the second step reads it (own segment,
+// face columns, z ends; D^-1 from the stored inverse diagonal, so every wave
+// forms the same value for a node) and never stored; then
+//   r = b - A x1, d = c1 x1 + c2 D^-1 r, xout = x1 + d (dout = d if given).
+template <typename T, typename TB, int ZPL, bool LABEL>
+__global__ __launch_bounds__(CTHREADS) void k_col_cheb_first2(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
+                                                              const T *__restrict__ dinv, T *__restrict__ xout,
+                                                              T *__restrict__ dout, T c0, T c1, T c2, const Scal *sc,
+                                                              long long vs)
+{
+    T *lds = col_lds<T, ZPL, LABEL>();
+    const Seg<ZPL> s = make_seg<ZPL>(topo);
+    if (s.bk < 0) return;
+    const bool done = col_stopped(sc);
+    b += blockIdx.y * vs;
+    xout += blockIdx.y * vs;
+    if (dout) dout += blockIdx.y * vs;
+    SegOp<T, ZPL, LABEL> A;
+    A.load(op, s, lds);
+    SegVals<TB, ZPL> B;
+    B.load(b, s);
+    SegVals<T, ZPL> DI;
+    DI.load(dinv, s);
+    // x1 on the segment, the face columns and the z ends (0 where nothing is read)
+    SegVals<T, ZPL> X;
+#pragma unroll
+    for (int z = 0; z < ZPL; ++z) {
+        X.c[z] = c0 * (T)B.c[z] * DI.c[z];
+        X.ex[z] = c0 * (T)B.ex[z] * DI.ex[z];
+        X.ey[z] = c0 * (T)B.ey[z] * DI.ey[z];
+    }
+    X.zm = c0 * (T)B.zm * DI.zm;
+    X.zp = c0 * (T)B.zp * DI.zp;
+    A.stage(op, s);
+    if (done) return;
+#pragma unroll
+    for (int z = 0; z < ZPL; ++z) {
+        T W[6], N[6];
+        A.weights(s, z, W);
+        X.nbrs(s, z, N);
+        const T D = diag_of(W);
+        T xo = T(0), dn = T(0);
+        if (s.active && D > T(0)) {
+            const T r = (T)B.c[z] - stencil_apply(X.c[z], N, W);
+            dn = c1 * X.c[z] + c2 * r / D;
+            xo = X.c[z] + dn;
+        }
+        if (s.active) {
+            xout[s.self + 64 * z] = xo;
+            if (dout) dout[s.self + 64 * z] = dn;
+        }
+    }
+}
+
 // Coarse-grid correction of a structured level, x += scale * P x_c, applied
 // to the values a segment reads: the coarse node of fine node (tx,ty,tz) of
 // brick b is node (4 (f.x & 1) + tx/2, ...) of the parent brick, f = coord of b.
@@ -781,6 +836,22 @@ hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, 
     return hipGetLastError();
 }
 
+template <typename T, typename TB>
+hipError_t launch_cheb_first2(const OpArgs<T> &op, Topo topo, const TB *b, const T *dinv, T *xout, T *dout, T c0,
+                              T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    if (!dinv) return hipErrorInvalidValue;
+    constexpr int Z = zpl_cycle<T>();
+    if (op.w)
+        SPFD_LAUNCH((k_col_cheb_first2<T, TB, Z, false>), col_grid<Z>(topo.nb, bt.n), dim3(CTHREADS), 0, s, op, topo,
+                    b, dinv, xout, dout, c0, c1, c2, sc, bt.vs);
+    else
+        SPFD_LAUNCH((k_col_cheb_first2<T, TB, Z, true>), col_grid<Z>(topo.nb, bt.n), dim3(CTHREADS), 0, s, op, topo,
+                    b, dinv, xout, dout, c0, c1, c2, sc, bt.vs);
+    return hipGetLastError();
+}
+
 template <typename T, typename TB, int ZPL, bool LAB, bool PRO, bool DOT>
 static void cheb_step_z(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din, T *dout,
                         T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s, const Prolong &pr, Dots dt)
@@ -910,6 +981,8 @@ template hipError_t launch_spmv<float>(const OpArgs<double> &, Topo, const float
 #define SPFD_INST_COL(T, TB)                                                                                          \
     template hipError_t launch_cheb_first<T, TB>(const OpArgs<T> &, Topo, const TB *, T *, T, const Scal *,       \
                                                  const Batch &, hipStream_t);                                       \
+    template hipError_t launch_cheb_first2<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *, T *, T, T, T, \
+                                                  const Scal *, const Batch &, hipStream_t);                        \
     template hipError_t launch_cheb_step<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *, const T *, T *, \
                                                 T, T, const Scal *, const Batch &, hipStream_t, const T *,          \
                                                 const int *, const int4 *, T, const double *, double *);             \
