@@ -28,13 +28,12 @@ HBM_PEAK_GBS = 8000.0
 FINE_CLASSES = {0: "k_col_cg_step (outer CG: p, deferred x, q = A p, p.q)",
                 1: "k_rupdate (r -= alpha q, ||r||^2, FP32 copy of r)",
                 2: "k_col_cheb_step + CG dots (last post-smoothing step)",
-                4: "k_col_cheb_step (pre-smoothing step)",
-                5: "k_col_cheb_first (first Chebyshev step)",
+                4: "k_col_cheb_first2 (first two Chebyshev steps, the pre-smoothing)",
                 6: "k_col_resid_restrict (residual + restriction)",
                 7: "k_col_cheb_step + prolongation (first post-smoothing step)"}
 # rocprofv3 summaries under profiles/ (HBM bytes per launch from FETCH_SIZE / WRITE_SIZE)
-PROFILE_OF = {0: "k_col_cg_step", 1: "k_rupdate", 2: "k_col_cheb_step_dots", 4: "k_col_cheb_step",
-              5: "k_col_cheb_first", 6: "k_col_resid_restrict", 7: "k_col_cheb_step_prolong"}
+PROFILE_OF = {0: "k_col_cg_step", 1: "k_rupdate", 2: "k_col_cheb_step_dots", 4: "k_col_cheb_first2",
+              6: "k_col_resid_restrict", 7: "k_col_cheb_step_prolong"}
 KERNEL_SOURCES = ["paper_2010_12879_amd/csrc/kernels_col.hip", "paper_2010_12879_amd/csrc/kernels.hip",
                   "paper_2010_12879_amd/csrc/common.h", "paper_2010_12879_amd/csrc/kernels.h"]
 
