@@ -314,8 +314,13 @@ __global__ void k_cc_local(const double *__restrict__ w, long long stride, int *
     if (lp[t] >= 0) parent[base + t] = (int)base + lfind(lp, t);
 }
 
+// Unions across the three plus faces of a brick.  Most face edges join the
+// same pair of brick-local components as the face edge next to them: a face
+// node whose (own parent, neighbour's parent) pair equals that of the previous
+// node on the face skips its union (same sets, already joined or about to be).
 __global__ void k_cc_union(const double *__restrict__ w, long long stride, Topo topo, int *parent)
 {
+    __shared__ int la[BS], lb[BS];
     const int b = blockIdx.x, t = threadIdx.x;
     int nb[6];
     brick_nbrs(topo.nbr, b, nb);
@@ -323,9 +328,23 @@ __global__ void k_cc_union(const double *__restrict__ w, long long stride, Topo 
     brick_xyz(t, tx, ty, tz);
     const long long base = (long long)b * BS;
     const int me = (int)(base + t);
-    if (tx == 7 && nb[NPX] >= 0 && w[base + t] > 0.0) punite(parent, me, nb[NPX] * BS + t - 7);
-    if (ty == 7 && nb[NPY] >= 0 && w[stride + base + t] > 0.0) punite(parent, me, nb[NPY] * BS + t - 56);
-    if (tz == 7 && nb[NPZ] >= 0 && w[2 * stride + base + t] > 0.0) punite(parent, me, nb[NPZ] * BS + t - 448);
+    for (int d = 0; d < 3; ++d) {
+        const bool face = d == 0 ? tx == 7 : d == 1 ? ty == 7 : tz == 7;
+        const int nbk = nb[d == 0 ? NPX : d == 1 ? NPY : NPZ];
+        const int other = nbk * BS + t - (d == 0 ? 7 : d == 1 ? 56 : 448);
+        const bool edge = face && nbk >= 0 && w[d * stride + base + t] > 0.0;
+        la[t] = edge ? pload(parent, me) : -1;
+        lb[t] = edge ? pload(parent, other) : -1;
+        __syncthreads();
+        // previous node on the face: one step along its first in-face axis, else its second
+        int prev = -1;
+        if (d == 0) prev = ty > 0 ? t - 8 : (tz > 0 ? t - 64 : -1);
+        else if (d == 1) prev = tx > 0 ? t - 1 : (tz > 0 ? t - 64 : -1);
+        else prev = tx > 0 ? t - 1 : (ty > 0 ? t - 8 : -1);
+        const bool same = prev >= 0 && la[prev] == la[t] && lb[prev] == lb[t];
+        if (edge && !same) punite(parent, me, other);
+        __syncthreads();
+    }
 }
 
 __global__ void k_cc_flatten(int *parent, long long n, int *flag)
@@ -653,88 +672,106 @@ hipError_t launch_col_masks(const double *w64, long long stride, Topo topo, unsi
 // Make the coarsest matrix definite: A += sum over its connected components c
 // of (mean diagonal of c / |c|) 1_c 1_c^T.  For right sides with zero sum per
 // component the inverse of the result applies the pseudo-inverse and returns
-// the solution with zero sum per component.  (One workgroup: the components
-// by repeated minimum-label propagation over the dense pattern.)
+// the solution with zero sum per component.  Three kernels: the sparsity
+// pattern as adjacency lists (one wave per row, many workgroups), the
+// components by minimum-label propagation and their diagonal sums (one
+// workgroup), the rank-one updates (many workgroups).
 constexpr int CMAXADJ = 64;
 
-__global__ void k_coarse_regularize(int n, double *A, int *work)
+struct CoarseWork {
+    int *comp, *csize, *deg, *adj;  // labels, component sizes, row degree (-1: dense row), [n][CMAXADJ]
+    double *cdiag;                  // diagonal sum per component (indexed by the component's label)
+};
+
+__host__ __device__ inline CoarseWork coarse_work(int n, int *work)
 {
-    const int t = threadIdx.x, nt = blockDim.x;
-    int *comp = work;
-    int *csize = work + n;
-    double *colk = (double *)(work + 2 * n + ((2 * n) & 1));
-    int *deg = work + 4 * n + 2;          // row degree (-1: more than CMAXADJ, scan the dense row)
-    int *adj = deg + n;                   // [n][CMAXADJ] off-diagonal nonzero columns
-    __shared__ int changed;
-    // the pattern once, as adjacency lists: one wave per row, 64 columns per step
-    const int lane = t & 63, nw = nt >> 6;
-    for (int q = t >> 6; q < n; q += nw) {
-        if (lane == 0) {
-            comp[q] = q;
-            csize[q] = 0;
-        }
-        int d = 0;
-        for (int m0 = 0; m0 < n; m0 += 64) {
-            const int m = m0 + lane;
-            const bool nz = m < n && m != q && A[(long long)q * n + m] != 0.0;
-            const unsigned long long bal = __ballot(nz);
-            const int pos = d + __popcll(bal & ((1ull << lane) - 1ull));
-            if (nz && d >= 0 && pos < CMAXADJ) adj[(long long)q * CMAXADJ + pos] = m;
-            if (d >= 0) d += __popcll(bal);
-            if (d > CMAXADJ) d = -1;
-        }
-        if (lane == 0) deg[q] = d;
+    CoarseWork w;
+    w.comp = work;
+    w.csize = work + n;
+    w.cdiag = (double *)(work + 2 * n + ((2 * n) & 1));
+    w.deg = work + 4 * n + 2;
+    w.adj = w.deg + n;
+    return w;
+}
+
+__global__ __launch_bounds__(256) void k_creg_pattern(int n, const double *__restrict__ A, int *work)
+{
+    const CoarseWork w = coarse_work(n, work);
+    const int lane = threadIdx.x & 63;
+    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= n) return;
+    if (lane == 0) {
+        w.comp[q] = q;
+        w.csize[q] = 0;
     }
-    __syncthreads();
+    int d = 0;
+    for (int m0 = 0; m0 < n; m0 += 64) {
+        const int m = m0 + lane;
+        const bool nz = m < n && m != q && A[(long long)q * n + m] != 0.0;
+        const unsigned long long bal = __ballot(nz);
+        const int pos = d + __popcll(bal & ((1ull << lane) - 1ull));
+        if (nz && d >= 0 && pos < CMAXADJ) w.adj[(long long)q * CMAXADJ + pos] = m;
+        if (d >= 0) d += __popcll(bal);
+        if (d > CMAXADJ) d = -1;
+    }
+    if (lane == 0) w.deg[q] = d;
+}
+
+__global__ __launch_bounds__(1024) void k_creg_components(int n, const double *__restrict__ A, int *work)
+{
+    const CoarseWork w = coarse_work(n, work);
+    const int t = threadIdx.x, nt = blockDim.x;
+    __shared__ int changed;
     // minimum label over each component: neighbour minima plus pointer jumping
     do {
         __syncthreads();
         if (t == 0) changed = 0;
         __syncthreads();
         for (int q = t; q < n; q += nt) {
-            int c = __hip_atomic_load(comp + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            const int d = deg[q];
+            int c = __hip_atomic_load(w.comp + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int d = w.deg[q];
             const int cnt = d >= 0 ? d : n;
             for (int k = 0; k < cnt; ++k) {
-                const int m = d >= 0 ? adj[(long long)q * CMAXADJ + k] : k;
+                const int m = d >= 0 ? w.adj[(long long)q * CMAXADJ + k] : k;
                 if (d < 0 && (m == q || A[(long long)q * n + m] == 0.0)) continue;
-                const int cm = __hip_atomic_load(comp + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const int cm = __hip_atomic_load(w.comp + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (cm < c) c = cm;
             }
-            const int cc = __hip_atomic_load(comp + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int cc = __hip_atomic_load(w.comp + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (cc < c) c = cc;
-            if (c < __hip_atomic_load(comp + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-                __hip_atomic_store(comp + q, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (c < __hip_atomic_load(w.comp + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                __hip_atomic_store(w.comp + q, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 changed = 1;
             }
         }
         __syncthreads();
     } while (changed);
-    for (int q = t; q < n; q += nt) atomicAdd(csize + comp[q], 1);
-    __syncthreads();
-    double *cdiag = colk;  // scratch before the elimination
-    for (int q = t; q < n; q += nt) cdiag[q] = 0.0;
-    __syncthreads();
+    for (int q = t; q < n; q += nt) atomicAdd(w.csize + w.comp[q], 1);
     // per-component diagonal sums in a fixed order (deterministic): diagonal and labels staged in LDS
     __shared__ double sdiag[1024], ssum[1024];
     __shared__ int scomp[1024];
     for (int q = t; q < n; q += nt) {
         sdiag[q] = A[(long long)q * n + q];
-        scomp[q] = comp[q];
+        scomp[q] = w.comp[q];
         ssum[q] = 0.0;
     }
     __syncthreads();
     if (t == 0)
         for (int q = 0; q < n; ++q) ssum[scomp[q]] += sdiag[q];
     __syncthreads();
-    for (int q = t; q < n; q += nt) cdiag[q] = ssum[q];
-    __syncthreads();
-    for (long long e = t; e < (long long)n * n; e += nt) {
+    for (int q = t; q < n; q += nt) w.cdiag[q] = ssum[q];
+}
+
+__global__ __launch_bounds__(256) void k_creg_update(int n, double *A, const int *work)
+{
+    const CoarseWork w = coarse_work(n, const_cast<int *>(work));
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < (long long)n * n;
+         e += (long long)gridDim.x * blockDim.x) {
         const int i = (int)(e / n), j = (int)(e % n);
-        const int c = scomp[i];
-        if (scomp[j] == c) {
-            const double sz = (double)csize[c];
-            A[e] += (ssum[c] / sz) / sz;
+        const int c = w.comp[i];
+        if (w.comp[j] == c) {
+            const double sz = (double)w.csize[c];
+            A[e] += (w.cdiag[c] / sz) / sz;
         }
     }
 }
@@ -752,7 +789,11 @@ size_t coarse_factor_work_ints(int n) { return (size_t)(5 + CMAXADJ) * n + 8; }
 hipError_t launch_coarse_factor(int n, double *A, int *work, double *dwork, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    SPFD_LAUNCH(k_coarse_regularize, dim3(1), dim3(1024), 0, s, n, A, work);
+    SPFD_LAUNCH(k_creg_pattern, dim3((n + 3) / 4), dim3(256), 0, s, n, A, work);
+    SPFD_LAUNCH(k_creg_components, dim3(1), dim3(1024), 0, s, n, A, work);
+    const long long nn = (long long)n * n;
+    SPFD_LAUNCH(k_creg_update, dim3((unsigned)((nn + 255) / 256 > 4096 ? 4096 : (nn + 255) / 256)), dim3(256), 0, s,
+                n, A, work);
     HIP_RETURN_IF(hipGetLastError());
     return launch_dense_inverse(n, A, dwork, s);
     return hipGetLastError();
