@@ -1284,8 +1284,12 @@ void fgmres_iterations(Ctx *c, const double *b, long long bvs, Scal *sc, const s
         HIPCHK(launch_fg_scale(c->d_r, V, v32, n0, st, sc, c->stream));
     }
     if (poll()) return;
-    int j = 0;
-    for (;;) {
+    // Columns run one ahead of the host's check, as the CG steps do: column j+1
+    // is enqueued before the host reads the stop test of column j (a column
+    // after the last one finds the stop flag and stores nothing), unless the
+    // residual estimates predict that column j ends the solve, or j ends the cycle.
+    Scal *ring[2] = {c->h_ring, c->h_ring + 1};
+    auto enqueue_column = [&](int j) {
         T *zj = Z + (long long)j * n0;
         if (mixed)
             vcycle<T, float>(c, v32, zj, sc, 1);
@@ -1316,14 +1320,35 @@ void fgmres_iterations(Ctx *c, const double *b, long long bvs, Scal *sc, const s
             TScope ts(c, SPFD_K_UPDATE, nd * (16.0 + (mixed ? 4.0 : 0.0)));
             HIPCHK(launch_fg_scale(w, V + (long long)nv * n0, v32, n0, st, sc, c->stream));
         }
-        const bool done = poll();
-        j = nv;
-        if (!done && j < m) continue;
-        // end of a cycle: x += Z y
-        HIPCHK(launch_fg_ysolve(st, j, c->stream));
+        HIPCHK(hipMemcpyAsync(ring[j & 1], sc, sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipEventRecord(c->ev_it[j & 1], c->stream));
+    };
+    double rr1 = -1.0, rr2 = -1.0;  // residual estimates of the last two columns seen
+    int j = 0, queued = -1;
+    for (;;) {
+        if (queued < j) {
+            enqueue_column(j);
+            queued = j;
+        }
+        const bool likely_last = rr1 > 0.0 && rr2 > 0.0 && rr1 * (rr1 / rr2) <= HOLD_MARGIN * ring[0]->tol2;
+        if (j + 1 < m && !likely_last) {
+            enqueue_column(j + 1);
+            queued = j + 1;
+        }
+        HIPCHK(hipEventSynchronize(c->ev_it[j & 1]));
+        const bool done = ring[j & 1]->done != 0;
+        rr2 = rr1;
+        rr1 = ring[j & 1]->rr;
+        const int k = j + 1;
+        if (!done && k < m) {
+            j = k;
+            continue;
+        }
+        // end of a cycle or of the solve: x += Z y over the k columns formed
+        HIPCHK(launch_fg_ysolve(st, k, c->stream));
         {
-            TScope ts(c, SPFD_K_UPDATE, nd * (16.0 + j * (double)sizeof(T)));
-            HIPCHK(launch_fg_xupdate<T>(c->d_x, Z, n0, n0, j, st, c->stream));
+            TScope ts(c, SPFD_K_UPDATE, nd * (16.0 + k * (double)sizeof(T)));
+            HIPCHK(launch_fg_xupdate<T>(c->d_x, Z, n0, n0, k, st, c->stream));
         }
         if (done) return;
         // restart from the true residual
@@ -1335,6 +1360,8 @@ void fgmres_iterations(Ctx *c, const double *b, long long bvs, Scal *sc, const s
         }
         if (poll()) return;
         j = 0;
+        queued = -1;
+        rr1 = rr2 = -1.0;
     }
 }
 
