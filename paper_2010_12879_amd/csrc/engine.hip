@@ -131,6 +131,8 @@ struct Ctx {
     int nbat = 0;             // right sides the solve buffers hold
     int *d_ints = nullptr;    // small scratch ints
     int *h_ints = nullptr;    // pinned
+    uint8_t *h_stage = nullptr;   // pinned staging for the host-built tables of the hierarchy
+    size_t stage_cap = 0;
     // the library's own stream (all work) and the caller's stream it follows
     hipStream_t user_stream = nullptr;
     hipEvent_t ev_user = nullptr;
@@ -324,6 +326,22 @@ struct TScope {
 };
 
 // ------------------------------------------------------------ brick topology on the host
+// Pinned staging of at least `bytes` (copies from pageable memory go through a
+// slow bounce buffer).  Call only while nothing in the stream uses the previous area.
+uint8_t *stage(Ctx *c, size_t bytes)
+{
+    if (bytes > c->stage_cap) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (c->h_stage) (void)hipHostFree(c->h_stage);
+        c->h_stage = nullptr;
+        c->stage_cap = 0;
+        const size_t cap = std::max<size_t>(bytes, (size_t)4 << 20);
+        HIPCHK(hipHostMalloc((void **)&c->h_stage, cap, hipHostMallocDefault));
+        c->stage_cap = cap;
+    }
+    return c->h_stage;
+}
+
 void build_topology(Ctx *c, Level &L, const std::vector<uint8_t> &flags, std::vector<void *> &owner)
 {
     const int G0 = L.G[0], G1 = L.G[1], G2 = L.G[2];
@@ -357,10 +375,17 @@ void build_topology(Ctx *c, Level &L, const std::vector<uint8_t> &flags, std::ve
     L.d_slot_of = dalloc<int>(c, owner, L.slot_of.size());
     L.d_nbr = dalloc<int>(c, owner, nbr.size());
     L.d_coord = dalloc<int4>(c, owner, L.coord.size() + 1);
-    HIPCHK(hipMemcpyAsync(L.d_slot_of, L.slot_of.data(), L.slot_of.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(L.d_nbr, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
-    if (L.nb)
-        HIPCHK(hipMemcpyAsync(L.d_coord, L.coord.data(), L.coord.size() * sizeof(int4), hipMemcpyHostToDevice, c->stream));
+    // the three tables through one pinned staging area
+    const size_t b0 = L.slot_of.size() * sizeof(int), b1 = nbr.size() * sizeof(int),
+                 b2 = L.coord.size() * sizeof(int4);
+    const size_t o1 = (b0 + 255) & ~(size_t)255, o2 = o1 + ((b1 + 255) & ~(size_t)255);
+    uint8_t *st = stage(c, o2 + b2);
+    memcpy(st, L.slot_of.data(), b0);
+    memcpy(st + o1, nbr.data(), b1);
+    if (b2) memcpy(st + o2, L.coord.data(), b2);
+    HIPCHK(hipMemcpyAsync(L.d_slot_of, st, b0, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(L.d_nbr, st + o1, b1, hipMemcpyHostToDevice, c->stream));
+    if (L.nb) HIPCHK(hipMemcpyAsync(L.d_coord, st + o2, b2, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
 }
 
@@ -861,10 +886,11 @@ spfd_status do_build(Ctx *c)
     HIPCHK(hipMemsetAsync(c->d_ints, 0, 4 * sizeof(int), c->stream));
     HIPCHK(launch_brick_flags(c->d_labels, c->d_table64, c->nlab, c->voxel_mode ? c->d_sigvox : nullptr, g, d_flags,
                               c->d_ints, c->stream));
-    std::vector<uint8_t> flags(nbg);
-    HIPCHK(hipMemcpyAsync(flags.data(), d_flags, nbg, hipMemcpyDeviceToHost, c->stream));
+    uint8_t *hflags = stage(c, nbg);
+    HIPCHK(hipMemcpyAsync(hflags, d_flags, nbg, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(c->h_ints, c->d_ints, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    std::vector<uint8_t> flags(hflags, hflags + nbg);
     if (c->h_ints[0] == 1) return fail(c, SPFD_INVALID_ARG, "a voxel label is not covered by the sigma table");
     if (c->h_ints[0] == 2) return fail(c, SPFD_INVALID_ARG, "per-voxel sigma must be finite and >= 0");
     c->lv.emplace_back();
@@ -930,7 +956,11 @@ spfd_status do_build(Ctx *c)
             ps[s] = C.slot_of[(q.x >> 1) + (size_t)C.G[0] * ((q.y >> 1) + (size_t)C.G[1] * (q.z >> 1))];
         }
         F.d_parent_slot = dalloc<int>(c, c->hier_allocs, F.nb);
-        HIPCHK(hipMemcpyAsync(F.d_parent_slot, ps.data(), ps.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        {
+            uint8_t *st = stage(c, ps.size() * sizeof(int));  // (the stream is idle: topology just synced)
+            memcpy(st, ps.data(), ps.size() * sizeof(int));
+            HIPCHK(hipMemcpyAsync(F.d_parent_slot, st, ps.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        }
         C.d_w64 = dalloc<double>(c, c->hier_allocs, (size_t)3 * C.nodes());
         C.d_w32 = dalloc<float>(c, c->hier_allocs, (size_t)3 * C.nodes());
         HIPCHK(launch_galerkin(F.d_w64, F.nodes(), F.d_slot_of, F.G[0], F.G[1], F.G[2], F.N[0], F.N[1], F.N[2], C.d_coord,
@@ -1659,6 +1689,7 @@ void spfd_destroy(spfd_handle h)
     for (hipEvent_t e : h->ev_it)
         if (e) (void)hipEventDestroy(e);
     if (h->h_ints) (void)hipHostFree(h->h_ints);
+    if (h->h_stage) (void)hipHostFree(h->h_stage);
     for (int k = 0; k < SPFD_K_COUNT; ++k)
         for (hipEvent_t e : h->tev[k]) (void)hipEventDestroy(e);
     if (h->ev_user) (void)hipEventDestroy(h->ev_user);
