@@ -784,7 +784,10 @@ void alloc_cycle_buffers(Ctx *c, int nb)
     c->d_q = dalloc<double>(c, c->rhs_allocs, n0);
     c->d_z = dalloc<uint8_t>(c, c->rhs_allocs, n0 * w);
     c->d_r32 = mixed ? dalloc<float>(c, c->rhs_allocs, n0) : nullptr;
+    // every vector starts at zero: slots of node columns without unknowns are never written and must
+    // read as (finite) zeros, since stencils multiply them by conductance 0
     HIPCHK(hipMemsetAsync(c->d_z, 0, n0 * w, c->stream));
+    if (c->d_r32) HIPCHK(hipMemsetAsync(c->d_r32, 0, n0 * sizeof(float), c->stream));
     HIPCHK(hipMemsetAsync(c->d_p, 0, n0 * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(c->d_p2, 0, n0 * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(c->d_q, 0, n0 * sizeof(double), c->stream));
