@@ -112,6 +112,35 @@ def test_manufactured_solution(prec):
     assert _rel(u.cpu().numpy(), u_exact) <= BAR[prec] * 10
 
 
+def test_many_components_against_oracle():
+    """27 separate blocks (more than 16 components: the gauge takes its atomic per-component path),
+    blocks cut by brick faces, anisotropic voxels."""
+    print("case many components", flush=True)
+    rng = np.random.default_rng(77)
+    nx, ny, nz = 45, 41, 43
+    labels = np.zeros((nz, ny, nx), np.uint8)
+    for k in range(3):
+        for j in range(3):
+            for i in range(3):
+                x0, y0, z0 = 2 + 15 * i, 1 + 14 * j, 3 + 14 * k
+                labels[z0:z0 + 9, y0:y0 + 10, x0:x0 + 11] = rng.integers(1, 4, (9, 10, 11))
+    table = np.array([0.0, 0.3, 1.1, 0.05])
+    a = rng.normal(size=(3, nz + 1, ny + 1, nx + 1)) * 1e-6
+    w = W.Workload("blocks27", nx, ny, nz, (1e-3, 1.3e-3, 0.8e-3), labels, table, a)
+    sig = w.sigma_voxel()
+    comp, ncomp = oracle.components(sig, w.h)
+    assert ncomp == 27
+    ref, oinfo = oracle.solve(sig, w.h, w.a, tol=1e-12)
+    for prec in ("fp64", "mixed"):
+        psi, _, info, sinfo = _solve(w, prec)
+        assert sinfo["n_components"] == 27
+        assert info["status"] == "OK"
+        assert _rel(psi, ref) <= BAR[prec], prec
+        # zero mean on every component
+        for c in range(27):
+            assert abs(psi[comp == c].mean()) <= 1e-9 * np.abs(ref).max()
+
+
 def test_efield_kernel_matches_oracle_given_psi():
     print("case efield-only", flush=True)
     w = W.config(1)
