@@ -786,6 +786,8 @@ void alloc_cycle_buffers(Ctx *c, int nb)
     c->d_r32 = mixed ? dalloc<float>(c, c->rhs_allocs, n0) : nullptr;
     // every vector starts at zero: slots of node columns without unknowns are never written and must
     // read as (finite) zeros, since stencils multiply them by conductance 0
+    HIPCHK(hipMemsetAsync(c->d_x, 0, n0 * sizeof(double), c->stream));
+    HIPCHK(hipMemsetAsync(c->d_r, 0, n0 * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(c->d_z, 0, n0 * w, c->stream));
     if (c->d_r32) HIPCHK(hipMemsetAsync(c->d_r32, 0, n0 * sizeof(float), c->stream));
     HIPCHK(hipMemsetAsync(c->d_p, 0, n0 * sizeof(double), c->stream));

@@ -52,6 +52,19 @@ __device__ __forceinline__ T lane_get(T v, int src)
     return __shfl(v, src & 63, 64);
 }
 
+// 1/d: the hardware reciprocal in FP32 (about 1 ulp, the FP32 smoother's own
+// precision), a correctly rounded division in FP64
+template <typename T>
+__device__ __forceinline__ T recip(T d)
+{
+    return T(1) / d;
+}
+template <>
+__device__ __forceinline__ float recip<float>(float d)
+{
+    return __builtin_amdgcn_rcpf(d);
+}
+
 // Where a wave's segment lies.  Absent neighbour bricks hold no unknowns and
 // the edges into them have conductance 0: their values are never loaded and
 // read as 0.  Columns without unknowns likewise read as 0.
@@ -260,12 +273,14 @@ struct SegOp<T, ZPL, false> {
 };
 
 // values of x along the segment, the face lanes' columns in the neighbour
-// bricks (ex, ey) and the two z ends; 0 where nothing is to be read
+// bricks (ex, ey) and the two z ends.  Nothing is masked: a column without
+// unknowns reads the zeros its slots hold, and where a neighbour is absent
+// the value read is a finite stand-in (the lane's own slot) whose edge
+// weight is exactly 0, so every term W (x0 - N) it enters is 0.
 template <typename T, int ZPL>
 struct SegVals {
     T c[ZPL], ex[ZPL], ey[ZPL], zm, zp;
 
-    // unconditional loads, masked afterwards (as in the stored-form operator)
     __device__ __forceinline__ void load(const T *__restrict__ x, const Seg<ZPL> &s)
     {
 #pragma unroll
@@ -276,14 +291,6 @@ struct SegVals {
         }
         zm = x[s.zm];
         zp = x[s.zp];
-#pragma unroll
-        for (int z = 0; z < ZPL; ++z) {
-            c[z] = s.active ? c[z] : T(0);
-            ex[z] = s.active && s.bx ? ex[z] : T(0);
-            ey[z] = s.active && s.by ? ey[z] : T(0);
-        }
-        zm = s.active && s.has[NMZ] ? zm : T(0);
-        zp = s.active && s.has[NPZ] ? zp : T(0);
     }
 
     // the six neighbours of node z0+z; all 64 lanes of the wave must call this
@@ -330,7 +337,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo 
     for (int z = 0; z < ZPL; ++z) braw[z] = b[s.self + 64 * z];
     T bv[ZPL];
 #pragma unroll
-    for (int z = 0; z < ZPL; ++z) bv[z] = s.active ? (T)braw[z] : T(0);
+    for (int z = 0; z < ZPL; ++z) bv[z] = (T)braw[z];
     A.stage(op, s);
     if (done) return;
 #pragma unroll
@@ -338,7 +345,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo 
         T W[6];
         A.weights(s, z, W);
         const T D = diag_of(W);
-        if (s.active) x[s.self + 64 * z] = D > T(0) ? c0 * bv[z] / D : T(0);
+        if (s.active) x[s.self + 64 * z] = D > T(0) ? c0 * bv[z] * recip(D) : T(0);
     }
 }
 
@@ -366,7 +373,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first2(OpArgs<T> op, Topo
     B.load(b, s);
     SegVals<T, ZPL> DI;
     DI.load(dinv, s);
-    // x1 on the segment, the face columns and the z ends (0 where nothing is read)
+    // x1 on the segment, the face columns and the z ends
     SegVals<T, ZPL> X;
 #pragma unroll
     for (int z = 0; z < ZPL; ++z) {
@@ -383,11 +390,12 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first2(OpArgs<T> op, Topo
         T W[6], N[6];
         A.weights(s, z, W);
         X.nbrs(s, z, N);
-        const T D = diag_of(W);
+        // the stored inverse diagonal (0 where the diagonal vanishes), as in x1
+        const T di = DI.c[z];
         T xo = T(0), dn = T(0);
-        if (s.active && D > T(0)) {
+        if (s.active && di > T(0)) {
             const T r = (T)B.c[z] - stencil_apply(X.c[z], N, W);
-            dn = c1 * X.c[z] + c2 * r / D;
+            dn = c1 * X.c[z] + c2 * r * di;
             xo = X.c[z] + dn;
         }
         if (s.active) {
@@ -422,7 +430,7 @@ template <typename T, int ZPL>
 __device__ __forceinline__ void apply_prolong(const Prolong &pr, const Topo &topo, const Seg<ZPL> &s,
                                               SegVals<T, ZPL> &X)
 {
-    // every lane loads, the corrections are masked (see SegVals::load)
+    // every lane loads from a valid slot
     const T *xc = (const T *)pr.xc + blockIdx.y * pr.vsc;
     const T sc = (T)pr.scale;
     int nb[6];
@@ -445,15 +453,15 @@ __device__ __forceinline__ void apply_prolong(const Prolong &pr, const Topo &top
         vy[h] = xc[cy + 64 * h];
     }
     const T vm = xc[czm], vp = xc[czp];
-    const bool a = s.active;
+    // unmasked, like SegVals: a stand-in value only meets edge weights of 0
 #pragma unroll
     for (int z = 0; z < ZPL; ++z) {
-        X.c[z] += a ? sc * v0[z >> 1] : T(0);
-        X.ex[z] += a && s.bx ? sc * vx[z >> 1] : T(0);
-        X.ey[z] += a && s.by ? sc * vy[z >> 1] : T(0);
+        X.c[z] += sc * v0[z >> 1];
+        X.ex[z] += sc * vx[z >> 1];
+        X.ey[z] += sc * vy[z >> 1];
     }
-    X.zm += a && s.has[NMZ] ? sc * vm : T(0);
-    X.zp += a && s.has[NPZ] ? sc * vp : T(0);
+    X.zm += sc * vm;
+    X.zp += sc * vp;
 }
 
 // Dot products of the outer flexible CG that ride on the last finest-level
@@ -527,7 +535,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo t
                 T xo = T(0), dn = T(0);
                 if (s.active && D > T(0)) {
                     const T r = bv[z] - stencil_apply(X.c[z], N, W);
-                    dn = c1 * dv[z] + c2 * r / D;
+                    dn = c1 * dv[z] + c2 * r * recip(D);
                     xo = X.c[z] + dn;
                 }
                 if (s.active) {
@@ -591,7 +599,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
     for (int z = 0; z < ZPL; ++z) braw[z] = b[s.self + 64 * z];
     T bv[ZPL];
 #pragma unroll
-    for (int z = 0; z < ZPL; ++z) bv[z] = s.active ? (T)braw[z] : T(0);
+    for (int z = 0; z < ZPL; ++z) bv[z] = (T)braw[z];
     const int4 fc = fcoord[s.bk];
     const long long pbase = (long long)parent_slot[s.bk] * BS;
     const int ox = (fc.x & 1) * 4 + (s.tx >> 1), oy = (fc.y & 1) * 4 + (s.ty >> 1);
@@ -634,12 +642,11 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
 // p_k at the neighbours is formed from z and p_{k-1}; pin and pout are
 // different buffers.  The step records in sc->pad which buffer holds the
 // pending p (1 + parity) for the final deferred update.
-template <typename TZ, int ZPL, bool LABEL>
+template <typename TZ, int ZPL, bool LABEL, bool FIRST>
 __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Topo topo, const TZ *__restrict__ zv,
                                                           const double *__restrict__ pin, double *__restrict__ pout,
                                                           double *__restrict__ x, double *__restrict__ q,
-                                                          double *part, Scal *sc, int first, int parity, long long vs,
-                                                          int ps)
+                                                          double *part, Scal *sc, int parity, long long vs, int ps)
 {
     double *lds = col_lds<double, ZPL, LABEL>();
     __shared__ double red[CWAVES];
@@ -661,24 +668,23 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
         Z.load(zv, s);
         SegVals<double, ZPL> Pi;
         double xv[ZPL];
-        if (!first) {
+        if constexpr (!FIRST) {
             Pi.load(pin, s);
-            if (s.active)
 #pragma unroll
-                for (int z = 0; z < ZPL; ++z) xv[z] = x[s.self + 64 * z];
+            for (int z = 0; z < ZPL; ++z) xv[z] = x[s.self + 64 * z];
         }
-        const double beta = first ? 0.0 : sc->beta;
-        const double alpha = first ? 0.0 : sc->alpha;
+        const double beta = FIRST ? 0.0 : sc->beta;
+        const double alpha = FIRST ? 0.0 : sc->alpha;
         // p_k on the segment, the face columns and the z ends
         SegVals<double, ZPL> P;
 #pragma unroll
         for (int z = 0; z < ZPL; ++z) {
-            P.c[z] = first ? (double)Z.c[z] : (double)Z.c[z] + beta * Pi.c[z];
-            P.ex[z] = first ? (double)Z.ex[z] : (double)Z.ex[z] + beta * Pi.ex[z];
-            P.ey[z] = first ? (double)Z.ey[z] : (double)Z.ey[z] + beta * Pi.ey[z];
+            P.c[z] = FIRST ? (double)Z.c[z] : (double)Z.c[z] + beta * Pi.c[z];
+            P.ex[z] = FIRST ? (double)Z.ex[z] : (double)Z.ex[z] + beta * Pi.ex[z];
+            P.ey[z] = FIRST ? (double)Z.ey[z] : (double)Z.ey[z] + beta * Pi.ey[z];
         }
-        P.zm = first ? (double)Z.zm : (double)Z.zm + beta * Pi.zm;
-        P.zp = first ? (double)Z.zp : (double)Z.zp + beta * Pi.zp;
+        P.zm = FIRST ? (double)Z.zm : (double)Z.zm + beta * Pi.zm;
+        P.zp = FIRST ? (double)Z.zp : (double)Z.zp + beta * Pi.zp;
         A.stage(op, s);
         if (!done) {
 #pragma unroll
@@ -689,7 +695,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
                 const double y = stencil_apply(P.c[z], N, W);
                 if (s.active) {
                     const long long n = s.self + 64 * z;
-                    if (!first) x[n] = xv[z] + alpha * Pi.c[z];
+                    if constexpr (!FIRST) x[n] = xv[z] + alpha * Pi.c[z];
                     pout[n] = P.c[z];
                     q[n] = y;
                     dot += P.c[z] * y;
@@ -940,12 +946,16 @@ hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, cons
     if (topo.nb <= 0) return hipSuccess;
     if (pin == pout) return hipErrorInvalidValue;
     const dim3 g = col_grid<ZPL_CG>(topo.nb, bt.n);
-    if (op.w)
-        SPFD_LAUNCH((k_col_cg_step<TZ, ZPL_CG, false>), g, dim3(CTHREADS), 0, s, op, topo, z, pin, pout, x, q,
-                           part, sc, first, parity, bt.vs, bt.ps);
-    else
-        SPFD_LAUNCH((k_col_cg_step<TZ, ZPL_CG, true>), g, dim3(CTHREADS), 0, s, op, topo, z, pin, pout, x, q,
-                           part, sc, first, parity, bt.vs, bt.ps);
+#define SPFD_CG(LB, F) SPFD_LAUNCH((k_col_cg_step<TZ, ZPL_CG, LB, F>), g, dim3(CTHREADS), 0, s, op, topo, z, pin, \
+                                   pout, x, q, part, sc, parity, bt.vs, bt.ps)
+    if (op.w) {
+        if (first) SPFD_CG(false, true);
+        else SPFD_CG(false, false);
+    } else {
+        if (first) SPFD_CG(true, true);
+        else SPFD_CG(true, false);
+    }
+#undef SPFD_CG
     return hipGetLastError();
 }
 
