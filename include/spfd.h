@@ -59,6 +59,7 @@ typedef enum {
 
 enum { SPFD_FP64 = 0, SPFD_MIXED = 1 };          /* precision of the multigrid cycle */
 enum { SPFD_CYCLE_V = 0 };
+enum { SPFD_SMOOTH_CHEBYSHEV = 0, SPFD_SMOOTH_L1_JACOBI = 1 };  /* smoother of every level */
 
 /* Multigrid preconditioner (the paper uses an algebraic multigrid
  * preconditioner inside a Krylov solver, Sec. III; its configuration is not
@@ -77,6 +78,10 @@ typedef struct {
     int level1_degree;    /* Chebyshev degree per pre/post smoothing on the first coarse level, default 4,
                              max 8 (that level costs about an eighth of the finest one per step, and
                              smoothing it harder lowers the iteration count) */
+    int smoother;         /* SPFD_SMOOTH_CHEBYSHEV (default) or SPFD_SMOOTH_L1_JACOBI: smooth_degree
+                             (level1_degree) sweeps x += D_l1^-1 (b - A x), D_l1 the row l1 norms,
+                             which equal twice the diagonal here (every level's rows sum to zero);
+                             any other value is rejected with SPFD_INVALID_ARG */
 } spfd_amg_options;
 
 typedef struct {

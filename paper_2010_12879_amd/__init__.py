@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libspfd.so")
 
 FP64, MIXED = 0, 1
 CYCLE_V = 0
+SMOOTH_CHEBYSHEV, SMOOTH_L1_JACOBI = 0, 1
 CG, FGMRES = 0, 1
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "BAD_STATE", 3: "OUT_OF_MEMORY", 4: "HIP_ERROR", 5: "NOT_CONVERGED",
           6: "BREAKDOWN"}
@@ -35,7 +36,8 @@ class SPFDError(RuntimeError):
 class AmgOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("cycle", ctypes.c_int), ("smooth_degree", ctypes.c_int),
                 ("coarsest_max", ctypes.c_int), ("cheby_ratio", ctypes.c_double), ("coarse_scale", ctypes.c_double),
-                ("split_level", ctypes.c_int), ("no_split", ctypes.c_int), ("level1_degree", ctypes.c_int)]
+                ("split_level", ctypes.c_int), ("no_split", ctypes.c_int), ("level1_degree", ctypes.c_int),
+                ("smoother", ctypes.c_int)]
 
 
 class SolveOptions(ctypes.Structure):
@@ -291,7 +293,8 @@ class Solver:
     """
 
     def __init__(self, labels, sigma, h, precision="fp64", device=None, smooth_degree=2, coarsest_max=1024,
-                 cheby_ratio=8.0, coarse_scale=1.9, split_level=2, split=True, stream=None, level1_degree=4):
+                 cheby_ratio=8.0, coarse_scale=1.9, split_level=2, split=True, stream=None, level1_degree=4,
+                 smoother="chebyshev"):
         import torch
         self.device = labels.device if device is None else torch.device(device)
         self.nz, self.ny, self.nx = labels.shape
@@ -307,7 +310,8 @@ class Solver:
                 spfd_set_sigma_table(self.handle, list(sigma))
             self.opts = AmgOptions(MIXED if precision == "mixed" else FP64, CYCLE_V,
                                    smooth_degree, coarsest_max, cheby_ratio, coarse_scale, split_level,
-                                   0 if split else 1, level1_degree)
+                                   0 if split else 1, level1_degree,
+                                   {"chebyshev": SMOOTH_CHEBYSHEV, "l1jacobi": SMOOTH_L1_JACOBI}[smoother])
             spfd_build(self.handle, self.opts)
         except Exception:
             spfd_destroy(self.handle)

@@ -734,14 +734,24 @@ void set_defaults(spfd_amg_options &o)
     if (o.level1_degree > 8) o.level1_degree = 8;
 }
 
+// Step k of a smoothing pass is d_k = c1[k] d_{k-1} + c2[k] D^-1 (b - A x),
+// x += d_k (the first, from x = 0: x = c0 D^-1 b).  Chebyshev on [lmax/ratio,
+// lmax] of D^-1 A with lmax = 2 (the largest eigenvalue of D^-1 A for a
+// weighted graph Laplacian on a bipartite grid graph); l1-Jacobi is
+// c1 = 0, c2 = c0 = 1/2, since the l1 norm of every row is twice its diagonal.
 void chebyshev_coefficients(Ctx *c)
 {
+    c->cheb_c1.assign(8, 0.0);
+    c->cheb_c2.assign(8, 0.0);
+    if (c->opt.smoother == SPFD_SMOOTH_L1_JACOBI) {
+        c->cheb_c0 = 0.5;
+        for (int k = 1; k < 8; ++k) c->cheb_c2[k] = 0.5;
+        return;
+    }
     const double lmax = 2.0, lmin = lmax / c->opt.cheby_ratio;
     const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
     const double sigma1 = theta / delta;
     c->cheb_c0 = 1.0 / theta;
-    c->cheb_c1.assign(8, 0.0);
-    c->cheb_c2.assign(8, 0.0);
     double rho_prev = 1.0 / sigma1;
     for (int k = 1; k < 8; ++k) {
         const double rho = 1.0 / (2.0 * sigma1 - rho_prev);
@@ -1807,6 +1817,8 @@ spfd_status spfd_build(spfd_handle h, const spfd_amg_options *opt)
     spfd_amg_options o{};
     if (opt) o = *opt;
     if (o.cycle != SPFD_CYCLE_V) return fail(h, SPFD_INVALID_ARG, "unknown cycle (only SPFD_CYCLE_V)");
+    if (o.smoother != SPFD_SMOOTH_CHEBYSHEV && o.smoother != SPFD_SMOOTH_L1_JACOBI)
+        return fail(h, SPFD_INVALID_ARG, "unknown smoother");
     set_defaults(o);
     h->opt = o;
     try {

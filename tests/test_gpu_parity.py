@@ -310,6 +310,39 @@ def test_fgmres_option_errors():
     s2.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_l1_jacobi_smoother_against_oracle(prec):
+    """The l1-Jacobi smoother option (the same cycle with sweeps x += D_l1^-1 (b - A x)) reaches the
+    oracle's solution; it smooths less than Chebyshev of the same degree, so it needs more iterations."""
+    print(f"case l1-jacobi {prec}", flush=True)
+    w = W.config(1)
+    _, _, info_c, _ = _solve(w, prec)
+    psi, _, info, _ = _solve(w, prec, smoother="l1jacobi")
+    ref, _ = oracle.solve(w.sigma_voxel(), w.h, w.a, tol=1e-12)
+    print(f"l1-jacobi {prec}: it={info['iterations']} (chebyshev {info_c['iterations']})", flush=True)
+    assert info["status"] == "OK" and info["rel_residual"] <= 1e-12
+    assert _rel(psi, ref) <= BAR[prec]
+    assert info["iterations"] > info_c["iterations"]
+
+
+def test_smoother_option_errors():
+    print("case smoother errors", flush=True)
+    w = W.config(0)
+    h = P.spfd_create(0)
+    try:
+        P.spfd_set_geometry(h, w.nx, w.ny, w.nz, *w.h, _dev(w.labels))
+        P.spfd_set_sigma_table(h, list(w.sigma_table))
+        opts = P.AmgOptions()
+        opts.smoother = 2
+        with pytest.raises(P.SPFDError) as e:
+            P.spfd_build(h, opts)
+        assert e.value.status == 1
+        opts.smoother = P.SMOOTH_L1_JACOBI
+        P.spfd_build(h, opts)
+    finally:
+        P.spfd_destroy(h)
+
+
 def test_tree_cotree_potentials_bit_exact():
     """Edge potentials from facet fluxes (Eq. (2), tree-cotree gauge): same recurrences in the same
     order as the oracle, so bit-identical; the fluxes are the facet circulations of the phantom's
