@@ -25,6 +25,7 @@
 //    three weight arrays (edge to +x, +y, +z); the minus-side weights are the
 //    plus-side weights of the minus neighbours.
 #include <math.h>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -229,10 +230,11 @@ template <typename T, int ZPL>
 struct SegOp<T, ZPL, false> {
     T wp[3][ZPL], wmx[ZPL], wmy[ZPL], wmz;
 
-    // Every lane loads (the slots stand in for absent ones) and the values
-    // are masked afterwards: a load under a per-lane condition becomes a
-    // branch, and a use of its value sunk into that branch waits for it
-    // there, one load at a time.
+    // Every lane loads its own weights, the lanes of the minus faces also
+    // the neighbour brick's (stand-in slots where it is absent), and the
+    // values are masked afterwards.  Nothing converts a value loaded under
+    // the face condition: a use sunk into such a branch would wait for its
+    // load there, one load at a time.
     __device__ __forceinline__ void load(const OpArgs<T> &op, const Seg<ZPL> &s, T *)
     {
         const T *w = op.w;
@@ -242,10 +244,18 @@ struct SegOp<T, ZPL, false> {
             wp[0][z] = w[s.self + 64 * z];
             wp[1][z] = w[st + s.self + 64 * z];
             wp[2][z] = w[2 * st + s.self + 64 * z];
-            wmx[z] = w[s.xe + 64 * z];
-            wmy[z] = w[st + s.ye + 64 * z];
+            wmx[z] = wmy[z] = T(0);
         }
         wmz = w[2 * st + s.zm];
+        // minus-face weights: only the lanes on that face load (as in SegVals)
+        if (s.tx == 0) {
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) wmx[z] = w[s.xe + 64 * z];
+        }
+        if (s.ty == 0) {
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) wmy[z] = w[st + s.ye + 64 * z];
+        }
         const bool mx = s.active && s.bx && s.tx == 0, my = s.active && s.by && s.ty == 0;
 #pragma unroll
         for (int z = 0; z < ZPL; ++z) {
@@ -281,16 +291,36 @@ template <typename T, int ZPL>
 struct SegVals {
     T c[ZPL], ex[ZPL], ey[ZPL], zm, zp;
 
+    // FACES: only the lanes on an x (y) face load ex (ey), the others read 0
+    // (they never use it); a quarter of the lanes per face load instruction
+    // (finest first two smoothing steps 44 -> 39.5 us).  Off where the
+    // caller converts the values (a conversion sunk into the branch would
+    // wait for each load there).
+    template <bool FACES = true>
     __device__ __forceinline__ void load(const T *__restrict__ x, const Seg<ZPL> &s)
     {
 #pragma unroll
-        for (int z = 0; z < ZPL; ++z) {
-            c[z] = x[s.self + 64 * z];
-            ex[z] = x[s.xe + 64 * z];
-            ey[z] = x[s.ye + 64 * z];
-        }
+        for (int z = 0; z < ZPL; ++z) c[z] = x[s.self + 64 * z];
         zm = x[s.zm];
         zp = x[s.zp];
+        if constexpr (FACES) {
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) ex[z] = ey[z] = T(0);
+            if (s.tx == 0 || s.tx == 7) {
+#pragma unroll
+                for (int z = 0; z < ZPL; ++z) ex[z] = x[s.xe + 64 * z];
+            }
+            if (s.ty == 0 || s.ty == 7) {
+#pragma unroll
+                for (int z = 0; z < ZPL; ++z) ey[z] = x[s.ye + 64 * z];
+            }
+        } else {
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) {
+                ex[z] = x[s.xe + 64 * z];
+                ey[z] = x[s.ye + 64 * z];
+            }
+        }
     }
 
     // the six neighbours of node z0+z; all 64 lanes of the wave must call this
@@ -370,7 +400,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first2(OpArgs<T> op, Topo
     SegOp<T, ZPL, LABEL> A;
     A.load(op, s, lds);
     SegVals<TB, ZPL> B;
-    B.load(b, s);
+    B.template load<std::is_same<T, TB>::value>(b, s);
     SegVals<T, ZPL> DI;
     DI.load(dinv, s);
     // x1 on the segment, the face columns and the z ends
@@ -665,7 +695,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
         SegOp<double, ZPL, LABEL> A;
         A.load(op, s, lds);
         SegVals<TZ, ZPL> Z;
-        Z.load(zv, s);
+        Z.template load<std::is_same<TZ, double>::value>(zv, s);
         SegVals<double, ZPL> Pi;
         double xv[ZPL];
         if constexpr (!FIRST) {
@@ -781,7 +811,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_spmv(OpArgs<double> op, Topo t
     SegOp<double, ZPL, LABEL> A;
     A.load(op, s, lds);
     SegVals<TZ, ZPL> Z;
-    Z.load(zv, s);
+    Z.template load<std::is_same<TZ, double>::value>(zv, s);
     A.stage(op, s);
     if (done) return;
 #pragma unroll
