@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # the dominant one (largest estimated share of the solve) carries the roofline figure
 FINE_CLASSES = {0: "k_col_cg_step (outer CG: p, deferred x, q = A p, p.q)",
                 1: "k_rupdate (r -= alpha q, ||r||^2, FP32 copy of r)",
-                2: "k_col_cheb_step + CG dots (last post-smoothing step)",
+                2: "k_col_cheb_step + CG dot z.r (last post-smoothing step)",
                 4: "k_col_cheb_first2 (first two Chebyshev steps, the pre-smoothing)",
                 6: "k_col_resid_restrict (residual + restriction)",
                 7: "k_col_cheb_step + prolongation (first post-smoothing step)"}
@@ -258,20 +258,21 @@ def scale_1mm(P, torch, args):
 
 
 def fgmres_compare(w, lab, a, P, torch, args):
-    """The paper's outer solver (flexible GMRES(30)) against the flexible CG, same FP32 cycle and criterion."""
+    """The paper's outer solver (flexible GMRES(30)) against the CG (standard beta, the default, and the
+    flexible beta), same FP32 cycle and criterion."""
     s = P.Solver(lab, w.sigma_table, w.h, precision="mixed")
     out = {}
-    for method in ("cg", "fgmres"):
-        s.solve(a, tol=args.tol, method=method)              # warm-up (allocates the basis)
+    for name, method, flexible in (("cg", "cg", False), ("cg_flexible", "cg", True), ("fgmres", "fgmres", False)):
+        s.solve(a, tol=args.tol, method=method, flexible=flexible)   # warm-up (allocates the basis)
         times, info = [], None
         for _ in range(3):
             torch.cuda.synchronize()
             t = time.perf_counter()
-            _, info = s.solve(a, tol=args.tol, method=method)
+            _, info = s.solve(a, tol=args.tol, method=method, flexible=flexible)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t)
-        out[method] = {"solve_ms": min(times) * 1e3, "iterations": info["iterations"],
-                       "rel_residual": info["rel_residual"]}
+        out[name] = {"solve_ms": min(times) * 1e3, "iterations": info["iterations"],
+                     "rel_residual": info["rel_residual"]}
     s.close()
     out["restart"] = 30
     out["fgmres_vs_cg_time"] = out["fgmres"]["solve_ms"] / out["cg"]["solve_ms"]

@@ -90,9 +90,13 @@ typedef struct {
     int use_x0;           /* nonzero: psi holds the start iterate on entry */
     int eager;            /* nonzero: launch every kernel from the host instead of replaying the
                              captured HIP graph of a CG iteration (same kernels, same results) */
-    int method;           /* SPFD_CG (default): flexible preconditioned CG; SPFD_FGMRES: flexible GMRES
+    int method;           /* SPFD_CG (default): preconditioned CG (see flexible); SPFD_FGMRES: flexible GMRES
                              (the paper's Krylov method, Sec. III), one right side per handle only */
     int restart;          /* FGMRES basis vectors per cycle, 1..32, default 30 */
+    int flexible;         /* SPFD_CG only.  0 (default): standard beta = (r.z)_k / (r.z)_{k-1};
+                             nonzero: flexible beta = -alpha_{k-1} (z_k.q_{k-1}) / (r.z)_{k-1}
+                             (Polak-Ribiere form, robust to a preconditioner that varies
+                             between iterations; reads q once more per iteration) */
 } spfd_solve_options;
 
 enum { SPFD_CG = 0, SPFD_FGMRES = 1 };

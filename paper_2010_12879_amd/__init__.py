@@ -42,7 +42,8 @@ class AmgOptions(ctypes.Structure):
 
 class SolveOptions(ctypes.Structure):
     _fields_ = [("rel_tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("use_x0", ctypes.c_int),
-                ("eager", ctypes.c_int), ("method", ctypes.c_int), ("restart", ctypes.c_int)]
+                ("eager", ctypes.c_int), ("method", ctypes.c_int), ("restart", ctypes.c_int),
+                ("flexible", ctypes.c_int)]
 
 
 class RhsInfo(ctypes.Structure):
@@ -361,9 +362,11 @@ class Solver:
         for r in range(a.shape[0]):
             spfd_set_source(self.handle, r, a[r].contiguous())
 
-    def solve(self, a=None, tol=1e-8, max_iter=500, x0=None, check=True, eager=False, method="cg", restart=30):
+    def solve(self, a=None, tol=1e-8, max_iter=500, x0=None, check=True, eager=False, method="cg", restart=30,
+              flexible=False):
         """Psi (nrhs or none, Nz, Ny, Nx) and the per-source info dicts (eager: no graph replay;
-        method "cg" or "fgmres" with `restart` basis vectors per cycle)."""
+        method "cg" or "fgmres" with `restart` basis vectors per cycle; flexible: the CG's
+        Polak-Ribiere beta instead of the standard one)."""
         import torch
         squeeze = a is not None and a.dim() == 4
         if a is not None:
@@ -373,7 +376,7 @@ class Solver:
         else:
             psi = torch.empty((self.nrhs,) + self.node_shape, dtype=torch.float64, device=self.device)
         opts = SolveOptions(tol, max_iter, 1 if x0 is not None else 0, 1 if eager else 0,
-                            FGMRES if method == "fgmres" else CG, restart)
+                            FGMRES if method == "fgmres" else CG, restart, 1 if flexible else 0)
         st, info = spfd_solve(self.handle, opts, psi, self.nrhs)
         if check and st != 0:
             raise SPFDError(st, spfd_last_error(self.handle))

@@ -144,7 +144,8 @@ struct Ctx {
         double bytes[SPFD_K_COUNT] = {};
     };
     StepGraph sg[2];
-    int sg_nb = -1, sg_max_iter = -1;
+    int sg_nb = -1, sg_max_iter = -1, sg_flexible = -1;
+    bool cg_flexible = false;   // beta of the CG: flexible (-alpha z.q / (r.z)_old) or standard (r.z / (r.z)_old)
     const Scal *sg_sc = nullptr;
     StepGraph *capturing = nullptr;
     int step_ctx = 0;   // 0: outside the CG loop, 1: in an untimed CG step, 2: in the sampled step
@@ -532,7 +533,7 @@ void cheb_step(Ctx *c, int l, const TB *b, const T *xin, T *xout, const T *din, 
     }
     double per = sizeof(TB) + op_bytes<T>(c, l) + sizeof(T) * (2 + (din ? 1 : 0) + (dout ? 1 : 0));
     if (with_prolong) per += sizeof(T) / 8.0;
-    if (dots) per += 8.0;
+    if (dots && dots->q) per += 8.0;
     const int cls = l == 0 ? (with_prolong ? SPFD_K_PROLONG0 : dots ? SPFD_K_DOTS : SPFD_K_SMOOTH0) : SPFD_K_COARSE;
     TScope ts(c, cls, nb * (double)L.dofs * per);
     const T *xc = nullptr;
@@ -1067,7 +1068,7 @@ void pcg_begin(Ctx *c, Scal *sc, int nb)
     const Batch bt = level_batch(c, 0, nb);
     T *z = (T *)c->d_z;
     const double n0 = (double)L0.dofs * nb;
-    CycleDots dots{c->d_q, c->d_part};
+    CycleDots dots{nullptr, c->d_part};   // r.z only
     if (vcycle<T, double>(c, c->d_r, z, sc, nb, &dots)) {
         finish(c, cheb_dot_parts<T>(topo.nb), FIN_BETA0, sc, 0, nb);
         return;
@@ -1105,18 +1106,20 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
         HIPCHK(launch_rupdate(topo, c->d_r, c->d_q, c->d_part, sc, bt, r32, c->stream));
     }
     finish(c, topo.nb, FIN_RR, sc, max_iter, nb);
-    // z = B r, with the dot products z.r and z.q formed by the cycle's last step
-    CycleDots dots{c->d_q, c->d_part};
+    // z = B r, with the dot products z.r (and z.q for the flexible beta) formed by the cycle's last step
+    const bool flex = c->cg_flexible;
+    const int bmode = flex ? FIN_BETA : FIN_BETA_STD;
+    CycleDots dots{flex ? c->d_q : nullptr, c->d_part};
     const bool fused = r32 ? vcycle<T, float>(c, r32, z, sc, nb, &dots) : vcycle<T, double>(c, c->d_r, z, sc, nb, &dots);
     if (fused) {
-        finish(c, cheb_dot_parts<T>(topo.nb), FIN_BETA, sc, 0, nb, c->step_mirror);
+        finish(c, cheb_dot_parts<T>(topo.nb), bmode, sc, 0, nb, c->step_mirror);
         return;
     }
     {
-        TScope ts(c, SPFD_K_DOTS, n0 * (wz + 16.0));
-        HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 0, bt, c->stream));
+        TScope ts(c, SPFD_K_DOTS, n0 * (wz + (flex ? 16.0 : 8.0)));
+        HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, flex ? 0 : 1, bt, c->stream));
     }
-    finish(c, topo.nb, FIN_BETA, sc, 0, nb, c->step_mirror);
+    finish(c, topo.nb, bmode, sc, 0, nb, c->step_mirror);
 }
 
 void pcg_end(Ctx *c, Scal *sc, int nb)
@@ -1178,11 +1181,12 @@ void pcg_step_enqueue(Ctx *c, Scal *sc, Scal *hsc, int nb, int it, int max_iter,
         c->step_ctx = 0;
         return;
     }
-    if (c->sg_nb != nb || c->sg_sc != sc || c->sg_max_iter != max_iter) {
+    if (c->sg_nb != nb || c->sg_sc != sc || c->sg_max_iter != max_iter || c->sg_flexible != (int)c->cg_flexible) {
         drop_graphs(c);
         c->sg_nb = nb;
         c->sg_sc = sc;
         c->sg_max_iter = max_iter;
+        c->sg_flexible = (int)c->cg_flexible;
     }
     Ctx::StepGraph &g = c->sg[it & 1];
     if (g.exec && g.mirror != mirror) {
@@ -1230,6 +1234,7 @@ void pcg_iterations(Ctx *c, Scal *sc, int nb, const spfd_solve_options &so)
 {
     Scal *ring[2] = {c->h_ring, c->h_ring + nb};
     const bool eager = so.eager != 0;
+    c->cg_flexible = so.flexible != 0;
     c->step_ctx = 1;
     pcg_begin_any(c, sc, nb);
     c->step_ctx = 0;
@@ -1548,6 +1553,7 @@ spfd_status solve_many(Ctx **hs, int n, const spfd_solve_options &so, double **p
         Ctx *c = hs[k];
         const long long n0 = c->lv[0].nodes();
         HIPCHK(hipSetDevice(c->device));
+        c->cg_flexible = so.flexible != 0;
         HIPCHK(launch_scal_init(c->d_scal, so.rel_tol, 0, c->nrhs, c->stream));
         HIPCHK(hipMemsetAsync(c->d_x, 0, c->nrhs * n0 * sizeof(double), c->stream));
         HIPCHK(hipMemcpyAsync(c->d_r, c->d_bs, c->nrhs * n0 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));

@@ -103,7 +103,8 @@ enum {
     FIN_BETA = 4,     // flexible beta = -alpha z.q / (r.z)_old (partials of z.q follow those of r.z)
     FIN_RESID0 = 5,   // ||b - A x0||^2 at the start of a warm-started solve
     FIN_RESID1 = 6,   // true ||b - A x||^2 at the end of a solve (kept in zq)
-    FIN_MEAN = 7      // mean of one component
+    FIN_MEAN = 7,     // mean of one component
+    FIN_BETA_STD = 8  // standard beta = r.z / (r.z)_old
 };
 // mirror != nullptr: the scalars of right side i are also written to
 // mirror[i] (host-visible memory) when the kernel ends, also when the solve

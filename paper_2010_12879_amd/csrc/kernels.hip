@@ -876,7 +876,7 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
     __shared__ double red[16];
     part += (long long)blockIdx.x * ps;
     if (sc) sc += blockIdx.x;
-    if (mode == FIN_ALPHA || mode == FIN_RR || mode == FIN_BETA0 || mode == FIN_BETA)
+    if (mode == FIN_ALPHA || mode == FIN_RR || mode == FIN_BETA0 || mode == FIN_BETA || mode == FIN_BETA_STD)
         if (sc->done) {
             if (threadIdx.x == 0) store_mirror(mirror, sc);
             return;
@@ -930,10 +930,12 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
         }
         break;
     case FIN_BETA0:
-    case FIN_BETA: {
+    case FIN_BETA:
+    case FIN_BETA_STD: {
         if (mode == FIN_BETA0) sc->pad = 0;
         double beta = 0.0;
         if (mode == FIN_BETA) beta = -sc->alpha * b / sc->rz;
+        if (mode == FIN_BETA_STD) beta = a / sc->rz;
         if (!(a > 0.0) || !isfinite(beta)) {
             sc->status = 6;
             sc->done = 1;

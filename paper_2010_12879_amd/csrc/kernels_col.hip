@@ -542,9 +542,14 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo t
             if (din) dv[z] = din[s.self + 64 * z];
         }
         if constexpr (DOT) {
-            const double *q = dt.q + blockIdx.y * vs;
+            // z.q only for the flexible beta (q == nullptr: partials of 0)
 #pragma unroll
-            for (int z = 0; z < ZPL; ++z) qv[z] = q[s.self + 64 * z];
+            for (int z = 0; z < ZPL; ++z) qv[z] = 0.0;
+            if (dt.q) {
+                const double *q = dt.q + blockIdx.y * vs;
+#pragma unroll
+                for (int z = 0; z < ZPL; ++z) qv[z] = q[s.self + 64 * z];
+            }
         }
         T bv[ZPL];
 #pragma unroll
@@ -906,7 +911,6 @@ hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T
     if (topo.nb <= 0) return hipSuccess;
     if (xin == xout) return hipErrorInvalidValue;
     if (xc && !(parent_slot && fcoord)) return hipErrorInvalidValue;
-    if (dot_part && !dot_q) return hipErrorInvalidValue;
     constexpr int Z = zpl_cycle<T>();
     const Prolong pr{xc, parent_slot, fcoord, (double)pscale, bt.vsc};
     const Dots dt{dot_q, dot_part, bt.ps, 0};

@@ -325,6 +325,28 @@ def test_l1_jacobi_smoother_against_oracle(prec):
     assert info["iterations"] > info_c["iterations"]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_flexible_beta_against_oracle(prec):
+    """Both CG betas reach the oracle's solution: the standard r.z / (r.z)_old (default) and the flexible
+    -alpha z.q / (r.z)_old; switching between them re-captures the replayed step graphs."""
+    print(f"case cg beta {prec}", flush=True)
+    w = W.config(1)
+    s = P.Solver(_dev(w.labels), w.sigma_table, w.h, precision=prec)
+    a = _dev(w.a)
+    p_std, i_std = s.solve(a, tol=1e-12, max_iter=400)
+    p_flex, i_flex = s.solve(a, tol=1e-12, max_iter=400, flexible=True)
+    p_std2, _ = s.solve(a, tol=1e-12, max_iter=400)
+    p_eager, _ = s.solve(a, tol=1e-12, max_iter=400, eager=True)
+    s.close()
+    assert torch.equal(p_std, p_std2) and torch.equal(p_std, p_eager)
+    ref, _ = oracle.solve(w.sigma_voxel(), w.h, w.a, tol=1e-12)
+    print(f"cg beta {prec}: standard it={i_std['iterations']} flexible it={i_flex['iterations']}", flush=True)
+    for psi, info in ((p_std, i_std), (p_flex, i_flex)):
+        assert info["status"] == "OK" and info["rel_residual"] <= 1e-12
+        assert _rel(psi.cpu().numpy(), ref) <= BAR[prec]
+    assert abs(i_std["iterations"] - i_flex["iterations"]) <= 2
+
+
 def test_smoother_option_errors():
     print("case smoother errors", flush=True)
     w = W.config(0)
