@@ -284,37 +284,47 @@ struct SegOp<T, ZPL, false> {
 
 // values of x along the segment, the face lanes' columns in the neighbour
 // bricks (ex, ey) and the two z ends.  Nothing is masked: a column without
-// unknowns reads the zeros its slots hold, and where a neighbour is absent
-// the value read is a finite stand-in (the lane's own slot) whose edge
-// weight is exactly 0, so every term W (x0 - N) it enters is 0.
+// unknowns holds zeros (read from its slots, or set without a load), and
+// where a neighbour is absent the value read is a finite stand-in (the
+// lane's own slot) whose edge weight is exactly 0, so every term W (x0 - N)
+// it enters is 0.
 template <typename T, int ZPL>
 struct SegVals {
     T c[ZPL], ex[ZPL], ey[ZPL], zm, zp;
 
     // FACES: only the lanes on an x (y) face load ex (ey), the others read 0
     // (they never use it); a quarter of the lanes per face load instruction
-    // (finest first two smoothing steps 44 -> 39.5 us).  Off where the
+    // (finest first two smoothing steps 44 -> 39.5 us); lanes of columns
+    // without unknowns load nothing (-1.2 % per solve).  Off where the
     // caller converts the values (a conversion sunk into the branch would
     // wait for each load there).
     template <bool FACES = true>
     __device__ __forceinline__ void load(const T *__restrict__ x, const Seg<ZPL> &s)
     {
-#pragma unroll
-        for (int z = 0; z < ZPL; ++z) c[z] = x[s.self + 64 * z];
-        zm = x[s.zm];
-        zp = x[s.zp];
         if constexpr (FACES) {
+            // lanes of columns without unknowns load nothing (their slots hold 0)
 #pragma unroll
-            for (int z = 0; z < ZPL; ++z) ex[z] = ey[z] = T(0);
-            if (s.tx == 0 || s.tx == 7) {
+            for (int z = 0; z < ZPL; ++z) c[z] = ex[z] = ey[z] = T(0);
+            zm = zp = T(0);
+            if (s.active) {
+#pragma unroll
+                for (int z = 0; z < ZPL; ++z) c[z] = x[s.self + 64 * z];
+                zm = x[s.zm];
+                zp = x[s.zp];
+            }
+            if (s.active && (s.tx == 0 || s.tx == 7)) {
 #pragma unroll
                 for (int z = 0; z < ZPL; ++z) ex[z] = x[s.xe + 64 * z];
             }
-            if (s.ty == 0 || s.ty == 7) {
+            if (s.active && (s.ty == 0 || s.ty == 7)) {
 #pragma unroll
                 for (int z = 0; z < ZPL; ++z) ey[z] = x[s.ye + 64 * z];
             }
         } else {
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) c[z] = x[s.self + 64 * z];
+            zm = x[s.zm];
+            zp = x[s.zp];
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) {
                 ex[z] = x[s.xe + 64 * z];
@@ -537,15 +547,20 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo t
         T dv[ZPL];
         double qv[DOT ? ZPL : 1];
 #pragma unroll
-        for (int z = 0; z < ZPL; ++z) {
-            braw[z] = b[s.self + 64 * z];
-            if (din) dv[z] = din[s.self + 64 * z];
+        for (int z = 0; z < ZPL; ++z) braw[z] = dv[z] = 0;
+        if (s.active || !std::is_same<T, TB>::value) {
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) braw[z] = b[s.self + 64 * z];
+        }
+        if (din && s.active) {
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) dv[z] = din[s.self + 64 * z];
         }
         if constexpr (DOT) {
             // z.q only for the flexible beta (q == nullptr: partials of 0)
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) qv[z] = 0.0;
-            if (dt.q) {
+            if (dt.q && s.active) {
                 const double *q = dt.q + blockIdx.y * vs;
 #pragma unroll
                 for (int z = 0; z < ZPL; ++z) qv[z] = q[s.self + 64 * z];
@@ -706,7 +721,10 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
         if constexpr (!FIRST) {
             Pi.load(pin, s);
 #pragma unroll
-            for (int z = 0; z < ZPL; ++z) xv[z] = x[s.self + 64 * z];
+            for (int z = 0; z < ZPL; ++z) xv[z] = 0.0;
+            if (s.active)
+#pragma unroll
+                for (int z = 0; z < ZPL; ++z) xv[z] = x[s.self + 64 * z];
         }
         const double beta = FIRST ? 0.0 : sc->beta;
         const double alpha = FIRST ? 0.0 : sc->alpha;
