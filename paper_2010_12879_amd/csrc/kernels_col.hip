@@ -230,9 +230,9 @@ template <typename T, int ZPL>
 struct SegOp<T, ZPL, false> {
     T wp[3][ZPL], wmx[ZPL], wmy[ZPL], wmz;
 
-    // Every lane loads its own weights, the lanes of the minus faces also
-    // the neighbour brick's (stand-in slots where it is absent), and the
-    // values are masked afterwards.  Nothing converts a value loaded under
+    // Lanes of columns with unknowns load their own weights, the lanes of
+    // the minus faces also the neighbour brick's (stand-in slots where it is
+    // absent), and the values are masked afterwards.  Nothing converts a value loaded under
     // the face condition: a use sunk into such a branch would wait for its
     // load there, one load at a time.
     __device__ __forceinline__ void load(const OpArgs<T> &op, const Seg<ZPL> &s, T *)
@@ -241,26 +241,31 @@ struct SegOp<T, ZPL, false> {
         const long long st = op.stride;
 #pragma unroll
         for (int z = 0; z < ZPL; ++z) {
-            wp[0][z] = w[s.self + 64 * z];
-            wp[1][z] = w[st + s.self + 64 * z];
-            wp[2][z] = w[2 * st + s.self + 64 * z];
+            wp[0][z] = wp[1][z] = wp[2][z] = T(0);
             wmx[z] = wmy[z] = T(0);
+        }
+        // a column without unknowns has weights 0 (not loaded)
+        if (s.active) {
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) {
+                wp[0][z] = w[s.self + 64 * z];
+                wp[1][z] = w[st + s.self + 64 * z];
+                wp[2][z] = w[2 * st + s.self + 64 * z];
+            }
         }
         wmz = w[2 * st + s.zm];
         // minus-face weights: only the lanes on that face load (as in SegVals)
-        if (s.tx == 0) {
+        if (s.active && s.tx == 0) {
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) wmx[z] = w[s.xe + 64 * z];
         }
-        if (s.ty == 0) {
+        if (s.active && s.ty == 0) {
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) wmy[z] = w[st + s.ye + 64 * z];
         }
         const bool mx = s.active && s.bx && s.tx == 0, my = s.active && s.by && s.ty == 0;
 #pragma unroll
         for (int z = 0; z < ZPL; ++z) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) wp[d][z] = s.active ? wp[d][z] : T(0);
             wmx[z] = mx ? wmx[z] : T(0);
             wmy[z] = my ? wmy[z] : T(0);
         }
