@@ -67,8 +67,9 @@ __device__ __forceinline__ float recip<float>(float d)
 }
 
 // Where a wave's segment lies.  Absent neighbour bricks hold no unknowns and
-// the edges into them have conductance 0: their values are never loaded and
-// read as 0.  Columns without unknowns likewise read as 0.
+// the edges into them have conductance 0: in their place a lane reads its own
+// slot (a finite stand-in that only meets weights of 0).  Columns without
+// unknowns hold zeros and are never written.
 template <int ZPL>
 struct Seg {
     static constexpr int WPB = 8 / ZPL;           // waves per brick
@@ -106,8 +107,9 @@ __device__ __forceinline__ Seg<ZPL> make_seg(const Topo &topo)
     s.bk = b < topo.nb ? b : -1;
     s.active = false;
     if (s.bk < 0) return s;
-    // a column without unknowns neither loads nor stores: its slots stay zero,
-    // and edges into them have conductance 0
+    // a column without unknowns stores nothing (its slots stay zero) and
+    // loads only what its neighbours' stencils need (nothing in most kernels);
+    // edges into it have conductance 0
     s.active = !topo.cmask || ((topo.cmask[s.bk] >> s.lane) & 1ull);
     int nb[6];
     brick_nbrs(topo.nbr, s.bk, nb);
@@ -224,17 +226,17 @@ struct SegOp<T, ZPL, true> {
 // Stored form: w[d*stride + n] = conductance of the edge from n to +d; the
 // minus-side weights are the plus-side weights of the minus neighbours, inside
 // the brick taken from lanes l-1 and l-8, on the minus faces loaded from the
-// neighbour brick.  Columns without unknowns read as 0 (every edge at such a
-// node has conductance 0).
+// neighbour brick.  Columns without unknowns have weights 0 (every edge at
+// such a node has conductance 0).
 template <typename T, int ZPL>
 struct SegOp<T, ZPL, false> {
     T wp[3][ZPL], wmx[ZPL], wmy[ZPL], wmz;
 
     // Lanes of columns with unknowns load their own weights, the lanes of
     // the minus faces also the neighbour brick's (stand-in slots where it is
-    // absent), and the values are masked afterwards.  Nothing converts a value loaded under
-    // the face condition: a use sunk into such a branch would wait for its
-    // load there, one load at a time.
+    // absent, masked afterwards).  Nothing converts a value loaded under a
+    // lane condition: a use sunk into such a branch would wait for its load
+    // there, one load at a time.
     __device__ __forceinline__ void load(const OpArgs<T> &op, const Seg<ZPL> &s, T *)
     {
         const T *w = op.w;
