@@ -41,6 +41,9 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The cycle kernels of a right side that has stopped return before loading
+// anything (the step that stops still has its cycle queued behind it): the
+// flag's load overlaps the brick-table loads every wave waits for anyway.
 __device__ __forceinline__ bool col_stopped(const Scal *sc)
 {
     return sc && __hip_atomic_load(&sc[blockIdx.y].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -374,7 +377,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo 
     T *lds = col_lds<T, ZPL, LABEL>();
     const Seg<ZPL> s = make_seg<ZPL>(topo);
     if (s.bk < 0) return;
-    const bool done = col_stopped(sc);
+    if (col_stopped(sc)) return;
     b += blockIdx.y * vs;
     x += blockIdx.y * vs;
     SegOp<T, ZPL, LABEL> A;
@@ -386,7 +389,6 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo 
 #pragma unroll
     for (int z = 0; z < ZPL; ++z) bv[z] = (T)braw[z];
     A.stage(op, s);
-    if (done) return;
 #pragma unroll
     for (int z = 0; z < ZPL; ++z) {
         T W[6];
@@ -410,7 +412,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first2(OpArgs<T> op, Topo
     T *lds = col_lds<T, ZPL, LABEL>();
     const Seg<ZPL> s = make_seg<ZPL>(topo);
     if (s.bk < 0) return;
-    const bool done = col_stopped(sc);
+    if (col_stopped(sc)) return;
     b += blockIdx.y * vs;
     xout += blockIdx.y * vs;
     if (dout) dout += blockIdx.y * vs;
@@ -431,7 +433,6 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first2(OpArgs<T> op, Topo
     X.zm = c0 * (T)B.zm * DI.zm;
     X.zp = c0 * (T)B.zp * DI.zp;
     A.stage(op, s);
-    if (done) return;
 #pragma unroll
     for (int z = 0; z < ZPL; ++z) {
         T W[6], N[6];
@@ -537,7 +538,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo t
     __shared__ double red[2][CWAVES];
     const Seg<ZPL> s = make_seg<ZPL>(topo);
     if (DOT ? s.grp < 0 : s.bk < 0) return;
-    const bool done = col_stopped(sc);
+    if (col_stopped(sc)) return;
     double dzr = 0.0, dzq = 0.0;
     if (s.bk >= 0) {
         b += blockIdx.y * vs;
@@ -582,32 +583,29 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo t
             for (int z = 0; z < ZPL; ++z) dv[z] = X.c[z];
         }
         A.stage(op, s);
-        if (!done) {
 #pragma unroll
-            for (int z = 0; z < ZPL; ++z) {
-                T W[6], N[6];
-                A.weights(s, z, W);
-                X.nbrs(s, z, N);
-                const T D = diag_of(W);
-                T xo = T(0), dn = T(0);
-                if (s.active && D > T(0)) {
-                    const T r = bv[z] - stencil_apply(X.c[z], N, W);
-                    dn = c1 * dv[z] + c2 * r * recip(D);
-                    xo = X.c[z] + dn;
-                }
-                if (s.active) {
-                    xout[s.self + 64 * z] = xo;
-                    if (dout) dout[s.self + 64 * z] = dn;
-                    if constexpr (DOT) {
-                        dzr += (double)xo * (double)bv[z];
-                        dzq += (double)xo * qv[z];
-                    }
+        for (int z = 0; z < ZPL; ++z) {
+            T W[6], N[6];
+            A.weights(s, z, W);
+            X.nbrs(s, z, N);
+            const T D = diag_of(W);
+            T xo = T(0), dn = T(0);
+            if (s.active && D > T(0)) {
+                const T r = bv[z] - stencil_apply(X.c[z], N, W);
+                dn = c1 * dv[z] + c2 * r * recip(D);
+                xo = X.c[z] + dn;
+            }
+            if (s.active) {
+                xout[s.self + 64 * z] = xo;
+                if (dout) dout[s.self + 64 * z] = dn;
+                if constexpr (DOT) {
+                    dzr += (double)xo * (double)bv[z];
+                    dzq += (double)xo * qv[z];
                 }
             }
         }
     }
     if constexpr (DOT) {
-        if (done) return;
         dzr = wave_sum(dzr);
         dzq = wave_sum(dzq);
         if (s.lane == 0) {
@@ -643,7 +641,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
     T *lds = col_lds<T, ZPL, LABEL>();
     const Seg<ZPL> s = make_seg<ZPL>(topo);
     if (s.bk < 0) return;
-    const bool done = col_stopped(sc);
+    if (col_stopped(sc)) return;
     b += blockIdx.y * vs;
     x += blockIdx.y * vs;
     bc += blockIdx.y * vsc;
@@ -661,7 +659,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
     const long long pbase = (long long)parent_slot[s.bk] * BS;
     const int ox = (fc.x & 1) * 4 + (s.tx >> 1), oy = (fc.y & 1) * 4 + (s.ty >> 1);
     const int oz = (fc.z & 1) * 4 + (s.z0 >> 1);
-    const bool corner = ((s.tx | s.ty) & 1) == 0 && !done;
+    const bool corner = ((s.tx | s.ty) & 1) == 0;
     // inverse diagonals of the coarse nodes this lane may store (loaded early: no tail latency)
     T dc[ZPL / 2];
     if (xc && corner)
@@ -835,7 +833,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_spmv(OpArgs<double> op, Topo t
     double *lds = col_lds<double, ZPL, LABEL>();
     const Seg<ZPL> s = make_seg<ZPL>(topo);
     if (s.bk < 0) return;
-    const bool done = col_stopped(sc);
+    if (col_stopped(sc)) return;
     zv += blockIdx.y * vs;
     w += blockIdx.y * vs;
     SegOp<double, ZPL, LABEL> A;
@@ -843,7 +841,6 @@ __global__ __launch_bounds__(CTHREADS) void k_col_spmv(OpArgs<double> op, Topo t
     SegVals<TZ, ZPL> Z;
     Z.template load<std::is_same<TZ, double>::value>(zv, s);
     A.stage(op, s);
-    if (done) return;
 #pragma unroll
     for (int z = 0; z < ZPL; ++z) {
         double W[6], P[6];
