@@ -708,7 +708,8 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
     sc += blockIdx.y;
     const Seg<ZPL> s = make_seg<ZPL>(topo);
     if (s.grp < 0) return;
-    const int done = __hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // a stopped right side (batched solves, a step queued past the stop) returns before its loads
+    if (__hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     zv += blockIdx.y * vs;
     pin += blockIdx.y * vs;
     pout += blockIdx.y * vs;
@@ -744,24 +745,21 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
         P.zm = FIRST ? (double)Z.zm : (double)Z.zm + beta * Pi.zm;
         P.zp = FIRST ? (double)Z.zp : (double)Z.zp + beta * Pi.zp;
         A.stage(op, s);
-        if (!done) {
 #pragma unroll
-            for (int z = 0; z < ZPL; ++z) {
-                double W[6], N[6];
-                A.weights(s, z, W);
-                P.nbrs(s, z, N);
-                const double y = stencil_apply(P.c[z], N, W);
-                if (s.active) {
-                    const long long n = s.self + 64 * z;
-                    if constexpr (!FIRST) x[n] = xv[z] + alpha * Pi.c[z];
-                    pout[n] = P.c[z];
-                    q[n] = y;
-                    dot += P.c[z] * y;
-                }
+        for (int z = 0; z < ZPL; ++z) {
+            double W[6], N[6];
+            A.weights(s, z, W);
+            P.nbrs(s, z, N);
+            const double y = stencil_apply(P.c[z], N, W);
+            if (s.active) {
+                const long long n = s.self + 64 * z;
+                if constexpr (!FIRST) x[n] = xv[z] + alpha * Pi.c[z];
+                pout[n] = P.c[z];
+                q[n] = y;
+                dot += P.c[z] * y;
             }
         }
     }
-    if (done) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->pad = 1 + parity;
     dot = wave_sum(dot);
     if (s.lane == 0) red[threadIdx.x >> 6] = dot;
