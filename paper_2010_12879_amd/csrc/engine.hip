@@ -45,6 +45,8 @@ struct Level {
     uint8_t *d_tiles = nullptr;    // finest level, label form
     double *d_w64 = nullptr;
     float *d_w32 = nullptr;
+    uint16_t *d_w16 = nullptr;     // first coarse level of an FP32 cycle: FP16 weights / w16s
+    float w16s = 0.0f;
     // cycle buffers (type of the cycle)
     void *x = nullptr, *x2 = nullptr, *d = nullptr, *b = nullptr;
     long long dofs = 0;
@@ -454,6 +456,10 @@ OpArgs<float> level_op<float>(Ctx *c, int l)
         for (int d = 0; d < 3; ++d) op.geo4[d] = (float)c->geo4[d];
     } else {
         op.w = L.d_w32;
+        if (l == 1 && L.d_w16) {
+            op.wh = L.d_w16;
+            op.whs = L.w16s;
+        }
     }
     return op;
 }
@@ -464,7 +470,9 @@ OpArgs<float> level_op<float>(Ctx *c, int l)
 template <typename T>
 double op_bytes(Ctx *c, int l)
 {
-    return (l == 0 && !c->voxel_mode) ? 1.0 : 3.0 * sizeof(T);
+    if (l == 0 && !c->voxel_mode) return 1.0;
+    if (sizeof(T) == sizeof(float) && l == 1 && c->lv[1].d_w16) return 3.0 * sizeof(uint16_t);
+    return 3.0 * sizeof(T);
 }
 
 template <typename T>
@@ -981,6 +989,24 @@ spfd_status do_build(Ctx *c)
         C.d_w32 = dalloc<float>(c, c->hier_allocs, (size_t)3 * C.nodes());
         HIPCHK(launch_galerkin(F.d_w64, F.nodes(), F.d_slot_of, F.G[0], F.G[1], F.G[2], F.N[0], F.N[1], F.N[2], C.d_coord,
                                C.nb, C.d_w64, C.d_w32, C.nodes(), c->stream));
+        // the first coarse level of an FP32 cycle is bandwidth-bound and smoothed hardest: its smoothing
+        // and restriction read FP16 weights scaled so the largest is 2^15 (relative rounding 2^-11;
+        // the Galerkin operators below it come from the FP64 weights)
+        if (c->opt.precision == SPFD_MIXED && c->lv.size() == 1) {
+            unsigned *dm = dalloc<unsigned>(c, c->hier_allocs, 1);
+            HIPCHK(hipMemsetAsync(dm, 0, sizeof(unsigned), c->stream));
+            HIPCHK(launch_wmax(C.d_w32, 3LL * C.nodes(), dm, c->stream));
+            unsigned hm = 0;
+            HIPCHK(hipMemcpyAsync(&hm, dm, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            float mw;
+            memcpy(&mw, &hm, sizeof(float));
+            if (mw > 0.0f) {
+                C.w16s = mw / 32768.0f;
+                C.d_w16 = dalloc<uint16_t>(c, c->hier_allocs, (size_t)3 * C.nodes());
+                HIPCHK(launch_w16(C.d_w32, 3LL * C.nodes(), 1.0f / C.w16s, C.d_w16, c->stream));
+            }
+        }
         HIPCHK(hipStreamSynchronize(c->stream));
         c->lv.push_back(std::move(C));
         c->lv.back().dofs = count_dofs(c, c->lv.back());

@@ -46,6 +46,8 @@ struct OpArgs {
     const T *table;          // sigma per label (device)
     int nlab;
     T geo4[3];               // dual area / length / 4 per direction
+    const uint16_t *wh = nullptr;  // FP16 bits of w / whs (first coarse level of an FP32 cycle), read instead of w
+    float whs = 0.0f;
 };
 
 // A batch of right sides solved together: launch grids get a y-dimension of
@@ -71,6 +73,10 @@ hipError_t launch_label_tiles(const uint8_t *labels, const Grid &g, const int4 *
                               hipStream_t s);
 hipError_t launch_weights0(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,
                            const double geo4[3], const int4 *coord, int nb, double *w64, float *w32, hipStream_t s);
+// largest of n non-negative weights (its bits atomically maxed into *out, which starts at 0),
+// and FP16 copies h = w * inv rounded to nearest
+hipError_t launch_wmax(const float *w, long long n, unsigned *out, hipStream_t s);
+hipError_t launch_w16(const float *w, long long n, float inv, uint16_t *h, hipStream_t s);
 hipError_t launch_galerkin(const double *wf, long long fstride, const int *f_slot_of, int fGx, int fGy, int fGz,
                            int fNx, int fNy, int fNz, const int4 *ccoord, int cnb, double *wc64, float *wc32,
                            long long cstride, hipStream_t s);

@@ -6,6 +6,7 @@
 #include <math.h>
 
 #include "kernels.h"
+#include <hip/hip_fp16.h>
 
 namespace spfd {
 
@@ -76,6 +77,30 @@ __global__ void k_brick_flags(const uint8_t *__restrict__ labels, const double *
             flags[bi + (long long)g.Gx * (bj + (long long)g.Gy * bk)] = 1;
         }
     }
+}
+
+// non-negative floats order like their bit patterns
+__global__ void k_wmax(const float *w, long long n, unsigned *out)
+{
+    float m = 0.0f;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        m = fmaxf(m, w[i]);
+    atomicMax(out, __float_as_uint(m));
+}
+__global__ void k_w16(const float *w, long long n, float inv, uint16_t *h)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        h[i] = __half_as_ushort(__float2half_rn(w[i] * inv));
+}
+hipError_t launch_wmax(const float *w, long long n, unsigned *out, hipStream_t s)
+{
+    SPFD_LAUNCH(k_wmax, dim3(1024), dim3(256), 0, s, w, n, out);
+    return hipGetLastError();
+}
+hipError_t launch_w16(const float *w, long long n, float inv, uint16_t *h, hipStream_t s)
+{
+    SPFD_LAUNCH(k_w16, dim3(1024), dim3(256), 0, s, w, n, inv, h);
+    return hipGetLastError();
 }
 
 hipError_t launch_brick_flags(const uint8_t *labels, const double *table, int nlab, const double *sig_vox,

@@ -26,6 +26,7 @@
 //    plus-side weights of the minus neighbours.
 #include <math.h>
 #include <type_traits>
+#include <hip/hip_fp16.h>
 
 #include "kernels.h"
 
@@ -240,8 +241,42 @@ struct SegOp<T, ZPL, false> {
     // absent, masked afterwards).  Nothing converts a value loaded under a
     // lane condition: a use sunk into such a branch would wait for its load
     // there, one load at a time.
+    // FP16 weights (scaled by op.whs): every load unconditional, including
+    // the faces', since each value is converted where it is used
+    __device__ __forceinline__ void load_h(const OpArgs<T> &op, const Seg<ZPL> &s)
+    {
+        const uint16_t *w = op.wh;
+        const long long st = op.stride;
+        uint16_t hp[3][ZPL], hx[ZPL], hy[ZPL];
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) {
+            hp[0][z] = w[s.self + 64 * z];
+            hp[1][z] = w[st + s.self + 64 * z];
+            hp[2][z] = w[2 * st + s.self + 64 * z];
+            hx[z] = w[s.xe + 64 * z];
+            hy[z] = w[st + s.ye + 64 * z];
+        }
+        const uint16_t hz = w[2 * st + s.zm];
+        const T sc = (T)op.whs;
+        const bool mx = s.active && s.bx && s.tx == 0, my = s.active && s.by && s.ty == 0;
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) wp[d][z] = (T)__half2float(__ushort_as_half(hp[d][z])) * sc;
+            wmx[z] = mx ? (T)__half2float(__ushort_as_half(hx[z])) * sc : T(0);
+            wmy[z] = my ? (T)__half2float(__ushort_as_half(hy[z])) * sc : T(0);
+        }
+        wmz = s.active && s.has[NMZ] ? (T)__half2float(__ushort_as_half(hz)) * sc : T(0);
+    }
+
     __device__ __forceinline__ void load(const OpArgs<T> &op, const Seg<ZPL> &s, T *)
     {
+        if constexpr (std::is_same<T, float>::value) {
+            if (op.wh) {
+                load_h(op, s);
+                return;
+            }
+        }
         const T *w = op.w;
         const long long st = op.stride;
 #pragma unroll
