@@ -65,7 +65,8 @@ enum { SPFD_SMOOTH_CHEBYSHEV = 0, SPFD_SMOOTH_L1_JACOBI = 1 };  /* smoother of e
  * preconditioner inside a Krylov solver, Sec. III; its configuration is not
  * given).  Zero-initialised options select the defaults. */
 typedef struct {
-    int precision;        /* SPFD_FP64 (default) or SPFD_MIXED: FP32 cycle, FP64 outer CG, dots and coarsest solve */
+    int precision;        /* SPFD_FP64 (default) or SPFD_MIXED: FP32 cycle (FP16 weights on its first coarse
+                             level), FP64 outer CG, dots and coarsest solve */
     int cycle;            /* SPFD_CYCLE_V (the only cycle; any other value is rejected) */
     int smooth_degree;    /* Chebyshev degree per pre/post smoothing, default 2, max 4 */
     int coarsest_max;     /* coarsen until the coarsest level has <= this many unknowns, default and max 1024 */
