@@ -188,15 +188,21 @@ def pnorm_objective(emag, p=8):
     return J, g
 
 
-def percentile_nearest_rank(emag, labels, q=0.99, n_labels=None):
+def percentile_nearest_rank(emag, labels, sigma, q=0.99, n_labels=None):
     """Nearest-rank q-quantile of the voxel |E| over the conducting voxels (step 6 of the
     paper's technical summary, Sec. II.A; the voxel-averaged field, Sec. III.F), whole body
     and per label: sort the n values ascending and take the one of rank ceil(q n) (1-based).
-    Air voxels (|E| = 0 with label 0) are excluded; a label without voxels gets NaN.
+    The body is the set of voxels with sigma > 0 (Sec. III.A: only conducting tissue is
+    modelled), so a labelled voxel whose conductivity is 0 is excluded as air is; per label
+    the set is the body voxels carrying that label, and a label without any gets NaN.
+    sigma is the per-voxel conductivity array (same shape as emag and labels).
     Returns (whole-body value, per-label array)."""
     e = np.asarray(emag, dtype=np.float64).reshape(-1)
     lab = np.asarray(labels).reshape(-1)
-    body = lab > 0
+    sig = np.asarray(sigma, dtype=np.float64).reshape(-1)
+    if not (e.shape == lab.shape == sig.shape):
+        raise ValueError("emag, labels and sigma must have the same number of voxels")
+    body = sig > 0
 
     def nearest_rank(v):
         if v.size == 0:
@@ -206,7 +212,7 @@ def percentile_nearest_rank(emag, labels, q=0.99, n_labels=None):
         return float(v[max(r, 1) - 1])
 
     n_labels = int(lab.max()) + 1 if n_labels is None else n_labels
-    per = np.array([nearest_rank(e[lab == t]) if t > 0 else float("nan") for t in range(n_labels)])
+    per = np.array([nearest_rank(e[body & (lab == t)]) for t in range(n_labels)])
     return nearest_rank(e[body]), per
 
 

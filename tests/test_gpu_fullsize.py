@@ -76,7 +76,7 @@ def test_fullsize_percentile_by_oracle(body):
     w = body["w"]
     _, emag, _, (p_body, p_per), _ = body["mixed"]
     print("case full-size percentile", flush=True)
-    ref, ref_per = oracle.percentile_nearest_rank(emag, w.labels, 0.99, n_labels=len(w.sigma_table))
+    ref, ref_per = oracle.percentile_nearest_rank(emag, w.labels, w.sigma_voxel(), 0.99, n_labels=len(w.sigma_table))
     assert p_body == ref
     for t in range(1, len(w.sigma_table)):
         if np.isnan(ref_per[t]):

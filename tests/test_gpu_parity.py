@@ -241,7 +241,7 @@ def test_percentile_matches_oracle(q):
     body, per = s.percentile(emag, q)
     s.close()
     e = emag.cpu().numpy()
-    ref, ref_per = oracle.percentile_nearest_rank(e, w.labels, q, n_labels=len(w.sigma_table))
+    ref, ref_per = oracle.percentile_nearest_rank(e, w.labels, w.sigma_voxel(), q, n_labels=len(w.sigma_table))
     assert body == ref
     for t in range(1, len(w.sigma_table)):
         if np.isnan(ref_per[t]):

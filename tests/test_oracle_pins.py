@@ -346,40 +346,153 @@ def test_percentile_nearest_rank_by_hand():
     # 10 values 1..10 in scrambled order: rank ceil(0.99*10) = 10 -> 10; q = 0.5 -> rank 5 -> 5
     e = np.array([[[7.0, 2.0, 9.0, 1.0, 10.0, 3.0, 5.0, 8.0, 4.0, 6.0, 0.0]]])
     lab = np.array([[[1, 1, 2, 1, 2, 1, 1, 2, 1, 1, 0]]])
-    p99, per = oracle.percentile_nearest_rank(e, lab, 0.99)
+    sig = np.where(lab > 0, 0.3, 0.0)
+    p99, per = oracle.percentile_nearest_rank(e, lab, sig, 0.99)
     assert p99 == 10.0
-    p50, per50 = oracle.percentile_nearest_rank(e, lab, 0.5)
+    p50, per50 = oracle.percentile_nearest_rank(e, lab, sig, 0.5)
     assert p50 == 5.0
     # label 2 holds 9, 10, 8 -> rank ceil(0.5*3) = 2 -> 9; label 1 holds 7,2,1,3,5,4,6 -> rank 4 -> 4
     assert per50[2] == 9.0 and per50[1] == 4.0 and np.isnan(per50[0])
+
+
+def test_percentile_body_is_the_conducting_voxels():
+    # Sec. III.A: only conducting voxels are modelled.  A labelled tissue with sigma = 0 is not body:
+    # the same 10 values as above, but label 2 (values 9, 10, 8) is given sigma = 0 and the field 0 there
+    # (as Eq. (1) leaves air voxels).  Body = 7,2,1,3,5,4,6 -> q = 0.99: rank 7 -> 7; q = 0.5: rank 4 -> 4.
+    e = np.array([[[7.0, 2.0, 0.0, 1.0, 0.0, 3.0, 5.0, 0.0, 4.0, 6.0, 0.0]]])
+    lab = np.array([[[1, 1, 2, 1, 2, 1, 1, 2, 1, 1, 0]]])
+    sig = np.where(lab == 1, 0.3, 0.0)
+    p99, per = oracle.percentile_nearest_rank(e, lab, sig, 0.99)
+    assert p99 == 7.0 and per[1] == 7.0 and np.isnan(per[2]) and np.isnan(per[0])
+    p50, _ = oracle.percentile_nearest_rank(e, lab, sig, 0.5)
+    assert p50 == 4.0
+    # a voxel of label 0 that conducts (per-voxel conductivities) is body and forms group 0
+    sig2 = sig.copy()
+    sig2[0, 0, 10] = 0.1
+    e2 = e.copy()
+    e2[0, 0, 10] = 11.0
+    p, per = oracle.percentile_nearest_rank(e2, lab, sig2, 1.0)
+    assert p == 11.0 and per[0] == 11.0
 
 
 def test_percentile_matches_inverted_cdf():
     rng = np.random.default_rng(5)
     e = rng.lognormal(size=(7, 9, 11))
     lab = rng.integers(0, 4, size=e.shape)
-    e[lab == 0] = 0.0
-    p, per = oracle.percentile_nearest_rank(e, lab, 0.99)
-    assert p == np.percentile(e[lab > 0], 99, method="inverted_cdf")
+    sig = np.where(lab > 0, 0.2, 0.0)
+    sig[(lab == 3) & (rng.random(e.shape) < 0.3)] = 0.0   # some tissue voxels without conductivity
+    e[sig == 0] = 0.0
+    p, per = oracle.percentile_nearest_rank(e, lab, sig, 0.99)
+    assert p == np.percentile(e[sig > 0], 99, method="inverted_cdf")
     for t in range(1, 4):
-        assert per[t] == np.percentile(e[lab == t], 99, method="inverted_cdf")
+        assert per[t] == np.percentile(e[(lab == t) & (sig > 0)], 99, method="inverted_cdf")
 
 
 def test_percentile_ties_and_extremes():
     # ties: values 1,1,2,2,2,3 -> rank ceil(0.5*6) = 3 -> 2; q = 1 -> maximum; q tiny -> minimum
     e = np.array([[[2.0, 1.0, 2.0, 3.0, 1.0, 2.0]]])
     lab = np.ones_like(e, dtype=np.uint8)
-    assert oracle.percentile_nearest_rank(e, lab, 0.5)[0] == 2.0
-    assert oracle.percentile_nearest_rank(e, lab, 1.0)[0] == 3.0
-    assert oracle.percentile_nearest_rank(e, lab, 1e-9)[0] == 1.0
+    sig = np.ones_like(e)
+    assert oracle.percentile_nearest_rank(e, lab, sig, 0.5)[0] == 2.0
+    assert oracle.percentile_nearest_rank(e, lab, sig, 1.0)[0] == 3.0
+    assert oracle.percentile_nearest_rank(e, lab, sig, 1e-9)[0] == 1.0
     # brute force on random data: the result r satisfies #(v <= r) >= k and #(v < r) < k, k = ceil(q n)
     rng = np.random.default_rng(11)
     v = np.round(rng.random(997) * 50) / 7.0
     lab = np.ones((1, 1, v.size), np.uint8)
+    sig = np.ones((1, 1, v.size))
     for q in (0.01, 0.37, 0.99, 1.0):
-        r = oracle.percentile_nearest_rank(v.reshape(1, 1, -1), lab, q)[0]
+        r = oracle.percentile_nearest_rank(v.reshape(1, 1, -1), lab, sig, q)[0]
         k = int(np.ceil(q * v.size))
         assert np.sum(v <= r) >= k and np.sum(v < r) < k
+
+
+# ---------------------------------------------------------------------------- residual of a given potential
+# oracle.residual is the check applied at sizes the oracle cannot solve in test time; it must return
+# ||b - A psi||_2 / ||b||_2 over the unknowns with b = -G^T M a (Eq. (3); the relative residual of
+# Sec. II.A).  Pinned here to a hand value, the zero potential, exact manufactured answers, an
+# independent element assembly and the solver's own true residual.
+def test_residual_single_voxel_by_hand():
+    # one voxel, sigma 2, h 1: every edge conducts 0.5; a = 1 on the x-edge 0 -> 1 gives b = (0.5, -0.5, 0, ...).
+    # psi = 1 at node 0: A psi = column 0 of the cube Laplacian = (1.5, -0.5, -0.5, 0, -0.5, 0, 0, 0),
+    # r = (-1, 0, 0.5, 0, 0.5, 0, 0, 0): ||r||^2 = 1.5, ||b||^2 = 0.5, ratio sqrt(3)
+    sig = np.full((1, 1, 1), 2.0)
+    a = np.zeros((3, 2, 2, 2))
+    a[0, 0, 0, 0] = 1.0
+    psi = np.zeros((2, 2, 2))
+    psi[0, 0, 0] = 1.0
+    rel, r = oracle.residual(sig, (1.0, 1.0, 1.0), a, psi, want_nodes=True)
+    assert abs(rel - np.sqrt(3.0)) <= 1e-15
+    np.testing.assert_array_equal(r.reshape(-1), [-1.0, 0.0, 0.5, 0.0, 0.5, 0.0, 0.0, 0.0])
+    # a constant added to psi is in the null space: same residual
+    assert abs(oracle.residual(sig, (1.0, 1.0, 1.0), a, psi + 7.0) - np.sqrt(3.0)) <= 1e-14
+
+
+@pytest.mark.parametrize("seed,shape", [(21, (4, 3, 5)), (22, (6, 6, 4))])
+def test_residual_of_zero_potential_is_one(seed, shape):
+    w = W.tiny_random_phantom(*shape, seed=seed)
+    rel = oracle.residual(w.sigma_voxel(), w.h, w.a, np.zeros((w.nz + 1, w.ny + 1, w.nx + 1)))
+    assert abs(rel - 1.0) <= 1e-15
+
+
+@pytest.mark.parametrize("cfg", ["ellipsoid", "hetero"])
+def test_residual_of_manufactured_answer_vanishes(cfg):
+    # a = -G psi* + M^-1 C^T W gives b = A psi* exactly (C G = 0), whatever constant psi* carries
+    rng = np.random.default_rng(12)
+    if cfg == "ellipsoid":
+        w = W.homogeneous_ellipsoid(n_nodes=20, semi=(7.0, 6.0, 8.0))
+    else:
+        w = W.random_ellipsoid_phantom(24, 20, 28, seed=98, n_ell=6, semi_range=(3.0, 8.0))
+    sig = w.sigma_voxel()
+    M = oracle.edge_conductance(sig, w.h)
+    a, psi_star, _ = D.manufactured(M, sig > 0, rng)
+    comp, _ = oracle.components(sig, w.h)
+    assert oracle.residual(sig, w.h, a, D.project_mean_zero(psi_star, comp)) <= 1e-13
+    assert oracle.residual(sig, w.h, a, psi_star + 3e-6) <= 1e-13
+    # a wrong potential is seen: psi* with one body node moved
+    bad = psi_star.copy()
+    k, j, i = np.argwhere(comp >= 0)[len(np.argwhere(comp >= 0)) // 2]
+    bad[k, j, i] += 1e-6
+    assert oracle.residual(sig, w.h, a, bad) > 1e-3
+
+
+@pytest.mark.parametrize("seed,shape,fill", [(23, (4, 4, 4), 0.5), (24, (5, 3, 6), 0.35), (25, (3, 6, 4), 0.7)])
+def test_residual_matches_independent_assembly(seed, shape, fill):
+    # A from the voxel-by-voxel element scatter, b = -G^T M a with M read off that A: a different route
+    # to b - A psi than the oracle's edge gather, on random potentials at every node (also off the body)
+    w = W.tiny_random_phantom(*shape, seed=seed, fill=fill)
+    sig = w.sigma_voxel()
+    Afull = _element_assembly(sig, w.h)
+    Nz, Ny, Nx = w.nz + 1, w.ny + 1, w.nx + 1
+    dof = np.where(np.abs(Afull).sum(axis=1) > 0)[0]
+    M = np.zeros_like(w.a)
+    flatM = M.reshape(3, -1)
+    step = (1, Nx, Nx * Ny)
+    for d in range(3):
+        for n in range(Nx * Ny * Nz):
+            i, j, k = n % Nx, (n // Nx) % Ny, n // (Nx * Ny)
+            if (d == 0 and i == Nx - 1) or (d == 1 and j == Ny - 1) or (d == 2 and k == Nz - 1):
+                continue
+            flatM[d, n] = -Afull[n, n + step[d]]
+    bfull = -D.div_T(M * w.a).reshape(-1)
+    rng = np.random.default_rng(seed)
+    psi = rng.standard_normal((Nz, Ny, Nx)) * 1e-3
+    rfull = bfull - Afull @ psi.reshape(-1)
+    expect = np.linalg.norm(rfull[dof]) / np.linalg.norm(bfull[dof])
+    rel, r = oracle.residual(sig, w.h, w.a, psi, want_nodes=True)
+    assert abs(rel - expect) <= 1e-12 * expect
+    np.testing.assert_allclose(r.reshape(-1)[dof], rfull[dof], rtol=0, atol=1e-12 * np.abs(rfull).max())
+    assert np.all(np.delete(r.reshape(-1), dof) == 0)
+
+
+def test_residual_matches_the_solvers_true_residual():
+    # a loose solve leaves a residual far above rounding: the relative residual the solve reports
+    # (its own true residual at exit) and the residual of its returned potential agree
+    w = W.random_ellipsoid_phantom(20, 18, 24, seed=97, n_ell=5, semi_range=(3.0, 7.0))
+    sig = w.sigma_voxel()
+    psi, info = oracle.solve(sig, w.h, w.a, tol=1e-6)
+    assert 1e-8 < info["relres"] <= 1e-6
+    assert abs(oracle.residual(sig, w.h, w.a, psi) - info["relres"]) <= 1e-9 * info["relres"]
 
 
 # ---------------------------------------------------------------------------- tree-cotree gauge (Eq. (2))
