@@ -94,8 +94,9 @@ def copy_calibration(mib, torch):
 
 def run_precision(prec, w, lab, a, args, P, torch):
     dev = lab.device
-    stream = torch.cuda.current_stream(dev).cuda_stream
-    h = P.spfd_create(dev.index or 0, stream)
+    cur = torch.cuda.current_stream(dev)
+    alloc = P.torch_allocator(dev, cur)    # the handle's device memory from PyTorch's caching allocator
+    h = P.spfd_create(dev.index or 0, cur.cuda_stream, alloc)
     nx, ny, nz = w.nx, w.ny, w.nz
     P.spfd_set_geometry(h, nx, ny, nz, *w.h, lab)
     opts = P.AmgOptions(P.MIXED if prec == "mixed" else P.FP64, P.CYCLE_V, 0, 0, 0.0, 0.0)

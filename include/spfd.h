@@ -83,6 +83,13 @@ typedef struct {
                              (level1_degree) sweeps x += D_l1^-1 (b - A x), D_l1 the row l1 norms,
                              which equal twice the diagonal here (every level's rows sum to zero);
                              any other value is rejected with SPFD_INVALID_ARG */
+    int short_segment_bricks; /* structured levels with stored weights and fewer bricks than this run
+                             4-node column segments per lane, larger ones 8 (FP32) / 4 (FP64);
+                             0 = default 8192, negative = never (every FP32 level runs 8-node segments) */
+    int level1_fp32;      /* SPFD_MIXED only.  0 (default): the first coarse level's smoothing and
+                             restriction read FP16 copies of its weights, scaled so that the largest is
+                             2^15, unless the smallest nonzero weight would then fall below FP16's normal
+                             range (then FP32 weights are kept); nonzero: always FP32 weights */
 } spfd_amg_options;
 
 typedef struct {
@@ -108,8 +115,24 @@ typedef struct {
     int status;           /* spfd_status of this right-hand side */
 } spfd_rhs_info;
 
-/* Create a handle on HIP device `device`; `hip_stream` is a hipStream_t (NULL = default stream). */
-spfd_status spfd_create(int device, void *hip_stream, spfd_handle *out);
+/* Device memory of a handle.  alloc(bytes, user) returns a device pointer on
+ * the handle's GPU (NULL on failure: the call reports SPFD_OUT_OF_MEMORY) and
+ * free(ptr, user) releases one; both are called from the thread that calls
+ * the library, only inside spfd_* calls, and every buffer is freed again by
+ * spfd_destroy at the latest, after the handle's work has completed.  A caller
+ * that owns a caching allocator (e.g. PyTorch's) passes it here so that the
+ * handle's working memory is accounted and reused there. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} spfd_allocator;
+
+/* Create a handle on HIP device `device`; `hip_stream` is a hipStream_t (NULL
+ * = default stream).  alloc (host, nullable; copied): the allocator of the
+ * handle's device memory, hipMalloc/hipFree when NULL or when both of its
+ * functions are NULL; SPFD_INVALID_ARG when only one of them is given. */
+spfd_status spfd_create(int device, void *hip_stream, const spfd_allocator *alloc, spfd_handle *out);
 void spfd_destroy(spfd_handle h);
 /* Message of the last failing call on h (valid until the next call on h). */
 const char *spfd_last_error(spfd_handle h);
@@ -124,7 +147,14 @@ spfd_status spfd_set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, 
 spfd_status spfd_set_sigma_table(spfd_handle h, const double *sigma, int n_labels);
 /* Conductivity per voxel (device, [nvox], finite, >= 0): overrides the table. */
 spfd_status spfd_set_sigma_voxel(spfd_handle h, const double *sigma_voxel);
-/* Assemble the edge conductances and build the multigrid hierarchy (opt may be NULL). */
+/* Assemble the edge conductances M_kappa of Eq. (3) from the conductivities
+ * (mean of the four voxels around each edge times dual facet area over edge
+ * length; Sec. III.A: nodes of conducting voxels are the unknowns), find the
+ * connected conductors (the constants of Eq. (3)'s null space), and build the
+ * multigrid hierarchy of the preconditioner (the paper solves Eq. (3) with an
+ * algebraic multigrid preconditioner inside a Krylov method, Sec. III).
+ * opt (host) may be NULL (defaults).  SPFD_INVALID_ARG when no voxel conducts
+ * or an option is out of range; the previous hierarchy is released first. */
 spfd_status spfd_build(spfd_handle h, const spfd_amg_options *opt);
 /* Sizes after build (any pointer may be NULL): unknowns, connected
  * components, multigrid levels, device bytes held by the handle. */
@@ -148,12 +178,13 @@ spfd_status spfd_set_source(spfd_handle h, int rhs, const double *a);
  * mean per connected component and 0 at nodes outside the conductor.
  * info [nrhs] (host) may be NULL.  opt may be NULL (defaults). */
 spfd_status spfd_solve(spfd_handle h, const spfd_solve_options *opt, double *psi, spfd_rhs_info *info);
-/* Eq. (1) and the voxel average (Sec. III.F) for one source:
- * u_edges [3][nnodes] (device, nullable) = a + G psi on conducting edges
- * (0 elsewhere), so that Im(e) = -omega*u and Re(e) = 0;
- * emag [nvox] (device) = omega * |mean of the voxel's d-edges / h_d| per
- * conducting voxel, 0 in air.  a and psi as in spfd_set_source / spfd_solve. */
-spfd_status spfd_efield(spfd_handle h, double omega, const double *a, const double *psi,
+/* Eq. (1) and the voxel average (Sec. III.F) for nsrc >= 1 sources:
+ * a [nsrc][3][nnodes] and psi [nsrc][nnodes] (device) as in spfd_set_source /
+ * spfd_solve; u_edges [nsrc][3][nnodes] (device, nullable) = a + G psi on
+ * conducting edges (0 elsewhere), so that Im(e) = -omega*u and Re(e) = 0;
+ * emag [nsrc][nvox] (device) = omega * |mean of the voxel's d-edges / h_d|
+ * per conducting voxel, 0 in air. */
+spfd_status spfd_efield(spfd_handle h, double omega, int nsrc, const double *a, const double *psi,
                         double *u_edges, double *emag);
 
 /* Edge potentials from facet fluxes, Eq. (2) b = C a, solved in a tree-cotree

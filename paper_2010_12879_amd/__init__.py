@@ -37,7 +37,37 @@ class AmgOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("cycle", ctypes.c_int), ("smooth_degree", ctypes.c_int),
                 ("coarsest_max", ctypes.c_int), ("cheby_ratio", ctypes.c_double), ("coarse_scale", ctypes.c_double),
                 ("split_level", ctypes.c_int), ("no_split", ctypes.c_int), ("level1_degree", ctypes.c_int),
-                ("smoother", ctypes.c_int)]
+                ("smoother", ctypes.c_int), ("short_segment_bricks", ctypes.c_int), ("level1_fp32", ctypes.c_int)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    """spfd_allocator: device memory of a handle (alloc(bytes, user) -> pointer or NULL, free(ptr, user))."""
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
+def torch_allocator(device, stream=None):
+    """An Allocator that takes the handle's device memory from PyTorch's caching allocator on `device`
+    (blocks tied to `stream`, default the current stream).  Keep the returned object alive as long as
+    the handle: the library calls its functions until spfd_destroy."""
+    import torch
+
+    def _alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+        except Exception:   # out of memory: NULL, reported as SPFD_OUT_OF_MEMORY
+            return None
+
+    def _free(ptr, user):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:   # interpreter shutdown: the process releases the memory
+            pass
+
+    return Allocator(_ALLOC_FN(_alloc), _FREE_FN(_free), None)
 
 
 class SolveOptions(ctypes.Structure):
@@ -56,7 +86,8 @@ class RhsInfo(ctypes.Structure):
 _lib = None
 EXPORTS = ["spfd_create", "spfd_destroy", "spfd_last_error", "spfd_set_geometry", "spfd_set_sigma_table",
            "spfd_set_sigma_voxel", "spfd_build", "spfd_get_info", "spfd_level_info", "spfd_set_num_rhs", "spfd_set_source",
-           "spfd_solve", "spfd_solve_many", "spfd_efield", "spfd_edge_potentials", "spfd_percentile", "spfd_adjoint", "spfd_timing", "spfd_timing_get"]
+           "spfd_solve", "spfd_solve_many", "spfd_efield", "spfd_edge_potentials", "spfd_percentile",
+           "spfd_adjoint", "spfd_timing", "spfd_timing_get"]
 # kernel classes of spfd_timing / spfd_timing_get (order of the enum in spfd.h)
 KERNEL_CLASSES = ["spmv", "update", "dots", "pupdate", "smooth0", "smooth0_first", "restrict0", "prolong0", "coarse",
                   "finish", "rhs", "efield", "gauge", "resid"]
@@ -73,7 +104,7 @@ def load_library(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     H = ctypes.c_void_p
-    lib.spfd_create.argtypes = [I, P, ctypes.POINTER(H)]
+    lib.spfd_create.argtypes = [I, P, ctypes.POINTER(Allocator), ctypes.POINTER(H)]
     lib.spfd_destroy.argtypes = [H]
     lib.spfd_destroy.restype = None
     lib.spfd_last_error.argtypes = [H]
@@ -89,7 +120,7 @@ def load_library(path: str = LIB_PATH):
     lib.spfd_set_num_rhs.argtypes = [H, I]
     lib.spfd_set_source.argtypes = [H, I, P]
     lib.spfd_solve.argtypes = [H, ctypes.POINTER(SolveOptions), P, ctypes.POINTER(RhsInfo)]
-    lib.spfd_efield.argtypes = [H, D, P, P, P, P]
+    lib.spfd_efield.argtypes = [H, D, I, P, P, P, P]
     lib.spfd_adjoint.argtypes = [H, D, P, P, P, ctypes.POINTER(SolveOptions), P, P, ctypes.POINTER(RhsInfo)]
     lib.spfd_percentile.argtypes = [H, P, D, ctypes.POINTER(D), P]
     lib.spfd_edge_potentials.argtypes = [H, P, P]
@@ -129,10 +160,13 @@ def _require_cuda(t, dtype, shape=None, name="tensor"):
 
 
 # ---------------------------------------------------------------- the C names
-def spfd_create(device: int = 0, stream=None):
+def spfd_create(device: int = 0, stream=None, allocator: Allocator | None = None):
+    """A handle on `device` working on the hipStream_t `stream` (an int, None = default stream);
+    allocator: its device memory (torch_allocator(...)), hipMalloc when None."""
     lib = load_library()
     h = ctypes.c_void_p()
-    st = lib.spfd_create(device, ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+    st = lib.spfd_create(device, ctypes.c_void_p(stream) if stream else None,
+                         ctypes.byref(allocator) if allocator is not None else None, ctypes.byref(h))
     if st != 0:
         raise SPFDError(st, "spfd_create failed")
     return h
@@ -229,13 +263,15 @@ def solve_many(solvers, sources, tol=1e-8, max_iter=500):
     return [p[0] if p.shape[0] == 1 else p for p in psis], info
 
 
-def spfd_efield(h, omega, a, psi, u_edges, emag):
+def spfd_efield(h, omega, a, psi, u_edges, emag, nsrc=1):
+    """|E| (and u) of nsrc sources: a [nsrc][3][nnodes], psi [nsrc][nnodes], emag [nsrc][nvox]."""
     import torch
     for t, n in ((a, "a"), (psi, "psi"), (emag, "emag")):
         _require_cuda(t, torch.float64, None, n)
     if u_edges is not None:
         _require_cuda(u_edges, torch.float64, None, "u_edges")
-    return _check(h, load_library().spfd_efield(h, float(omega), _ptr(a), _ptr(psi), _ptr(u_edges), _ptr(emag)))
+    return _check(h, load_library().spfd_efield(h, float(omega), int(nsrc), _ptr(a), _ptr(psi), _ptr(u_edges),
+                                                _ptr(emag)))
 
 
 def spfd_adjoint(h, omega, a, psi, grad_emag, opts: SolveOptions | None, grad_sigma_voxel, n_table: int = 0):
@@ -295,14 +331,18 @@ class Solver:
 
     def __init__(self, labels, sigma, h, precision="fp64", device=None, smooth_degree=2, coarsest_max=1024,
                  cheby_ratio=8.0, coarse_scale=1.9, split_level=2, split=True, stream=None, level1_degree=4,
-                 smoother="chebyshev"):
+                 smoother="chebyshev", short_segment_bricks=0, level1_fp32=False, torch_memory=True):
+        """torch_memory: the handle's device memory comes from PyTorch's caching allocator
+        (torch.cuda.memory_allocated() accounts for it); False: hipMalloc inside the library."""
         import torch
         self.device = labels.device if device is None else torch.device(device)
         self.nz, self.ny, self.nx = labels.shape
         self.h = tuple(float(v) for v in h)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         stream = self.stream.cuda_stream
-        self.handle = spfd_create(self.device.index or 0, stream)
+        self._allocator = torch_allocator(self.device, self.stream) if torch_memory else None
+        self.version = 0    # bumped by every set_sigma (the hierarchy an adjoint needs)
+        self.handle = spfd_create(self.device.index or 0, stream, self._allocator)
         try:
             spfd_set_geometry(self.handle, self.nx, self.ny, self.nz, *self.h, labels)
             if isinstance(sigma, torch.Tensor):
@@ -312,7 +352,8 @@ class Solver:
             self.opts = AmgOptions(MIXED if precision == "mixed" else FP64, CYCLE_V,
                                    smooth_degree, coarsest_max, cheby_ratio, coarse_scale, split_level,
                                    0 if split else 1, level1_degree,
-                                   {"chebyshev": SMOOTH_CHEBYSHEV, "l1jacobi": SMOOTH_L1_JACOBI}[smoother])
+                                   {"chebyshev": SMOOTH_CHEBYSHEV, "l1jacobi": SMOOTH_L1_JACOBI}[smoother],
+                                   short_segment_bricks, 1 if level1_fp32 else 0)
             spfd_build(self.handle, self.opts)
         except Exception:
             spfd_destroy(self.handle)
@@ -331,6 +372,7 @@ class Solver:
             vals = sigma.detach().cpu().tolist() if isinstance(sigma, torch.Tensor) else list(sigma)
             spfd_set_sigma_table(self.handle, vals)
             self.n_table = len(vals)
+        self.version += 1
         spfd_build(self.handle, self.opts)
         self.nrhs = 1
 
@@ -383,11 +425,18 @@ class Solver:
         return (psi[0] if squeeze else psi), (info[0] if squeeze else info)
 
     def efield(self, a, psi, omega, want_u=False):
-        """|E| per voxel (nz, ny, nx) [and u edges (3, Nz, Ny, Nx)] for one source."""
+        """|E| per voxel (nz, ny, nx) [and u edges (3, Nz, Ny, Nx)] for one source; for n sources
+        (a (n, 3, Nz, Ny, Nx), psi (n, Nz, Ny, Nx)) the same with a leading dimension n."""
         import torch
-        emag = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
-        u = torch.empty((3,) + self.node_shape, dtype=torch.float64, device=self.device) if want_u else None
-        spfd_efield(self.handle, omega, a.contiguous(), psi.contiguous(), u, emag)
+        many = a.dim() == 5
+        n = a.shape[0] if many else 1
+        nn = (self.nz + 1) * (self.ny + 1) * (self.nx + 1)
+        if tuple(a.shape[-4:]) != (3,) + self.node_shape or psi.numel() != n * nn:
+            raise ValueError(f"a must be ([n,] 3) + {self.node_shape} and psi hold n * {nn} node values")
+        lead = (n,) if many else ()
+        emag = torch.empty(lead + (self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        u = torch.empty(lead + (3,) + self.node_shape, dtype=torch.float64, device=self.device) if want_u else None
+        spfd_efield(self.handle, omega, a.contiguous(), psi.contiguous(), u, emag, n)
         return (emag, u) if want_u else emag
 
     def edge_potentials(self, flux):
@@ -438,12 +487,19 @@ def _autograd_function():
             ctx.per_voxel = sigma.dim() == 3
             ctx.n = sigma.numel()
             ctx.sigma_device, ctx.sigma_dtype = sigma.device, sigma.dtype
+            # the conductivities this forward ran with, and the solver state they gave
+            ctx.sigma_used = sigma.detach().clone()
+            ctx.version = solver.version
             ctx.save_for_backward(a, psi)
             return emag
 
         @staticmethod
         def backward(ctx, grad_emag):
             a, psi = ctx.saved_tensors
+            if ctx.solver.version != ctx.version:
+                # another forward changed the solver's conductivities since: the adjoint solve and
+                # dM/dsigma need this forward's, so its hierarchy is rebuilt first
+                ctx.solver.set_sigma(ctx.sigma_used)
             gvox, gtab, info = ctx.solver.adjoint(a, psi, ctx.omega, grad_emag.contiguous(), tol=ctx.tol)
             if ctx.per_voxel:
                 g = gvox.to(ctx.sigma_dtype)

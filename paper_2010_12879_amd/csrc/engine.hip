@@ -90,6 +90,7 @@ struct Ctx {
     int *d_comp = nullptr;
     int *d_counts = nullptr;
     double *d_means = nullptr;
+    double *d_cpart = nullptr;   // partials of the component means (comp_mean_parts of the finest level)
     int ncoarse = 0;
     int *d_cdof_node = nullptr;
     int *d_node_cdof = nullptr;
@@ -165,6 +166,8 @@ struct Ctx {
     std::vector<std::pair<size_t, void *>> pool;
     std::vector<std::pair<void *, size_t>> sizes;
     size_t bytes = 0;
+    // device memory of the handle: the caller's allocator if given, else hipMalloc / hipFree
+    spfd_allocator alloc{};
 };
 
 struct HipFail {
@@ -216,6 +219,24 @@ size_t size_of(Ctx *c, void *p)
     return 0;
 }
 
+// one device buffer from the caller's allocator or hipMalloc, and its release
+hipError_t raw_alloc(Ctx *c, void **p, size_t bytes)
+{
+    if (c->alloc.alloc) {
+        *p = c->alloc.alloc(bytes, c->alloc.user);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+void raw_free(Ctx *c, void *p)
+{
+    if (c->alloc.alloc)
+        c->alloc.free(p, c->alloc.user);
+    else
+        (void)hipFree(p);
+}
+
 template <typename T>
 T *dalloc(Ctx *c, std::vector<void *> &owner, size_t count)
 {
@@ -229,13 +250,20 @@ T *dalloc(Ctx *c, std::vector<void *> &owner, size_t count)
             break;
         }
     if (!p) {
-        hipError_t e = hipMalloc(&p, bytes);
+        hipError_t e = raw_alloc(c, &p, bytes);
         if (e != hipSuccess) {
             // give the cached buffers back and try once more
-            for (auto &q : c->pool) (void)hipFree(q.second);
+            for (auto &q : c->pool) {
+                raw_free(c, q.second);
+                for (size_t i = 0; i < c->sizes.size(); ++i)
+                    if (c->sizes[i].first == q.second) {
+                        c->sizes.erase(c->sizes.begin() + i);
+                        break;
+                    }
+            }
             c->pool.clear();
-            e = hipMalloc(&p, bytes);
-            if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
+            e = raw_alloc(c, &p, bytes);
+            if (e != hipSuccess) throw HipFail{e, "device allocation"};
         }
         c->sizes.push_back({p, bytes});
     }
@@ -258,10 +286,11 @@ void free_all(Ctx *c, std::vector<void *> &owner)
 // return every buffer to the device
 void release_device(Ctx *c)
 {
+    free_all(c, c->src_allocs);
     free_all(c, c->rhs_allocs);
     free_all(c, c->hier_allocs);
     free_all(c, c->geo_allocs);
-    for (auto &q : c->pool) (void)hipFree(q.second);
+    for (auto &q : c->pool) raw_free(c, q.second);
     c->pool.clear();
     c->sizes.clear();
     c->bytes = 0;
@@ -430,6 +459,7 @@ OpArgs<double> level_op<double>(Ctx *c, int l)
     OpArgs<double> op{};
     const Level &L = c->lv[l];
     op.stride = L.nodes();
+    op.short_below = c->opt.short_segment_bricks;
     if (l == 0 && !c->voxel_mode) {
         op.w = nullptr;
         op.tiles = L.d_tiles;
@@ -448,6 +478,7 @@ OpArgs<float> level_op<float>(Ctx *c, int l)
     OpArgs<float> op{};
     const Level &L = c->lv[l];
     op.stride = L.nodes();
+    op.short_below = c->opt.short_segment_bricks;
     if (l == 0 && !c->voxel_mode) {
         op.w = nullptr;
         op.tiles = L.d_tiles;
@@ -741,6 +772,8 @@ void set_defaults(spfd_amg_options &o)
     if (o.split_level <= 0) o.split_level = 2;
     if (o.level1_degree <= 0) o.level1_degree = 4;
     if (o.level1_degree > 8) o.level1_degree = 8;
+    if (o.short_segment_bricks == 0) o.short_segment_bricks = 8192;
+    if (o.short_segment_bricks < 0) o.short_segment_bricks = 0;
 }
 
 // Step k of a smoothing pass is d_k = c1[k] d_{k-1} + c2[k] D^-1 (b - A x),
@@ -947,6 +980,7 @@ spfd_status do_build(Ctx *c)
         c->ncomp = c->h_ints[0];
         c->d_counts = dalloc<int>(c, c->hier_allocs, c->ncomp + 1);
         c->d_means = dalloc<double>(c, c->hier_allocs, c->ncomp + 1);
+        c->d_cpart = dalloc<double>(c, c->hier_allocs, comp_mean_parts(L0.nb));
         HIPCHK(hipMemsetAsync(c->d_counts, 0, (c->ncomp + 1) * sizeof(int), c->stream));
         HIPCHK(launch_comp_counts(c->d_comp, n, c->d_counts, c->stream));
     }
@@ -991,17 +1025,20 @@ spfd_status do_build(Ctx *c)
                                C.nb, C.d_w64, C.d_w32, C.nodes(), c->stream));
         // the first coarse level of an FP32 cycle is bandwidth-bound and smoothed hardest: its smoothing
         // and restriction read FP16 weights scaled so the largest is 2^15 (relative rounding 2^-11;
-        // the Galerkin operators below it come from the FP64 weights)
-        if (c->opt.precision == SPFD_MIXED && c->lv.size() == 1) {
-            unsigned *dm = dalloc<unsigned>(c, c->hier_allocs, 1);
-            HIPCHK(hipMemsetAsync(dm, 0, sizeof(unsigned), c->stream));
+        // the Galerkin operators below it come from the FP64 weights).  If the smallest nonzero
+        // weight would then fall below FP16's normal range (2^-14), the FP32 weights are kept.
+        if (c->opt.precision == SPFD_MIXED && c->lv.size() == 1 && !c->opt.level1_fp32) {
+            unsigned *dm = dalloc<unsigned>(c, c->hier_allocs, 2);
+            const unsigned init[2] = {0u, 0x7f800000u};
+            memcpy(c->h_ints, init, sizeof(init));
+            HIPCHK(hipMemcpyAsync(dm, c->h_ints, sizeof(init), hipMemcpyHostToDevice, c->stream));
             HIPCHK(launch_wmax(C.d_w32, 3LL * C.nodes(), dm, c->stream));
-            unsigned hm = 0;
-            HIPCHK(hipMemcpyAsync(&hm, dm, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipMemcpyAsync(c->h_ints, dm, sizeof(init), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
-            float mw;
-            memcpy(&mw, &hm, sizeof(float));
-            if (mw > 0.0f) {
+            float mw, mp;
+            memcpy(&mw, &c->h_ints[0], sizeof(float));
+            memcpy(&mp, &c->h_ints[1], sizeof(float));
+            if (mw > 0.0f && (double)mp / mw * 32768.0 >= 0x1p-14) {
                 C.w16s = mw / 32768.0f;
                 C.d_w16 = dalloc<uint16_t>(c, c->hier_allocs, (size_t)3 * C.nodes());
                 HIPCHK(launch_w16(C.d_w32, 3LL * C.nodes(), 1.0f / C.w16s, C.d_w16, c->stream));
@@ -1538,7 +1575,7 @@ spfd_status solve_batch(Ctx *c, const double *b, long long bvs, Scal *sc, Scal *
         if (status[i] != 0 && worst == SPFD_OK) worst = (spfd_status)status[i];
         // gauge: zero mean per connected component, 0 outside the conductor
         TScope ts(c, SPFD_K_GAUGE, (double)L0.dofs * (12.0 * (c->ncomp < 16 ? c->ncomp : 1) + 12.0) + nn * 8.0);
-        HIPCHK(launch_comp_mean(topo, c->d_x + i * n0, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_part,
+        HIPCHK(launch_comp_mean(topo, c->d_x + i * n0, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_cpart,
                                 c->stream));
         HIPCHK(launch_psi_out(c->d_x + i * n0, c->d_comp, c->d_means, L0.d_slot_of, c->g, psi + i * nn, c->stream));
         if (info) {
@@ -1655,7 +1692,7 @@ spfd_status solve_many(Ctx **hs, int n, const spfd_solve_options &so, double **p
                 if (status != 0 && st == SPFD_OK) st = (spfd_status)status;
                 TScope ts(c, SPFD_K_GAUGE, (double)L0.dofs * 24.0 + nn * 8.0);
                 HIPCHK(launch_comp_mean(L0.topo(), c->d_x + i * n0, c->d_comp, c->ncomp, c->d_counts, c->d_means,
-                                        c->d_part, c->stream));
+                                        c->d_cpart, c->stream));
                 HIPCHK(launch_psi_out(c->d_x + i * n0, c->d_comp, c->d_means, L0.d_slot_of, c->g, psi[k] + i * nn,
                                       c->stream));
                 if (info) {
@@ -1694,16 +1731,18 @@ struct spfd_ctx : Ctx {};
 
 extern "C" {
 
-spfd_status spfd_create(int device, void *hip_stream, spfd_handle *out)
+spfd_status spfd_create(int device, void *hip_stream, const spfd_allocator *alloc, spfd_handle *out)
 {
     if (!out) return SPFD_INVALID_ARG;
     *out = nullptr;
+    if (alloc && (!alloc->alloc != !alloc->free)) return SPFD_INVALID_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SPFD_INVALID_ARG;
     spfd_ctx *c = new (std::nothrow) spfd_ctx();
     if (!c) return SPFD_OUT_OF_MEMORY;
     c->device = device;
     c->user_stream = (hipStream_t)hip_stream;
+    if (alloc && alloc->alloc) c->alloc = *alloc;
     try {
         HIPCHK(hipSetDevice(device));
         // own stream (default priority, no implicit sync with the null stream), ordered after the caller's
@@ -1713,6 +1752,7 @@ spfd_status spfd_create(int device, void *hip_stream, spfd_handle *out)
         c->d_ints = dalloc<int>(c, c->geo_allocs, 64);
         HIPCHK(hipHostMalloc((void **)&c->h_ints, 64 * sizeof(int), hipHostMallocDefault));
     } catch (const HipFail &f) {
+        release_device(c);
         if (c->ev_user) (void)hipEventDestroy(c->ev_user);
         for (hipEvent_t e : c->ev_it)
             if (e) (void)hipEventDestroy(e);
@@ -1954,27 +1994,36 @@ spfd_status spfd_solve(spfd_handle h, const spfd_solve_options *opt, double *psi
     API_GUARD(h)
 }
 
-spfd_status spfd_efield(spfd_handle h, double omega, const double *a, const double *psi, double *u_edges, double *emag)
+spfd_status spfd_efield(spfd_handle h, double omega, int nsrc, const double *a, const double *psi, double *u_edges,
+                        double *emag)
 {
     if (!h) return SPFD_INVALID_ARG;
     if (h->state < 2) return fail(h, SPFD_BAD_STATE, "set geometry and conductivities first");
     if (!a || !psi || !emag) return fail(h, SPFD_INVALID_ARG, "a, psi and emag are required");
+    if (nsrc < 1) return fail(h, SPFD_INVALID_ARG, "nsrc must be >= 1");
     if (!isfinite(omega)) return fail(h, SPFD_INVALID_ARG, "omega must be finite");
     try {
         HIPCHK(hipSetDevice(h->device));
         enter(h);
         const double *sv = h->voxel_mode ? h->d_sigvox : nullptr;
-        const double nvox = (double)h->g.nx * h->g.ny * h->g.nz;
+        const long long nvl = (long long)h->g.nx * h->g.ny * h->g.nz;
+        const long long nnl = (long long)h->g.Nx * h->g.Ny * h->g.Nz;
+        const double nvox = (double)nvl, nn = (double)nnl;
         const double body = h->state >= 3 ? (double)h->lv[0].dofs : nvox;
-        {
-            // labels of all voxels, |E| of all voxels; psi (8 corners) and a (12 edges) counted once per body node
-            TScope ts(h, SPFD_K_EFIELD, nvox * (1.0 + 8.0) + body * (8.0 + 24.0));
-            HIPCHK(launch_efield(h->d_labels, h->d_table64, sv, h->g, h->h, omega, a, psi, emag, h->stream));
-        }
-        if (u_edges) {
-            const double nn = (double)h->g.Nx * h->g.Ny * h->g.Nz;
-            TScope ts(h, SPFD_K_EFIELD, nvox * 1.0 + nn * 24.0 + body * (8.0 + 24.0));
-            HIPCHK(launch_uedges(h->d_labels, h->d_table64, sv, h->g, a, psi, u_edges, h->stream));
+        for (int k = 0; k < nsrc; ++k) {
+            const double *ak = a + (long long)k * 3 * nnl;
+            const double *pk = psi + (long long)k * nnl;
+            {
+                // labels of all voxels, |E| of all voxels; psi (8 corners) and a (12 edges) counted once per body node
+                TScope ts(h, SPFD_K_EFIELD, nvox * (1.0 + 8.0) + body * (8.0 + 24.0));
+                HIPCHK(launch_efield(h->d_labels, h->d_table64, sv, h->g, h->h, omega, ak, pk, emag + k * nvl,
+                                     h->stream));
+            }
+            if (u_edges) {
+                TScope ts(h, SPFD_K_EFIELD, nvox * 1.0 + nn * 24.0 + body * (8.0 + 24.0));
+                HIPCHK(launch_uedges(h->d_labels, h->d_table64, sv, h->g, ak, pk, u_edges + (long long)k * 3 * nnl,
+                                     h->stream));
+            }
         }
         HIPCHK(hipStreamSynchronize(h->stream));
         return SPFD_OK;

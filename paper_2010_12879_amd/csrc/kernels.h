@@ -48,6 +48,7 @@ struct OpArgs {
     T geo4[3];               // dual area / length / 4 per direction
     const uint16_t *wh = nullptr;  // FP16 bits of w / whs (first coarse level of an FP32 cycle), read instead of w
     float whs = 0.0f;
+    int short_below = 8192;        // stored-weight levels with fewer bricks run 4-node column segments
 };
 
 // A batch of right sides solved together: launch grids get a y-dimension of
@@ -73,8 +74,9 @@ hipError_t launch_label_tiles(const uint8_t *labels, const Grid &g, const int4 *
                               hipStream_t s);
 hipError_t launch_weights0(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,
                            const double geo4[3], const int4 *coord, int nb, double *w64, float *w32, hipStream_t s);
-// largest of n non-negative weights (its bits atomically maxed into *out, which starts at 0),
-// and FP16 copies h = w * inv rounded to nearest
+// largest and smallest positive of n non-negative weights (bits atomically maxed into out[0], which
+// starts at 0, and minned into out[1], which starts at the bits of +inf), and FP16 copies
+// h = w * inv rounded to nearest
 hipError_t launch_wmax(const float *w, long long n, unsigned *out, hipStream_t s);
 hipError_t launch_w16(const float *w, long long n, float inv, uint16_t *h, hipStream_t s);
 hipError_t launch_galerkin(const double *wf, long long fstride, const int *f_slot_of, int fGx, int fGy, int fGz,
@@ -215,8 +217,10 @@ hipError_t launch_coarse_apply(const TB *bc, T *xc, const double *Ainv, const in
                                const Scal *sc, const Batch &bt, hipStream_t s);
 
 // ---------------------------------------------------------------- gauge, output, post-processing
+// means[c] = mean of x over component c, in a fixed summation order; part holds comp_mean_parts(nb) doubles
+size_t comp_mean_parts(int nb);
 hipError_t launch_comp_mean(Topo topo, const double *x, const int *comp, int ncomp, const int *counts,
-                            double *sums, double *part, hipStream_t s);
+                            double *means, double *part, hipStream_t s);
 hipError_t launch_psi_out(const double *x, const int *comp, const double *means, const int *slot_of, const Grid &g,
                           double *psi, hipStream_t s);
 hipError_t launch_psi_in(const double *psi, const int *comp, const int4 *coord, int nb, const Grid &g, double *x,

@@ -80,12 +80,18 @@ __global__ void k_brick_flags(const uint8_t *__restrict__ labels, const double *
 }
 
 // non-negative floats order like their bit patterns
+// out[0]: bits of the largest weight (starts at 0), out[1]: bits of the smallest positive one (starts at
+// the bits of +inf); non-negative floats order like their bit patterns
 __global__ void k_wmax(const float *w, long long n, unsigned *out)
 {
-    float m = 0.0f;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        m = fmaxf(m, w[i]);
+    float m = 0.0f, mp = INFINITY;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float v = w[i];
+        m = fmaxf(m, v);
+        if (v > 0.0f) mp = fminf(mp, v);
+    }
     atomicMax(out, __float_as_uint(m));
+    atomicMin(out + 1, __float_as_uint(mp));
 }
 __global__ void k_w16(const float *w, long long n, float inv, uint16_t *h)
 {
@@ -1256,51 +1262,66 @@ template hipError_t launch_coarse_apply<float, double>(const double *, float *, 
 // gauge, output, post-processing
 // ============================================================================
 
-// partial sums of x over component c (deterministic two-stage sum, one pass per component)
+// Component means in a fixed summation order (bitwise reproducible for any
+// number of components): up to COMP_PASS components per pass; every brick
+// workgroup forms the sum of each component over its 512 nodes (wave sums,
+// then the eight waves in order) and stores one partial per (component,
+// brick); one workgroup per component then adds its partials in brick order.
+constexpr int COMP_PASS = 16;
+
 __global__ __launch_bounds__(NT) void k_comp_sum(Topo topo, const double *__restrict__ x, const int *__restrict__ comp,
-                                                 int c, double *part)
+                                                 int c0, int nk, double *part)
 {
-    __shared__ double red[8];
+    __shared__ double red[COMP_PASS][NT / 64];
     const int bk = xcd_brick(blockIdx.x, topo.nb);
     if (bk < 0) return;
     const long long n = (long long)bk * BS + threadIdx.x;
-    const double v = comp[n] == c ? x[n] : 0.0;
-    const double tot = block_sum(v, red);
-    if (threadIdx.x == 0) part[bk] = tot;
-}
-
-// many components: FP64 atomics (order-dependent rounding) then division
-__global__ void k_comp_sum_atomic(long long n, const double *__restrict__ x, const int *__restrict__ comp, double *sums)
-{
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        const int c = comp[i];
-        if (c >= 0) atomicAdd(sums + c, x[i]);
+    const int c = comp[n] - c0;
+    const double v = x[n];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < nk; ++k) {
+        const double t = wave_sum(c == k ? v : 0.0);
+        if (lane == 0) red[k][wv] = t;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nk) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) t += red[threadIdx.x][w];
+        part[(long long)threadIdx.x * topo.nb + bk] = t;
     }
 }
 
-__global__ void k_comp_div(int nc, const int *counts, double *means)
+// mean of component c0 + blockIdx.x: its nb partials summed in a fixed order
+__global__ __launch_bounds__(1024) void k_comp_finish(const double *__restrict__ part, int nb, int c0,
+                                                      const int *__restrict__ counts, double *means)
 {
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x)
-        means[c] = counts[c] > 0 ? means[c] / (double)counts[c] : 0.0;
+    __shared__ double red[16];
+    const int k = blockIdx.x;
+    const double *p = part + (long long)k * nb;
+    double t = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) t += p[i];
+    t = wave_sum(t);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+        const int cnt = counts[c0 + k];
+        means[c0 + k] = cnt > 0 ? s / (double)cnt : 0.0;
+    }
 }
+
+size_t comp_mean_parts(int nb) { return (size_t)COMP_PASS * (nb > 0 ? nb : 1); }
 
 hipError_t launch_comp_mean(Topo topo, const double *x, const int *comp, int ncomp, const int *counts, double *means,
                             double *part, hipStream_t s)
 {
     if (topo.nb <= 0 || ncomp <= 0) return hipSuccess;
-    if (ncomp <= 16) {
-        for (int c = 0; c < ncomp; ++c) {
-            SPFD_LAUNCH(k_comp_sum, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, comp, c, part);
-            hipError_t e = launch_finish(part, topo.nb, FIN_MEAN, nullptr, 0, s, means, counts, c, 1, 0);
-            if (e != hipSuccess) return e;
-        }
-    } else {
-        const long long n = (long long)topo.nb * BS;
-        hipError_t e = launch_fill<double>(means, ncomp, 0.0, s);
-        if (e != hipSuccess) return e;
-        const unsigned gb = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
-        SPFD_LAUNCH(k_comp_sum_atomic, dim3(gb), dim3(256), 0, s, n, x, comp, means);
-        SPFD_LAUNCH(k_comp_div, dim3((ncomp + 255) / 256), dim3(256), 0, s, ncomp, counts, means);
+    for (int c0 = 0; c0 < ncomp; c0 += COMP_PASS) {
+        const int nk = ncomp - c0 < COMP_PASS ? ncomp - c0 : COMP_PASS;
+        SPFD_LAUNCH(k_comp_sum, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, topo, x, comp, c0, nk, part);
+        SPFD_LAUNCH(k_comp_finish, dim3(nk), dim3(1024), 0, s, part, topo.nb, c0, counts, means);
     }
     return hipGetLastError();
 }

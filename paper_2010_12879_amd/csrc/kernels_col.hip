@@ -902,11 +902,11 @@ static dim3 col_grid(int nb, int nbatch)
     return dim3(xcd_grid(col_ngroups<ZPL>(nb)), nbatch);
 }
 
-// Coarser structured levels (stored weights) with few bricks run shorter
-// segments: all their waves are resident at once, so a kernel lasts about one
-// wave's load-to-store latency, which shrinks with the segment (body phantom:
-// 8 -> 4 nodes per lane saves 0.3 ms per solve, 2 is no better than 4).
-constexpr int SMALL_NB = 8192;
+// Coarser structured levels (stored weights) with few bricks (op.short_below,
+// 8192 by default) run shorter segments: all their waves are resident at once,
+// so a kernel lasts about one wave's load-to-store latency, which shrinks with
+// the segment (body phantom: 8 -> 4 nodes per lane saves 0.3 ms per solve, 2
+// is no better than 4).
 constexpr int ZPL_SMALL = 4;
 
 template <typename T, typename TB, int ZPL, bool LABEL>
@@ -925,7 +925,7 @@ hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, 
     constexpr int Z = zpl_cycle<T>();
     if (!op.w)
         cheb_first_z<T, TB, Z, true>(op, topo, b, x, c0, sc, bt, s);
-    else if (topo.nb < SMALL_NB)
+    else if (topo.nb < op.short_below)
         cheb_first_z<T, TB, ZPL_SMALL, false>(op, topo, b, x, c0, sc, bt, s);
     else
         cheb_first_z<T, TB, Z, false>(op, topo, b, x, c0, sc, bt, s);
@@ -970,7 +970,7 @@ hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T
     const Prolong pr{xc, parent_slot, fcoord, (double)pscale, bt.vsc};
     const Dots dt{dot_q, dot_part, bt.ps, 0};
     // the dot-product partials are counted by cheb_dot_parts (segment length Z)
-    const bool small = op.w && !dot_part && topo.nb < SMALL_NB;
+    const bool small = op.w && !dot_part && topo.nb < op.short_below;
     const int sel = (small ? 8 : 0) | (op.w ? 0 : 4) | (xc ? 2 : 0) | (dot_part ? 1 : 0);
 #define SPFD_CHEB_CASE(K, ZZ, LAB, PRO, DOT)                                                                          \
     case K:                                                                                                           \
@@ -1020,7 +1020,7 @@ hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, co
     constexpr int Z = zpl_cycle<T>();
     if (!op.w)
         resid_restrict_z<T, TB, Z, true>(op, topo, b, x, bc, parent_slot, fcoord, sc, bt, s, xc, dinv_c, c0);
-    else if (topo.nb < SMALL_NB)
+    else if (topo.nb < op.short_below)
         resid_restrict_z<T, TB, ZPL_SMALL, false>(op, topo, b, x, bc, parent_slot, fcoord, sc, bt, s, xc, dinv_c, c0);
     else
         resid_restrict_z<T, TB, Z, false>(op, topo, b, x, bc, parent_slot, fcoord, sc, bt, s, xc, dinv_c, c0);

@@ -104,7 +104,8 @@ hipError_t launch_quantiles(const uint8_t *labels, const double *table, const do
 {
     SelState *st = (SelState *)work;
     unsigned int *hist = (unsigned int *)(st + ngroups);
-    hipError_t e = hipMemsetAsync(hist, 0, (size_t)ngroups * SEL_BINS * sizeof(unsigned int), s);
+    // cleared by a kernel, not a memset node: callers may capture this into a graph
+    hipError_t e = launch_fill<int>((int *)hist, (long long)ngroups * SEL_BINS, 0, s);
     if (e != hipSuccess) return e;
     long long blocks = (nvox + 255) / 256;
     if (blocks > 4096) blocks = 4096;

@@ -140,3 +140,16 @@ def voxel_emag_bruteforce(u, body, h, omega):
                     comp.append(s / 4.0 / h[d])
                 E[k, j, i] = omega * np.sqrt(sum(x * x for x in comp))
     return E
+
+
+def project_mean_zero_fast(x, comp, ncomp):
+    """project_mean_zero for large grids: per-component means by bincount (comp = -1 marks non-DOF
+    nodes, set to 0); the same arithmetic definition, summed in a different order."""
+    c = comp.reshape(-1)
+    v = x.reshape(-1)
+    sel = c >= 0
+    sums = np.bincount(c[sel], weights=v[sel], minlength=ncomp)
+    cnt = np.bincount(c[sel], minlength=ncomp)
+    out = np.zeros_like(v)
+    out[sel] = v[sel] - (sums / np.maximum(cnt, 1))[c[sel]]
+    return out.reshape(x.shape)

@@ -44,3 +44,15 @@ def test_binding_refuses_without_library(tmp_path):
             P.load_library(str(tmp_path / "missing.so"))
     finally:
         P._lib = saved
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libspfd.so not built")
+def test_create_rejects_half_an_allocator():
+    # argument validation only (returns before any device call): alloc without free
+    import paper_2010_12879_amd as P
+    P.load_library()
+    half = P.Allocator()
+    half.alloc = P._ALLOC_FN(lambda n, u: None)
+    h = ctypes.c_void_p()
+    st = P._lib.spfd_create(0, None, ctypes.byref(half), ctypes.byref(h))
+    assert st == 1 and not h.value

@@ -1,0 +1,176 @@
+"""Boundary and robustness of the HIP path (through the C-ABI):
+
+* the handle's device memory from a caller's allocator (PyTorch's caching allocator):
+  torch.cuda.memory_allocated() accounts for the handle's device_bytes and gets it back at
+  destroy, with results bit-identical to the library's own hipMalloc;
+* spfd_efield over several sources equals one call per source, bitwise;
+* the autograd Function's backward is taken at the conductivities of its own forward, also after
+  another forward has changed the solver (checked against the oracle's adjoint);
+* the per-component gauge is reproducible bit for bit with more than 16 components;
+* the FP32 cycle with 8-node segments on the first coarse level, with its FP16 and FP32 weights,
+  reaches the oracle's solution (the path a level above 8,192 bricks takes);
+* per-voxel conductivities (stored-weight finest level): forward solve, |E| and adjoint gradient
+  against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2010_12879_amd as P  # noqa: E402
+
+DEV = torch.device("cuda:0")
+BAR = {"fp64": 1e-7, "mixed": 1e-6}
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _relmax(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def test_torch_allocator_accounts_device_memory():
+    print("case torch allocator", flush=True)
+    w = W.config(1)
+    lab, a = _dev(w.labels), _dev(w.a)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated(DEV)
+    s = P.Solver(lab, w.sigma_table, w.h, precision="mixed", torch_memory=True)
+    psi_t, info_t = s.solve(a, tol=1e-10)
+    held = torch.cuda.memory_allocated(DEV) - before - psi_t.numel() * 8
+    nbytes = s.info()["device_bytes"]
+    print(f"device_bytes {nbytes}, torch accounts {held}", flush=True)
+    # every buffer of the handle is a block of torch's allocator (blocks rounded up to 512 bytes)
+    assert nbytes <= held <= nbytes + (1 << 20)
+    s.close()
+    torch.cuda.synchronize()
+    # everything the handle held is back (only psi remains, in a block rounded up to 512 bytes)
+    assert 0 <= torch.cuda.memory_allocated(DEV) - before - psi_t.numel() * 8 < 512
+    s2 = P.Solver(lab, w.sigma_table, w.h, precision="mixed", torch_memory=False)
+    psi_h, info_h = s2.solve(a, tol=1e-10)
+    s2.close()
+    assert torch.equal(psi_t, psi_h) and info_t == info_h
+
+
+def test_efield_many_sources_equals_single():
+    print("case efield batched", flush=True)
+    w = W.config(1)
+    rng = np.random.default_rng(8)
+    a2 = np.stack([w.a, w.a * 0.5 + rng.standard_normal(w.a.shape) * 1e-9])
+    s = P.Solver(_dev(w.labels), w.sigma_table, w.h, precision="fp64")
+    ad = _dev(a2)
+    psi, infos = s.solve(ad, tol=1e-10)
+    emag, u = s.efield(ad, psi, w.omega, want_u=True)
+    assert emag.shape == (2, w.nz, w.ny, w.nx) and u.shape == (2, 3, w.nz + 1, w.ny + 1, w.nx + 1)
+    for k in range(2):
+        e1, u1 = s.efield(ad[k], psi[k], w.omega, want_u=True)
+        assert torch.equal(e1, emag[k]) and torch.equal(u1, u[k])
+    s.close()
+
+
+def test_backward_after_another_forward():
+    print("case autograd state", flush=True)
+    w = W.random_ellipsoid_phantom(40, 32, 48, seed=17, n_ell=8, semi_range=(3.0, 9.0))
+    lab, a = _dev(w.labels), _dev(w.a)
+    solver = P.Solver(lab, w.sigma_table, w.h, precision="fp64")
+    sig1 = torch.tensor(w.sigma_table, dtype=torch.float64, requires_grad=True)
+    e1 = P.SPFDField.apply(sig1, solver, a, w.omega, 1e-13)
+    J1 = torch.linalg.vector_norm(e1.reshape(-1), ord=8)
+    # a second forward on the same solver with other conductivities, before the first backward
+    other = np.array(w.sigma_table) * np.linspace(0.5, 2.0, len(w.sigma_table))
+    sig2 = torch.tensor(other, dtype=torch.float64, requires_grad=True)
+    e2 = P.SPFDField.apply(sig2, solver, a, w.omega, 1e-13)
+    J1.backward()
+    g1 = sig1.grad.numpy().copy()
+    # reference: the oracle's adjoint at the first conductivities and the first forward's potential
+    sv = w.sigma_voxel()
+    psi_ref, _ = oracle.solve(sv, w.h, w.a, tol=1e-13)
+    _, e_ref = oracle.efield(sv, w.h, w.a, psi_ref, w.omega)
+    _, gE = oracle.pnorm_objective(e_ref)
+    _, gt_ref, _ = oracle.adjoint(sv, w.h, w.a, psi_ref, w.omega, gE, tol=1e-13, labels=w.labels,
+                                  n_labels=len(w.sigma_table))
+    scale = np.abs(gt_ref).max()
+    assert np.abs(g1 - gt_ref).max() <= 1e-6 * scale, (g1, gt_ref)
+    # the second forward's own backward still works afterwards
+    torch.linalg.vector_norm(e2.reshape(-1), ord=8).backward()
+    assert np.all(np.isfinite(sig2.grad.numpy()))
+    solver.close()
+
+
+def test_many_components_gauge_is_deterministic():
+    print("case many components determinism", flush=True)
+    rng = np.random.default_rng(77)
+    nx, ny, nz = 45, 41, 43
+    labels = np.zeros((nz, ny, nx), np.uint8)
+    for k in range(3):
+        for j in range(3):
+            for i in range(3):
+                x0, y0, z0 = 2 + 15 * i, 1 + 14 * j, 3 + 14 * k
+                labels[z0:z0 + 9, y0:y0 + 10, x0:x0 + 11] = rng.integers(1, 4, (9, 10, 11))
+    table = np.array([0.0, 0.3, 1.1, 0.05])
+    a = rng.normal(size=(3, nz + 1, ny + 1, nx + 1)) * 1e-6
+    s = P.Solver(_dev(labels), table, (1e-3, 1.3e-3, 0.8e-3), precision="mixed")
+    assert s.info()["n_components"] == 27
+    ad = _dev(a)
+    p1, i1 = s.solve(ad, tol=1e-12)
+    p2, i2 = s.solve(ad, tol=1e-12)
+    s.close()
+    assert torch.equal(p1, p2) and i1 == i2
+
+
+@pytest.mark.parametrize("fp32_weights", [False, True])
+def test_long_segments_on_first_coarse_level(fp32_weights):
+    print(f"case level-1 8-node segments fp32_weights={fp32_weights}", flush=True)
+    w = W.config(1)
+    s = P.Solver(_dev(w.labels), w.sigma_table, w.h, precision="mixed", short_segment_bricks=-1,
+                 level1_fp32=fp32_weights)
+    a = _dev(w.a)
+    psi, info = s.solve(a, tol=1e-12, max_iter=400)
+    s.close()
+    ref, _ = oracle.solve(w.sigma_voxel(), w.h, w.a, tol=1e-12)
+    p = psi.cpu().numpy()
+    print(f"level-1 long segments: it={info['iterations']} err={_rel(p, ref):.2e}", flush=True)
+    assert info["status"] == "OK" and info["rel_residual"] <= 1e-12
+    assert _rel(p, ref) <= BAR["mixed"] and _relmax(p, ref) <= BAR["mixed"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_per_voxel_sigma_against_oracle(prec):
+    print(f"case per-voxel sigma {prec}", flush=True)
+    w = W.config(1)
+    rng = np.random.default_rng(19)
+    sv = w.sigma_voxel() * np.exp(rng.uniform(-0.5, 0.5, size=w.labels.shape))   # varies inside tissues
+    s = P.Solver(_dev(w.labels), _dev(sv), w.h, precision=prec)
+    a = _dev(w.a)
+    psi, info = s.solve(a, tol=1e-12, max_iter=400)
+    emag = s.efield(a, psi, w.omega)
+    ref, oinfo = oracle.solve(sv, w.h, w.a, tol=1e-12)
+    _, e_ref = oracle.efield(sv, w.h, w.a, ref, w.omega)
+    p, e = psi.cpu().numpy(), emag.cpu().numpy()
+    print(f"per-voxel {prec}: it={info['iterations']} psi err={_rel(p, ref):.2e} E err={_rel(e, e_ref):.2e}",
+          flush=True)
+    assert info["status"] == "OK" and s.info()["n_dofs"] == oinfo["ndof"]
+    assert _rel(p, ref) <= BAR[prec] and _relmax(p, ref) <= BAR[prec]
+    assert _rel(e, e_ref) <= BAR[prec]
+    if prec == "fp64":
+        # adjoint gradient per voxel, at the GPU's forward potential
+        J, gE = oracle.pnorm_objective(e)
+        gvox, gtab, ainfo = s.adjoint(a, psi, w.omega, _dev(gE), tol=1e-13, max_iter=400)
+        gs_ref, _, _ = oracle.adjoint(sv, w.h, w.a, p, w.omega, gE, tol=1e-13)
+        g = gvox.cpu().numpy()
+        print(f"per-voxel adjoint: err {_rel(g, gs_ref):.2e}", flush=True)
+        assert ainfo["status"] == "OK" and _rel(g, gs_ref) <= 1e-7
+    s.close()

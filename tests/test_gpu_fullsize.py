@@ -90,3 +90,48 @@ def test_fullsize_mixed_matches_fp64(body):
     p_mixed = body["mixed"][0]
     p_64 = body["fp64"][0]
     assert np.linalg.norm(p_mixed - p_64) <= 1e-6 * np.linalg.norm(p_64)
+
+
+@pytest.fixture(scope="module")
+def manufactured_body():
+    """The body phantom with a manufactured source: a = -G psi* + M^-1 C^T W, so that the exact
+    discrete answer is psi = Pi psi* (zero mean per component) and u = M^-1 C^T W (C G = 0)."""
+    print("case full-size manufactured: generating", flush=True)
+    from tests import discrete as D
+    w = W.body_phantom(with_source=False)
+    sig = w.sigma_voxel()
+    M = oracle.edge_conductance(sig, w.h)
+    a, psi_star, u_exact = D.manufactured(M, sig > 0, np.random.default_rng(2010))
+    del M
+    comp, ncomp = oracle.components(sig, w.h)
+    expect = D.project_mean_zero_fast(psi_star, comp, ncomp)
+    return w, a, expect, u_exact
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fullsize_manufactured_solution(manufactured_body, prec):
+    """Eq. (3) at the benchmark's size against its exact discrete solution, both sides at the
+    matching criterion 1e-12: relative 2-norm and max-norm of the potential, and the edge
+    voltages u = a + G psi (Eq. (1)) against M^-1 C^T W."""
+    w, a, expect, u_exact = manufactured_body
+    print(f"case full-size manufactured {prec}", flush=True)
+    bar = {"fp64": 1e-7, "mixed": 1e-6}[prec]
+    s = P.Solver(torch.from_numpy(w.labels).to(DEV), w.sigma_table, w.h, precision=prec)
+    ad = torch.from_numpy(a).to(DEV)
+    psi, info = s.solve(ad, tol=1e-12, max_iter=400)
+    _, u = s.efield(ad, psi, w.omega, want_u=True)
+    s.close()
+    p = psi.cpu().numpy()
+    del psi
+    u = u.cpu().numpy()
+    e2 = np.linalg.norm(p - expect) / np.linalg.norm(expect)
+    emax = np.abs(p - expect).max() / np.abs(expect).max()
+    cond = u_exact != 0
+    u2 = np.linalg.norm(u - u_exact) / np.linalg.norm(u_exact)
+    print(f"full-size manufactured {prec}: it={info['iterations']} relres={info['rel_residual']:.2e} "
+          f"psi 2-norm {e2:.2e} max {emax:.2e}, u 2-norm {u2:.2e}", flush=True)
+    assert info["status"] == "OK" and info["rel_residual"] <= 1e-12
+    assert e2 <= bar and emax <= bar
+    assert u2 <= 10 * bar   # u = a + G psi: G differences the potential's error
+    # where the exact edge voltage vanishes (non-conducting edges) the GPU's is exactly 0
+    assert np.all(u[~cond & (np.abs(a) == 0)] == 0)
