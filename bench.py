@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the multi-source and multi-phantom runs")
     ap.add_argument("--scale-1mm", action="store_true",
                     help="also solve the 1 mm body phantom (500x300x1800 voxels, ~69.7 M unknowns)")
+    ap.add_argument("--no-cold", action="store_true", help="skip the cold-cache per-kernel timing")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient and its finite differences")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the runs, copy a MIB-sized device buffer 3 times (a plain copy kernel of known "
                          "size, to scale hardware byte counters)")
@@ -134,10 +136,29 @@ def run_precision(prec, w, lab, a, args, P, torch):
     for _ in range(args.steps):
         step(True)
     stats = {name: P.spfd_timing_get(h, k) for k, name in enumerate(P.KERNEL_CLASSES)}
+    cold = None
+    if not args.no_cold:
+        # the same kernels with the caches flushed before every sampled launch (outside its events)
+        P.spfd_timing(h, sum(1 << k for k in FINE_CLASSES) | P.TIMING_COLD)
+        for _ in range(2):
+            step(False)
+        cold = {name: P.spfd_timing_get(h, k) for k, name in enumerate(P.KERNEL_CLASSES)}
+        P.spfd_timing(h, 0)
+    psi_out = psi.cpu().numpy()
+    # the paper's own criterion (relative residual below 1e-12, Sec. II.A), same hierarchy
+    tight = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st12, inf12 = P.spfd_solve(h, P.SolveOptions(1e-12, 500, 0), psi, 1)
+        torch.cuda.synchronize()
+        tight.append(time.perf_counter() - t0)
+    tight_info = {"solve_ms_mean": mean(tight[1:]) * 1e3, "iterations": inf12[0]["iterations"],
+                  "rel_residual": inf12[0]["rel_residual"], "status": inf12[0]["status"]}
     ndofs = P.spfd_get_info(h)
     ndofs["hierarchy"] = [P.spfd_level_info(h, lv) for lv in range(ndofs["n_levels"])]
     P.spfd_destroy(h)
-    return phases, info, stats, ndofs, psi.cpu().numpy(), emag
+    return phases, info, stats, ndofs, psi_out, emag, cold, tight_info
 
 
 def mean(v):
@@ -280,6 +301,71 @@ def fgmres_compare(w, lab, a, P, torch, args):
     return out
 
 
+def stream_ceiling(torch, P):
+    """Best STREAM triad over three 1 GiB float64 arrays (HBM, far beyond the Infinity Cache), GB/s."""
+    n = (1 << 30) // 8
+    bufs = [torch.ones(n, dtype=torch.float64, device="cuda:0") for _ in range(3)]
+    torch.cuda.synchronize()
+    g = P.spfd_stream_triad(bufs[0], bufs[1], bufs[2], reps=5, stream=torch.cuda.current_stream().cuda_stream)
+    del bufs
+    torch.cuda.empty_cache()
+    return g
+
+
+def adjoint_block(w, lab, a, P, torch):
+    """Gradient of J = (sum over body voxels of |E|^8)^(1/8) with respect to the 40 tissue conductivities
+    on the benchmark phantom: forward solve, E-field and adjoint solve (FP64 cycle, same hierarchy), timed;
+    then central finite differences (h = 1e-6 sigma_t, two rebuilt hierarchies and solves per tissue) on
+    all tissues."""
+    tol = 1e-13
+    s = P.Solver(lab, w.sigma_table, w.h, precision="fp64")
+
+    def J_of(emag):
+        return torch.linalg.vector_norm(emag.reshape(-1), ord=8)
+
+    s.solve(a, tol=tol)                                   # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psi, info = s.solve(a, tol=tol)
+    emag = s.efield(a, psi, w.omega)
+    J = J_of(emag)
+    gE = (emag / J) ** 7                                  # dJ/d|E_v| (0 in air, where |E| = 0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gvox, gtab, ainfo = s.adjoint(a, psi, w.omega, gE, tol=tol)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    grad = gtab[:len(w.sigma_table)]
+    fd = []
+    base = list(w.sigma_table)
+    t3 = time.perf_counter()
+    for t in range(1, len(base)):
+        hstep = 1e-6 * base[t]
+        vals = []
+        for sgn in (1.0, -1.0):
+            tab = list(base)
+            tab[t] += sgn * hstep
+            s.set_sigma(tab)
+            p_, _ = s.solve(a, tol=tol)
+            vals.append(float(J_of(s.efield(a, p_, w.omega))))
+        fd.append((vals[0] - vals[1]) / (2 * hstep))
+    t4 = time.perf_counter()
+    s.close()
+    scale = max(abs(grad[t] * base[t]) for t in range(1, len(base)))
+    errs = []
+    for t in range(1, len(base)):
+        if abs(grad[t] * base[t]) >= 1e-3 * scale:
+            errs.append(abs(grad[t] - fd[t - 1]) / abs(fd[t - 1]))
+    euler = sum(grad[t] * base[t] for t in range(1, len(base))) / sum(abs(grad[t] * base[t]) for t in range(1, len(base)))
+    return {"workload": f"{w.name}, J = 8-norm of voxel |E| over the body, 40 tissue conductivities",
+            "tol": tol, "forward_solve_and_efield_ms": (t1 - t0) * 1e3, "adjoint_solve_ms": (t2 - t1) * 1e3,
+            "forward_iterations": info["iterations"], "adjoint_iterations": ainfo["iterations"],
+            "adjoint_status": ainfo["status"], "J": float(J),
+            "fd_tissues": len(base) - 1, "fd_compared": len(errs), "fd_max_rel_err": max(errs) if errs else None,
+            "fd_median_rel_err": sorted(errs)[len(errs) // 2] if errs else None,
+            "fd_s": t4 - t3, "euler_identity_rel": euler}
+
+
 def batch_phantoms(P, torch, args):
     """16 phantoms of 64^3 ... 192^3 voxels, each with its own hierarchy and stream, solved in lockstep."""
     import workloads as W
@@ -336,12 +422,12 @@ def main():
     res = {}
     for prec in args.precisions.split(","):
         res[prec] = run_precision(prec, w, lab, a, args, P, torch)
-        ph, info, stats, ninfo, _, _ = res[prec]
+        ph, info, stats, ninfo = res[prec][:4]
         print(f"# {prec}: solve {mean(ph['solve'])*1e3:.2f} ms, {info['iterations']} it, "
               f"relres {info['rel_residual']:.2e}", file=sys.stderr, flush=True)
 
     head = "mixed" if "mixed" in res else list(res)[0]
-    ph, info, stats, ninfo, psi_head, _ = res[head]
+    ph, info, stats, ninfo, psi_head, _, cold, tight = res[head]
     solve_s = mean(ph["solve"])
     # algorithmic HBM bytes of the solve: every kernel class except setup/rhs/efield, per step
     solve_bytes = sum(v["bytes"] for k, v in stats.items() if k not in ("rhs", "efield")) / args.steps
@@ -355,6 +441,19 @@ def main():
                          "est_ms_per_solve": avg_ms * v["launches"] / args.steps,
                          "algorithmic_gbs": v["timed_bytes"] / (v["timed_ms"] * 1e-3) / 1e9,
                          "bytes_per_launch": v["timed_bytes"] / v["timed_launches"]}
+    if cold:
+        for k, desc in FINE_CLASSES.items():
+            v = cold[P.KERNEL_CLASSES[k]]
+            if desc in kernels and v["timed_launches"] > 0 and v["timed_ms"] > 0:
+                c_us = v["timed_ms"] / v["timed_launches"] * 1e3
+                kernels[desc]["avg_us_cold"] = c_us
+                kernels[desc]["algorithmic_gbs_cold"] = v["timed_bytes"] / (v["timed_ms"] * 1e-3) / 1e9
+    ceiling = stream_ceiling(torch, P)
+    for d in kernels.values():
+        d["frac_of_peak"] = d["algorithmic_gbs"] / HBM_PEAK_GBS
+        d["frac_of_stream"] = d["algorithmic_gbs"] / ceiling if ceiling else None
+        if "algorithmic_gbs_cold" in d:
+            d["frac_of_peak_cold"] = d["algorithmic_gbs_cold"] / HBM_PEAK_GBS
     dom = max(kernels, key=lambda d: kernels[d]["est_ms_per_solve"]) if kernels else None
     achieved = kernels[dom]["algorithmic_gbs"] if dom else None
     dom_class = next((k for k, d in FINE_CLASSES.items() if d == dom), None)
@@ -375,7 +474,8 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 cycle / f64 CG" if head == "mixed" else "f64",
+        "dtype": ("f64 CG, f32 cycle (f16 weights on coarse level 1), f64 coarsest" if head == "mixed"
+                  else "f64"),
         "data": "synthetic",
         "config": {"workload": f"{w.name}: 2 mm body phantom, {ninfo['n_dofs']} unknowns, 40 tissues, "
                                f"rectangular loop 0.3x0.2 m at 85 kHz",
@@ -397,16 +497,27 @@ def main():
                      "traffic_gbs": traffic / (kernels[dom]["avg_us"] * 1e-6) / 1e9 if traffic else None,
                      "rocprof_median_us": float(prof_us) if prof_us else None,
                      "avg_us": kernels[dom]["avg_us"] if dom else None,
-                     "algorithmic_bytes_per_launch": kernels[dom]["bytes_per_launch"] if dom else None},
+                     "algorithmic_bytes_per_launch": kernels[dom]["bytes_per_launch"] if dom else None,
+                     "stream_triad_gbs": ceiling,
+                     "frac_of_stream": achieved / ceiling if (achieved and ceiling) else None,
+                     "avg_us_cold": kernels[dom].get("avg_us_cold") if dom else None,
+                     "frac_cold": kernels[dom].get("frac_of_peak_cold") if dom else None},
+        "solve_1e-12": {"mixed" if head == "mixed" else head: tight},
         "finest_level_kernels": kernels,
     }
     if "fp64" in res and head != "fp64":
-        ph64, info64, _, _, psi64, _ = res["fp64"]
+        ph64, info64, _, _, psi64, _, _, tight64 = res["fp64"]
         out["fp64_solve_ms_mean"] = mean(ph64["solve"]) * 1e3
         out["fp64_iterations"] = info64["iterations"]
         out["mixed_vs_fp64_speedup"] = mean(ph64["solve"]) / solve_s
         import numpy as np
         out["mixed_vs_fp64_rel_diff"] = float(np.linalg.norm(psi_head - psi64) / np.linalg.norm(psi64))
+        out["solve_1e-12"]["fp64"] = tight64
+        out["solve_1e-12"]["mixed_vs_fp64_speedup"] = tight64["solve_ms_mean"] / tight["solve_ms_mean"]
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_block(w, lab, a, P, torch)
+        print(f"# adjoint: {out['adjoint']['adjoint_solve_ms']:.1f} ms, fd max rel err "
+              f"{out['adjoint']['fd_max_rel_err']:.2e}", file=sys.stderr, flush=True)
     if not args.no_batch:
         out["fgmres_vs_cg"] = fgmres_compare(w, lab, a, P, torch, args)
         print(f"# fgmres: {out['fgmres_vs_cg']['fgmres']}", file=sys.stderr, flush=True)

@@ -209,6 +209,16 @@ spfd_status spfd_edge_potentials(spfd_handle h, const double *flux, double *a);
  * without conducting voxels.  Exact (radix selection on the FP64 values). */
 spfd_status spfd_percentile(spfd_handle h, const double *emag, double q, double *out_body, double *out_labels);
 
+/* A measurement aid for the roofline of the bandwidth-bound kernels: the
+ * STREAM triad a = b + 1.5 c over n doubles (device arrays, caller-owned,
+ * 16-byte aligned), in two launch shapes, each timed reps times with HIP
+ * events on hip_stream of `device` after one untimed run; *best_gbs (host)
+ * = the best 24 n bytes / time in GB/s.  Arrays much larger than the
+ * 256 MB Infinity Cache measure HBM.  SPFD_INVALID_ARG for null pointers,
+ * n < 2, reps < 1 or a bad device. */
+spfd_status spfd_stream_triad(int device, void *hip_stream, double *a, const double *b, const double *c,
+                              long long n, int reps, double *best_gbs);
+
 /* Solve Eq. (3) on several voxel models at once (each handle built, with its
  * sources set, on the same device).  The CG iterations of all handles advance
  * in lockstep, each handle's kernels on its own stream, so that problems of
@@ -255,7 +265,12 @@ enum {
  * counters.  While enabled, the launches of such a class in the second CG
  * iteration of every solve (run from the host, not from the captured graph)
  * are bracketed by two HIP events on the handle's stream: a sample of every
- * solve, at the cost of one eagerly launched iteration. */
+ * solve, at the cost of one eagerly launched iteration.  With
+ * SPFD_TIMING_COLD in the mask, a kernel that reads and writes a 1 GiB buffer
+ * (four times the Infinity Cache) runs before every timed launch, outside
+ * its events, so each sample starts from cold caches; the buffer is held
+ * until timing is set again without the flag. */
+#define SPFD_TIMING_COLD 0x80000000u
 spfd_status spfd_timing(spfd_handle h, unsigned int class_mask);
 /* Counters of a class since the last spfd_timing call: all launches and their
  * algorithmic bytes (counted whether or not the class is timed), and the timed

@@ -87,7 +87,8 @@ _lib = None
 EXPORTS = ["spfd_create", "spfd_destroy", "spfd_last_error", "spfd_set_geometry", "spfd_set_sigma_table",
            "spfd_set_sigma_voxel", "spfd_build", "spfd_get_info", "spfd_level_info", "spfd_set_num_rhs", "spfd_set_source",
            "spfd_solve", "spfd_solve_many", "spfd_efield", "spfd_edge_potentials", "spfd_percentile",
-           "spfd_adjoint", "spfd_timing", "spfd_timing_get"]
+           "spfd_adjoint", "spfd_timing", "spfd_timing_get", "spfd_stream_triad"]
+TIMING_COLD = 0x80000000
 # kernel classes of spfd_timing / spfd_timing_get (order of the enum in spfd.h)
 KERNEL_CLASSES = ["spmv", "update", "dots", "pupdate", "smooth0", "smooth0_first", "restrict0", "prolong0", "coarse",
                   "finish", "rhs", "efield", "gauge", "resid"]
@@ -127,6 +128,7 @@ def load_library(path: str = LIB_PATH):
     lib.spfd_solve_many.argtypes = [ctypes.POINTER(H), I, ctypes.POINTER(SolveOptions), ctypes.POINTER(P),
                                     ctypes.POINTER(RhsInfo)]
     lib.spfd_timing.argtypes = [H, ctypes.c_uint]
+    lib.spfd_stream_triad.argtypes = [I, P, P, P, P, ctypes.c_longlong, I, ctypes.POINTER(D)]
     LL = ctypes.POINTER(ctypes.c_longlong)
     lib.spfd_timing_get.argtypes = [H, I, LL, ctypes.POINTER(D), LL, ctypes.POINTER(D), ctypes.POINTER(D)]
     for name in EXPORTS:
@@ -304,6 +306,21 @@ def spfd_percentile(h, emag, q=0.99, n_labels=0):
     labs = (ctypes.c_double * n_labels)() if n_labels else None
     _check(h, load_library().spfd_percentile(h, _ptr(emag), float(q), ctypes.byref(body), labs))
     return body.value, (list(labs) if labs is not None else None)
+
+
+def spfd_stream_triad(a, b, c, reps=5, device=0, stream=None):
+    """Best STREAM-triad bandwidth (GB/s) a = b + 1.5 c over three float64 CUDA tensors of equal size."""
+    import torch
+    for t, n in ((a, "a"), (b, "b"), (c, "c")):
+        _require_cuda(t, torch.float64, None, n)
+    if not (a.numel() == b.numel() == c.numel()):
+        raise ValueError("a, b and c must have the same size")
+    best = ctypes.c_double()
+    st = load_library().spfd_stream_triad(int(device), ctypes.c_void_p(stream) if stream else None, _ptr(a), _ptr(b),
+                                          _ptr(c), int(a.numel()), int(reps), ctypes.byref(best))
+    if st != 0:
+        raise SPFDError(st, "spfd_stream_triad failed")
+    return best.value
 
 
 def spfd_timing(h, class_mask: int):

@@ -152,8 +152,11 @@ struct Ctx {
     const Scal *sg_sc = nullptr;
     StepGraph *capturing = nullptr;
     int step_ctx = 0;   // 0: outside the CG loop, 1: in an untimed CG step, 2: in the sampled step
-    // per-class launch timing (tracing aid)
+    // per-class launch timing (tracing aid); cold: a flush of d_flush before every timed launch
     unsigned tmask = 0;
+    bool tcold = false;
+    void *d_flush = nullptr;
+    std::vector<void *> flush_allocs;
     std::vector<hipEvent_t> tev[SPFD_K_COUNT];
     size_t tused[SPFD_K_COUNT] = {};
     long long tlaunch[SPFD_K_COUNT] = {};
@@ -286,6 +289,8 @@ void free_all(Ctx *c, std::vector<void *> &owner)
 // return every buffer to the device
 void release_device(Ctx *c)
 {
+    free_all(c, c->flush_allocs);
+    c->d_flush = nullptr;
     free_all(c, c->src_allocs);
     free_all(c, c->rhs_allocs);
     free_all(c, c->hier_allocs);
@@ -304,6 +309,8 @@ spfd_status fail(Ctx *c, spfd_status s, const std::string &msg)
 
 // Brackets one launch of kernel class `cls` with HIP events when timing is on
 // for that class, and adds the launch's algorithmic bytes to the class counter.
+constexpr size_t FLUSH_BYTES = (size_t)1 << 30;   // four times the Infinity Cache
+
 struct TScope {
     Ctx *c;
     int cls;
@@ -320,6 +327,8 @@ struct TScope {
         c->tlaunch[cls] += 1;
         c->tbytes[cls] += bytes;
         if (on) {
+            // cold timing: the caches are flushed first (outside the timed interval)
+            if (c->tcold && c->d_flush) (void)launch_flush(c->d_flush, FLUSH_BYTES, c->stream);
             // the launch inside the scope records both events itself
             hipEvent_t e0 = event(), e1 = event();
             if (!e0 || !e1) {
@@ -2183,7 +2192,16 @@ spfd_status spfd_timing(spfd_handle h, unsigned int class_mask)
     try {
         HIPCHK(hipSetDevice(h->device));
         HIPCHK(hipStreamSynchronize(h->stream));
-        h->tmask = class_mask;
+        h->tcold = (class_mask & SPFD_TIMING_COLD) != 0;
+        h->tmask = class_mask & ~(unsigned)SPFD_TIMING_COLD;
+        if (h->tcold && !h->d_flush) {
+            h->d_flush = dalloc<uint8_t>(h, h->flush_allocs, FLUSH_BYTES);
+            HIPCHK(hipMemsetAsync(h->d_flush, 0, FLUSH_BYTES, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+        } else if (!h->tcold && h->d_flush) {
+            free_all(h, h->flush_allocs);
+            h->d_flush = nullptr;
+        }
         for (int k = 0; k < SPFD_K_COUNT; ++k) {
             h->tused[k] = 0;
             h->tlaunch[k] = 0;

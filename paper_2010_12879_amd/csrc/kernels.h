@@ -310,4 +310,11 @@ hipError_t launch_adj_grad(const uint8_t *labels, const double *table, const dou
                            const double geo4[3], const double *a, const double *psi, const double *lam, double *grad,
                            double *lab_part, int nlab, double *lab_out, hipStream_t s);
 
+// ---------------------------------------------------------------- measurement aids
+// a = b + s c over n doubles (variant 0: one pair of doubles per thread; 1: four pairs)
+hipError_t launch_triad(double *a, const double *b, const double *c, long long n, double s, int variant,
+                        hipStream_t st);
+// read and write every 32-bit word of buf (evicts the caches before a cold timing)
+hipError_t launch_flush(void *buf, size_t bytes, hipStream_t st);
+
 }  // namespace spfd
