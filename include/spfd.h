@@ -209,6 +209,27 @@ spfd_status spfd_edge_potentials(spfd_handle h, const double *flux, double *a);
  * without conducting voxels.  Exact (radix selection on the FP64 values). */
 spfd_status spfd_percentile(spfd_handle h, const double *emag, double q, double *out_body, double *out_labels);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * quantile of spfd_percentile without a handle and without any allocation.
+ * Its work area is a fixed device array inside the library (272 KiB per GPU,
+ * held until the process ends), which limits it to n_labels <= 256; larger
+ * values give SPFD_INVALID_ARG.  All arrays are device memory: labels [nvox]
+ * (uint8); sigma_table [n_labels] (FP64, nullable when sigma_voxel is given);
+ * sigma_voxel [nvox] (FP64, nullable: then sigma_table[labels[v]]); emag
+ * [nvox]; out [1 + n_labels] (FP64, written): out[0] the whole body's value,
+ * out[1 + l] the value over the conducting voxels of label l (NaN if none).
+ * The body is the voxels with sigma > 0, the rule nearest rank (as in
+ * spfd_percentile).  The work is enqueued on hip_stream (NULL = default
+ * stream) of `device` and not waited for: out is valid once that stream has
+ * passed it.  Calls that overlap on one GPU share the work area and race;
+ * calls in order on one stream do not.  SPFD_INVALID_ARG for a null required
+ * pointer, nvox <= 0, q outside (0, 1] or a bad device; SPFD_HIP_ERROR if a
+ * launch fails. */
+spfd_status spfd_percentile_noalloc(int device, void *hip_stream, const uint8_t *labels, const double *sigma_table,
+                                    int n_labels, const double *sigma_voxel, long long nvox, const double *emag,
+                                    double q, double *out);
+
 /* A measurement aid for the roofline of the bandwidth-bound kernels: the
  * STREAM triad a = b + 1.5 c over n doubles (device arrays, caller-owned,
  * 16-byte aligned), in two launch shapes, each timed reps times with HIP

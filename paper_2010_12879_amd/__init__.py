@@ -87,7 +87,7 @@ _lib = None
 EXPORTS = ["spfd_create", "spfd_destroy", "spfd_last_error", "spfd_set_geometry", "spfd_set_sigma_table",
            "spfd_set_sigma_voxel", "spfd_build", "spfd_get_info", "spfd_level_info", "spfd_set_num_rhs", "spfd_set_source",
            "spfd_solve", "spfd_solve_many", "spfd_efield", "spfd_edge_potentials", "spfd_percentile",
-           "spfd_adjoint", "spfd_timing", "spfd_timing_get", "spfd_stream_triad"]
+           "spfd_percentile_noalloc", "spfd_adjoint", "spfd_timing", "spfd_timing_get", "spfd_stream_triad"]
 TIMING_COLD = 0x80000000
 # kernel classes of spfd_timing / spfd_timing_get (order of the enum in spfd.h)
 KERNEL_CLASSES = ["spmv", "update", "dots", "pupdate", "smooth0", "smooth0_first", "restrict0", "prolong0", "coarse",
@@ -125,6 +125,7 @@ def load_library(path: str = LIB_PATH):
     lib.spfd_adjoint.argtypes = [H, D, P, P, P, ctypes.POINTER(SolveOptions), P, P, ctypes.POINTER(RhsInfo)]
     lib.spfd_percentile.argtypes = [H, P, D, ctypes.POINTER(D), P]
     lib.spfd_edge_potentials.argtypes = [H, P, P]
+    lib.spfd_percentile_noalloc.argtypes = [I, P, P, P, I, P, ctypes.c_longlong, P, D, P]
     lib.spfd_solve_many.argtypes = [ctypes.POINTER(H), I, ctypes.POINTER(SolveOptions), ctypes.POINTER(P),
                                     ctypes.POINTER(RhsInfo)]
     lib.spfd_timing.argtypes = [H, ctypes.c_uint]
@@ -306,6 +307,29 @@ def spfd_percentile(h, emag, q=0.99, n_labels=0):
     labs = (ctypes.c_double * n_labels)() if n_labels else None
     _check(h, load_library().spfd_percentile(h, _ptr(emag), float(q), ctypes.byref(body), labs))
     return body.value, (list(labs) if labs is not None else None)
+
+
+def spfd_percentile_noalloc(labels, sigma_table, sigma_voxel, emag, q, out, device=0, stream=None):
+    """Allocation-free quantile: writes out[0] (whole body) and out[1 + l] (label l) on the device;
+    sigma_table (n_labels,) and/or sigma_voxel, labels, emag and out are CUDA tensors.  Enqueued on
+    `stream` (a hipStream_t int, None = default stream), not waited for."""
+    import torch
+    _require_cuda(labels, torch.uint8, None, "labels")
+    _require_cuda(emag, torch.float64, None, "emag")
+    _require_cuda(out, torch.float64, None, "out")
+    n_labels = sigma_table.numel() if sigma_table is not None else out.numel() - 1
+    if sigma_table is not None:
+        _require_cuda(sigma_table, torch.float64, None, "sigma_table")
+    if sigma_voxel is not None:
+        _require_cuda(sigma_voxel, torch.float64, None, "sigma_voxel")
+    if out.numel() < 1 + n_labels or labels.numel() != emag.numel():
+        raise ValueError("out needs 1 + n_labels entries and labels one per voxel of emag")
+    st = load_library().spfd_percentile_noalloc(int(device), ctypes.c_void_p(stream) if stream else None,
+                                                _ptr(labels), _ptr(sigma_table), int(n_labels), _ptr(sigma_voxel),
+                                                int(emag.numel()), _ptr(emag), float(q), _ptr(out))
+    if st != 0:
+        raise SPFDError(st, "spfd_percentile_noalloc failed")
+    return st
 
 
 def spfd_stream_triad(a, b, c, reps=5, device=0, stream=None):

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspfd.so")
-SOURCES = ["kernels.hip", "kernels_ell.hip", "kernels_col.hip", "kernels_dense.hip", "kernels_krylov.hip", "kernels_gauge.hip", "kernels_post.hip", "probe.hip", "engine.hip"]
+SOURCES = ["kernels.hip", "kernels_ell.hip", "kernels_col.hip", "kernels_dense.hip", "kernels_krylov.hip", "kernels_gauge.hip", "kernels_post.hip", "noalloc.hip", "probe.hip", "engine.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
