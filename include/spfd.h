@@ -240,6 +240,34 @@ spfd_status spfd_percentile_noalloc(int device, void *hip_stream, const uint8_t 
 spfd_status spfd_stream_triad(int device, void *hip_stream, double *a, const double *b, const double *c,
                               long long n, int reps, double *best_gbs);
 
+/* Several voxel models in one handle (many phantoms of uneven size solved
+ * together, each with its own conductivities, source and CG scalars): the
+ * models are stacked along z in one packed grid, each starting on a node
+ * layer that is a multiple of 64 and at least one empty voxel layer above the
+ * previous one, so that no brick of the structured multigrid levels and no
+ * aggregate spans two models.  One hierarchy serves all of them: every level
+ * kernel runs once over all models (the cycle is block-diagonal), and the
+ * finest-level CG kernels run one launch row per model over that model's
+ * bricks, with the model's own alpha, beta, residual norms and stop test
+ * (so each model's iterates are those of its own preconditioned CG).
+ * n (1..16) models; dims [n][3] (host): nx, ny, nz voxels of model m; labels
+ * [n] (host array of device pointers to uint8 [nz][ny][nx] arrays, copied);
+ * h as for spfd_set_geometry.  Then spfd_set_sigma_tables, spfd_build (split
+ * aggregation from level 3 or finer), spfd_set_source(h, m, a_m) with a_m in
+ * model m's own layout [3][(nx+1)(ny+1)(nz+1)], and spfd_solve, whose psi is
+ * the models' node arrays one after the other and info one entry per model.
+ * The number of right sides is the number of models.  spfd_efield,
+ * spfd_adjoint, spfd_percentile, spfd_edge_potentials, spfd_solve_many, the
+ * per-label and per-voxel conductivity calls, FGMRES and warm starts give
+ * SPFD_BAD_STATE / SPFD_INVALID_ARG on such a handle. */
+spfd_status spfd_set_geometry_many(spfd_handle h, int n, const int *dims, double hx, double hy, double hz,
+                                   const uint8_t *const *labels);
+/* Conductivity tables of the packed models: tables [n] (host array of host
+ * arrays), n_labels [n] (1..256 each; finite, >= 0; 0 = air).  A voxel whose
+ * label its model's table does not cover makes spfd_build fail with
+ * SPFD_INVALID_ARG. */
+spfd_status spfd_set_sigma_tables(spfd_handle h, const double *const *tables, const int *n_labels);
+
 /* Solve Eq. (3) on several voxel models at once (each handle built, with its
  * sources set, on the same device).  The CG iterations of all handles advance
  * in lockstep, each handle's kernels on its own stream, so that problems of

@@ -87,7 +87,8 @@ _lib = None
 EXPORTS = ["spfd_create", "spfd_destroy", "spfd_last_error", "spfd_set_geometry", "spfd_set_sigma_table",
            "spfd_set_sigma_voxel", "spfd_build", "spfd_get_info", "spfd_level_info", "spfd_set_num_rhs", "spfd_set_source",
            "spfd_solve", "spfd_solve_many", "spfd_efield", "spfd_edge_potentials", "spfd_percentile",
-           "spfd_percentile_noalloc", "spfd_adjoint", "spfd_timing", "spfd_timing_get", "spfd_stream_triad"]
+           "spfd_percentile_noalloc", "spfd_adjoint", "spfd_timing", "spfd_timing_get", "spfd_stream_triad",
+           "spfd_set_geometry_many", "spfd_set_sigma_tables"]
 TIMING_COLD = 0x80000000
 # kernel classes of spfd_timing / spfd_timing_get (order of the enum in spfd.h)
 KERNEL_CLASSES = ["spmv", "update", "dots", "pupdate", "smooth0", "smooth0_first", "restrict0", "prolong0", "coarse",
@@ -113,6 +114,8 @@ def load_library(path: str = LIB_PATH):
     lib.spfd_set_geometry.argtypes = [H, I, I, I, D, D, D, P]
     lib.spfd_set_sigma_table.argtypes = [H, P, I]
     lib.spfd_set_sigma_voxel.argtypes = [H, P]
+    lib.spfd_set_geometry_many.argtypes = [H, I, ctypes.POINTER(I), D, D, D, ctypes.POINTER(P)]
+    lib.spfd_set_sigma_tables.argtypes = [H, ctypes.POINTER(ctypes.POINTER(D)), ctypes.POINTER(I)]
     lib.spfd_build.argtypes = [H, ctypes.POINTER(AmgOptions)]
     lib.spfd_get_info.argtypes = [H, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I), ctypes.POINTER(I),
                                   ctypes.POINTER(ctypes.c_size_t)]
@@ -188,6 +191,29 @@ def spfd_set_geometry(h, nx, ny, nz, hx, hy, hz, labels):
     import torch
     _require_cuda(labels, torch.uint8, (nz, ny, nx), "labels")
     return _check(h, load_library().spfd_set_geometry(h, nx, ny, nz, hx, hy, hz, _ptr(labels)))
+
+
+def spfd_set_geometry_many(h, labels_list, hx, hy, hz):
+    """Several voxel models (uint8 CUDA tensors (nz, ny, nx) each) packed into one handle."""
+    import torch
+    n = len(labels_list)
+    dims = (ctypes.c_int * (3 * n))()
+    ptrs = (ctypes.c_void_p * n)()
+    for m, lab in enumerate(labels_list):
+        _require_cuda(lab, torch.uint8, None, f"labels[{m}]")
+        nz, ny, nx = lab.shape
+        dims[3 * m], dims[3 * m + 1], dims[3 * m + 2] = nx, ny, nz
+        ptrs[m] = lab.data_ptr()
+    return _check(h, load_library().spfd_set_geometry_many(h, n, dims, hx, hy, hz, ptrs))
+
+
+def spfd_set_sigma_tables(h, tables):
+    """One conductivity table (sequence per label) per packed model."""
+    n = len(tables)
+    arrs = [(ctypes.c_double * len(t))(*[float(v) for v in t]) for t in tables]
+    ptrs = (ctypes.POINTER(ctypes.c_double) * n)(*[ctypes.cast(a, ctypes.POINTER(ctypes.c_double)) for a in arrs])
+    counts = (ctypes.c_int * n)(*[len(t) for t in tables])
+    return _check(h, load_library().spfd_set_sigma_tables(h, ptrs, counts))
 
 
 def spfd_set_sigma_table(h, sigma):
@@ -494,6 +520,83 @@ class Solver:
         if emag.numel() != self.nx * self.ny * self.nz:
             raise ValueError(f"emag must hold {self.nx * self.ny * self.nz} voxel values")
         return spfd_percentile(self.handle, emag.contiguous(), q, self.n_table if self.n_table else 256)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            spfd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MultiSolver:
+    """Eq. (3) on several voxel models of uneven size in one handle (packed along z, one hierarchy,
+    every level kernel launched once for all models, one CG per model).
+
+    labels_list: uint8 CUDA tensors (nz, ny, nx), one per model; tables: one conductivity sequence
+    per model; h: voxel edge lengths shared by all models (m).
+    """
+
+    def __init__(self, labels_list, tables, h, precision="fp64", device=None, stream=None, torch_memory=True,
+                 **amg):
+        import torch
+        self.device = labels_list[0].device if device is None else torch.device(device)
+        self.shapes = [tuple(l.shape) for l in labels_list]
+        self.node_shapes = [(nz + 1, ny + 1, nx + 1) for nz, ny, nx in self.shapes]
+        self.h = tuple(float(v) for v in h)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._allocator = torch_allocator(self.device, self.stream) if torch_memory else None
+        self.handle = spfd_create(self.device.index or 0, self.stream.cuda_stream, self._allocator)
+        try:
+            spfd_set_geometry_many(self.handle, labels_list, *self.h)
+            spfd_set_sigma_tables(self.handle, [list(t) for t in tables])
+            opts = AmgOptions(MIXED if precision == "mixed" else FP64, CYCLE_V, amg.get("smooth_degree", 2),
+                              amg.get("coarsest_max", 1024), amg.get("cheby_ratio", 8.0), amg.get("coarse_scale", 1.9),
+                              amg.get("split_level", 2), 0, amg.get("level1_degree", 4), SMOOTH_CHEBYSHEV,
+                              amg.get("short_segment_bricks", 0), 1 if amg.get("level1_fp32") else 0)
+            spfd_build(self.handle, opts)
+        except Exception:
+            spfd_destroy(self.handle)
+            self.handle = None
+            raise
+
+    @property
+    def n_models(self):
+        return len(self.shapes)
+
+    def info(self):
+        return spfd_get_info(self.handle)
+
+    def set_sources(self, sources):
+        """sources: one float64 CUDA tensor (3, Nz, Ny, Nx) per model."""
+        import torch
+        if len(sources) != self.n_models:
+            raise ValueError("one source per model")
+        for m, a in enumerate(sources):
+            if tuple(a.shape) != (3,) + self.node_shapes[m]:
+                raise ValueError(f"source {m} must have shape {(3,) + self.node_shapes[m]}")
+            spfd_set_source(self.handle, m, a.to(torch.float64).contiguous())
+
+    def solve(self, sources=None, tol=1e-8, max_iter=500, check=True, flexible=False, eager=False):
+        """(list of psi (Nz, Ny, Nx) per model, list of info dicts)."""
+        import torch
+        if sources is not None:
+            self.set_sources(sources)
+        sizes = [nz * ny * nx for nz, ny, nx in self.node_shapes]
+        flat = torch.empty(sum(sizes), dtype=torch.float64, device=self.device)
+        opts = SolveOptions(tol, max_iter, 0, 1 if eager else 0, CG, 30, 1 if flexible else 0)
+        st, info = spfd_solve(self.handle, opts, flat, self.n_models)
+        if check and st != 0:
+            raise SPFDError(st, spfd_last_error(self.handle))
+        out, off = [], 0
+        for n, shp in zip(sizes, self.node_shapes):
+            out.append(flat[off:off + n].view(shp))
+            off += n
+        return out, info
 
     def close(self):
         if getattr(self, "handle", None) is not None:

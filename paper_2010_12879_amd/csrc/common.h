@@ -38,12 +38,24 @@ struct Scal {
     int pad;         // 1 + buffer parity of a pending deferred x update, 0 if none
 };
 
+constexpr int MAX_MODELS = 16;     // voxel models packed into one handle
+
 struct Topo {
     int nb;                                    // active bricks
     const int *nbr;                            // [nb*6]
     const unsigned long long *cmask = nullptr; // [nb]: bit tx + 8 ty set when the node column (tx,ty,*)
                                                // holds an unknown (nullptr: all columns)
+    // np > 0: the bricks of np voxel models packed into one level; launch row blockIdx.y = m works on
+    // model m's bricks [prange[m].x, prange[m].x + prange[m].y) (its own scalars and partial sums).
+    // The ranges live in device memory (a uniform load), not in the kernel arguments: an argument
+    // array indexed by blockIdx.y would be copied to scratch memory in every kernel.
+    int np = 0;
+    int pmax = 0;                    // largest range
+    const int2 *prange = nullptr;    // [np] (first brick, bricks)
 };
+
+// bricks per launch row: all bricks, or the largest model's
+__host__ __device__ __forceinline__ int topo_count(const Topo &t) { return t.np ? t.pmax : t.nb; }
 
 // XCD-aware workgroup -> brick map: the hardware hands consecutive workgroup
 // ids to the 8 XCDs in turn; giving each XCD a contiguous run of bricks keeps
@@ -56,6 +68,23 @@ __device__ __forceinline__ int xcd_brick(int wg, int nb)
 }
 
 __host__ __forceinline__ int xcd_grid(int nb) { return ((nb + 7) >> 3) << 3; }
+
+// The brick of a one-brick workgroup (-1 for padding) and its index within its
+// launch row (local; the index of its partial sum): with packed models, row
+// blockIdx.y = m covers model m's bricks.
+__device__ __forceinline__ int topo_brick(const Topo &t, int &local)
+{
+    if (t.np == 0) {
+        local = xcd_brick(blockIdx.x, t.nb);
+        return local;
+    }
+    // the map is taken over the launch row's full length (the largest model), so that every brick of
+    // a smaller model has exactly one workgroup; the rest of the row has none
+    const int2 r = t.prange[blockIdx.y];
+    local = xcd_brick(blockIdx.x, t.pmax);
+    if (local >= r.y) local = -1;
+    return local < 0 ? -1 : r.x + local;
+}
 
 __device__ __forceinline__ void brick_xyz(int t, int &tx, int &ty, int &tz)
 {

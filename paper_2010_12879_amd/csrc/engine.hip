@@ -79,6 +79,14 @@ struct Ctx {
     uint8_t *d_labels = nullptr;
     double *d_sigvox = nullptr;
     bool voxel_mode = false;
+    // several voxel models packed along z into one handle (spfd_set_geometry_many); np = 0: one model
+    int np = 0;
+    ModelBoxes mbox{};
+    Grid mgrid[MAX_MODELS];
+    long long mnodes_off[MAX_MODELS + 1] = {};   // offsets of the models' dense node arrays in psi
+    int mfirst[MAX_MODELS] = {}, mcount[MAX_MODELS] = {};   // the models' finest-level bricks (after build)
+    int2 *d_mrange = nullptr;                               // the same on the device (first, count)
+    double *d_mtables = nullptr;                            // [MAX_MODELS][MAX_LABELS] conductivity tables
     int nlab = 0;
     double table[MAX_LABELS];
     double *d_table64 = nullptr;
@@ -365,6 +373,9 @@ struct TScope {
     }
     int next_pending = 0;
 };
+
+// packed voxel models start at node layers that are multiples of this, one empty layer apart at least
+constexpr int MODEL_ALIGN = 64;
 
 // ------------------------------------------------------------ brick topology on the host
 // Pinned staging of at least `bytes` (copies from pageable memory go through a
@@ -763,10 +774,40 @@ bool vcycle(Ctx *c, const TR *r, T *z, const Scal *sc, int nb, const CycleDots *
     return dots != nullptr;
 }
 
-void finish(Ctx *c, int n, int mode, Scal *sc, int max_iter, int nb = 1, Scal *mirror = nullptr)
+// Partial sums of the CG kernels per launch row: packed models write one row per model, of the model's
+// own count (bricks, or groups of the CG step), and the finisher sums just those.
+enum { ROWS_BRICKS = 1, ROWS_CG_GROUPS = 2 };
+
+void finish(Ctx *c, int n, int mode, Scal *sc, int max_iter, int nb = 1, Scal *mirror = nullptr, int rows = 0)
 {
     TScope ts(c, SPFD_K_FINISH, nb * (double)n * 8.0 * (mode == FIN_BETA ? 2 : 1));
-    HIPCHK(launch_finish(c->d_part, n, mode, sc, max_iter, c->stream, nullptr, nullptr, 0, nb, c->pstride, mirror));
+    FinRows fr{};
+    if (c->np && rows) {
+        fr.used = 1;
+        for (int m = 0; m < c->np; ++m) fr.n[m] = rows == ROWS_BRICKS ? c->mcount[m] : cg_step_parts(c->mcount[m]);
+    }
+    HIPCHK(launch_finish(c->d_part, n, mode, sc, max_iter, c->stream, nullptr, nullptr, 0, nb, c->pstride, mirror,
+                         fr.used ? &fr : nullptr));
+}
+
+// The finest level as the CG kernels see it: all bricks, or one launch row per packed model (its bricks,
+// its scalars, its partial sums; the vectors are shared, so no per-row offset)
+Topo cg_topo(Ctx *c)
+{
+    Topo t = c->lv[0].topo();
+    if (c->np) {
+        t.np = c->np;
+        t.prange = c->d_mrange;
+        for (int m = 0; m < c->np; ++m) t.pmax = std::max(t.pmax, c->mcount[m]);
+    }
+    return t;
+}
+
+Batch cg_batch(Ctx *c, int nb)
+{
+    Batch bt = level_batch(c, 0, nb);
+    if (c->np) bt.vs = bt.vsc = 0;
+    return bt;
 }
 
 void set_defaults(spfd_amg_options &o)
@@ -825,9 +866,10 @@ void alloc_cycle_buffers(Ctx *c, int nb)
     c->fg_m = 0;
     const bool mixed = c->opt.precision == SPFD_MIXED;
     const size_t w = mixed ? sizeof(float) : sizeof(double);
+    const int nvec = c->np ? 1 : nb;   // packed models share one vector of each kind
     for (size_t l = 0; l < c->lv.size(); ++l) {
         Level &L = c->lv[l];
-        const size_t n = (size_t)L.nodes() * nb;
+        const size_t n = (size_t)L.nodes() * nvec;
         L.x = dalloc<uint8_t>(c, c->rhs_allocs, n * w);
         L.x2 = dalloc<uint8_t>(c, c->rhs_allocs, n * w);
         L.d = dalloc<uint8_t>(c, c->rhs_allocs, n * w);
@@ -837,7 +879,7 @@ void alloc_cycle_buffers(Ctx *c, int nb)
         HIPCHK(hipMemsetAsync(L.d, 0, n * w, c->stream));
         HIPCHK(hipMemsetAsync(L.b, 0, n * w, c->stream));
     }
-    const size_t n0 = (size_t)c->lv[0].nodes() * nb;
+    const size_t n0 = (size_t)c->lv[0].nodes() * nvec;
     c->d_x = dalloc<double>(c, c->rhs_allocs, n0);
     c->d_r = dalloc<double>(c, c->rhs_allocs, n0);
     c->d_p = dalloc<double>(c, c->rhs_allocs, n0);
@@ -856,6 +898,7 @@ void alloc_cycle_buffers(Ctx *c, int nb)
     HIPCHK(hipMemsetAsync(c->d_q, 0, n0 * sizeof(double), c->stream));
     c->pstride = 2 * c->lv[0].nb + 64;
     c->d_part = dalloc<double>(c, c->rhs_allocs, (size_t)c->pstride * nb);
+    HIPCHK(hipMemsetAsync(c->d_part, 0, (size_t)c->pstride * nb * sizeof(double), c->stream));
     c->nbat = nb;
 }
 
@@ -1104,11 +1147,40 @@ spfd_status do_build(Ctx *c)
     return SPFD_OK;
 }
 
+// Packed models: each model's finest-level bricks form one contiguous slot range (slots follow the
+// brick grid with z slowest, and the models sit in disjoint brick layers).  Checked, not assumed.
+spfd_status model_ranges(Ctx *c)
+{
+    const Level &L0 = c->lv[0];
+    int m = 0;
+    for (int k = 0; k < c->np; ++k) c->mfirst[k] = c->mcount[k] = 0;
+    for (int b = 0; b < L0.nb; ++b) {
+        const int z0 = L0.coord[b].z * BD;   // first node layer of the brick
+        while (m < c->np && z0 > c->mbox.zoff[m] + c->mbox.nz[m]) ++m;
+        if (m == c->np || z0 + BD - 1 < c->mbox.zoff[m])
+            return fail(c, SPFD_HIP_ERROR, "a brick lies outside every model's layers");
+        if (c->mcount[m] == 0) c->mfirst[m] = b;
+        if (c->mfirst[m] + c->mcount[m] != b) return fail(c, SPFD_HIP_ERROR, "a model's bricks are not contiguous");
+        c->mcount[m] += 1;
+    }
+    for (int k = 0; k < c->np; ++k)
+        if (c->mcount[k] == 0) return fail(c, SPFD_INVALID_ARG, "a voxel model has no conducting voxel");
+    int2 rg[MAX_MODELS];
+    for (int k = 0; k < c->np; ++k) rg[k] = make_int2(c->mfirst[k], c->mcount[k]);
+    c->d_mrange = dalloc<int2>(c, c->hier_allocs, MAX_MODELS);
+    HIPCHK(hipMemcpyAsync(c->d_mrange, rg, c->np * sizeof(int2), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return SPFD_OK;
+}
+
 spfd_status do_set_num_rhs(Ctx *c, int nrhs)
 {
     free_all(c, c->src_allocs);
+    // packed models: one right side per model, in one shared vector
+    if (c->np) nrhs = c->np;
     const size_t n0 = (size_t)c->lv[0].nodes();
-    c->d_bs = dalloc<double>(c, c->src_allocs, n0 * nrhs);
+    c->d_bs = dalloc<double>(c, c->src_allocs, n0 * (c->np ? 1 : nrhs));
+    HIPCHK(hipMemsetAsync(c->d_bs, 0, n0 * (c->np ? 1 : nrhs) * sizeof(double), c->stream));
     c->has_source.assign(nrhs, 0);
     c->d_scal = dalloc<Scal>(c, c->src_allocs, nrhs);
     c->d_again = dalloc<int>(c, c->src_allocs, nrhs + 1);
@@ -1132,16 +1204,20 @@ spfd_status do_set_num_rhs(Ctx *c, int nrhs)
 // The flexible CG of a batch, split into phases so that a driver can advance
 // several handles in lockstep: begin (z0 = B r0, r0.z0), step (one iteration),
 // end (the deferred x update).
+// With packed models the cycle runs once over all of them (it is block-diagonal: no aggregate, brick or
+// component spans two models) with no stop flag, and the dot products follow per model.
 template <typename T>
 void pcg_begin(Ctx *c, Scal *sc, int nb)
 {
     Level &L0 = c->lv[0];
-    const Topo topo = L0.topo();
-    const Batch bt = level_batch(c, 0, nb);
+    const Topo topo = cg_topo(c);
+    const Batch bt = cg_batch(c, nb);
     T *z = (T *)c->d_z;
-    const double n0 = (double)L0.dofs * nb;
+    const double n0 = (double)L0.dofs * (c->np ? 1 : nb);
     CycleDots dots{nullptr, c->d_part};   // r.z only
-    if (vcycle<T, double>(c, c->d_r, z, sc, nb, &dots)) {
+    if (c->np) {
+        vcycle<T, double>(c, c->d_r, z, nullptr, 1, nullptr);
+    } else if (vcycle<T, double>(c, c->d_r, z, sc, nb, &dots)) {
         finish(c, cheb_dot_parts<T>(topo.nb), FIN_BETA0, sc, 0, nb);
         return;
     }
@@ -1149,18 +1225,19 @@ void pcg_begin(Ctx *c, Scal *sc, int nb)
         TScope ts(c, SPFD_K_DOTS, n0 * (sizeof(T) + 8.0));
         HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, 1, bt, c->stream));
     }
-    finish(c, topo.nb, FIN_BETA0, sc, 0, nb);
+    finish(c, topo_count(topo), FIN_BETA0, sc, 0, nb, nullptr, ROWS_BRICKS);
 }
 
 template <typename T>
 void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
 {
     Level &L0 = c->lv[0];
-    const Topo topo = L0.topo();
+    const Topo topo = cg_topo(c);
+    const int nmax = topo_count(topo);
     const OpArgs<double> op = level_op<double>(c, 0);
-    const Batch bt = level_batch(c, 0, nb);
+    const Batch bt = cg_batch(c, nb);
     T *z = (T *)c->d_z;
-    const double n0 = (double)L0.dofs * nb;
+    const double n0 = (double)L0.dofs * (c->np ? 1 : nb);
     const double wz = sizeof(T);
     // an FP32 cycle reads an FP32 copy of the residual, written by the update kernel
     float *r32 = sizeof(T) == sizeof(float) ? c->d_r32 : nullptr;
@@ -1172,17 +1249,25 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
         HIPCHK(launch_cg_step<T>(op, topo, z, pbuf[par ^ 1], pbuf[par], c->d_x, c->d_q, c->d_part, sc, it == 0, par, bt,
                                  c->stream));
     }
-    finish(c, cg_step_parts(topo.nb), FIN_ALPHA, sc, 0, nb);
+    finish(c, cg_step_parts(nmax), FIN_ALPHA, sc, 0, nb, nullptr, ROWS_CG_GROUPS);
     {
         TScope ts(c, SPFD_K_UPDATE, n0 * (24.0 + (r32 ? 4.0 : 0.0)));
         HIPCHK(launch_rupdate(topo, c->d_r, c->d_q, c->d_part, sc, bt, r32, c->stream));
     }
-    finish(c, topo.nb, FIN_RR, sc, max_iter, nb);
+    finish(c, nmax, FIN_RR, sc, max_iter, nb, nullptr, ROWS_BRICKS);
     // z = B r, with the dot products z.r (and z.q for the flexible beta) formed by the cycle's last step
     const bool flex = c->cg_flexible;
     const int bmode = flex ? FIN_BETA : FIN_BETA_STD;
     CycleDots dots{flex ? c->d_q : nullptr, c->d_part};
-    const bool fused = r32 ? vcycle<T, float>(c, r32, z, sc, nb, &dots) : vcycle<T, double>(c, c->d_r, z, sc, nb, &dots);
+    bool fused = false;
+    if (c->np) {
+        if (r32)
+            vcycle<T, float>(c, r32, z, nullptr, 1, nullptr);
+        else
+            vcycle<T, double>(c, c->d_r, z, nullptr, 1, nullptr);
+    } else {
+        fused = r32 ? vcycle<T, float>(c, r32, z, sc, nb, &dots) : vcycle<T, double>(c, c->d_r, z, sc, nb, &dots);
+    }
     if (fused) {
         finish(c, cheb_dot_parts<T>(topo.nb), bmode, sc, 0, nb, c->step_mirror);
         return;
@@ -1191,15 +1276,15 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
         TScope ts(c, SPFD_K_DOTS, n0 * (wz + (flex ? 16.0 : 8.0)));
         HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, flex ? 0 : 1, bt, c->stream));
     }
-    finish(c, topo.nb, bmode, sc, 0, nb, c->step_mirror);
+    finish(c, nmax, bmode, sc, 0, nb, c->step_mirror, ROWS_BRICKS);
 }
 
 void pcg_end(Ctx *c, Scal *sc, int nb)
 {
     // the update x += alpha p deferred by the last step of each right side
     Level &L0 = c->lv[0];
-    TScope ts(c, SPFD_K_PUPDATE, (double)L0.dofs * nb * 24.0);
-    HIPCHK(launch_x_final(L0.topo(), c->d_x, c->d_p, c->d_p2, sc, level_batch(c, 0, nb), c->stream));
+    TScope ts(c, SPFD_K_PUPDATE, (double)L0.dofs * (c->np ? 1 : nb) * 24.0);
+    HIPCHK(launch_x_final(cg_topo(c), c->d_x, c->d_p, c->d_p2, sc, cg_batch(c, nb), c->stream));
 }
 
 void pcg_begin_any(Ctx *c, Scal *sc, int nb)
@@ -1504,12 +1589,13 @@ void krylov_iterations(Ctx *c, const double *b, long long bvs, Scal *sc, int nb,
 void resid_b(Ctx *c, const double *b, long long bvs, Scal *sc, double *r, int mode, int nb)
 {
     Level &L0 = c->lv[0];
+    const Topo topo = cg_topo(c);
     {
-        TScope ts(c, SPFD_K_RESID, nb * (double)L0.dofs * (16.0 + (r ? 8.0 : 0.0) + op_bytes<double>(c, 0)));
-        HIPCHK(launch_resid(level_op<double>(c, 0), L0.topo(), b, c->d_x, r, c->d_part, bvs, level_batch(c, 0, nb),
+        TScope ts(c, SPFD_K_RESID, (c->np ? 1 : nb) * (double)L0.dofs * (16.0 + (r ? 8.0 : 0.0) + op_bytes<double>(c, 0)));
+        HIPCHK(launch_resid(level_op<double>(c, 0), topo, b, c->d_x, r, c->d_part, c->np ? 0 : bvs, cg_batch(c, nb),
                             c->stream));
     }
-    finish(c, cg_step_parts(L0.nb), mode == 0 ? FIN_RESID0 : FIN_RESID1, sc, 0, nb);
+    finish(c, cg_step_parts(topo_count(topo)), mode == 0 ? FIN_RESID0 : FIN_RESID1, sc, 0, nb, nullptr, ROWS_CG_GROUPS);
 }
 
 
@@ -1534,14 +1620,16 @@ spfd_status solve_batch(Ctx *c, const double *b, long long bvs, Scal *sc, Scal *
     const Topo topo = L0.topo();
     const long long n0 = L0.nodes();
     const long long nn = (long long)c->g.Nx * c->g.Ny * c->g.Nz;
+    // packed models share one vector of each kind
+    const int nvec = c->np ? 1 : nb;
     HIPCHK(launch_scal_init(sc, so.rel_tol, so.use_x0, nb, c->stream));
     if (so.use_x0) {
-        for (int i = 0; i < nb; ++i)
+        for (int i = 0; i < nvec; ++i)
             HIPCHK(launch_psi_in(psi + i * nn, c->d_comp, L0.d_coord, L0.nb, c->g, c->d_x + i * n0, c->stream));
         resid_b(c, b, bvs, sc, c->d_r, 0, nb);
     } else {
-        HIPCHK(hipMemsetAsync(c->d_x, 0, nb * n0 * sizeof(double), c->stream));
-        for (int i = 0; i < nb; ++i)
+        HIPCHK(hipMemsetAsync(c->d_x, 0, nvec * n0 * sizeof(double), c->stream));
+        for (int i = 0; i < nvec; ++i)
             HIPCHK(hipMemcpyAsync(c->d_r + i * n0, b + i * bvs, n0 * sizeof(double), hipMemcpyDeviceToDevice,
                                   c->stream));
     }
@@ -1579,14 +1667,25 @@ spfd_status solve_batch(Ctx *c, const double *b, long long bvs, Scal *sc, Scal *
         }
     }
     spfd_status worst = SPFD_OK;
+    if (c->np) {
+        // one gauge pass over the packed vector (no component spans two models), then each model's array
+        TScope ts(c, SPFD_K_GAUGE, (double)L0.dofs * 24.0 + c->mnodes_off[c->np] * 8.0);
+        HIPCHK(launch_comp_mean(topo, c->d_x, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_cpart, c->stream));
+    }
     for (int i = 0; i < nb; ++i) {
         if (bb[i] > 0.0 && status[i] == 0 && relres[i] > so.rel_tol) status[i] = SPFD_NOT_CONVERGED;
         if (status[i] != 0 && worst == SPFD_OK) worst = (spfd_status)status[i];
-        // gauge: zero mean per connected component, 0 outside the conductor
-        TScope ts(c, SPFD_K_GAUGE, (double)L0.dofs * (12.0 * (c->ncomp < 16 ? c->ncomp : 1) + 12.0) + nn * 8.0);
-        HIPCHK(launch_comp_mean(topo, c->d_x + i * n0, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_cpart,
-                                c->stream));
-        HIPCHK(launch_psi_out(c->d_x + i * n0, c->d_comp, c->d_means, L0.d_slot_of, c->g, psi + i * nn, c->stream));
+        if (c->np) {
+            HIPCHK(launch_psi_out(c->d_x, c->d_comp, c->d_means, L0.d_slot_of, c->mgrid[i], psi + c->mnodes_off[i],
+                                  c->stream, &c->g, c->mbox.zoff[i]));
+        } else {
+            // gauge: zero mean per connected component, 0 outside the conductor
+            TScope ts(c, SPFD_K_GAUGE, (double)L0.dofs * (12.0 * (c->ncomp < 16 ? c->ncomp : 1) + 12.0) + nn * 8.0);
+            HIPCHK(launch_comp_mean(topo, c->d_x + i * n0, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_cpart,
+                                    c->stream));
+            HIPCHK(launch_psi_out(c->d_x + i * n0, c->d_comp, c->d_means, L0.d_slot_of, c->g, psi + i * nn,
+                                  c->stream));
+        }
         if (info) {
             info[i].iterations = iters[i];
             info[i].rel_residual = relres[i];
@@ -1795,13 +1894,9 @@ void spfd_destroy(spfd_handle h)
 
 const char *spfd_last_error(spfd_handle h) { return h ? h->err.c_str() : "null handle"; }
 
-spfd_status spfd_set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, double hy, double hz,
-                              const uint8_t *labels)
+// labels NULL: every voxel air (the packed grid of several models, filled by the caller)
+spfd_status set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, double hy, double hz, const uint8_t *labels)
 {
-    if (!h) return SPFD_INVALID_ARG;
-    if (nx <= 0 || ny <= 0 || nz <= 0) return fail(h, SPFD_INVALID_ARG, "grid sizes must be positive");
-    if (!finite_pos(hx) || !finite_pos(hy) || !finite_pos(hz)) return fail(h, SPFD_INVALID_ARG, "voxel sizes must be finite and positive");
-    if (!labels) return fail(h, SPFD_INVALID_ARG, "labels is NULL");
     const long long nvox = (long long)nx * ny * nz;
     const long long nn = (long long)(nx + 1) * (ny + 1) * (nz + 1);
     if (nn > 0x7fffffffLL * 4) return fail(h, SPFD_INVALID_ARG, "grid too large");
@@ -1831,8 +1926,13 @@ spfd_status spfd_set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, 
         h->geo4[0] = 0.25 * (hy * hz / hx);
         h->geo4[1] = 0.25 * (hx * hz / hy);
         h->geo4[2] = 0.25 * (hx * hy / hz);
+        h->np = 0;
+        h->d_mtables = nullptr;
         h->d_labels = dalloc<uint8_t>(h, h->geo_allocs, nvox);
-        HIPCHK(hipMemcpyAsync(h->d_labels, labels, nvox, hipMemcpyDefault, h->stream));
+        if (labels)
+            HIPCHK(hipMemcpyAsync(h->d_labels, labels, nvox, hipMemcpyDefault, h->stream));
+        else
+            HIPCHK(hipMemsetAsync(h->d_labels, 0, nvox, h->stream));
         h->d_table64 = dalloc<double>(h, h->geo_allocs, MAX_LABELS);
         h->d_table32 = dalloc<float>(h, h->geo_allocs, MAX_LABELS);
         h->d_sigvox = nullptr;
@@ -1845,9 +1945,20 @@ spfd_status spfd_set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, 
     API_GUARD(h)
 }
 
+spfd_status spfd_set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, double hy, double hz,
+                              const uint8_t *labels)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (nx <= 0 || ny <= 0 || nz <= 0) return fail(h, SPFD_INVALID_ARG, "grid sizes must be positive");
+    if (!finite_pos(hx) || !finite_pos(hy) || !finite_pos(hz)) return fail(h, SPFD_INVALID_ARG, "voxel sizes must be finite and positive");
+    if (!labels) return fail(h, SPFD_INVALID_ARG, "labels is NULL");
+    return set_geometry(h, nx, ny, nz, hx, hy, hz, labels);
+}
+
 spfd_status spfd_set_sigma_table(spfd_handle h, const double *sigma, int n_labels)
 {
     if (!h) return SPFD_INVALID_ARG;
+    if (h->np) return fail(h, SPFD_BAD_STATE, "not available for packed voxel models (spfd_set_geometry_many)");
     if (h->state < 1) return fail(h, SPFD_BAD_STATE, "set_geometry first");
     if (!sigma || n_labels <= 0 || n_labels > MAX_LABELS) return fail(h, SPFD_INVALID_ARG, "need 1..256 labels");
     for (int i = 0; i < n_labels; ++i)
@@ -1874,6 +1985,7 @@ spfd_status spfd_set_sigma_table(spfd_handle h, const double *sigma, int n_label
 spfd_status spfd_set_sigma_voxel(spfd_handle h, const double *sigma_voxel)
 {
     if (!h) return SPFD_INVALID_ARG;
+    if (h->np) return fail(h, SPFD_BAD_STATE, "not available for packed voxel models (spfd_set_geometry_many)");
     if (h->state < 1) return fail(h, SPFD_BAD_STATE, "set_geometry first");
     if (!sigma_voxel) return fail(h, SPFD_INVALID_ARG, "sigma_voxel is NULL");
     try {
@@ -1891,6 +2003,92 @@ spfd_status spfd_set_sigma_voxel(spfd_handle h, const double *sigma_voxel)
     API_GUARD(h)
 }
 
+spfd_status spfd_set_geometry_many(spfd_handle h, int n, const int *dims, double hx, double hy, double hz,
+                                   const uint8_t *const *labels)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (n < 1 || n > MAX_MODELS) return fail(h, SPFD_INVALID_ARG, "n must be in 1..16");
+    if (!dims || !labels) return fail(h, SPFD_INVALID_ARG, "dims and labels are required");
+    if (!finite_pos(hx) || !finite_pos(hy) || !finite_pos(hz)) return fail(h, SPFD_INVALID_ARG, "voxel sizes must be finite and positive");
+    ModelBoxes mb{};
+    mb.np = n;
+    int NX = 0, NY = 0;
+    long long z = 0;
+    for (int m = 0; m < n; ++m) {
+        const int nx = dims[3 * m], ny = dims[3 * m + 1], nz = dims[3 * m + 2];
+        if (nx <= 0 || ny <= 0 || nz <= 0) return fail(h, SPFD_INVALID_ARG, "grid sizes must be positive");
+        if (!labels[m]) return fail(h, SPFD_INVALID_ARG, "a label pointer is NULL");
+        mb.nx[m] = nx;
+        mb.ny[m] = ny;
+        mb.nz[m] = nz;
+        mb.zoff[m] = (int)z;
+        NX = std::max(NX, nx);
+        NY = std::max(NY, ny);
+        // the next model starts on the next aligned node layer above this model's top node layer
+        z = (z + nz + 1 + MODEL_ALIGN - 1) / MODEL_ALIGN * MODEL_ALIGN;
+        if (z > (1 << 24)) return fail(h, SPFD_INVALID_ARG, "models too large");
+    }
+    const int NZ = mb.zoff[n - 1] + mb.nz[n - 1];
+    const long long nn = (long long)(NX + 1) * (NY + 1) * (NZ + 1);
+    if (nn > 0x7fffffffLL * 4) return fail(h, SPFD_INVALID_ARG, "models too large");
+    const spfd_status st = set_geometry(h, NX, NY, NZ, hx, hy, hz, nullptr);
+    if (st != SPFD_OK) return st;
+    try {
+        for (int m = 0; m < n; ++m)
+            HIPCHK(launch_pack_labels(labels[m], mb.nx[m], mb.ny[m], mb.nz[m], h->d_labels, NX, NY, mb.zoff[m],
+                                      h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->np = n;
+        h->mbox = mb;
+        long long off = 0;
+        for (int m = 0; m < n; ++m) {
+            Grid &g = h->mgrid[m];
+            g.nx = mb.nx[m]; g.ny = mb.ny[m]; g.nz = mb.nz[m];
+            g.Nx = g.nx + 1; g.Ny = g.ny + 1; g.Nz = g.nz + 1;
+            g.Gx = (g.Nx + 7) / 8; g.Gy = (g.Ny + 7) / 8; g.Gz = (g.Nz + 7) / 8;
+            h->mnodes_off[m] = off;
+            off += (long long)g.Nx * g.Ny * g.Nz;
+        }
+        h->mnodes_off[n] = off;
+        return SPFD_OK;
+    }
+    API_GUARD(h)
+}
+
+spfd_status spfd_set_sigma_tables(spfd_handle h, const double *const *tables, const int *n_labels)
+{
+    if (!h) return SPFD_INVALID_ARG;
+    if (h->state < 1 || !h->np) return fail(h, SPFD_BAD_STATE, "set_geometry_many first");
+    if (!tables || !n_labels) return fail(h, SPFD_INVALID_ARG, "tables and n_labels are required");
+    // labels a model's table does not cover get NaN: the build rejects them (non-finite conductivity)
+    std::vector<double> tab((size_t)h->np * MAX_LABELS, NAN);
+    for (int m = 0; m < h->np; ++m) {
+        if (!tables[m] || n_labels[m] < 1 || n_labels[m] > MAX_LABELS)
+            return fail(h, SPFD_INVALID_ARG, "each model needs a table of 1..256 conductivities");
+        for (int l = 0; l < n_labels[m]; ++l) {
+            const double v = tables[m][l];
+            if (!isfinite(v) || v < 0.0) return fail(h, SPFD_INVALID_ARG, "conductivities must be finite and >= 0");
+            tab[(size_t)m * MAX_LABELS + l] = v;
+        }
+    }
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        enter(h);
+        const long long nvox = (long long)h->g.nx * h->g.ny * h->g.nz;
+        if (!h->d_mtables) h->d_mtables = dalloc<double>(h, h->geo_allocs, (size_t)MAX_MODELS * MAX_LABELS);
+        double *dt = h->d_mtables;
+        HIPCHK(hipMemcpyAsync(dt, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        if (!h->d_sigvox) h->d_sigvox = dalloc<double>(h, h->geo_allocs, nvox);
+        HIPCHK(launch_pack_sigma(h->d_labels, h->g, h->mbox, dt, h->d_sigvox, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->voxel_mode = true;
+        h->nlab = MAX_LABELS;
+        h->state = 2;
+        return SPFD_OK;
+    }
+    API_GUARD(h)
+}
+
 spfd_status spfd_build(spfd_handle h, const spfd_amg_options *opt)
 {
     if (!h) return SPFD_INVALID_ARG;
@@ -1901,11 +2099,16 @@ spfd_status spfd_build(spfd_handle h, const spfd_amg_options *opt)
     if (o.smoother != SPFD_SMOOTH_CHEBYSHEV && o.smoother != SPFD_SMOOTH_L1_JACOBI)
         return fail(h, SPFD_INVALID_ARG, "unknown smoother");
     set_defaults(o);
+    // packed models sit MODEL_ALIGN node layers apart: bricks of the structured levels up to level 3
+    // (64 fine nodes) never span two models, and split aggregates never do
+    if (h->np && (o.no_split || o.split_level > 3))
+        return fail(h, SPFD_INVALID_ARG, "packed voxel models need split aggregation from level 3 or finer");
     h->opt = o;
     try {
         HIPCHK(hipSetDevice(h->device));
         enter(h);
         spfd_status s = do_build(h);
+        if (s == SPFD_OK && h->np) s = model_ranges(h);
         if (s != SPFD_OK) {
             h->state = 2;
             return s;
@@ -1965,12 +2168,27 @@ spfd_status spfd_set_source(spfd_handle h, int rhs, const double *a)
         enter(h);
         Level &L0 = h->lv[0];
         HIPCHK(hipMemsetAsync(h->d_scal + rhs, 0, sizeof(Scal), h->stream));
-        {
-            TScope ts(h, SPFD_K_RHS, (double)L0.dofs * (24.0 + 8.0 + op_bytes<double>(h, 0)));
-            HIPCHK(launch_rhs(level_op<double>(h, 0), L0.topo(), L0.d_coord, h->g, a, h->d_bs + rhs * L0.nodes(),
-                              h->d_part, h->d_scal + rhs, h->stream));
+        if (h->np) {
+            // model rhs: its bricks of the shared vector, its dense a, ||b||^2 from its own row of partials
+            Topo t = L0.topo();
+            t.np = 1;
+            t.prange = h->d_mrange + rhs;
+            t.pmax = h->mcount[rhs];
+            double *part = h->d_part + (long long)rhs * h->pstride;
+            {
+                TScope ts(h, SPFD_K_RHS, (double)t.pmax * BS * (24.0 + 8.0 + op_bytes<double>(h, 0)));
+                HIPCHK(launch_rhs(level_op<double>(h, 0), t, L0.d_coord, h->mgrid[rhs], a, h->d_bs, part,
+                                  h->d_scal + rhs, h->stream, h->mbox.zoff[rhs]));
+            }
+            HIPCHK(launch_finish(part, t.pmax, FIN_BB, h->d_scal + rhs, 0, h->stream));
+        } else {
+            {
+                TScope ts(h, SPFD_K_RHS, (double)L0.dofs * (24.0 + 8.0 + op_bytes<double>(h, 0)));
+                HIPCHK(launch_rhs(level_op<double>(h, 0), L0.topo(), L0.d_coord, h->g, a, h->d_bs + rhs * L0.nodes(),
+                                  h->d_part, h->d_scal + rhs, h->stream));
+            }
+            finish(h, L0.nb, FIN_BB, h->d_scal + rhs, 0);
         }
-        finish(h, L0.nb, FIN_BB, h->d_scal + rhs, 0);
         HIPCHK(hipMemcpyAsync(h->h_scal + rhs, h->d_scal + rhs, sizeof(Scal), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         if (!isfinite(h->h_scal[rhs].bb)) return fail(h, SPFD_INVALID_ARG, "source potentials must be finite");
@@ -1994,7 +2212,8 @@ spfd_status spfd_solve(spfd_handle h, const spfd_solve_options *opt, double *psi
     if (opt) so = *opt;
     if (!(so.rel_tol > 0.0) || !isfinite(so.rel_tol)) return fail(h, SPFD_INVALID_ARG, "rel_tol must be positive");
     if (so.max_iter <= 0) return fail(h, SPFD_INVALID_ARG, "max_iter must be positive");
-    if (const char *e = check_method(so, h->nrhs)) return fail(h, SPFD_INVALID_ARG, e);
+    if (const char *e = check_method(so, h->np ? 2 : h->nrhs)) return fail(h, SPFD_INVALID_ARG, e);
+    if (h->np && so.use_x0) return fail(h, SPFD_INVALID_ARG, "packed voxel models start from zero (use_x0 = 0)");
     try {
         HIPCHK(hipSetDevice(h->device));
         enter(h);
@@ -2007,6 +2226,7 @@ spfd_status spfd_efield(spfd_handle h, double omega, int nsrc, const double *a, 
                         double *emag)
 {
     if (!h) return SPFD_INVALID_ARG;
+    if (h->np) return fail(h, SPFD_BAD_STATE, "not available for packed voxel models (spfd_set_geometry_many)");
     if (h->state < 2) return fail(h, SPFD_BAD_STATE, "set geometry and conductivities first");
     if (!a || !psi || !emag) return fail(h, SPFD_INVALID_ARG, "a, psi and emag are required");
     if (nsrc < 1) return fail(h, SPFD_INVALID_ARG, "nsrc must be >= 1");
@@ -2045,6 +2265,7 @@ spfd_status spfd_adjoint(spfd_handle h, double omega, const double *a, const dou
                          spfd_rhs_info *info)
 {
     if (!h) return SPFD_INVALID_ARG;
+    if (h->np) return fail(h, SPFD_BAD_STATE, "not available for packed voxel models (spfd_set_geometry_many)");
     if (h->state < 3) return fail(h, SPFD_BAD_STATE, "build first");
     if (!a || !psi || !grad_emag || !grad_sigma_voxel)
         return fail(h, SPFD_INVALID_ARG, "a, psi, grad_emag and grad_sigma_voxel are required");
@@ -2107,6 +2328,7 @@ spfd_status spfd_solve_many(spfd_handle *hs, int n, const spfd_solve_options *op
     if (!hs || n <= 0 || !psi) return SPFD_INVALID_ARG;
     for (int k = 0; k < n; ++k) {
         if (!hs[k]) return SPFD_INVALID_ARG;
+        if (hs[k]->np) return fail(hs[k], SPFD_BAD_STATE, "packed voxel models solve with spfd_solve");
         if (hs[k]->state < 4) return fail(hs[k], SPFD_BAD_STATE, "set the sources first");
         for (int i = 0; i < hs[k]->nrhs; ++i)
             if (!hs[k]->has_source[i]) return fail(hs[k], SPFD_BAD_STATE, "a right-hand side has no source");
@@ -2137,6 +2359,7 @@ spfd_status spfd_solve_many(spfd_handle *hs, int n, const spfd_solve_options *op
 spfd_status spfd_edge_potentials(spfd_handle h, const double *flux, double *a)
 {
     if (!h) return SPFD_INVALID_ARG;
+    if (h->np) return fail(h, SPFD_BAD_STATE, "not available for packed voxel models (spfd_set_geometry_many)");
     if (h->state < 1) return fail(h, SPFD_BAD_STATE, "set the geometry first");
     if (!flux || !a) return fail(h, SPFD_INVALID_ARG, "flux and a are required");
     if (flux == a) return fail(h, SPFD_INVALID_ARG, "flux and a must not alias");
@@ -2157,6 +2380,7 @@ spfd_status spfd_edge_potentials(spfd_handle h, const double *flux, double *a)
 spfd_status spfd_percentile(spfd_handle h, const double *emag, double q, double *out_body, double *out_labels)
 {
     if (!h) return SPFD_INVALID_ARG;
+    if (h->np) return fail(h, SPFD_BAD_STATE, "not available for packed voxel models (spfd_set_geometry_many)");
     if (h->state < 2) return fail(h, SPFD_BAD_STATE, "set geometry and conductivities first");
     if (!emag || !out_body) return fail(h, SPFD_INVALID_ARG, "emag and out_body are required");
     if (!(q > 0.0 && q <= 1.0)) return fail(h, SPFD_INVALID_ARG, "q must be in (0, 1]");

@@ -117,15 +117,23 @@ enum {
 // mirror != nullptr: the scalars of right side i are also written to
 // mirror[i] (host-visible memory) when the kernel ends, also when the solve
 // had already stopped: the host reads them after the stream has passed here.
+// rows (nullable, used != 0): row r sums only its first n[r] partials (packed models: each model's own
+// count of bricks or groups); the z.q partials of FIN_BETA start at part + n in every row
+struct FinRows {
+    int used;
+    int n[MAX_MODELS];
+};
 hipError_t launch_finish(const double *part, int n, int mode, Scal *sc, int max_iter, hipStream_t s,
                          double *means = nullptr, const int *counts = nullptr, int comp = 0, int nbatch = 1,
-                         int ps = 0, Scal *mirror = nullptr);
+                         int ps = 0, Scal *mirror = nullptr, const FinRows *rows = nullptr);
 
 template <typename T>
 hipError_t launch_fill(T *x, long long n, T v, hipStream_t s);
 
+// b = -G^T M a and the ||b||^2 partials (one per brick of the launch row).  Packed models: topo holds one
+// model (np = 1), g is that model's grid and zoff its first node layer in the packed grid.
 hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, const Grid &g, const double *a,
-                      double *b, double *part, Scal *sc, hipStream_t s);
+                      double *b, double *part, Scal *sc, hipStream_t s, int zoff = 0);
 hipError_t launch_scal_init(Scal *sc, double tol, int use_x0, int nbatch, hipStream_t s);
 // fused CG step: p = z + beta p (p = z when first), x += alpha p_old (deferred), q = A p, p.q partials;
 // pin and pout are different buffers (neighbours read p_old)
@@ -163,7 +171,7 @@ hipError_t launch_fg_xupdate(double *x, const TZ *Z, long long ldz, long long n,
 template <typename TZ>
 hipError_t launch_spmv(const OpArgs<double> &op, Topo topo, const TZ *z, double *w, const Scal *sc, const Batch &bt,
                        hipStream_t s);
-// number of partial sums launch_cg_step writes per right side
+// number of partial sums launch_cg_step writes per right side (nb: bricks per launch row, topo_count)
 int cg_step_parts(int nb);
 template <typename TZ>
 hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, const double *pin, double *pout,
@@ -216,13 +224,26 @@ template <typename T, typename TB>
 hipError_t launch_coarse_apply(const TB *bc, T *xc, const double *Ainv, const int *node_of_dof, int n,
                                const Scal *sc, const Batch &bt, hipStream_t s);
 
+// ---------------------------------------------------------------- several voxel models in one handle
+// model boxes in the packed grid: model m has nx x ny x nz voxels from voxel layer zoff on
+struct ModelBoxes {
+    int np;
+    int nx[MAX_MODELS], ny[MAX_MODELS], nz[MAX_MODELS], zoff[MAX_MODELS];
+};
+hipError_t launch_pack_labels(const uint8_t *src, int nx, int ny, int nz, uint8_t *dst, int NX, int NY, int zoff,
+                              hipStream_t s);
+hipError_t launch_pack_sigma(const uint8_t *labels, const Grid &g, const ModelBoxes &mb, const double *tables,
+                             double *sig, hipStream_t s);
+
 // ---------------------------------------------------------------- gauge, output, post-processing
 // means[c] = mean of x over component c, in a fixed summation order; part holds comp_mean_parts(nb) doubles
 size_t comp_mean_parts(int nb);
 hipError_t launch_comp_mean(Topo topo, const double *x, const int *comp, int ncomp, const int *counts,
                             double *means, double *part, hipStream_t s);
+// gbricks (nullable): the grid of the brick layout when it is not g (packed models; the output's model
+// starts at node layer zoff of it)
 hipError_t launch_psi_out(const double *x, const int *comp, const double *means, const int *slot_of, const Grid &g,
-                          double *psi, hipStream_t s);
+                          double *psi, hipStream_t s, const Grid *gbricks = nullptr, int zoff = 0);
 hipError_t launch_psi_in(const double *psi, const int *comp, const int4 *coord, int nb, const Grid &g, double *x,
                          hipStream_t s);
 hipError_t launch_efield(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,

@@ -79,7 +79,6 @@ __global__ void k_brick_flags(const uint8_t *__restrict__ labels, const double *
     }
 }
 
-// non-negative floats order like their bit patterns
 // out[0]: bits of the largest weight (starts at 0), out[1]: bits of the smallest positive one (starts at
 // the bits of +inf); non-negative floats order like their bit patterns
 __global__ void k_wmax(const float *w, long long n, unsigned *out)
@@ -900,9 +899,11 @@ __device__ __forceinline__ void store_mirror(Scal *mirror, const Scal *sc)
     if (mirror) mirror[blockIdx.x] = *sc;
 }
 
+// rows.used: row r sums its first rows.n[r] partials (packed models: each model's own count), else n;
+// the second set of partials (z.q) starts at part + n in every row
 __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part, int n, int mode, Scal *sc,
                                                  int max_iter, double *means, const int *counts, int comp, int ps,
-                                                 Scal *mirror)
+                                                 Scal *mirror, FinRows rows)
 {
     __shared__ double red[16];
     part += (long long)blockIdx.x * ps;
@@ -912,20 +913,21 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
             if (threadIdx.x == 0) store_mirror(mirror, sc);
             return;
         }
+    const int nr = rows.used ? rows.n[blockIdx.x] : n;
     // four independent loads in flight per thread and round (fixed order: deterministic)
     const int nt = blockDim.x;
     double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < n; i += 4 * nt) {
+    for (int i = threadIdx.x; i < nr; i += 4 * nt) {
         const double v0 = part[i];
-        const double v1 = i + nt < n ? part[i + nt] : 0.0;
-        const double v2 = i + 2 * nt < n ? part[i + 2 * nt] : 0.0;
-        const double v3 = i + 3 * nt < n ? part[i + 3 * nt] : 0.0;
+        const double v1 = i + nt < nr ? part[i + nt] : 0.0;
+        const double v2 = i + 2 * nt < nr ? part[i + 2 * nt] : 0.0;
+        const double v3 = i + 3 * nt < nr ? part[i + 3 * nt] : 0.0;
         a += (v0 + v1) + (v2 + v3);
         if (mode == FIN_BETA) {
             const double w0 = part[n + i];
-            const double w1 = i + nt < n ? part[n + i + nt] : 0.0;
-            const double w2 = i + 2 * nt < n ? part[n + i + 2 * nt] : 0.0;
-            const double w3 = i + 3 * nt < n ? part[n + i + 3 * nt] : 0.0;
+            const double w1 = i + nt < nr ? part[n + i + nt] : 0.0;
+            const double w2 = i + 2 * nt < nr ? part[n + i + 2 * nt] : 0.0;
+            const double w3 = i + 3 * nt < nr ? part[n + i + 3 * nt] : 0.0;
             b += (w0 + w1) + (w2 + w3);
         }
     }
@@ -992,24 +994,29 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
 }
 
 hipError_t launch_finish(const double *part, int n, int mode, Scal *sc, int max_iter, hipStream_t s, double *means,
-                         const int *counts, int comp, int nbatch, int ps, Scal *mirror)
+                         const int *counts, int comp, int nbatch, int ps, Scal *mirror, const FinRows *rows)
 {
     if (mirror && !sc) return hipErrorInvalidValue;
+    if (rows && rows->used && nbatch > MAX_MODELS) return hipErrorInvalidValue;
+    const FinRows fr = rows ? *rows : FinRows{};
     SPFD_LAUNCH(k_finish, dim3(nbatch), dim3(1024), 0, s, part, n, mode, sc, max_iter, means, counts, comp, ps,
-                mirror);
+                mirror, fr);
     return hipGetLastError();
 }
 
 // b = -G^T M a on the unknowns of the finest level (Eq. (3), right side):
 // b_n = sum over edges leaving n of M_e a_e - sum over edges entering n of M_e a_e,
 // and ||b||^2.  a is read only on conducting edges (M_e > 0), which all lie in the grid.
+// With packed models (topo.np > 0, one launch row): g is the model's grid, zoff its first node layer in
+// the packed grid, and the bricks are the model's.
 template <bool LABEL>
 __global__ __launch_bounds__(NT) void k_rhs(OpArgs<double> op, Topo topo, const int4 *__restrict__ coord, Grid g,
-                                            const double *__restrict__ a, double *b, double *part)
+                                            int zoff, const double *__restrict__ a, double *b, double *part)
 {
     __shared__ double tile[TILE_VOX + 7];
     __shared__ double red[8];
-    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    int loc;
+    const int bk = topo_brick(topo, loc);
     if (bk < 0) return;
     int nb[6];
     brick_nbrs(topo.nbr, bk, nb);
@@ -1023,7 +1030,7 @@ __global__ __launch_bounds__(NT) void k_rhs(OpArgs<double> op, Topo topo, const 
     double W[6];
     op_weights(op, tile, base, t, tx, ty, tz, I, W);
     const int4 c = coord[bk];
-    const long long i = c.x * 8 + tx, j = c.y * 8 + ty, k = c.z * 8 + tz;
+    const long long i = c.x * 8 + tx, j = c.y * 8 + ty, k = c.z * 8 + tz - zoff;
     const long long n = i + (long long)g.Nx * (j + (long long)g.Ny * k);
     const long long nn = (long long)g.Nx * g.Ny * g.Nz;
     double s = 0.0;
@@ -1035,17 +1042,19 @@ __global__ __launch_bounds__(NT) void k_rhs(OpArgs<double> op, Topo topo, const 
     if (W[NMZ] != 0.0) s -= W[NMZ] * a[2 * nn + n - (long long)g.Nx * g.Ny];
     b[base + t] = s;
     const double tot = block_sum(s * s, red);
-    if (t == 0) part[bk] = tot;
+    if (t == 0) part[loc] = tot;
 }
 
 hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, const Grid &g, const double *a,
-                      double *b, double *part, Scal *sc, hipStream_t s)
+                      double *b, double *part, Scal *sc, hipStream_t s, int zoff)
 {
     if (topo.nb <= 0) return hipSuccess;
+    if (topo.np > 1) return hipErrorInvalidValue;   // one model per call
+    const dim3 grid(xcd_grid(topo_count(topo)));
     if (op.w)
-        SPFD_LAUNCH(k_rhs<false>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, coord, g, a, b, part);
+        SPFD_LAUNCH(k_rhs<false>, grid, dim3(NT), 0, s, op, topo, coord, g, zoff, a, b, part);
     else
-        SPFD_LAUNCH(k_rhs<true>, dim3(xcd_grid(topo.nb)), dim3(NT), 0, s, op, topo, coord, g, a, b, part);
+        SPFD_LAUNCH(k_rhs<true>, grid, dim3(NT), 0, s, op, topo, coord, g, zoff, a, b, part);
     return hipGetLastError();
 }
 
@@ -1054,7 +1063,8 @@ hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, co
 __global__ __launch_bounds__(NT) void k_x_final(Topo topo, double *__restrict__ x, const double *__restrict__ pa,
                                                 const double *__restrict__ pb, const Scal *sc, long long vs)
 {
-    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    int loc;
+    const int bk = topo_brick(topo, loc);
     if (bk < 0) return;
     sc += blockIdx.y;
     const int pend = sc->pad;
@@ -1068,7 +1078,7 @@ hipError_t launch_x_final(Topo topo, double *x, const double *pa, const double *
                           hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    SPFD_LAUNCH(k_x_final, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, x, pa, pb, sc, bt.vs);
+    SPFD_LAUNCH(k_x_final, dim3(xcd_grid(topo_count(topo)), bt.n), dim3(NT), 0, s, topo, x, pa, pb, sc, bt.vs);
     return hipGetLastError();
 }
 
@@ -1080,22 +1090,23 @@ __global__ __launch_bounds__(NT) void k_rupdate(Topo topo, double *__restrict__ 
     __shared__ double red[8];
     sc += blockIdx.y;
     if (sc->done) return;
-    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    int loc;
+    const int bk = topo_brick(topo, loc);
     if (bk < 0) return;
     const long long n = blockIdx.y * vs + (long long)bk * BS + threadIdx.x;
     const double rn = r[n] - sc->alpha * q[n];
     r[n] = rn;
     if (r32) r32[n] = (float)rn;
     const double tot = block_sum(rn * rn, red);
-    if (threadIdx.x == 0) part[(long long)blockIdx.y * ps + bk] = tot;
+    if (threadIdx.x == 0) part[(long long)blockIdx.y * ps + loc] = tot;
 }
 
 hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, Scal *sc, const Batch &bt, float *r32,
                           hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    SPFD_LAUNCH(k_rupdate, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, r, q, part, sc, bt.vs, bt.ps,
-                       r32);
+    SPFD_LAUNCH(k_rupdate, dim3(xcd_grid(topo_count(topo)), bt.n), dim3(NT), 0, s, topo, r, q, part, sc, bt.vs,
+                bt.ps, r32);
     return hipGetLastError();
 }
 
@@ -1108,7 +1119,8 @@ __global__ __launch_bounds__(NT) void k_dots(Topo topo, const TZ *__restrict__ z
     __shared__ double red[8];
     sc += blockIdx.y;
     if (sc->done) return;
-    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    int loc;
+    const int bk = topo_brick(topo, loc);
     if (bk < 0) return;
     z += blockIdx.y * vs;
     r += blockIdx.y * vs;
@@ -1119,8 +1131,9 @@ __global__ __launch_bounds__(NT) void k_dots(Topo topo, const TZ *__restrict__ z
     const double a = block_sum(zv * r[n], red);
     const double c = first ? 0.0 : block_sum(zv * q[n], red);
     if (threadIdx.x == 0) {
-        part[bk] = a;
-        part[topo.nb + bk] = c;
+        // z.q partials follow the topo_count(topo) partials of r.z
+        part[loc] = a;
+        part[topo_count(topo) + loc] = c;
     }
 }
 
@@ -1129,8 +1142,8 @@ hipError_t launch_dots(Topo topo, const TZ *z, const double *r, const double *q,
                        const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    SPFD_LAUNCH(k_dots<TZ>, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, z, r, q, part, sc, first, bt.vs,
-                       bt.ps);
+    SPFD_LAUNCH(k_dots<TZ>, dim3(xcd_grid(topo_count(topo)), bt.n), dim3(NT), 0, s, topo, z, r, q, part, sc, first,
+                bt.vs, bt.ps);
     return hipGetLastError();
 }
 template hipError_t launch_dots<double>(Topo, const double *, const double *, const double *, double *, Scal *, int,
@@ -1144,7 +1157,8 @@ __global__ __launch_bounds__(NT) void k_pupdate(Topo topo, const TZ *__restrict_
 {
     sc += blockIdx.y;
     if (sc->done) return;
-    const int bk = xcd_brick(blockIdx.x, topo.nb);
+    int loc;
+    const int bk = topo_brick(topo, loc);
     if (bk < 0) return;
     z += blockIdx.y * vs;
     p += blockIdx.y * vs;
@@ -1158,7 +1172,7 @@ hipError_t launch_pupdate(Topo topo, const TZ *z, double *p, const Scal *sc, int
                           hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    SPFD_LAUNCH(k_pupdate<TZ>, dim3(xcd_grid(topo.nb), bt.n), dim3(NT), 0, s, topo, z, p, sc, first, bt.vs);
+    SPFD_LAUNCH(k_pupdate<TZ>, dim3(xcd_grid(topo_count(topo)), bt.n), dim3(NT), 0, s, topo, z, p, sc, first, bt.vs);
     return hipGetLastError();
 }
 template hipError_t launch_pupdate<double>(Topo, const double *, double *, const Scal *, int, const Batch &,
@@ -1326,14 +1340,63 @@ hipError_t launch_comp_mean(Topo topo, const double *x, const int *comp, int nco
     return hipGetLastError();
 }
 
-// dense node array from the brick layout: psi = x - mean(component), 0 outside the conductor
+// ---------------------------------------------------------------- several voxel models in one handle
+// model m's labels (nx, ny, nz voxels) into the packed label grid (NX, NY voxels per layer) from voxel
+// layer zoff on; the rest of the packed grid stays as it is (air)
+__global__ void k_pack_labels(const uint8_t *__restrict__ src, int nx, int ny, int nz, uint8_t *__restrict__ dst,
+                              int NX, int NY, int zoff)
+{
+    const long long n = (long long)nx * ny * nz;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(v % nx), j = (int)((v / nx) % ny), k = (int)(v / ((long long)nx * ny));
+        dst[i + (long long)NX * (j + (long long)NY * (k + zoff))] = src[v];
+    }
+}
+
+hipError_t launch_pack_labels(const uint8_t *src, int nx, int ny, int nz, uint8_t *dst, int NX, int NY, int zoff,
+                              hipStream_t s)
+{
+    const long long n = (long long)nx * ny * nz;
+    const unsigned gb = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
+    SPFD_LAUNCH(k_pack_labels, dim3(gb), dim3(256), 0, s, src, nx, ny, nz, dst, NX, NY, zoff);
+    return hipGetLastError();
+}
+
+// conductivity of every voxel of the packed grid: its model's table at its label (tables [np][256]),
+// 0 outside every model's box
+__global__ void k_pack_sigma(const uint8_t *__restrict__ labels, Grid g, ModelBoxes mb,
+                             const double *__restrict__ tables, double *__restrict__ sig)
+{
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(v % g.nx), j = (int)((v / g.nx) % g.ny), k = (int)(v / ((long long)g.nx * g.ny));
+        double sv = 0.0;
+        for (int m = 0; m < mb.np; ++m)
+            if (k >= mb.zoff[m] && k < mb.zoff[m] + mb.nz[m] && i < mb.nx[m] && j < mb.ny[m])
+                sv = tables[m * MAX_LABELS + labels[v]];
+        sig[v] = sv;
+    }
+}
+
+hipError_t launch_pack_sigma(const uint8_t *labels, const Grid &g, const ModelBoxes &mb, const double *tables,
+                             double *sig, hipStream_t s)
+{
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    const unsigned gb = (unsigned)((n + 255) / 256 > 65536 ? 65536 : (n + 255) / 256);
+    SPFD_LAUNCH(k_pack_sigma, dim3(gb), dim3(256), 0, s, labels, g, mb, tables, sig);
+    return hipGetLastError();
+}
+
+// dense node array from the brick layout: psi = x - mean(component), 0 outside the conductor.  g: the
+// output's grid; gb: the grid of the brick layout (the same, or the packed grid of several models, in
+// which the output's model starts at node layer zoff)
 __global__ void k_psi_out(const double *__restrict__ x, const int *__restrict__ comp, const double *__restrict__ means,
-                          const int *__restrict__ slot_of, Grid g, double *psi)
+                          const int *__restrict__ slot_of, Grid g, Grid gb, int zoff, double *psi)
 {
     const long long nn = (long long)g.Nx * g.Ny * g.Nz;
     for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(n % g.Nx), j = (int)((n / g.Nx) % g.Ny), k = (int)(n / ((long long)g.Nx * g.Ny));
-        const int sl = slot_of[(i >> 3) + g.Gx * ((j >> 3) + g.Gy * (k >> 3))];
+        const int i = (int)(n % g.Nx), j = (int)((n / g.Nx) % g.Ny), k = (int)(n / ((long long)g.Nx * g.Ny)) + zoff;
+        const int sl = slot_of[(i >> 3) + gb.Gx * ((j >> 3) + gb.Gy * (k >> 3))];
         // both loads issued together (slot 0 stands in outside the bricks), then masked
         const long long idx = sl >= 0 ? (long long)sl * BS + (i & 7) + 8 * (j & 7) + 64 * (k & 7) : 0;
         const int c = comp[idx];
@@ -1344,11 +1407,11 @@ __global__ void k_psi_out(const double *__restrict__ x, const int *__restrict__ 
 }
 
 hipError_t launch_psi_out(const double *x, const int *comp, const double *means, const int *slot_of, const Grid &g,
-                          double *psi, hipStream_t s)
+                          double *psi, hipStream_t s, const Grid *gbricks, int zoff)
 {
     const long long nn = (long long)g.Nx * g.Ny * g.Nz;
     const unsigned gb = (unsigned)((nn + 255) / 256 > 131072 ? 131072 : (nn + 255) / 256);
-    SPFD_LAUNCH(k_psi_out, dim3(gb), dim3(256), 0, s, x, comp, means, slot_of, g, psi);
+    SPFD_LAUNCH(k_psi_out, dim3(gb), dim3(256), 0, s, x, comp, means, slot_of, g, gbricks ? *gbricks : g, zoff, psi);
     return hipGetLastError();
 }
 

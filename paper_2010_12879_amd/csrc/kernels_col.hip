@@ -96,19 +96,25 @@ __host__ __device__ __forceinline__ int col_ngroups(int nb)
     return (nb + Seg<ZPL>::BPG - 1) / Seg<ZPL>::BPG;
 }
 
+// (with packed models, launch row blockIdx.y = m covers model m's bricks; grp
+// is the group's index within the row, the index of its partial sum)
 template <int ZPL>
 __device__ __forceinline__ Seg<ZPL> make_seg(const Topo &topo)
 {
     Seg<ZPL> s;
-    const int ng = col_ngroups<ZPL>(topo.nb);
+    const int2 rg = topo.np ? topo.prange[blockIdx.y] : make_int2(0, topo.nb);
+    const int cnt = rg.y, first = rg.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    s.grp = xcd_brick(blockIdx.x, ng);
+    // the map covers the launch row's full length (with packed models, the largest model's groups), so
+    // that each group of a smaller model has exactly one workgroup
+    s.grp = xcd_brick(blockIdx.x, col_ngroups<ZPL>(topo_count(topo)));
+    if (s.grp >= col_ngroups<ZPL>(cnt)) s.grp = -1;
     s.lane = threadIdx.x & 63;
     s.tx = s.lane & 7;
     s.ty = s.lane >> 3;
     s.z0 = (wave % Seg<ZPL>::WPB) * ZPL;
     const int b = s.grp < 0 ? -1 : s.grp * Seg<ZPL>::BPG + wave / Seg<ZPL>::WPB;
-    s.bk = b < topo.nb ? b : -1;
+    s.bk = b >= 0 && b < cnt ? first + b : -1;
     s.active = false;
     if (s.bk < 0) return s;
     // a column without unknowns stores nothing (its slots stay zero) and
@@ -913,7 +919,7 @@ template <typename T, typename TB, int ZPL, bool LABEL>
 static void cheb_first_z(const OpArgs<T> &op, Topo topo, const TB *b, T *x, T c0, const Scal *sc, const Batch &bt,
                          hipStream_t s)
 {
-    SPFD_LAUNCH((k_col_cheb_first<T, TB, ZPL, LABEL>), col_grid<ZPL>(topo.nb, bt.n), dim3(CTHREADS), 0, s, op, topo,
+    SPFD_LAUNCH((k_col_cheb_first<T, TB, ZPL, LABEL>), col_grid<ZPL>(topo_count(topo), bt.n), dim3(CTHREADS), 0, s, op, topo,
                 b, x, c0, sc, bt.vs);
 }
 
@@ -940,10 +946,10 @@ hipError_t launch_cheb_first2(const OpArgs<T> &op, Topo topo, const TB *b, const
     if (!dinv) return hipErrorInvalidValue;
     constexpr int Z = zpl_cycle<T>();
     if (op.w)
-        SPFD_LAUNCH((k_col_cheb_first2<T, TB, Z, false>), col_grid<Z>(topo.nb, bt.n), dim3(CTHREADS), 0, s, op, topo,
+        SPFD_LAUNCH((k_col_cheb_first2<T, TB, Z, false>), col_grid<Z>(topo_count(topo), bt.n), dim3(CTHREADS), 0, s, op, topo,
                     b, dinv, xout, dout, c0, c1, c2, sc, bt.vs);
     else
-        SPFD_LAUNCH((k_col_cheb_first2<T, TB, Z, true>), col_grid<Z>(topo.nb, bt.n), dim3(CTHREADS), 0, s, op, topo,
+        SPFD_LAUNCH((k_col_cheb_first2<T, TB, Z, true>), col_grid<Z>(topo_count(topo), bt.n), dim3(CTHREADS), 0, s, op, topo,
                     b, dinv, xout, dout, c0, c1, c2, sc, bt.vs);
     return hipGetLastError();
 }
@@ -952,8 +958,8 @@ template <typename T, typename TB, int ZPL, bool LAB, bool PRO, bool DOT>
 static void cheb_step_z(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din, T *dout,
                         T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s, const Prolong &pr, Dots dt)
 {
-    dt.nparts = col_ngroups<ZPL>(topo.nb);
-    SPFD_LAUNCH((k_col_cheb_step<T, TB, ZPL, LAB, PRO, DOT>), col_grid<ZPL>(topo.nb, bt.n), dim3(CTHREADS), 0, s, op,
+    dt.nparts = col_ngroups<ZPL>(topo_count(topo));
+    SPFD_LAUNCH((k_col_cheb_step<T, TB, ZPL, LAB, PRO, DOT>), col_grid<ZPL>(topo_count(topo), bt.n), dim3(CTHREADS), 0, s, op,
                 topo, b, xin, xout, din, dout, c1, c2, sc, bt.vs, pr, dt);
 }
 
@@ -1006,7 +1012,7 @@ static void resid_restrict_z(const OpArgs<T> &op, Topo topo, const TB *b, const 
                              const int4 *fcoord, const Scal *sc, const Batch &bt, hipStream_t s, T *xc,
                              const T *dinv_c, T c0)
 {
-    SPFD_LAUNCH((k_col_resid_restrict<T, TB, ZPL, LABEL>), col_grid<ZPL>(topo.nb, bt.n), dim3(CTHREADS), 0, s, op,
+    SPFD_LAUNCH((k_col_resid_restrict<T, TB, ZPL, LABEL>), col_grid<ZPL>(topo_count(topo), bt.n), dim3(CTHREADS), 0, s, op,
                 topo, b, x, bc, parent_slot, fcoord, sc, bt.vs, bt.vsc, xc, dinv_c, c0);
 }
 
@@ -1034,7 +1040,7 @@ hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, cons
 {
     if (topo.nb <= 0) return hipSuccess;
     if (pin == pout) return hipErrorInvalidValue;
-    const dim3 g = col_grid<ZPL_CG>(topo.nb, bt.n);
+    const dim3 g = col_grid<ZPL_CG>(topo_count(topo), bt.n);
 #define SPFD_CG(LB, F) SPFD_LAUNCH((k_col_cg_step<TZ, ZPL_CG, LB, F>), g, dim3(CTHREADS), 0, s, op, topo, z, pin, \
                                    pout, x, q, part, sc, parity, bt.vs, bt.ps)
     if (op.w) {
@@ -1052,7 +1058,7 @@ hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, co
                         double *part, long long bvs, const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    const dim3 g = col_grid<ZPL_CG>(topo.nb, bt.n);
+    const dim3 g = col_grid<ZPL_CG>(topo_count(topo), bt.n);
     if (op.w)
         SPFD_LAUNCH((k_col_resid<ZPL_CG, false>), g, dim3(CTHREADS), 0, s, op, topo, b, x, r, part, bvs, bt.vs, bt.ps);
     else
@@ -1065,7 +1071,7 @@ hipError_t launch_spmv(const OpArgs<double> &op, Topo topo, const TZ *z, double 
                        hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    const dim3 g = col_grid<ZPL_CG>(topo.nb, bt.n);
+    const dim3 g = col_grid<ZPL_CG>(topo_count(topo), bt.n);
     if (op.w)
         SPFD_LAUNCH((k_col_spmv<TZ, ZPL_CG, false>), g, dim3(CTHREADS), 0, s, op, topo, z, w, sc, bt.vs);
     else

@@ -92,3 +92,90 @@ def test_solve_many_uneven_phantoms_equals_single():
         assert rel <= 1e-11 * 1.01
     for s in solvers:
         s.close()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _relmax(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_packed_models_against_oracle(prec):
+    """Several voxel models of uneven size in one handle (packed along z, one hierarchy, every level
+    kernel launched once for all of them, one CG per model): each potential against the oracle at the
+    matching criterion 1e-12, and against the model solved alone."""
+    print(f"case packed models {prec}", flush=True)
+    dims = [(24, 20, 28), (40, 32, 48), (17, 23, 9), (33, 29, 37), (8, 8, 8)]
+    ws = [W.random_ellipsoid_phantom(nx, ny, nz, seed=300 + i, n_ell=5, semi_range=(2.5, 9.0), name=f"p{i}")
+          for i, (nx, ny, nz) in enumerate(dims)]
+    ws = [w for w in ws if np.any(w.sigma_voxel() > 0)]
+    assert len(ws) >= 4
+    bar = {"fp64": 1e-7, "mixed": 1e-6}[prec]
+    ms = P.MultiSolver([_dev(w.labels) for w in ws], [w.sigma_table for w in ws], ws[0].h, precision=prec)
+    psis, infos = ms.solve([_dev(w.a) for w in ws], tol=1e-12, max_iter=400)
+    # a second solve gives the same result bit for bit (replayed graphs, fixed reductions)
+    psis2, infos2 = ms.solve([_dev(w.a) for w in ws], tol=1e-12, max_iter=400)
+    assert infos == infos2 and all(torch.equal(a, b) for a, b in zip(psis, psis2))
+    ms.close()
+    for k, w in enumerate(ws):
+        assert infos[k]["status"] == "OK" and infos[k]["rel_residual"] <= 1e-12, (k, infos[k])
+        ref, oinfo = oracle.solve(w.sigma_voxel(), w.h, w.a, tol=1e-12)
+        p = psis[k].cpu().numpy()
+        print(f"packed {prec} model {k}: it={infos[k]['iterations']} err={_rel(p, ref):.2e}", flush=True)
+        assert _rel(p, ref) <= bar and _relmax(p, ref) <= bar, k
+        s = P.Solver(_dev(w.labels), w.sigma_table, w.h, precision=prec)
+        p1, i1 = s.solve(_dev(w.a), tol=1e-12, max_iter=400)
+        s.close()
+        assert _rel(p, p1.cpu().numpy()) <= bar, k
+
+
+def test_packed_uneven_phantoms():
+    """The 16 phantoms of 64^3 ... 192^3 voxels in one handle, FP32 cycle: each model's residual by the
+    oracle's own assembly at the benchmark's criterion, and each potential against its own single-model
+    solve (both at 1e-12)."""
+    print("case packed uneven phantoms", flush=True)
+    ws = W.uneven_phantoms()
+    ms = P.MultiSolver([_dev(w.labels) for w in ws], [w.sigma_table for w in ws], ws[0].h, precision="mixed")
+    srcs = [_dev(w.a) for w in ws]
+    psis, infos = ms.solve(srcs, tol=1e-8)
+    for k, w in enumerate(ws):
+        assert infos[k]["status"] == "OK"
+        rel = oracle.residual(w.sigma_voxel(), w.h, w.a, psis[k].cpu().numpy())
+        assert rel <= 1e-8 and abs(rel - infos[k]["rel_residual"]) <= 1e-6 * rel, (k, rel, infos[k])
+    tight, _ = ms.solve(srcs, tol=1e-12, max_iter=400)
+    ms.close()
+    for k, w in enumerate(ws):
+        s = P.Solver(_dev(w.labels), w.sigma_table, w.h, precision="mixed")
+        p1, i1 = s.solve(srcs[k], tol=1e-12, max_iter=400)
+        s.close()
+        err = _rel(tight[k].cpu().numpy(), p1.cpu().numpy())
+        print(f"packed uneven model {k} ({w.name}): it={infos[k]['iterations']} vs single {err:.2e}", flush=True)
+        assert err <= 1e-6, k
+
+
+def test_packed_models_errors():
+    print("case packed errors", flush=True)
+    ws = [W.random_ellipsoid_phantom(16, 16, 16, seed=400 + i, n_ell=4, semi_range=(2.5, 6.0)) for i in range(2)]
+    h = P.spfd_create(0)
+    try:
+        P.spfd_set_geometry_many(h, [_dev(w.labels) for w in ws], *ws[0].h)
+        with pytest.raises(P.SPFDError) as e:       # label 19 not covered by a two-entry table
+            P.spfd_set_sigma_tables(h, [[0.0, 0.3], ws[1].sigma_table])
+            P.spfd_build(h)
+        assert e.value.status == 1
+        P.spfd_set_sigma_tables(h, [w.sigma_table for w in ws])
+        opts = P.AmgOptions()
+        opts.no_split = 1
+        with pytest.raises(P.SPFDError) as e:
+            P.spfd_build(h, opts)
+        assert e.value.status == 1
+        P.spfd_build(h)
+        emag = torch.zeros(1, dtype=torch.float64, device=DEV)
+        with pytest.raises(P.SPFDError) as e:
+            P.spfd_percentile(h, emag)
+        assert e.value.status == 2
+    finally:
+        P.spfd_destroy(h)
