@@ -59,7 +59,7 @@ typedef enum {
 
 enum { SPFD_FP64 = 0, SPFD_MIXED = 1 };          /* precision of the multigrid cycle */
 enum { SPFD_CYCLE_V = 0 };
-enum { SPFD_SMOOTH_CHEBYSHEV = 0, SPFD_SMOOTH_L1_JACOBI = 1 };  /* smoother of every level */
+enum { SPFD_SMOOTH_CHEBYSHEV = 0, SPFD_SMOOTH_L1_JACOBI = 1, SPFD_SMOOTH_CHEBYSHEV4 = 2 };  /* smoother of every level */
 
 /* Multigrid preconditioner (the paper uses an algebraic multigrid
  * preconditioner inside a Krylov solver, Sec. III; its configuration is not
@@ -83,9 +83,12 @@ typedef struct {
                              (level1_degree) sweeps x += D_l1^-1 (b - A x), D_l1 the row l1 norms,
                              which equal twice the diagonal here (every level's rows sum to zero);
                              any other value is rejected with SPFD_INVALID_ARG */
-    int short_segment_bricks; /* structured levels with stored weights and fewer bricks than this run
-                             4-node column segments per lane, larger ones 8 (FP32) / 4 (FP64);
-                             0 = default 8192, negative = never (every FP32 level runs 8-node segments) */
+    int short_segment_bricks; /* column segment (nodes per lane) of the stencil kernels of structured levels
+                             with stored weights in an FP32 cycle: 0 (default) = tuned per level at build
+                             (one Chebyshev step timed with 4- and 8-node segments, the faster kept; the
+                             results are the same either way); > 0 = levels with fewer bricks than this run
+                             4-node segments, larger ones 8; negative = 8-node segments everywhere.
+                             FP64 cycles always run 4-node segments */
     int level1_fp32;      /* SPFD_MIXED only.  0 (default): the first coarse level's smoothing and
                              restriction read FP16 copies of its weights, scaled so that the largest is
                              2^15, unless the smallest nonzero weight would then fall below FP16's normal
@@ -164,10 +167,12 @@ spfd_status spfd_get_info(spfd_handle h, long long *n_dofs, int *n_components, i
  * may be NULL): kind 0 = structured brick level (7-point stencil), 1 =
  * unstructured level (rows of the split aggregation, ELL storage); its
  * unknowns; the slots of its vectors (bricks x 512, or rows); the entries per
- * matrix row (7, or 1 + the ELL width).  The last level is the one solved
- * directly.  SPFD_INVALID_ARG for a level outside [0, n_levels). */
+ * matrix row (7, or 1 + the ELL width); the column segment of its smoothing
+ * kernels in the cycle (nodes per lane, 4 or 8; 0 for ELL levels and the
+ * coarsest level).  The last level is the one solved directly.
+ * SPFD_INVALID_ARG for a level outside [0, n_levels). */
 spfd_status spfd_level_info(spfd_handle h, int level, int *kind, long long *unknowns, long long *slots,
-                            int *row_entries);
+                            int *row_entries, int *segment);
 /* Number of right-hand sides solved together (default 1); resets the sources. */
 spfd_status spfd_set_num_rhs(spfd_handle h, int nrhs);
 /* Right-hand side of Eq. (3) for source `rhs`: b = -G^T M_kappa a, with

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libspfd.so")
 
 FP64, MIXED = 0, 1
 CYCLE_V = 0
-SMOOTH_CHEBYSHEV, SMOOTH_L1_JACOBI = 0, 1
+SMOOTH_CHEBYSHEV, SMOOTH_L1_JACOBI, SMOOTH_CHEBYSHEV4 = 0, 1, 2
 CG, FGMRES = 0, 1
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "BAD_STATE", 3: "OUT_OF_MEMORY", 4: "HIP_ERROR", 5: "NOT_CONVERGED",
           6: "BREAKDOWN"}
@@ -120,7 +120,7 @@ def load_library(path: str = LIB_PATH):
     lib.spfd_get_info.argtypes = [H, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I), ctypes.POINTER(I),
                                   ctypes.POINTER(ctypes.c_size_t)]
     lib.spfd_level_info.argtypes = [H, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_longlong),
-                                    ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I)]
+                                    ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I), ctypes.POINTER(I)]
     lib.spfd_set_num_rhs.argtypes = [H, I]
     lib.spfd_set_source.argtypes = [H, I, P]
     lib.spfd_solve.argtypes = [H, ctypes.POINTER(SolveOptions), P, ctypes.POINTER(RhsInfo)]
@@ -238,12 +238,12 @@ def spfd_get_info(h):
 
 
 def spfd_level_info(h, level):
-    """kind ("structured" or "ell"), unknowns, slots and entries per row of one level."""
-    k, n, sl, re = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
+    """kind ("structured" or "ell"), unknowns, slots, entries per row and column segment of one level."""
+    k, n, sl, re, sg = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int(), ctypes.c_int()
     _check(h, load_library().spfd_level_info(h, level, ctypes.byref(k), ctypes.byref(n), ctypes.byref(sl),
-                                             ctypes.byref(re)))
+                                             ctypes.byref(re), ctypes.byref(sg)))
     return {"kind": "ell" if k.value else "structured", "unknowns": n.value, "slots": sl.value,
-            "row_entries": re.value}
+            "row_entries": re.value, "segment": sg.value}
 
 
 def spfd_set_num_rhs(h, nrhs):
@@ -419,7 +419,7 @@ class Solver:
             self.opts = AmgOptions(MIXED if precision == "mixed" else FP64, CYCLE_V,
                                    smooth_degree, coarsest_max, cheby_ratio, coarse_scale, split_level,
                                    0 if split else 1, level1_degree,
-                                   {"chebyshev": SMOOTH_CHEBYSHEV, "l1jacobi": SMOOTH_L1_JACOBI}[smoother],
+                                   {"chebyshev": SMOOTH_CHEBYSHEV, "l1jacobi": SMOOTH_L1_JACOBI, "chebyshev4": SMOOTH_CHEBYSHEV4}[smoother],
                                    short_segment_bricks, 1 if level1_fp32 else 0)
             spfd_build(self.handle, self.opts)
         except Exception:

@@ -63,6 +63,8 @@ struct Level {
     unsigned long long *d_cmask = nullptr;  // node columns with unknowns, per brick (structured levels)
     double *d_dinv64 = nullptr;             // inverse diagonal (0 where it vanishes), FP64 and FP32
     float *d_dinv32 = nullptr;
+    int seg = 0;                            // column segment (nodes per lane) of an FP32 cycle on this level:
+                                            // 4 or 8 when tuned at build, 0 = by the brick-count threshold
     Topo topo() const { return Topo{nb, d_nbr, d_cmask}; }
     long long nodes() const { return ell ? (long long)nrow : (long long)nb * BS; }
 };
@@ -140,6 +142,8 @@ struct Ctx {
     int pstride = 0;          // partial sums per right side
     int *d_again = nullptr;   // per right side: restart from the true residual
     int nbat = 0;             // right sides the solve buffers hold
+    int nbat_vec = 0;         // vectors of each kind the solve buffers hold (1 for packed models)
+    std::vector<std::pair<int, int>> seg_cache;   // per level: bricks and the tuned segment (4 or 8)
     int *d_ints = nullptr;    // small scratch ints
     int *h_ints = nullptr;    // pinned
     uint8_t *h_stage = nullptr;   // pinned staging for the host-built tables of the hierarchy
@@ -498,7 +502,7 @@ OpArgs<float> level_op<float>(Ctx *c, int l)
     OpArgs<float> op{};
     const Level &L = c->lv[l];
     op.stride = L.nodes();
-    op.short_below = c->opt.short_segment_bricks;
+    op.short_below = L.seg == 4 ? 0x7fffffff : L.seg == 8 ? 0 : c->opt.short_segment_bricks;
     if (l == 0 && !c->voxel_mode) {
         op.w = nullptr;
         op.tiles = L.d_tiles;
@@ -822,6 +826,7 @@ void set_defaults(spfd_amg_options &o)
     if (o.split_level <= 0) o.split_level = 2;
     if (o.level1_degree <= 0) o.level1_degree = 4;
     if (o.level1_degree > 8) o.level1_degree = 8;
+    // 0: tuned per level at build (the threshold below stands until then); < 0: 8-node segments everywhere
     if (o.short_segment_bricks == 0) o.short_segment_bricks = 8192;
     if (o.short_segment_bricks < 0) o.short_segment_bricks = 0;
 }
@@ -835,6 +840,17 @@ void chebyshev_coefficients(Ctx *c)
 {
     c->cheb_c1.assign(8, 0.0);
     c->cheb_c2.assign(8, 0.0);
+    if (c->opt.smoother == SPFD_SMOOTH_CHEBYSHEV4) {
+        // Chebyshev polynomial of the fourth kind in D^-1 A on [0, lmax] (no lower bound): the error
+        // polynomial p_m satisfies max |p_m(l)| sqrt(l / lmax) = 1 / (2m + 1) on [0, lmax]
+        const double rho = 2.0;
+        c->cheb_c0 = 4.0 / (3.0 * rho);
+        for (int k = 1; k < 8; ++k) {
+            c->cheb_c1[k] = (2.0 * k - 1.0) / (2.0 * k + 3.0);
+            c->cheb_c2[k] = (8.0 * k + 4.0) / ((2.0 * k + 3.0) * rho);
+        }
+        return;
+    }
     if (c->opt.smoother == SPFD_SMOOTH_L1_JACOBI) {
         c->cheb_c0 = 0.5;
         for (int k = 1; k < 8; ++k) c->cheb_c2[k] = 0.5;
@@ -853,6 +869,68 @@ void chebyshev_coefficients(Ctx *c)
     }
 }
 
+// The column segment of every structured level with stored weights in an FP32
+// cycle (4 or 8 nodes per lane): both variants of one Chebyshev step are timed
+// on the level's own buffers (best of three after a warm-up each) and the
+// faster one is kept for every kernel of that level.  Both compute each node
+// the same way, so the choice changes the speed only, never a result.
+void tune_segments(Ctx *c)
+{
+    if (c->opt.precision != SPFD_MIXED) return;
+    // levels to tune: structured, stored weights, smoothed; a level of the same brick count as at the
+    // last tuning of this handle keeps its choice (a rebuild with new conductivities, same geometry)
+    std::vector<int> todo;
+    for (size_t l = 0; l + 1 < c->lv.size(); ++l) {
+        Level &L = c->lv[l];
+        L.seg = 0;
+        if (L.ell || (l == 0 && !c->voxel_mode) || L.nb <= 0) continue;
+        if (l < c->seg_cache.size() && c->seg_cache[l].first == L.nb) {
+            L.seg = c->seg_cache[l].second;
+            continue;
+        }
+        todo.push_back((int)l);
+    }
+    if (todo.empty()) return;
+    constexpr int REPS = 3;   // per variant, after one warm-up launch; variants alternate
+    std::vector<hipEvent_t> ev(todo.size() * 2 * (REPS + 1) * 2, nullptr);
+    for (hipEvent_t &e : ev) HIPCHK(hipEventCreate(&e));
+    size_t k = 0;
+    for (int l : todo) {
+        Level &L = c->lv[l];
+        for (int rep = 0; rep <= REPS; ++rep)
+            for (int v = 0; v < 2; ++v) {
+                L.seg = v == 0 ? 4 : 8;
+                HIPCHK(hipEventRecord(ev[k++], c->stream));
+                HIPCHK(launch_cheb_step<float, float>(level_op<float>(c, l), L.topo(), (const float *)L.b,
+                                                      (const float *)L.x, (float *)L.x2, (const float *)L.d, nullptr,
+                                                      0.5f, 0.5f, nullptr, level_batch(c, l, 1), c->stream));
+                HIPCHK(hipEventRecord(ev[k++], c->stream));
+            }
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    k = 0;
+    for (int l : todo) {
+        float best[2] = {1e30f, 1e30f};
+        for (int rep = 0; rep <= REPS; ++rep)
+            for (int v = 0; v < 2; ++v) {
+                float ms = 0.0f;
+                HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+                k += 2;
+                if (rep > 0 && ms < best[v]) best[v] = ms;
+            }
+        Level &L = c->lv[l];
+        L.seg = best[0] <= best[1] ? 4 : 8;
+        if (c->seg_cache.size() <= (size_t)l) c->seg_cache.resize(l + 1, {-1, 0});
+        c->seg_cache[l] = {L.nb, L.seg};
+    }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    // the tuning steps wrote x2 (zeros, from zero inputs); cleared again all the same
+    for (int l : todo) {
+        Level &L = c->lv[l];
+        HIPCHK(hipMemsetAsync(L.x2, 0, (size_t)L.nodes() * c->nbat_vec * sizeof(float), c->stream));
+    }
+}
+
 // solve buffers for nb right sides: cycle vectors of every level, the outer
 // CG vectors and the partial sums
 void alloc_cycle_buffers(Ctx *c, int nb)
@@ -867,6 +945,7 @@ void alloc_cycle_buffers(Ctx *c, int nb)
     const bool mixed = c->opt.precision == SPFD_MIXED;
     const size_t w = mixed ? sizeof(float) : sizeof(double);
     const int nvec = c->np ? 1 : nb;   // packed models share one vector of each kind
+    c->nbat_vec = nvec;
     for (size_t l = 0; l < c->lv.size(); ++l) {
         Level &L = c->lv[l];
         const size_t n = (size_t)L.nodes() * nvec;
@@ -1035,8 +1114,14 @@ spfd_status do_build(Ctx *c)
         c->d_cpart = dalloc<double>(c, c->hier_allocs, comp_mean_parts(L0.nb));
         HIPCHK(hipMemsetAsync(c->d_counts, 0, (c->ncomp + 1) * sizeof(int), c->stream));
         HIPCHK(launch_comp_counts(c->d_comp, n, c->d_counts, c->stream));
+        // the unknowns of the finest level are the nodes of the components
+        int *hc = (int *)stage(c, (size_t)(c->ncomp + 1) * sizeof(int));
+        HIPCHK(hipMemcpyAsync(hc, c->d_counts, (size_t)c->ncomp * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        long long nd = 0;
+        for (int k = 0; k < c->ncomp; ++k) nd += hc[k];
+        L0.dofs = nd;
     }
-    L0.dofs = count_dofs(c, L0);
     // 4. coarsening: 2x2x2 aggregation until the level is small enough; from
     //    level split_level on, aggregates are split into their connected pieces
     while (c->lv.back().dofs > c->opt.coarsest_max && c->lv.size() < 20) {
@@ -1928,6 +2013,7 @@ spfd_status set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, doubl
         h->geo4[2] = 0.25 * (hx * hy / hz);
         h->np = 0;
         h->d_mtables = nullptr;
+        h->seg_cache.clear();
         h->d_labels = dalloc<uint8_t>(h, h->geo_allocs, nvox);
         if (labels)
             HIPCHK(hipMemcpyAsync(h->d_labels, labels, nvox, hipMemcpyDefault, h->stream));
@@ -2095,8 +2181,9 @@ spfd_status spfd_build(spfd_handle h, const spfd_amg_options *opt)
     if (h->state < 2) return fail(h, SPFD_BAD_STATE, "set geometry and conductivities first");
     spfd_amg_options o{};
     if (opt) o = *opt;
+    const bool tune = o.short_segment_bricks == 0;   // the default: segments tuned per level
     if (o.cycle != SPFD_CYCLE_V) return fail(h, SPFD_INVALID_ARG, "unknown cycle (only SPFD_CYCLE_V)");
-    if (o.smoother != SPFD_SMOOTH_CHEBYSHEV && o.smoother != SPFD_SMOOTH_L1_JACOBI)
+    if (o.smoother != SPFD_SMOOTH_CHEBYSHEV && o.smoother != SPFD_SMOOTH_L1_JACOBI && o.smoother != SPFD_SMOOTH_CHEBYSHEV4)
         return fail(h, SPFD_INVALID_ARG, "unknown smoother");
     set_defaults(o);
     // packed models sit MODEL_ALIGN node layers apart: bricks of the structured levels up to level 3
@@ -2114,7 +2201,9 @@ spfd_status spfd_build(spfd_handle h, const spfd_amg_options *opt)
             return s;
         }
         h->state = 3;
-        return do_set_num_rhs(h, 1);
+        s = do_set_num_rhs(h, 1);
+        if (s == SPFD_OK && tune) tune_segments(h);
+        return s;
     }
     API_GUARD(h)
 }
@@ -2131,7 +2220,7 @@ spfd_status spfd_get_info(spfd_handle h, long long *n_dofs, int *n_components, i
 }
 
 spfd_status spfd_level_info(spfd_handle h, int level, int *kind, long long *unknowns, long long *slots,
-                            int *row_entries)
+                            int *row_entries, int *segment)
 {
     if (!h) return SPFD_INVALID_ARG;
     if (h->state < 3) return fail(h, SPFD_BAD_STATE, "build first");
@@ -2141,6 +2230,17 @@ spfd_status spfd_level_info(spfd_handle h, int level, int *kind, long long *unkn
     if (unknowns) *unknowns = L.ell ? (long long)L.nrow : L.dofs;
     if (slots) *slots = L.nodes();
     if (row_entries) *row_entries = L.ell ? 1 + L.K : 7;
+    if (segment) {
+        const bool fp32 = h->opt.precision == SPFD_MIXED;
+        if (L.ell || level + 1 == (int)h->lv.size())
+            *segment = 0;
+        else if (!fp32)
+            *segment = 4;
+        else if (level == 0 && !h->voxel_mode)
+            *segment = 8;
+        else
+            *segment = L.seg ? L.seg : (L.nb < h->opt.short_segment_bricks ? 4 : 8);
+    }
     return SPFD_OK;
 }
 

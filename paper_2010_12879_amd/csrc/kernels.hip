@@ -81,16 +81,33 @@ __global__ void k_brick_flags(const uint8_t *__restrict__ labels, const double *
 
 // out[0]: bits of the largest weight (starts at 0), out[1]: bits of the smallest positive one (starts at
 // the bits of +inf); non-negative floats order like their bit patterns
-__global__ void k_wmax(const float *w, long long n, unsigned *out)
+__global__ __launch_bounds__(256) void k_wmax(const float *w, long long n, unsigned *out)
 {
+    __shared__ float smax[4], smin[4];
     float m = 0.0f, mp = INFINITY;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const float v = w[i];
         m = fmaxf(m, v);
         if (v > 0.0f) mp = fminf(mp, v);
     }
-    atomicMax(out, __float_as_uint(m));
-    atomicMin(out + 1, __float_as_uint(mp));
+    // wave, then workgroup, then one atomic per workgroup
+    for (int off = 32; off > 0; off >>= 1) {
+        m = fmaxf(m, __shfl_down(m, off, 64));
+        mp = fminf(mp, __shfl_down(mp, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        smax[threadIdx.x >> 6] = m;
+        smin[threadIdx.x >> 6] = mp;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 4; ++k) {
+            m = fmaxf(m, smax[k]);
+            mp = fminf(mp, smin[k]);
+        }
+        atomicMax(out, __float_as_uint(m));
+        atomicMin(out + 1, __float_as_uint(mp));
+    }
 }
 __global__ void k_w16(const float *w, long long n, float inv, uint16_t *h)
 {

@@ -174,3 +174,24 @@ def test_per_voxel_sigma_against_oracle(prec):
         print(f"per-voxel adjoint: err {_rel(g, gs_ref):.2e}", flush=True)
         assert ainfo["status"] == "OK" and _rel(g, gs_ref) <= 1e-7
     s.close()
+
+
+def test_segment_tuning_changes_speed_only():
+    """The column segment of the FP32 cycle's stored-weight levels (4 or 8 nodes per lane) is tuned per
+    level at build by default; each node is computed the same way in both, so the potential is
+    bit-identical whichever segments the levels run."""
+    print("case segment tuning", flush=True)
+    w = W.config(1)
+    lab, a = _dev(w.labels), _dev(w.a)
+    out = {}
+    for name, seg in (("tuned", 0), ("all8", -1), ("all4", 1 << 30)):
+        s = P.Solver(lab, w.sigma_table, w.h, precision="mixed", short_segment_bricks=seg)
+        levels = [P.spfd_level_info(s.handle, l) for l in range(s.info()["n_levels"])]
+        psi, info = s.solve(a, tol=1e-10)
+        s.close()
+        out[name] = (psi, info, [lv["segment"] for lv in levels])
+        print(f"segments {name}: {out[name][2]}", flush=True)
+    assert all(sg in (4, 8) for sg in out["tuned"][2][1:2])
+    assert out["all8"][2][1] == 8 and out["all4"][2][1] == 4
+    for name in ("all8", "all4"):
+        assert torch.equal(out[name][0], out["tuned"][0]) and out[name][1] == out["tuned"][1], name
