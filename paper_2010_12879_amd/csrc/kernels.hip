@@ -1199,7 +1199,7 @@ template hipError_t launch_pupdate<float>(Topo, const float *, double *, const S
 // ---------------------------------------------------------------- multigrid level kernels
 __device__ __forceinline__ bool stopped(const Scal *sc)
 {
-    return sc && __hip_atomic_load(&sc[blockIdx.y].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return sc && sc[blockIdx.y].done;   // written by an earlier kernel only: a plain (scalar) load
 }
 
 // x += s * P x_c

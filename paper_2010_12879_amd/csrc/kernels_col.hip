@@ -43,11 +43,15 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // The cycle kernels of a right side that has stopped return before loading
-// anything (the step that stops still has its cycle queued behind it): the
-// flag's load overlaps the brick-table loads every wave waits for anyway.
+// anything (the step that stops still has its cycle queued behind it).  The
+// flag is written only by an earlier kernel of the stream (a finisher), whose
+// writes every later kernel sees, so a plain load suffices; at a uniform
+// address it is a scalar load, issued with the brick-table loads every wave
+// waits for anyway.  (An atomic load was a vector load that the wave waited
+// for before issuing any data load: one more memory round trip per wave.)
 __device__ __forceinline__ bool col_stopped(const Scal *sc)
 {
-    return sc && __hip_atomic_load(&sc[blockIdx.y].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return sc && sc[blockIdx.y].done;
 }
 
 // value of v in lane `src` of the wave (src taken modulo 64)
@@ -750,7 +754,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
     const Seg<ZPL> s = make_seg<ZPL>(topo);
     if (s.grp < 0) return;
     // a stopped right side (batched solves, a step queued past the stop) returns before its loads
-    if (__hip_atomic_load(&sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    if (sc->done) return;
     zv += blockIdx.y * vs;
     pin += blockIdx.y * vs;
     pout += blockIdx.y * vs;

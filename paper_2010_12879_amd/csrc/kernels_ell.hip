@@ -370,7 +370,7 @@ hipError_t launch_galerkin_ell(const FineLevelArgs &fa, const int *agg, int nc, 
 // ============================================================================
 __device__ __forceinline__ bool ell_stopped(const Scal *sc)
 {
-    return sc && __hip_atomic_load(&sc[blockIdx.y].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return sc && sc[blockIdx.y].done;   // written by an earlier kernel only: a plain (scalar) load
 }
 
 // (A x)_i and the diagonal D of an ELL row.  Padding entries (col < 0) read
