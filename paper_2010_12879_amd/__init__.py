@@ -51,8 +51,8 @@ class Allocator(ctypes.Structure):
 
 def torch_allocator(device, stream=None):
     """An Allocator that takes the handle's device memory from PyTorch's caching allocator on `device`
-    (blocks tied to `stream`, default the current stream).  Keep the returned object alive as long as
-    the handle: the library calls its functions until spfd_destroy."""
+    (blocks tied to `stream`, default the current stream).  spfd_create keeps it alive until
+    spfd_destroy: the library calls its functions until then."""
     import torch
 
     def _alloc(nbytes, user):
@@ -84,6 +84,8 @@ class RhsInfo(ctypes.Structure):
 
 
 _lib = None
+# allocator of each live handle (by address), held here so that its ctypes callbacks stay valid
+_HANDLE_ALLOCATORS = {}
 EXPORTS = ["spfd_create", "spfd_destroy", "spfd_last_error", "spfd_set_geometry", "spfd_set_sigma_table",
            "spfd_set_sigma_voxel", "spfd_build", "spfd_get_info", "spfd_level_info", "spfd_set_num_rhs", "spfd_set_source",
            "spfd_solve", "spfd_solve_many", "spfd_efield", "spfd_edge_potentials", "spfd_percentile",
@@ -175,11 +177,14 @@ def spfd_create(device: int = 0, stream=None, allocator: Allocator | None = None
                          ctypes.byref(allocator) if allocator is not None else None, ctypes.byref(h))
     if st != 0:
         raise SPFDError(st, "spfd_create failed")
+    if allocator is not None:
+        _HANDLE_ALLOCATORS[h.value] = allocator   # its callbacks must outlive the handle
     return h
 
 
 def spfd_destroy(h):
     load_library().spfd_destroy(h)
+    _HANDLE_ALLOCATORS.pop(h.value if isinstance(h, ctypes.c_void_p) else h, None)
 
 
 def spfd_last_error(h) -> str:

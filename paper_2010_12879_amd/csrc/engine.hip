@@ -120,6 +120,7 @@ struct Ctx {
     Scal *h_scal = nullptr;   // pinned, one per right side plus one for the adjoint solve
     Scal *h_ring = nullptr;   // pinned, 2 x (nrhs + 1): scalars of the last two enqueued CG steps
     Scal *h_ring_dev = nullptr;   // device address of h_ring (written by the last kernel of a CG step)
+    Scal *d_nostop = nullptr;     // zeroed scalars (never stopped) for cycles run outside a CG step
     Scal *step_mirror = nullptr;  // where the CG step being enqueued leaves its scalars
     hipEvent_t ev_it[2] = {nullptr, nullptr};
     // adjoint solve
@@ -733,6 +734,11 @@ bool vcycle(Ctx *c, const TR *r, T *z, const Scal *sc, int nb, const CycleDots *
 {
     const int nl = (int)c->lv.size();
     std::vector<T *> res(nl, nullptr);
+    // the stencil kernels read a stop flag per launch row: a cycle outside a CG step never stops
+    if (!sc) {
+        if (!c->d_nostop || nb > c->nbat) throw HipFail{hipErrorInvalidValue, "cycle without scalars"};
+        sc = c->d_nostop;
+    }
     if (nl == 1) {
         coarse_solve<T, TR>(c, r, z, sc, nb);  // single level: the dense solve is exact
         return false;
@@ -903,7 +909,7 @@ void tune_segments(Ctx *c)
                 HIPCHK(hipEventRecord(ev[k++], c->stream));
                 HIPCHK(launch_cheb_step<float, float>(level_op<float>(c, l), L.topo(), (const float *)L.b,
                                                       (const float *)L.x, (float *)L.x2, (const float *)L.d, nullptr,
-                                                      0.5f, 0.5f, nullptr, level_batch(c, l, 1), c->stream));
+                                                      0.5f, 0.5f, c->d_nostop, level_batch(c, l, 1), c->stream));
                 HIPCHK(hipEventRecord(ev[k++], c->stream));
             }
     }
@@ -978,6 +984,8 @@ void alloc_cycle_buffers(Ctx *c, int nb)
     c->pstride = 2 * c->lv[0].nb + 64;
     c->d_part = dalloc<double>(c, c->rhs_allocs, (size_t)c->pstride * nb);
     HIPCHK(hipMemsetAsync(c->d_part, 0, (size_t)c->pstride * nb * sizeof(double), c->stream));
+    c->d_nostop = dalloc<Scal>(c, c->rhs_allocs, nb);
+    HIPCHK(hipMemsetAsync(c->d_nostop, 0, (size_t)nb * sizeof(Scal), c->stream));
     c->nbat = nb;
 }
 

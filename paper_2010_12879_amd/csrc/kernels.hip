@@ -925,28 +925,30 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
     __shared__ double red[16];
     part += (long long)blockIdx.x * ps;
     if (sc) sc += blockIdx.x;
-    if (mode == FIN_ALPHA || mode == FIN_RR || mode == FIN_BETA0 || mode == FIN_BETA || mode == FIN_BETA_STD)
-        if (sc->done) {
-            if (threadIdx.x == 0) store_mirror(mirror, sc);
-            return;
-        }
+    // a stopped right side keeps its scalars; the flag is loaded with the partials and tested after them
+    // (a test first would put one more memory round trip before the loads)
+    const bool may_stop =
+        mode == FIN_ALPHA || mode == FIN_RR || mode == FIN_BETA0 || mode == FIN_BETA || mode == FIN_BETA_STD;
+    const int stopped = may_stop ? sc->done : 0;
     const int nr = rows.used ? rows.n[blockIdx.x] : n;
-    // four independent loads in flight per thread and round (fixed order: deterministic)
+    // eight independent loads in flight per thread and round, summed in a fixed order (deterministic)
+    constexpr int U = 8;
     const int nt = blockDim.x;
     double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nr; i += 4 * nt) {
-        const double v0 = part[i];
-        const double v1 = i + nt < nr ? part[i + nt] : 0.0;
-        const double v2 = i + 2 * nt < nr ? part[i + 2 * nt] : 0.0;
-        const double v3 = i + 3 * nt < nr ? part[i + 3 * nt] : 0.0;
-        a += (v0 + v1) + (v2 + v3);
-        if (mode == FIN_BETA) {
-            const double w0 = part[n + i];
-            const double w1 = i + nt < nr ? part[n + i + nt] : 0.0;
-            const double w2 = i + 2 * nt < nr ? part[n + i + 2 * nt] : 0.0;
-            const double w3 = i + 3 * nt < nr ? part[n + i + 3 * nt] : 0.0;
-            b += (w0 + w1) + (w2 + w3);
+    for (int i0 = threadIdx.x; i0 < nr; i0 += U * nt) {
+        double v[U], w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * nt;
+            v[u] = i < nr ? part[i] : 0.0;
+            w[u] = mode == FIN_BETA && i < nr ? part[n + i] : 0.0;
         }
+        a += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+        b += ((w[0] + w[1]) + (w[2] + w[3])) + ((w[4] + w[5]) + (w[6] + w[7]));
+    }
+    if (stopped) {
+        if (threadIdx.x == 0) store_mirror(mirror, sc);
+        return;
     }
     a = block_sum_any(a, red);
     if (mode == FIN_BETA) b = block_sum_any(b, red);
@@ -1106,16 +1108,21 @@ __global__ __launch_bounds__(NT) void k_rupdate(Topo topo, double *__restrict__ 
 {
     __shared__ double red[8];
     sc += blockIdx.y;
-    if (sc->done) return;
     int loc;
     const int bk = topo_brick(topo, loc);
     if (bk < 0) return;
     const long long n = blockIdx.y * vs + (long long)bk * BS + threadIdx.x;
-    const double rn = r[n] - sc->alpha * q[n];
-    r[n] = rn;
-    if (r32) r32[n] = (float)rn;
-    const double tot = block_sum(rn * rn, red);
-    if (threadIdx.x == 0) part[(long long)blockIdx.y * ps + loc] = tot;
+    // The loads do not wait for the stop flag (a test before them would cost one more memory round
+    // trip): a stopped right side loads, but stores nothing.
+    const double rv = r[n], qv = q[n];
+    const bool run = sc->done == 0;
+    const double rn = rv - sc->alpha * qv;
+    if (run) {
+        r[n] = rn;
+        if (r32) r32[n] = (float)rn;
+    }
+    const double tot = block_sum(run ? rn * rn : 0.0, red);
+    if (threadIdx.x == 0 && run) part[(long long)blockIdx.y * ps + loc] = tot;
 }
 
 hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, Scal *sc, const Batch &bt, float *r32,

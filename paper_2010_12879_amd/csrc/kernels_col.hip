@@ -42,18 +42,6 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The cycle kernels of a right side that has stopped return before loading
-// anything (the step that stops still has its cycle queued behind it).  The
-// flag is written only by an earlier kernel of the stream (a finisher), whose
-// writes every later kernel sees, so a plain load suffices; at a uniform
-// address it is a scalar load, issued with the brick-table loads every wave
-// waits for anyway.  (An atomic load was a vector load that the wave waited
-// for before issuing any data load: one more memory round trip per wave.)
-__device__ __forceinline__ bool col_stopped(const Scal *sc)
-{
-    return sc && sc[blockIdx.y].done;
-}
-
 // value of v in lane `src` of the wave (src taken modulo 64)
 template <typename T>
 __device__ __forceinline__ T lane_get(T v, int src)
@@ -85,6 +73,7 @@ struct Seg {
     int bk;                                       // brick (-1: this wave has none)
     int grp;                                      // brick group of the workgroup (-1: padding)
     int z0, lane, tx, ty;
+    int nb[6];                                    // neighbour bricks of bk (-1: absent)
     long long self;                               // slot of (tx, ty, z0)
     long long xe, ye;                             // lanes with tx = 0 or 7 (ty = 0 or 7): slot of the x (y)
                                                   // neighbour of (tx, ty, z0) in the next brick
@@ -92,6 +81,7 @@ struct Seg {
     bool has[6];                                  // neighbour slot exists
     bool bx, by;                                  // xe (ye) is to be read: face lane, neighbour brick present
     bool active;                                  // the lane's node column holds an unknown
+    bool stop;                                    // the launch row's right side has stopped: return at once
 };
 
 template <int ZPL>
@@ -102,8 +92,18 @@ __host__ __device__ __forceinline__ int col_ngroups(int nb)
 
 // (with packed models, launch row blockIdx.y = m covers model m's bricks; grp
 // is the group's index within the row, the index of its partial sum)
-template <int ZPL>
-__device__ __forceinline__ Seg<ZPL> make_seg(const Topo &topo)
+//
+// The uniform records a wave needs before its first vector load (the brick's
+// neighbour table and column mask) and the stop flag of its right side are
+// scalar loads from memory.  They are issued as one batch (at brick 0 for a
+// wave without a brick) and waited for once: a branch on any of them, or on
+// whether a pointer is given, before the others were issued would cost one
+// more memory round trip per wave, a large part of a wave's life in these
+// short kernels.  So the column mask and the scalars are required (launches
+// that never stop pass zeroed scalars).  The stop flag is written only by an
+// earlier kernel of the stream, so a plain load sees it.
+template <int ZPL, bool FLAG = true>
+__device__ __forceinline__ Seg<ZPL> make_seg(const Topo &topo, const Scal *sc)
 {
     Seg<ZPL> s;
     const int2 rg = topo.np ? topo.prange[blockIdx.y] : make_int2(0, topo.nb);
@@ -119,14 +119,17 @@ __device__ __forceinline__ Seg<ZPL> make_seg(const Topo &topo)
     s.z0 = (wave % Seg<ZPL>::WPB) * ZPL;
     const int b = s.grp < 0 ? -1 : s.grp * Seg<ZPL>::BPG + wave / Seg<ZPL>::WPB;
     s.bk = b >= 0 && b < cnt ? first + b : -1;
+    const int bl = s.bk < 0 ? 0 : s.bk;
+    const unsigned long long cm = topo.cmask[bl];
+    s.stop = FLAG && sc[blockIdx.y].done != 0;
+    brick_nbrs(topo.nbr, bl, s.nb);
     s.active = false;
     if (s.bk < 0) return s;
     // a column without unknowns stores nothing (its slots stay zero) and
     // loads only what its neighbours' stencils need (nothing in most kernels);
     // edges into it have conductance 0
-    s.active = !topo.cmask || ((topo.cmask[s.bk] >> s.lane) & 1ull);
-    int nb[6];
-    brick_nbrs(topo.nbr, s.bk, nb);
+    s.active = (cm >> s.lane) & 1ull;
+    const int *nb = s.nb;
     const long long base = (long long)s.bk * BS;
     const int t0 = s.lane + 64 * s.z0;
     s.self = base + t0;
@@ -420,9 +423,8 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo 
                                                              T *__restrict__ x, T c0, const Scal *sc, long long vs)
 {
     T *lds = col_lds<T, ZPL, LABEL>();
-    const Seg<ZPL> s = make_seg<ZPL>(topo);
-    if (s.bk < 0) return;
-    if (col_stopped(sc)) return;
+    const Seg<ZPL> s = make_seg<ZPL>(topo, sc);
+    if (s.bk < 0 || s.stop) return;
     b += blockIdx.y * vs;
     x += blockIdx.y * vs;
     SegOp<T, ZPL, LABEL> A;
@@ -455,9 +457,8 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first2(OpArgs<T> op, Topo
                                                               long long vs)
 {
     T *lds = col_lds<T, ZPL, LABEL>();
-    const Seg<ZPL> s = make_seg<ZPL>(topo);
-    if (s.bk < 0) return;
-    if (col_stopped(sc)) return;
+    const Seg<ZPL> s = make_seg<ZPL>(topo, sc);
+    if (s.bk < 0 || s.stop) return;
     b += blockIdx.y * vs;
     xout += blockIdx.y * vs;
     if (dout) dout += blockIdx.y * vs;
@@ -526,8 +527,7 @@ __device__ __forceinline__ void apply_prolong(const Prolong &pr, const Topo &top
     // every lane loads from a valid slot
     const T *xc = (const T *)pr.xc + blockIdx.y * pr.vsc;
     const T sc = (T)pr.scale;
-    int nb[6];
-    brick_nbrs(topo.nbr, s.bk, nb);
+    const int *nb = s.nb;
     const int tx = s.tx, ty = s.ty, z0 = s.z0;
     // coarse slots of the lane's own column, of its face column in the x (y)
     // neighbour brick and of the two z ends (absent -> own column, never read)
@@ -581,9 +581,8 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo t
 {
     T *lds = col_lds<T, ZPL, LABEL>();
     __shared__ double red[2][CWAVES];
-    const Seg<ZPL> s = make_seg<ZPL>(topo);
-    if (DOT ? s.grp < 0 : s.bk < 0) return;
-    if (col_stopped(sc)) return;
+    const Seg<ZPL> s = make_seg<ZPL>(topo, sc);
+    if ((DOT ? s.grp < 0 : s.bk < 0) || s.stop) return;
     double dzr = 0.0, dzq = 0.0;
     if (s.bk >= 0) {
         b += blockIdx.y * vs;
@@ -684,9 +683,8 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
                                                                  const T *__restrict__ dinv_c, T c0)
 {
     T *lds = col_lds<T, ZPL, LABEL>();
-    const Seg<ZPL> s = make_seg<ZPL>(topo);
-    if (s.bk < 0) return;
-    if (col_stopped(sc)) return;
+    const Seg<ZPL> s = make_seg<ZPL>(topo, sc);
+    if (s.bk < 0 || s.stop) return;
     b += blockIdx.y * vs;
     x += blockIdx.y * vs;
     bc += blockIdx.y * vsc;
@@ -750,11 +748,10 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
 {
     double *lds = col_lds<double, ZPL, LABEL>();
     __shared__ double red[CWAVES];
+    const Seg<ZPL> s = make_seg<ZPL>(topo, sc);
     sc += blockIdx.y;
-    const Seg<ZPL> s = make_seg<ZPL>(topo);
-    if (s.grp < 0) return;
     // a stopped right side (batched solves, a step queued past the stop) returns before its loads
-    if (sc->done) return;
+    if (s.grp < 0 || s.stop) return;
     zv += blockIdx.y * vs;
     pin += blockIdx.y * vs;
     pout += blockIdx.y * vs;
@@ -828,7 +825,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid(OpArgs<double> op, Topo 
 {
     double *lds = col_lds<double, ZPL, LABEL>();
     __shared__ double red[CWAVES];
-    const Seg<ZPL> s = make_seg<ZPL>(topo);
+    const Seg<ZPL> s = make_seg<ZPL, false>(topo, nullptr);
     if (s.grp < 0) return;
     double rr = 0.0;
     if (s.bk >= 0) {
@@ -874,9 +871,8 @@ __global__ __launch_bounds__(CTHREADS) void k_col_spmv(OpArgs<double> op, Topo t
                                                        double *__restrict__ w, const Scal *sc, long long vs)
 {
     double *lds = col_lds<double, ZPL, LABEL>();
-    const Seg<ZPL> s = make_seg<ZPL>(topo);
-    if (s.bk < 0) return;
-    if (col_stopped(sc)) return;
+    const Seg<ZPL> s = make_seg<ZPL>(topo, sc);
+    if (s.bk < 0 || s.stop) return;
     zv += blockIdx.y * vs;
     w += blockIdx.y * vs;
     SegOp<double, ZPL, LABEL> A;
@@ -906,6 +902,13 @@ constexpr int ZPL_CG = 4;
 
 int cg_step_parts(int nb) { return col_ngroups<ZPL_CG>(nb); }
 
+// the column kernels read the level's column mask and (except the true
+// residual) the scalars of every launch row unconditionally
+static bool col_args_ok(const Topo &topo, const Scal *sc, bool need_sc = true)
+{
+    return topo.cmask && topo.nbr && (sc || !need_sc);
+}
+
 template <int ZPL>
 static dim3 col_grid(int nb, int nbatch)
 {
@@ -932,6 +935,7 @@ hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, 
                              hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
+    if (!col_args_ok(topo, sc)) return hipErrorInvalidValue;
     constexpr int Z = zpl_cycle<T>();
     if (!op.w)
         cheb_first_z<T, TB, Z, true>(op, topo, b, x, c0, sc, bt, s);
@@ -947,6 +951,7 @@ hipError_t launch_cheb_first2(const OpArgs<T> &op, Topo topo, const TB *b, const
                               T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
+    if (!col_args_ok(topo, sc)) return hipErrorInvalidValue;
     if (!dinv) return hipErrorInvalidValue;
     constexpr int Z = zpl_cycle<T>();
     if (op.w)
@@ -974,6 +979,7 @@ hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T
                             double *dot_part)
 {
     if (topo.nb <= 0) return hipSuccess;
+    if (!col_args_ok(topo, sc)) return hipErrorInvalidValue;
     if (xin == xout) return hipErrorInvalidValue;
     if (xc && !(parent_slot && fcoord)) return hipErrorInvalidValue;
     constexpr int Z = zpl_cycle<T>();
@@ -1027,6 +1033,7 @@ hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, co
 {
     if (xc && !dinv_c) return hipErrorInvalidValue;
     if (topo.nb <= 0) return hipSuccess;
+    if (!col_args_ok(topo, sc)) return hipErrorInvalidValue;
     constexpr int Z = zpl_cycle<T>();
     if (!op.w)
         resid_restrict_z<T, TB, Z, true>(op, topo, b, x, bc, parent_slot, fcoord, sc, bt, s, xc, dinv_c, c0);
@@ -1043,6 +1050,7 @@ hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, cons
                           hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
+    if (!col_args_ok(topo, sc)) return hipErrorInvalidValue;
     if (pin == pout) return hipErrorInvalidValue;
     const dim3 g = col_grid<ZPL_CG>(topo_count(topo), bt.n);
 #define SPFD_CG(LB, F) SPFD_LAUNCH((k_col_cg_step<TZ, ZPL_CG, LB, F>), g, dim3(CTHREADS), 0, s, op, topo, z, pin, \
@@ -1062,6 +1070,7 @@ hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, co
                         double *part, long long bvs, const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
+    if (!col_args_ok(topo, nullptr, false)) return hipErrorInvalidValue;
     const dim3 g = col_grid<ZPL_CG>(topo_count(topo), bt.n);
     if (op.w)
         SPFD_LAUNCH((k_col_resid<ZPL_CG, false>), g, dim3(CTHREADS), 0, s, op, topo, b, x, r, part, bvs, bt.vs, bt.ps);
@@ -1075,6 +1084,7 @@ hipError_t launch_spmv(const OpArgs<double> &op, Topo topo, const TZ *z, double 
                        hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
+    if (!col_args_ok(topo, sc)) return hipErrorInvalidValue;
     const dim3 g = col_grid<ZPL_CG>(topo_count(topo), bt.n);
     if (op.w)
         SPFD_LAUNCH((k_col_spmv<TZ, ZPL_CG, false>), g, dim3(CTHREADS), 0, s, op, topo, z, w, sc, bt.vs);
