@@ -165,6 +165,7 @@ struct Ctx {
     const Scal *sg_sc = nullptr;
     StepGraph *capturing = nullptr;
     int step_ctx = 0;   // 0: outside the CG loop, 1: in an untimed CG step, 2: in the sampled step
+    bool r32_ready = false;   // d_r32 holds the FP32 copy of the residual the next CG start reads
     // per-class launch timing (tracing aid); cold: a flush of d_flush before every timed launch
     unsigned tmask = 0;
     bool tcold = false;
@@ -1308,9 +1309,15 @@ void pcg_begin(Ctx *c, Scal *sc, int nb)
     T *z = (T *)c->d_z;
     const double n0 = (double)L0.dofs * (c->np ? 1 : nb);
     CycleDots dots{nullptr, c->d_part};   // r.z only
+    // an FP32 cycle starts from the FP32 copy of r when the start wrote one (as every later cycle does)
+    const bool r32 = sizeof(T) == sizeof(float) && c->r32_ready;
+    c->r32_ready = false;
     if (c->np) {
-        vcycle<T, double>(c, c->d_r, z, nullptr, 1, nullptr);
-    } else if (vcycle<T, double>(c, c->d_r, z, sc, nb, &dots)) {
+        if (r32)
+            vcycle<T, float>(c, c->d_r32, z, nullptr, 1, nullptr);
+        else
+            vcycle<T, double>(c, c->d_r, z, nullptr, 1, nullptr);
+    } else if (r32 ? vcycle<T, float>(c, c->d_r32, z, sc, nb, &dots) : vcycle<T, double>(c, c->d_r, z, sc, nb, &dots)) {
         finish(c, cheb_dot_parts<T>(topo.nb), FIN_BETA0, sc, 0, nb);
         return;
     }
@@ -1716,15 +1723,16 @@ spfd_status solve_batch(Ctx *c, const double *b, long long bvs, Scal *sc, Scal *
     // packed models share one vector of each kind
     const int nvec = c->np ? 1 : nb;
     HIPCHK(launch_scal_init(sc, so.rel_tol, so.use_x0, nb, c->stream));
+    c->r32_ready = false;
     if (so.use_x0) {
         for (int i = 0; i < nvec; ++i)
             HIPCHK(launch_psi_in(psi + i * nn, c->d_comp, L0.d_coord, L0.nb, c->g, c->d_x + i * n0, c->stream));
         resid_b(c, b, bvs, sc, c->d_r, 0, nb);
     } else {
-        HIPCHK(hipMemsetAsync(c->d_x, 0, nvec * n0 * sizeof(double), c->stream));
-        for (int i = 0; i < nvec; ++i)
-            HIPCHK(hipMemcpyAsync(c->d_r + i * n0, b + i * bvs, n0 * sizeof(double), hipMemcpyDeviceToDevice,
-                                  c->stream));
+        // x = 0, r = b and (FP32 cycle) the FP32 copy of r for the first cycle, in one pass
+        const bool mixed = c->opt.precision == SPFD_MIXED && so.method != SPFD_FGMRES;
+        HIPCHK(launch_start(n0, b, bvs, c->d_x, c->d_r, mixed ? c->d_r32 : nullptr, nvec, c->stream));
+        c->r32_ready = mixed;
     }
     // no host round trip here: a right side that is already done (b = 0, or an exact x0) stops the
     // kernels through its device-side flag, and ||b||^2 comes back with the final scalars
@@ -1732,12 +1740,36 @@ spfd_status solve_batch(Ctx *c, const double *b, long long bvs, Scal *sc, Scal *
     std::vector<int> status(nb, 0), iters(nb, 0);
     bool any = true;
     int *again = c->d_again;
+    // gauge and dense output of every right side: zero mean per connected component, 0 outside the
+    // conductor (packed models: one gauge pass over the shared vector, no component spans two models)
+    auto emit = [&]() {
+        if (c->np) {
+            TScope ts(c, SPFD_K_GAUGE, (double)L0.dofs * 24.0 + c->mnodes_off[c->np] * 8.0);
+            HIPCHK(launch_comp_mean(topo, c->d_x, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_cpart, c->stream));
+        }
+        for (int i = 0; i < nb; ++i) {
+            if (c->np) {
+                HIPCHK(launch_psi_out(c->d_x, c->d_comp, c->d_means, L0.d_slot_of, c->mgrid[i], psi + c->mnodes_off[i],
+                                      c->stream, &c->g, c->mbox.zoff[i]));
+            } else {
+                TScope ts(c, SPFD_K_GAUGE,
+                          (double)L0.dofs * (12.0 * (c->ncomp < 16 ? c->ncomp : 1) + 12.0) + nn * 8.0);
+                HIPCHK(launch_comp_mean(topo, c->d_x + i * n0, c->d_comp, c->ncomp, c->d_counts, c->d_means,
+                                        c->d_cpart, c->stream));
+                HIPCHK(launch_psi_out(c->d_x + i * n0, c->d_comp, c->d_means, L0.d_slot_of, c->g, psi + i * nn,
+                                      c->stream));
+            }
+        }
+    };
     for (int pass = 0; pass < 3 && any; ++pass) {
         krylov_iterations(c, b, bvs, sc, nb, so);
         // true residual of every iterate (also of those that converged in an earlier pass); r itself is
         // only needed for a restart and is formed again then
         resid_b(c, b, bvs, sc, nullptr, 1, nb);
         HIPCHK(hipMemcpyAsync(hsc, sc, nb * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
+        // the output is formed before the host has seen the residuals (no idle GPU during that round
+        // trip); a restart forms it again
+        emit();
         HIPCHK(hipStreamSynchronize(c->stream));
         any = false;
         std::vector<int> redo(nb, 0);
@@ -1760,25 +1792,9 @@ spfd_status solve_batch(Ctx *c, const double *b, long long bvs, Scal *sc, Scal *
         }
     }
     spfd_status worst = SPFD_OK;
-    if (c->np) {
-        // one gauge pass over the packed vector (no component spans two models), then each model's array
-        TScope ts(c, SPFD_K_GAUGE, (double)L0.dofs * 24.0 + c->mnodes_off[c->np] * 8.0);
-        HIPCHK(launch_comp_mean(topo, c->d_x, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_cpart, c->stream));
-    }
     for (int i = 0; i < nb; ++i) {
         if (bb[i] > 0.0 && status[i] == 0 && relres[i] > so.rel_tol) status[i] = SPFD_NOT_CONVERGED;
         if (status[i] != 0 && worst == SPFD_OK) worst = (spfd_status)status[i];
-        if (c->np) {
-            HIPCHK(launch_psi_out(c->d_x, c->d_comp, c->d_means, L0.d_slot_of, c->mgrid[i], psi + c->mnodes_off[i],
-                                  c->stream, &c->g, c->mbox.zoff[i]));
-        } else {
-            // gauge: zero mean per connected component, 0 outside the conductor
-            TScope ts(c, SPFD_K_GAUGE, (double)L0.dofs * (12.0 * (c->ncomp < 16 ? c->ncomp : 1) + 12.0) + nn * 8.0);
-            HIPCHK(launch_comp_mean(topo, c->d_x + i * n0, c->d_comp, c->ncomp, c->d_counts, c->d_means, c->d_cpart,
-                                    c->stream));
-            HIPCHK(launch_psi_out(c->d_x + i * n0, c->d_comp, c->d_means, L0.d_slot_of, c->g, psi + i * nn,
-                                  c->stream));
-        }
         if (info) {
             info[i].iterations = iters[i];
             info[i].rel_residual = relres[i];

@@ -244,6 +244,9 @@ hipError_t launch_comp_mean(Topo topo, const double *x, const int *comp, int nco
 // starts at node layer zoff of it)
 hipError_t launch_psi_out(const double *x, const int *comp, const double *means, const int *slot_of, const Grid &g,
                           double *psi, hipStream_t s, const Grid *gbricks = nullptr, int zoff = 0);
+// start of a solve from x = 0 for nvec right sides: x = 0, r = b and r32 = (float)b (r32 may be null)
+hipError_t launch_start(long long n, const double *b, long long bvs, double *x, double *r, float *r32, int nvec,
+                        hipStream_t s);
 hipError_t launch_psi_in(const double *psi, const int *comp, const int4 *coord, int nb, const Grid &g, double *x,
                          hipStream_t s);
 hipError_t launch_efield(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,

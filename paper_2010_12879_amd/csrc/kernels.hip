@@ -1417,25 +1417,54 @@ hipError_t launch_pack_sigma(const uint8_t *labels, const Grid &g, const ModelBo
 __global__ void k_psi_out(const double *__restrict__ x, const int *__restrict__ comp, const double *__restrict__ means,
                           const int *__restrict__ slot_of, Grid g, Grid gb, int zoff, double *psi)
 {
-    const long long nn = (long long)g.Nx * g.Ny * g.Nz;
-    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(n % g.Nx), j = (int)((n / g.Nx) % g.Ny), k = (int)(n / ((long long)g.Nx * g.Ny)) + zoff;
-        const int sl = slot_of[(i >> 3) + gb.Gx * ((j >> 3) + gb.Gy * (k >> 3))];
+    // one workgroup per node row (j, k): contiguous stores, no 64-bit index division
+    const int row = blockIdx.x;
+    const int j = row % g.Ny, kb = row / g.Ny + zoff;
+    const int *srow = slot_of + gb.Gx * ((j >> 3) + gb.Gy * (kb >> 3));
+    const int off = 8 * (j & 7) + 64 * (kb & 7);
+    double *prow = psi + (long long)row * g.Nx;
+    for (int i = threadIdx.x; i < g.Nx; i += blockDim.x) {
+        const int sl = srow[i >> 3];
         // both loads issued together (slot 0 stands in outside the bricks), then masked
-        const long long idx = sl >= 0 ? (long long)sl * BS + (i & 7) + 8 * (j & 7) + 64 * (k & 7) : 0;
+        const long long idx = sl >= 0 ? (long long)sl * BS + (i & 7) + off : 0;
         const int c = comp[idx];
         const double xv = x[idx];
         const double m = means[c >= 0 ? c : 0];
-        psi[n] = (sl >= 0 && c >= 0) ? xv - m : 0.0;
+        prow[i] = (sl >= 0 && c >= 0) ? xv - m : 0.0;
     }
 }
 
 hipError_t launch_psi_out(const double *x, const int *comp, const double *means, const int *slot_of, const Grid &g,
                           double *psi, hipStream_t s, const Grid *gbricks, int zoff)
 {
-    const long long nn = (long long)g.Nx * g.Ny * g.Nz;
-    const unsigned gb = (unsigned)((nn + 255) / 256 > 131072 ? 131072 : (nn + 255) / 256);
-    SPFD_LAUNCH(k_psi_out, dim3(gb), dim3(256), 0, s, x, comp, means, slot_of, g, gbricks ? *gbricks : g, zoff, psi);
+    const long long rows = (long long)g.Ny * g.Nz;
+    if (rows <= 0) return hipSuccess;
+    SPFD_LAUNCH(k_psi_out, dim3((unsigned)rows), dim3(256), 0, s, x, comp, means, slot_of, g, gbricks ? *gbricks : g,
+                zoff, psi);
+    return hipGetLastError();
+}
+
+// start of a solve from x = 0: x = 0, r = b (right side i at b + i*bvs, vectors at i*n) and, for an
+// FP32 cycle, the FP32 copy of r that the first cycle reads
+__global__ void k_start(long long n, const double *__restrict__ b, long long bvs, double *__restrict__ x,
+                        double *__restrict__ r, float *__restrict__ r32)
+{
+    const long long off = (long long)blockIdx.y * n;
+    b += (long long)blockIdx.y * bvs;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+        const double v = b[k];
+        x[off + k] = 0.0;
+        r[off + k] = v;
+        if (r32) r32[off + k] = (float)v;
+    }
+}
+
+hipError_t launch_start(long long n, const double *b, long long bvs, double *x, double *r, float *r32, int nvec,
+                        hipStream_t s)
+{
+    if (n <= 0 || nvec <= 0) return hipSuccess;
+    const long long blocks = (n + 255) / 256;
+    SPFD_LAUNCH(k_start, dim3((unsigned)(blocks > 65536 ? 65536 : blocks), nvec), dim3(256), 0, s, n, b, bvs, x, r, r32);
     return hipGetLastError();
 }
 
@@ -1469,17 +1498,20 @@ __global__ void k_efield(const uint8_t *__restrict__ labels, const double *__res
                          const double *__restrict__ sig_vox, Grid g, double hx, double hy, double hz, double omega,
                          const double *__restrict__ a, const double *__restrict__ psi, double *emag)
 {
-    const long long nvox = (long long)g.nx * g.ny * g.nz;
+    // one workgroup per voxel row (j, k): contiguous loads and stores, no 64-bit index division
+    const int row = blockIdx.x;
+    const int j = row % g.ny, k = row / g.ny;
     const long long nn = (long long)g.Nx * g.Ny * g.Nz;
     const long long sy = g.Nx, sz = (long long)g.Nx * g.Ny;
-    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (long long)gridDim.x * blockDim.x) {
+    const long long v0 = (long long)row * g.nx, nrow = j * sy + k * sz;
+    for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
+        const long long v = v0 + i;
         const double s = sig_vox ? sig_vox[v] : table[labels[v]];
         if (!(s > 0.0)) {
             emag[v] = 0.0;
             continue;
         }
-        const long long i = v % g.nx, j = (v / g.nx) % g.ny, k = v / ((long long)g.nx * g.ny);
-        const long long n0 = i + g.Nx * (j + (long long)g.Ny * k);
+        const long long n0 = nrow + i;
         // x-edges start at (i, j..j+1, k..k+1)
         const long long ex[4] = {n0, n0 + sy, n0 + sz, n0 + sy + sz};
         const long long ey[4] = {n0, n0 + 1, n0 + sz, n0 + 1 + sz};
@@ -1499,10 +1531,10 @@ hipError_t launch_efield(const uint8_t *labels, const double *table, const doubl
                          const double h[3], double omega, const double *a, const double *psi, double *emag,
                          hipStream_t s)
 {
-    const long long nvox = (long long)g.nx * g.ny * g.nz;
-    const unsigned gb = (unsigned)((nvox + 255) / 256 > 131072 ? 131072 : (nvox + 255) / 256);
-    SPFD_LAUNCH(k_efield, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, h[0], h[1], h[2], omega, a, psi,
-                       emag);
+    const long long rows = (long long)g.ny * g.nz;
+    if (rows <= 0) return hipSuccess;
+    SPFD_LAUNCH(k_efield, dim3((unsigned)rows), dim3(256), 0, s, labels, table, sig_vox, g, h[0], h[1], h[2], omega, a,
+                psi, emag);
     return hipGetLastError();
 }
 
@@ -1512,8 +1544,11 @@ __global__ void k_uedges(const uint8_t *__restrict__ labels, const double *__res
                          const double *__restrict__ psi, double *u)
 {
     const long long nn = (long long)g.Nx * g.Ny * g.Nz;
-    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(n % g.Nx), j = (int)((n / g.Nx) % g.Ny), k = (int)(n / ((long long)g.Nx * g.Ny));
+    // one workgroup per node row (j, k): contiguous loads and stores, no 64-bit index division
+    const int row = blockIdx.x;
+    const int j = row % g.Ny, k = row / g.Ny;
+    for (int i = threadIdx.x; i < g.Nx; i += blockDim.x) {
+        const long long n = (long long)row * g.Nx + i;
         // x-edge: voxels (i, j-1..j, k-1..k)
         double sx = 0.0, sy = 0.0, sz = 0.0;
         if (i < g.nx)
@@ -1534,9 +1569,9 @@ __global__ void k_uedges(const uint8_t *__restrict__ labels, const double *__res
 hipError_t launch_uedges(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,
                          const double *a, const double *psi, double *u, hipStream_t s)
 {
-    const long long nn = (long long)g.Nx * g.Ny * g.Nz;
-    const unsigned gb = (unsigned)((nn + 255) / 256 > 131072 ? 131072 : (nn + 255) / 256);
-    SPFD_LAUNCH(k_uedges, dim3(gb), dim3(256), 0, s, labels, table, sig_vox, g, a, psi, u);
+    const long long rows = (long long)g.Ny * g.Nz;
+    if (rows <= 0) return hipSuccess;
+    SPFD_LAUNCH(k_uedges, dim3((unsigned)rows), dim3(256), 0, s, labels, table, sig_vox, g, a, psi, u);
     return hipGetLastError();
 }
 
