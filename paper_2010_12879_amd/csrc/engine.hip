@@ -1049,7 +1049,9 @@ Level split_level(Ctx *c, Level &F)
     HIPCHK(hipMemcpyAsync(c->h_ints + 2, c->d_ints + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (c->h_ints[2]) throw HipFail{hipErrorInvalidValue, "split aggregate with too many coarse neighbours"};
-    C.K = c->h_ints[3] > 0 ? c->h_ints[3] : 1;
+    // rows of up to 8 entries are stored with 8 (padding: column -1, value 0), the width of the fixed-width
+    // cycle kernels of the ELL levels
+    C.K = std::max(c->h_ints[3], 8);
     C.d_col = dalloc<int>(c, c->hier_allocs, (size_t)C.K * nc + 1);
     C.d_val64 = dalloc<double>(c, c->hier_allocs, (size_t)C.K * nc + 1);
     C.d_val32 = dalloc<float>(c, c->hier_allocs, (size_t)C.K * nc + 1);

@@ -559,6 +559,81 @@ hipError_t launch_dinv_ell(int n, int K, const int *col, const double *val, doub
     return hipGetLastError();
 }
 
+// The same step for levels stored with ELL_K8 entries per row (every level with rows of at most that many;
+// the build pads them to it), one row per thread, written so that a
+// thread's loads go out in two rounds without a wait in between the loads of a round: first its row (the
+// eight column indices and values, b, d and its own x, and with the prolongation its aggregate), then the
+// gathers of the neighbours' x (and their aggregates and coarse values).  The stop flag is loaded with the
+// first round and tested after it was issued (the opaque copy keeps the compiler from testing it first,
+// which would put one more memory round trip in front of the loads).
+constexpr int ELL_K8 = 8;
+
+// (No __restrict__ here: with it the compiler may move the row loads past the opaque flag and its test.)
+template <typename T, bool PRO>
+__global__ __launch_bounds__(256) void k_ell_cheb_step8(int n, int K, const int *col, const T *val, const T *b,
+                                                        const T *xin, T *xout, const T *din, T *dout, T c1, T c2,
+                                                        const Scal *sc, long long vs, const int *agg, const T *xc,
+                                                        T scale, long long vsc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int stop = sc[blockIdx.y].done;
+    b += blockIdx.y * vs;
+    xin += blockIdx.y * vs;
+    xout += blockIdx.y * vs;
+    const bool has_d = din != nullptr;
+    const T *dsrc = has_d ? din + blockIdx.y * vs : xin;   // (a valid address either way)
+    if (dout) dout += blockIdx.y * vs;
+    if (PRO) xc += blockIdx.y * vsc;
+    int j[ELL_K8];
+    T v[ELL_K8];
+#pragma unroll
+    for (int k = 0; k < ELL_K8; ++k) {
+        j[k] = col[(long long)k * n + i];
+        v[k] = val[(long long)k * n + i];
+    }
+    const T bi = b[i];
+    const T dd = dsrc[i];
+    const T x0 = xin[i];
+    const int a0 = PRO ? agg[i] : -1;
+    asm volatile("" : "+s"(stop) : : "memory");
+    if (stop) return;
+    // second round: the neighbours (padding entries read the row's own slot with weight 0)
+    T xj[ELL_K8];
+    int aj[ELL_K8];
+#pragma unroll
+    for (int k = 0; k < ELL_K8; ++k) {
+        const int jj = j[k] >= 0 ? j[k] : i;
+        xj[k] = xin[jj];
+        if (PRO) aj[k] = agg[jj];
+    }
+    T xi = x0;
+    if (PRO) {
+        const T c0v = xc[a0 >= 0 ? a0 : 0];
+        T cj[ELL_K8];
+#pragma unroll
+        for (int k = 0; k < ELL_K8; ++k) cj[k] = xc[aj[k] >= 0 ? aj[k] : 0];
+        xi = a0 >= 0 ? x0 + scale * c0v : x0;
+#pragma unroll
+        for (int k = 0; k < ELL_K8; ++k) xj[k] = aj[k] >= 0 ? xj[k] + scale * cj[k] : xj[k];
+    }
+    T y = T(0), d = T(0);
+#pragma unroll
+    for (int k = 0; k < ELL_K8; ++k) {
+        const T w = j[k] >= 0 ? v[k] : T(0);
+        d += w;
+        y += w * (xi - xj[k]);
+    }
+    T xo = T(0), dn = T(0);
+    if (d > T(0)) {
+        const T dold = has_d ? dd : xi;
+        dn = c1 * dold + c2 * (bi - y) / d;
+        xo = xi + dn;
+    }
+    xout[i] = xo;
+    if (dout) dout[i] = dn;
+}
+
 // x_f += scale * x_c[agg]
 template <typename T>
 __global__ void k_prolong_agg(long long n, const int *__restrict__ agg, T *__restrict__ x, const T *__restrict__ xc,
@@ -590,6 +665,16 @@ hipError_t launch_ell_cheb_step(int n, int K, const int *col, const T *val, cons
 {
     if (n <= 0) return hipSuccess;
     if (agg && !xc) return hipErrorInvalidValue;
+    const long long nb = (n + 255) / 256;
+    if (K == ELL_K8 && sc && nb <= 65536) {
+        if (agg)
+            SPFD_LAUNCH((k_ell_cheb_step8<T, true>), dim3((unsigned)nb, bt.n), dim3(256), 0, s, n, K, col, val, b, xin,
+                        xout, din, dout, c1, c2, sc, bt.vs, agg, xc, scale, bt.vsc);
+        else
+            SPFD_LAUNCH((k_ell_cheb_step8<T, false>), dim3((unsigned)nb, bt.n), dim3(256), 0, s, n, K, col, val, b, xin,
+                        xout, din, dout, c1, c2, sc, bt.vs, agg, xc, scale, bt.vsc);
+        return hipGetLastError();
+    }
     SPFD_LAUNCH(k_ell_cheb_step<T>, dim3(gblocks(n), bt.n), dim3(256), 0, s, n, K, col, val, b, xin, xout, din, dout,
                 c1, c2, sc, bt.vs, agg, xc, scale, bt.vsc);
     return hipGetLastError();
