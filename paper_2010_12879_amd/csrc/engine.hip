@@ -59,6 +59,7 @@ struct Level {
     int4 *d_pos = nullptr;          // grid position of each row at this level
     int *d_mptr = nullptr;          // members of each row in the finer level (CSR)
     int *d_mem = nullptr;
+    int *d_memb = nullptr;          // the same as a direct table of 8 per row (null: an aggregate has more)
     int *d_agg = nullptr;           // this level's unknown -> row of the next (split) level, -1 if none
     unsigned long long *d_cmask = nullptr;  // node columns with unknowns, per brick (structured levels)
     double *d_dinv64 = nullptr;             // inverse diagonal (0 where it vanishes), FP64 and FP32
@@ -690,7 +691,7 @@ void restrict_level(Ctx *c, int l, const TB *b, const T *x, const Scal *sc, int 
         }
         TScope ts(c, SPFD_K_COARSE, nb * ((double)L.dofs * 3.0 * sizeof(T) + (double)C.nrow * 8.0) + fb);
         HIPCHK(launch_restrict_members<T>(f, L.nodes(), (const T *)b, x, C.nrow, C.d_mptr, C.d_mem,
-                                          (T *)C.b, sc, bt, c->stream, xc, dc, c0));
+                                          (T *)C.b, sc, bt, c->stream, xc, dc, c0, C.d_memb));
         return;
     }
     const double by = nb * ((double)L.dofs * (sizeof(TB) + op_bytes<T>(c, l) + sizeof(T)) + (double)C.dofs * sizeof(T));
@@ -1030,6 +1031,9 @@ Level split_level(Ctx *c, Level &F)
     C.d_mem = dalloc<int>(c, c->hier_allocs, nmem + 1);
     HIPCHK(hipMemsetAsync(count, 0, (nc + 1) * sizeof(int), c->stream));
     HIPCHK(launch_members(F.d_agg, nf, nc, C.d_mptr, count, C.d_mem, c->stream));
+    C.d_memb = dalloc<int>(c, c->hier_allocs, (size_t)nc * 8 + 1);
+    HIPCHK(hipMemsetAsync(c->d_ints + 4, 0, sizeof(int), c->stream));
+    HIPCHK(launch_members8(nc, C.d_mptr, C.d_mem, C.d_memb, c->d_ints + 4, c->stream));
     // Galerkin rows: lengths, then the ELL arrays
     FineLevelArgs fa{};
     if (F.ell) {
@@ -1046,9 +1050,10 @@ Level split_level(Ctx *c, Level &F)
     HIPCHK(hipMemsetAsync(c->d_ints + 2, 0, 2 * sizeof(int), c->stream));
     HIPCHK(launch_galerkin_ell(fa, F.d_agg, nc, C.d_mptr, C.d_mem, 0, len, 0, nullptr, nullptr, nullptr, c->d_ints + 2,
                                c->d_ints + 3, c->stream));
-    HIPCHK(hipMemcpyAsync(c->h_ints + 2, c->d_ints + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(c->h_ints + 2, c->d_ints + 2, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (c->h_ints[2]) throw HipFail{hipErrorInvalidValue, "split aggregate with too many coarse neighbours"};
+    if (c->h_ints[4]) C.d_memb = nullptr;   // an aggregate of more than 8 members: the CSR restriction
     // rows of up to 8 entries are stored with 8 (padding: column -1, value 0), the width of the fixed-width
     // cycle kernels of the ELL levels
     C.K = std::max(c->h_ints[3], 8);

@@ -303,7 +303,10 @@ hipError_t launch_ell_cheb_step(int n, int K, const int *col, const T *val, cons
 template <typename T>
 hipError_t launch_restrict_members(const FineLevelT<T> &f, long long nrows, const T *b, const T *x, int nc,
                                    const int *mptr, const int *mem, T *bc, const Scal *sc, const Batch &bt,
-                                   hipStream_t s, T *xc = nullptr, const T *dinv_c = nullptr, T c0 = T(0));
+                                   hipStream_t s, T *xc = nullptr, const T *dinv_c = nullptr, T c0 = T(0),
+                                   const int *memb = nullptr);
+// direct member table memb[p*8 + j] of the restriction (*over = 1 if an aggregate has more than 8 members)
+hipError_t launch_members8(int nc, const int *mptr, const int *mem, int *memb, int *over, hipStream_t s);
 // inverse diagonals (0 where the diagonal vanishes): ELL level, structured level
 hipError_t launch_dinv_ell(int n, int K, const int *col, const double *val, double *d64, float *d32, hipStream_t s);
 hipError_t launch_dinv_struct(const double *w64, long long stride, Topo topo, double *d64, float *d32,

@@ -186,6 +186,20 @@ __global__ void k_members_sort(int nc, const int *__restrict__ mptr, int *mem)
     }
 }
 
+// Direct member table of the restriction: memb[p*8 + j] = member j of aggregate p (-1: none), one load
+// instead of the CSR pair (pointer, then member); an aggregate with more than eight members sets *over
+// (the restriction then keeps the CSR form).
+__global__ void k_members8(int nc, const int *__restrict__ mptr, const int *__restrict__ mem, int *__restrict__ memb,
+                           int *over)
+{
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += gridDim.x * blockDim.x) {
+        const int b = mptr[p], e = mptr[p + 1];
+        if (e - b > 8) *over = 1;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) memb[(long long)p * 8 + j] = b + j < e ? mem[b + j] : -1;
+    }
+}
+
 // ---------------------------------------------------------------- Galerkin rows
 constexpr int GAL_MAX = 48;   // distinct coarse neighbours a row may collect
 
@@ -343,6 +357,13 @@ hipError_t launch_members(const int *agg, long long n, int nc, const int *mptr, 
 {
     SPFD_LAUNCH(k_members_fill, dim3(gblocks(n)), dim3(256), 0, s, agg, n, mptr, cursor, mem);
     if (nc > 0) SPFD_LAUNCH(k_members_sort, dim3(gblocks(nc)), dim3(256), 0, s, nc, mptr, mem);
+    return hipGetLastError();
+}
+
+hipError_t launch_members8(int nc, const int *mptr, const int *mem, int *memb, int *over, hipStream_t s)
+{
+    if (nc <= 0) return hipSuccess;
+    SPFD_LAUNCH(k_members8, dim3(gblocks(nc)), dim3(256), 0, s, nc, mptr, mem, memb, over);
     return hipGetLastError();
 }
 
@@ -510,6 +531,7 @@ __device__ __forceinline__ T fine_resid(const FineLevelT<T> &f, const T *__restr
 // depend on scheduling.  With xc: also the coarse level's first Chebyshev
 // step, xc = c0 D^-1 b_c.
 constexpr int RLANES = 8;
+constexpr int ELL_K8 = 8;   // row width of the fixed-width ELL kernels
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict_rows(FineLevelT<T> f, int nc, const int *__restrict__ mptr,
@@ -535,6 +557,58 @@ __global__ __launch_bounds__(256) void k_restrict_rows(FineLevelT<T> f, int nc, 
             bc[p] = s;
             if (xc) xc[p] = c0 * s * dinv[p];
         }
+    }
+}
+
+// The same restriction from the direct member table (aggregates of at most eight members; lane j of a
+// group takes member j): the member index, then the member's row or stencil, then the neighbours, with no
+// wait inside a round.  FELL: the finer level is an ELL level stored with 8 entries per row; otherwise a
+// structured level with stored weights.  The stop flag only guards the stores.
+template <typename T, bool FELL>
+__global__ __launch_bounds__(256) void k_restrict8(FineLevelT<T> f, int nc, const int *__restrict__ memb,
+                                                   const T *__restrict__ b, const T *__restrict__ x,
+                                                   T *__restrict__ bc, const Scal *sc, long long vs, long long vsc,
+                                                   T *__restrict__ xc, const T *__restrict__ dinv, T c0)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = (int)(t / RLANES), j = (int)(t % RLANES);
+    const bool inr = p < nc;   // (every lane of a group reaches the butterfly)
+    const int stop = sc[blockIdx.y].done;
+    b += blockIdx.y * vs;
+    x += blockIdx.y * vs;
+    bc += blockIdx.y * vsc;
+    // unconditional loads at clamped indices (a load under a condition becomes a branch that waits for it)
+    const int mi = memb[inr ? (long long)p * RLANES + j : 0];
+    const T dq = (xc ? dinv : b)[inr ? p : 0];
+    const int i = inr ? mi : -1;
+    const T dp = xc ? dq : T(0);
+    const long long ii = i >= 0 ? i : 0;   // a valid row for the loads of a lane without a member
+    T r;
+    if constexpr (FELL) {
+        int jj[ELL_K8];
+        T vv[ELL_K8];
+#pragma unroll
+        for (int k = 0; k < ELL_K8; ++k) {
+            jj[k] = f.col[(long long)k * f.n + ii];
+            vv[k] = f.val[(long long)k * f.n + ii];
+        }
+        const T xi = x[ii], bi = b[ii];
+        T xj[ELL_K8];
+#pragma unroll
+        for (int k = 0; k < ELL_K8; ++k) xj[k] = x[jj[k] >= 0 ? jj[k] : ii];
+        T y = T(0);
+#pragma unroll
+        for (int k = 0; k < ELL_K8; ++k) y += (jj[k] >= 0 ? vv[k] : T(0)) * (xi - xj[k]);
+        r = bi - y;
+    } else {
+        r = fine_resid(f, b, x, ii);
+    }
+    T sum = i >= 0 ? r : T(0);
+#pragma unroll
+    for (int m = 1; m < RLANES; m <<= 1) sum += __shfl_xor(sum, m, RLANES);
+    if (j == 0 && inr && !stop) {
+        bc[p] = sum;
+        if (xc) xc[blockIdx.y * vsc + p] = c0 * sum * dp;
     }
 }
 
@@ -566,8 +640,6 @@ hipError_t launch_dinv_ell(int n, int K, const int *col, const double *val, doub
 // gathers of the neighbours' x (and their aggregates and coarse values).  The stop flag is loaded with the
 // first round and tested after it was issued (the opaque copy keeps the compiler from testing it first,
 // which would put one more memory round trip in front of the loads).
-constexpr int ELL_K8 = 8;
-
 // (No __restrict__ here: with it the compiler may move the row loads past the opaque flag and its test.)
 template <typename T, bool PRO>
 __global__ __launch_bounds__(256) void k_ell_cheb_step8(int n, int K, const int *col, const T *val, const T *b,
@@ -639,12 +711,17 @@ template <typename T>
 __global__ void k_prolong_agg(long long n, const int *__restrict__ agg, T *__restrict__ x, const T *__restrict__ xc,
                               T scale, const Scal *sc, long long vs, long long vsc)
 {
-    if (ell_stopped(sc)) return;
+    // the stop flag guards the stores only (tested before the loads it would cost one more round trip)
+    const bool stop = ell_stopped(sc);
     x += blockIdx.y * vs;
     xc += blockIdx.y * vsc;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const int a = agg[i];
-        if (a >= 0) x[i] += scale * xc[a];
+        const T xv = x[i];
+        const T cv = xc[a >= 0 ? a : 0];
+        // (stored unconditionally, unchanged where nothing applies, so that the load of x is not moved
+        // behind the aggregate's)
+        x[i] = a >= 0 && !stop ? xv + scale * cv : xv;
     }
 }
 
@@ -683,10 +760,20 @@ hipError_t launch_ell_cheb_step(int n, int K, const int *col, const T *val, cons
 template <typename T>
 hipError_t launch_restrict_members(const FineLevelT<T> &f, long long nrows, const T *b, const T *x, int nc,
                                    const int *mptr, const int *mem, T *bc, const Scal *sc, const Batch &bt,
-                                   hipStream_t s, T *xc, const T *dinv_c, T c0)
+                                   hipStream_t s, T *xc, const T *dinv_c, T c0, const int *memb)
 {
     if (nc <= 0 || nrows <= 0) return hipSuccess;
     if (xc && !dinv_c) return hipErrorInvalidValue;
+    const long long nt = (long long)nc * RLANES, nbk = (nt + 255) / 256;
+    if (memb && sc && nbk <= 65536 && (f.w || f.K == ELL_K8)) {
+        if (f.w)
+            SPFD_LAUNCH((k_restrict8<T, false>), dim3((unsigned)nbk, bt.n), dim3(256), 0, s, f, nc, memb, b, x, bc, sc,
+                        bt.vs, bt.vsc, xc, dinv_c, c0);
+        else
+            SPFD_LAUNCH((k_restrict8<T, true>), dim3((unsigned)nbk, bt.n), dim3(256), 0, s, f, nc, memb, b, x, bc, sc,
+                        bt.vs, bt.vsc, xc, dinv_c, c0);
+        return hipGetLastError();
+    }
     SPFD_LAUNCH(k_restrict_rows<T>, dim3(gblocks((long long)nc * RLANES, 256), bt.n), dim3(256), 0, s, f, nc, mptr,
                 mem, b, x, bc, sc, bt.vs, bt.vsc, xc, dinv_c, c0);
     return hipGetLastError();
@@ -710,7 +797,7 @@ hipError_t launch_prolong_agg(long long n, const int *agg, T *x, const T *xc, T 
                                                 const int *, const T *, T);                                         \
     template hipError_t launch_restrict_members<T>(const FineLevelT<T> &, long long, const T *, const T *, int,      \
                                                    const int *, const int *, T *, const Scal *, const Batch &,      \
-                                                   hipStream_t, T *, const T *, T);                                 \
+                                                   hipStream_t, T *, const T *, T, const int *);                    \
     template hipError_t launch_prolong_agg<T>(long long, const int *, T *, const T *, T, const Scal *,             \
                                               const Batch &, hipStream_t);
 SPFD_INST_ELL(double)
