@@ -323,9 +323,12 @@ def adjoint_block(w, lab, a, P, torch):
     def J_of(emag):
         return torch.linalg.vector_norm(emag.reshape(-1), ord=8)
 
-    p0, _ = s.solve(a, tol=tol)                           # warm-up (graph capture)
-    J_of(s.efield(a, p0, w.omega))                        # warm-up (the first torch reduction loads its kernel)
-    del p0
+    # warm-up of the whole timed block (graph capture; the first torch reduction and power load their kernels)
+    p0, _ = s.solve(a, tol=tol)
+    e0 = s.efield(a, p0, w.omega)
+    J0 = J_of(e0)
+    _ = (e0 / J0) ** 7
+    del p0, e0, J0, _
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     psi, info = s.solve(a, tol=tol)
