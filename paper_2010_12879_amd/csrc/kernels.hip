@@ -1001,9 +1001,13 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
     case FIN_RESID0:
         sc->rr = a;
         if (a <= sc->tol2) sc->done = 1;
+        sc->pad = 0;   // (a pending x update is applied before any true residual)
         break;
     case FIN_RESID1:
         sc->zq = a;
+        // the pending update was applied (k_x_final): a later pass must not apply it again to a right
+        // side that is not restarted
+        sc->pad = 0;
         break;
     case FIN_MEAN:
         means[comp] = counts[comp] > 0 ? a / (double)counts[comp] : 0.0;

@@ -69,33 +69,46 @@ __device__ __forceinline__ void tile_mul(const double *a, const double *b, doubl
 // P = A_kk^-1 by Gauss-Jordan: for pivot p with a = A_pp,
 // A_pp <- 1/a, A_pj <- A_pj / a, A_ip <- -A_ip / a, A_ij <- A_ij - A_ip A_pj / a.
 // 1024 threads hold four entries each in registers (row i = t/16, columns
-// 4 (t%16) .. +3); per pivot only row p and column p pass through LDS.
+// 4 (t%16) .. +3); per pivot only row p (with 1/a, formed once by its owner) and
+// column p pass through LDS.  They are published for pivot p + 1 by the threads
+// that hold them right after their update of pivot p, into the other of two LDS
+// buffers, so each pivot needs one barrier.
 __global__ __launch_bounds__(1024) void k_gj_diag(int ld, int k0, const double *__restrict__ W, double *__restrict__ P)
 {
-    __shared__ double row[GT], col[GT];
+    __shared__ double row[2][GT + 1], col[2][GT];   // row[.][GT] = 1 / pivot
     const int t = threadIdx.x;
     const int i = t >> 4, j0 = (t & 15) * 4;
     double a[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) a[q] = W[(long long)(k0 + i) * ld + k0 + j0 + q];
-    for (int p = 0; p < GT; ++p) {
-        if (i == p)
+    // publish row and column 0
+    auto publish = [&](int p, int buf) {
+        if (i == p) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) row[j0 + q] = a[q];
+            for (int q = 0; q < 4; ++q) {
+                row[buf][j0 + q] = a[q];
+                if (j0 + q == p) row[buf][GT] = 1.0 / a[q];
+            }
+        }
         if (p >= j0 && p < j0 + 4) {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                if (j0 + q == p) col[i] = a[q];
+                if (j0 + q == p) col[buf][i] = a[q];
         }
-        __syncthreads();
-        const double piv = 1.0 / row[p];
-        const double ci = col[i];
+    };
+    publish(0, 0);
+    __syncthreads();
+    for (int p = 0; p < GT; ++p) {
+        const int cur = p & 1;
+        const double piv = row[cur][GT];
+        const double ci = col[cur][i];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int j = j0 + q;
-            const double rpj = (j == p) ? 1.0 : row[j];
+            const double rpj = (j == p) ? 1.0 : row[cur][j];
             a[q] = (i == p) ? rpj * piv : (j == p ? 0.0 : a[q]) - ci * piv * rpj;
         }
+        if (p + 1 < GT) publish(p + 1, cur ^ 1);
         __syncthreads();
     }
 #pragma unroll
