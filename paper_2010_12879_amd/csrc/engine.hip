@@ -1335,6 +1335,10 @@ void pcg_begin(Ctx *c, Scal *sc, int nb)
     finish(c, topo_count(topo), FIN_BETA0, sc, 0, nb, nullptr, ROWS_BRICKS);
 }
 
+// CG step `it`: for it >= 1 first z = B r (the cycle, which also forms z.r and, for the flexible beta,
+// z.q) and beta; then p = z + beta p, the deferred x update and q = A p, alpha, and the residual update
+// with its norm, which decides the stop.  The step ends at the stop decision, so the step that converges
+// leaves no cycle behind it (step 0's cycle and beta are formed by pcg_begin).
 template <typename T>
 void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
 {
@@ -1349,6 +1353,29 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
     // an FP32 cycle reads an FP32 copy of the residual, written by the update kernel
     float *r32 = sizeof(T) == sizeof(float) ? c->d_r32 : nullptr;
     double *pbuf[2] = {c->d_p, c->d_p2};
+    if (it > 0) {
+        const bool flex = c->cg_flexible;
+        const int bmode = flex ? FIN_BETA : FIN_BETA_STD;
+        CycleDots dots{flex ? c->d_q : nullptr, c->d_part};
+        bool fused = false;
+        if (c->np) {
+            if (r32)
+                vcycle<T, float>(c, r32, z, nullptr, 1, nullptr);
+            else
+                vcycle<T, double>(c, c->d_r, z, nullptr, 1, nullptr);
+        } else {
+            fused = r32 ? vcycle<T, float>(c, r32, z, sc, nb, &dots) : vcycle<T, double>(c, c->d_r, z, sc, nb, &dots);
+        }
+        if (fused) {
+            finish(c, cheb_dot_parts<T>(topo.nb), bmode, sc, 0, nb);
+        } else {
+            {
+                TScope ts(c, SPFD_K_DOTS, n0 * (wz + (flex ? 16.0 : 8.0)));
+                HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, flex ? 0 : 1, bt, c->stream));
+            }
+            finish(c, nmax, bmode, sc, 0, nb, nullptr, ROWS_BRICKS);
+        }
+    }
     // p_k = z_k + beta p_{k-1}, x_k = x_{k-1} + alpha p_{k-1}, q_k = A p_k
     const int par = it & 1;
     {
@@ -1361,29 +1388,7 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
         TScope ts(c, SPFD_K_UPDATE, n0 * (24.0 + (r32 ? 4.0 : 0.0)));
         HIPCHK(launch_rupdate(topo, c->d_r, c->d_q, c->d_part, sc, bt, r32, c->stream));
     }
-    finish(c, nmax, FIN_RR, sc, max_iter, nb, nullptr, ROWS_BRICKS);
-    // z = B r, with the dot products z.r (and z.q for the flexible beta) formed by the cycle's last step
-    const bool flex = c->cg_flexible;
-    const int bmode = flex ? FIN_BETA : FIN_BETA_STD;
-    CycleDots dots{flex ? c->d_q : nullptr, c->d_part};
-    bool fused = false;
-    if (c->np) {
-        if (r32)
-            vcycle<T, float>(c, r32, z, nullptr, 1, nullptr);
-        else
-            vcycle<T, double>(c, c->d_r, z, nullptr, 1, nullptr);
-    } else {
-        fused = r32 ? vcycle<T, float>(c, r32, z, sc, nb, &dots) : vcycle<T, double>(c, c->d_r, z, sc, nb, &dots);
-    }
-    if (fused) {
-        finish(c, cheb_dot_parts<T>(topo.nb), bmode, sc, 0, nb, c->step_mirror);
-        return;
-    }
-    {
-        TScope ts(c, SPFD_K_DOTS, n0 * (wz + (flex ? 16.0 : 8.0)));
-        HIPCHK(launch_dots<T>(topo, z, c->d_r, c->d_q, c->d_part, sc, flex ? 0 : 1, bt, c->stream));
-    }
-    finish(c, nmax, bmode, sc, 0, nb, c->step_mirror, ROWS_BRICKS);
+    finish(c, nmax, FIN_RR, sc, max_iter, nb, c->step_mirror, ROWS_BRICKS);
 }
 
 void pcg_end(Ctx *c, Scal *sc, int nb)

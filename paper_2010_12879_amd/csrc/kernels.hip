@@ -1418,32 +1418,48 @@ hipError_t launch_pack_sigma(const uint8_t *labels, const Grid &g, const ModelBo
 // dense node array from the brick layout: psi = x - mean(component), 0 outside the conductor.  g: the
 // output's grid; gb: the grid of the brick layout (the same, or the packed grid of several models, in
 // which the output's model starts at node layer zoff)
-__global__ void k_psi_out(const double *__restrict__ x, const int *__restrict__ comp, const double *__restrict__ means,
-                          const int *__restrict__ slot_of, Grid g, Grid gb, int zoff, double *psi)
+constexpr int PSI_ROWS = 8;   // node rows per workgroup: the eight y rows of one brick row
+
+__global__ __launch_bounds__(256) void k_psi_out(const double *__restrict__ x, const int *__restrict__ comp,
+                                                 const double *__restrict__ means, const int *__restrict__ slot_of,
+                                                 Grid g, Grid gb, int zoff, double *psi)
 {
-    // one workgroup per node row (j, k): contiguous stores, no 64-bit index division
-    const int row = blockIdx.x;
-    const int j = row % g.Ny, kb = row / g.Ny + zoff;
-    const int *srow = slot_of + gb.Gx * ((j >> 3) + gb.Gy * (kb >> 3));
-    const int off = 8 * (j & 7) + 64 * (kb & 7);
-    double *prow = psi + (long long)row * g.Nx;
+    // workgroup: node rows j0..j0+7 of layer k (contiguous stores, no 64-bit index division).  The eight
+    // rows lie in the same bricks, so one slot lookup per lane serves all of them, and each lane keeps the
+    // eight rows' loads in flight together.  Rows past the grid's end (the last brick row) are loaded, as
+    // they lie inside their bricks, but not stored.
+    const int gy = (g.Ny + PSI_ROWS - 1) / PSI_ROWS;
+    const int jb = blockIdx.x % gy, k = blockIdx.x / gy;
+    const int kb = k + zoff, j0 = jb * PSI_ROWS;
+    const int nr = g.Ny - j0 < PSI_ROWS ? g.Ny - j0 : PSI_ROWS;
+    const int *srow = slot_of + gb.Gx * (jb + gb.Gy * (kb >> 3));
+    double *prow = psi + ((long long)k * g.Ny + j0) * g.Nx;
     for (int i = threadIdx.x; i < g.Nx; i += blockDim.x) {
         const int sl = srow[i >> 3];
-        // both loads issued together (slot 0 stands in outside the bricks), then masked
-        const long long idx = sl >= 0 ? (long long)sl * BS + (i & 7) + off : 0;
-        const int c = comp[idx];
-        const double xv = x[idx];
-        const double m = means[c >= 0 ? c : 0];
-        prow[i] = (sl >= 0 && c >= 0) ? xv - m : 0.0;
+        // slot 0 stands in outside the bricks; the values are masked below
+        const long long base = sl >= 0 ? (long long)sl * BS + (i & 7) + 64 * (kb & 7) : 0;
+        int c[PSI_ROWS];
+        double xv[PSI_ROWS];
+#pragma unroll
+        for (int r = 0; r < PSI_ROWS; ++r) {
+            const long long idx = sl >= 0 ? base + 8 * r : 0;
+            c[r] = comp[idx];
+            xv[r] = x[idx];
+        }
+#pragma unroll
+        for (int r = 0; r < PSI_ROWS; ++r) {
+            const double m = means[c[r] >= 0 ? c[r] : 0];
+            if (r < nr) prow[(long long)r * g.Nx + i] = (sl >= 0 && c[r] >= 0) ? xv[r] - m : 0.0;
+        }
     }
 }
 
 hipError_t launch_psi_out(const double *x, const int *comp, const double *means, const int *slot_of, const Grid &g,
                           double *psi, hipStream_t s, const Grid *gbricks, int zoff)
 {
-    const long long rows = (long long)g.Ny * g.Nz;
-    if (rows <= 0) return hipSuccess;
-    SPFD_LAUNCH(k_psi_out, dim3((unsigned)rows), dim3(256), 0, s, x, comp, means, slot_of, g, gbricks ? *gbricks : g,
+    const long long groups = (long long)((g.Ny + PSI_ROWS - 1) / PSI_ROWS) * g.Nz;
+    if (groups <= 0 || g.Nx <= 0) return hipSuccess;
+    SPFD_LAUNCH(k_psi_out, dim3((unsigned)groups), dim3(256), 0, s, x, comp, means, slot_of, g, gbricks ? *gbricks : g,
                 zoff, psi);
     return hipGetLastError();
 }
