@@ -506,7 +506,8 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("f64 CG, f32 cycle (f16 weights on coarse level 1), f64 coarsest" if head == "mixed"
+        "dtype": ("f64 CG (x, r, q, dots; search direction p stored in f32), f32 cycle (f16 weights on coarse level 1), "
+                  "f64 coarsest" if head == "mixed"
                   else "f64"),
         "data": "synthetic",
         "config": {"workload": f"{w.name}: 2 mm body phantom, {ninfo['n_dofs']} unknowns, 40 tissues, "

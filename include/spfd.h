@@ -66,7 +66,8 @@ enum { SPFD_SMOOTH_CHEBYSHEV = 0, SPFD_SMOOTH_L1_JACOBI = 1, SPFD_SMOOTH_CHEBYSH
  * given).  Zero-initialised options select the defaults. */
 typedef struct {
     int precision;        /* SPFD_FP64 (default) or SPFD_MIXED: FP32 cycle (FP16 weights on its first coarse
-                             level), FP64 outer CG, dots and coarsest solve */
+                             level), FP64 outer CG (x, r, q = A p, dots; the search direction p is stored
+                             in FP32 and q is formed from the stored value) and coarsest solve */
     int cycle;            /* SPFD_CYCLE_V (the only cycle; any other value is rejected) */
     int smooth_degree;    /* Chebyshev degree per pre/post smoothing, default 2, max 4 */
     int coarsest_max;     /* coarsen until the coarsest level has <= this many unknowns, default and max 1024 */

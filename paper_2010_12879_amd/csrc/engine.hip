@@ -1352,7 +1352,8 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
     const double wz = sizeof(T);
     // an FP32 cycle reads an FP32 copy of the residual, written by the update kernel
     float *r32 = sizeof(T) == sizeof(float) ? c->d_r32 : nullptr;
-    double *pbuf[2] = {c->d_p, c->d_p2};
+    // p in the cycle's precision (the FP64 buffers hold it in their first half with an FP32 cycle)
+    T *pbuf[2] = {(T *)c->d_p, (T *)c->d_p2};
     if (it > 0) {
         const bool flex = c->cg_flexible;
         const int bmode = flex ? FIN_BETA : FIN_BETA_STD;
@@ -1379,7 +1380,8 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
     // p_k = z_k + beta p_{k-1}, x_k = x_{k-1} + alpha p_{k-1}, q_k = A p_k
     const int par = it & 1;
     {
-        TScope ts(c, SPFD_K_SPMV, n0 * (wz + (it ? 40.0 : 16.0) + op_bytes<double>(c, 0)));
+        // z, p_{k-1}, x (read and written), p_k in the cycle's precision; q in FP64
+        TScope ts(c, SPFD_K_SPMV, n0 * (wz + (it ? 2.0 * wz + 24.0 : wz + 8.0) + op_bytes<double>(c, 0)));
         HIPCHK(launch_cg_step<T>(op, topo, z, pbuf[par ^ 1], pbuf[par], c->d_x, c->d_q, c->d_part, sc, it == 0, par, bt,
                                  c->stream));
     }
@@ -1395,8 +1397,13 @@ void pcg_end(Ctx *c, Scal *sc, int nb)
 {
     // the update x += alpha p deferred by the last step of each right side
     Level &L0 = c->lv[0];
-    TScope ts(c, SPFD_K_PUPDATE, (double)L0.dofs * (c->np ? 1 : nb) * 24.0);
-    HIPCHK(launch_x_final(cg_topo(c), c->d_x, c->d_p, c->d_p2, sc, cg_batch(c, nb), c->stream));
+    const double wp = c->opt.precision == SPFD_MIXED ? 4.0 : 8.0;
+    TScope ts(c, SPFD_K_PUPDATE, (double)L0.dofs * (c->np ? 1 : nb) * (16.0 + wp));
+    if (c->opt.precision == SPFD_MIXED)
+        HIPCHK(launch_x_final<float>(cg_topo(c), c->d_x, (const float *)c->d_p, (const float *)c->d_p2, sc,
+                                     cg_batch(c, nb), c->stream));
+    else
+        HIPCHK(launch_x_final<double>(cg_topo(c), c->d_x, c->d_p, c->d_p2, sc, cg_batch(c, nb), c->stream));
 }
 
 void pcg_begin_any(Ctx *c, Scal *sc, int nb)

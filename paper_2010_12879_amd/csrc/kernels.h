@@ -174,10 +174,12 @@ hipError_t launch_spmv(const OpArgs<double> &op, Topo topo, const TZ *z, double 
 // number of partial sums launch_cg_step writes per right side (nb: bricks per launch row, topo_count)
 int cg_step_parts(int nb);
 template <typename TZ>
-hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, const double *pin, double *pout,
+hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, const TZ *pin, TZ *pout,
                           double *x, double *q, double *part, Scal *sc, int first, int parity, const Batch &bt,
                           hipStream_t s);
-hipError_t launch_x_final(Topo topo, double *x, const double *pa, const double *pb, const Scal *sc, const Batch &bt,
+// p in the cycle's precision TP, as the CG step stores it
+template <typename TP>
+hipError_t launch_x_final(Topo topo, double *x, const TP *pa, const TP *pb, const Scal *sc, const Batch &bt,
                           hipStream_t s);
 hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, Scal *sc, const Batch &bt, float *r32,
                           hipStream_t s);

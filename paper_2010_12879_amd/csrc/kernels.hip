@@ -1083,8 +1083,9 @@ hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, co
 
 // x += alpha p: the update deferred by the CG step, applied once after the last
 // step of a pass, from the buffer that step wrote (sc->pad: 0 = none pending)
-__global__ __launch_bounds__(NT) void k_x_final(Topo topo, double *__restrict__ x, const double *__restrict__ pa,
-                                                const double *__restrict__ pb, const Scal *sc, long long vs)
+template <typename TP>
+__global__ __launch_bounds__(NT) void k_x_final(Topo topo, double *__restrict__ x, const TP *__restrict__ pa,
+                                                const TP *__restrict__ pb, const Scal *sc, long long vs)
 {
     int loc;
     const int bk = topo_brick(topo, loc);
@@ -1092,18 +1093,23 @@ __global__ __launch_bounds__(NT) void k_x_final(Topo topo, double *__restrict__ 
     sc += blockIdx.y;
     const int pend = sc->pad;
     if (pend == 0) return;
-    const double *p = pend == 1 ? pa : pb;
+    const TP *p = pend == 1 ? pa : pb;
     const long long n = blockIdx.y * vs + (long long)bk * BS + threadIdx.x;
-    x[n] += sc->alpha * p[n];
+    x[n] += sc->alpha * (double)p[n];
 }
 
-hipError_t launch_x_final(Topo topo, double *x, const double *pa, const double *pb, const Scal *sc, const Batch &bt,
+template <typename TP>
+hipError_t launch_x_final(Topo topo, double *x, const TP *pa, const TP *pb, const Scal *sc, const Batch &bt,
                           hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
-    SPFD_LAUNCH(k_x_final, dim3(xcd_grid(topo_count(topo)), bt.n), dim3(NT), 0, s, topo, x, pa, pb, sc, bt.vs);
+    SPFD_LAUNCH(k_x_final<TP>, dim3(xcd_grid(topo_count(topo)), bt.n), dim3(NT), 0, s, topo, x, pa, pb, sc, bt.vs);
     return hipGetLastError();
 }
+template hipError_t launch_x_final<float>(Topo, double *, const float *, const float *, const Scal *, const Batch &,
+                                          hipStream_t);
+template hipError_t launch_x_final<double>(Topo, double *, const double *, const double *, const Scal *,
+                                           const Batch &, hipStream_t);
 
 // r -= alpha q, ||r||^2 partials and the FP32 copy of r (x is updated by the CG step)
 __global__ __launch_bounds__(NT) void k_rupdate(Topo topo, double *__restrict__ r, const double *__restrict__ q,

@@ -740,12 +740,26 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
 // p_k at the neighbours is formed from z and p_{k-1}; pin and pout are
 // different buffers.  The step records in sc->pad which buffer holds the
 // pending p (1 + parity) for the final deferred update.
+//
+// p is kept in the cycle's precision TZ (FP32 with the FP32 cycle): it is formed by one fused
+// multiply-add in TZ wherever it is needed, so every wave forms the same value at a node, and q = A p
+// (FP64 operator and arithmetic) and the later x += alpha p use exactly the stored p.  x and r then stay
+// consistent to FP64 rounding; the rounding of p only perturbs the search directions, by as much as the
+// FP32 cycle already perturbs z.
+template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c);
+template <>
+__device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <>
+__device__ __forceinline__ double fma_t<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename TZ, int ZPL, bool LABEL, bool FIRST>
 __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Topo topo, const TZ *__restrict__ zv,
-                                                          const double *__restrict__ pin, double *__restrict__ pout,
+                                                          const TZ *__restrict__ pin, TZ *__restrict__ pout,
                                                           double *__restrict__ x, double *__restrict__ q,
                                                           double *part, Scal *sc, int parity, long long vs, int ps)
 {
+    constexpr bool WIDE = std::is_same<TZ, double>::value;
     double *lds = col_lds<double, ZPL, LABEL>();
     __shared__ double red[CWAVES];
     const Seg<ZPL> s = make_seg<ZPL>(topo, sc);
@@ -763,42 +777,46 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
         SegOp<double, ZPL, LABEL> A;
         A.load(op, s, lds);
         SegVals<TZ, ZPL> Z;
-        Z.template load<std::is_same<TZ, double>::value>(zv, s);
-        SegVals<double, ZPL> Pi;
+        Z.template load<WIDE>(zv, s);
+        SegVals<TZ, ZPL> Pi;
         double xv[ZPL];
         if constexpr (!FIRST) {
-            Pi.load(pin, s);
+            Pi.template load<WIDE>(pin, s);
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) xv[z] = 0.0;
             if (s.active)
 #pragma unroll
                 for (int z = 0; z < ZPL; ++z) xv[z] = x[s.self + 64 * z];
         }
-        const double beta = FIRST ? 0.0 : sc->beta;
+        const TZ beta = FIRST ? TZ(0) : (TZ)sc->beta;
         const double alpha = FIRST ? 0.0 : sc->alpha;
         // p_k on the segment, the face columns and the z ends
-        SegVals<double, ZPL> P;
+        SegVals<TZ, ZPL> P;
 #pragma unroll
         for (int z = 0; z < ZPL; ++z) {
-            P.c[z] = FIRST ? (double)Z.c[z] : (double)Z.c[z] + beta * Pi.c[z];
-            P.ex[z] = FIRST ? (double)Z.ex[z] : (double)Z.ex[z] + beta * Pi.ex[z];
-            P.ey[z] = FIRST ? (double)Z.ey[z] : (double)Z.ey[z] + beta * Pi.ey[z];
+            P.c[z] = FIRST ? Z.c[z] : fma_t<TZ>(beta, Pi.c[z], Z.c[z]);
+            P.ex[z] = FIRST ? Z.ex[z] : fma_t<TZ>(beta, Pi.ex[z], Z.ex[z]);
+            P.ey[z] = FIRST ? Z.ey[z] : fma_t<TZ>(beta, Pi.ey[z], Z.ey[z]);
         }
-        P.zm = FIRST ? (double)Z.zm : (double)Z.zm + beta * Pi.zm;
-        P.zp = FIRST ? (double)Z.zp : (double)Z.zp + beta * Pi.zp;
+        P.zm = FIRST ? Z.zm : fma_t<TZ>(beta, Pi.zm, Z.zm);
+        P.zp = FIRST ? Z.zp : fma_t<TZ>(beta, Pi.zp, Z.zp);
         A.stage(op, s);
 #pragma unroll
         for (int z = 0; z < ZPL; ++z) {
             double W[6], N[6];
+            TZ Nt[6];
             A.weights(s, z, W);
-            P.nbrs(s, z, N);
-            const double y = stencil_apply(P.c[z], N, W);
+            P.nbrs(s, z, Nt);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) N[k] = (double)Nt[k];
+            const double pc = (double)P.c[z];
+            const double y = stencil_apply(pc, N, W);
             if (s.active) {
                 const long long n = s.self + 64 * z;
-                if constexpr (!FIRST) x[n] = xv[z] + alpha * Pi.c[z];
+                if constexpr (!FIRST) x[n] = xv[z] + alpha * (double)Pi.c[z];
                 pout[n] = P.c[z];
                 q[n] = y;
-                dot += P.c[z] * y;
+                dot += pc * y;
             }
         }
     }
@@ -1045,7 +1063,7 @@ hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, co
 }
 
 template <typename TZ>
-hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, const double *pin, double *pout,
+hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, const TZ *pin, TZ *pout,
                           double *x, double *q, double *part, Scal *sc, int first, int parity, const Batch &bt,
                           hipStream_t s)
 {
@@ -1114,7 +1132,7 @@ SPFD_INST_COL(float, double)
 
 template hipError_t launch_cg_step<double>(const OpArgs<double> &, Topo, const double *, const double *, double *,
                                            double *, double *, double *, Scal *, int, int, const Batch &, hipStream_t);
-template hipError_t launch_cg_step<float>(const OpArgs<double> &, Topo, const float *, const double *, double *,
+template hipError_t launch_cg_step<float>(const OpArgs<double> &, Topo, const float *, const float *, float *,
                                           double *, double *, double *, Scal *, int, int, const Batch &, hipStream_t);
 
 }  // namespace spfd
