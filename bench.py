@@ -25,14 +25,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # finest-level kernel classes timed with events (one sampled CG iteration per solve);
 # the dominant one (largest estimated share of the solve) carries the roofline figure
-FINE_CLASSES = {0: "k_col_cg_step (outer CG: p, deferred x, q = A p, p.q)",
-                1: "k_rupdate (r -= alpha q, ||r||^2, FP32 copy of r)",
+FINE_CLASSES = {0: "k_col_cg_step (outer CG: p, deferred x, p.Ap)",
+                1: "k_col_rupdate (r -= alpha A p, A p formed again; ||r||^2, FP32 copy of r)",
                 2: "k_col_cheb_step + CG dot z.r (last post-smoothing step)",
                 4: "k_col_cheb_first2 (first two Chebyshev steps, the pre-smoothing)",
                 6: "k_col_resid_restrict (residual + restriction)",
                 7: "k_col_cheb_step + prolongation (first post-smoothing step)"}
 # rocprofv3 summaries under profiles/ (HBM bytes per launch from FETCH_SIZE / WRITE_SIZE)
-PROFILE_OF = {0: "k_col_cg_step", 1: "k_rupdate", 2: "k_col_cheb_step_dots", 4: "k_col_cheb_first2",
+PROFILE_OF = {0: "k_col_cg_step", 1: "k_col_rupdate", 2: "k_col_cheb_step_dots", 4: "k_col_cheb_first2",
               6: "k_col_resid_restrict", 7: "k_col_cheb_step_prolong"}
 KERNEL_SOURCES = ["paper_2010_12879_amd/csrc/kernels_col.hip", "paper_2010_12879_amd/csrc/kernels.hip",
                   "paper_2010_12879_amd/csrc/common.h", "paper_2010_12879_amd/csrc/kernels.h"]

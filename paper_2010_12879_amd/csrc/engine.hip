@@ -1377,20 +1377,32 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
             finish(c, nmax, bmode, sc, 0, nb, nullptr, ROWS_BRICKS);
         }
     }
-    // p_k = z_k + beta p_{k-1}, x_k = x_{k-1} + alpha p_{k-1}, q_k = A p_k
+    // p_k = z_k + beta p_{k-1}, x_k = x_{k-1} + alpha p_{k-1}, q_k = A p_k.  Only the flexible beta reads
+    // q_k later (z.q); with the standard beta the residual update forms A p_k again from p_k instead.
+    const bool keep_q = c->cg_flexible;
     const int par = it & 1;
     {
         // z, p_{k-1}, x (read and written), p_k in the cycle's precision; q in FP64
-        TScope ts(c, SPFD_K_SPMV, n0 * (wz + (it ? 2.0 * wz + 24.0 : wz + 8.0) + op_bytes<double>(c, 0)));
-        HIPCHK(launch_cg_step<T>(op, topo, z, pbuf[par ^ 1], pbuf[par], c->d_x, c->d_q, c->d_part, sc, it == 0, par, bt,
-                                 c->stream));
+        TScope ts(c, SPFD_K_SPMV,
+                  n0 * (wz + (it ? 2.0 * wz + 16.0 : wz) + (keep_q ? 8.0 : 0.0) + op_bytes<double>(c, 0)));
+        HIPCHK(launch_cg_step<T>(op, topo, z, pbuf[par ^ 1], pbuf[par], c->d_x, keep_q ? c->d_q : nullptr, c->d_part,
+                                 sc, it == 0, par, bt, c->stream));
     }
     finish(c, cg_step_parts(nmax), FIN_ALPHA, sc, 0, nb, nullptr, ROWS_CG_GROUPS);
-    {
-        TScope ts(c, SPFD_K_UPDATE, n0 * (24.0 + (r32 ? 4.0 : 0.0)));
-        HIPCHK(launch_rupdate(topo, c->d_r, c->d_q, c->d_part, sc, bt, r32, c->stream));
+    if (keep_q) {
+        {
+            TScope ts(c, SPFD_K_UPDATE, n0 * (24.0 + (r32 ? 4.0 : 0.0)));
+            HIPCHK(launch_rupdate(topo, c->d_r, c->d_q, c->d_part, sc, bt, r32, c->stream));
+        }
+        finish(c, nmax, FIN_RR, sc, max_iter, nb, c->step_mirror, ROWS_BRICKS);
+    } else {
+        {
+            // r (read and written), p_k and the operator; the FP32 copy of r
+            TScope ts(c, SPFD_K_UPDATE, n0 * (16.0 + wz + op_bytes<double>(c, 0) + (r32 ? 4.0 : 0.0)));
+            HIPCHK(launch_col_rupdate<T>(op, topo, pbuf[par], c->d_r, r32, c->d_part, sc, bt, c->stream));
+        }
+        finish(c, cg_step_parts(nmax), FIN_RR, sc, max_iter, nb, c->step_mirror, ROWS_CG_GROUPS);
     }
-    finish(c, nmax, FIN_RR, sc, max_iter, nb, c->step_mirror, ROWS_BRICKS);
 }
 
 void pcg_end(Ctx *c, Scal *sc, int nb)

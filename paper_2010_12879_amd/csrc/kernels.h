@@ -183,6 +183,11 @@ hipError_t launch_x_final(Topo topo, double *x, const TP *pa, const TP *pb, cons
                           hipStream_t s);
 hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, Scal *sc, const Batch &bt, float *r32,
                           hipStream_t s);
+// r -= alpha A p with A p formed again from the stored p (the CG step then stores no q), ||r||^2 partials
+// (cg_step_parts(nb) per right side) and the FP32 copy of r (r32 nullable)
+template <typename TZ>
+hipError_t launch_col_rupdate(const OpArgs<double> &op, Topo topo, const TZ *p, double *r, float *r32, double *part,
+                              const Scal *sc, const Batch &bt, hipStream_t s);
 // r = b - A x (r nullable) and the partials of ||r||^2 (cg_step_parts(nb) per right side).  b has its own
 // batch stride bvs (the right sides may live apart from the solve vectors).
 hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,

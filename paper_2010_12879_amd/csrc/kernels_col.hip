@@ -733,10 +733,12 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
 }
 
 // ---------------------------------------------------------------- outer CG step
-// Fused flexible-CG step with the x update deferred by one step:
+// Fused CG step with the x update deferred by one step:
 //   x_k = x_{k-1} + alpha_{k-1} p_{k-1}   (skipped on the first step)
 //   p_k = z_k + beta_{k-1} p_{k-1}        (p_k = z_k on the first step)
 //   q_k = A p_k and the partials of p_k.q_k (one per workgroup)
+// q_k is stored only where a later kernel reads it (q == nullptr: not
+// stored; the residual update then forms A p_k again, k_col_rupdate).
 // p_k at the neighbours is formed from z and p_{k-1}; pin and pout are
 // different buffers.  The step records in sc->pad which buffer holds the
 // pending p (1 + parity) for the final deferred update.
@@ -770,7 +772,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
     pin += blockIdx.y * vs;
     pout += blockIdx.y * vs;
     x += blockIdx.y * vs;
-    q += blockIdx.y * vs;
+    if (q) q += blockIdx.y * vs;
     part += (long long)blockIdx.y * ps;
     double dot = 0.0;
     if (s.bk >= 0) {
@@ -815,7 +817,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
                 const long long n = s.self + 64 * z;
                 if constexpr (!FIRST) x[n] = xv[z] + alpha * (double)Pi.c[z];
                 pout[n] = P.c[z];
-                q[n] = y;
+                if (q) q[n] = y;
                 dot += pc * y;
             }
         }
@@ -829,6 +831,69 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
 #pragma unroll
         for (int w = 0; w < CWAVES; ++w) t += red[w];
         part[s.grp] = t;
+    }
+}
+
+// ---------------------------------------------------------------- residual update
+// r_{k+1} = r_k - alpha_k A p_k, the partials of ||r_{k+1}||^2 (one per
+// workgroup, as in the CG step) and the FP32 copy of r (r32 nullable).  A p_k
+// is formed again from the stored p_k with the CG step's operator, segment
+// and order of operations, so it equals the q_k that step formed for p.q bit
+// for bit; reading p_k in the cycle's precision and the labels costs fewer
+// bytes than storing q_k in FP64 and reading it back.
+template <typename TZ, int ZPL, bool LABEL>
+__global__ __launch_bounds__(CTHREADS) void k_col_rupdate(OpArgs<double> op, Topo topo, const TZ *__restrict__ pv,
+                                                          double *__restrict__ r, float *__restrict__ r32,
+                                                          double *part, const Scal *sc, long long vs, int ps)
+{
+    constexpr bool WIDE = std::is_same<TZ, double>::value;
+    double *lds = col_lds<double, ZPL, LABEL>();
+    __shared__ double red[CWAVES];
+    const Seg<ZPL> s = make_seg<ZPL>(topo, sc);
+    if (s.grp < 0 || s.stop) return;
+    const double alpha = sc[blockIdx.y].alpha;
+    pv += blockIdx.y * vs;
+    r += blockIdx.y * vs;
+    if (r32) r32 += blockIdx.y * vs;
+    double rr = 0.0;
+    if (s.bk >= 0) {
+        SegOp<double, ZPL, LABEL> A;
+        A.load(op, s, lds);
+        SegVals<TZ, ZPL> P;
+        P.template load<WIDE>(pv, s);
+        double rv[ZPL];
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) rv[z] = 0.0;
+        if (s.active)
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) rv[z] = r[s.self + 64 * z];
+        A.stage(op, s);
+#pragma unroll
+        for (int z = 0; z < ZPL; ++z) {
+            double W[6], N[6];
+            TZ Nt[6];
+            A.weights(s, z, W);
+            P.nbrs(s, z, Nt);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) N[k] = (double)Nt[k];
+            const double y = stencil_apply((double)P.c[z], N, W);
+            if (s.active) {
+                const long long n = s.self + 64 * z;
+                const double rn = rv[z] - alpha * y;
+                r[n] = rn;
+                if (r32) r32[n] = (float)rn;
+                rr += rn * rn;
+            }
+        }
+    }
+    rr = wave_sum(rr);
+    if (s.lane == 0) red[threadIdx.x >> 6] = rr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < CWAVES; ++w) t += red[w];
+        part[(long long)blockIdx.y * ps + s.grp] = t;
     }
 }
 
@@ -1083,6 +1148,26 @@ hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, cons
 #undef SPFD_CG
     return hipGetLastError();
 }
+
+template <typename TZ>
+hipError_t launch_col_rupdate(const OpArgs<double> &op, Topo topo, const TZ *p, double *r, float *r32, double *part,
+                              const Scal *sc, const Batch &bt, hipStream_t s)
+{
+    if (topo.nb <= 0) return hipSuccess;
+    if (!col_args_ok(topo, sc)) return hipErrorInvalidValue;
+    const dim3 g = col_grid<ZPL_CG>(topo_count(topo), bt.n);
+    if (op.w)
+        SPFD_LAUNCH((k_col_rupdate<TZ, ZPL_CG, false>), g, dim3(CTHREADS), 0, s, op, topo, p, r, r32, part, sc, bt.vs,
+                    bt.ps);
+    else
+        SPFD_LAUNCH((k_col_rupdate<TZ, ZPL_CG, true>), g, dim3(CTHREADS), 0, s, op, topo, p, r, r32, part, sc, bt.vs,
+                    bt.ps);
+    return hipGetLastError();
+}
+template hipError_t launch_col_rupdate<double>(const OpArgs<double> &, Topo, const double *, double *, float *,
+                                               double *, const Scal *, const Batch &, hipStream_t);
+template hipError_t launch_col_rupdate<float>(const OpArgs<double> &, Topo, const float *, double *, float *,
+                                              double *, const Scal *, const Batch &, hipStream_t);
 
 hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,
                         double *part, long long bvs, const Batch &bt, hipStream_t s)
