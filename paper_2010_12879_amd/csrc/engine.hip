@@ -583,9 +583,11 @@ struct CycleDots {
     double *part = nullptr;
 };
 
+// dmode (structured levels): where the step takes the previous update from (CHEB_D_*); the ELL levels
+// always use din / dout
 template <typename T, typename TB>
 void cheb_step(Ctx *c, int l, const TB *b, const T *xin, T *xout, const T *din, T *dout, T c1, T c2, const Scal *sc,
-               int nb, bool with_prolong = false, const CycleDots *dots = nullptr)
+               int nb, bool with_prolong = false, const CycleDots *dots = nullptr, int dmode = CHEB_D_AUTO)
 {
     Level &L = c->lv[l];
     const Batch bt = level_batch(c, l, nb);
@@ -597,16 +599,17 @@ void cheb_step(Ctx *c, int l, const TB *b, const T *xin, T *xout, const T *din, 
                                        pro ? (const T *)c->lv[l + 1].x : nullptr, (T)c->opt.coarse_scale));
         return;
     }
-    double per = sizeof(TB) + op_bytes<T>(c, l) + sizeof(T) * (2 + (din ? 1 : 0) + (dout ? 1 : 0));
-    if (with_prolong) per += sizeof(T) / 8.0;
+    const bool prev = dmode == CHEB_D_PREV || dmode == CHEB_D_PREV_PRO;
+    double per = sizeof(TB) + op_bytes<T>(c, l) + sizeof(T) * (2 + (din || prev ? 1 : 0) + (dout ? 1 : 0));
+    if (with_prolong || dmode == CHEB_D_PREV_PRO) per += sizeof(T) / 8.0;
     if (dots && dots->q) per += 8.0;
     const int cls = l == 0 ? (with_prolong ? SPFD_K_PROLONG0 : dots ? SPFD_K_DOTS : SPFD_K_SMOOTH0) : SPFD_K_COARSE;
     TScope ts(c, cls, nb * (double)L.dofs * per);
     const T *xc = nullptr;
-    if (with_prolong) xc = (const T *)c->lv[l + 1].x;
+    if (with_prolong || dmode == CHEB_D_PREV_PRO) xc = (const T *)c->lv[l + 1].x;
     HIPCHK(launch_cheb_step<T, TB>(level_op<T>(c, l), L.topo(), b, xin, xout, din, dout, c1, c2, sc, bt, c->stream, xc,
                                    L.d_parent_slot, L.d_coord, (T)c->opt.coarse_scale, dots ? dots->q : nullptr,
-                                   dots ? dots->part : nullptr));
+                                   dots ? dots->part : nullptr, dmode));
 }
 
 // Chebyshev degree of level l (any degree keeps the buffer parity of the
@@ -637,9 +640,19 @@ void smooth_pre(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc, 
     } else if (!first_done) {
         cheb_first<T, TB>(c, l, b, cur, sc, nb);
     }
+    // On the structured levels no step stores its update d: the buffer a step writes holds the iterate
+    // before its input (ping-pong), from which the step forms d itself.  The first two finest steps in one
+    // pass never store x1, so they store d for the third step (degree > 2).
+    const bool ell = c->lv[l].ell;
     for (int k = k0; k < m; ++k) {
-        cheb_step<T, TB>(c, l, b, cur, other, k == 1 ? nullptr : d, k < m - 1 ? d : nullptr, (T)c->cheb_c1[k],
-                         (T)c->cheb_c2[k], sc, nb);
+        if (ell) {
+            cheb_step<T, TB>(c, l, b, cur, other, k == 1 ? nullptr : d, k < m - 1 ? d : nullptr, (T)c->cheb_c1[k],
+                             (T)c->cheb_c2[k], sc, nb);
+        } else {
+            const int dm = k == 1 ? CHEB_D_FROM_X : (k0 == 2 && k == 2 ? CHEB_D_STORED : CHEB_D_PREV);
+            cheb_step<T, TB>(c, l, b, cur, other, dm == CHEB_D_STORED ? d : nullptr, nullptr, (T)c->cheb_c1[k],
+                             (T)c->cheb_c2[k], sc, nb, false, nullptr, dm);
+        }
         T *t = cur; cur = other; other = t;
     }
 }
@@ -650,11 +663,20 @@ void smooth_post(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc,
 {
     const int m = level_degree(c, l);
     T *d = (T *)c->lv[l].d;
+    const bool ell = c->lv[l].ell;
     for (int k = 0; k < m; ++k) {
         const T c1 = k == 0 ? T(0) : (T)c->cheb_c1[k];
         const T c2 = k == 0 ? (T)c->cheb_c0 : (T)c->cheb_c2[k];
-        cheb_step<T, TB>(c, l, b, cur, other, k == 0 ? nullptr : d, k < m - 1 ? d : nullptr, c1, c2, sc, nb,
-                         with_prolong && k == 0, k == m - 1 ? dots : nullptr);
+        if (ell) {
+            cheb_step<T, TB>(c, l, b, cur, other, k == 0 ? nullptr : d, k < m - 1 ? d : nullptr, c1, c2, sc, nb,
+                             with_prolong && k == 0, k == m - 1 ? dots : nullptr);
+        } else {
+            // the first step needs no d (c1 = 0); the second finds the pre-smoothed iterate in its output
+            // buffer, without the coarse-grid correction if the first step applied it on the fly
+            const int dm = k == 0 ? CHEB_D_FROM_X : (k == 1 && with_prolong ? CHEB_D_PREV_PRO : CHEB_D_PREV);
+            cheb_step<T, TB>(c, l, b, cur, other, nullptr, nullptr, c1, c2, sc, nb, with_prolong && k == 0,
+                             k == m - 1 ? dots : nullptr, dm);
+        }
         T *t = cur; cur = other; other = t;
     }
 }

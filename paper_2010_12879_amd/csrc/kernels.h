@@ -207,7 +207,12 @@ hipError_t launch_cheb_first(const OpArgs<T> &op, Topo topo, const TB *b, T *x, 
 template <typename T, typename TB>
 hipError_t launch_cheb_first2(const OpArgs<T> &op, Topo topo, const TB *b, const T *dinv, T *xout, T *dout, T c0,
                               T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s);
-// xc != nullptr: xin is first corrected by pscale * P xc from the structured
+// Where a Chebyshev step takes the previous update d_old = x_k - x_{k-1} from: AUTO (din if given, else
+// FROM_X), FROM_X (d_old = xin: right after a zero start, or unused with c1 = 0), STORED (din), PREV (xin minus
+// x_{k-1}, which the output buffer holds before the step overwrites it), PREV_PRO (as PREV, x_{k-1} first
+// corrected by pscale * P xc: the previous step applied that correction on the fly)
+enum { CHEB_D_AUTO = -1, CHEB_D_FROM_X = 0, CHEB_D_STORED = 1, CHEB_D_PREV = 2, CHEB_D_PREV_PRO = 3 };
+// xc != nullptr (dmode other than PREV_PRO): xin is first corrected by pscale * P xc from the structured
 // coarser level (parent_slot / fcoord of this level), i.e. the prolongation
 // fused into the step.  dot_part != nullptr: the step also writes the
 // partials of xout.b (dot_part[g]) and xout.dot_q (dot_part[n + g]),
@@ -216,7 +221,8 @@ template <typename T, typename TB>
 hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din,
                             T *dout, T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s,
                             const T *xc = nullptr, const int *parent_slot = nullptr, const int4 *fcoord = nullptr,
-                            T pscale = T(0), const double *dot_q = nullptr, double *dot_part = nullptr);
+                            T pscale = T(0), const double *dot_q = nullptr, double *dot_part = nullptr,
+                            int dmode = CHEB_D_AUTO);
 template <typename T>
 int cheb_dot_parts(int nb);
 // xc != nullptr: also the coarse level's first Chebyshev step, xc = c0 dinv_c bc

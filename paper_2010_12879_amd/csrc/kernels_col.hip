@@ -567,17 +567,27 @@ struct Dots {
     int nparts;
 };
 
-// general step: r = b - A xin; d = c1 d_old + c2 D^-1 r; xout = xin + d
-// (d_old = xin when din == nullptr, i.e. right after a zero start).  With PRO,
-// xin is first corrected from the coarser level (the prolongation of the
-// upward leg, fused into the first post-smoothing step); with DOT the step
-// also forms the CG dot products of its output with b (the residual the
+// general step: r = b - A xin; d = c1 d_old + c2 D^-1 r; xout = xin + d.
+// d_old, the previous step's update x_k - x_{k-1} (dmode, CHEB_D_*):
+//   FROM_X   d_old = xin (right after a zero start, or unused when c1 = 0);
+//   STORED   read from din;
+//   PREV     xin - x_{k-1}, with x_{k-1} read from xout before it is
+//            overwritten: the ping-pong buffer the step writes holds the
+//            iterate before xin, so no d has to be stored (4 bytes per node
+//            written and read less);
+//   PREV_PRO as PREV where the previous step applied the coarse-grid
+//            correction to its input on the fly: x_{k-1} in xout lacks it,
+//            so it is applied again here (pr, own column only).
+// With PRO, xin is first corrected from the coarser level (the prolongation
+// of the upward leg, fused into the first post-smoothing step); with DOT the
+// step also forms the CG dot products of its output with b (the residual the
 // cycle was given, as the cycle reads it) and with q.
 template <typename T, typename TB, int ZPL, bool LABEL, bool PRO, bool DOT>
 __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
                                                             const T *__restrict__ xin, T *__restrict__ xout,
                                                             const T *__restrict__ din, T *__restrict__ dout, T c1,
-                                                            T c2, const Scal *sc, long long vs, Prolong pr, Dots dt)
+                                                            T c2, const Scal *sc, long long vs, Prolong pr, Dots dt,
+                                                            int dmode)
 {
     T *lds = col_lds<T, ZPL, LABEL>();
     __shared__ double red[2][CWAVES];
@@ -596,17 +606,29 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo t
         X.load(xin, s);
         // (loaded by every lane, used only where the column holds unknowns)
         TB braw[ZPL];
-        T dv[ZPL];
+        T dv[ZPL], xprev[ZPL];
         double qv[DOT ? ZPL : 1];
 #pragma unroll
-        for (int z = 0; z < ZPL; ++z) braw[z] = dv[z] = 0;
+        for (int z = 0; z < ZPL; ++z) braw[z] = dv[z] = xprev[z] = 0;
         if (s.active || !std::is_same<T, TB>::value) {
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) braw[z] = b[s.self + 64 * z];
         }
-        if (din && s.active) {
+        if (dmode == CHEB_D_STORED && s.active) {
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) dv[z] = din[s.self + 64 * z];
+        }
+        if (dmode >= CHEB_D_PREV && s.active) {
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) xprev[z] = xout[s.self + 64 * z];
+        }
+        // PREV_PRO: the correction of the own column, as apply_prolong forms it (every lane loads from a valid slot)
+        T vpro[ZPL / 2];
+        if (dmode == CHEB_D_PREV_PRO) {
+            const T *xc = (const T *)pr.xc + blockIdx.y * pr.vsc;
+            const long long cs = coarse_slot(pr, s.bk, s.tx, s.ty, s.z0);
+#pragma unroll
+            for (int h = 0; h < ZPL / 2; ++h) vpro[h] = xc[cs + 64 * h];
         }
         if constexpr (DOT) {
             // z.q only for the flexible beta (q == nullptr: partials of 0)
@@ -622,9 +644,20 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo t
 #pragma unroll
         for (int z = 0; z < ZPL; ++z) bv[z] = (T)braw[z];
         if constexpr (PRO) apply_prolong(pr, topo, s, X);
-        if (!din) {
+        if (dmode == CHEB_D_FROM_X) {
 #pragma unroll
             for (int z = 0; z < ZPL; ++z) dv[z] = X.c[z];
+        } else if (dmode == CHEB_D_PREV_PRO) {
+            const T ps = (T)pr.scale;
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) {
+                T xp = xprev[z];
+                xp += ps * vpro[z >> 1];
+                dv[z] = X.c[z] - xp;
+            }
+        } else if (dmode == CHEB_D_PREV) {
+#pragma unroll
+            for (int z = 0; z < ZPL; ++z) dv[z] = X.c[z] - xprev[z];
         }
         A.stage(op, s);
 #pragma unroll
@@ -1048,32 +1081,39 @@ hipError_t launch_cheb_first2(const OpArgs<T> &op, Topo topo, const TB *b, const
 
 template <typename T, typename TB, int ZPL, bool LAB, bool PRO, bool DOT>
 static void cheb_step_z(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din, T *dout,
-                        T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s, const Prolong &pr, Dots dt)
+                        T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s, const Prolong &pr, Dots dt,
+                        int dmode)
 {
     dt.nparts = col_ngroups<ZPL>(topo_count(topo));
     SPFD_LAUNCH((k_col_cheb_step<T, TB, ZPL, LAB, PRO, DOT>), col_grid<ZPL>(topo_count(topo), bt.n), dim3(CTHREADS), 0, s, op,
-                topo, b, xin, xout, din, dout, c1, c2, sc, bt.vs, pr, dt);
+                topo, b, xin, xout, din, dout, c1, c2, sc, bt.vs, pr, dt, dmode);
 }
 
 template <typename T, typename TB>
 hipError_t launch_cheb_step(const OpArgs<T> &op, Topo topo, const TB *b, const T *xin, T *xout, const T *din, T *dout,
                             T c1, T c2, const Scal *sc, const Batch &bt, hipStream_t s, const T *xc,
                             const int *parent_slot, const int4 *fcoord, T pscale, const double *dot_q,
-                            double *dot_part)
+                            double *dot_part, int dmode)
 {
     if (topo.nb <= 0) return hipSuccess;
     if (!col_args_ok(topo, sc)) return hipErrorInvalidValue;
     if (xin == xout) return hipErrorInvalidValue;
     if (xc && !(parent_slot && fcoord)) return hipErrorInvalidValue;
+    // the legacy selection by din; the previous iterate in xout (xc: the correction to apply to it)
+    if (dmode == CHEB_D_AUTO) dmode = din ? CHEB_D_STORED : CHEB_D_FROM_X;
+    if (dmode < CHEB_D_FROM_X || dmode > CHEB_D_PREV_PRO) return hipErrorInvalidValue;
+    if (dmode == CHEB_D_STORED && !din) return hipErrorInvalidValue;
+    if (dmode == CHEB_D_PREV_PRO && !xc) return hipErrorInvalidValue;
     constexpr int Z = zpl_cycle<T>();
     const Prolong pr{xc, parent_slot, fcoord, (double)pscale, bt.vsc};
     const Dots dt{dot_q, dot_part, bt.ps, 0};
     // the dot-product partials are counted by cheb_dot_parts (segment length Z)
     const bool small = op.w && !dot_part && topo.nb < op.short_below;
-    const int sel = (small ? 8 : 0) | (op.w ? 0 : 4) | (xc ? 2 : 0) | (dot_part ? 1 : 0);
+    const bool pro = xc && dmode != CHEB_D_PREV_PRO;
+    const int sel = (small ? 8 : 0) | (op.w ? 0 : 4) | (pro ? 2 : 0) | (dot_part ? 1 : 0);
 #define SPFD_CHEB_CASE(K, ZZ, LAB, PRO, DOT)                                                                          \
     case K:                                                                                                           \
-        cheb_step_z<T, TB, ZZ, LAB, PRO, DOT>(op, topo, b, xin, xout, din, dout, c1, c2, sc, bt, s, pr, dt);         \
+        cheb_step_z<T, TB, ZZ, LAB, PRO, DOT>(op, topo, b, xin, xout, din, dout, c1, c2, sc, bt, s, pr, dt, dmode);  \
         break;
     switch (sel) {
         SPFD_CHEB_CASE(0, Z, false, false, false)
@@ -1207,7 +1247,7 @@ template hipError_t launch_spmv<float>(const OpArgs<double> &, Topo, const float
                                                   const Scal *, const Batch &, hipStream_t);                        \
     template hipError_t launch_cheb_step<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *, const T *, T *, \
                                                 T, T, const Scal *, const Batch &, hipStream_t, const T *,          \
-                                                const int *, const int4 *, T, const double *, double *);             \
+                                                const int *, const int4 *, T, const double *, double *, int);        \
     template hipError_t launch_resid_restrict<T, TB>(const OpArgs<T> &, Topo, const TB *, const T *, T *,           \
                                                      const int *, const int4 *, const Scal *, const Batch &,        \
                                                      hipStream_t, T *, const T *, T);
