@@ -167,6 +167,7 @@ struct Ctx {
     StepGraph *capturing = nullptr;
     int step_ctx = 0;   // 0: outside the CG loop, 1: in an untimed CG step, 2: in the sampled step
     bool r32_ready = false;   // d_r32 holds the FP32 copy of the residual the next CG start reads
+    bool bscale0 = false;     // the running cycle's finest-level right side is held as D^-1 b (OpArgs::bscale)
     // per-class launch timing (tracing aid); cold: a flush of d_flush before every timed launch
     unsigned tmask = 0;
     bool tcold = false;
@@ -512,6 +513,7 @@ OpArgs<float> level_op<float>(Ctx *c, int l)
         op.table = c->d_table32;
         op.nlab = c->nlab;
         for (int d = 0; d < 3; ++d) op.geo4[d] = (float)c->geo4[d];
+        op.bscale = c->bscale0 ? 1 : 0;
     } else {
         op.w = L.d_w32;
         if (l == 1 && L.d_w16) {
@@ -531,6 +533,15 @@ double op_bytes(Ctx *c, int l)
     if (l == 0 && !c->voxel_mode) return 1.0;
     if (sizeof(T) == sizeof(float) && l == 1 && c->lv[1].d_w16) return 3.0 * sizeof(uint16_t);
     return 3.0 * sizeof(T);
+}
+
+// The FP32 copy of the outer residual that an FP32 cycle reads is held as D^-1 r where the finest level is
+// in label form and the cycle has more than one level: its first two smoothing steps then read no inverse
+// diagonal (the kernels form D r where they need r).  Written so by the solve start and the residual update
+// of the standard-beta CG.
+bool r32_scaled(const Ctx *c)
+{
+    return c->opt.precision == SPFD_MIXED && !c->voxel_mode && c->lv.size() > 1 && c->lv[0].d_dinv32 != nullptr;
 }
 
 template <typename T>
@@ -630,7 +641,9 @@ void smooth_pre(Ctx *c, int l, const TB *b, T *&cur, T *&other, const Scal *sc, 
         // the first two steps in one pass on the finest level (x1 formed where read: one kernel and one
         // write and read of x1 less; 53 -> 45 us per cycle on the body phantom)
         Level &L = c->lv[0];
-        TScope ts(c, SPFD_K_SMOOTH0, nb * (double)L.dofs * (sizeof(TB) + op_bytes<T>(c, 0) + 2.0 * sizeof(T)) +
+        // b, the operator, the inverse diagonal (none with a scaled b) and the output
+        TScope ts(c, SPFD_K_SMOOTH0, nb * (double)L.dofs * (sizeof(TB) + op_bytes<T>(c, 0) +
+                                                            (c->bscale0 ? 1.0 : 2.0) * sizeof(T)) +
                                          nb * (double)L.dofs * (m > 2 ? sizeof(T) : 0.0));
         HIPCHK(launch_cheb_first2<T, TB>(level_op<T>(c, 0), L.topo(), b, dinv_of<T>(L), other, m > 2 ? d : nullptr,
                                          (T)c->cheb_c0, (T)c->cheb_c1[1], (T)c->cheb_c2[1], sc, level_batch(c, 0, nb),
@@ -753,11 +766,19 @@ void coarse_solve(Ctx *c, const TB *b, T *x, const Scal *sc, int nb)
 // dots (optional): the finest post-smoothing step also writes the partials of
 // z.r and z.q (cheb_dot_parts<T> per right side); returns false when the
 // cycle has no smoothing step to carry them (single level)
+// bs: r is the scaled FP32 copy D^-1 r (r32_scaled)
 template <typename T, typename TR>
-bool vcycle(Ctx *c, const TR *r, T *z, const Scal *sc, int nb, const CycleDots *dots = nullptr)
+bool vcycle(Ctx *c, const TR *r, T *z, const Scal *sc, int nb, const CycleDots *dots = nullptr, bool bs = false)
 {
     const int nl = (int)c->lv.size();
     std::vector<T *> res(nl, nullptr);
+    if (bs && !(sizeof(T) == sizeof(float) && sizeof(TR) == sizeof(float) && r32_scaled(c)))
+        throw HipFail{hipErrorInvalidValue, "scaled right side outside an FP32 cycle in label form"};
+    struct ScaleScope {
+        Ctx *c;
+        ScaleScope(Ctx *c_, bool v) : c(c_) { c->bscale0 = v; }
+        ~ScaleScope() { c->bscale0 = false; }
+    } scs(c, bs);
     // the stencil kernels read a stop flag per launch row: a cycle outside a CG step never stops
     if (!sc) {
         if (!c->d_nostop || nb > c->nbat) throw HipFail{hipErrorInvalidValue, "cycle without scalars"};
@@ -1341,12 +1362,15 @@ void pcg_begin(Ctx *c, Scal *sc, int nb)
     // an FP32 cycle starts from the FP32 copy of r when the start wrote one (as every later cycle does)
     const bool r32 = sizeof(T) == sizeof(float) && c->r32_ready;
     c->r32_ready = false;
+    // (the start pass writes the scaled copy where r32_scaled holds)
+    const bool bs = r32 && r32_scaled(c);
     if (c->np) {
         if (r32)
-            vcycle<T, float>(c, c->d_r32, z, nullptr, 1, nullptr);
+            vcycle<T, float>(c, c->d_r32, z, nullptr, 1, nullptr, bs);
         else
             vcycle<T, double>(c, c->d_r, z, nullptr, 1, nullptr);
-    } else if (r32 ? vcycle<T, float>(c, c->d_r32, z, sc, nb, &dots) : vcycle<T, double>(c, c->d_r, z, sc, nb, &dots)) {
+    } else if (r32 ? vcycle<T, float>(c, c->d_r32, z, sc, nb, &dots, bs)
+                   : vcycle<T, double>(c, c->d_r, z, sc, nb, &dots)) {
         finish(c, cheb_dot_parts<T>(topo.nb), FIN_BETA0, sc, 0, nb);
         return;
     }
@@ -1380,14 +1404,17 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
         const bool flex = c->cg_flexible;
         const int bmode = flex ? FIN_BETA : FIN_BETA_STD;
         CycleDots dots{flex ? c->d_q : nullptr, c->d_part};
+        // the residual update of the standard beta writes the scaled copy where r32_scaled holds
+        const bool bs = r32 && !flex && r32_scaled(c);
         bool fused = false;
         if (c->np) {
             if (r32)
-                vcycle<T, float>(c, r32, z, nullptr, 1, nullptr);
+                vcycle<T, float>(c, r32, z, nullptr, 1, nullptr, bs);
             else
                 vcycle<T, double>(c, c->d_r, z, nullptr, 1, nullptr);
         } else {
-            fused = r32 ? vcycle<T, float>(c, r32, z, sc, nb, &dots) : vcycle<T, double>(c, c->d_r, z, sc, nb, &dots);
+            fused = r32 ? vcycle<T, float>(c, r32, z, sc, nb, &dots, bs)
+                        : vcycle<T, double>(c, c->d_r, z, sc, nb, &dots);
         }
         if (fused) {
             finish(c, cheb_dot_parts<T>(topo.nb), bmode, sc, 0, nb);
@@ -1421,7 +1448,8 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
         {
             // r (read and written), p_k and the operator; the FP32 copy of r
             TScope ts(c, SPFD_K_UPDATE, n0 * (16.0 + wz + op_bytes<double>(c, 0) + (r32 ? 4.0 : 0.0)));
-            HIPCHK(launch_col_rupdate<T>(op, topo, pbuf[par], c->d_r, r32, c->d_part, sc, bt, c->stream));
+            HIPCHK(launch_col_rupdate<T>(op, topo, pbuf[par], c->d_r, r32, c->d_part, sc, bt, c->stream,
+                                         r32 && r32_scaled(c)));
         }
         finish(c, cg_step_parts(nmax), FIN_RR, sc, max_iter, nb, c->step_mirror, ROWS_CG_GROUPS);
     }
@@ -1784,7 +1812,8 @@ spfd_status solve_batch(Ctx *c, const double *b, long long bvs, Scal *sc, Scal *
     } else {
         // x = 0, r = b and (FP32 cycle) the FP32 copy of r for the first cycle, in one pass
         const bool mixed = c->opt.precision == SPFD_MIXED && so.method != SPFD_FGMRES;
-        HIPCHK(launch_start(n0, b, bvs, c->d_x, c->d_r, mixed ? c->d_r32 : nullptr, nvec, c->stream));
+        HIPCHK(launch_start(n0, b, bvs, c->d_x, c->d_r, mixed ? c->d_r32 : nullptr, nvec, c->stream,
+                            mixed && r32_scaled(c) ? c->lv[0].d_dinv32 : nullptr));
         c->r32_ready = mixed;
     }
     // no host round trip here: a right side that is already done (b = 0, or an exact x0) stops the
@@ -1881,15 +1910,17 @@ spfd_status solve_many(Ctx **hs, int n, const spfd_solve_options &so, double **p
         off[k] = tot;
         tot += hs[k]->nrhs;
     }
-    // start: x0 = 0, r = b
+    // start: x0 = 0, r = b and the FP32 copy of r, as in solve_batch (the same first cycle)
     for (int k = 0; k < n; ++k) {
         Ctx *c = hs[k];
         const long long n0 = c->lv[0].nodes();
         HIPCHK(hipSetDevice(c->device));
         c->cg_flexible = so.flexible != 0;
         HIPCHK(launch_scal_init(c->d_scal, so.rel_tol, 0, c->nrhs, c->stream));
-        HIPCHK(hipMemsetAsync(c->d_x, 0, c->nrhs * n0 * sizeof(double), c->stream));
-        HIPCHK(hipMemcpyAsync(c->d_r, c->d_bs, c->nrhs * n0 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        const bool mixed = c->opt.precision == SPFD_MIXED;
+        HIPCHK(launch_start(n0, c->d_bs, n0, c->d_x, c->d_r, mixed ? c->d_r32 : nullptr, c->np ? 1 : c->nrhs,
+                            c->stream, mixed && r32_scaled(c) ? c->lv[0].d_dinv32 : nullptr));
+        c->r32_ready = mixed;
         HIPCHK(hipMemcpyAsync(c->h_scal, c->d_scal, c->nrhs * sizeof(Scal), hipMemcpyDeviceToHost, c->stream));
     }
     for (int k = 0; k < n; ++k) {

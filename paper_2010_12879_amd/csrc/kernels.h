@@ -49,6 +49,8 @@ struct OpArgs {
     const uint16_t *wh = nullptr;  // FP16 bits of w / whs (first coarse level of an FP32 cycle), read instead of w
     float whs = 0.0f;
     int short_below = 8192;        // stored-weight levels with fewer bricks run 4-node column segments
+    int bscale = 0;                // the right side b is held as D^-1 b (finest level of an FP32 cycle in label
+                                   // form): the kernels form D b where they need b
 };
 
 // A batch of right sides solved together: launch grids get a y-dimension of
@@ -187,7 +189,7 @@ hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, S
 // (cg_step_parts(nb) per right side) and the FP32 copy of r (r32 nullable)
 template <typename TZ>
 hipError_t launch_col_rupdate(const OpArgs<double> &op, Topo topo, const TZ *p, double *r, float *r32, double *part,
-                              const Scal *sc, const Batch &bt, hipStream_t s);
+                              const Scal *sc, const Batch &bt, hipStream_t s, int r32_scaled);
 // r = b - A x (r nullable) and the partials of ||r||^2 (cg_step_parts(nb) per right side).  b has its own
 // batch stride bvs (the right sides may live apart from the solve vectors).
 hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,
@@ -257,9 +259,10 @@ hipError_t launch_comp_mean(Topo topo, const double *x, const int *comp, int nco
 // starts at node layer zoff of it)
 hipError_t launch_psi_out(const double *x, const int *comp, const double *means, const int *slot_of, const Grid &g,
                           double *psi, hipStream_t s, const Grid *gbricks = nullptr, int zoff = 0);
-// start of a solve from x = 0 for nvec right sides: x = 0, r = b and r32 = (float)b (r32 may be null)
+// start of a solve from x = 0 for nvec right sides: x = 0, r = b and r32 = (float)b (r32 may be null;
+// dinv given: r32 = (float)(dinv b), the scaled form an FP32 cycle in label form reads)
 hipError_t launch_start(long long n, const double *b, long long bvs, double *x, double *r, float *r32, int nvec,
-                        hipStream_t s);
+                        hipStream_t s, const float *dinv = nullptr);
 hipError_t launch_psi_in(const double *psi, const int *comp, const int4 *coord, int nb, const Grid &g, double *x,
                          hipStream_t s);
 hipError_t launch_efield(const uint8_t *labels, const double *table, const double *sig_vox, const Grid &g,

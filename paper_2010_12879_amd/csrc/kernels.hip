@@ -1473,7 +1473,7 @@ hipError_t launch_psi_out(const double *x, const int *comp, const double *means,
 // start of a solve from x = 0: x = 0, r = b (right side i at b + i*bvs, vectors at i*n) and, for an
 // FP32 cycle, the FP32 copy of r that the first cycle reads
 __global__ void k_start(long long n, const double *__restrict__ b, long long bvs, double *__restrict__ x,
-                        double *__restrict__ r, float *__restrict__ r32)
+                        double *__restrict__ r, float *__restrict__ r32, const float *__restrict__ dinv)
 {
     const long long off = (long long)blockIdx.y * n;
     b += (long long)blockIdx.y * bvs;
@@ -1481,16 +1481,18 @@ __global__ void k_start(long long n, const double *__restrict__ b, long long bvs
         const double v = b[k];
         x[off + k] = 0.0;
         r[off + k] = v;
-        if (r32) r32[off + k] = (float)v;
+        if (r32) r32[off + k] = dinv ? (float)(v * (double)dinv[k]) : (float)v;
     }
 }
 
 hipError_t launch_start(long long n, const double *b, long long bvs, double *x, double *r, float *r32, int nvec,
-                        hipStream_t s)
+                        hipStream_t s, const float *dinv)
 {
     if (n <= 0 || nvec <= 0) return hipSuccess;
+    if (dinv && !r32) return hipErrorInvalidValue;
     const long long blocks = (n + 255) / 256;
-    SPFD_LAUNCH(k_start, dim3((unsigned)(blocks > 65536 ? 65536 : blocks), nvec), dim3(256), 0, s, n, b, bvs, x, r, r32);
+    SPFD_LAUNCH(k_start, dim3((unsigned)(blocks > 65536 ? 65536 : blocks), nvec), dim3(256), 0, s, n, b, bvs, x, r, r32,
+                dinv);
     return hipGetLastError();
 }
 

@@ -441,7 +441,9 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo 
         T W[6];
         A.weights(s, z, W);
         const T D = diag_of(W);
-        if (s.active) x[s.self + 64 * z] = D > T(0) ? c0 * bv[z] * recip(D) : T(0);
+        // (a scaled right side already holds D^-1 b)
+        const T v = op.bscale ? c0 * bv[z] : c0 * bv[z] * recip(D);
+        if (s.active) x[s.self + 64 * z] = D > T(0) ? v : T(0);
     }
 }
 
@@ -450,7 +452,10 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first(OpArgs<T> op, Topo 
 // face columns, z ends; D^-1 from the stored inverse diagonal, so every wave
 // forms the same value for a node) and never stored; then
 //   r = b - A x1, d = c1 x1 + c2 D^-1 r, xout = x1 + d (dout = d if given).
-template <typename T, typename TB, int ZPL, bool LABEL>
+// SB: b holds D^-1 b (op.bscale), so x1 = c0 b needs no inverse diagonal at
+// all, and the own nodes form D b and D^-1 from their weights: one of the
+// kernel's two vectors with halo less to load.
+template <typename T, typename TB, int ZPL, bool LABEL, bool SB>
 __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first2(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
                                                               const T *__restrict__ dinv, T *__restrict__ xout,
                                                               T *__restrict__ dout, T c0, T c1, T c2, const Scal *sc,
@@ -467,28 +472,47 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_first2(OpArgs<T> op, Topo
     SegVals<TB, ZPL> B;
     B.template load<std::is_same<T, TB>::value>(b, s);
     SegVals<T, ZPL> DI;
-    DI.load(dinv, s);
+    if constexpr (!SB) DI.load(dinv, s);
     // x1 on the segment, the face columns and the z ends
     SegVals<T, ZPL> X;
 #pragma unroll
     for (int z = 0; z < ZPL; ++z) {
-        X.c[z] = c0 * (T)B.c[z] * DI.c[z];
-        X.ex[z] = c0 * (T)B.ex[z] * DI.ex[z];
-        X.ey[z] = c0 * (T)B.ey[z] * DI.ey[z];
+        if constexpr (SB) {
+            X.c[z] = c0 * (T)B.c[z];
+            X.ex[z] = c0 * (T)B.ex[z];
+            X.ey[z] = c0 * (T)B.ey[z];
+        } else {
+            X.c[z] = c0 * (T)B.c[z] * DI.c[z];
+            X.ex[z] = c0 * (T)B.ex[z] * DI.ex[z];
+            X.ey[z] = c0 * (T)B.ey[z] * DI.ey[z];
+        }
     }
-    X.zm = c0 * (T)B.zm * DI.zm;
-    X.zp = c0 * (T)B.zp * DI.zp;
+    if constexpr (SB) {
+        X.zm = c0 * (T)B.zm;
+        X.zp = c0 * (T)B.zp;
+    } else {
+        X.zm = c0 * (T)B.zm * DI.zm;
+        X.zp = c0 * (T)B.zp * DI.zp;
+    }
     A.stage(op, s);
 #pragma unroll
     for (int z = 0; z < ZPL; ++z) {
         T W[6], N[6];
         A.weights(s, z, W);
         X.nbrs(s, z, N);
-        // the stored inverse diagonal (0 where the diagonal vanishes), as in x1
-        const T di = DI.c[z];
+        // the stored inverse diagonal (0 where the diagonal vanishes), as in x1; SB: from the weights
+        T di, bz;
+        if constexpr (SB) {
+            const T D = diag_of(W);
+            di = D > T(0) ? recip(D) : T(0);
+            bz = D * (T)B.c[z];
+        } else {
+            di = DI.c[z];
+            bz = (T)B.c[z];
+        }
         T xo = T(0), dn = T(0);
         if (s.active && di > T(0)) {
-            const T r = (T)B.c[z] - stencil_apply(X.c[z], N, W);
+            const T r = bz - stencil_apply(X.c[z], N, W);
             dn = c1 * X.c[z] + c2 * r * di;
             xo = X.c[z] + dn;
         }
@@ -666,9 +690,11 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo t
             A.weights(s, z, W);
             X.nbrs(s, z, N);
             const T D = diag_of(W);
+            // b as the cycle takes it (a scaled right side holds D^-1 b)
+            const T bz = op.bscale ? D * bv[z] : bv[z];
             T xo = T(0), dn = T(0);
             if (s.active && D > T(0)) {
-                const T r = bv[z] - stencil_apply(X.c[z], N, W);
+                const T r = bz - stencil_apply(X.c[z], N, W);
                 dn = c1 * dv[z] + c2 * r * recip(D);
                 xo = X.c[z] + dn;
             }
@@ -676,7 +702,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo t
                 xout[s.self + 64 * z] = xo;
                 if (dout) dout[s.self + 64 * z] = dn;
                 if constexpr (DOT) {
-                    dzr += (double)xo * (double)bv[z];
+                    dzr += (double)xo * (double)bz;
                     dzq += (double)xo * qv[z];
                 }
             }
@@ -706,8 +732,10 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cheb_step(OpArgs<T> op, Topo t
 
 // coarse right side b_c = P^T (b - A x), P = 2x2x2 piecewise-constant
 // aggregation: z pairs add in the lane, x pairs across lanes l, l+1, y pairs
-// across l, l+8; the lane of the even corner stores the aggregate
-template <typename T, typename TB, int ZPL, bool LABEL>
+// across l, l+8; the lane of the even corner stores the aggregate.
+// SB: b holds D^-1 b (op.bscale); then b - A x = -sum_k W_k ((x - b) - N_k),
+// the stencil applied to x - b, which needs no diagonal.
+template <typename T, typename TB, int ZPL, bool LABEL, bool SB>
 __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, Topo topo, const TB *__restrict__ b,
                                                                  const T *__restrict__ x, T *__restrict__ bc,
                                                                  const int *__restrict__ parent_slot,
@@ -748,7 +776,7 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
         T W[6], N[6];
         A.weights(s, z, W);
         X.nbrs(s, z, N);
-        const T rz = bv[z] - stencil_apply(X.c[z], N, W);
+        const T rz = SB ? -stencil_apply(X.c[z] - bv[z], N, W) : bv[z] - stencil_apply(X.c[z], N, W);
         r[z] = s.active ? rz : T(0);
     }
 #pragma unroll
@@ -869,7 +897,8 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
 
 // ---------------------------------------------------------------- residual update
 // r_{k+1} = r_k - alpha_k A p_k, the partials of ||r_{k+1}||^2 (one per
-// workgroup, as in the CG step) and the FP32 copy of r (r32 nullable).  A p_k
+// workgroup, as in the CG step) and the FP32 copy of r (r32 nullable; with
+// r32_scaled, of D^-1 r, the form an FP32 cycle in label form reads).  A p_k
 // is formed again from the stored p_k with the CG step's operator, segment
 // and order of operations, so it equals the q_k that step formed for p.q bit
 // for bit; reading p_k in the cycle's precision and the labels costs fewer
@@ -877,7 +906,8 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
 template <typename TZ, int ZPL, bool LABEL>
 __global__ __launch_bounds__(CTHREADS) void k_col_rupdate(OpArgs<double> op, Topo topo, const TZ *__restrict__ pv,
                                                           double *__restrict__ r, float *__restrict__ r32,
-                                                          double *part, const Scal *sc, long long vs, int ps)
+                                                          double *part, const Scal *sc, long long vs, int ps,
+                                                          int r32_scaled)
 {
     constexpr bool WIDE = std::is_same<TZ, double>::value;
     double *lds = col_lds<double, ZPL, LABEL>();
@@ -914,7 +944,11 @@ __global__ __launch_bounds__(CTHREADS) void k_col_rupdate(OpArgs<double> op, Top
                 const long long n = s.self + 64 * z;
                 const double rn = rv[z] - alpha * y;
                 r[n] = rn;
-                if (r32) r32[n] = (float)rn;
+                // the FP32 copy the cycle reads; scaled: D^-1 r with the FP32 reciprocal (the cycle's own
+                // precision; the first smoothing steps then need no inverse diagonal), 0 at the nodes of
+                // the column that are no unknowns (D = 0, r = 0)
+                const float D = (float)diag_of(W);
+                if (r32) r32[n] = r32_scaled ? (D > 0.0f ? (float)rn * recip(D) : 0.0f) : (float)rn;
                 rr += rn * rn;
             }
         }
@@ -1068,14 +1102,19 @@ hipError_t launch_cheb_first2(const OpArgs<T> &op, Topo topo, const TB *b, const
 {
     if (topo.nb <= 0) return hipSuccess;
     if (!col_args_ok(topo, sc)) return hipErrorInvalidValue;
-    if (!dinv) return hipErrorInvalidValue;
+    if (!dinv && !op.bscale) return hipErrorInvalidValue;
     constexpr int Z = zpl_cycle<T>();
-    if (op.w)
-        SPFD_LAUNCH((k_col_cheb_first2<T, TB, Z, false>), col_grid<Z>(topo_count(topo), bt.n), dim3(CTHREADS), 0, s, op, topo,
-                    b, dinv, xout, dout, c0, c1, c2, sc, bt.vs);
-    else
-        SPFD_LAUNCH((k_col_cheb_first2<T, TB, Z, true>), col_grid<Z>(topo_count(topo), bt.n), dim3(CTHREADS), 0, s, op, topo,
-                    b, dinv, xout, dout, c0, c1, c2, sc, bt.vs);
+    const dim3 g = col_grid<Z>(topo_count(topo), bt.n);
+#define SPFD_F2(LB, SB) SPFD_LAUNCH((k_col_cheb_first2<T, TB, Z, LB, SB>), g, dim3(CTHREADS), 0, s, op, topo, b, dinv, \
+                                    xout, dout, c0, c1, c2, sc, bt.vs)
+    if (op.w) {
+        if (op.bscale) SPFD_F2(false, true);
+        else SPFD_F2(false, false);
+    } else {
+        if (op.bscale) SPFD_F2(true, true);
+        else SPFD_F2(true, false);
+    }
+#undef SPFD_F2
     return hipGetLastError();
 }
 
@@ -1145,8 +1184,12 @@ static void resid_restrict_z(const OpArgs<T> &op, Topo topo, const TB *b, const 
                              const int4 *fcoord, const Scal *sc, const Batch &bt, hipStream_t s, T *xc,
                              const T *dinv_c, T c0)
 {
-    SPFD_LAUNCH((k_col_resid_restrict<T, TB, ZPL, LABEL>), col_grid<ZPL>(topo_count(topo), bt.n), dim3(CTHREADS), 0, s, op,
-                topo, b, x, bc, parent_slot, fcoord, sc, bt.vs, bt.vsc, xc, dinv_c, c0);
+    if (op.bscale)
+        SPFD_LAUNCH((k_col_resid_restrict<T, TB, ZPL, LABEL, true>), col_grid<ZPL>(topo_count(topo), bt.n),
+                    dim3(CTHREADS), 0, s, op, topo, b, x, bc, parent_slot, fcoord, sc, bt.vs, bt.vsc, xc, dinv_c, c0);
+    else
+        SPFD_LAUNCH((k_col_resid_restrict<T, TB, ZPL, LABEL, false>), col_grid<ZPL>(topo_count(topo), bt.n),
+                    dim3(CTHREADS), 0, s, op, topo, b, x, bc, parent_slot, fcoord, sc, bt.vs, bt.vsc, xc, dinv_c, c0);
 }
 
 template <typename T, typename TB>
@@ -1191,23 +1234,24 @@ hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, cons
 
 template <typename TZ>
 hipError_t launch_col_rupdate(const OpArgs<double> &op, Topo topo, const TZ *p, double *r, float *r32, double *part,
-                              const Scal *sc, const Batch &bt, hipStream_t s)
+                              const Scal *sc, const Batch &bt, hipStream_t s, int r32_scaled)
 {
     if (topo.nb <= 0) return hipSuccess;
     if (!col_args_ok(topo, sc)) return hipErrorInvalidValue;
+    if (r32_scaled && !r32) return hipErrorInvalidValue;
     const dim3 g = col_grid<ZPL_CG>(topo_count(topo), bt.n);
     if (op.w)
         SPFD_LAUNCH((k_col_rupdate<TZ, ZPL_CG, false>), g, dim3(CTHREADS), 0, s, op, topo, p, r, r32, part, sc, bt.vs,
-                    bt.ps);
+                    bt.ps, r32_scaled);
     else
         SPFD_LAUNCH((k_col_rupdate<TZ, ZPL_CG, true>), g, dim3(CTHREADS), 0, s, op, topo, p, r, r32, part, sc, bt.vs,
-                    bt.ps);
+                    bt.ps, r32_scaled);
     return hipGetLastError();
 }
 template hipError_t launch_col_rupdate<double>(const OpArgs<double> &, Topo, const double *, double *, float *,
-                                               double *, const Scal *, const Batch &, hipStream_t);
+                                               double *, const Scal *, const Batch &, hipStream_t, int);
 template hipError_t launch_col_rupdate<float>(const OpArgs<double> &, Topo, const float *, double *, float *,
-                                              double *, const Scal *, const Batch &, hipStream_t);
+                                              double *, const Scal *, const Batch &, hipStream_t, int);
 
 hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,
                         double *part, long long bvs, const Batch &bt, hipStream_t s)
