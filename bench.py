@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # finest-level kernel classes timed with events (one sampled CG iteration per solve);
 # the dominant one (largest estimated share of the solve) carries the roofline figure
-FINE_CLASSES = {0: "k_col_cg_step (outer CG: p, deferred x, p.Ap)",
+FINE_CLASSES = {0: "k_col_cg_step (outer CG: p = z + beta p, p.Ap)",
                 1: "k_col_rupdate (r -= alpha A p, A p formed again; ||r||^2, FP32 copy of r)",
                 2: "k_col_cheb_step + CG dot z.r (last post-smoothing step)",
                 4: "k_col_cheb_first2 (first two Chebyshev steps, the pre-smoothing)",
@@ -506,7 +506,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("f64 CG (x, r, q, dots; search direction p stored in f32), f32 cycle (f16 weights on coarse level 1), "
+        "dtype": ("f64 CG (x, r, A p, dots; search directions p stored in f32), f32 cycle (f16 weights on coarse level 1), "
                   "f64 coarsest" if head == "mixed"
                   else "f64"),
         "data": "synthetic",

@@ -300,12 +300,12 @@ spfd_status spfd_adjoint(spfd_handle h, double omega, const double *a, const dou
 
 /* Per-launch timing, a tracing aid.  Kernel classes: */
 enum {
-    SPFD_K_SPMV = 0,          /* outer CG: p = z + beta p, deferred x += alpha p, q = A p, p.q partials (FP64);
-                                 q is stored only for the flexible beta */
+    SPFD_K_SPMV = 0,          /* outer CG: p = z + beta p, q = A p, p.q partials (FP64); q is stored only for
+                                 the flexible beta */
     SPFD_K_UPDATE = 1,        /* outer CG: r -= alpha q (standard beta: q = A p formed again from the stored p),
                                  ||r||^2 partials, FP32 copy of r */
     SPFD_K_DOTS = 2,          /* outer CG: last finest-level smoothing step with the r.z and z.q partials */
-    SPFD_K_PUPDATE = 3,       /* outer CG: the deferred x += alpha p after the last step */
+    SPFD_K_PUPDATE = 3,       /* outer CG: x += sum alpha_j p_j over a window of kept search directions */
     SPFD_K_SMOOTH0 = 4,       /* finest level: Chebyshev step with a stencil application */
     SPFD_K_SMOOTH0_FIRST = 5, /* finest level: first Chebyshev step from zero (no stencil) */
     SPFD_K_RESTRICT0 = 6,     /* finest level: residual and restriction */

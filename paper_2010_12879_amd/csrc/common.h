@@ -35,7 +35,7 @@ struct Scal {
     int done;        // 1 = converged or stopped: later kernels of this solve return at once
     int iters;
     int status;      // 0 ok, 5 not converged, 6 breakdown
-    int pad;         // 1 + buffer parity of a pending deferred x update, 0 if none
+    int hcount;      // search directions kept since x was last updated (CG steps of the current window)
 };
 
 constexpr int MAX_MODELS = 16;     // voxel models packed into one handle

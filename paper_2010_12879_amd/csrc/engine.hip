@@ -114,7 +114,14 @@ struct Ctx {
     int nrhs = 0;
     double *d_bs = nullptr;   // right sides [nrhs][n0]
     std::vector<int> has_source;
-    double *d_x = nullptr, *d_r = nullptr, *d_p = nullptr, *d_p2 = nullptr, *d_q = nullptr;
+    double *d_x = nullptr, *d_r = nullptr, *d_q = nullptr;
+    // the search directions of the current window of CG steps (a right side's p_k in the slot given by its
+    // Scal::hcount, in the cycle's precision; slots phist_stride elements apart) and their step sizes
+    // [nrhs][phist_len]; x is updated from them every phist_len steps and at the end of a pass
+    uint8_t *d_phist = nullptr;
+    double *d_ahist = nullptr;
+    int phist_len = 2;
+    long long phist_stride = 0;
     void *d_z = nullptr;
     float *d_r32 = nullptr;
     Scal *d_scal = nullptr;
@@ -153,7 +160,7 @@ struct Ctx {
     // the library's own stream (all work) and the caller's stream it follows
     hipStream_t user_stream = nullptr;
     hipEvent_t ev_user = nullptr;
-    // captured CG iterations (one per buffer parity), replayed with hipGraphLaunch
+    // captured CG iterations (one per slot of the host ring), replayed with hipGraphLaunch
     struct StepGraph {
         hipGraphExec_t exec = nullptr;
         const Scal *mirror = nullptr;
@@ -1012,9 +1019,21 @@ void alloc_cycle_buffers(Ctx *c, int nb)
     const size_t n0 = (size_t)c->lv[0].nodes() * nvec;
     c->d_x = dalloc<double>(c, c->rhs_allocs, n0);
     c->d_r = dalloc<double>(c, c->rhs_allocs, n0);
-    c->d_p = dalloc<double>(c, c->rhs_allocs, n0);
-    c->d_p2 = dalloc<double>(c, c->rhs_allocs, n0);
     c->d_q = dalloc<double>(c, c->rhs_allocs, n0);
+    // window of search directions: up to MAX_PHIST steps within about 4 GiB, at least two, an even count
+    // (the step graphs alternate the two slots of the host ring); a 1e-8 solve of the 8.9 M-unknown body
+    // takes 21 steps, so x is updated once at its end
+    {
+        const size_t per = n0 * w;
+        size_t h = per ? ((size_t)4 << 30) / per : (size_t)MAX_PHIST;
+        h = std::max<size_t>(2, std::min<size_t>(MAX_PHIST, h)) & ~(size_t)1;
+        c->phist_len = (int)h;
+        c->phist_stride = (long long)n0;
+        c->d_phist = dalloc<uint8_t>(c, c->rhs_allocs, h * per);
+        HIPCHK(hipMemsetAsync(c->d_phist, 0, h * per, c->stream));
+        c->d_ahist = dalloc<double>(c, c->rhs_allocs, (size_t)nb * h);
+        HIPCHK(hipMemsetAsync(c->d_ahist, 0, (size_t)nb * h * sizeof(double), c->stream));
+    }
     c->d_z = dalloc<uint8_t>(c, c->rhs_allocs, n0 * w);
     c->d_r32 = mixed ? dalloc<float>(c, c->rhs_allocs, n0) : nullptr;
     // every vector starts at zero: slots of node columns without unknowns are never written and must
@@ -1023,8 +1042,6 @@ void alloc_cycle_buffers(Ctx *c, int nb)
     HIPCHK(hipMemsetAsync(c->d_r, 0, n0 * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(c->d_z, 0, n0 * w, c->stream));
     if (c->d_r32) HIPCHK(hipMemsetAsync(c->d_r32, 0, n0 * sizeof(float), c->stream));
-    HIPCHK(hipMemsetAsync(c->d_p, 0, n0 * sizeof(double), c->stream));
-    HIPCHK(hipMemsetAsync(c->d_p2, 0, n0 * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(c->d_q, 0, n0 * sizeof(double), c->stream));
     c->pstride = 2 * c->lv[0].nb + 64;
     c->d_part = dalloc<double>(c, c->rhs_allocs, (size_t)c->pstride * nb);
@@ -1398,8 +1415,10 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
     const double wz = sizeof(T);
     // an FP32 cycle reads an FP32 copy of the residual, written by the update kernel
     float *r32 = sizeof(T) == sizeof(float) ? c->d_r32 : nullptr;
-    // p in the cycle's precision (the FP64 buffers hold it in their first half with an FP32 cycle)
-    T *pbuf[2] = {(T *)c->d_p, (T *)c->d_p2};
+    // p_k in the window slot Scal::hcount (= it % nh: x is updated and the window emptied every nh steps),
+    // in the cycle's precision
+    const int nh = c->phist_len;
+    T *ph = (T *)c->d_phist;
     if (it > 0) {
         const bool flex = c->cg_flexible;
         const int bmode = flex ? FIN_BETA : FIN_BETA_STD;
@@ -1426,46 +1445,53 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
             finish(c, nmax, bmode, sc, 0, nb, nullptr, ROWS_BRICKS);
         }
     }
-    // p_k = z_k + beta p_{k-1}, x_k = x_{k-1} + alpha p_{k-1}, q_k = A p_k.  Only the flexible beta reads
-    // q_k later (z.q); with the standard beta the residual update forms A p_k again from p_k instead.
+    // p_k = z_k + beta p_{k-1}, q_k = A p_k.  Only the flexible beta reads q_k later (z.q); with the
+    // standard beta the residual update forms A p_k again from p_k instead.  x is updated at the end of
+    // the window (x_flush).
     const bool keep_q = c->cg_flexible;
-    const int par = it & 1;
     {
-        // z, p_{k-1}, x (read and written), p_k in the cycle's precision; q in FP64
-        TScope ts(c, SPFD_K_SPMV,
-                  n0 * (wz + (it ? 2.0 * wz + 16.0 : wz) + (keep_q ? 8.0 : 0.0) + op_bytes<double>(c, 0)));
-        HIPCHK(launch_cg_step<T>(op, topo, z, pbuf[par ^ 1], pbuf[par], c->d_x, keep_q ? c->d_q : nullptr, c->d_part,
-                                 sc, it == 0, par, bt, c->stream));
+        // z, p_{k-1}, p_k in the cycle's precision; q in FP64
+        TScope ts(c, SPFD_K_SPMV, n0 * (wz + (it ? 2.0 * wz : wz) + (keep_q ? 8.0 : 0.0) + op_bytes<double>(c, 0)));
+        HIPCHK(launch_cg_step<T>(op, topo, z, ph, c->phist_stride, nh, keep_q ? c->d_q : nullptr, c->d_part, sc,
+                                 it == 0, bt, c->stream));
     }
     finish(c, cg_step_parts(nmax), FIN_ALPHA, sc, 0, nb, nullptr, ROWS_CG_GROUPS);
     if (keep_q) {
         {
             TScope ts(c, SPFD_K_UPDATE, n0 * (24.0 + (r32 ? 4.0 : 0.0)));
-            HIPCHK(launch_rupdate(topo, c->d_r, c->d_q, c->d_part, sc, bt, r32, c->stream));
+            HIPCHK(launch_rupdate(topo, c->d_r, c->d_q, c->d_part, sc, bt, r32, c->stream, c->d_ahist, nh));
         }
         finish(c, nmax, FIN_RR, sc, max_iter, nb, c->step_mirror, ROWS_BRICKS);
     } else {
         {
             // r (read and written), p_k and the operator; the FP32 copy of r
             TScope ts(c, SPFD_K_UPDATE, n0 * (16.0 + wz + op_bytes<double>(c, 0) + (r32 ? 4.0 : 0.0)));
-            HIPCHK(launch_col_rupdate<T>(op, topo, pbuf[par], c->d_r, r32, c->d_part, sc, bt, c->stream,
-                                         r32 && r32_scaled(c)));
+            HIPCHK(launch_col_rupdate<T>(op, topo, ph, c->phist_stride, nh, c->d_r, r32, c->d_part, sc, bt, c->stream,
+                                         r32 && r32_scaled(c), c->d_ahist));
         }
         finish(c, cg_step_parts(nmax), FIN_RR, sc, max_iter, nb, c->step_mirror, ROWS_CG_GROUPS);
     }
 }
 
-void pcg_end(Ctx *c, Scal *sc, int nb)
+// x += sum alpha_j p_j over the steps of the window taken since the last update, then an empty window
+// (steps: how many the window holds, for the byte count)
+void x_flush(Ctx *c, Scal *sc, int nb, int steps)
 {
-    // the update x += alpha p deferred by the last step of each right side
     Level &L0 = c->lv[0];
     const double wp = c->opt.precision == SPFD_MIXED ? 4.0 : 8.0;
-    TScope ts(c, SPFD_K_PUPDATE, (double)L0.dofs * (c->np ? 1 : nb) * (16.0 + wp));
+    TScope ts(c, SPFD_K_PUPDATE, (double)L0.dofs * (c->np ? 1 : nb) * (16.0 + steps * wp));
     if (c->opt.precision == SPFD_MIXED)
-        HIPCHK(launch_x_final<float>(cg_topo(c), c->d_x, (const float *)c->d_p, (const float *)c->d_p2, sc,
-                                     cg_batch(c, nb), c->stream));
+        HIPCHK(launch_x_flush<float>(cg_topo(c), c->d_x, (const float *)c->d_phist, c->phist_stride, c->d_ahist,
+                                     c->phist_len, sc, cg_batch(c, nb), c->stream));
     else
-        HIPCHK(launch_x_final<double>(cg_topo(c), c->d_x, c->d_p, c->d_p2, sc, cg_batch(c, nb), c->stream));
+        HIPCHK(launch_x_flush<double>(cg_topo(c), c->d_x, (const double *)c->d_phist, c->phist_stride, c->d_ahist,
+                                      c->phist_len, sc, cg_batch(c, nb), c->stream));
+}
+
+void pcg_end(Ctx *c, Scal *sc, int nb, int steps)
+{
+    // the search directions of the last, partial window
+    x_flush(c, sc, nb, steps % c->phist_len);
 }
 
 void pcg_begin_any(Ctx *c, Scal *sc, int nb)
@@ -1513,10 +1539,13 @@ void pcg_step_enqueue(Ctx *c, Scal *sc, Scal *hsc, int nb, int it, int max_iter,
         ~MirrorScope() { c->step_mirror = nullptr; }
     } ms(c, mirror);
     const bool timed_sample = c->tmask != 0 && it == 1;
+    // a full window of search directions updates x before the next step overwrites its first slot
+    const bool flush = (it + 1) % c->phist_len == 0;
     if (eager || it == 0 || timed_sample) {
         c->step_ctx = timed_sample ? 2 : 1;
         pcg_step_any(c, sc, nb, it, max_iter);
         c->step_ctx = 0;
+        if (flush) x_flush(c, sc, nb, c->phist_len);
         return;
     }
     if (c->sg_nb != nb || c->sg_sc != sc || c->sg_max_iter != max_iter || c->sg_flexible != (int)c->cg_flexible) {
@@ -1556,6 +1585,7 @@ void pcg_step_enqueue(Ctx *c, Scal *sc, Scal *hsc, int nb, int it, int max_iter,
         c->tlaunch[k] += g.launch[k];
         c->tbytes[k] += g.bytes[k];
     }
+    if (flush) x_flush(c, sc, nb, c->phist_len);
 }
 
 // Host loop of the CG iterations, one step ahead: step it+1 is enqueued before
@@ -1618,7 +1648,7 @@ void pcg_iterations(Ctx *c, Scal *sc, int nb, const spfd_solve_options &so)
         }
         if (all) break;
     }
-    pcg_end(c, sc, nb);
+    pcg_end(c, sc, nb, queued + 1);
 }
 
 void resid_b(Ctx *c, const double *b, long long bvs, Scal *sc, double *r, int mode, int nb);
@@ -1955,14 +1985,14 @@ spfd_status solve_many(Ctx **hs, int n, const spfd_solve_options &so, double **p
                 bool all = true;
                 for (int i = 0; i < c->nrhs; ++i) all = all && hs_it[i].done;
                 if (all) {
-                    pcg_end(c, c->d_scal, c->nrhs);
+                    pcg_end(c, c->d_scal, c->nrhs, steps[k]);
                     active[k] = 0;
                     --left;
                 }
             }
     }
     for (int k = 0; k < n; ++k)
-        if (active[k]) pcg_end(hs[k], hs[k]->d_scal, hs[k]->nrhs);
+        if (active[k]) pcg_end(hs[k], hs[k]->d_scal, hs[k]->nrhs, steps[k]);
     // true residuals, restarts, gauge and output
     spfd_status worst = SPFD_OK;
     for (int k = 0; k < n; ++k) {

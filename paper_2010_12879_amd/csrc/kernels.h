@@ -144,6 +144,7 @@ hipError_t launch_tree_cotree(const double *flux, double *a, const Grid &g, hipS
 
 // ---------------------------------------------------------------- flexible GMRES
 constexpr int FG_MAXM = 32;     // largest restart length (basis vectors per cycle)
+constexpr int MAX_PHIST = 32;   // most CG search directions kept between two updates of x
 constexpr int FG_PARTS = 1024;  // partial sums per dot product
 // least-squares state of one cycle (device memory): H column-major with leading dimension FG_MAXM + 1
 struct FGState {
@@ -175,21 +176,26 @@ hipError_t launch_spmv(const OpArgs<double> &op, Topo topo, const TZ *z, double 
                        hipStream_t s);
 // number of partial sums launch_cg_step writes per right side (nb: bricks per launch row, topo_count)
 int cg_step_parts(int nb);
+// Window of search directions: p_j of window slot j at ph + j * hs (+ row * vs), its step size at
+// ahist[row * nh + j]; a right side's current slot is its Scal::hcount (steps since x was last updated).
+// p = z + beta p_prev into the current slot, q = A p (q nullable: not stored), p.q partials
 template <typename TZ>
-hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, const TZ *pin, TZ *pout,
-                          double *x, double *q, double *part, Scal *sc, int first, int parity, const Batch &bt,
-                          hipStream_t s);
-// p in the cycle's precision TP, as the CG step stores it
+hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, TZ *ph, long long hs, int nh, double *q,
+                          double *part, Scal *sc, int first, const Batch &bt, hipStream_t s);
+// x += sum_j alpha_j p_j over the window's slots 0 .. hcount-1, in step order; then hcount = 0
 template <typename TP>
-hipError_t launch_x_final(Topo topo, double *x, const TP *pa, const TP *pb, const Scal *sc, const Batch &bt,
-                          hipStream_t s);
+hipError_t launch_x_flush(Topo topo, double *x, const TP *ph, long long hs, const double *ahist, int nh, Scal *sc,
+                          const Batch &bt, hipStream_t s);
+// r -= alpha q, ||r||^2 partials, the FP32 copy of r; alpha also into the window slot hcount
 hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, Scal *sc, const Batch &bt, float *r32,
-                          hipStream_t s);
-// r -= alpha A p with A p formed again from the stored p (the CG step then stores no q), ||r||^2 partials
-// (cg_step_parts(nb) per right side) and the FP32 copy of r (r32 nullable)
+                          hipStream_t s, double *ahist, int nh);
+// r -= alpha A p with A p formed again from p in the window slot hcount (the CG step then stores no q),
+// ||r||^2 partials (cg_step_parts(nb) per right side) and the FP32 copy of r (r32 nullable); alpha also
+// into that slot
 template <typename TZ>
-hipError_t launch_col_rupdate(const OpArgs<double> &op, Topo topo, const TZ *p, double *r, float *r32, double *part,
-                              const Scal *sc, const Batch &bt, hipStream_t s, int r32_scaled);
+hipError_t launch_col_rupdate(const OpArgs<double> &op, Topo topo, const TZ *ph, long long hs, int nh, double *r,
+                              float *r32, double *part, const Scal *sc, const Batch &bt, hipStream_t s, int r32_scaled,
+                              double *ahist);
 // r = b - A x (r nullable) and the partials of ||r||^2 (cg_step_parts(nb) per right side).  b has its own
 // batch stride bvs (the right sides may live apart from the solve vectors).
 hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,

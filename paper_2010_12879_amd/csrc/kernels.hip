@@ -880,7 +880,7 @@ __global__ void k_scal_init(Scal *sc, double tol, int use_x0)
         sc->rr = bb;
         sc->tol2 = tol * tol * bb;
         sc->done = bb > 0.0 ? 0 : 1;
-        sc->iters = 0; sc->status = 0; sc->pad = 0;
+        sc->iters = 0; sc->status = 0; sc->hcount = 0;
     }
 }
 
@@ -971,6 +971,7 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
     case FIN_RR:
         sc->rr = a;
         sc->iters += 1;
+        sc->hcount += 1;   // the step's search direction and step size are kept
         if (a <= sc->tol2) {
             sc->done = 1;
         } else if (!isfinite(a)) {
@@ -984,7 +985,6 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
     case FIN_BETA0:
     case FIN_BETA:
     case FIN_BETA_STD: {
-        if (mode == FIN_BETA0) sc->pad = 0;
         double beta = 0.0;
         if (mode == FIN_BETA) beta = -sc->alpha * b / sc->rz;
         if (mode == FIN_BETA_STD) beta = a / sc->rz;
@@ -1001,13 +1001,9 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
     case FIN_RESID0:
         sc->rr = a;
         if (a <= sc->tol2) sc->done = 1;
-        sc->pad = 0;   // (a pending x update is applied before any true residual)
         break;
     case FIN_RESID1:
         sc->zq = a;
-        // the pending update was applied (k_x_final): a later pass must not apply it again to a right
-        // side that is not restarted
-        sc->pad = 0;
         break;
     case FIN_MEAN:
         means[comp] = counts[comp] > 0 ? a / (double)counts[comp] : 0.0;
@@ -1081,43 +1077,74 @@ hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, co
     return hipGetLastError();
 }
 
-// x += alpha p: the update deferred by the CG step, applied once after the last
-// step of a pass, from the buffer that step wrote (sc->pad: 0 = none pending)
+// x += sum_j alpha_j p_j over the search directions kept in the window (slots 0 .. hcount-1, filled in
+// step order), in step order: x receives the same sequence of updates as with one update per step,
+// whatever the window length.  k_hist_reset then starts the next window.
 template <typename TP>
-__global__ __launch_bounds__(NT) void k_x_final(Topo topo, double *__restrict__ x, const TP *__restrict__ pa,
-                                                const TP *__restrict__ pb, const Scal *sc, long long vs)
+__global__ __launch_bounds__(NT) void k_x_flush(Topo topo, double *__restrict__ x, const TP *__restrict__ ph,
+                                                long long hs, const double *__restrict__ ahist, int nh, long long vs,
+                                                const Scal *sc)
 {
     int loc;
     const int bk = topo_brick(topo, loc);
     if (bk < 0) return;
-    sc += blockIdx.y;
-    const int pend = sc->pad;
-    if (pend == 0) return;
-    const TP *p = pend == 1 ? pa : pb;
+    const double *ah = ahist + (long long)blockIdx.y * nh;
+    const int m = min(sc[blockIdx.y].hcount, nh);
+    if (m <= 0) return;
     const long long n = blockIdx.y * vs + (long long)bk * BS + threadIdx.x;
-    x[n] += sc->alpha * (double)p[n];
+    // every direction's load in flight (fully unrolled, wave-uniform conditions: no indexed private
+    // array), then the updates in step order
+    double a[MAX_PHIST];
+    TP pv[MAX_PHIST];
+#pragma unroll
+    for (int j = 0; j < MAX_PHIST; ++j) {
+        a[j] = 0.0;
+        pv[j] = TP(0);
+        if (j < m) {
+            a[j] = ah[j];
+            pv[j] = ph[(long long)j * hs + n];
+        }
+    }
+    double xv = x[n];
+#pragma unroll
+    for (int j = 0; j < MAX_PHIST; ++j)
+        if (j < m) xv = __builtin_fma(a[j], (double)pv[j], xv);
+    x[n] = xv;
+}
+
+// the next window starts empty
+__global__ void k_hist_reset(Scal *sc, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) sc[i].hcount = 0;
 }
 
 template <typename TP>
-hipError_t launch_x_final(Topo topo, double *x, const TP *pa, const TP *pb, const Scal *sc, const Batch &bt,
-                          hipStream_t s)
+hipError_t launch_x_flush(Topo topo, double *x, const TP *ph, long long hs, const double *ahist, int nh, Scal *sc,
+                          const Batch &bt, hipStream_t s)
 {
-    if (topo.nb <= 0) return hipSuccess;
-    SPFD_LAUNCH(k_x_final<TP>, dim3(xcd_grid(topo_count(topo)), bt.n), dim3(NT), 0, s, topo, x, pa, pb, sc, bt.vs);
+    if (topo.nb <= 0 || bt.n <= 0) return hipSuccess;
+    if (nh < 2 || nh > MAX_PHIST || !ph || !ahist || !sc) return hipErrorInvalidValue;
+    SPFD_LAUNCH(k_x_flush<TP>, dim3(xcd_grid(topo_count(topo)), bt.n), dim3(NT), 0, s, topo, x, ph, hs, ahist, nh,
+                bt.vs, sc);
+    SPFD_LAUNCH(k_hist_reset, dim3((bt.n + 63) / 64), dim3(64), 0, s, sc, bt.n);
     return hipGetLastError();
 }
-template hipError_t launch_x_final<float>(Topo, double *, const float *, const float *, const Scal *, const Batch &,
-                                          hipStream_t);
-template hipError_t launch_x_final<double>(Topo, double *, const double *, const double *, const Scal *,
+template hipError_t launch_x_flush<float>(Topo, double *, const float *, long long, const double *, int, Scal *,
+                                          const Batch &, hipStream_t);
+template hipError_t launch_x_flush<double>(Topo, double *, const double *, long long, const double *, int, Scal *,
                                            const Batch &, hipStream_t);
 
-// r -= alpha q, ||r||^2 partials and the FP32 copy of r (x is updated by the CG step)
+// r -= alpha q, ||r||^2 partials and the FP32 copy of r (x is updated once per window of steps, k_x_flush)
 __global__ __launch_bounds__(NT) void k_rupdate(Topo topo, double *__restrict__ r, const double *__restrict__ q,
                                                 double *part, const Scal *sc, long long vs, int ps,
-                                                float *__restrict__ r32)
+                                                float *__restrict__ r32, double *ahist, int nh)
 {
     __shared__ double red[8];
     sc += blockIdx.y;
+    // the step size of this search direction (window slot hcount), for the update of x at the window's end
+    if (blockIdx.x == 0 && threadIdx.x == 0 && sc->done == 0 && sc->hcount < nh)
+        ahist[blockIdx.y * nh + sc->hcount] = sc->alpha;
     int loc;
     const int bk = topo_brick(topo, loc);
     if (bk < 0) return;
@@ -1136,11 +1163,12 @@ __global__ __launch_bounds__(NT) void k_rupdate(Topo topo, double *__restrict__ 
 }
 
 hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, Scal *sc, const Batch &bt, float *r32,
-                          hipStream_t s)
+                          hipStream_t s, double *ahist, int nh)
 {
     if (topo.nb <= 0) return hipSuccess;
+    if (!ahist || nh < 2 || nh > MAX_PHIST) return hipErrorInvalidValue;
     SPFD_LAUNCH(k_rupdate, dim3(xcd_grid(topo_count(topo)), bt.n), dim3(NT), 0, s, topo, r, q, part, sc, bt.vs,
-                bt.ps, r32);
+                bt.ps, r32, ahist, nh);
     return hipGetLastError();
 }
 

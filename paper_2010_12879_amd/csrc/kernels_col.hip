@@ -82,6 +82,7 @@ struct Seg {
     bool bx, by;                                  // xe (ye) is to be read: face lane, neighbour brick present
     bool active;                                  // the lane's node column holds an unknown
     bool stop;                                    // the launch row's right side has stopped: return at once
+    int hc;                                       // the launch row's Scal::hcount (CG search-direction slot)
 };
 
 template <int ZPL>
@@ -121,7 +122,14 @@ __device__ __forceinline__ Seg<ZPL> make_seg(const Topo &topo, const Scal *sc)
     s.bk = b >= 0 && b < cnt ? first + b : -1;
     const int bl = s.bk < 0 ? 0 : s.bk;
     const unsigned long long cm = topo.cmask[bl];
-    s.stop = FLAG && sc[blockIdx.y].done != 0;
+    if constexpr (FLAG) {
+        // (adjacent fields of the row's scalars: loaded together)
+        s.stop = sc[blockIdx.y].done != 0;
+        s.hc = sc[blockIdx.y].hcount;
+    } else {
+        s.stop = false;
+        s.hc = 0;
+    }
     brick_nbrs(topo.nbr, bl, s.nb);
     s.active = false;
     if (s.bk < 0) return s;
@@ -794,15 +802,16 @@ __global__ __launch_bounds__(CTHREADS) void k_col_resid_restrict(OpArgs<T> op, T
 }
 
 // ---------------------------------------------------------------- outer CG step
-// Fused CG step with the x update deferred by one step:
-//   x_k = x_{k-1} + alpha_{k-1} p_{k-1}   (skipped on the first step)
+// Fused CG step:
 //   p_k = z_k + beta_{k-1} p_{k-1}        (p_k = z_k on the first step)
 //   q_k = A p_k and the partials of p_k.q_k (one per workgroup)
 // q_k is stored only where a later kernel reads it (q == nullptr: not
 // stored; the residual update then forms A p_k again, k_col_rupdate).
-// p_k at the neighbours is formed from z and p_{k-1}; pin and pout are
-// different buffers.  The step records in sc->pad which buffer holds the
-// pending p (1 + parity) for the final deferred update.
+// p_k at the neighbours is formed from z and p_{k-1}.  x is not touched: the
+// search directions of a window of steps are kept (p_k in the window slot
+// hcount, p_{k-1} in the slot before it), with their step sizes, and
+// x += sum alpha_j p_j is formed once per window (k_x_flush), which saves
+// reading and writing x (FP64) in every step.
 //
 // p is kept in the cycle's precision TZ (FP32 with the FP32 cycle): it is formed by one fused
 // multiply-add in TZ wherever it is needed, so every wave forms the same value at a node, and q = A p
@@ -818,21 +827,20 @@ __device__ __forceinline__ double fma_t<double>(double a, double b, double c) { 
 
 template <typename TZ, int ZPL, bool LABEL, bool FIRST>
 __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Topo topo, const TZ *__restrict__ zv,
-                                                          const TZ *__restrict__ pin, TZ *__restrict__ pout,
-                                                          double *__restrict__ x, double *__restrict__ q,
-                                                          double *part, Scal *sc, int parity, long long vs, int ps)
+                                                          TZ *ph, long long hs, int nh, double *__restrict__ q,
+                                                          double *part, Scal *sc, long long vs, int ps)
 {
     constexpr bool WIDE = std::is_same<TZ, double>::value;
     double *lds = col_lds<double, ZPL, LABEL>();
     __shared__ double red[CWAVES];
     const Seg<ZPL> s = make_seg<ZPL>(topo, sc);
     sc += blockIdx.y;
-    // a stopped right side (batched solves, a step queued past the stop) returns before its loads
-    if (s.grp < 0 || s.stop) return;
+    // a stopped right side (batched solves, a step queued past the stop) returns before its loads; a full
+    // window (not reached: the host updates x first) stores nothing
+    if (s.grp < 0 || s.stop || s.hc < 0 || s.hc >= nh) return;
     zv += blockIdx.y * vs;
-    pin += blockIdx.y * vs;
-    pout += blockIdx.y * vs;
-    x += blockIdx.y * vs;
+    const TZ *__restrict__ pin = ph + (long long)(s.hc == 0 ? nh - 1 : s.hc - 1) * hs + blockIdx.y * vs;
+    TZ *__restrict__ pout = ph + (long long)s.hc * hs + blockIdx.y * vs;
     if (q) q += blockIdx.y * vs;
     part += (long long)blockIdx.y * ps;
     double dot = 0.0;
@@ -842,17 +850,8 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
         SegVals<TZ, ZPL> Z;
         Z.template load<WIDE>(zv, s);
         SegVals<TZ, ZPL> Pi;
-        double xv[ZPL];
-        if constexpr (!FIRST) {
-            Pi.template load<WIDE>(pin, s);
-#pragma unroll
-            for (int z = 0; z < ZPL; ++z) xv[z] = 0.0;
-            if (s.active)
-#pragma unroll
-                for (int z = 0; z < ZPL; ++z) xv[z] = x[s.self + 64 * z];
-        }
+        if constexpr (!FIRST) Pi.template load<WIDE>(pin, s);
         const TZ beta = FIRST ? TZ(0) : (TZ)sc->beta;
-        const double alpha = FIRST ? 0.0 : sc->alpha;
         // p_k on the segment, the face columns and the z ends
         SegVals<TZ, ZPL> P;
 #pragma unroll
@@ -876,14 +875,12 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
             const double y = stencil_apply(pc, N, W);
             if (s.active) {
                 const long long n = s.self + 64 * z;
-                if constexpr (!FIRST) x[n] = xv[z] + alpha * (double)Pi.c[z];
                 pout[n] = P.c[z];
                 if (q) q[n] = y;
                 dot += pc * y;
             }
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->pad = 1 + parity;
     dot = wave_sum(dot);
     if (s.lane == 0) red[threadIdx.x >> 6] = dot;
     __syncthreads();
@@ -898,24 +895,28 @@ __global__ __launch_bounds__(CTHREADS) void k_col_cg_step(OpArgs<double> op, Top
 // ---------------------------------------------------------------- residual update
 // r_{k+1} = r_k - alpha_k A p_k, the partials of ||r_{k+1}||^2 (one per
 // workgroup, as in the CG step) and the FP32 copy of r (r32 nullable; with
-// r32_scaled, of D^-1 r, the form an FP32 cycle in label form reads).  A p_k
+// r32_scaled, of D^-1 r, the form an FP32 cycle in label form reads); alpha_k
+// goes to the window slot of p_k for the later update of x.  A p_k
 // is formed again from the stored p_k with the CG step's operator, segment
 // and order of operations, so it equals the q_k that step formed for p.q bit
 // for bit; reading p_k in the cycle's precision and the labels costs fewer
 // bytes than storing q_k in FP64 and reading it back.
 template <typename TZ, int ZPL, bool LABEL>
-__global__ __launch_bounds__(CTHREADS) void k_col_rupdate(OpArgs<double> op, Topo topo, const TZ *__restrict__ pv,
-                                                          double *__restrict__ r, float *__restrict__ r32,
+__global__ __launch_bounds__(CTHREADS) void k_col_rupdate(OpArgs<double> op, Topo topo, const TZ *ph, long long hs,
+                                                          int nh, double *__restrict__ r, float *__restrict__ r32,
                                                           double *part, const Scal *sc, long long vs, int ps,
-                                                          int r32_scaled)
+                                                          int r32_scaled, double *ahist)
 {
     constexpr bool WIDE = std::is_same<TZ, double>::value;
     double *lds = col_lds<double, ZPL, LABEL>();
     __shared__ double red[CWAVES];
     const Seg<ZPL> s = make_seg<ZPL>(topo, sc);
-    if (s.grp < 0 || s.stop) return;
+    if (s.stop || s.hc < 0 || s.hc >= nh) return;
     const double alpha = sc[blockIdx.y].alpha;
-    pv += blockIdx.y * vs;
+    // the step size of this search direction, for the update of x at the end of the window
+    if (blockIdx.x == 0 && threadIdx.x == 0) ahist[blockIdx.y * nh + s.hc] = alpha;
+    if (s.grp < 0) return;
+    const TZ *__restrict__ pv = ph + (long long)s.hc * hs + blockIdx.y * vs;
     r += blockIdx.y * vs;
     if (r32) r32 += blockIdx.y * vs;
     double rr = 0.0;
@@ -1211,16 +1212,15 @@ hipError_t launch_resid_restrict(const OpArgs<T> &op, Topo topo, const TB *b, co
 }
 
 template <typename TZ>
-hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, const TZ *pin, TZ *pout,
-                          double *x, double *q, double *part, Scal *sc, int first, int parity, const Batch &bt,
-                          hipStream_t s)
+hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, TZ *ph, long long hs, int nh, double *q,
+                          double *part, Scal *sc, int first, const Batch &bt, hipStream_t s)
 {
     if (topo.nb <= 0) return hipSuccess;
     if (!col_args_ok(topo, sc)) return hipErrorInvalidValue;
-    if (pin == pout) return hipErrorInvalidValue;
+    if (!ph || nh < 2 || nh > MAX_PHIST) return hipErrorInvalidValue;
     const dim3 g = col_grid<ZPL_CG>(topo_count(topo), bt.n);
-#define SPFD_CG(LB, F) SPFD_LAUNCH((k_col_cg_step<TZ, ZPL_CG, LB, F>), g, dim3(CTHREADS), 0, s, op, topo, z, pin, \
-                                   pout, x, q, part, sc, parity, bt.vs, bt.ps)
+#define SPFD_CG(LB, F) SPFD_LAUNCH((k_col_cg_step<TZ, ZPL_CG, LB, F>), g, dim3(CTHREADS), 0, s, op, topo, z, ph, hs, \
+                                   nh, q, part, sc, bt.vs, bt.ps)
     if (op.w) {
         if (first) SPFD_CG(false, true);
         else SPFD_CG(false, false);
@@ -1233,25 +1233,29 @@ hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, cons
 }
 
 template <typename TZ>
-hipError_t launch_col_rupdate(const OpArgs<double> &op, Topo topo, const TZ *p, double *r, float *r32, double *part,
-                              const Scal *sc, const Batch &bt, hipStream_t s, int r32_scaled)
+hipError_t launch_col_rupdate(const OpArgs<double> &op, Topo topo, const TZ *ph, long long hs, int nh, double *r,
+                              float *r32, double *part, const Scal *sc, const Batch &bt, hipStream_t s, int r32_scaled,
+                              double *ahist)
 {
     if (topo.nb <= 0) return hipSuccess;
     if (!col_args_ok(topo, sc)) return hipErrorInvalidValue;
     if (r32_scaled && !r32) return hipErrorInvalidValue;
+    if (!ph || !ahist || nh < 2 || nh > MAX_PHIST) return hipErrorInvalidValue;
     const dim3 g = col_grid<ZPL_CG>(topo_count(topo), bt.n);
     if (op.w)
-        SPFD_LAUNCH((k_col_rupdate<TZ, ZPL_CG, false>), g, dim3(CTHREADS), 0, s, op, topo, p, r, r32, part, sc, bt.vs,
-                    bt.ps, r32_scaled);
+        SPFD_LAUNCH((k_col_rupdate<TZ, ZPL_CG, false>), g, dim3(CTHREADS), 0, s, op, topo, ph, hs, nh, r, r32, part,
+                    sc, bt.vs, bt.ps, r32_scaled, ahist);
     else
-        SPFD_LAUNCH((k_col_rupdate<TZ, ZPL_CG, true>), g, dim3(CTHREADS), 0, s, op, topo, p, r, r32, part, sc, bt.vs,
-                    bt.ps, r32_scaled);
+        SPFD_LAUNCH((k_col_rupdate<TZ, ZPL_CG, true>), g, dim3(CTHREADS), 0, s, op, topo, ph, hs, nh, r, r32, part,
+                    sc, bt.vs, bt.ps, r32_scaled, ahist);
     return hipGetLastError();
 }
-template hipError_t launch_col_rupdate<double>(const OpArgs<double> &, Topo, const double *, double *, float *,
-                                               double *, const Scal *, const Batch &, hipStream_t, int);
-template hipError_t launch_col_rupdate<float>(const OpArgs<double> &, Topo, const float *, double *, float *,
-                                              double *, const Scal *, const Batch &, hipStream_t, int);
+template hipError_t launch_col_rupdate<double>(const OpArgs<double> &, Topo, const double *, long long, int, double *,
+                                               float *, double *, const Scal *, const Batch &, hipStream_t, int,
+                                               double *);
+template hipError_t launch_col_rupdate<float>(const OpArgs<double> &, Topo, const float *, long long, int, double *,
+                                              float *, double *, const Scal *, const Batch &, hipStream_t, int,
+                                              double *);
 
 hipError_t launch_resid(const OpArgs<double> &op, Topo topo, const double *b, const double *x, double *r,
                         double *part, long long bvs, const Batch &bt, hipStream_t s)
@@ -1299,9 +1303,9 @@ SPFD_INST_COL(double, double)
 SPFD_INST_COL(float, float)
 SPFD_INST_COL(float, double)
 
-template hipError_t launch_cg_step<double>(const OpArgs<double> &, Topo, const double *, const double *, double *,
-                                           double *, double *, double *, Scal *, int, int, const Batch &, hipStream_t);
-template hipError_t launch_cg_step<float>(const OpArgs<double> &, Topo, const float *, const float *, float *,
-                                          double *, double *, double *, Scal *, int, int, const Batch &, hipStream_t);
+template hipError_t launch_cg_step<double>(const OpArgs<double> &, Topo, const double *, double *, long long, int,
+                                           double *, double *, Scal *, int, const Batch &, hipStream_t);
+template hipError_t launch_cg_step<float>(const OpArgs<double> &, Topo, const float *, float *, long long, int,
+                                          double *, double *, Scal *, int, const Batch &, hipStream_t);
 
 }  // namespace spfd
