@@ -838,7 +838,7 @@ bool vcycle(Ctx *c, const TR *r, T *z, const Scal *sc, int nb, const CycleDots *
 
 // Partial sums of the CG kernels per launch row: packed models write one row per model, of the model's
 // own count (bricks, or groups of the CG step), and the finisher sums just those.
-enum { ROWS_BRICKS = 1, ROWS_CG_GROUPS = 2 };
+enum { ROWS_BRICKS = 1, ROWS_CG_GROUPS = 2, ROWS_RU_GROUPS = 3 };
 
 void finish(Ctx *c, int n, int mode, Scal *sc, int max_iter, int nb = 1, Scal *mirror = nullptr, int rows = 0)
 {
@@ -846,7 +846,10 @@ void finish(Ctx *c, int n, int mode, Scal *sc, int max_iter, int nb = 1, Scal *m
     FinRows fr{};
     if (c->np && rows) {
         fr.used = 1;
-        for (int m = 0; m < c->np; ++m) fr.n[m] = rows == ROWS_BRICKS ? c->mcount[m] : cg_step_parts(c->mcount[m]);
+        for (int m = 0; m < c->np; ++m)
+            fr.n[m] = rows == ROWS_BRICKS      ? c->mcount[m]
+                      : rows == ROWS_RU_GROUPS ? rupdate_parts(c->mcount[m])
+                                               : cg_step_parts(c->mcount[m]);
     }
     HIPCHK(launch_finish(c->d_part, n, mode, sc, max_iter, c->stream, nullptr, nullptr, 0, nb, c->pstride, mirror,
                          fr.used ? &fr : nullptr));
@@ -1469,7 +1472,7 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
             HIPCHK(launch_col_rupdate<T>(op, topo, ph, c->phist_stride, nh, c->d_r, r32, c->d_part, sc, bt, c->stream,
                                          r32 && r32_scaled(c), c->d_ahist));
         }
-        finish(c, cg_step_parts(nmax), FIN_RR, sc, max_iter, nb, c->step_mirror, ROWS_CG_GROUPS);
+        finish(c, rupdate_parts(nmax), FIN_RR, sc, max_iter, nb, c->step_mirror, ROWS_RU_GROUPS);
     }
 }
 

@@ -174,8 +174,10 @@ hipError_t launch_fg_xupdate(double *x, const TZ *Z, long long ldz, long long n,
 template <typename TZ>
 hipError_t launch_spmv(const OpArgs<double> &op, Topo topo, const TZ *z, double *w, const Scal *sc, const Batch &bt,
                        hipStream_t s);
-// number of partial sums launch_cg_step writes per right side (nb: bricks per launch row, topo_count)
+// number of partial sums launch_cg_step (launch_col_rupdate) writes per right side (nb: bricks per launch
+// row, topo_count)
 int cg_step_parts(int nb);
+int rupdate_parts(int nb);
 // Window of search directions: p_j of window slot j at ph + j * hs (+ row * vs), its step size at
 // ahist[row * nh + j]; a right side's current slot is its Scal::hcount (steps since x was last updated).
 // p = z + beta p_prev into the current slot, q = A p (q nullable: not stored), p.q partials
@@ -190,7 +192,7 @@ hipError_t launch_x_flush(Topo topo, double *x, const TP *ph, long long hs, cons
 hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, Scal *sc, const Batch &bt, float *r32,
                           hipStream_t s, double *ahist, int nh);
 // r -= alpha A p with A p formed again from p in the window slot hcount (the CG step then stores no q),
-// ||r||^2 partials (cg_step_parts(nb) per right side) and the FP32 copy of r (r32 nullable); alpha also
+// ||r||^2 partials (rupdate_parts(nb) per right side) and the FP32 copy of r (r32 nullable); alpha also
 // into that slot
 template <typename TZ>
 hipError_t launch_col_rupdate(const OpArgs<double> &op, Topo topo, const TZ *ph, long long hs, int nh, double *r,

@@ -1091,6 +1091,8 @@ __global__ __launch_bounds__(NT) void k_x_flush(Topo topo, double *__restrict__ 
     const double *ah = ahist + (long long)blockIdx.y * nh;
     const int m = min(sc[blockIdx.y].hcount, nh);
     if (m <= 0) return;
+    // a node column without unknowns holds zeros in x and every p: nothing to read or write
+    if (topo.cmask && !((topo.cmask[bk] >> (threadIdx.x & 63)) & 1ull)) return;
     const long long n = blockIdx.y * vs + (long long)bk * BS + threadIdx.x;
     // every direction's load in flight (fully unrolled, wave-uniform conditions: no indexed private
     // array), then the updates in step order
