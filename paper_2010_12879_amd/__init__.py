@@ -37,7 +37,8 @@ class AmgOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("cycle", ctypes.c_int), ("smooth_degree", ctypes.c_int),
                 ("coarsest_max", ctypes.c_int), ("cheby_ratio", ctypes.c_double), ("coarse_scale", ctypes.c_double),
                 ("split_level", ctypes.c_int), ("no_split", ctypes.c_int), ("level1_degree", ctypes.c_int),
-                ("smoother", ctypes.c_int), ("short_segment_bricks", ctypes.c_int), ("level1_fp32", ctypes.c_int)]
+                ("smoother", ctypes.c_int), ("short_segment_bricks", ctypes.c_int), ("level1_fp32", ctypes.c_int),
+                ("cg_window", ctypes.c_int)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -403,9 +404,10 @@ class Solver:
 
     def __init__(self, labels, sigma, h, precision="fp64", device=None, smooth_degree=2, coarsest_max=1024,
                  cheby_ratio=8.0, coarse_scale=1.9, split_level=2, split=True, stream=None, level1_degree=4,
-                 smoother="chebyshev", short_segment_bricks=0, level1_fp32=False, torch_memory=True):
+                 smoother="chebyshev", short_segment_bricks=0, level1_fp32=False, torch_memory=True, cg_window=0):
         """torch_memory: the handle's device memory comes from PyTorch's caching allocator
-        (torch.cuda.memory_allocated() accounts for it); False: hipMalloc inside the library."""
+        (torch.cuda.memory_allocated() accounts for it); False: hipMalloc inside the library.
+        cg_window: CG search directions kept before x is updated (0: the library's choice)."""
         import torch
         self.device = labels.device if device is None else torch.device(device)
         self.nz, self.ny, self.nx = labels.shape
@@ -425,7 +427,7 @@ class Solver:
                                    smooth_degree, coarsest_max, cheby_ratio, coarse_scale, split_level,
                                    0 if split else 1, level1_degree,
                                    {"chebyshev": SMOOTH_CHEBYSHEV, "l1jacobi": SMOOTH_L1_JACOBI, "chebyshev4": SMOOTH_CHEBYSHEV4}[smoother],
-                                   short_segment_bricks, 1 if level1_fp32 else 0)
+                                   short_segment_bricks, 1 if level1_fp32 else 0, cg_window)
             spfd_build(self.handle, self.opts)
         except Exception:
             spfd_destroy(self.handle)
@@ -562,7 +564,8 @@ class MultiSolver:
             opts = AmgOptions(MIXED if precision == "mixed" else FP64, CYCLE_V, amg.get("smooth_degree", 2),
                               amg.get("coarsest_max", 1024), amg.get("cheby_ratio", 8.0), amg.get("coarse_scale", 1.9),
                               amg.get("split_level", 2), 0, amg.get("level1_degree", 4), SMOOTH_CHEBYSHEV,
-                              amg.get("short_segment_bricks", 0), 1 if amg.get("level1_fp32") else 0)
+                              amg.get("short_segment_bricks", 0), 1 if amg.get("level1_fp32") else 0,
+                              amg.get("cg_window", 0))
             spfd_build(self.handle, opts)
         except Exception:
             spfd_destroy(self.handle)

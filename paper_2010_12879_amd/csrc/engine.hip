@@ -1023,12 +1023,13 @@ void alloc_cycle_buffers(Ctx *c, int nb)
     c->d_x = dalloc<double>(c, c->rhs_allocs, n0);
     c->d_r = dalloc<double>(c, c->rhs_allocs, n0);
     c->d_q = dalloc<double>(c, c->rhs_allocs, n0);
-    // window of search directions: up to MAX_PHIST steps within about 4 GiB, at least two, an even count
-    // (the step graphs alternate the two slots of the host ring); a 1e-8 solve of the 8.9 M-unknown body
-    // takes 21 steps, so x is updated once at its end
+    // window of search directions (cg_window, or by default up to MAX_PHIST steps within about 4 GiB, at
+    // least two), an even count (the step graphs alternate the two slots of the host ring); a 1e-8 solve
+    // of the 8.9 M-unknown body takes 21 steps, so x is updated once at its end
     {
         const size_t per = n0 * w;
         size_t h = per ? ((size_t)4 << 30) / per : (size_t)MAX_PHIST;
+        if (c->opt.cg_window > 0) h = (size_t)c->opt.cg_window;
         h = std::max<size_t>(2, std::min<size_t>(MAX_PHIST, h)) & ~(size_t)1;
         c->phist_len = (int)h;
         c->phist_stride = (long long)n0;
@@ -2324,6 +2325,8 @@ spfd_status spfd_build(spfd_handle h, const spfd_amg_options *opt)
     if (opt) o = *opt;
     const bool tune = o.short_segment_bricks == 0;   // the default: segments tuned per level
     if (o.cycle != SPFD_CYCLE_V) return fail(h, SPFD_INVALID_ARG, "unknown cycle (only SPFD_CYCLE_V)");
+    if (o.cg_window != 0 && (o.cg_window < 2 || o.cg_window > MAX_PHIST || (o.cg_window & 1)))
+        return fail(h, SPFD_INVALID_ARG, "cg_window must be 0 or an even number from 2 to 32");
     if (o.smoother != SPFD_SMOOTH_CHEBYSHEV && o.smoother != SPFD_SMOOTH_L1_JACOBI && o.smoother != SPFD_SMOOTH_CHEBYSHEV4)
         return fail(h, SPFD_INVALID_ARG, "unknown smoother");
     set_defaults(o);

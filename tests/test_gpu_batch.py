@@ -98,6 +98,53 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_short_window_of_search_directions_same_bits(prec):
+    """x is formed from a window of kept CG search directions, in step order: a window of 2 (x updated
+    every second step, with right sides of a batch stopping at different steps, one at once) gives the
+    same potentials bit for bit as the default window, and they meet the oracle's residual."""
+    print(f"case window {prec}", flush=True)
+    w = W.random_ellipsoid_phantom(32, 32, 40, seed=47, n_ell=8, semi_range=(3.0, 9.0))
+    srcs = _sources(w, 4, 13)
+    srcs[1] = 0.0                         # stops before its first step
+    srcs[3] *= 1e-3
+    res = {}
+    for win in (0, 2, 6):
+        s = P.Solver(_dev(w.labels), w.sigma_table, w.h, precision=prec, cg_window=win)
+        res[win] = s.solve(_dev(srcs), tol=1e-11, max_iter=300)
+        s.close()
+    psi0, info0 = res[0]
+    assert all(i["status"] == "OK" for i in info0)
+    assert len({i["iterations"] for i in info0}) >= 2        # uneven stops within the batch
+    for win in (2, 6):
+        psi, info = res[win]
+        assert [i["iterations"] for i in info] == [i["iterations"] for i in info0], win
+        assert torch.equal(psi, psi0), win
+    for i in (0, 2, 3):
+        rel = oracle.residual(w.sigma_voxel(), w.h, srcs[i], psi0[i].cpu().numpy())
+        assert rel <= 1e-11 * 1.01, (i, rel)
+    with pytest.raises(RuntimeError):
+        P.Solver(_dev(w.labels), w.sigma_table, w.h, precision=prec, cg_window=3)
+
+
+def test_packed_models_short_window_same_bits():
+    """Packed models (one CG per model, each with its own window counter) with a window of 2 against the
+    default window: the same potentials bit for bit."""
+    print("case packed window", flush=True)
+    dims = [(24, 20, 28), (40, 32, 48), (17, 23, 9)]
+    ws = [W.random_ellipsoid_phantom(nx, ny, nz, seed=310 + i, n_ell=5, semi_range=(2.5, 9.0), name=f"q{i}")
+          for i, (nx, ny, nz) in enumerate(dims)]
+    ws = [w for w in ws if np.any(w.sigma_voxel() > 0)]
+    out = {}
+    for win in (0, 2):
+        ms = P.MultiSolver([_dev(w.labels) for w in ws], [w.sigma_table for w in ws], ws[0].h, precision="mixed",
+                           cg_window=win)
+        out[win] = ms.solve([_dev(w.a) for w in ws], tol=1e-11, max_iter=400)
+        ms.close()
+    assert out[0][1] == out[2][1]
+    assert all(torch.equal(a, b) for a, b in zip(out[0][0], out[2][0]))
+
+
 def _relmax(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
