@@ -35,7 +35,9 @@ struct Scal {
     int done;        // 1 = converged or stopped: later kernels of this solve return at once
     int iters;
     int status;      // 0 ok, 5 not converged, 6 breakdown
-    int hcount;      // search directions kept since x was last updated (CG steps of the current window)
+    int hcount;      // CG steps of the current window of kept search directions (the next one's slot)
+    int happlied;    // of these, the directions already added to x (an update of x before the window is full)
+    int pad;
 };
 
 constexpr int MAX_MODELS = 16;     // voxel models packed into one handle

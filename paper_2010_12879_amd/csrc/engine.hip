@@ -1477,19 +1477,19 @@ void pcg_step(Ctx *c, Scal *sc, int nb, int it, int max_iter)
     }
 }
 
-// x += sum alpha_j p_j over the steps of the window taken since the last update, then an empty window
-// (steps: how many the window holds, for the byte count)
-void x_flush(Ctx *c, Scal *sc, int nb, int steps)
+// x += sum alpha_j p_j over the steps of the window taken and not yet added; full: then an empty window
+// (steps: how many directions are added, for the byte count)
+void x_flush(Ctx *c, Scal *sc, int nb, int steps, bool full = true)
 {
     Level &L0 = c->lv[0];
     const double wp = c->opt.precision == SPFD_MIXED ? 4.0 : 8.0;
     TScope ts(c, SPFD_K_PUPDATE, (double)L0.dofs * (c->np ? 1 : nb) * (16.0 + steps * wp));
     if (c->opt.precision == SPFD_MIXED)
         HIPCHK(launch_x_flush<float>(cg_topo(c), c->d_x, (const float *)c->d_phist, c->phist_stride, c->d_ahist,
-                                     c->phist_len, sc, cg_batch(c, nb), c->stream));
+                                     c->phist_len, sc, cg_batch(c, nb), c->stream, full ? 1 : 0));
     else
         HIPCHK(launch_x_flush<double>(cg_topo(c), c->d_x, (const double *)c->d_phist, c->phist_stride, c->d_ahist,
-                                      c->phist_len, sc, cg_batch(c, nb), c->stream));
+                                      c->phist_len, sc, cg_batch(c, nb), c->stream, full ? 1 : 0));
 }
 
 void pcg_end(Ctx *c, Scal *sc, int nb, int steps)
@@ -1638,6 +1638,10 @@ void pcg_iterations(Ctx *c, Scal *sc, int nb, const spfd_solve_options &so)
         if (it + 1 <= so.max_iter && !likely_last()) {
             enqueue(it + 1);
             queued = it + 1;
+        } else if (queued == it) {
+            // step it+1 is held back: the GPU would idle during the host's poll, so x takes the directions
+            // kept so far now (the window goes on: they are only marked as added)
+            x_flush(c, sc, nb, (it + 1) % c->phist_len, false);
         }
         HIPCHK(hipEventSynchronize(c->ev_it[it & 1]));
         const Scal *hs = ring[it & 1];

@@ -184,10 +184,11 @@ int rupdate_parts(int nb);
 template <typename TZ>
 hipError_t launch_cg_step(const OpArgs<double> &op, Topo topo, const TZ *z, TZ *ph, long long hs, int nh, double *q,
                           double *part, Scal *sc, int first, const Batch &bt, hipStream_t s);
-// x += sum_j alpha_j p_j over the window's slots 0 .. hcount-1, in step order; then hcount = 0
+// x += sum_j alpha_j p_j over the window's slots happlied .. hcount-1, in step order; then (full) an empty
+// window, else happlied = hcount
 template <typename TP>
 hipError_t launch_x_flush(Topo topo, double *x, const TP *ph, long long hs, const double *ahist, int nh, Scal *sc,
-                          const Batch &bt, hipStream_t s);
+                          const Batch &bt, hipStream_t s, int full);
 // r -= alpha q, ||r||^2 partials, the FP32 copy of r; alpha also into the window slot hcount
 hipError_t launch_rupdate(Topo topo, double *r, const double *q, double *part, Scal *sc, const Batch &bt, float *r32,
                           hipStream_t s, double *ahist, int nh);

@@ -880,7 +880,7 @@ __global__ void k_scal_init(Scal *sc, double tol, int use_x0)
         sc->rr = bb;
         sc->tol2 = tol * tol * bb;
         sc->done = bb > 0.0 ? 0 : 1;
-        sc->iters = 0; sc->status = 0; sc->hcount = 0;
+        sc->iters = 0; sc->status = 0; sc->hcount = 0; sc->happlied = 0; sc->pad = 0;
     }
 }
 
@@ -1077,9 +1077,10 @@ hipError_t launch_rhs(const OpArgs<double> &op, Topo topo, const int4 *coord, co
     return hipGetLastError();
 }
 
-// x += sum_j alpha_j p_j over the search directions kept in the window (slots 0 .. hcount-1, filled in
-// step order), in step order: x receives the same sequence of updates as with one update per step,
-// whatever the window length.  k_hist_reset then starts the next window.
+// x += sum_j alpha_j p_j over the search directions kept in the window and not yet added (slots happlied ..
+// hcount-1, filled in step order), in step order: x receives the same sequence of updates as with one
+// update per step, whatever the window length and whenever the updates happen.  k_hist_reset then starts
+// the next window (full) or marks the directions added (an update before the window is full).
 template <typename TP>
 __global__ __launch_bounds__(NT) void k_x_flush(Topo topo, double *__restrict__ x, const TP *__restrict__ ph,
                                                 long long hs, const double *__restrict__ ahist, int nh, long long vs,
@@ -1090,7 +1091,8 @@ __global__ __launch_bounds__(NT) void k_x_flush(Topo topo, double *__restrict__ 
     if (bk < 0) return;
     const double *ah = ahist + (long long)blockIdx.y * nh;
     const int m = min(sc[blockIdx.y].hcount, nh);
-    if (m <= 0) return;
+    const int lo = max(sc[blockIdx.y].happlied, 0);
+    if (m <= lo) return;
     // a node column without unknowns holds zeros in x and every p: nothing to read or write
     if (topo.cmask && !((topo.cmask[bk] >> (threadIdx.x & 63)) & 1ull)) return;
     const long long n = blockIdx.y * vs + (long long)bk * BS + threadIdx.x;
@@ -1102,7 +1104,7 @@ __global__ __launch_bounds__(NT) void k_x_flush(Topo topo, double *__restrict__ 
     for (int j = 0; j < MAX_PHIST; ++j) {
         a[j] = 0.0;
         pv[j] = TP(0);
-        if (j < m) {
+        if (j >= lo && j < m) {
             a[j] = ah[j];
             pv[j] = ph[(long long)j * hs + n];
         }
@@ -1110,32 +1112,38 @@ __global__ __launch_bounds__(NT) void k_x_flush(Topo topo, double *__restrict__ 
     double xv = x[n];
 #pragma unroll
     for (int j = 0; j < MAX_PHIST; ++j)
-        if (j < m) xv = __builtin_fma(a[j], (double)pv[j], xv);
+        if (j >= lo && j < m) xv = __builtin_fma(a[j], (double)pv[j], xv);
     x[n] = xv;
 }
 
-// the next window starts empty
-__global__ void k_hist_reset(Scal *sc, int n)
+// full: the next window starts empty; else the window goes on, its directions so far marked as added
+__global__ void k_hist_reset(Scal *sc, int n, int full)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) sc[i].hcount = 0;
+    if (i >= n) return;
+    if (full) {
+        sc[i].hcount = 0;
+        sc[i].happlied = 0;
+    } else {
+        sc[i].happlied = sc[i].hcount;
+    }
 }
 
 template <typename TP>
 hipError_t launch_x_flush(Topo topo, double *x, const TP *ph, long long hs, const double *ahist, int nh, Scal *sc,
-                          const Batch &bt, hipStream_t s)
+                          const Batch &bt, hipStream_t s, int full)
 {
     if (topo.nb <= 0 || bt.n <= 0) return hipSuccess;
     if (nh < 2 || nh > MAX_PHIST || !ph || !ahist || !sc) return hipErrorInvalidValue;
     SPFD_LAUNCH(k_x_flush<TP>, dim3(xcd_grid(topo_count(topo)), bt.n), dim3(NT), 0, s, topo, x, ph, hs, ahist, nh,
                 bt.vs, sc);
-    SPFD_LAUNCH(k_hist_reset, dim3((bt.n + 63) / 64), dim3(64), 0, s, sc, bt.n);
+    SPFD_LAUNCH(k_hist_reset, dim3((bt.n + 63) / 64), dim3(64), 0, s, sc, bt.n, full);
     return hipGetLastError();
 }
 template hipError_t launch_x_flush<float>(Topo, double *, const float *, long long, const double *, int, Scal *,
-                                          const Batch &, hipStream_t);
+                                          const Batch &, hipStream_t, int);
 template hipError_t launch_x_flush<double>(Topo, double *, const double *, long long, const double *, int, Scal *,
-                                           const Batch &, hipStream_t);
+                                           const Batch &, hipStream_t, int);
 
 // r -= alpha q, ||r||^2 partials and the FP32 copy of r (x is updated once per window of steps, k_x_flush)
 __global__ __launch_bounds__(NT) void k_rupdate(Topo topo, double *__restrict__ r, const double *__restrict__ q,
