@@ -1,21 +1,23 @@
 // Dense inverse of the coarsest-level matrix by blocked Gauss-Jordan
-// elimination on 64x64 tiles, spread over many workgroups.
+// elimination on 64x64 tiles, one launch per tile step.
 //
 // The matrix (after the rank-one regularisation of every connected component,
 // which makes it symmetric positive definite) is copied into an ld x ld work
 // array, ld = n rounded up to 64, with the identity on the padding.  For each
-// diagonal tile k:
-//   P       = A_kk^-1                      (one workgroup, in LDS)
-//   A_kj   <- P A_kj  (j != k),  A_kk <- P (row block, one workgroup per tile)
-//   A_ij   <- A_ij - A_ik A_kj  (i, j != k), A_ik <- -A_ik P (all other tiles)
-// with the old column block A_ik saved before the row-block step.  No
-// pivoting is needed for a symmetric positive definite matrix.
+// diagonal tile k, with P = A_kk^-1:
+//   A_kk <- P,   A_kj <- P A_kj,   A_ik <- -A_ik P,
+//   A_ij <- A_ij - (A_ik P) A_kj            (i, j != k; old A_ik, A_kj)
+// Every tile of step k reads only the previous matrix and writes the next one
+// (two work matrices used in turn), so one launch covers the whole step; P of
+// the next step is formed by one workgroup from the new diagonal tile in
+// between.  No pivoting is needed for a symmetric positive definite matrix.
 #include "kernels.h"
 
 namespace spfd {
 
 constexpr int GT = 64;        // tile edge
 constexpr int GS = GT + 1;    // LDS row stride (bank spread)
+constexpr int GI = 4;         // columns per thread in the tile inverse (1024 threads: 16 per row)
 
 __global__ __launch_bounds__(256) void k_gj_pad(int n, int ld, const double *__restrict__ A, double *__restrict__ W)
 {
@@ -66,117 +68,130 @@ __device__ __forceinline__ void tile_mul(const double *a, const double *b, doubl
     }
 }
 
-// P = A_kk^-1 by Gauss-Jordan: for pivot p with a = A_pp,
-// A_pp <- 1/a, A_pj <- A_pj / a, A_ip <- -A_ip / a, A_ij <- A_ij - A_ip A_pj / a.
-// 1024 threads hold four entries each in registers (row i = t/16, columns
-// 4 (t%16) .. +3); per pivot only row p (with 1/a, formed once by its owner) and
-// column p pass through LDS.  They are published for pivot p + 1 by the threads
-// that hold them right after their update of pivot p, into the other of two LDS
-// buffers, so each pivot needs one barrier.
-__global__ __launch_bounds__(1024) void k_gj_diag(int ld, int k0, const double *__restrict__ W, double *__restrict__ P)
+// In-place Gauss-Jordan inverse of a 64x64 tile held by 1024 threads: thread
+// t holds row t/16, columns 4 (t%16) .. +3.  For pivot p with d = A_pp:
+//   A_pj <- A_pj / d (j != p),  A_pp <- 1/d,
+//   A_ij <- A_ij - (A_ip / d) A_pj (i, j != p),  A_ip <- -A_ip / d,
+// that is, one multiply-add per entry once row p carries 1 in place of d and
+// the entries of column p outside row p start from 0.  Row p (with 1/d
+// beside it) and column p pass through LDS; the threads that own row and
+// column p + 1 publish them right after their update for pivot p, into the
+// other of two buffers, so each pivot needs one barrier.
+struct InvLds {
+    double row[2][GT + 2];   // [GT]: reciprocal pivot; rows 16-byte aligned for wide loads
+    double col[2][GT];
+};
+
+__device__ __forceinline__ void tile_inverse(double a[GI], InvLds &L)
 {
-    __shared__ double row[2][GT + 1], col[2][GT];   // row[.][GT] = 1 / pivot
-    const int t = threadIdx.x;
-    const int i = t >> 4, j0 = (t & 15) * 4;
-    double a[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) a[q] = W[(long long)(k0 + i) * ld + k0 + j0 + q];
-    // publish row and column 0
+    const int i = threadIdx.x >> 4, j0 = (threadIdx.x & 15) * GI;
     auto publish = [&](int p, int buf) {
+        const bool mine = p >= j0 && p < j0 + GI;
+        double d = 0.0;
+#pragma unroll
+        for (int q = 0; q < GI; ++q)
+            if (j0 + q == p) d = a[q];
         if (i == p) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                row[buf][j0 + q] = a[q];
-                if (j0 + q == p) row[buf][GT] = 1.0 / a[q];
-            }
+            for (int q = 0; q < GI; ++q) L.row[buf][j0 + q] = (j0 + q == p) ? 1.0 : a[q];
+            if (mine) L.row[buf][GT] = 1.0 / d;
         }
-        if (p >= j0 && p < j0 + 4) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (j0 + q == p) col[buf][i] = a[q];
-        }
+        if (mine) L.col[buf][i] = d;
     };
     publish(0, 0);
     __syncthreads();
     for (int p = 0; p < GT; ++p) {
         const int cur = p & 1;
-        const double piv = row[cur][GT];
-        const double ci = col[cur][i];
+        const double piv = L.row[cur][GT];
+        if (i == p) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int j = j0 + q;
-            const double rpj = (j == p) ? 1.0 : row[cur][j];
-            a[q] = (i == p) ? rpj * piv : (j == p ? 0.0 : a[q]) - ci * piv * rpj;
+            for (int q = 0; q < GI; ++q) a[q] = L.row[cur][j0 + q] * piv;
+        } else {
+            const double cp = L.col[cur][i] * piv;
+#pragma unroll
+            for (int q = 0; q < GI; ++q) a[q] = __builtin_fma(-cp, L.row[cur][j0 + q], (j0 + q == p) ? 0.0 : a[q]);
         }
         if (p + 1 < GT) publish(p + 1, cur ^ 1);
         __syncthreads();
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) P[i * GT + j0 + q] = a[q];
 }
 
-// row block k <- P A_k*, A_kk <- P; and the old column block (rows outside k) into C [ld][64]
-__global__ __launch_bounds__(256) void k_gj_row(int ld, int k0, double *__restrict__ W, const double *__restrict__ P,
-                                                double *__restrict__ C)
+// P = A_kk^-1 (the diagonal tile of step k)
+__global__ __launch_bounds__(1024) void k_gj_diag(int ld, int k0, const double *__restrict__ W, double *__restrict__ P)
 {
-    __shared__ double p[GT * GS];
-    __shared__ double a[GT * GS];
-    const int j0 = blockIdx.x * GT;
-    // column block piece: rows j0..j0+63 of columns k0..k0+63 (not written by any workgroup here)
-    if (j0 != k0)
-        for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) {
-            const int r = e / GT, c = e % GT;
-            C[(long long)(j0 + r) * GT + c] = W[(long long)(j0 + r) * ld + k0 + c];
-        }
-    for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) p[(e / GT) * GS + e % GT] = P[e];
-    if (j0 == k0) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < GT * GT; e += blockDim.x)
-            W[(long long)(k0 + e / GT) * ld + k0 + e % GT] = p[(e / GT) * GS + e % GT];
+    __shared__ __align__(16) InvLds L;
+    const int i = threadIdx.x >> 4, j0 = (threadIdx.x & 15) * GI;
+    double a[GI];
+#pragma unroll
+    for (int q = 0; q < GI; ++q) a[q] = W[(long long)(k0 + i) * ld + k0 + j0 + q];
+    tile_inverse(a, L);
+#pragma unroll
+    for (int q = 0; q < GI; ++q) P[i * GT + j0 + q] = a[q];
+}
+
+// Step k: tile (blockIdx.y, blockIdx.x) of Wn from Wo and P = (Wo)_kk^-1
+__global__ __launch_bounds__(256) void k_gj_step(int ld, int k, const double *__restrict__ Wo,
+                                                 double *__restrict__ Wn, const double *__restrict__ P)
+{
+    __shared__ double t0[GT * GS];
+    __shared__ double t1[GT * GS];
+    __shared__ double t2[GT * GS];
+    const int bi = blockIdx.y, bj = blockIdx.x;
+    const int k0 = k * GT, i0 = bi * GT, j0 = bj * GT;
+    const int r0 = (threadIdx.x >> 4) * 4, c0 = (threadIdx.x & 15) * 4;
+    double acc[4][4];
+    if (bi == k && bj == k) {   // A_kk <- P
+        for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) Wn[(long long)(k0 + e / GT) * ld + k0 + e % GT] = P[e];
         return;
     }
-    tile_load(W, ld, k0, j0, a);
-    __syncthreads();
-    double acc[4][4];
-    tile_mul(p, a, acc);
-    const int r0 = (threadIdx.x >> 4) * 4, c0 = (threadIdx.x & 15) * 4;
+    if (bi == k || bj == k) {   // row block: P A_kj;  column block: -A_ik P
+        if (bi == k) {
+            for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) t0[(e / GT) * GS + e % GT] = P[e];
+            tile_load(Wo, ld, k0, j0, t1);
+        } else {
+            tile_load(Wo, ld, i0, k0, t0);
+            for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) t1[(e / GT) * GS + e % GT] = P[e];
+        }
+        __syncthreads();
+        tile_mul(t0, t1, acc);
+        const double sg = bi == k ? 1.0 : -1.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) Wn[(long long)(i0 + r0 + i) * ld + j0 + c0 + j] = sg * acc[i][j];
+        return;
+    }
+    // other tiles: A_ij - (A_ik P) A_kj; all three tiles and the old A_ij loaded up front
+    double old[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) W[(long long)(k0 + r0 + i) * ld + j0 + c0 + j] = acc[i][j];
-}
-
-// every tile outside row block k: A_ij -= C_i A_kj (j != k), A_ik = -C_i P
-__global__ __launch_bounds__(256) void k_gj_update(int ld, int k0, double *__restrict__ W,
-                                                   const double *__restrict__ P, const double *__restrict__ C)
-{
-    __shared__ double ct[GT * GS];
-    __shared__ double rt[GT * GS];
-    const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
-    if (i0 == k0) return;
-    for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) ct[(e / GT) * GS + e % GT] = C[(long long)(i0 + e / GT) * GT + e % GT];
-    if (j0 == k0) {
-        for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) rt[(e / GT) * GS + e % GT] = P[e];
-    } else {
-        tile_load(W, ld, k0, j0, rt);
-    }
+        for (int j = 0; j < 4; ++j) old[i][j] = Wo[(long long)(i0 + r0 + i) * ld + j0 + c0 + j];
+    tile_load(Wo, ld, i0, k0, t0);
+    for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) t1[(e / GT) * GS + e % GT] = P[e];
+    tile_load(Wo, ld, k0, j0, t2);
     __syncthreads();
-    double acc[4][4];
-    tile_mul(ct, rt, acc);
-    const int r0 = (threadIdx.x >> 4) * 4, c0 = (threadIdx.x & 15) * 4;
+    tile_mul(t0, t1, acc);      // T = A_ik P
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t0[(r0 + i) * GS + c0 + j] = acc[i][j];
+    __syncthreads();
+    tile_mul(t0, t2, acc);      // T A_kj
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            double *w = W + (long long)(i0 + r0 + i) * ld + j0 + c0 + j;
-            *w = (j0 == k0) ? -acc[i][j] : *w - acc[i][j];
+            acc[i][j] = old[i][j] - acc[i][j];
+            Wn[(long long)(i0 + r0 + i) * ld + j0 + c0 + j] = acc[i][j];
         }
 }
 
 size_t dense_inverse_work_doubles(int n)
 {
     const long long ld = ((long long)n + GT - 1) / GT * GT;
-    return (size_t)(ld * ld + ld * GT + GT * GT);
+    return (size_t)(2 * ld * ld + GT * GT);
 }
 
 hipError_t launch_dense_inverse(int n, double *A, double *work, hipStream_t s)
@@ -184,16 +199,15 @@ hipError_t launch_dense_inverse(int n, double *A, double *work, hipStream_t s)
     if (n <= 0) return hipSuccess;
     const int ld = (n + GT - 1) / GT * GT;
     const int nt = ld / GT;
-    double *W = work, *C = work + (long long)ld * ld, *P = C + (long long)ld * GT;
+    double *W[2] = {work, work + (long long)ld * ld};
+    double *P = work + 2LL * ld * ld;
     auto blocks = [](long long m) { return (unsigned)((m + 255) / 256 > 65536 ? 65536 : (m + 255) / 256); };
-    SPFD_LAUNCH(k_gj_pad, dim3(blocks((long long)ld * ld)), dim3(256), 0, s, n, ld, A, W);
+    SPFD_LAUNCH(k_gj_pad, dim3(blocks((long long)ld * ld)), dim3(256), 0, s, n, ld, A, W[0]);
     for (int k = 0; k < nt; ++k) {
-        const int k0 = k * GT;
-        SPFD_LAUNCH(k_gj_diag, dim3(1), dim3(1024), 0, s, ld, k0, W, P);
-        SPFD_LAUNCH(k_gj_row, dim3(nt), dim3(256), 0, s, ld, k0, W, P, C);
-        SPFD_LAUNCH(k_gj_update, dim3(nt, nt), dim3(256), 0, s, ld, k0, W, P, C);
+        SPFD_LAUNCH(k_gj_diag, dim3(1), dim3(1024), 0, s, ld, k * GT, W[k & 1], P);
+        SPFD_LAUNCH(k_gj_step, dim3(nt, nt), dim3(256), 0, s, ld, k, W[k & 1], W[(k + 1) & 1], P);
     }
-    SPFD_LAUNCH(k_gj_unpad, dim3(blocks((long long)n * n)), dim3(256), 0, s, n, ld, W, A);
+    SPFD_LAUNCH(k_gj_unpad, dim3(blocks((long long)n * n)), dim3(256), 0, s, n, ld, W[nt & 1], A);
     return hipGetLastError();
 }
 
