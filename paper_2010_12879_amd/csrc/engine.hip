@@ -992,6 +992,70 @@ void tune_segments(Ctx *c)
     }
 }
 
+// Zeroes up to ZL_MAX device ranges in one launch (one grid row per range),
+// in place of one hipMemsetAsync per buffer: each memset call costs as much
+// host time as a kernel launch.  Ranges start 16-byte aligned (every buffer
+// here is a whole allocation) and hold whole 4-byte words.
+constexpr int ZL_MAX = 32;
+struct ZeroList {
+    int n = 0;
+    void *ptr[ZL_MAX];
+    unsigned long long bytes[ZL_MAX];
+};
+
+__global__ __launch_bounds__(256) void k_zero_list(ZeroList zl)
+{
+    uint8_t *p = (uint8_t *)zl.ptr[blockIdx.y];
+    const unsigned long long nb = zl.bytes[blockIdx.y];
+    const unsigned long long n16 = nb / 16, t = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (unsigned long long i = t; i < n16; i += (unsigned long long)gridDim.x * blockDim.x)
+        ((uint4 *)p)[i] = make_uint4(0u, 0u, 0u, 0u);
+    const unsigned long long tail = n16 * 16 + 4 * t;   // the last (< 16) bytes, one word per thread
+    if (tail < nb) *(unsigned *)(p + tail) = 0u;
+}
+
+// queue zeroing of [p, p + bytes): into the list, or by memset when the list is full or the range does not
+// fit the kernel's alignment
+void zero_add(Ctx *c, ZeroList &zl, void *p, size_t bytes)
+{
+    if (!p || bytes == 0) return;
+    if (zl.n == ZL_MAX || ((uintptr_t)p & 15) || (bytes & 3)) {
+        HIPCHK(hipMemsetAsync(p, 0, bytes, c->stream));
+        return;
+    }
+    zl.ptr[zl.n] = p;
+    zl.bytes[zl.n] = bytes;
+    ++zl.n;
+}
+
+void zero_flush(Ctx *c, ZeroList &zl)
+{
+    if (zl.n == 0) return;
+    unsigned long long mx = 0;
+    for (int i = 0; i < zl.n; ++i) mx = std::max(mx, zl.bytes[i]);
+    const unsigned long long need = (mx / 16 + 255) / 256;
+    const unsigned gx = (unsigned)std::max<unsigned long long>(1, std::min<unsigned long long>(need, 1024));
+    hipLaunchKernelGGL(k_zero_list, dim3(gx, (unsigned)zl.n), dim3(256), 0, c->stream, zl);
+    HIPCHK(hipGetLastError());
+    zl.n = 0;
+}
+
+// Zeroes the node columns without unknowns (clear bits of each brick's column
+// mask) of nv consecutive vectors of the finest level's layout, one wave per
+// brick.  No kernel writes those slots, but the stencils of neighbouring
+// columns read them (with conductance 0), so they must hold finite values.
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero_empty_cols(const unsigned long long *__restrict__ cmask, int nb,
+                                                         long long nodes, int nv, T *__restrict__ v)
+{
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (b >= nb || ((cmask[b] >> lane) & 1ull)) return;
+    T *p = v + (long long)b * BS + lane;
+    for (int y = 0; y < nv; ++y, p += nodes)
+#pragma unroll
+        for (int z = 0; z < BD; ++z) p[64 * z] = T(0);
+}
+
 // solve buffers for nb right sides: cycle vectors of every level, the outer
 // CG vectors and the partial sums
 void alloc_cycle_buffers(Ctx *c, int nb)
@@ -1007,6 +1071,7 @@ void alloc_cycle_buffers(Ctx *c, int nb)
     const size_t w = mixed ? sizeof(float) : sizeof(double);
     const int nvec = c->np ? 1 : nb;   // packed models share one vector of each kind
     c->nbat_vec = nvec;
+    ZeroList zl;
     for (size_t l = 0; l < c->lv.size(); ++l) {
         Level &L = c->lv[l];
         const size_t n = (size_t)L.nodes() * nvec;
@@ -1014,10 +1079,10 @@ void alloc_cycle_buffers(Ctx *c, int nb)
         L.x2 = dalloc<uint8_t>(c, c->rhs_allocs, n * w);
         L.d = dalloc<uint8_t>(c, c->rhs_allocs, n * w);
         L.b = dalloc<uint8_t>(c, c->rhs_allocs, n * w);
-        HIPCHK(hipMemsetAsync(L.x, 0, n * w, c->stream));
-        HIPCHK(hipMemsetAsync(L.x2, 0, n * w, c->stream));
-        HIPCHK(hipMemsetAsync(L.d, 0, n * w, c->stream));
-        HIPCHK(hipMemsetAsync(L.b, 0, n * w, c->stream));
+        zero_add(c, zl, L.x, n * w);
+        zero_add(c, zl, L.x2, n * w);
+        zero_add(c, zl, L.d, n * w);
+        zero_add(c, zl, L.b, n * w);
     }
     const size_t n0 = (size_t)c->lv[0].nodes() * nvec;
     c->d_x = dalloc<double>(c, c->rhs_allocs, n0);
@@ -1034,24 +1099,42 @@ void alloc_cycle_buffers(Ctx *c, int nb)
         c->phist_len = (int)h;
         c->phist_stride = (long long)n0;
         c->d_phist = dalloc<uint8_t>(c, c->rhs_allocs, h * per);
-        HIPCHK(hipMemsetAsync(c->d_phist, 0, h * per, c->stream));
+        // every step writes all nodes of the columns with unknowns of its slot before a later step reads
+        // them, so only the other columns are cleared; packed models stop one by one (a stopped model's
+        // bricks keep whatever the allocation held, and a neighbouring model's stencil may read them):
+        // all of it
+        const Level &L0 = c->lv[0];
+        if (c->np || !L0.d_cmask) {
+            zero_add(c, zl, c->d_phist, h * per);
+        } else if (L0.nb > 0) {
+            const dim3 grid((unsigned)((L0.nb + 3) / 4));
+            const int nv = (int)(h * nvec);
+            if (mixed)
+                hipLaunchKernelGGL(k_zero_empty_cols<float>, grid, dim3(256), 0, c->stream, L0.d_cmask, L0.nb,
+                                   L0.nodes(), nv, (float *)c->d_phist);
+            else
+                hipLaunchKernelGGL(k_zero_empty_cols<double>, grid, dim3(256), 0, c->stream, L0.d_cmask, L0.nb,
+                                   L0.nodes(), nv, (double *)c->d_phist);
+            HIPCHK(hipGetLastError());
+        }
         c->d_ahist = dalloc<double>(c, c->rhs_allocs, (size_t)nb * h);
-        HIPCHK(hipMemsetAsync(c->d_ahist, 0, (size_t)nb * h * sizeof(double), c->stream));
+        zero_add(c, zl, c->d_ahist, (size_t)nb * h * sizeof(double));
     }
     c->d_z = dalloc<uint8_t>(c, c->rhs_allocs, n0 * w);
     c->d_r32 = mixed ? dalloc<float>(c, c->rhs_allocs, n0) : nullptr;
     // every vector starts at zero: slots of node columns without unknowns are never written and must
     // read as (finite) zeros, since stencils multiply them by conductance 0
-    HIPCHK(hipMemsetAsync(c->d_x, 0, n0 * sizeof(double), c->stream));
-    HIPCHK(hipMemsetAsync(c->d_r, 0, n0 * sizeof(double), c->stream));
-    HIPCHK(hipMemsetAsync(c->d_z, 0, n0 * w, c->stream));
-    if (c->d_r32) HIPCHK(hipMemsetAsync(c->d_r32, 0, n0 * sizeof(float), c->stream));
-    HIPCHK(hipMemsetAsync(c->d_q, 0, n0 * sizeof(double), c->stream));
+    zero_add(c, zl, c->d_x, n0 * sizeof(double));
+    zero_add(c, zl, c->d_r, n0 * sizeof(double));
+    zero_add(c, zl, c->d_z, n0 * w);
+    zero_add(c, zl, c->d_r32, n0 * sizeof(float));
+    zero_add(c, zl, c->d_q, n0 * sizeof(double));
     c->pstride = 2 * c->lv[0].nb + 64;
     c->d_part = dalloc<double>(c, c->rhs_allocs, (size_t)c->pstride * nb);
-    HIPCHK(hipMemsetAsync(c->d_part, 0, (size_t)c->pstride * nb * sizeof(double), c->stream));
+    zero_add(c, zl, c->d_part, (size_t)c->pstride * nb * sizeof(double));
     c->d_nostop = dalloc<Scal>(c, c->rhs_allocs, nb);
-    HIPCHK(hipMemsetAsync(c->d_nostop, 0, (size_t)nb * sizeof(Scal), c->stream));
+    zero_add(c, zl, c->d_nostop, (size_t)nb * sizeof(Scal));
+    zero_flush(c, zl);
     c->nbat = nb;
 }
 
