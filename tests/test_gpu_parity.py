@@ -229,6 +229,43 @@ def test_level_info():
         P.spfd_destroy(h)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rebuild_with_other_conducting_set_same_bits(prec):
+    """Rebuilds on one handle reuse its buffers; a tissue switched to sigma = 0 and back changes which node
+    columns hold unknowns (the solve buffers clear only the others).  Each solve equals a fresh handle's
+    at the same conductivities bit for bit."""
+    print(f"case rebuild conducting set {prec}", flush=True)
+    w = W.random_ellipsoid_phantom(40, 36, 48, seed=53, n_ell=14, semi_range=(3.0, 10.0))
+    lab, cnt = np.unique(w.labels[w.labels > 0], return_counts=True)
+    t1 = np.array(w.sigma_table, dtype=float)
+    t2 = t1.copy()
+    t2[lab[np.argmax(cnt)]] = 0.0            # the most frequent tissue stops conducting
+    t2 *= 1.7
+    a = _dev(w.a)
+
+    def fresh(table):
+        f = P.Solver(_dev(w.labels), list(table), w.h, precision=prec)
+        out = f.solve(a, tol=1e-11, max_iter=400)
+        f.close()
+        return out
+
+    s = P.Solver(_dev(w.labels), list(t1), w.h, precision=prec)
+    p1, i1 = s.solve(a, tol=1e-11, max_iter=400)
+    s.set_sigma(list(t2))
+    p2, i2 = s.solve(a, tol=1e-11, max_iter=400)
+    s.set_sigma(list(t1))
+    p3, i3 = s.solve(a, tol=1e-11, max_iter=400)
+    s.close()
+    r1, j1 = fresh(t1)
+    r2, j2 = fresh(t2)
+    assert i1["status"] == "OK" and i2["status"] == "OK"
+    assert i1 == j1 and i3 == j1 and i2 == j2
+    assert torch.equal(p1, r1) and torch.equal(p3, r1) and torch.equal(p2, r2)
+    assert not torch.equal(p1, p2)
+    rel = oracle.residual(t2[w.labels], w.h, w.a, p2.cpu().numpy())
+    assert rel <= 1e-11 * 1.01, rel
+
+
 def test_warm_start_and_determinism():
     print("case warm start", flush=True)
     w = W.config(1)
