@@ -95,7 +95,7 @@ typedef struct {
                              2^15, unless the smallest nonzero weight would then fall below FP16's normal
                              range (then FP32 weights are kept); nonzero: always FP32 weights */
     int cg_window;        /* CG search directions kept (in the cycle's precision) before x is updated from
-                             them: 0 (default) = up to 32, as many as fit in about 4 GiB for the handle's
+                             them: 0 (default) = up to 32, as many as fit in about 16 GiB for the handle's
                              right sides, at least 2; else an even number 2..32.  x receives the same
                              updates in the same order whatever the window (the results are bitwise the
                              same); a longer window saves reading and writing x in FP64 per CG step */

@@ -1088,12 +1088,12 @@ void alloc_cycle_buffers(Ctx *c, int nb)
     c->d_x = dalloc<double>(c, c->rhs_allocs, n0);
     c->d_r = dalloc<double>(c, c->rhs_allocs, n0);
     c->d_q = dalloc<double>(c, c->rhs_allocs, n0);
-    // window of search directions (cg_window, or by default up to MAX_PHIST steps within about 4 GiB, at
+    // window of search directions (cg_window, or by default up to MAX_PHIST steps within about 16 GiB, at
     // least two), an even count (the step graphs alternate the two slots of the host ring); a 1e-8 solve
     // of the 8.9 M-unknown body takes 21 steps, so x is updated once at its end
     {
         const size_t per = n0 * w;
-        size_t h = per ? ((size_t)4 << 30) / per : (size_t)MAX_PHIST;
+        size_t h = per ? ((size_t)16 << 30) / per : (size_t)MAX_PHIST;
         if (c->opt.cg_window > 0) h = (size_t)c->opt.cg_window;
         h = std::max<size_t>(2, std::min<size_t>(MAX_PHIST, h)) & ~(size_t)1;
         c->phist_len = (int)h;
