@@ -128,6 +128,7 @@ struct Ctx {
     Scal *h_scal = nullptr;   // pinned, one per right side plus one for the adjoint solve
     Scal *h_ring = nullptr;   // pinned, 2 x (nrhs + 1): scalars of the last two enqueued CG steps
     Scal *h_ring_dev = nullptr;   // device address of h_ring (written by the last kernel of a CG step)
+    int h_cap = 0;                // right sides h_scal and h_ring hold (plus one each)
     Scal *d_nostop = nullptr;     // zeroed scalars (never stopped) for cycles run outside a CG step
     Scal *step_mirror = nullptr;  // where the CG step being enqueued leaves its scalars
     hipEvent_t ev_it[2] = {nullptr, nullptr};
@@ -1433,16 +1434,26 @@ spfd_status do_set_num_rhs(Ctx *c, int nrhs)
     c->d_scal = dalloc<Scal>(c, c->src_allocs, nrhs);
     c->d_again = dalloc<int>(c, c->src_allocs, nrhs + 1);
     HIPCHK(hipMemsetAsync(c->d_scal, 0, nrhs * sizeof(Scal), c->stream));
-    if (c->h_scal) (void)hipHostFree(c->h_scal);
-    c->h_scal = nullptr;
-    if (c->h_ring) (void)hipHostFree(c->h_ring);
-    c->h_ring = nullptr;
-    HIPCHK(hipHostMalloc((void **)&c->h_scal, sizeof(Scal) * (nrhs + 1), hipHostMallocDefault));
-    // coherent: the step's last kernel stores the scalars here, the host reads them after an event
-    HIPCHK(hipHostMalloc((void **)&c->h_ring, sizeof(Scal) * 2 * (nrhs + 1),
-                         hipHostMallocMapped | hipHostMallocCoherent));
-    HIPCHK(hipHostGetDevicePointer((void **)&c->h_ring_dev, c->h_ring, 0));
     drop_graphs(c);
+    // pinned host scalars: kept while they hold enough right sides (a pinned allocation costs ~50-100 us of
+    // host time, every rebuild passes here), cleared once the stream is idle (no step writes the ring)
+    if (c->h_scal && c->h_ring && c->h_cap >= nrhs) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        memset(c->h_scal, 0, sizeof(Scal) * (c->h_cap + 1));
+        memset(c->h_ring, 0, sizeof(Scal) * 2 * (c->h_cap + 1));
+    } else {
+        if (c->h_scal) (void)hipHostFree(c->h_scal);
+        c->h_scal = nullptr;
+        if (c->h_ring) (void)hipHostFree(c->h_ring);
+        c->h_ring = nullptr;
+        c->h_cap = 0;
+        HIPCHK(hipHostMalloc((void **)&c->h_scal, sizeof(Scal) * (nrhs + 1), hipHostMallocDefault));
+        // coherent: the step's last kernel stores the scalars here, the host reads them after an event
+        HIPCHK(hipHostMalloc((void **)&c->h_ring, sizeof(Scal) * 2 * (nrhs + 1),
+                             hipHostMallocMapped | hipHostMallocCoherent));
+        HIPCHK(hipHostGetDevicePointer((void **)&c->h_ring_dev, c->h_ring, 0));
+        c->h_cap = nrhs;
+    }
     c->nrhs = nrhs;
     alloc_cycle_buffers(c, nrhs);
     HIPCHK(hipStreamSynchronize(c->stream));
