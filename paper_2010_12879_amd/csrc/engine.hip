@@ -73,6 +73,10 @@ struct Level {
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // second stream of the build (default priority): the connected components run there beside the
+    // coarsening, joined before the build returns
+    hipStream_t side = nullptr;
+    hipEvent_t ev_side[2] = {nullptr, nullptr};   // weights ready (main -> side), components done (side -> main)
     std::string err;
     // geometry
     int state = 0;  // 0 created, 1 geometry, 2 sigma, 3 built, 4 sources
@@ -1222,6 +1226,7 @@ Level split_level(Ctx *c, Level &F)
 spfd_status do_build(Ctx *c)
 {
     drop_graphs(c);
+    HIPCHK(hipStreamSynchronize(c->side));   // an earlier build that failed may have left its components running
     free_all(c, c->hier_allocs);
     c->d_adj_b = c->d_adj_c = c->d_adj_lam = c->d_adj_labpart = c->d_adj_labout = nullptr;
     c->d_adj_scal = nullptr;
@@ -1261,7 +1266,10 @@ spfd_status do_build(Ctx *c)
         L0.d_tiles = dalloc<uint8_t>(c, c->hier_allocs, (size_t)L0.nb * TILE_BYTES);
         HIPCHK(launch_label_tiles(c->d_labels, g, L0.d_coord, L0.nb, L0.d_tiles, c->stream));
     }
-    // 3. connected components of the conductor (the gauge of Eq. (3))
+    // 3. connected components of the conductor (the gauge of Eq. (3)): on the side stream, beside the
+    //    coarsening, which needs only the number of unknowns (the nodes with a positive diagonal, counted
+    //    here); joined at the end of the build
+    int *d_ncomp = dalloc<int>(c, c->hier_allocs, 1);
     {
         const long long n = L0.nodes();
         int *parent = dalloc<int>(c, c->hier_allocs, n);
@@ -1269,22 +1277,11 @@ spfd_status do_build(Ctx *c)
         int *idx = dalloc<int>(c, c->hier_allocs, n);
         int *tmp = dalloc<int>(c, c->hier_allocs, n / 2048 + 2);
         c->d_comp = dalloc<int>(c, c->hier_allocs, n);
-        HIPCHK(launch_components(L0.d_w64, n, L0.topo(), parent, flag, idx, tmp, c->d_comp, nullptr, c->d_ints, c->stream));
-        HIPCHK(hipMemcpyAsync(c->h_ints, c->d_ints, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        c->ncomp = c->h_ints[0];
-        c->d_counts = dalloc<int>(c, c->hier_allocs, c->ncomp + 1);
-        c->d_means = dalloc<double>(c, c->hier_allocs, c->ncomp + 1);
-        c->d_cpart = dalloc<double>(c, c->hier_allocs, comp_mean_parts(L0.nb));
-        HIPCHK(hipMemsetAsync(c->d_counts, 0, (c->ncomp + 1) * sizeof(int), c->stream));
-        HIPCHK(launch_comp_counts(c->d_comp, n, c->d_counts, c->stream));
-        // the unknowns of the finest level are the nodes of the components
-        int *hc = (int *)stage(c, (size_t)(c->ncomp + 1) * sizeof(int));
-        HIPCHK(hipMemcpyAsync(hc, c->d_counts, (size_t)c->ncomp * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        long long nd = 0;
-        for (int k = 0; k < c->ncomp; ++k) nd += hc[k];
-        L0.dofs = nd;
+        HIPCHK(hipEventRecord(c->ev_side[0], c->stream));
+        HIPCHK(hipStreamWaitEvent(c->side, c->ev_side[0], 0));
+        HIPCHK(launch_components(L0.d_w64, n, L0.topo(), parent, flag, idx, tmp, c->d_comp, nullptr, d_ncomp, c->side));
+        HIPCHK(hipEventRecord(c->ev_side[1], c->side));
+        L0.dofs = count_dofs(c, L0);
     }
     // 4. coarsening: 2x2x2 aggregation until the level is small enough; from
     //    level split_level on, aggregates are split into their connected pieces
@@ -1377,6 +1374,20 @@ spfd_status do_build(Ctx *c)
                                                 c->d_Ainv, c->stream));
         double *dwork = dalloc<double>(c, c->hier_allocs, dense_inverse_work_doubles(c->ncoarse));
         HIPCHK(launch_coarse_factor(c->ncoarse, c->d_Ainv, c->d_cwork, dwork, c->stream));
+    }
+    // join the components: their count sizes the gauge's buffers
+    {
+        HIPCHK(hipStreamWaitEvent(c->stream, c->ev_side[1], 0));
+        HIPCHK(hipMemcpyAsync(c->h_ints, d_ncomp, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        c->ncomp = c->h_ints[0];
+        const Level &F0 = c->lv[0];   // (the coarsening above may have moved the level vector)
+        const long long n = F0.nodes();
+        c->d_counts = dalloc<int>(c, c->hier_allocs, c->ncomp + 1);
+        c->d_means = dalloc<double>(c, c->hier_allocs, c->ncomp + 1);
+        c->d_cpart = dalloc<double>(c, c->hier_allocs, comp_mean_parts(F0.nb));
+        HIPCHK(hipMemsetAsync(c->d_counts, 0, (c->ncomp + 1) * sizeof(int), c->stream));
+        HIPCHK(launch_comp_counts(c->d_comp, n, c->d_counts, c->stream));
     }
     // column masks of the structured levels (the stencil kernels skip columns without unknowns) and
     // the inverse diagonals (first Chebyshev steps folded into neighbouring kernels)
@@ -2180,6 +2191,8 @@ spfd_status spfd_create(int device, void *hip_stream, const spfd_allocator *allo
         HIPCHK(hipSetDevice(device));
         // own stream (default priority, no implicit sync with the null stream), ordered after the caller's
         HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        for (hipEvent_t &e : c->ev_side) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->ev_user, hipEventDisableTiming));
         for (hipEvent_t &e : c->ev_it) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         c->d_ints = dalloc<int>(c, c->geo_allocs, 64);
@@ -2189,6 +2202,9 @@ spfd_status spfd_create(int device, void *hip_stream, const spfd_allocator *allo
         if (c->ev_user) (void)hipEventDestroy(c->ev_user);
         for (hipEvent_t e : c->ev_it)
             if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : c->ev_side)
+            if (e) (void)hipEventDestroy(e);
+        if (c->side) (void)hipStreamDestroy(c->side);
         if (c->stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return f.e == hipErrorOutOfMemory ? SPFD_OUT_OF_MEMORY : SPFD_HIP_ERROR;
@@ -2202,6 +2218,7 @@ void spfd_destroy(spfd_handle h)
     if (!h) return;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
+    if (h->side) (void)hipStreamSynchronize(h->side);
     drop_graphs(h);
     release_device(h);
     if (h->h_scal) (void)hipHostFree(h->h_scal);
@@ -2213,6 +2230,9 @@ void spfd_destroy(spfd_handle h)
     for (int k = 0; k < SPFD_K_COUNT; ++k)
         for (hipEvent_t e : h->tev[k]) (void)hipEventDestroy(e);
     if (h->ev_user) (void)hipEventDestroy(h->ev_user);
+    for (hipEvent_t e : h->ev_side)
+        if (e) (void)hipEventDestroy(e);
+    if (h->side) (void)hipStreamDestroy(h->side);
     if (h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }
@@ -2229,6 +2249,7 @@ spfd_status set_geometry(spfd_handle h, int nx, int ny, int nz, double hx, doubl
         HIPCHK(hipSetDevice(h->device));
         enter(h);
         HIPCHK(hipStreamSynchronize(h->stream));
+        HIPCHK(hipStreamSynchronize(h->side));
         free_all(h, h->rhs_allocs);
         free_all(h, h->hier_allocs);
         free_all(h, h->geo_allocs);
