@@ -138,9 +138,12 @@ typedef struct {
 } spfd_allocator;
 
 /* Create a handle on HIP device `device`; `hip_stream` is a hipStream_t (NULL
- * = default stream).  alloc (host, nullable; copied): the allocator of the
- * handle's device memory, hipMalloc/hipFree when NULL or when both of its
- * functions are NULL; SPFD_INVALID_ARG when only one of them is given. */
+ * = default stream).  Each call orders its work after the work already on
+ * hip_stream and runs it on streams the handle owns (default priority;
+ * spfd_build overlaps two parts of the setup on two of them).  alloc (host,
+ * nullable; copied): the allocator of the handle's device memory,
+ * hipMalloc/hipFree when NULL or when both of its functions are NULL;
+ * SPFD_INVALID_ARG when only one of them is given. */
 spfd_status spfd_create(int device, void *hip_stream, const spfd_allocator *alloc, spfd_handle *out);
 void spfd_destroy(spfd_handle h);
 /* Message of the last failing call on h (valid until the next call on h). */
