@@ -1280,7 +1280,6 @@ spfd_status do_build(Ctx *c)
         HIPCHK(hipEventRecord(c->ev_side[0], c->stream));
         HIPCHK(hipStreamWaitEvent(c->side, c->ev_side[0], 0));
         HIPCHK(launch_components(L0.d_w64, n, L0.topo(), parent, flag, idx, tmp, c->d_comp, nullptr, d_ncomp, c->side));
-        HIPCHK(hipEventRecord(c->ev_side[1], c->side));
         L0.dofs = count_dofs(c, L0);
     }
     // 4. coarsening: 2x2x2 aggregation until the level is small enough; from
@@ -1346,6 +1345,23 @@ spfd_status do_build(Ctx *c)
         c->lv.push_back(std::move(C));
         c->lv.back().dofs = count_dofs(c, c->lv.back());
     }
+    // column masks of the structured levels (the stencil kernels skip columns without unknowns) and
+    // the inverse diagonals (first Chebyshev steps folded into neighbouring kernels): on the side stream,
+    // after the components, beside the coarsest inverse; joined with them
+    HIPCHK(hipEventRecord(c->ev_side[0], c->stream));
+    HIPCHK(hipStreamWaitEvent(c->side, c->ev_side[0], 0));
+    for (Level &L : c->lv) {
+        L.d_dinv64 = dalloc<double>(c, c->hier_allocs, L.nodes());
+        L.d_dinv32 = dalloc<float>(c, c->hier_allocs, L.nodes());
+        if (L.ell) {
+            HIPCHK(launch_dinv_ell(L.nrow, L.K, L.d_col, L.d_val64, L.d_dinv64, L.d_dinv32, c->side));
+        } else if (L.nb > 0) {
+            L.d_cmask = dalloc<unsigned long long>(c, c->hier_allocs, L.nb);
+            HIPCHK(launch_col_masks(L.d_w64, L.nodes(), L.topo(), L.d_cmask, c->side));
+            HIPCHK(launch_dinv_struct(L.d_w64, L.nodes(), Topo{L.nb, L.d_nbr}, L.d_dinv64, L.d_dinv32, c->side));
+        }
+    }
+    HIPCHK(hipEventRecord(c->ev_side[1], c->side));
     // 5. coarsest level: dense pseudo-inverse
     {
         Level &C = c->lv.back();
@@ -1375,7 +1391,8 @@ spfd_status do_build(Ctx *c)
         double *dwork = dalloc<double>(c, c->hier_allocs, dense_inverse_work_doubles(c->ncoarse));
         HIPCHK(launch_coarse_factor(c->ncoarse, c->d_Ainv, c->d_cwork, dwork, c->stream));
     }
-    // join the components: their count sizes the gauge's buffers
+    // join the side stream (components, masks, inverse diagonals); the component count sizes the gauge's
+    // buffers
     {
         HIPCHK(hipStreamWaitEvent(c->stream, c->ev_side[1], 0));
         HIPCHK(hipMemcpyAsync(c->h_ints, d_ncomp, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -1388,19 +1405,6 @@ spfd_status do_build(Ctx *c)
         c->d_cpart = dalloc<double>(c, c->hier_allocs, comp_mean_parts(F0.nb));
         HIPCHK(hipMemsetAsync(c->d_counts, 0, (c->ncomp + 1) * sizeof(int), c->stream));
         HIPCHK(launch_comp_counts(c->d_comp, n, c->d_counts, c->stream));
-    }
-    // column masks of the structured levels (the stencil kernels skip columns without unknowns) and
-    // the inverse diagonals (first Chebyshev steps folded into neighbouring kernels)
-    for (Level &L : c->lv) {
-        L.d_dinv64 = dalloc<double>(c, c->hier_allocs, L.nodes());
-        L.d_dinv32 = dalloc<float>(c, c->hier_allocs, L.nodes());
-        if (L.ell) {
-            HIPCHK(launch_dinv_ell(L.nrow, L.K, L.d_col, L.d_val64, L.d_dinv64, L.d_dinv32, c->stream));
-        } else if (L.nb > 0) {
-            L.d_cmask = dalloc<unsigned long long>(c, c->hier_allocs, L.nb);
-            HIPCHK(launch_col_masks(L.d_w64, L.nodes(), L.topo(), L.d_cmask, c->stream));
-            HIPCHK(launch_dinv_struct(L.d_w64, L.nodes(), Topo{L.nb, L.d_nbr}, L.d_dinv64, L.d_dinv32, c->stream));
-        }
     }
     chebyshev_coefficients(c);
     HIPCHK(hipStreamSynchronize(c->stream));
