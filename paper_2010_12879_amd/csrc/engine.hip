@@ -73,10 +73,11 @@ struct Level {
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    // second stream of the build (default priority): the connected components run there beside the
-    // coarsening, joined before the build returns
+    // second stream of the build (default priority): the connected components, then the column masks and
+    // inverse diagonals, run there beside the coarsening and the coarsest inverse; joined before the build
+    // returns
     hipStream_t side = nullptr;
-    hipEvent_t ev_side[2] = {nullptr, nullptr};   // weights ready (main -> side), components done (side -> main)
+    hipEvent_t ev_side[2] = {nullptr, nullptr};   // [0] main -> side (inputs ready), [1] side -> main (work done)
     std::string err;
     // geometry
     int state = 0;  // 0 created, 1 geometry, 2 sigma, 3 built, 4 sources
