@@ -481,6 +481,25 @@ __global__ void k_count_dofs(const double *w, long long stride, Topo topo, int *
     if (t == 0 && cnt) atomicAdd(count, cnt);
 }
 
+// rows of an ELL level with a positive diagonal (the sum of the row's stored entries, in the order the
+// enumeration of the coarsest level uses), counted by many workgroups
+__global__ __launch_bounds__(256) void k_count_ell_dofs(int n, int K, const int *__restrict__ col,
+                                                        const double *__restrict__ val, int *count)
+{
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        double d = 0.0;
+        for (int k = 0; k < K; ++k)
+            if (col[(long long)k * n + i] >= 0) d += val[(long long)k * n + i];
+        if (d > 0.0) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt) atomicAdd(count, cnt);
+}
+
 long long count_dofs(Ctx *c, const Level &L)
 {
     HIPCHK(hipMemsetAsync(c->d_ints, 0, sizeof(int), c->stream));
@@ -1216,8 +1235,12 @@ Level split_level(Ctx *c, Level &F)
     HIPCHK(launch_galerkin_ell(fa, F.d_agg, nc, C.d_mptr, C.d_mem, 1, len, C.K, C.d_col, C.d_val64, C.d_val32,
                                c->d_ints + 2, c->d_ints + 3, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    // unknowns of the new level: rows with a conducting connection
-    HIPCHK(launch_coarse_enum_ell(C.nrow, C.K, C.d_col, C.d_val64, flag, idx, c->d_ints, 0, c->stream));
+    // unknowns of the new level: rows with a conducting connection (their number only)
+    HIPCHK(hipMemsetAsync(c->d_ints, 0, sizeof(int), c->stream));
+    if (C.nrow > 0)
+        hipLaunchKernelGGL(k_count_ell_dofs, dim3((unsigned)((C.nrow + 255) / 256)), dim3(256), 0, c->stream, C.nrow,
+                           C.K, C.d_col, C.d_val64, c->d_ints);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(c->h_ints, c->d_ints, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     C.dofs = c->h_ints[0];
